@@ -1,0 +1,208 @@
+"""Plain CPU oracle for the space-time Ripley's K estimator -- TEST INFRASTRUCTURE.
+
+Only ``tests/``, the smoke check in ``__graft_entry__`` and the CPU-baseline leg
+of ``bench.py`` import this package.  It shares no code with the HIP library in
+``paper_1912_04753_amd``; the two meet only through the seeded input
+generators in ``paper_1912_04753_amd.workloads``, which hold none of the
+method's arithmetic.
+
+Contents
+  * ``liboracle.so`` (from ``oracle.c``): FP64, O(n^2) over every ordered pair,
+    OpenMP over centre points.  Histogram over the smallest containing grid
+    step, 2-D prefix sum, K (Eq. 2), L (Eq. 4), Monte Carlo CSR simulations with
+    Philox4x64-10 and min/max envelopes (Sec. 3).
+  * ``literal``: Eq. 2 evaluated literally, one grid point (s, t) at a time.
+  * ``omega_ref``: the isotropic spatial weight by direct arc-union on the
+    circle, in FP64 and in 50-digit mpmath.
+
+Every function states the passage of the paper (Wang et al., arXiv 1912.04753)
+it follows.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+
+EDGE_SPATIAL = 1
+EDGE_TEMPORAL = 2
+EDGE_ISO = 3
+NORM_NN1 = 0
+NORM_N2 = 1
+
+
+class OrcDesc(ctypes.Structure):
+    _fields_ = [
+        ("x0", ctypes.c_int64), ("y0", ctypes.c_int64),
+        ("x1", ctypes.c_int64), ("y1", ctypes.c_int64),
+        ("t0", ctypes.c_int64), ("t1", ctypes.c_int64),
+        ("s_max", ctypes.c_int64), ("t_max", ctypes.c_int64),
+        ("n_s", ctypes.c_int32), ("n_t", ctypes.c_int32),
+        ("edge", ctypes.c_uint32), ("norm", ctypes.c_uint32),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load ``liboracle.so``, building it first if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from . import build as _b
+            _b.build()
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER
+        i32p, u64p, f64p = P(ctypes.c_int32), P(ctypes.c_uint64), P(ctypes.c_double)
+        i64p = P(ctypes.c_int64)
+        dp = P(OrcDesc)
+        L.orc_thresholds.argtypes = [dp, i64p, i64p]
+        L.orc_omega.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, dp]
+        L.orc_omega.restype = ctypes.c_double
+        L.orc_vt.argtypes = [ctypes.c_int64, ctypes.c_int64, dp]
+        L.orc_vt.restype = ctypes.c_double
+        L.orc_hist.argtypes = [dp, i32p, i32p, i32p, ctypes.c_int64, ctypes.c_int64,
+                               ctypes.c_int, u64p, f64p]
+        L.orc_estimate.argtypes = [dp, i32p, i32p, i32p, ctypes.c_int64, ctypes.c_int64,
+                                   ctypes.c_int, u64p, f64p, f64p, f64p]
+        L.orc_philox4x64_10.argtypes = [u64p, u64p, u64p]
+        L.orc_csr_points.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64, dp,
+                                     i32p, i32p, i32p]
+        L.orc_envelope.argtypes = [dp, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64,
+                                   ctypes.c_int, f64p, f64p, f64p, f64p, u64p, f64p, f64p]
+        L.orc_now.restype = ctypes.c_double
+        L.orc_max_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def desc(window, s_max, t_max, n_s, n_t, edge=EDGE_ISO, norm=NORM_NN1):
+    """Pack a study window ``(x0, y0, x1, y1, t0, t1)`` and grid into OrcDesc."""
+    x0, y0, x1, y1, t0, t1 = (int(v) for v in window)
+    return OrcDesc(x0, y0, x1, y1, t0, t1, int(s_max), int(t_max), int(n_s), int(n_t),
+                   int(edge), int(norm))
+
+
+def _ptr(a, ct):
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+def thresholds(d):
+    """Exact integer thresholds (S2[k], T[l]) of the grid (Eq. 3)."""
+    S2 = np.zeros(d.n_s, np.int64)
+    T = np.zeros(d.n_t, np.int64)
+    lib().orc_thresholds(ctypes.byref(d), _ptr(S2, ctypes.c_int64), _ptr(T, ctypes.c_int64))
+    return S2, T
+
+
+def omega(x, y, d2, d):
+    """Isotropic spatial weight of centre (x, y) at squared radius d2 (Sec. 3)."""
+    return lib().orc_omega(int(x), int(y), int(d2), ctypes.byref(d))
+
+
+def vt(t, u, d):
+    """Temporal weight of centre time t at temporal distance u (Sec. 3)."""
+    return lib().orc_vt(int(t), int(u), ctypes.byref(d))
+
+
+def _soa(x, y, t):
+    return (np.ascontiguousarray(x, np.int32), np.ascontiguousarray(y, np.int32),
+            np.ascontiguousarray(t, np.int32))
+
+
+def hist(d, x, y, t, n_centres=None, threads=0):
+    """Per-step histogram (Hc, Hw) over ordered pairs with centre i < n_centres."""
+    x, y, t = _soa(x, y, t)
+    n = len(x)
+    nc = n if n_centres is None else int(n_centres)
+    nb = d.n_s * d.n_t
+    Hc = np.zeros(nb, np.uint64)
+    Hw = np.zeros(nb, np.float64)
+    rc = lib().orc_hist(ctypes.byref(d), _ptr(x, ctypes.c_int32), _ptr(y, ctypes.c_int32),
+                        _ptr(t, ctypes.c_int32), n, nc, int(threads),
+                        _ptr(Hc, ctypes.c_uint64), _ptr(Hw, ctypes.c_double))
+    if rc:
+        raise ValueError("orc_hist failed")
+    return Hc.reshape(d.n_s, d.n_t), Hw.reshape(d.n_s, d.n_t)
+
+
+def estimate(d, x, y, t, n_centres=None, threads=0):
+    """Cumulative counts C, weight sums W, K (Eq. 2) and L (Eq. 4), each n_s x n_t."""
+    x, y, t = _soa(x, y, t)
+    n = len(x)
+    nc = n if n_centres is None else int(n_centres)
+    nb = d.n_s * d.n_t
+    C = np.zeros(nb, np.uint64)
+    W = np.zeros(nb, np.float64)
+    K = np.zeros(nb, np.float64)
+    L = np.zeros(nb, np.float64)
+    with np.errstate(all="ignore"):
+        rc = lib().orc_estimate(ctypes.byref(d), _ptr(x, ctypes.c_int32),
+                                _ptr(y, ctypes.c_int32), _ptr(t, ctypes.c_int32), n, nc,
+                                int(threads), _ptr(C, ctypes.c_uint64),
+                                _ptr(W, ctypes.c_double), _ptr(K, ctypes.c_double),
+                                _ptr(L, ctypes.c_double))
+    if rc:
+        raise ValueError("orc_estimate failed")
+    s = (d.n_s, d.n_t)
+    return {"C": C.reshape(s), "W": W.reshape(s), "K": K.reshape(s), "L": L.reshape(s)}
+
+
+def philox4x64_10(counter, key):
+    """Philox4x64-10 block function (Salmon et al., SC'11)."""
+    c = np.ascontiguousarray(counter, np.uint64)
+    k = np.ascontiguousarray(key, np.uint64)
+    out = np.zeros(4, np.uint64)
+    lib().orc_philox4x64_10(_ptr(c, ctypes.c_uint64), _ptr(k, ctypes.c_uint64),
+                            _ptr(out, ctypes.c_uint64))
+    return out
+
+
+def csr_points(d, n, sim, seed):
+    """Simulation ``sim`` of n CSR points from Philox(counter=(i, sim, 0, 0), key=(seed, 0))."""
+    x = np.zeros(n, np.int32)
+    y = np.zeros(n, np.int32)
+    t = np.zeros(n, np.int32)
+    lib().orc_csr_points(int(n), int(sim), int(seed) & (2**64 - 1), ctypes.byref(d),
+                         _ptr(x, ctypes.c_int32), _ptr(y, ctypes.c_int32),
+                         _ptr(t, ctypes.c_int32))
+    return x, y, t
+
+
+def envelope(d, n, m, seed, threads=0, per_sim=True):
+    """Min/max envelopes of K and L over m CSR simulations (Sec. 3)."""
+    nb = d.n_s * d.n_t
+    out = {k: np.zeros(nb, np.float64) for k in ("K_lo", "K_hi", "L_lo", "L_hi")}
+    Cs = np.zeros(m * nb, np.uint64) if per_sim else None
+    Ws = np.zeros(m * nb, np.float64) if per_sim else None
+    Ks = np.zeros(m * nb, np.float64) if per_sim else None
+    null_u = ctypes.POINTER(ctypes.c_uint64)()
+    null_d = ctypes.POINTER(ctypes.c_double)()
+    with np.errstate(all="ignore"):
+        rc = lib().orc_envelope(
+            ctypes.byref(d), int(n), int(m), int(seed) & (2**64 - 1), int(threads),
+            _ptr(out["K_lo"], ctypes.c_double), _ptr(out["K_hi"], ctypes.c_double),
+            _ptr(out["L_lo"], ctypes.c_double), _ptr(out["L_hi"], ctypes.c_double),
+            _ptr(Cs, ctypes.c_uint64) if per_sim else null_u,
+            _ptr(Ws, ctypes.c_double) if per_sim else null_d,
+            _ptr(Ks, ctypes.c_double) if per_sim else null_d)
+    if rc:
+        raise ValueError("orc_envelope failed")
+    s = (d.n_s, d.n_t)
+    res = {k: v.reshape(s) for k, v in out.items()}
+    if per_sim:
+        res["C_sims"] = Cs.reshape((m,) + s)
+        res["W_sims"] = Ws.reshape((m,) + s)
+        res["K_sims"] = Ks.reshape((m,) + s)
+    return res
+
+
+def now():
+    return lib().orc_now()
+
+
+def max_threads():
+    return lib().orc_max_threads()

@@ -1,0 +1,146 @@
+"""Seeded synthetic point sets for the benchmark and the tests.
+
+This module holds input generation only -- no part of the estimator's
+arithmetic -- so that the HIP library and the CPU oracle can be fed the very
+same points.  Everything is drawn from ``numpy.random.Generator(PCG64(seed))``.
+
+The paper's own data (enterprise registrations in Hubei, 1949-2015, and a
+synthetic US set; Sec. 6.1 and the appendix) are not available, so these
+recipes stand in for them:
+
+* ``uniform``  -- integer coordinates uniform on the half-open window
+  [x0, x1) x [y0, y1) x [t0, t1) (complete spatio-temporal randomness).
+* ``thomas``   -- a space-time Thomas-type cluster process: P parents uniform in
+  the window; every point picks a parent uniformly at random and is displaced
+  by independent N(0, sigma_xy) in x and y and N(0, sigma_t) in t; displaced
+  points falling outside the closed window are drawn again; coordinates are
+  floored to integers.  It stands in for the strongly skewed POI data the
+  paper describes (Sec. 6.2).
+
+Sizes and grids bracket the paper's experiments (10k-500k points, 10-20 grid
+steps per axis; Sec. 6.1, Table 5, appendix Table A).  Units: metres and
+seconds; a day is 86,400 s.
+"""
+import math
+
+import numpy as np
+
+DAY = 86400
+
+
+def _rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def uniform_points(rng, n, window):
+    x0, y0, x1, y1, t0, t1 = window
+    x = rng.integers(x0, x1, size=n, dtype=np.int64)
+    y = rng.integers(y0, y1, size=n, dtype=np.int64)
+    t = rng.integers(t0, t1, size=n, dtype=np.int64)
+    return x.astype(np.int32), y.astype(np.int32), t.astype(np.int32)
+
+
+def thomas_points(rng, n, window, parents, sigma_xy, sigma_t):
+    x0, y0, x1, y1, t0, t1 = window
+    px = rng.uniform(x0, x1, size=parents)
+    py = rng.uniform(y0, y1, size=parents)
+    pt = rng.uniform(t0, t1, size=parents)
+    par = rng.integers(0, parents, size=n)
+    x = np.empty(n, np.float64)
+    y = np.empty(n, np.float64)
+    t = np.empty(n, np.float64)
+    todo = np.arange(n)
+    while todo.size:
+        p = par[todo]
+        cx = px[p] + rng.normal(0.0, sigma_xy, size=todo.size)
+        cy = py[p] + rng.normal(0.0, sigma_xy, size=todo.size)
+        ct = pt[p] + rng.normal(0.0, sigma_t, size=todo.size)
+        ok = (cx >= x0) & (cx <= x1) & (cy >= y0) & (cy <= y1) & (ct >= t0) & (ct <= t1)
+        x[todo[ok]] = cx[ok]
+        y[todo[ok]] = cy[ok]
+        t[todo[ok]] = ct[ok]
+        todo = todo[~ok]
+    return (np.floor(x).astype(np.int32), np.floor(y).astype(np.int32),
+            np.floor(t).astype(np.int32))
+
+
+# The five workloads.  ``window`` = (x0, y0, x1, y1, t0, t1); isotropic spatial
+# and temporal edge correction (edge = 3) throughout.
+CONFIGS = {
+    1: dict(name="uniform-2k", seed=1, window=(0, 0, 10_000, 10_000, 0, 365 * DAY),
+            s_max=1_000, n_s=10, t_max=30 * DAY, n_t=10, sims=0,
+            parts=[("uniform", 2_000, {})]),
+    2: dict(name="thomas-200k", seed=2, window=(0, 0, 50_000, 50_000, 0, 365 * DAY),
+            s_max=5_000, n_s=20, t_max=60 * DAY, n_t=20, sims=0,
+            parts=[("thomas", 200_000, dict(parents=500, sigma_xy=200.0,
+                                            sigma_t=5.0 * DAY))]),
+    3: dict(name="uniform-100k-99csr", seed=3, window=(0, 0, 20_000, 20_000, 0, 180 * DAY),
+            s_max=2_000, n_s=25, t_max=30 * DAY, n_t=15, sims=99,
+            parts=[("uniform", 100_000, {})]),
+    4: dict(name="mixed-2M-19csr", seed=4, window=(0, 0, 100_000, 100_000, 0, 730 * DAY),
+            s_max=10_000, n_s=50, t_max=90 * DAY, n_t=30, sims=19,
+            parts=[("uniform", 1_000_000, {}),
+                   ("thomas", 1_000_000, dict(parents=2_000, sigma_xy=500.0,
+                                              sigma_t=10.0 * DAY))]),
+}
+
+
+def make_points(cfg):
+    """Observed point set of a workload dict: three int32 arrays (x, y, t)."""
+    rng = _rng(cfg["seed"])
+    xs, ys, ts = [], [], []
+    for kind, n, kw in cfg["parts"]:
+        if kind == "uniform":
+            x, y, t = uniform_points(rng, n, cfg["window"])
+        elif kind == "thomas":
+            x, y, t = thomas_points(rng, n, cfg["window"], **kw)
+        else:
+            raise ValueError(kind)
+        xs.append(x); ys.append(y); ts.append(t)
+    return np.concatenate(xs), np.concatenate(ys), np.concatenate(ts)
+
+
+def config(i):
+    return dict(CONFIGS[i])
+
+
+def serving_requests(num=5000, rate=None, seed=5):
+    """The request stream: one dict per request with its own window, grid and points.
+
+    n is log-uniform in [1e3, 5e5]; each set is uniform or Thomas with equal
+    odds (P log-uniform in [500, 2000], sigma_xy in [200, 500] m, sigma_t in
+    [5, 10] d); window side U[10, 100] km, duration U[180, 730] d; s_max =
+    min(U[1, 10] km, side/4) with U{10..50} steps; t_max = min(U[30, 90] d,
+    D/4) with U{10..50} steps; U{0..99} CSR simulations with Philox key
+    5*2^32 + request id.  Arrival times are Poisson at ``rate`` per second
+    (None: all at t = 0).  Points are generated lazily by ``request_points``.
+    """
+    rng = _rng(seed)
+    t_arr = 0.0
+    out = []
+    for r in range(num):
+        if rate:
+            t_arr += rng.exponential(1.0 / rate)
+        n = int(math.floor(math.exp(rng.uniform(math.log(1e3), math.log(5e5)))))
+        side = int(rng.uniform(10_000, 100_000))
+        dur = int(rng.uniform(180, 730) * DAY)
+        s_max = int(min(rng.uniform(1_000, 10_000), side / 4))
+        t_max = int(min(rng.uniform(30, 90) * DAY, dur / 4))
+        kind = "uniform" if rng.random() < 0.5 else "thomas"
+        kw = {}
+        if kind == "thomas":
+            kw = dict(parents=int(math.exp(rng.uniform(math.log(500), math.log(2000)))),
+                      sigma_xy=float(rng.uniform(200, 500)),
+                      sigma_t=float(rng.uniform(5, 10) * DAY))
+        out.append(dict(id=r, arrival=t_arr, seed=(5 << 32) + r, point_seed=seed * 1_000_003 + r,
+                        window=(0, 0, side, side, 0, dur), s_max=s_max,
+                        n_s=int(rng.integers(10, 51)), t_max=t_max,
+                        n_t=int(rng.integers(10, 51)), sims=int(rng.integers(0, 100)),
+                        parts=[(kind, n, kw)]))
+    return out
+
+
+def request_points(req):
+    cfg = dict(req)
+    cfg["seed"] = req["point_seed"]
+    return make_points(cfg)
