@@ -1,0 +1,143 @@
+"""Benchmark: space-time Ripley's K pair range count on one MI355X.
+
+One step = the whole path over the batched-envelope workload: K/L of the
+observed set (100,000 uniform points in 20 km x 20 km x 180 d, 25 x 15 grid to
+2 km / 30 d, isotropic spatial + temporal correction) followed by the envelope
+of 99 Monte Carlo CSR simulations of the same size drawn on the device.  Inputs
+are resident in device memory before timing starts.
+
+Printed: one JSON line.  ``value`` = ordered in-range pair tests per second
+(N_in over the step, in units of 1e9/s); ``sims_per_s``; ``roofline`` for the
+pair kernel (integer ALU bound: 9 lane-ops per candidate pair against
+256 CU x 64 lanes x 2.4 GHz); ``cpu_baseline`` = the FP64 oracle on the host
+cores over a bounded sample of centres of the observed set.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "G space-time pair tests/s + sims/s at 1 GPU; served p50/p99 latency vs plain path"
+OPS_PER_EVAL = 9            # minimal integer test of one candidate pair (lane-ops)
+PEAK_LANE_OPS = 256 * 64 * 2.4e9   # CUs x lanes x clock
+
+
+def cpu_baseline(cfg, x, y, t, target_s):
+    import numpy as np
+    import oracle
+    d = oracle.desc(cfg["window"], cfg["s_max"], cfg["t_max"], cfg["n_s"], cfg["n_t"])
+    n = len(x)
+    threads = oracle.max_threads()
+    # calibrate on a small sample, then size the timed sample to ~target_s
+    nc = 500
+    t0 = oracle.now()
+    oracle.estimate(d, x, y, t, n_centres=nc, threads=threads)
+    dt = max(oracle.now() - t0, 1e-3)
+    nc = int(min(n, max(1000, nc * target_s / dt)))
+    t0 = oracle.now()
+    r = oracle.estimate(d, x, y, t, n_centres=nc, threads=threads)
+    dt = oracle.now() - t0
+    n_in = int(r["C"][-1, -1])
+    return {"value": n_in / dt / 1e9, "unit": "G pair tests/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"observed set of the workload, first {nc} of {n} points as centres "
+                      f"against all {n}; {n_in} in-range ordered pairs in {dt:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(sharding is a design note); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1912_04753_amd import ripk, workloads
+
+    torch.cuda.set_device(0)
+    cfg = workloads.config(3)
+    x, y, t = workloads.make_points(cfg)
+    n, m = len(x), cfg["sims"]
+    dx, dy, dt = (torch.from_numpy(a).cuda() for a in (x, y, t))
+    torch.cuda.synchronize()
+    desc = ripk.make_desc(cfg["window"], cfg["s_max"], cfg["t_max"], cfg["n_s"], cfg["n_t"],
+                          n_max=n, m_max=m, flags=ripk.RIPK_PLAN_TIMING)
+    plan = ripk.ripk_plan(desc)
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def step():
+        t0 = time.perf_counter()
+        r = ripk.ripk_compute_K(plan, dx, dy, dt, stream=stream)
+        s_obs = ripk.ripk_plan_stats(plan)
+        t1 = time.perf_counter()
+        ripk.ripk_simulate_envelope(plan, n, m, cfg["seed"], L_obs=r["L"], stream=stream)
+        s_sim = ripk.ripk_plan_stats(plan)
+        t2 = time.perf_counter()
+        return s_obs, s_sim, t1 - t0, t2 - t1
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    recs = []
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        recs.append(step())
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    plan.destroy()
+
+    ms = 1e3 * t_total / args.steps
+    n_in = recs[0][0]["n_in"] + recs[0][1]["n_in"]
+    value = n_in / (t_total / args.steps) / 1e9
+    t_sim = sum(r[3] for r in recs) / len(recs)
+    # dominant kernel: the persistent pair kernel, two launches per step
+    pair_us = [r[0]["us_pair"] for r in recs] + [r[1]["us_pair"] for r in recs]
+    evals = recs[0][0]["n_eval"] + recs[0][1]["n_eval"]
+    avg_us = sum(pair_us) / len(pair_us)
+    achieved = OPS_PER_EVAL * (evals / 2) / (avg_us * 1e-6) / 1e12
+    peak = PEAK_LANE_OPS / 1e12
+    out = {
+        "metric": METRIC,
+        "value": round(value, 4),
+        "unit": "G pair tests/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "i32+f32",
+        "data": "synthetic",
+        "config": {"workload": "config3: 100k uniform points, 20km x 20km x 180d, "
+                               "25x15 grid to 2km/30d, observed K + 99 CSR simulations",
+                   "n": n, "sims": m, "n_s": cfg["n_s"], "n_t": cfg["n_t"]},
+        "sims_per_s": round(m / t_sim, 3),
+        "n_in_per_step": n_in,
+        "n_eval_per_step": evals,
+        "pair_kernel_us": {"observed": round(sum(r[0]["us_pair"] for r in recs) / len(recs), 2),
+                           "simulations": round(sum(r[1]["us_pair"] for r in recs) / len(recs), 2)},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 4), "peak": round(peak, 4),
+                     "unit": "T int lane-ops/s", "frac": round(achieved / peak, 4),
+                     "traffic": None,
+                     "note": f"{OPS_PER_EVAL} lane-ops per candidate pair x candidates per "
+                             f"launch / mean pair-kernel launch time ({avg_us:.1f} us)"},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, x, y, t, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

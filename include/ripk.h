@@ -1,0 +1,194 @@
+/*
+ * ripk.h -- C ABI of the MI355X (gfx950) space-time Ripley's K library.
+ *
+ * The library evaluates the space-time K function of Wang et al.,
+ * "Distributed space-time Ripley's K function" (arXiv 1912.04753), Sec. 3:
+ *
+ *   K(s,t) = A*D/N * sum_i sum_{j!=i} I(d_ij <= s, u_ij <= t) / (omega_ij v_ij)  (Eq. 2, 3)
+ *   L(s,t) = sqrt(K(s,t) / (2 pi t)) - s                                          (Eq. 4)
+ *
+ * with Ripley's isotropic spatial correction omega_ij (share of the circle
+ * centred on i with radius d_ij inside the study rectangle) and the temporal
+ * correction v_ij (1 if [t_i-u_ij, t_i+u_ij] lies in the study period, else
+ * 1/2), on the grid s_k = k*s_max/n_s, t_l = l*t_max/n_t (k, l >= 1), and the
+ * Monte Carlo CSR simulation envelopes used to judge significance (Sec. 3).
+ *
+ * Conventions shared by every call
+ *  - Every call returns a ripk_status and never throws.  On an error no
+ *    output buffer is written; ripk_last_error() gives a detail string for the
+ *    calling thread.
+ *  - Coordinates are int32 metres (x, y) and int32 seconds (t).  d_ij^2 and u_ij
+ *    are exact integers, so pair counts are exact; weights 1/(omega v) are
+ *    computed in FP32 and summed in 128-bit fixed point with 23 fractional bits,
+ *    so weighted sums do not depend on summation order.  K and L are FP64.
+ *  - Grids are s-major: element (k, l) (0-based) sits at index k*n_t + l.
+ *  - A plan is used by one thread at a time.  Handles are created and freed by
+ *    the library; caller buffers are never retained after a call returns.
+ *  - `stream` is a hipStream_t (NULL = the null stream of the plan's device).
+ *    All calls return only after their results are in the caller's buffers.
+ */
+#ifndef RIPK_H
+#define RIPK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ripk_status;
+enum {
+  RIPK_OK = 0,
+  RIPK_PENDING = 1,       /* request not finished yet (ripk_poll)                    */
+  RIPK_EINVAL = -1,       /* bad argument: see ripk_last_error()                     */
+  RIPK_ERANGE = -2,       /* a point lies outside the closed study window            */
+  RIPK_ENOMEM = -3,       /* device or host allocation failed                        */
+  RIPK_EDEVICE = -4,      /* HIP runtime error                                       */
+  RIPK_E2BIG = -5,        /* request larger than the plan's / server's capacity      */
+  RIPK_EAGAIN = -6,       /* server queue full, try again                            */
+  RIPK_EOVERFLOW = -7,    /* an accumulator bound would be exceeded                  */
+  RIPK_ECANCELED = -8,    /* request cancelled by server shutdown                    */
+  RIPK_ENOTFOUND = -9     /* unknown ticket                                          */
+};
+
+/* edge-correction bits (Sec. 3): omega_ij and v_ij can be switched on separately */
+#define RIPK_EDGE_SPATIAL_ISO 1u
+#define RIPK_EDGE_TEMPORAL 2u
+#define RIPK_EDGE_ISO 3u
+
+/* normalisation N of Eq. 2: n(n-1) (unbiased under CSR, default) or n^2 as printed */
+#define RIPK_NORM_NN1 0u
+#define RIPK_NORM_N2 1u
+
+/* simulation method (Sec. 3): Monte Carlo under complete spatio-temporal randomness */
+#define RIPK_SIM_CSR 0u
+
+/* plan flags */
+#define RIPK_PLAN_ORDERED (1u << 0) /* evaluate ordered pairs (full stencil) even when   */
+                                    /* every point is a centre; default: each unordered */
+                                    /* pair once, both weights added                    */
+#define RIPK_PLAN_TIMING (1u << 1)  /* record per-phase device timings for stats         */
+
+/*
+ * Problem statement (the job parameters of Sec. 4.1 and the GUI of Sec. 5:
+ * study area, period, spatial/temporal thresholds and steps, edge correction,
+ * simulation method and count).
+ *
+ * Requirements (RIPK_EINVAL otherwise):
+ *   x0 < x1, y0 < y1, t0 < t1, all within int32; x1-x0 and y1-y0 < 2^24;
+ *   t1-t0 < 2^31;  1 <= n_s, n_t <= 64;  s_max >= 1, t_max >= 1;
+ *   with RIPK_EDGE_SPATIAL_ISO: 2*s_max <= min(x1-x0, y1-y0) (so omega >= 1/4);
+ *   with RIPK_EDGE_TEMPORAL:   t_max <= t1-t0;
+ *   s_max < 2^23;  n_max >= 2;  0 <= m_max;  (m_max+1)*n_max < 2^31.
+ */
+typedef struct {
+  int64_t x0, y0, x1, y1; /* closed study rectangle [x0,x1] x [y0,y1], metres     */
+  int64_t t0, t1;         /* closed study period [t0,t1], seconds                 */
+  int64_t s_max, t_max;   /* largest spatial / temporal distance of the grid      */
+  int32_t n_s, n_t;       /* number of grid steps in s and in t                    */
+  uint32_t edge;          /* RIPK_EDGE_* bits                                      */
+  uint32_t norm;          /* RIPK_NORM_*                                           */
+  uint32_t sim_method;    /* RIPK_SIM_CSR                                          */
+  int64_t n_max;          /* capacity: largest point count per set                 */
+  int32_t m_max;          /* capacity: largest simulation count per call           */
+  uint32_t flags;         /* RIPK_PLAN_* bits                                      */
+  int32_t device;         /* HIP device ordinal                                    */
+  int32_t cell_div;       /* spatial cells per s_max (0 = library default)         */
+  int32_t tcell_div;      /* temporal cells per t_max (0 = library default)        */
+} ripk_plan_desc;
+
+typedef struct ripk_plan_s *ripk_plan_t;
+
+/* Geometry a plan derives from its descriptor; filled by ripk_plan_check
+ * without touching any device. */
+typedef struct {
+  int64_t S2[64];          /* floor((k*s_max)^2/n_s^2), k = 1..n_s (Eq. 3 on integers)   */
+  int64_t T[64];           /* floor(l*t_max/n_t), l = 1..n_t                             */
+  int64_t cell_s, cell_t;  /* cell edge in metres / seconds                              */
+  int32_t nx, ny, nt;      /* cells per axis                                             */
+  int32_t reach_s, reach_t;/* stencil half-width in cells (space, time)                  */
+  int64_t n_cells;         /* nx*ny*nt                                                   */
+  int32_t wide;            /* 1 if squared distances need 64-bit arithmetic              */
+  int32_t n_bins;          /* n_s*n_t                                                    */
+  int64_t device_bytes;    /* device memory a plan of this descriptor allocates          */
+} ripk_plan_info;
+
+/* A point set in structure-of-arrays form.  Points [0, n_centres) act as
+ * centres i of Eq. 2; points [n_centres, n) are neighbours j only (a halo,
+ * as when one shard of a larger set is evaluated).  n_centres = 0 means all.
+ * on_device = 1: x, y, t are device pointers on the plan's device, ordered on
+ * the call's stream; 0: host pointers. */
+typedef struct {
+  const int32_t *x, *y, *t;
+  int64_t n;
+  int64_t n_centres;
+  int32_t on_device;
+} ripk_points;
+
+/* Outputs of ripk_compute_K: host buffers of n_s*n_t elements each, any may
+ * be NULL.  C: cumulative ordered-pair counts; W: cumulative sums of
+ * 1/(omega v); K: Eq. 2; L: Eq. 4. */
+typedef struct {
+  uint64_t *C;
+  double *W, *K, *L;
+} ripk_K_out;
+
+/* Outputs of ripk_simulate_envelope: host buffers, any may be NULL.
+ * K_lo/K_hi/L_lo/L_hi: pointwise min/max over the m simulations (n_s*n_t);
+ * dL_hi: L_obs - L_hi (needs L_obs);  C_sims/W_sims/K_sims: per simulation,
+ * m*n_s*n_t, simulation-major. */
+typedef struct {
+  double *K_lo, *K_hi, *L_lo, *L_hi, *dL_hi;
+  uint64_t *C_sims;
+  double *W_sims, *K_sims;
+} ripk_env_out;
+
+/* Counters and timings of the last compute call on a plan. */
+typedef struct {
+  int64_t n_sets;          /* point sets evaluated                                      */
+  int64_t n_points;        /* points over all sets                                      */
+  int64_t n_in;            /* ordered in-range pairs, summed over sets                   */
+  int64_t n_eval;          /* candidate pairs the pair kernel examined                   */
+  int64_t n_items;         /* work items of the pair kernel                              */
+  int32_t pair_grid;       /* workgroups of the persistent pair kernel                   */
+  int32_t symmetric;       /* 1 if unordered pairs were evaluated once                   */
+  double us_total;         /* wall time of the call, microseconds                        */
+  double us_gen, us_grid, us_pair, us_finalize; /* device phases (RIPK_PLAN_TIMING)      */
+} ripk_stats;
+
+/* Validate a descriptor and derive its geometry; host only, no device use.
+ * Returns RIPK_OK or RIPK_EINVAL. */
+ripk_status ripk_plan_check(const ripk_plan_desc *desc, ripk_plan_info *info);
+
+/* Create a plan: validate, derive thresholds and the cell grid, and allocate
+ * every device buffer for n_max points and m_max simulations on desc->device.
+ * Errors: EINVAL, ENOMEM, EDEVICE.  Free with ripk_plan_destroy. */
+ripk_status ripk_plan(const ripk_plan_desc *desc, ripk_plan_t *out);
+void ripk_plan_destroy(ripk_plan_t plan);
+
+/* K, L of one observed point set (Eq. 2-4).  Errors: EINVAL (n < 2,
+ * n > n_max, n_centres > n, NULL coordinates), ERANGE (a point outside the
+ * window), EDEVICE. */
+ripk_status ripk_compute_K(ripk_plan_t plan, const ripk_points *pts, void *stream,
+                           ripk_K_out *out);
+
+/* m Monte Carlo CSR simulations of n points each, drawn on the device with
+ * Philox4x64-10 (key = (seed, 0), counter = (point, simulation, 0, 0), x from
+ * the first output word by a 64x64 multiply-high onto [x0, x1), y and t
+ * likewise from the second and third), evaluated together, with pointwise
+ * min/max envelopes (Sec. 3).  L_obs (host, n_s*n_t, optional) gives dL_hi.
+ * Errors: EINVAL (n < 2, n > n_max, m < 1, m > m_max), EDEVICE. */
+ripk_status ripk_simulate_envelope(ripk_plan_t plan, int64_t n, int32_t m, uint64_t seed,
+                                   const double *L_obs, void *stream, ripk_env_out *out);
+
+/* Counters and timings of the plan's last compute call. */
+ripk_status ripk_plan_stats(ripk_plan_t plan, ripk_stats *out);
+
+const char *ripk_status_str(ripk_status s);
+const char *ripk_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RIPK_H */

@@ -1,0 +1,492 @@
+// Host runtime of the ripk C ABI: plan validation and geometry, device buffer
+// pool, the launch sequence of one evaluation, and the exported entry points.
+//
+// One evaluation of S point sets of n points each (S = 1 for an observed set,
+// S = m for Monte Carlo simulations, Sec. 3) runs, on the caller's stream:
+//   keys (or on-device CSR draw) -> radix sort by (set, cell, halo) -> cell
+//   bounds -> sorted point records -> work items -> pair kernel (persistent)
+//   -> per-set prefix sums, K (Eq. 2) and L (Eq. 4) -> envelopes -> copies out.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/ripk.h"
+#include "ripk_internal.h"
+
+using namespace ripk;
+
+namespace {
+
+thread_local std::string g_err;
+
+ripk_status fail(ripk_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+ripk_status fail(ripk_status s, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIPCHK(expr)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail(RIPK_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));       \
+  } while (0)
+
+constexpr int64_t kI32Min = -2147483648LL, kI32Max = 2147483647LL;
+
+int ceil_log2(uint64_t v) {
+  int b = 0;
+  while ((1ull << b) < v) ++b;
+  return b;
+}
+
+struct Layout {
+  ripk_plan_info info;
+  Geom g;
+  int32_t clamp_e;
+};
+
+// Validation and derived geometry; no device access.
+ripk_status derive(const ripk_plan_desc *d, Layout *L) {
+  if (!d || !L) return fail(RIPK_EINVAL, "null descriptor");
+  std::memset(L, 0, sizeof *L);
+  ripk_plan_info &I = L->info;
+  const int64_t W = d->x1 - d->x0, H = d->y1 - d->y0, D = d->t1 - d->t0;
+  if (d->x0 < kI32Min || d->x1 > kI32Max || d->y0 < kI32Min || d->y1 > kI32Max ||
+      d->t0 < kI32Min || d->t1 > kI32Max)
+    return fail(RIPK_EINVAL, "window must lie within int32");
+  if (W < 1 || H < 1 || D < 1) return fail(RIPK_EINVAL, "empty window (x1<=x0, y1<=y0 or t1<=t0)");
+  if (W >= (1LL << 24) || H >= (1LL << 24))
+    return fail(RIPK_EINVAL, "window sides must be below 2^24 m");
+  if (D >= (1LL << 31)) return fail(RIPK_EINVAL, "period must be below 2^31 s");
+  if (d->n_s < 1 || d->n_s > kMaxSteps || d->n_t < 1 || d->n_t > kMaxSteps)
+    return fail(RIPK_EINVAL, "n_s and n_t must be in [1, 64]");
+  if (d->s_max < 1 || d->t_max < 1) return fail(RIPK_EINVAL, "s_max and t_max must be >= 1");
+  if (d->s_max >= (1LL << 23)) return fail(RIPK_EINVAL, "s_max must be below 2^23");
+  if (d->t_max >= (1LL << 31)) return fail(RIPK_EINVAL, "t_max must be below 2^31");
+  if (d->edge & ~RIPK_EDGE_ISO) return fail(RIPK_EINVAL, "unknown edge-correction bits");
+  if ((d->edge & RIPK_EDGE_SPATIAL_ISO) && 2 * d->s_max > std::min(W, H))
+    return fail(RIPK_EINVAL,
+                "isotropic spatial correction needs 2*s_max <= min(width, height) "
+                "(the weight would reach 0 beyond that)");
+  if ((d->edge & RIPK_EDGE_TEMPORAL) && d->t_max > D)
+    return fail(RIPK_EINVAL, "temporal correction needs t_max <= t1-t0");
+  if (d->norm > RIPK_NORM_N2) return fail(RIPK_EINVAL, "unknown normalisation");
+  if (d->sim_method != RIPK_SIM_CSR) return fail(RIPK_EINVAL, "unknown simulation method");
+  if (d->n_max < 2) return fail(RIPK_EINVAL, "n_max must be >= 2");
+  if (d->m_max < 0) return fail(RIPK_EINVAL, "m_max must be >= 0");
+  const int64_t S = std::max<int64_t>(1, d->m_max);
+  if (S * d->n_max >= (1LL << 31)) return fail(RIPK_EINVAL, "(m_max)*n_max must be below 2^31");
+  if (d->cell_div < 0 || d->cell_div > 8 || d->tcell_div < 0 || d->tcell_div > 8)
+    return fail(RIPK_EINVAL, "cell_div and tcell_div must be in [0, 8]");
+
+  for (int k = 1; k <= d->n_s; ++k) {
+    __int128 a = (__int128)k * d->s_max;
+    I.S2[k - 1] = (int64_t)(a * a / ((__int128)d->n_s * d->n_s));
+  }
+  for (int l = 1; l <= d->n_t; ++l) I.T[l - 1] = (int64_t)l * d->t_max / d->n_t;
+
+  // cells: edge ceil(s_max/alpha) so that the stencil reaches alpha cells; grown
+  // when the grid would be too large for 32-bit keys.
+  const int alpha = d->cell_div ? d->cell_div : 1;
+  const int beta = d->tcell_div ? d->tcell_div : 1;
+  int64_t cs = (d->s_max + alpha - 1) / alpha, ct = (d->t_max + beta - 1) / beta;
+  int64_t nx, ny, nt;
+  for (;;) {
+    nx = std::max<int64_t>(1, W / cs);
+    ny = std::max<int64_t>(1, H / cs);
+    nt = std::max<int64_t>(1, D / ct);
+    if (nx * ny * nt * S * 2 < (1LL << 31) && nx * ny * nt <= (1LL << 24)) break;
+    if (nx * ny >= nt) cs *= 2; else ct *= 2;
+  }
+  I.cell_s = cs;
+  I.cell_t = ct;
+  I.nx = (int32_t)nx;
+  I.ny = (int32_t)ny;
+  I.nt = (int32_t)nt;
+  I.reach_s = (int32_t)((d->s_max + cs - 1) / cs);
+  I.reach_t = (int32_t)((d->t_max + ct - 1) / ct);
+  I.n_cells = nx * ny * nt;
+  // largest squared distance a candidate can have: |dx| < (reach+1)*cell
+  const double reach_m = (double)(I.reach_s + 1) * (double)cs;
+  I.wide = (2.0 * reach_m * reach_m >= 4294967296.0) ? 1 : 0;
+  I.n_bins = d->n_s * d->n_t;
+
+  Geom &g = L->g;
+  g.x0 = (int32_t)d->x0; g.y0 = (int32_t)d->y0; g.x1 = (int32_t)d->x1; g.y1 = (int32_t)d->y1;
+  g.t0 = (int32_t)d->t0; g.t1 = (int32_t)d->t1;
+  g.cell_s = (int32_t)cs; g.cell_t = (int32_t)ct;
+  g.nx = I.nx; g.ny = I.ny; g.nt = I.nt;
+  g.rs = I.reach_s; g.rt = I.reach_t;
+  g.n_cells = (uint32_t)I.n_cells;
+  g.n_s = d->n_s; g.n_t = d->n_t;
+  g.edge = d->edge;
+  g.wide = (uint32_t)I.wide;
+  g.s2max = (uint64_t)I.S2[d->n_s - 1];
+  g.tmax = (uint32_t)I.T[d->n_t - 1];
+  g.inv_ds = (float)((double)d->n_s / (double)d->s_max);
+  g.inv_dt = (float)((double)d->n_t / (double)d->t_max);
+  L->clamp_e = (int32_t)d->s_max;
+
+  // device footprint
+  const int64_t N = S * d->n_max, NB = I.n_bins, NC = I.n_cells;
+  const int64_t items = S * (d->n_max / kChunk + NC + kItemsPerGroup);
+  int64_t bytes = 0;
+  bytes += 3 * 4 * N;                        // x, y, t staging / simulated points
+  bytes += 4 * 4 * N;                        // keys, vals (double buffered)
+  bytes += (int64_t)radix_sort_temp_bytes((uint32_t)N);
+  bytes += 4 * (2 * S * NC + 1);             // cell starts
+  bytes += 16 * N;                           // sorted point records
+  bytes += 4 * (S * NC) * 2 + 4 * (S + 1) + (int64_t)scan_temp_bytes((uint32_t)(S * NC));
+  bytes += 16 * items;                       // work items
+  bytes += 8 * 3 * S * NB;                   // bins
+  bytes += 8 * 4 * S * NB;                   // C, W, K, L
+  bytes += 8 * 6 * NB + 8 * 2 * kMaxSteps + 4096;
+  I.device_bytes = bytes;
+  return RIPK_OK;
+}
+
+}  // namespace
+
+struct ripk_plan_s {
+  ripk_plan_desc desc;
+  Layout lay;
+  int device = 0;
+  int cus = 0;
+  int64_t S = 1;     // set capacity
+  int64_t items_cap = 0;
+  // device buffers
+  int32_t *x = nullptr, *y = nullptr, *t = nullptr;
+  uint32_t *keys[2] = {nullptr, nullptr}, *vals[2] = {nullptr, nullptr};
+  void *sort_temp = nullptr;
+  uint32_t *cs = nullptr;
+  int4 *P = nullptr;
+  uint32_t *chunks = nullptr, *offs = nullptr, *set_base = nullptr;
+  void *scan_temp = nullptr;
+  Item *items = nullptr;
+  unsigned long long *binC = nullptr, *binW = nullptr;
+  unsigned long long *outC = nullptr;
+  double *outW = nullptr, *outK = nullptr, *outL = nullptr;
+  double *env = nullptr, *Lobs = nullptr;
+  uint64_t *S2 = nullptr;
+  uint32_t *T = nullptr;
+  unsigned long long *scal = nullptr;  // [0] n_eval, [1] n_in, [2] err|n_items|item_ctr (u32s)
+  hipEvent_t ev[6] = {};
+  ripk_stats stats{};
+};
+
+namespace {
+
+template <typename T>
+hipError_t dalloc(T **p, size_t count) {
+  return hipMalloc((void **)p, std::max<size_t>(count, 1) * sizeof(T));
+}
+
+void release(ripk_plan_s *p) {
+  if (!p) return;
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(p->device);
+  void *bufs[] = {p->x, p->y, p->t, p->keys[0], p->keys[1], p->vals[0], p->vals[1],
+                  p->sort_temp, p->cs, p->P, p->chunks, p->offs, p->set_base, p->scan_temp,
+                  p->items, p->binC, p->binW, p->outC, p->outW, p->outK, p->outL, p->env,
+                  p->Lobs, p->S2, p->T, p->scal};
+  for (void *b : bufs)
+    if (b) (void)hipFree(b);
+  for (auto &e : p->ev)
+    if (e) (void)hipEventDestroy(e);
+  (void)hipSetDevice(prev);
+  delete p;
+}
+
+struct DeviceGuard {
+  int prev = 0;
+  explicit DeviceGuard(int dev) {
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() { (void)hipSetDevice(prev); }
+};
+
+// Runs the whole path over S sets of n points each.  For sims != 0 the points
+// are drawn on the device; otherwise keys come from (x, y, t).
+ripk_status run_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_centres, const int32_t *x,
+                     const int32_t *y, const int32_t *t, bool simulate, uint64_t seed,
+                     const double *L_obs, hipStream_t st, bool symmetric) {
+  const Geom &g = p->lay.g;
+  const uint32_t NB = (uint32_t)p->lay.info.n_bins;
+  const uint32_t N = S * n;
+  const bool timing = (p->desc.flags & RIPK_PLAN_TIMING) != 0;
+  if (timing) HIPCHK(hipEventRecord(p->ev[0], st));
+  uint32_t *err = (uint32_t *)(p->scal + 2);
+  uint32_t *n_items = err + 1;
+  uint32_t *item_ctr = err + 2;
+  HIPCHK(launch_fill_u64(p->scal, 4, 0ull, st));
+  if (simulate) {
+    HIPCHK(launch_csr(n, S, seed, g, p->x, p->y, p->t, p->keys[0], p->vals[0], st));
+    x = p->x; y = p->y; t = p->t;
+  } else {
+    HIPCHK(launch_keys(x, y, t, n, n_centres, 0, 1, g, p->keys[0], p->vals[0], err, st));
+  }
+  if (timing) HIPCHK(hipEventRecord(p->ev[1], st));
+  const uint64_t n_keys = (uint64_t)S * g.n_cells * 2;
+  int alt = 0;
+  HIPCHK(radix_sort(p->keys[0], p->vals[0], p->keys[1], p->vals[1], N, ceil_log2(n_keys),
+                    p->sort_temp, st, &alt));
+  HIPCHK(launch_cell_bounds(p->keys[alt], N, (uint32_t)n_keys, p->cs, st));
+  HIPCHK(launch_gather(p->vals[alt], N, x, y, t, g, p->lay.clamp_e, p->P, st));
+  HIPCHK(launch_items(p->cs, S, g, p->chunks, p->offs, p->set_base, p->items, n_items,
+                      p->scan_temp, st));
+  HIPCHK(launch_fill_u64(p->binC, (size_t)S * NB, 0ull, st));
+  HIPCHK(launch_fill_u64(p->binW, (size_t)S * NB * 2, 0ull, st));
+  if (timing) HIPCHK(hipEventRecord(p->ev[2], st));
+
+  PairArgs a;
+  a.g = g;
+  a.P = p->P;
+  a.cs = p->cs;
+  a.items = p->items;
+  a.n_items = n_items;
+  a.item_ctr = item_ctr;
+  a.S2 = p->S2;
+  a.T = p->T;
+  a.binC = p->binC;
+  a.binW = p->binW;
+  a.n_eval = p->scal;
+  a.symmetric = symmetric ? 1 : 0;
+  int per_cu = 0;
+  HIPCHK(pair_occupancy((int)NB, a.symmetric, (int)g.wide, &per_cu));
+  if (per_cu < 1) return fail(RIPK_EINVAL, "pair kernel does not fit on a compute unit (n_bins=%u)", NB);
+  const int64_t groups_cap = ((int64_t)S * (n / kChunk + g.n_cells + kItemsPerGroup)) / kItemsPerGroup + 1;
+  const int grid = (int)std::min<int64_t>((int64_t)per_cu * p->cus, groups_cap);
+  HIPCHK(launch_pair(a, grid, st));
+  if (timing) HIPCHK(hipEventRecord(p->ev[3], st));
+
+  const double AD = (double)(p->desc.x1 - p->desc.x0) * (double)(p->desc.y1 - p->desc.y0) *
+                    (double)(p->desc.t1 - p->desc.t0);
+  const double Nn = p->desc.norm == RIPK_NORM_N2 ? (double)n * (double)n
+                                                 : (double)n * (double)(n - 1);
+  HIPCHK(launch_finalize(p->binC, p->binW, S, g.n_s, g.n_t, (double)p->desc.s_max,
+                         (double)p->desc.t_max, AD, Nn, p->outC, p->outW, p->outK, p->outL,
+                         p->scal + 1, st));
+  if (simulate) {
+    if (L_obs) HIPCHK(hipMemcpyAsync(p->Lobs, L_obs, sizeof(double) * NB, hipMemcpyHostToDevice, st));
+    HIPCHK(launch_envelope(p->outK, p->outL, S, (int)NB, L_obs ? p->Lobs : nullptr, p->env, st));
+  }
+  if (timing) HIPCHK(hipEventRecord(p->ev[4], st));
+  p->stats.pair_grid = grid;
+  p->stats.symmetric = symmetric ? 1 : 0;
+  return RIPK_OK;
+}
+
+ripk_status collect_stats(ripk_plan_s *p, hipStream_t st, uint32_t S, uint32_t n,
+                          uint32_t *err_out) {
+  unsigned long long sc[4];
+  HIPCHK(hipMemcpyAsync(sc, p->scal, sizeof sc, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  const uint32_t *w = (const uint32_t *)(sc + 2);
+  *err_out = w[0];
+  p->stats.n_eval = (int64_t)sc[0];
+  p->stats.n_in = (int64_t)sc[1];
+  p->stats.n_items = (int64_t)w[1];
+  p->stats.n_sets = S;
+  p->stats.n_points = (int64_t)S * n;
+  if (p->desc.flags & RIPK_PLAN_TIMING) {
+    float ms[4] = {0, 0, 0, 0};
+    for (int i = 0; i < 4; ++i) HIPCHK(hipEventElapsedTime(&ms[i], p->ev[i], p->ev[i + 1]));
+    p->stats.us_gen = 1e3 * ms[0];
+    p->stats.us_grid = 1e3 * ms[1];
+    p->stats.us_pair = 1e3 * ms[2];
+    p->stats.us_finalize = 1e3 * ms[3];
+  }
+  return RIPK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *ripk_status_str(ripk_status s) {
+  switch (s) {
+    case RIPK_OK: return "ok";
+    case RIPK_PENDING: return "pending";
+    case RIPK_EINVAL: return "invalid argument";
+    case RIPK_ERANGE: return "point outside the study window";
+    case RIPK_ENOMEM: return "out of memory";
+    case RIPK_EDEVICE: return "device error";
+    case RIPK_E2BIG: return "request exceeds capacity";
+    case RIPK_EAGAIN: return "queue full";
+    case RIPK_EOVERFLOW: return "accumulator overflow";
+    case RIPK_ECANCELED: return "cancelled";
+    case RIPK_ENOTFOUND: return "unknown ticket";
+    default: return "unknown status";
+  }
+}
+
+const char *ripk_last_error(void) { return g_err.c_str(); }
+
+ripk_status ripk_plan_check(const ripk_plan_desc *desc, ripk_plan_info *info) {
+  Layout L;
+  ripk_status s = derive(desc, &L);
+  if (s != RIPK_OK) return s;
+  if (info) *info = L.info;
+  return RIPK_OK;
+}
+
+ripk_status ripk_plan(const ripk_plan_desc *desc, ripk_plan_t *out) {
+  if (!out) return fail(RIPK_EINVAL, "null output handle");
+  *out = nullptr;
+  Layout L;
+  ripk_status s = derive(desc, &L);
+  if (s != RIPK_OK) return s;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
+    return fail(RIPK_EDEVICE, "no HIP device available");
+  if (desc->device < 0 || desc->device >= ndev)
+    return fail(RIPK_EINVAL, "device %d out of range (have %d)", desc->device, ndev);
+  DeviceGuard dg(desc->device);
+  ripk_plan_s *p = new ripk_plan_s();
+  p->desc = *desc;
+  p->lay = L;
+  p->device = desc->device;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, p->device) != hipSuccess) {
+    release(p);
+    return fail(RIPK_EDEVICE, "hipGetDeviceProperties failed");
+  }
+  p->cus = prop.multiProcessorCount;
+  const int lds = pair_lds_bytes(L.info.n_bins);
+  if ((size_t)lds > prop.sharedMemPerBlock) {
+    release(p);
+    return fail(RIPK_EINVAL, "grid of %d bins needs %d B of LDS per workgroup, device has %zu",
+                L.info.n_bins, lds, (size_t)prop.sharedMemPerBlock);
+  }
+  const int64_t S = std::max<int64_t>(1, desc->m_max);
+  p->S = S;
+  const int64_t N = S * desc->n_max, NB = L.info.n_bins, NC = L.info.n_cells;
+  p->items_cap = S * (desc->n_max / kChunk + NC + kItemsPerGroup);
+  hipError_t e = hipSuccess;
+#define ALLOC(ptr, cnt) \
+  if (e == hipSuccess) e = dalloc(&(ptr), (size_t)(cnt))
+  ALLOC(p->x, N); ALLOC(p->y, N); ALLOC(p->t, N);
+  ALLOC(p->keys[0], N); ALLOC(p->keys[1], N); ALLOC(p->vals[0], N); ALLOC(p->vals[1], N);
+  if (e == hipSuccess) e = hipMalloc(&p->sort_temp, radix_sort_temp_bytes((uint32_t)N));
+  ALLOC(p->cs, 2 * S * NC + 1);
+  ALLOC(p->P, N);
+  ALLOC(p->chunks, S * NC); ALLOC(p->offs, S * NC + 1); ALLOC(p->set_base, S + 1);
+  if (e == hipSuccess) e = hipMalloc(&p->scan_temp, scan_temp_bytes((uint32_t)(S * NC)) + 256);
+  ALLOC(p->items, p->items_cap);
+  ALLOC(p->binC, S * NB); ALLOC(p->binW, 2 * S * NB);
+  ALLOC(p->outC, S * NB); ALLOC(p->outW, S * NB); ALLOC(p->outK, S * NB); ALLOC(p->outL, S * NB);
+  ALLOC(p->env, 5 * NB); ALLOC(p->Lobs, NB);
+  ALLOC(p->S2, kMaxSteps); ALLOC(p->T, kMaxSteps);
+  ALLOC(p->scal, 4);
+#undef ALLOC
+  if (e != hipSuccess) {
+    release(p);
+    return fail(e == hipErrorOutOfMemory ? RIPK_ENOMEM : RIPK_EDEVICE, "allocation failed: %s",
+                hipGetErrorString(e));
+  }
+  uint64_t S2h[kMaxSteps] = {0};
+  uint32_t Th[kMaxSteps] = {0};
+  for (int k = 0; k < desc->n_s; ++k) S2h[k] = (uint64_t)L.info.S2[k];
+  for (int l = 0; l < desc->n_t; ++l) Th[l] = (uint32_t)L.info.T[l];
+  e = hipMemcpy(p->S2, S2h, sizeof S2h, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p->T, Th, sizeof Th, hipMemcpyHostToDevice);
+  for (auto &ev : p->ev)
+    if (e == hipSuccess) e = hipEventCreate(&ev);
+  if (e != hipSuccess) {
+    release(p);
+    return fail(RIPK_EDEVICE, "plan set-up failed: %s", hipGetErrorString(e));
+  }
+  *out = p;
+  return RIPK_OK;
+}
+
+void ripk_plan_destroy(ripk_plan_t plan) { release(plan); }
+
+ripk_status ripk_compute_K(ripk_plan_t p, const ripk_points *pts, void *stream, ripk_K_out *out) {
+  if (!p || !pts) return fail(RIPK_EINVAL, "null plan or points");
+  const int64_t n = pts->n;
+  const int64_t nc = pts->n_centres ? pts->n_centres : n;
+  if (n < 2) return fail(RIPK_EINVAL, "need n >= 2 points (n(n-1) = 0 otherwise)");
+  if (n > p->desc.n_max) return fail(RIPK_EINVAL, "n = %lld exceeds n_max = %lld", (long long)n, (long long)p->desc.n_max);
+  if (nc < 0 || nc > n) return fail(RIPK_EINVAL, "n_centres must be in [0, n]");
+  if (!pts->x || !pts->y || !pts->t) return fail(RIPK_EINVAL, "null coordinate array");
+  auto t0 = std::chrono::steady_clock::now();
+  DeviceGuard dg(p->device);
+  hipStream_t st = (hipStream_t)stream;
+  const int32_t *x = pts->x, *y = pts->y, *t = pts->t;
+  if (!pts->on_device) {
+    HIPCHK(hipMemcpyAsync(p->x, x, sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(p->y, y, sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(p->t, t, sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
+    x = p->x; y = p->y; t = p->t;
+  }
+  const bool sym = !(p->desc.flags & RIPK_PLAN_ORDERED) && nc == n;
+  ripk_status s = run_sets(p, 1, (uint32_t)n, (uint32_t)nc, x, y, t, false, 0, nullptr, st, sym);
+  if (s != RIPK_OK) return s;
+  uint32_t err = 0;
+  s = collect_stats(p, st, 1, (uint32_t)n, &err);
+  if (s != RIPK_OK) return s;
+  if (err) return fail(RIPK_ERANGE, "a point lies outside the study window");
+  const size_t NB = (size_t)p->lay.info.n_bins;
+  if (out) {
+    if (out->C) HIPCHK(hipMemcpyAsync(out->C, p->outC, 8 * NB, hipMemcpyDeviceToHost, st));
+    if (out->W) HIPCHK(hipMemcpyAsync(out->W, p->outW, 8 * NB, hipMemcpyDeviceToHost, st));
+    if (out->K) HIPCHK(hipMemcpyAsync(out->K, p->outK, 8 * NB, hipMemcpyDeviceToHost, st));
+    if (out->L) HIPCHK(hipMemcpyAsync(out->L, p->outL, 8 * NB, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  p->stats.us_total = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
+  return RIPK_OK;
+}
+
+ripk_status ripk_simulate_envelope(ripk_plan_t p, int64_t n, int32_t m, uint64_t seed,
+                                   const double *L_obs, void *stream, ripk_env_out *out) {
+  if (!p) return fail(RIPK_EINVAL, "null plan");
+  if (n < 2) return fail(RIPK_EINVAL, "need n >= 2 points");
+  if (n > p->desc.n_max) return fail(RIPK_EINVAL, "n = %lld exceeds n_max = %lld", (long long)n, (long long)p->desc.n_max);
+  if (m < 1 || m > p->desc.m_max) return fail(RIPK_EINVAL, "m = %d outside [1, m_max = %d]", m, p->desc.m_max);
+  auto t0 = std::chrono::steady_clock::now();
+  DeviceGuard dg(p->device);
+  hipStream_t st = (hipStream_t)stream;
+  const bool sym = !(p->desc.flags & RIPK_PLAN_ORDERED);
+  ripk_status s = run_sets(p, (uint32_t)m, (uint32_t)n, (uint32_t)n, nullptr, nullptr, nullptr,
+                           true, seed, L_obs, st, sym);
+  if (s != RIPK_OK) return s;
+  uint32_t err = 0;
+  s = collect_stats(p, st, (uint32_t)m, (uint32_t)n, &err);
+  if (s != RIPK_OK) return s;
+  const size_t NB = (size_t)p->lay.info.n_bins;
+  if (out) {
+    double *rows[5] = {out->K_lo, out->K_hi, out->L_lo, out->L_hi, L_obs ? out->dL_hi : nullptr};
+    for (int r = 0; r < 5; ++r)
+      if (rows[r]) HIPCHK(hipMemcpyAsync(rows[r], p->env + r * NB, 8 * NB, hipMemcpyDeviceToHost, st));
+    if (out->C_sims) HIPCHK(hipMemcpyAsync(out->C_sims, p->outC, 8 * NB * m, hipMemcpyDeviceToHost, st));
+    if (out->W_sims) HIPCHK(hipMemcpyAsync(out->W_sims, p->outW, 8 * NB * m, hipMemcpyDeviceToHost, st));
+    if (out->K_sims) HIPCHK(hipMemcpyAsync(out->K_sims, p->outK, 8 * NB * m, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  p->stats.us_total = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
+  return RIPK_OK;
+}
+
+ripk_status ripk_plan_stats(ripk_plan_t p, ripk_stats *out) {
+  if (!p || !out) return fail(RIPK_EINVAL, "null plan or output");
+  *out = p->stats;
+  return RIPK_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,118 @@
+// Cumulation, normalisation and envelopes on gfx950.
+//
+// The pair kernel leaves, per set, a histogram over the smallest grid step
+// (k, l) containing each pair.  Because the indicator of Eq. 3 is monotone in
+// s and t and the weights do not depend on the threshold, the sums of Eq. 2 at
+// every grid point are the 2-D inclusive prefix sums of that histogram.  This
+// file forms them (exact integers: counts in u64, weights in 128-bit fixed point
+// with 23 fraction bits), then K = A*D*W/N (Eq. 2) and L = sqrt(K/(2 pi t)) - s
+// (Eq. 4) in FP64, and the pointwise min/max envelopes over simulations (Sec. 3).
+#include "ripk_internal.h"
+
+namespace ripk {
+
+namespace {
+
+__device__ __forceinline__ void add128(unsigned long long &lo, unsigned long long &hi,
+                                       unsigned long long blo, unsigned long long bhi) {
+  unsigned long long r = lo + blo;
+  hi += bhi + (r < lo ? 1ull : 0ull);
+  lo = r;
+}
+
+// One workgroup per set.  binC/binW are cumulated in place.
+__global__ void k_finalize(unsigned long long *__restrict__ binC,
+                           unsigned long long *__restrict__ binW, int n_s, int n_t,
+                           double s_max, double t_max, double AD, double N,
+                           unsigned long long *__restrict__ C, double *__restrict__ W,
+                           double *__restrict__ K, double *__restrict__ L,
+                           unsigned long long *__restrict__ n_in) {
+  const int set = blockIdx.x;
+  const int nb = n_s * n_t;
+  unsigned long long *c = binC + (size_t)set * nb;
+  unsigned long long *w = binW + (size_t)set * nb * 2;
+  // prefix along t within each s row
+  for (int k = threadIdx.x; k < n_s; k += blockDim.x) {
+    unsigned long long rc = 0, rlo = 0, rhi = 0;
+    for (int l = 0; l < n_t; ++l) {
+      int b = k * n_t + l;
+      rc += c[b];
+      add128(rlo, rhi, w[2 * b], w[2 * b + 1]);
+      c[b] = rc;
+      w[2 * b] = rlo;
+      w[2 * b + 1] = rhi;
+    }
+  }
+  __threadfence_block();
+  __syncthreads();
+  // prefix along s within each t column
+  for (int l = threadIdx.x; l < n_t; l += blockDim.x) {
+    unsigned long long rc = 0, rlo = 0, rhi = 0;
+    for (int k = 0; k < n_s; ++k) {
+      int b = k * n_t + l;
+      rc += c[b];
+      add128(rlo, rhi, w[2 * b], w[2 * b + 1]);
+      c[b] = rc;
+      w[2 * b] = rlo;
+      w[2 * b + 1] = rhi;
+    }
+  }
+  __threadfence_block();
+  __syncthreads();
+  const double two_pi = 6.283185307179586476925286766559;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+    int k = b / n_t, l = b - k * n_t;
+    // W = (hi * 2^64 + lo) * 2^-23
+    double wv = ldexp((double)w[2 * b + 1], 64 - kFracBits) + ldexp((double)w[2 * b], -kFracBits);
+    double Kv = AD * wv / N;
+    double sk = (double)(k + 1) * s_max / (double)n_s;
+    double tl = (double)(l + 1) * t_max / (double)n_t;
+    size_t o = (size_t)set * nb + b;
+    C[o] = c[b];
+    W[o] = wv;
+    K[o] = Kv;
+    L[o] = sqrt(Kv / (two_pi * tl)) - sk;
+  }
+  if (threadIdx.x == 0) atomicAdd(n_in, c[nb - 1]);
+}
+
+// env rows: K_lo, K_hi, L_lo, L_hi, dL_hi
+__global__ void k_envelope(const double *__restrict__ K, const double *__restrict__ L,
+                           uint32_t m, int nb, const double *__restrict__ L_obs,
+                           double *__restrict__ env) {
+  int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  double klo = K[b], khi = K[b], llo = L[b], lhi = L[b];
+  for (uint32_t s = 1; s < m; ++s) {
+    double kv = K[(size_t)s * nb + b], lv = L[(size_t)s * nb + b];
+    klo = fmin(klo, kv);
+    khi = fmax(khi, kv);
+    llo = fmin(llo, lv);
+    lhi = fmax(lhi, lv);
+  }
+  env[b] = klo;
+  env[nb + b] = khi;
+  env[2 * nb + b] = llo;
+  env[3 * nb + b] = lhi;
+  env[4 * nb + b] = L_obs ? L_obs[b] - lhi : 0.0;
+}
+
+}  // namespace
+
+hipError_t launch_finalize(unsigned long long *binC, unsigned long long *binW, uint32_t n_sets,
+                           int n_s, int n_t, double s_max, double t_max, double AD, double N,
+                           unsigned long long *C, double *W, double *K, double *L,
+                           unsigned long long *n_in, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(n_sets), dim3(256), 0, s, binC, binW, n_s, n_t, s_max,
+                     t_max, AD, N, C, W, K, L, n_in);
+  return hipGetLastError();
+}
+
+hipError_t launch_envelope(const double *K, const double *L, uint32_t m, int n_bins,
+                           const double *L_obs, double *env, hipStream_t s) {
+  hipLaunchKernelGGL(k_envelope, dim3((n_bins + 255) / 256), dim3(256), 0, s, K, L, m, n_bins,
+                     L_obs, env);
+  return hipGetLastError();
+}
+
+}  // namespace ripk

@@ -1,0 +1,461 @@
+// Cell-grid construction on gfx950: cell keys, on-device Monte Carlo CSR points
+// (Philox4x64-10), a stable LSD radix sort, cell bounds, the sorted point
+// records and the work items of the pair kernel.
+//
+// The uniform space-time cell grid stands in for the paper's R-tree (Sec. 4.2):
+// with cells at least s_max wide in x and y and t_max long in t, every neighbour
+// of a centre within (s_max, t_max) lies in the 3x3x3 block of cells around it.
+#include "ripk_internal.h"
+
+namespace ripk {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ uint32_t cell_of(int32_t x, int32_t y, int32_t t, const Geom &g,
+                                            bool *outside) {
+  bool bad = x < g.x0 || x > g.x1 || y < g.y0 || y > g.y1 || t < g.t0 || t > g.t1;
+  *outside = bad;
+  // Clamp so that a bad point still maps to a valid cell; the call reports
+  // the error and discards every result.
+  uint32_t X = (uint32_t)(min(max(x, g.x0), g.x1) - g.x0);
+  uint32_t Y = (uint32_t)(min(max(y, g.y0), g.y1) - g.y0);
+  uint32_t T = (uint32_t)(min(max(t, g.t0), g.t1) - g.t0);
+  // the last cell of an axis absorbs the remainder, so it is never narrower
+  // than the cell edge
+  uint32_t cx = min(X / (uint32_t)g.cell_s, (uint32_t)g.nx - 1u);
+  uint32_t cy = min(Y / (uint32_t)g.cell_s, (uint32_t)g.ny - 1u);
+  uint32_t ct = min(T / (uint32_t)g.cell_t, (uint32_t)g.nt - 1u);
+  return (ct * (uint32_t)g.ny + cy) * (uint32_t)g.nx + cx;
+}
+
+// key = ((set * n_cells + cell) << 1) | halo ; val = global point index
+__global__ void k_keys(const int32_t *__restrict__ x, const int32_t *__restrict__ y,
+                       const int32_t *__restrict__ t, uint32_t n, uint32_t n_centres,
+                       uint32_t set_base, Geom g, uint32_t *__restrict__ keys,
+                       uint32_t *__restrict__ vals, uint32_t *__restrict__ err) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  bool bad;
+  uint32_t c = cell_of(x[i], y[i], t[i], g, &bad);
+  if (bad) atomicOr(err, 1u);
+  keys[i] = ((set_base * g.n_cells + c) << 1) | (i >= n_centres ? 1u : 0u);
+  vals[i] = i;
+}
+
+// ---- Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11) -----------------------
+struct U64x4 {
+  uint64_t v[4];
+};
+
+__device__ __forceinline__ U64x4 philox4x64_10(U64x4 c, uint64_t k0, uint64_t k1) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    uint64_t p0h = __umul64hi(M0, c.v[0]), p0l = M0 * c.v[0];
+    uint64_t p1h = __umul64hi(M1, c.v[2]), p1l = M1 * c.v[2];
+    U64x4 o;
+    o.v[0] = p1h ^ c.v[1] ^ k0;
+    o.v[1] = p1l;
+    o.v[2] = p0h ^ c.v[3] ^ k1;
+    o.v[3] = p0l;
+    c = o;
+    k0 += W0;
+    k1 += W1;
+  }
+  return c;
+}
+
+// Simulation s, point i: counter (i, s, 0, 0), key (seed, 0).  Coordinates on
+// the half-open window by 64x64 multiply-high.  Writes the SoA points and the
+// (key, value) pairs for the sort, sets ordered simulation-major.
+__global__ void k_csr(uint32_t n, uint32_t m, uint64_t seed, Geom g, int32_t *__restrict__ x,
+                      int32_t *__restrict__ y, int32_t *__restrict__ t,
+                      uint32_t *__restrict__ keys, uint32_t *__restrict__ vals) {
+  uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (uint64_t)n * m) return;
+  uint32_t s = (uint32_t)(gid / n), i = (uint32_t)(gid - (uint64_t)s * n);
+  U64x4 c;
+  c.v[0] = i;
+  c.v[1] = s;
+  c.v[2] = 0;
+  c.v[3] = 0;
+  U64x4 r = philox4x64_10(c, seed, 0);
+  uint64_t W = (uint64_t)(g.x1 - g.x0), H = (uint64_t)(g.y1 - g.y0), D = (uint64_t)(g.t1 - g.t0);
+  int32_t px = g.x0 + (int32_t)__umul64hi(r.v[0], W);
+  int32_t py = g.y0 + (int32_t)__umul64hi(r.v[1], H);
+  int32_t pt = g.t0 + (int32_t)__umul64hi(r.v[2], D);
+  x[gid] = px;
+  y[gid] = py;
+  t[gid] = pt;
+  bool bad;
+  uint32_t cell = cell_of(px, py, pt, g, &bad);
+  keys[gid] = (s * g.n_cells + cell) << 1;
+  vals[gid] = (uint32_t)gid;
+}
+
+// ---- exclusive scan of uint32 (3 phases) ------------------------------------
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kThreads * kScanItems;
+
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *lds,
+                                                         uint32_t *total) {
+  // lds: kThreads/64 + 1 words
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint32_t incl = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t nb = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += nb;
+  }
+  if (lane == 63) lds[w] = incl;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
+      uint32_t c = lds[i];
+      lds[i] = run;
+      run += c;
+    }
+    lds[blockDim.x >> 6] = run;
+  }
+  __syncthreads();
+  uint32_t res = lds[w] + incl - v;
+  *total = lds[blockDim.x >> 6];
+  __syncthreads();
+  return res;
+}
+
+__global__ void k_scan_reduce(const uint32_t *__restrict__ in, uint32_t n,
+                              uint32_t *__restrict__ part) {
+  __shared__ uint32_t lds[kThreads / 64 + 1];
+  uint32_t base = blockIdx.x * kScanTile;
+  uint32_t s = 0;
+  for (int k = 0; k < kScanItems; ++k) {
+    uint32_t i = base + k * kThreads + threadIdx.x;
+    if (i < n) s += in[i];
+  }
+  uint32_t tot;
+  block_exclusive_scan(s, lds, &tot);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+// single block: exclusive scan of part[0..nb) in place, part[nb] = total
+__global__ void k_scan_partials(uint32_t *part, uint32_t nb) {
+  __shared__ uint32_t lds[kThreads / 64 + 1];
+  uint32_t per = (nb + kThreads - 1) / kThreads;
+  uint32_t b0 = threadIdx.x * per;
+  uint32_t s = 0;
+  for (uint32_t k = 0; k < per; ++k)
+    if (b0 + k < nb) s += part[b0 + k];
+  uint32_t tot;
+  uint32_t run = block_exclusive_scan(s, lds, &tot);
+  for (uint32_t k = 0; k < per; ++k)
+    if (b0 + k < nb) {
+      uint32_t c = part[b0 + k];
+      part[b0 + k] = run;
+      run += c;
+    }
+  if (threadIdx.x == 0) part[nb] = tot;
+}
+
+__global__ void k_scan_down(const uint32_t *__restrict__ in, uint32_t n,
+                            const uint32_t *__restrict__ part, uint32_t *__restrict__ out) {
+  __shared__ uint32_t lds[kThreads / 64 + 1];
+  __shared__ uint32_t tile[kScanTile];
+  uint32_t base = blockIdx.x * kScanTile;
+  for (int k = 0; k < kScanItems; ++k) {
+    uint32_t i = base + k * kThreads + threadIdx.x;
+    tile[k * kThreads + threadIdx.x] = i < n ? in[i] : 0u;
+  }
+  __syncthreads();
+  uint32_t loc[kScanItems];
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    loc[k] = tile[threadIdx.x * kScanItems + k];
+    s += loc[k];
+  }
+  uint32_t tot;
+  uint32_t run = block_exclusive_scan(s, lds, &tot) + part[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    tile[threadIdx.x * kScanItems + k] = run;
+    run += loc[k];
+  }
+  __syncthreads();
+  for (int k = 0; k < kScanItems; ++k) {
+    uint32_t i = base + k * kThreads + threadIdx.x;
+    if (i < n) out[i] = tile[k * kThreads + threadIdx.x];
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = part[gridDim.x];
+}
+
+// ---- stable LSD radix sort, 8-bit digits --------------------------------------
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kThreads * kSortItems;
+
+__global__ void k_sort_hist(const uint32_t *__restrict__ keys, uint32_t n, int shift,
+                            uint32_t mask, uint32_t nblocks, uint32_t *__restrict__ counts) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  uint32_t base = blockIdx.x * kSortTile;
+  for (int k = 0; k < kSortItems; ++k) {
+    uint32_t i = base + k * kThreads + threadIdx.x;
+    if (i < n) atomicAdd(&h[(keys[i] >> shift) & mask], 1u);
+  }
+  __syncthreads();
+  counts[threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+// Tile order is round-major (round k holds items base + k*256 + tid), so a key's
+// stable rank is: keys of its digit in earlier rounds + in earlier waves of the
+// same round + in lower lanes of the same wave.
+__global__ void k_sort_scatter(const uint32_t *__restrict__ keys,
+                               const uint32_t *__restrict__ vals, uint32_t n, int shift,
+                               int nbits, uint32_t nblocks, const uint32_t *__restrict__ offs,
+                               uint32_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out) {
+  __shared__ uint32_t run[256];
+  __shared__ uint32_t wc[kThreads / 64][256];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint32_t mask = (1u << nbits) - 1u;
+  run[threadIdx.x] = offs[threadIdx.x * nblocks + blockIdx.x];
+  for (int q = 0; q < kThreads / 64; ++q) wc[q][threadIdx.x] = 0;
+  __syncthreads();
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  uint32_t base = blockIdx.x * kSortTile;
+  for (int k = 0; k < kSortItems; ++k) {
+    uint32_t i = base + k * kThreads + threadIdx.x;
+    bool valid = i < n;
+    uint32_t key = valid ? keys[i] : 0u;
+    uint32_t val = valid ? vals[i] : 0u;
+    uint32_t d = (key >> shift) & mask;
+    uint64_t peers = __ballot(valid);
+    for (int b = 0; b < nbits; ++b) {
+      uint64_t bb = __ballot((d >> b) & 1u);
+      peers &= ((d >> b) & 1u) ? bb : ~bb;
+    }
+    uint32_t rank = (uint32_t)__popcll(peers & lt);
+    if (valid && (peers & lt) == 0) wc[w][d] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    if (valid) {
+      uint32_t pos = run[d] + rank;
+      for (int q = 0; q < w; ++q) pos += wc[q][d];
+      keys_out[pos] = key;
+      vals_out[pos] = val;
+    }
+    __syncthreads();
+    {
+      uint32_t add = 0;
+      for (int q = 0; q < kThreads / 64; ++q) {
+        add += wc[q][threadIdx.x];
+        wc[q][threadIdx.x] = 0;
+      }
+      run[threadIdx.x] += add;
+    }
+    __syncthreads();
+  }
+}
+
+// cs[k] = first index whose key >= k, for k in [0, n_keys]
+__global__ void k_cell_bounds(const uint32_t *__restrict__ keys, uint32_t n, uint32_t n_keys,
+                              uint32_t *__restrict__ cs) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > n) return;
+  int64_t prev = (i == 0) ? -1 : (int64_t)keys[i - 1];
+  int64_t cur = (i == n) ? (int64_t)n_keys : (int64_t)keys[i];
+  for (int64_t k = prev + 1; k <= cur; ++k) cs[k] = i;
+}
+
+// Sorted point records: window-relative coordinates (all >= 0) and the distance
+// to the nearest side clamped to s_max (a circle no larger than that is whole).
+__global__ void k_gather(const uint32_t *__restrict__ vals, uint32_t n,
+                         const int32_t *__restrict__ x, const int32_t *__restrict__ y,
+                         const int32_t *__restrict__ t, Geom g, int32_t clamp_e,
+                         int4 *__restrict__ P) {
+  uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  uint32_t i = vals[r];
+  int32_t X = x[i] - g.x0, Y = y[i] - g.y0, T = t[i] - g.t0;
+  int32_t e = min(min(X, g.x1 - g.x0 - X), min(Y, g.y1 - g.y0 - Y));
+  e = min(max(e, 0), clamp_e);
+  P[r] = make_int4(X, Y, T, e);
+}
+
+__global__ void k_chunks(const uint32_t *__restrict__ cs, uint32_t ncell_total,
+                         uint32_t *__restrict__ chunks) {
+  uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ncell_total) return;
+  uint32_t c = cs[2 * g + 1] - cs[2 * g];
+  chunks[g] = (c + kChunk - 1) / kChunk;
+}
+
+// per set: padded item base so that every group of kItemsPerGroup items lies in one set
+__global__ void k_set_base(const uint32_t *__restrict__ offs, uint32_t n_sets,
+                           uint32_t n_cells, uint32_t *__restrict__ set_base,
+                           uint32_t *__restrict__ n_items) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  uint32_t run = 0;
+  for (uint32_t s = 0; s < n_sets; ++s) {
+    set_base[s] = run;
+    uint32_t tot = offs[(s + 1) * n_cells] - offs[s * n_cells];
+    run += (tot + kItemsPerGroup - 1) / kItemsPerGroup * kItemsPerGroup;
+  }
+  set_base[n_sets] = run;
+  *n_items = run;
+}
+
+__global__ void k_emit(const uint32_t *__restrict__ cs, const uint32_t *__restrict__ offs,
+                       const uint32_t *__restrict__ set_base, uint32_t n_sets, uint32_t n_cells,
+                       Item *__restrict__ items) {
+  uint32_t gidx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gidx >= n_sets * n_cells) return;
+  uint32_t s = gidx / n_cells, c = gidx - s * n_cells;
+  uint32_t o = set_base[s] + offs[gidx] - offs[s * n_cells];
+  uint32_t b = cs[2 * gidx], cnt = cs[2 * gidx + 1] - b;
+  for (uint32_t q = 0; q * kChunk < cnt; ++q) {
+    Item it;
+    it.set = s;
+    it.cell = c;
+    it.begin = b + q * kChunk;
+    it.count = min((uint32_t)kChunk, cnt - q * kChunk);
+    items[o + q] = it;
+  }
+  if (c == n_cells - 1) {
+    uint32_t end = set_base[s] + offs[(s + 1) * n_cells] - offs[s * n_cells];
+    for (uint32_t p = end; p < set_base[s + 1]; ++p) {
+      Item it;
+      it.set = s;
+      it.cell = 0;
+      it.begin = 0;
+      it.count = 0;
+      items[p] = it;
+    }
+  }
+}
+
+__global__ void k_fill_u64(unsigned long long *p, size_t n, unsigned long long v) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = v;
+}
+
+inline uint32_t blocks_for(uint64_t n, int per) { return (uint32_t)((n + per - 1) / per); }
+
+}  // namespace
+
+hipError_t launch_keys(const int32_t *x, const int32_t *y, const int32_t *t, uint32_t n,
+                       uint32_t n_centres, uint32_t set_base, uint32_t n_sets, const Geom &g,
+                       uint32_t *keys, uint32_t *vals, uint32_t *err, hipStream_t s) {
+  (void)n_sets;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_keys, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, s, x, y, t, n,
+                     n_centres, set_base, g, keys, vals, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_csr(uint32_t n, uint32_t m, uint64_t seed, const Geom &g, int32_t *x,
+                      int32_t *y, int32_t *t, uint32_t *keys, uint32_t *vals, hipStream_t s) {
+  uint64_t tot = (uint64_t)n * m;
+  if (tot == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_csr, dim3(blocks_for(tot, kThreads)), dim3(kThreads), 0, s, n, m, seed,
+                     g, x, y, t, keys, vals);
+  return hipGetLastError();
+}
+
+size_t scan_temp_bytes(uint32_t n) {
+  return sizeof(uint32_t) * ((size_t)blocks_for(n, kScanTile) + 1);
+}
+
+hipError_t exclusive_scan(const uint32_t *in, uint32_t *out, uint32_t n, void *temp,
+                          hipStream_t s) {
+  uint32_t nb = blocks_for(n, kScanTile);
+  uint32_t *part = (uint32_t *)temp;
+  if (n == 0) {
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kThreads), 0, s, out, 0u);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kThreads), 0, s, in, n, part);
+  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kThreads), 0, s, part, nb);
+  hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kThreads), 0, s, in, n, part, out);
+  return hipGetLastError();
+}
+
+size_t radix_sort_temp_bytes(uint32_t n) {
+  size_t nb = blocks_for(n > 0 ? n : 1, kSortTile);
+  size_t cnt = 256 * nb;
+  return sizeof(uint32_t) * (2 * cnt + 1) + scan_temp_bytes((uint32_t)cnt) + 256;
+}
+
+hipError_t radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt,
+                      uint32_t n, int key_bits, void *temp, hipStream_t s, int *result_in_alt) {
+  *result_in_alt = 0;
+  if (n <= 1 || key_bits <= 0) return hipSuccess;
+  uint32_t nb = blocks_for(n, kSortTile);
+  size_t cnt = 256 * (size_t)nb;
+  uint32_t *counts = (uint32_t *)temp;
+  uint32_t *offs = counts + cnt;
+  void *stemp = (void *)(((uintptr_t)(offs + cnt + 1) + 255) & ~(uintptr_t)255);
+  uint32_t *ka = keys, *va = vals, *kb = keys_alt, *vb = vals_alt;
+  int alt = 0;
+  for (int shift = 0; shift < key_bits; shift += 8) {
+    int nbits = key_bits - shift < 8 ? key_bits - shift : 8;
+    uint32_t mask = (1u << nbits) - 1u;
+    hipLaunchKernelGGL(k_sort_hist, dim3(nb), dim3(kThreads), 0, s, ka, n, shift, mask, nb,
+                       counts);
+    hipError_t e = exclusive_scan(counts, offs, (uint32_t)cnt, stemp, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sort_scatter, dim3(nb), dim3(kThreads), 0, s, ka, va, n, shift, nbits,
+                       nb, offs, kb, vb);
+    uint32_t *tk = ka, *tv = va;
+    ka = kb; va = vb; kb = tk; vb = tv;
+    alt ^= 1;
+  }
+  *result_in_alt = alt;
+  return hipGetLastError();
+}
+
+hipError_t launch_cell_bounds(const uint32_t *keys, uint32_t n, uint32_t n_keys, uint32_t *cs,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_cell_bounds, dim3(blocks_for((uint64_t)n + 1, kThreads)), dim3(kThreads),
+                     0, s, keys, n, n_keys, cs);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(const uint32_t *vals, uint32_t n, const int32_t *x, const int32_t *y,
+                         const int32_t *t, const Geom &g, int32_t clamp_e, int4 *P,
+                         hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, s, vals, n, x,
+                     y, t, g, clamp_e, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_items(const uint32_t *cs, uint32_t n_sets, const Geom &g, uint32_t *chunks,
+                        uint32_t *offs, uint32_t *set_base, Item *items, uint32_t *n_items,
+                        void *scan_temp, hipStream_t s) {
+  uint32_t tot = n_sets * g.n_cells;
+  hipLaunchKernelGGL(k_chunks, dim3(blocks_for(tot, kThreads)), dim3(kThreads), 0, s, cs, tot,
+                     chunks);
+  hipError_t e = exclusive_scan(chunks, offs, tot, scan_temp, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_set_base, dim3(1), dim3(64), 0, s, offs, n_sets, g.n_cells, set_base,
+                     n_items);
+  hipLaunchKernelGGL(k_emit, dim3(blocks_for(tot, kThreads)), dim3(kThreads), 0, s, cs, offs,
+                     set_base, n_sets, g.n_cells, items);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(unsigned long long *p, size_t n, unsigned long long v,
+                           hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  uint32_t nb = blocks_for(n, kThreads);
+  if (nb > 4096) nb = 4096;
+  hipLaunchKernelGGL(k_fill_u64, dim3(nb), dim3(kThreads), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+}  // namespace ripk

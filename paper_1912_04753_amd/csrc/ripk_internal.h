@@ -1,0 +1,88 @@
+// Internal interfaces between the host runtime (api.cpp) and the gfx950
+// kernels (*.hip).  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ripk {
+
+constexpr int kMaxSteps = 64;      // n_s, n_t <= 64
+constexpr int kChunk = 64;         // centres per work item = one wavefront
+constexpr int kItemsPerGroup = 4;  // work items grabbed together by one workgroup
+constexpr int kPairThreads = 256;  // workgroup size of the pair kernel (4 wavefronts)
+constexpr int kFracBits = 23;      // fixed-point fraction bits of the weight sums
+
+// Geometry and thresholds shared by the grid and pair kernels (by value).
+struct Geom {
+  int32_t x0, y0, x1, y1, t0, t1;  // closed window; all coordinates are int32
+  int32_t cell_s, cell_t;          // cell edge (metres, seconds)
+  int32_t nx, ny, nt;              // cells per axis
+  int32_t rs, rt;                  // stencil half-width in cells
+  uint32_t n_cells;                // nx*ny*nt
+  int32_t n_s, n_t;
+  uint32_t edge;
+  uint32_t wide;                   // 64-bit squared distances
+  uint64_t s2max;                  // S2[n_s-1]
+  uint32_t tmax;                   // T[n_t-1]
+  float inv_ds;                    // n_s / s_max
+  float inv_dt;                    // n_t / t_max
+};
+
+// Work item of the pair kernel: up to kChunk centres of one cell of one set.
+struct Item {
+  uint32_t set;
+  uint32_t cell;   // cell index within the set
+  uint32_t begin;  // first centre, index into the sorted point array
+  uint32_t count;  // number of centres (0 = padding)
+};
+
+struct PairArgs {
+  Geom g;
+  const int4 *P;          // sorted points: x, y, t, min(edge distance)
+  const uint32_t *cs;     // cell starts: 2*n_cells*n_sets + 1 entries
+  const Item *items;
+  const uint32_t *n_items;  // device scalar
+  uint32_t *item_ctr;       // device scalar, zeroed before launch
+  const uint64_t *S2;       // n_s thresholds (device)
+  const uint32_t *T;        // n_t thresholds (device)
+  unsigned long long *binC;  // [sets][n_bins] counts
+  unsigned long long *binW;  // [sets][n_bins][2] 128-bit fixed-point weight sums
+  unsigned long long *n_eval;  // device scalar
+  int symmetric;
+};
+
+// ---- launchers (kernels.hip) ----------------------------------------------
+hipError_t launch_keys(const int32_t *x, const int32_t *y, const int32_t *t, uint32_t n,
+                       uint32_t n_centres, uint32_t set_base, uint32_t n_sets,
+                       const Geom &g, uint32_t *keys, uint32_t *vals, uint32_t *err,
+                       hipStream_t s);
+hipError_t launch_csr(uint32_t n, uint32_t m, uint64_t seed, const Geom &g, int32_t *x,
+                      int32_t *y, int32_t *t, uint32_t *keys, uint32_t *vals,
+                      hipStream_t s);
+size_t radix_sort_temp_bytes(uint32_t n);
+hipError_t radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt,
+                      uint32_t n, int key_bits, void *temp, hipStream_t s, int *result_in_alt);
+size_t scan_temp_bytes(uint32_t n);
+hipError_t exclusive_scan(const uint32_t *in, uint32_t *out, uint32_t n, void *temp,
+                          hipStream_t s);
+hipError_t launch_cell_bounds(const uint32_t *keys, uint32_t n, uint32_t n_keys,
+                              uint32_t *cs, hipStream_t s);
+hipError_t launch_gather(const uint32_t *vals, uint32_t n, const int32_t *x, const int32_t *y,
+                         const int32_t *t, const Geom &g, int32_t clamp_e, int4 *P,
+                         hipStream_t s);
+hipError_t launch_items(const uint32_t *cs, uint32_t n_sets, const Geom &g, uint32_t *chunks,
+                        uint32_t *offs, uint32_t *set_base, Item *items, uint32_t *n_items,
+                        void *scan_temp, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long *p, size_t n, unsigned long long v,
+                           hipStream_t s);
+hipError_t launch_pair(const PairArgs &a, int grid, hipStream_t s);
+int pair_lds_bytes(int n_bins);
+hipError_t pair_occupancy(int n_bins, int symmetric, int wide, int *per_cu);
+hipError_t launch_finalize(unsigned long long *binC, unsigned long long *binW,
+                           uint32_t n_sets, int n_s, int n_t, double s_max, double t_max,
+                           double AD, double N, unsigned long long *C, double *W, double *K,
+                           double *L, unsigned long long *n_in, hipStream_t s);
+hipError_t launch_envelope(const double *K, const double *L, uint32_t m, int n_bins,
+                           const double *L_obs, double *env, hipStream_t s);
+
+}  // namespace ripk

@@ -1,0 +1,274 @@
+"""Python binding of the ripk C ABI (``include/ripk.h``) -- argument marshalling only.
+
+Every step of the computation runs in ``libripk.so`` (HIP kernels for gfx950).
+This module converts arguments and results: numpy arrays are passed as host
+buffers, torch CUDA tensors as device pointers ordered on the caller's current
+torch stream (torch serves only as the device allocator and stream source).
+Function names follow the C ABI.  There is no fallback: if the library is not
+built, every call raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libripk.so")
+
+RIPK_OK = 0
+RIPK_PENDING = 1
+RIPK_EINVAL = -1
+RIPK_ERANGE = -2
+RIPK_ENOMEM = -3
+RIPK_EDEVICE = -4
+RIPK_E2BIG = -5
+RIPK_EAGAIN = -6
+RIPK_EOVERFLOW = -7
+RIPK_ECANCELED = -8
+RIPK_ENOTFOUND = -9
+
+RIPK_EDGE_SPATIAL_ISO = 1
+RIPK_EDGE_TEMPORAL = 2
+RIPK_EDGE_ISO = 3
+RIPK_NORM_NN1 = 0
+RIPK_NORM_N2 = 1
+RIPK_SIM_CSR = 0
+RIPK_PLAN_ORDERED = 1
+RIPK_PLAN_TIMING = 2
+
+_i64, _i32, _u32, _u64, _f64 = (ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32,
+                                ctypes.c_uint64, ctypes.c_double)
+_P = ctypes.POINTER
+
+
+class PlanDesc(ctypes.Structure):
+    _fields_ = [("x0", _i64), ("y0", _i64), ("x1", _i64), ("y1", _i64),
+                ("t0", _i64), ("t1", _i64), ("s_max", _i64), ("t_max", _i64),
+                ("n_s", _i32), ("n_t", _i32), ("edge", _u32), ("norm", _u32),
+                ("sim_method", _u32), ("n_max", _i64), ("m_max", _i32), ("flags", _u32),
+                ("device", _i32), ("cell_div", _i32), ("tcell_div", _i32)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("S2", _i64 * 64), ("T", _i64 * 64), ("cell_s", _i64), ("cell_t", _i64),
+                ("nx", _i32), ("ny", _i32), ("nt", _i32), ("reach_s", _i32),
+                ("reach_t", _i32), ("n_cells", _i64), ("wide", _i32), ("n_bins", _i32),
+                ("device_bytes", _i64)]
+
+
+class Points(ctypes.Structure):
+    _fields_ = [("x", _P(_i32)), ("y", _P(_i32)), ("t", _P(_i32)), ("n", _i64),
+                ("n_centres", _i64), ("on_device", _i32)]
+
+
+class KOut(ctypes.Structure):
+    _fields_ = [("C", _P(_u64)), ("W", _P(_f64)), ("K", _P(_f64)), ("L", _P(_f64))]
+
+
+class EnvOut(ctypes.Structure):
+    _fields_ = [("K_lo", _P(_f64)), ("K_hi", _P(_f64)), ("L_lo", _P(_f64)),
+                ("L_hi", _P(_f64)), ("dL_hi", _P(_f64)), ("C_sims", _P(_u64)),
+                ("W_sims", _P(_f64)), ("K_sims", _P(_f64))]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n_sets", _i64), ("n_points", _i64), ("n_in", _i64), ("n_eval", _i64),
+                ("n_items", _i64), ("pair_grid", _i32), ("symmetric", _i32),
+                ("us_total", _f64), ("us_gen", _f64), ("us_grid", _f64), ("us_pair", _f64),
+                ("us_finalize", _f64)]
+
+
+class RipkError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        msg = f"{where}: {ripk_status_str(status)} ({status})"
+        detail = ripk_last_error()
+        if detail:
+            msg += f": {detail}"
+        super().__init__(msg)
+
+
+_lib = None
+
+# every function the header declares, with (restype, argtypes)
+_SIGS = {
+    "ripk_plan_check": (_i32, [_P(PlanDesc), _P(PlanInfo)]),
+    "ripk_plan": (_i32, [_P(PlanDesc), _P(ctypes.c_void_p)]),
+    "ripk_plan_destroy": (None, [ctypes.c_void_p]),
+    "ripk_compute_K": (_i32, [ctypes.c_void_p, _P(Points), ctypes.c_void_p, _P(KOut)]),
+    "ripk_simulate_envelope": (_i32, [ctypes.c_void_p, _i64, _i32, _u64, _P(_f64),
+                                      ctypes.c_void_p, _P(EnvOut)]),
+    "ripk_plan_stats": (_i32, [ctypes.c_void_p, _P(Stats)]),
+    "ripk_status_str": (ctypes.c_char_p, [_i32]),
+    "ripk_last_error": (ctypes.c_char_p, []),
+}
+
+
+def lib():
+    """Load ``libripk.so``; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(there is no fallback implementation)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def ripk_status_str(s):
+    return lib().ripk_status_str(int(s)).decode()
+
+
+def ripk_last_error():
+    r = lib().ripk_last_error()
+    return r.decode() if r else ""
+
+
+def _check(status, where):
+    if status != RIPK_OK:
+        raise RipkError(status, where)
+
+
+def make_desc(window, s_max, t_max, n_s, n_t, edge=RIPK_EDGE_ISO, norm=RIPK_NORM_NN1,
+              n_max=2, m_max=0, flags=0, device=0, cell_div=0, tcell_div=0):
+    """Descriptor for a window ``(x0, y0, x1, y1, t0, t1)`` and an (s, t) grid."""
+    x0, y0, x1, y1, t0, t1 = (int(v) for v in window)
+    return PlanDesc(x0, y0, x1, y1, t0, t1, int(s_max), int(t_max), int(n_s), int(n_t),
+                    int(edge), int(norm), RIPK_SIM_CSR, int(n_max), int(m_max), int(flags),
+                    int(device), int(cell_div), int(tcell_div))
+
+
+def ripk_plan_check(desc):
+    """Validate a descriptor and return its derived geometry (no device use)."""
+    info = PlanInfo()
+    _check(lib().ripk_plan_check(ctypes.byref(desc), ctypes.byref(info)), "ripk_plan_check")
+    ns, nt = desc.n_s, desc.n_t
+    return {"S2": np.array(info.S2[:ns], np.int64), "T": np.array(info.T[:nt], np.int64),
+            "cell_s": info.cell_s, "cell_t": info.cell_t, "nx": info.nx, "ny": info.ny,
+            "nt": info.nt, "reach_s": info.reach_s, "reach_t": info.reach_t,
+            "n_cells": info.n_cells, "wide": info.wide, "n_bins": info.n_bins,
+            "device_bytes": info.device_bytes}
+
+
+class Plan:
+    """Owns a ``ripk_plan_t``; destroyed explicitly or when garbage collected."""
+
+    def __init__(self, handle, desc):
+        self.handle = handle
+        self.desc = desc
+
+    @property
+    def shape(self):
+        return (self.desc.n_s, self.desc.n_t)
+
+    def destroy(self):
+        if self.handle:
+            lib().ripk_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def ripk_plan(desc):
+    h = ctypes.c_void_p()
+    _check(lib().ripk_plan(ctypes.byref(desc), ctypes.byref(h)), "ripk_plan")
+    return Plan(h, desc)
+
+
+def ripk_plan_destroy(plan):
+    plan.destroy()
+
+
+def _is_torch(a):
+    return type(a).__module__.split(".")[0] == "torch"
+
+
+def _stream_for(arrays, stream):
+    if stream is not None:
+        return ctypes.c_void_p(int(stream))
+    if any(_is_torch(a) and a.is_cuda for a in arrays):
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return ctypes.c_void_p(0)
+
+
+def _coord_ptr(a, n):
+    if _is_torch(a):
+        import torch
+        if a.dtype != torch.int32 or not a.is_contiguous() or a.numel() != n:
+            raise ValueError("coordinate tensors must be contiguous int32 of equal length")
+        return ctypes.cast(ctypes.c_void_p(a.data_ptr()), _P(_i32)), bool(a.is_cuda), a
+    arr = np.ascontiguousarray(a, dtype=np.int32)
+    if arr.shape != (n,):
+        raise ValueError("coordinate arrays must be 1-D of equal length")
+    return arr.ctypes.data_as(_P(_i32)), False, arr
+
+
+def _out(shape, dtype):
+    return np.zeros(shape, dtype)
+
+
+def ripk_compute_K(plan, x, y, t, n_centres=0, stream=None):
+    """K, L of one point set (Eq. 2-4).  Returns numpy arrays C, W, K, L of shape (n_s, n_t)."""
+    n = len(x)
+    px, dx, kx = _coord_ptr(x, n)
+    py, dy, ky = _coord_ptr(y, n)
+    pt, dt, kt = _coord_ptr(t, n)
+    if not (dx == dy == dt):
+        raise ValueError("coordinates must all be on the host or all on the device")
+    pts = Points(px, py, pt, n, int(n_centres), 1 if dx else 0)
+    shp = plan.shape
+    C = _out(shp, np.uint64)
+    W = _out(shp, np.float64)
+    K = _out(shp, np.float64)
+    L = _out(shp, np.float64)
+    out = KOut(C.ctypes.data_as(_P(_u64)), W.ctypes.data_as(_P(_f64)),
+               K.ctypes.data_as(_P(_f64)), L.ctypes.data_as(_P(_f64)))
+    st = _stream_for([x, y, t], stream)
+    _check(lib().ripk_compute_K(plan.handle, ctypes.byref(pts), st, ctypes.byref(out)),
+           "ripk_compute_K")
+    del kx, ky, kt
+    return {"C": C, "W": W, "K": K, "L": L}
+
+
+def ripk_simulate_envelope(plan, n, m, seed, L_obs=None, stream=None, per_sim=False):
+    """Envelopes over m on-device CSR simulations of n points (Sec. 3)."""
+    shp = plan.shape
+    res = {k: _out(shp, np.float64) for k in ("K_lo", "K_hi", "L_lo", "L_hi")}
+    ptr = lambda a, ct: a.ctypes.data_as(_P(ct))
+    lobs = None
+    null_d = _P(_f64)()
+    null_u = _P(_u64)()
+    if L_obs is not None:
+        lobs = np.ascontiguousarray(L_obs, np.float64).reshape(shp)
+        res["dL_hi"] = _out(shp, np.float64)
+    if per_sim:
+        res["C_sims"] = _out((m,) + shp, np.uint64)
+        res["W_sims"] = _out((m,) + shp, np.float64)
+        res["K_sims"] = _out((m,) + shp, np.float64)
+    out = EnvOut(ptr(res["K_lo"], _f64), ptr(res["K_hi"], _f64), ptr(res["L_lo"], _f64),
+                 ptr(res["L_hi"], _f64),
+                 ptr(res["dL_hi"], _f64) if lobs is not None else null_d,
+                 ptr(res["C_sims"], _u64) if per_sim else null_u,
+                 ptr(res["W_sims"], _f64) if per_sim else null_d,
+                 ptr(res["K_sims"], _f64) if per_sim else null_d)
+    st = ctypes.c_void_p(int(stream)) if stream is not None else ctypes.c_void_p(0)
+    _check(lib().ripk_simulate_envelope(plan.handle, int(n), int(m), int(seed) & (2**64 - 1),
+                                        ptr(lobs, _f64) if lobs is not None else null_d, st,
+                                        ctypes.byref(out)), "ripk_simulate_envelope")
+    return res
+
+
+def ripk_plan_stats(plan):
+    s = Stats()
+    _check(lib().ripk_plan_stats(plan.handle, ctypes.byref(s)), "ripk_plan_stats")
+    return {k: getattr(s, k) for k, _ in Stats._fields_}

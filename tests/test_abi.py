@@ -1,0 +1,89 @@
+"""The C-ABI library loads and exports what include/ripk.h declares; host-side
+plan validation and geometry (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1912_04753_amd import ripk
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "ripk.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ripk_[a-z_A-Z0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_functions()
+    assert "ripk_plan" in names and "ripk_compute_K" in names
+    lib = ctypes.CDLL(ripk.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_every_declared_symbol():
+    assert set(declared_functions()) <= set(ripk._SIGS) | {"ripk_plan_destroy"}
+
+
+def test_struct_sizes_match_header_layout():
+    # 8 int64 + 2 int32 + 3 uint32 + pad + int64 + int32 + uint32 + 3 int32 (+ pad)
+    assert ctypes.sizeof(ripk.PlanDesc) == 8 * 8 + 4 * 2 + 4 * 3 + 4 + 8 + 4 * 5 + 4
+    assert ctypes.sizeof(ripk.Points) == 3 * 8 + 8 + 8 + 8
+
+
+def desc(**kw):
+    base = dict(window=(0, 0, 20_000, 20_000, 0, 15_552_000), s_max=2000, t_max=2_592_000,
+                n_s=25, n_t=15, n_max=100_000, m_max=99)
+    base.update(kw)
+    w = base.pop("window")
+    return ripk.make_desc(w, **base)
+
+
+def test_plan_geometry_config3():
+    info = ripk.ripk_plan_check(desc())
+    assert (info["nx"], info["ny"], info["nt"]) == (10, 10, 6)
+    assert info["reach_s"] == 1 and info["reach_t"] == 1
+    assert info["wide"] == 0
+    assert info["n_bins"] == 375
+    # exact floors: d <= s_k <=> d2 <= S2[k] (Eq. 3)
+    for k, v in enumerate(info["S2"], 1):
+        assert v * 25 * 25 <= (k * 2000) ** 2 < (v + 1) * 25 * 25
+    for l, v in enumerate(info["T"], 1):
+        assert v * 15 <= l * 2_592_000 < (v + 1) * 15
+
+
+def test_plan_geometry_finer_cells_and_wide():
+    info = ripk.ripk_plan_check(desc(cell_div=2, tcell_div=3))
+    assert info["cell_s"] == 1000 and info["cell_t"] == 864_000
+    assert info["reach_s"] == 2 and info["reach_t"] == 3
+    w = ripk.ripk_plan_check(ripk.make_desc((0, 0, 200_000, 150_000, 0, 3_000_000), 40_000,
+                                            600_000, 20, 12, n_max=10))
+    assert w["wide"] == 1
+
+
+@pytest.mark.parametrize("bad", [
+    dict(n_s=0), dict(n_t=65), dict(s_max=10_001), dict(t_max=15_552_001),
+    dict(window=(0, 0, 0, 10, 0, 10)), dict(window=(0, 0, 2**24, 10**6, 0, 10**8), s_max=10),
+    dict(n_max=1), dict(m_max=-1), dict(n_max=2**26, m_max=64), dict(edge=4),
+    dict(norm=2), dict(cell_div=9), dict(s_max=0),
+])
+def test_plan_rejects_bad_descriptors(bad):
+    with pytest.raises(ripk.RipkError) as e:
+        ripk.ripk_plan_check(desc(**bad))
+    assert e.value.status == ripk.RIPK_EINVAL
+    assert ripk.ripk_last_error()
+
+
+def test_plan_allows_large_s_without_spatial_correction():
+    info = ripk.ripk_plan_check(desc(s_max=30_000, edge=ripk.RIPK_EDGE_TEMPORAL))
+    assert info["nx"] == 1
+
+
+def test_status_strings():
+    assert ripk.ripk_status_str(ripk.RIPK_ERANGE) == "point outside the study window"
+    assert ripk.ripk_status_str(0) == "ok"

@@ -1,0 +1,313 @@
+"""GPU parity: the HIP library through its C ABI against the FP64 CPU oracle.
+
+Counts are compared bit for bit; W, K and L within the tolerances stated in
+``tests/parity.py``.  Inputs are seeded synthetic sets from
+``paper_1912_04753_amd.workloads`` (the paper's data are not available).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1912_04753_amd import ripk, workloads
+from parity import compare, grid_values
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+def make_plan(window, s_max, t_max, n_s, n_t, n_max, m_max=0, edge=3, norm=0, flags=0,
+              cell_div=0, tcell_div=0):
+    d = ripk.make_desc(window, s_max, t_max, n_s, n_t, edge=edge, norm=norm, n_max=n_max,
+                       m_max=m_max, flags=flags, cell_div=cell_div, tcell_div=tcell_div)
+    return ripk.ripk_plan(d)
+
+
+def gpu_K(x, y, t, window, s_max, t_max, n_s, n_t, n_centres=0, **kw):
+    plan = make_plan(window, s_max, t_max, n_s, n_t, n_max=max(len(x), 2), **kw)
+    try:
+        r = ripk.ripk_compute_K(plan, x, y, t, n_centres=n_centres)
+        r["stats"] = ripk.ripk_plan_stats(plan)
+        return r
+    finally:
+        plan.destroy()
+
+
+def ref_K(x, y, t, window, s_max, t_max, n_s, n_t, n_centres=None, edge=3, norm=0):
+    d = oracle.desc(window, s_max, t_max, n_s, n_t, edge=edge, norm=norm)
+    return oracle.estimate(d, x, y, t, n_centres=n_centres)
+
+
+def cfg_args(c):
+    return (c["window"], c["s_max"], c["t_max"], c["n_s"], c["n_t"])
+
+
+# ------------------------------------------------------------ workloads -----
+def test_config1_full():
+    c = workloads.config(1)
+    x, y, t = workloads.make_points(c)
+    say("config1 n=%d" % len(x))
+    g = gpu_K(x, y, t, *cfg_args(c))
+    r = ref_K(x, y, t, *cfg_args(c))
+    err = compare(g, r, c["s_max"], c["t_max"], c["n_s"], c["n_t"], where="config1")
+    assert g["stats"]["n_in"] == int(r["C"][-1, -1])
+    say("config1 worst rel K err %.3g" % err)
+
+
+def test_config2_full_clustered():
+    c = workloads.config(2)
+    x, y, t = workloads.make_points(c)
+    say("config2 n=%d" % len(x))
+    g = gpu_K(x, y, t, *cfg_args(c))
+    r = ref_K(x, y, t, *cfg_args(c))
+    err = compare(g, r, c["s_max"], c["t_max"], c["n_s"], c["n_t"], where="config2")
+    say("config2 worst rel K err %.3g" % err)
+
+
+_c3 = {}
+
+
+def _config3_observed():
+    if not _c3:
+        c = workloads.config(3)
+        x, y, t = workloads.make_points(c)
+        _c3.update(c=c, x=x, y=y, t=t, ref=ref_K(x, y, t, *cfg_args(c)))
+    return _c3
+
+
+def test_config3_observed_full_and_modes_agree():
+    d = _config3_observed()
+    c, x, y, t = d["c"], d["x"], d["y"], d["t"]
+    say("config3 observed symmetric")
+    g = gpu_K(x, y, t, *cfg_args(c))
+    compare(g, d["ref"], c["s_max"], c["t_max"], c["n_s"], c["n_t"], where="config3")
+    assert g["stats"]["symmetric"] == 1
+    say("config3 observed ordered")
+    go = gpu_K(x, y, t, *cfg_args(c), flags=ripk.RIPK_PLAN_ORDERED)
+    assert go["stats"]["symmetric"] == 0
+    # both modes add the same exact integers: identical bits
+    assert np.array_equal(go["C"], g["C"]) and np.array_equal(go["W"], g["W"])
+    say("config3 observed finer cells")
+    gf = gpu_K(x, y, t, *cfg_args(c), cell_div=2, tcell_div=3)
+    assert np.array_equal(gf["C"], g["C"]) and np.array_equal(gf["W"], g["W"])
+
+
+def test_config3_simulations_sampled():
+    c = workloads.config(3)
+    n, m = 100_000, c["sims"]
+    say("config3 sims m=%d" % m)
+    plan = make_plan(*cfg_args(c), n_max=n, m_max=m)
+    try:
+        env = ripk.ripk_simulate_envelope(plan, n, m, seed=c["seed"], per_sim=True)
+        st = ripk.ripk_plan_stats(plan)
+    finally:
+        plan.destroy()
+    d = oracle.desc(*cfg_args(c))
+    for s in (0, 41, m - 1):
+        x, y, t = oracle.csr_points(d, n, s, c["seed"])
+        r = oracle.estimate(d, x, y, t)
+        g = {"C": env["C_sims"][s], "W": env["W_sims"][s], "K": env["K_sims"][s]}
+        compare(g, r, c["s_max"], c["t_max"], c["n_s"], c["n_t"], where=f"config3 sim {s}")
+    Ks = env["K_sims"]
+    assert np.array_equal(env["K_lo"], Ks.min(axis=0))
+    assert np.array_equal(env["K_hi"], Ks.max(axis=0))
+    assert st["n_in"] == int(env["C_sims"][:, -1, -1].sum())
+    # CSR expectation 2*pi*s^2*t (Sec. 3) holds for the mean over the simulations
+    s_, t_ = grid_values(c["s_max"], c["t_max"], c["n_s"], c["n_t"])
+    want = 2 * np.pi * s_ ** 2 * t_
+    se = Ks.std(axis=0, ddof=1) / math.sqrt(m)
+    cnt = env["C_sims"].mean(axis=0)
+    ok = cnt >= 1000
+    z = (Ks.mean(axis=0) - want) / se
+    assert np.all(np.abs(z[ok]) < 4.5), np.abs(z[ok]).max()
+
+
+def test_config4_sampled_centres():
+    c = workloads.config(4)
+    x, y, t = workloads.make_points(c)
+    n = len(x)
+    rng = np.random.default_rng(44)
+    pick = rng.choice(n, size=1200, replace=False)
+    rest = np.setdiff1d(np.arange(n), pick)
+    order = np.concatenate([pick, rest])
+    xs, ys, ts = x[order], y[order], t[order]
+    say("config4 n=%d sampled centres=%d" % (n, len(pick)))
+    g = gpu_K(xs, ys, ts, *cfg_args(c), n_centres=len(pick))
+    r = ref_K(xs, ys, ts, *cfg_args(c), n_centres=len(pick))
+    compare(g, r, c["s_max"], c["t_max"], c["n_s"], c["n_t"], where="config4 sample")
+
+
+def test_config4_full_properties_and_sim_path():
+    c = workloads.config(4)
+    x, y, t = workloads.make_points(c)
+    n, m = len(x), c["sims"]
+    say("config4 full n=%d" % n)
+    plan = make_plan(*cfg_args(c), n_max=n, m_max=m)
+    try:
+        full = ripk.ripk_compute_K(plan, x, y, t)
+        say("config4 sims m=%d" % m)
+        env = ripk.ripk_simulate_envelope(plan, n, m, seed=c["seed"], per_sim=True)
+        d = oracle.desc(*cfg_args(c))
+        xs, ys, ts = oracle.csr_points(d, n, 7, c["seed"])
+        say("config4 sim 7 through the observed path")
+        obs7 = ripk.ripk_compute_K(plan, xs, ys, ts)
+    finally:
+        plan.destroy()
+    C = full["C"].astype(np.int64)
+    assert np.all(C % 2 == 0)
+    assert np.all(np.diff(C, axis=0) >= 0) and np.all(np.diff(C, axis=1) >= 0)
+    assert np.all(full["W"] >= C) and np.all(full["W"] <= 8 * C)
+    # device CSR draw == the oracle's Philox draw, shown through bit-identical sums
+    assert np.array_equal(obs7["C"], env["C_sims"][7])
+    assert np.array_equal(obs7["W"], env["W_sims"][7])
+
+
+# ----------------------------------------------------------- edge cases -----
+def test_two_points_hand_derived():
+    """Two points 2 m from the left side, 4 m apart, 20 s apart (see the oracle pins)."""
+    win = (0, 0, 100, 100, 0, 100)
+    g = gpu_K(np.array([2, 2]), np.array([50, 54]), np.array([10, 30]), win, 8, 40, 4, 4)
+    on = np.zeros((4, 4), bool)
+    on[1:, 1:] = True
+    assert np.array_equal(g["C"], np.where(on, 2, 0).astype(np.uint64))
+    assert np.allclose(g["W"], np.where(on, 4.5, 0.0), rtol=1e-6, atol=0)
+
+
+@pytest.mark.parametrize("case", ["coincident", "edges", "dense", "ragged", "tiny_window"])
+def test_edge_case_sets(case):
+    rng = np.random.default_rng(["coincident", "edges", "dense", "ragged", "tiny_window"].index(case) + 101)
+    if case == "coincident":
+        win = (0, 0, 5000, 5000, 0, 1_000_000)
+        x = np.repeat(rng.integers(0, 5001, 40), 25)
+        y = np.repeat(rng.integers(0, 5001, 40), 25)
+        t = np.repeat(rng.integers(0, 1_000_001, 40), 25)
+        args = (win, 800, 100_000, 8, 5)
+    elif case == "edges":
+        win = (-3000, 1000, 3000, 9000, 500, 900_500)
+        n = 3000
+        x = rng.integers(-3000, 3001, n); y = rng.integers(1000, 9001, n); t = rng.integers(500, 900_501, n)
+        side = rng.integers(0, 6, n)
+        x[side == 0] = -3000; x[side == 1] = 3000; y[side == 2] = 1000; y[side == 3] = 9000
+        t[side == 4] = 500; t[side == 5] = 900_500
+        x[:8] = [-3000, 3000, -3000, 3000, -3000, 3000, -3000, 3000]
+        y[:8] = [1000, 1000, 9000, 9000, 1000, 1000, 9000, 9000]
+        args = (win, 3000, 450_000, 12, 9)
+    elif case == "dense":
+        win = (0, 0, 40_000, 40_000, 0, 10_000_000)
+        n = 6000
+        x = rng.integers(20_000, 20_050, n); y = rng.integers(20_000, 20_050, n)
+        t = rng.integers(5_000_000, 5_086_400, n)
+        x[:300] = rng.integers(0, 40_001, 300); y[:300] = rng.integers(0, 40_001, 300)
+        args = (win, 2000, 500_000, 16, 10)
+    elif case == "ragged":
+        win = (0, 0, 7000, 5000, 0, 3_000_000)
+        n = 64 * 37 + 29
+        x = rng.integers(0, 7001, n); y = rng.integers(0, 5001, n); t = rng.integers(0, 3_000_001, n)
+        args = (win, 1100, 400_000, 11, 7)
+    else:  # window smaller than a cell in time, one cell in space
+        win = (0, 0, 21, 30, 0, 50)
+        n = 500
+        x = rng.integers(0, 22, n); y = rng.integers(0, 31, n); t = rng.integers(0, 51, n)
+        args = (win, 10, 50, 5, 5)
+    say("edge case", case, len(x))
+    x, y, t = (np.asarray(a, np.int32) for a in (x, y, t))
+    g = gpu_K(x, y, t, *args)
+    r = ref_K(x, y, t, *args)
+    compare(g, r, args[1], args[2], args[3], args[4], where=case)
+    go = gpu_K(x, y, t, *args, flags=ripk.RIPK_PLAN_ORDERED)
+    assert np.array_equal(go["C"], g["C"]) and np.array_equal(go["W"], g["W"])
+
+
+def test_wide_distances():
+    """Cells so large that squared candidate distances need 64 bits."""
+    rng = np.random.default_rng(8)
+    win = (0, 0, 200_000, 150_000, 0, 30_000_000)
+    n = 20_000
+    x = rng.integers(0, 200_001, n); y = rng.integers(0, 150_001, n); t = rng.integers(0, 30_000_001, n)
+    args = (win, 40_000, 6_000_000, 20, 12)
+    info = ripk.ripk_plan_check(ripk.make_desc(*args, n_max=n))
+    assert info["wide"] == 1
+    say("wide n=%d" % n)
+    g = gpu_K(x, y, t, *args)
+    r = ref_K(x, y, t, *args)
+    compare(g, r, *args[1:], where="wide")
+
+
+@pytest.mark.parametrize("edge,norm", [(0, 0), (1, 0), (2, 1), (3, 1)])
+def test_edge_and_norm_switches(edge, norm):
+    c = workloads.config(1)
+    x, y, t = workloads.make_points(c)
+    say("switches edge=%d norm=%d" % (edge, norm))
+    g = gpu_K(x, y, t, *cfg_args(c), edge=edge, norm=norm)
+    r = ref_K(x, y, t, *cfg_args(c), edge=edge, norm=norm)
+    compare(g, r, c["s_max"], c["t_max"], c["n_s"], c["n_t"], where=f"edge{edge} norm{norm}")
+
+
+def test_halo_subset_and_additivity():
+    rng = np.random.default_rng(12)
+    win = (0, 0, 12_000, 12_000, 0, 20_000_000)
+    n = 30_000
+    x = rng.integers(0, 12_001, n).astype(np.int32)
+    y = rng.integers(0, 12_001, n).astype(np.int32)
+    t = rng.integers(0, 20_000_001, n).astype(np.int32)
+    args = (win, 1500, 2_000_000, 15, 10)
+    say("halo subset")
+    a = gpu_K(x, y, t, *args, n_centres=11_111)
+    ra = ref_K(x, y, t, *args, n_centres=11_111)
+    compare(a, ra, *args[1:], where="halo")
+    rot = np.r_[np.arange(11_111, n), np.arange(11_111)]
+    b = gpu_K(x[rot], y[rot], t[rot], *args, n_centres=n - 11_111)
+    full = gpu_K(x, y, t, *args)
+    assert np.array_equal(a["C"] + b["C"], full["C"])
+
+
+def test_device_tensors_and_plan_reuse():
+    torch = pytest.importorskip("torch")
+    c = workloads.config(1)
+    x, y, t = workloads.make_points(c)
+    plan = make_plan(*cfg_args(c), n_max=len(x))
+    try:
+        say("device tensors")
+        dx, dy, dt = (torch.from_numpy(a).cuda() for a in (x, y, t))
+        g1 = ripk.ripk_compute_K(plan, dx, dy, dt)
+        g2 = ripk.ripk_compute_K(plan, x, y, t)
+        g3 = ripk.ripk_compute_K(plan, x[:777], y[:777], t[:777])
+        g4 = ripk.ripk_compute_K(plan, dx, dy, dt)
+    finally:
+        plan.destroy()
+    assert np.array_equal(g1["C"], g2["C"]) and np.array_equal(g1["W"], g2["W"])
+    assert np.array_equal(g1["W"], g4["W"])
+    r3 = ref_K(x[:777], y[:777], t[:777], *cfg_args(c))
+    compare(g3, r3, c["s_max"], c["t_max"], c["n_s"], c["n_t"], where="reuse")
+
+
+def test_errors_are_reported():
+    c = workloads.config(1)
+    x, y, t = workloads.make_points(c)
+    plan = make_plan(*cfg_args(c), n_max=1000, m_max=3)
+    try:
+        say("errors")
+        with pytest.raises(ripk.RipkError) as e:
+            ripk.ripk_compute_K(plan, x[:1], y[:1], t[:1])
+        assert e.value.status == ripk.RIPK_EINVAL
+        with pytest.raises(ripk.RipkError) as e:
+            ripk.ripk_compute_K(plan, x[:1001], y[:1001], t[:1001])
+        assert e.value.status == ripk.RIPK_EINVAL
+        xb = x[:500].copy()
+        xb[17] = 10_001
+        with pytest.raises(ripk.RipkError) as e:
+            ripk.ripk_compute_K(plan, xb, y[:500], t[:500])
+        assert e.value.status == ripk.RIPK_ERANGE
+        with pytest.raises(ripk.RipkError) as e:
+            ripk.ripk_simulate_envelope(plan, 500, 4, 1)
+        assert e.value.status == ripk.RIPK_EINVAL
+        # the plan still works after the errors
+        g = ripk.ripk_compute_K(plan, x[:500], y[:500], t[:500])
+    finally:
+        plan.destroy()
+    r = ref_K(x[:500], y[:500], t[:500], *cfg_args(c))
+    compare(g, r, c["s_max"], c["t_max"], c["n_s"], c["n_t"], where="after errors")
