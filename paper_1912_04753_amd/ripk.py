@@ -108,6 +108,12 @@ def lib():
     """Load ``libripk.so``; raises if it has not been built."""
     global _lib
     if _lib is None:
+        # One HIP runtime per process: torch ships its own libamdhip64 with the
+        # same soname, so load torch first and let the library bind to it.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                                "(there is no fallback implementation)")

@@ -116,9 +116,16 @@ def test_config3_simulations_sampled():
     assert np.array_equal(env["K_lo"], Ks.min(axis=0))
     assert np.array_equal(env["K_hi"], Ks.max(axis=0))
     assert st["n_in"] == int(env["C_sims"][:, -1, -1].sum())
-    # CSR expectation 2*pi*s^2*t (Sec. 3) holds for the mean over the simulations
-    s_, t_ = grid_values(c["s_max"], c["t_max"], c["n_s"], c["n_t"])
-    want = 2 * np.pi * s_ ** 2 * t_
+    # CSR expectation (Sec. 3): 2*pi*s^2*t for continuous coordinates.  On the
+    # integer lattice the share of offsets within radius s is N(S2)/(pi s^2),
+    # N(S2) = #{(a, b) integer: a^2 + b^2 <= S2} (-0.13% at s = 80 m), so the
+    # mean over the simulations is checked against 2*N(S2_k)*t_l.
+    _, t_ = grid_values(c["s_max"], c["t_max"], c["n_s"], c["n_t"])
+    S2 = ripk.ripk_plan_check(ripk.make_desc(*cfg_args(c), n_max=2))["S2"]
+    lattice = np.array([sum(2 * math.isqrt(int(q) - a * a) + 1
+                            for a in range(-math.isqrt(int(q)), math.isqrt(int(q)) + 1))
+                        for q in S2], np.float64)[:, None]
+    want = 2 * lattice * t_
     se = Ks.std(axis=0, ddof=1) / math.sqrt(m)
     cnt = env["C_sims"].mean(axis=0)
     ok = cnt >= 1000
