@@ -76,7 +76,7 @@ enum {
  *
  * Requirements (RIPK_EINVAL otherwise):
  *   x0 < x1, y0 < y1, t0 < t1, all within int32; x1-x0 and y1-y0 < 2^24;
- *   t1-t0 < 2^31;  1 <= n_s, n_t <= 64;  s_max >= 1, t_max >= 1;
+ *   t1-t0 < 2^31;  1 <= n_s, n_t <= 64;  s_max >= 1;  1 <= t_max < 2^30;
  *   with RIPK_EDGE_SPATIAL_ISO: 2*s_max <= min(x1-x0, y1-y0) (so omega >= 1/4);
  *   with RIPK_EDGE_TEMPORAL:   t_max <= t1-t0;
  *   s_max < 2^23;  n_max >= 2;  0 <= m_max;  (m_max+1)*n_max < 2^31.
@@ -108,7 +108,7 @@ typedef struct {
   int32_t nx, ny, nt;      /* cells per axis                                             */
   int32_t reach_s, reach_t;/* stencil half-width in cells (space, time)                  */
   int64_t n_cells;         /* nx*ny*nt                                                   */
-  int32_t wide;            /* 1 if squared distances need 64-bit arithmetic              */
+  int32_t dist_mode;       /* distance test: 0 packed 16-bit, 1 32-bit, 2 64-bit squares */
   int32_t n_bins;          /* n_s*n_t                                                    */
   int64_t device_bytes;    /* device memory a plan of this descriptor allocates          */
 } ripk_plan_info;

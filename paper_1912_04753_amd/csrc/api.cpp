@@ -74,7 +74,7 @@ ripk_status derive(const ripk_plan_desc *d, Layout *L) {
     return fail(RIPK_EINVAL, "n_s and n_t must be in [1, 64]");
   if (d->s_max < 1 || d->t_max < 1) return fail(RIPK_EINVAL, "s_max and t_max must be >= 1");
   if (d->s_max >= (1LL << 23)) return fail(RIPK_EINVAL, "s_max must be below 2^23");
-  if (d->t_max >= (1LL << 31)) return fail(RIPK_EINVAL, "t_max must be below 2^31");
+  if (d->t_max >= (1LL << 30)) return fail(RIPK_EINVAL, "t_max must be below 2^30");
   if (d->edge & ~RIPK_EDGE_ISO) return fail(RIPK_EINVAL, "unknown edge-correction bits");
   if ((d->edge & RIPK_EDGE_SPATIAL_ISO) && 2 * d->s_max > std::min(W, H))
     return fail(RIPK_EINVAL,
@@ -118,9 +118,16 @@ ripk_status derive(const ripk_plan_desc *d, Layout *L) {
   I.reach_s = (int32_t)((d->s_max + cs - 1) / cs);
   I.reach_t = (int32_t)((d->t_max + ct - 1) / ct);
   I.n_cells = nx * ny * nt;
-  // largest squared distance a candidate can have: |dx| < (reach+1)*cell
-  const double reach_m = (double)(I.reach_s + 1) * (double)cs;
-  I.wide = (2.0 * reach_m * reach_m >= 4294967296.0) ? 1 : 0;
+  // Strict bound on |dx| and |dy| between a centre and any candidate: the
+  // stencil spans reach+1 cells and the last cell of an axis also holds the
+  // remainder of the side.
+  const int64_t span = (I.reach_s + 1) * cs + std::max(W % cs, H % cs);
+  if (span <= 32768)
+    I.dist_mode = kModePacked;  // |dx|, |dy| <= 32767 and dx^2 + dy^2 < 2^31
+  else if (2 * (span - 1) * (span - 1) < (1LL << 32))
+    I.dist_mode = kModeU32;
+  else
+    I.dist_mode = kModeWide;
   I.n_bins = d->n_s * d->n_t;
 
   Geom &g = L->g;
@@ -132,7 +139,7 @@ ripk_status derive(const ripk_plan_desc *d, Layout *L) {
   g.n_cells = (uint32_t)I.n_cells;
   g.n_s = d->n_s; g.n_t = d->n_t;
   g.edge = d->edge;
-  g.wide = (uint32_t)I.wide;
+  g.mode = I.dist_mode;
   g.s2max = (uint64_t)I.S2[d->n_s - 1];
   g.tmax = (uint32_t)I.T[d->n_t - 1];
   g.inv_ds = (float)((double)d->n_s / (double)d->s_max);
@@ -266,7 +273,7 @@ ripk_status run_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_centres,
   a.n_eval = p->scal;
   a.symmetric = symmetric ? 1 : 0;
   int per_cu = 0;
-  HIPCHK(pair_occupancy((int)NB, a.symmetric, (int)g.wide, &per_cu));
+  HIPCHK(pair_occupancy((int)NB, a.symmetric, g.mode, &per_cu));
   if (per_cu < 1) return fail(RIPK_EINVAL, "pair kernel does not fit on a compute unit (n_bins=%u)", NB);
   const int64_t groups_cap = ((int64_t)S * (n / kChunk + g.n_cells + kItemsPerGroup)) / kItemsPerGroup + 1;
   const int grid = (int)std::min<int64_t>((int64_t)per_cu * p->cus, groups_cap);

@@ -13,13 +13,26 @@
 //     global counter (persistent launch, items padded per set);
 //   * neighbours are visited as contiguous runs of the sorted point array (a run
 //     of consecutive x-cells per (y, t) row of the stencil), staged per wave in
-//     LDS tiles with coalesced loads and read back as wave-uniform broadcasts;
+//     two alternating LDS tiles (the next tile is fetched from HBM while the
+//     current one is scanned) and read back as wave-uniform broadcasts, four
+//     neighbours per LDS round trip;
 //   * symmetric mode visits each unordered pair once (forward half of the
 //     stencil, j > i inside the home cell) and adds both weights, since
 //     omega_ij / v_ij depend on the centre while the bin depends on d and u only;
-//   * the rare in-range pairs are compacted into a per-wave LDS queue and
-//     binned / weighted 64 at a time so that the costly part runs with full
-//     lanes rather than under a divergent branch.
+//   * divergence is removed in two levels: in-range pairs are compacted into a
+//     per-wave LDS queue and binned 64 at a time (integer bin search, temporal
+//     weight, interior fast path for omega); the pairs whose circle crosses the
+//     study boundary are compacted again into a second queue where the
+//     trigonometric weight runs with full lanes.
+//
+// Candidate test (one neighbour against 64 centres), by distance mode:
+//   PACKED: low 16 bits of x and y packed in one word; one packed 16-bit
+//           subtract and one 2-way dot product give dx^2 + dy^2 exactly while
+//           |dx|, |dy| < 2^15 (cells no wider than 2^15 / (reach + 1));
+//   U32:    32-bit squares with the 24-bit multiplier (d^2 < 2^32);
+//   WIDE:   64-bit squares and compare.
+// The time test is |t_i - t_j| <= t_max  <=>  (t_i + t_max - t_j) <= 2 t_max as
+// unsigned 32-bit values (t_max < 2^30).
 //
 // Weights are FP32: w = 1/omega * 1/v lies in [1, 8], so w * 2^23 is an exact
 // integer and the fixed-point sums are exact and order independent.
@@ -29,15 +42,28 @@ namespace ripk {
 
 namespace {
 
-constexpr int kJT = 128;   // tile points per wave
-constexpr int kQ = 128;    // per-wave queue ring (power of two, >= 2*64)
+constexpr int kJT = 64;    // points per tile slot (two slots per wave)
+constexpr int kQ = 128;    // ring size of each per-wave queue (>= 2*64)
 constexpr int kWaves = kPairThreads / 64;
 constexpr unsigned long long kFlushEvals = 1ull << 34;  // bound on candidates between flushes
+constexpr uint32_t kFarTime = 0xC0000000u;  // tile padding: fails every time test
+constexpr uint32_t kClampE = 32767u;         // side distances stored in 15 bits (PACKED)
 
+// LDS image of a point.  PACKED: {x|y<<16 (low 16 bits each), t, ex|ey<<16, -};
+// U32 / WIDE: {x, y, t, min side distance}.  Coordinates are window relative.
 struct WaveLds {
-  int4 tile[kJT];
-  int4 cen[64];
-  uint4 q[kQ];  // {j sorted index, centre lane | d2 high bits << 6, d2 low, u}
+  int4 tile[2 * kJT];  // two tile slots of neighbour points
+  int4 cen[64];        // the wave's centres
+  uint4 qa[kQ];        // in-range pairs: {d2 lo, t_i + t_max - t_j, lane | tile index << 6, d2 hi}
+  uint4 qb[kQ];        // boundary weights: {bin | halfv << 12 | d2 hi << 13, d2 lo, ex, ey}
+};
+
+struct QState {
+  uint32_t ha, na;      // queue A head and length
+  uint32_t hb, nb;      // queue B head and length
+  uint32_t drained;     // queue A entries drained so far (monotonic)
+  uint32_t prev_mark;   // queue A entries pushed before the previous tile began
+  uint32_t slot;        // tile slot being scanned
 };
 
 __device__ __forceinline__ void wave_sync() {
@@ -46,16 +72,22 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Isotropic correction on the rectangle in FP32, complementary-angle form:
-// beta_e = atan2(e, sqrt(d2 - e^2)) for each cut side (d2 - e^2 is an exact
-// integer).  Only the nearer x side and the nearer y side can cut a circle of
-// radius <= min(W, H)/2.  One side cut: 1/2 + beta/pi; two sides with the
-// corner outside (or on) the circle: (beta_x + beta_y)/pi; corner inside:
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// position of this lane among the set lanes of `mask`, plus `base`
+__device__ __forceinline__ uint32_t lane_rank(unsigned long long mask, uint32_t base) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, base));
+}
+
+// Isotropic correction on the rectangle in FP32 from the distances ex, ey to the
+// nearer x side and the nearer y side (only these can cut a circle of radius
+// <= min(W, H)/2), complementary-angle form: beta_e = atan2(e, sqrt(d2 - e^2))
+// with d2 - e^2 an exact integer.  One side cut: 1/2 + beta/pi; two sides with
+// the corner outside (or on) the circle: (beta_x + beta_y)/pi; corner inside:
 // 1/4 + (beta_x + beta_y)/(2 pi).  All terms are non-negative.
-__device__ __forceinline__ float omega_f32(int32_t X, int32_t Y, uint64_t d2, const Geom &g) {
-  const int32_t ex = min(X, g.x1 - g.x0 - X);
-  const int32_t ey = min(Y, g.y1 - g.y0 - Y);
-  const uint64_t ex2 = (uint64_t)ex * (uint64_t)ex, ey2 = (uint64_t)ey * (uint64_t)ey;
+__device__ __forceinline__ float omega_f32(uint32_t ex, uint32_t ey, uint64_t d2) {
+  const uint64_t ex2 = (uint64_t)ex * ex, ey2 = (uint64_t)ey * ey;
   const bool cx = ex2 < d2, cy = ey2 < d2;
   const float inv_pi = 0.318309886183790671538f;
   float bx = 0.0f, by = 0.0f;
@@ -70,122 +102,252 @@ __device__ __forceinline__ float omega_f32(int32_t X, int32_t Y, uint64_t d2, co
   return 1.0f;
 }
 
-// Fixed-point weight of one ordered pair with centre p: (1/omega)(1/v) * 2^23.
-__device__ __forceinline__ uint32_t qweight(const int4 p, uint64_t d2, uint32_t u, const Geom &g) {
-  uint32_t q = 1u << kFracBits;
-  if (g.edge & 2u) {
-    const uint32_t D = (uint32_t)(g.t1 - g.t0);
-    const uint32_t T = (uint32_t)p.z;
-    if (u > T || u > D - T) q <<= 1;  // an end of [t-u, t+u] leaves the period: v = 1/2
-  }
-  if (g.edge & 1u) {
-    const uint64_t e = (uint64_t)(uint32_t)p.w;
-    if (d2 > e * e) {
-      const float om = omega_f32(p.x, p.y, d2, g);
-      const float w = fmaxf(__frcp_rn(om), 1.0f);
-      q = (uint32_t)(w * (float)q);  // exact: w >= 1 has at most 23 fraction bits
-    }
-  }
-  return q;
-}
-
-__device__ __forceinline__ int kbin(uint64_t d2, const unsigned long long *S2, const Geom &g) {
-  int k = (int)ceilf(sqrtf((float)d2) * g.inv_ds);
-  k = min(max(k, 1), g.n_s);
-  while (k > 1 && d2 <= S2[k - 2]) --k;
-  while (d2 > S2[k - 1]) ++k;
-  return k - 1;
-}
-
-__device__ __forceinline__ int lbin(uint32_t u, const uint32_t *T, const Geom &g) {
-  int l = (int)ceilf((float)u * g.inv_dt);
-  l = min(max(l, 1), g.n_t);
-  while (l > 1 && u <= T[l - 2]) --l;
-  while (u > T[l - 1]) ++l;
-  return l - 1;
-}
-
-template <bool SYM>
-__device__ __forceinline__ void drain(WaveLds &W, uint32_t head, uint32_t c, int lane,
-                                      const PairArgs &a, unsigned long long *hc,
-                                      unsigned long long *hw, const unsigned long long *S2,
-                                      const uint32_t *T) {
-  const Geom &g = a.g;
+// Queue B: boundary weights with full lanes (out of line: rare, and large).
+__device__ __noinline__ void drain_b(WaveLds &W, uint32_t head, uint32_t c, int lane,
+                                     unsigned long long *hw) {
   wave_sync();
-  const uint4 r = W.q[(head + lane) & (kQ - 1)];
+  const uint4 r = W.qb[(head + lane) & (kQ - 1)];
   wave_sync();
   if ((uint32_t)lane < c) {
-    const uint32_t il = r.y & 63u;
-    const uint64_t d2 = (uint64_t)r.z | ((uint64_t)(r.y >> 6) << 32);
-    const uint32_t u = r.w;
-    const int bin = kbin(d2, S2, g) * g.n_t + lbin(u, T, g);
-    const int4 pi = W.cen[il];
-    uint32_t q = qweight(pi, d2, u, g);
-    if (SYM) {
-      const int4 pj = a.P[r.x];
-      q += qweight(pj, d2, u, g);
-    }
-    atomicAdd(&hc[bin], SYM ? 2ull : 1ull);
-    atomicAdd(&hw[bin], (unsigned long long)q);
+    const uint32_t bin = r.x & 0xFFFu;
+    const uint32_t half = (r.x >> 12) & 1u;
+    const uint64_t d2 = (uint64_t)r.y | ((uint64_t)(r.x >> 13) << 32);
+    const float om = omega_f32(r.z, r.w, d2);
+    const float w = fmaxf(__frcp_rn(om), 1.0f);
+    // w >= 1 has at most 23 fraction bits: w * 2^23 is an exact integer
+    const uint32_t qv = (uint32_t)(w * (float)(1u << kFracBits)) << half;
+    atomicAdd(&hw[bin], (unsigned long long)qv);
   }
 }
 
-template <bool SYM, bool WIDE, bool HOME>
-__device__ __forceinline__ void scan_run(uint32_t j0, uint32_t j1, const int4 me, bool valid,
-                                         uint32_t mi, int lane, WaveLds &W, uint32_t &qhead,
-                                         uint32_t &qn, const PairArgs &a, unsigned long long *hc,
-                                         unsigned long long *hw, const unsigned long long *S2,
-                                         const uint32_t *T) {
-  const Geom &g = a.g;
-  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+__device__ __forceinline__ void push_b(WaveLds &W, QState &q, bool need, uint32_t w0,
+                                       uint32_t d2lo, uint32_t ex, uint32_t ey, int lane,
+                                       unsigned long long *hw) {
+  const unsigned long long m = __builtin_amdgcn_ballot_w64(need);
+  if (m) {
+    const uint32_t pos = lane_rank(m, q.hb + q.nb) & (kQ - 1);
+    if (need) W.qb[pos] = make_uint4(w0, d2lo, ex, ey);
+    q.nb += (uint32_t)__popcll(m);
+    if (q.nb >= 64) {
+      drain_b(W, q.hb, 64, lane, hw);
+      q.hb = (q.hb + 64) & (kQ - 1);
+      q.nb -= 64;
+    }
+  }
+}
+
+// Time, side distances and squared interior radius of a point's LDS image.
+template <int MODE>
+__device__ __forceinline__ void side_info(const int4 p, const Geom &g, uint32_t &T,
+                                          uint32_t &ex, uint32_t &ey, uint64_t &emin2) {
+  if (MODE == kModePacked) {
+    T = (uint32_t)p.y;
+    ex = (uint32_t)p.z & 0xFFFFu;
+    ey = (uint32_t)p.z >> 16;
+    const uint32_t e = min(ex, ey);
+    emin2 = (uint64_t)(e * e);
+  } else {
+    T = (uint32_t)p.z;
+    ex = (uint32_t)min(p.x, g.x1 - g.x0 - p.x);
+    ey = (uint32_t)min(p.y, g.y1 - g.y0 - p.y);
+    emin2 = (uint64_t)(uint32_t)p.w * (uint32_t)p.w;
+  }
+}
+
+// Queue A: bin, temporal weight and the interior fast path of omega.
+template <bool SYM, int MODE>
+__device__ __forceinline__ void drain_a(WaveLds &W, QState &q, uint32_t c, int lane,
+                                        const Geom &g, unsigned long long *hc,
+                                        unsigned long long *hw, const uint32_t *S2lo,
+                                        const uint32_t *S2hi, const uint32_t *T) {
+  wave_sync();
+  const uint4 r = W.qa[(q.ha + lane) & (kQ - 1)];
+  wave_sync();
+  const bool v = (uint32_t)lane < c;
+  bool slow_i = false, slow_j = false;
+  uint32_t w0i = 0, w0j = 0, exi = 0, eyi = 0, exj = 0, eyj = 0;
+  if (v) {
+    const int4 pi = W.cen[r.z & 63u];
+    const int4 pj = W.tile[r.z >> 6];
+    const uint64_t d2 = (uint64_t)r.x | ((uint64_t)r.w << 32);
+    const int32_t sdt = (int32_t)(r.y - g.tmax);
+    const uint32_t u = (uint32_t)(sdt < 0 ? -sdt : sdt);
+    // k* = ceil(sqrt(d2) n_s / s_max) exactly (S2[k] = floor(s_k^2), d2 an
+    // integer); the FP32 quotient is within 1e-5 of it, so one comparison on
+    // each side of the estimate restores the exact step.  Same for l* with T.
+    const float d2f = MODE == kModeWide ? (float)d2 : (float)r.x;
+    int k = min(max((int)ceilf(sqrtf(d2f) * g.inv_ds), 1), g.n_s);
+    int l = min(max((int)ceilf((float)u * g.inv_dt), 1), g.n_t);
+    const int km2 = max(k - 2, 0), lm2 = max(l - 2, 0);
+    uint64_t s_a = S2lo[k - 1], s_b = S2lo[km2];
+    if (MODE == kModeWide) {
+      s_a |= (uint64_t)S2hi[k - 1] << 32;
+      s_b |= (uint64_t)S2hi[km2] << 32;
+    }
+    const uint32_t t_a = T[l - 1], t_b = T[lm2];
+    k += (d2 > s_a) ? 1 : ((k > 1 && d2 <= s_b) ? -1 : 0);
+    l += (u > t_a) ? 1 : ((l > 1 && u <= t_b) ? -1 : 0);
+    const uint32_t bin = (uint32_t)((min(k, g.n_s) - 1) * g.n_t + (min(l, g.n_t) - 1));
+    const uint32_t D = (uint32_t)(g.t1 - g.t0);
+    const bool sp = (g.edge & 1u) != 0, tp = (g.edge & 2u) != 0;
+    uint32_t Ti, Tj;
+    uint64_t e2i, e2j;
+    side_info<MODE>(pi, g, Ti, exi, eyi, e2i);
+    // v = 1/2 when an end of [t-u, t+u] leaves the period: the weight doubles
+    const uint32_t hfi = (tp && (u > Ti || u > D - Ti)) ? 1u : 0u;
+    slow_i = sp && d2 > e2i;
+    uint32_t qsum = slow_i ? 0u : (1u << (kFracBits + hfi));
+    w0i = bin | (hfi << 12) | (r.w << 13);
+    if (SYM) {
+      side_info<MODE>(pj, g, Tj, exj, eyj, e2j);
+      const uint32_t hfj = (tp && (u > Tj || u > D - Tj)) ? 1u : 0u;
+      slow_j = sp && d2 > e2j;
+      qsum += slow_j ? 0u : (1u << (kFracBits + hfj));
+      w0j = bin | (hfj << 12) | (r.w << 13);
+    }
+    atomicAdd(&hc[bin], SYM ? 2ull : 1ull);
+    if (qsum) atomicAdd(&hw[bin], (unsigned long long)qsum);
+  }
+  q.ha = (q.ha + c) & (kQ - 1);
+  q.na -= c;
+  q.drained += c;
+  push_b(W, q, slow_i, w0i, r.x, exi, eyi, lane, hw);
+  if (SYM) push_b(W, q, slow_j, w0j, r.x, exj, eyj, lane, hw);
+}
+
+// LDS image of a sorted point (see WaveLds).
+template <int MODE>
+__device__ __forceinline__ int4 image(const int4 p, const Geom &g) {
+  if (MODE == kModePacked) {
+    const uint32_t ex = min((uint32_t)min(p.x, g.x1 - g.x0 - p.x), kClampE);
+    const uint32_t ey = min((uint32_t)min(p.y, g.y1 - g.y0 - p.y), kClampE);
+    return make_int4((int)(((uint32_t)p.x & 0xFFFFu) | ((uint32_t)p.y << 16)), p.z,
+                     (int)(ex | (ey << 16)), 0);
+  }
+  return p;
+}
+
+template <int MODE>
+__device__ __forceinline__ int4 far_image() {
+  return MODE == kModePacked ? make_int4(0, (int)kFarTime, 0, 0)
+                             : make_int4(0, 0, (int)kFarTime, 0);
+}
+
+// Candidate test of one neighbour against this lane's centre: cs = space test,
+// ct = time test (kept apart so that each ballot folds to its compare mask).
+template <int MODE>
+__device__ __forceinline__ void cand(const int4 me, uint32_t tplus, const int4 pj, const Geom &g,
+                                     uint32_t &d2lo, uint32_t &d2hi, uint32_t &dtp, bool &cs,
+                                     bool &ct) {
+  if (MODE == kModePacked) {
+    typedef short s2 __attribute__((ext_vector_type(2)));
+    const s2 a = __builtin_bit_cast(s2, me.x), b = __builtin_bit_cast(s2, pj.x);
+    const s2 d = a - b;
+    d2lo = (uint32_t)__builtin_amdgcn_sdot2(d, d, 0, false);
+    d2hi = 0;
+    dtp = tplus - (uint32_t)pj.y;
+    cs = d2lo <= (uint32_t)g.s2max;
+  } else if (MODE == kModeU32) {
+    const int32_t dx = me.x - pj.x, dy = me.y - pj.y;
+    d2lo = (uint32_t)__mul24(dx, dx) + (uint32_t)__mul24(dy, dy);
+    d2hi = 0;
+    dtp = tplus - (uint32_t)pj.z;
+    cs = d2lo <= (uint32_t)g.s2max;
+  } else {
+    const int64_t dx = (int64_t)(me.x - pj.x), dy = (int64_t)(me.y - pj.y);
+    const uint64_t d2 = (uint64_t)(dx * dx + dy * dy);
+    d2lo = (uint32_t)d2;
+    d2hi = (uint32_t)(d2 >> 32);
+    dtp = tplus - (uint32_t)pj.z;
+    cs = d2 <= g.s2max;
+  }
+  ct = dtp <= 2u * g.tmax;
+}
+
+template <bool SYM, int MODE>
+struct Ctx {
+  WaveLds &W;
+  QState &q;
+  const Geom &g;
+  unsigned long long *hc, *hw;
+  const uint32_t *S2lo, *S2hi, *T;
+  int lane;
+};
+
+// Drain the c oldest entries of queue A.
+template <bool SYM, int MODE>
+__device__ __forceinline__ void drain_oldest(Ctx<SYM, MODE> &x, uint32_t c) {
+  drain_a<SYM, MODE>(x.W, x.q, c, x.lane, x.g, x.hc, x.hw, x.S2lo, x.S2hi, x.T);
+}
+
+template <bool SYM, int MODE, bool HOME>
+__device__ __forceinline__ void scan_run(Ctx<SYM, MODE> &x, uint32_t j0, uint32_t j1,
+                                         const int4 me, uint32_t tplus,
+                                         unsigned long long valid, uint32_t mi,
+                                         const int4 *__restrict__ P) {
+  const bool vlane = (valid >> x.lane) & 1ull;
+  QState &q = x.q;
+  WaveLds &W = x.W;
+  const int lane = x.lane;
+  if (j0 >= j1) return;
+  // raw record of the next tile; converted to its LDS image only when stored,
+  // so that the load stays in flight while the current tile is scanned
+  int4 nxt = make_int4(0, 0, 0, 0);
+  bool nxt_ok = j0 + (uint32_t)lane < j1;
+  if (nxt_ok) nxt = P[j0 + lane];
   for (uint32_t tb = j0; tb < j1; tb += kJT) {
-    const uint32_t nt = min((uint32_t)kJT, j1 - tb);
+    const uint32_t nt = uni(min((uint32_t)kJT, j1 - tb));
+    // the slot about to be refilled last held the tile before the previous one:
+    // its queue entries are the oldest and must be drained first
+    q.slot ^= 1u;
+    if (q.prev_mark > q.drained) drain_oldest(x, q.prev_mark - q.drained);
+    q.prev_mark = q.drained + q.na;
+    const uint32_t sbase = q.slot * kJT;
     wave_sync();
-    for (uint32_t q = lane; q < nt; q += 64) W.tile[q] = a.P[tb + q];
+    W.tile[sbase + lane] = nxt_ok ? image<MODE>(nxt, x.g) : far_image<MODE>();
     wave_sync();
-    for (uint32_t jj = 0; jj < nt; ++jj) {
-      const int4 pj = W.tile[jj];
-      const uint32_t adx = __usad((uint32_t)me.x, (uint32_t)pj.x, 0u);
-      const uint32_t ady = __usad((uint32_t)me.y, (uint32_t)pj.y, 0u);
-      const uint32_t u = __usad((uint32_t)me.z, (uint32_t)pj.z, 0u);
-      uint64_t d2;
-      bool acc;
-      if (WIDE) {
-        d2 = (uint64_t)adx * adx + (uint64_t)ady * ady;
-        acc = valid && d2 <= g.s2max && u <= g.tmax;
-      } else {
-        const uint32_t d2n = __umul24(adx, adx) + __umul24(ady, ady);
-        d2 = d2n;
-        acc = valid && d2n <= (uint32_t)g.s2max && u <= g.tmax;
-      }
-      const uint32_t j = tb + jj;
-      if (HOME) acc = acc && (SYM ? (j > mi) : (j != mi));
-      const unsigned long long mask = __ballot(acc);
-      if (mask) {
-        const uint32_t pos = (qhead + qn + (uint32_t)__popcll(mask & lt)) & (kQ - 1);
-        if (acc) W.q[pos] = make_uint4(j, (uint32_t)lane | ((uint32_t)(d2 >> 32) << 6),
-                                       (uint32_t)d2, u);
-        qn += (uint32_t)__popcll(mask);
-        if (qn >= 64) {
-          drain<SYM>(W, qhead, 64, lane, a, hc, hw, S2, T);
-          qhead = (qhead + 64) & (kQ - 1);
-          qn -= 64;
+    const uint32_t tn = tb + kJT;
+    if (tn < j1) {
+      nxt_ok = tn + (uint32_t)lane < j1;
+      if (nxt_ok) nxt = P[tn + lane];
+    }
+    const uint32_t lane_tag = (uint32_t)lane | (sbase << 6);
+    for (uint32_t jj = 0; jj < nt; jj += 4) {
+      int4 pj[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) pj[u] = W.tile[sbase + jj + u];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        uint32_t d2lo, d2hi, dtp;
+        bool cs, ct;
+        cand<MODE>(me, tplus, pj[u], x.g, d2lo, d2hi, dtp, cs, ct);
+        const uint32_t j = tb + jj + u;
+        const bool ch = HOME ? (SYM ? (j > mi) : (j != mi)) : true;
+        unsigned long long mask = __builtin_amdgcn_ballot_w64(cs) & __builtin_amdgcn_ballot_w64(ct) & valid;
+        if (HOME) mask &= __builtin_amdgcn_ballot_w64(ch);
+        if (mask) {
+          const uint32_t pos = lane_rank(mask, q.ha + q.na) & (kQ - 1);
+          if (cs && ct && ch && vlane)
+            W.qa[pos] = make_uint4(d2lo, dtp, lane_tag + ((jj + u) << 6), d2hi);
+          q.na += (uint32_t)__popcll(mask);
+          if (q.na >= 64) drain_oldest(x, 64);
         }
       }
     }
   }
 }
 
-template <bool SYM, bool WIDE>
+template <bool SYM, int MODE>
 __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const Geom &g = a.g;
   const int NB = g.n_s * g.n_t;
   unsigned long long *hc = (unsigned long long *)smem;
   unsigned long long *hw = hc + NB;
-  unsigned long long *S2 = hw + NB;
-  uint32_t *T = (uint32_t *)(S2 + kMaxSteps);
-  WaveLds *wl = (WaveLds *)(T + kMaxSteps);
+  uint32_t *S2lo = (uint32_t *)(hw + NB);
+  uint32_t *S2hi = S2lo + kMaxSteps;
+  uint32_t *T = S2hi + kMaxSteps;
+  WaveLds *wl = (WaveLds *)(T + kMaxSteps + 64);
   unsigned long long *evals_lds = (unsigned long long *)(wl + kWaves);
   uint32_t *grp_lds = (uint32_t *)(evals_lds + 1);
 
@@ -195,7 +357,10 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
     hc[b] = 0;
     hw[b] = 0;
   }
-  if (tid < g.n_s) S2[tid] = a.S2[tid];
+  if (tid < g.n_s) {
+    S2lo[tid] = (uint32_t)a.S2[tid];
+    S2hi[tid] = (uint32_t)(a.S2[tid] >> 32);
+  }
   if (tid < g.n_t) T[tid] = a.T[tid];
   if (tid == 0) *evals_lds = 0;
   const uint32_t n_items = *a.n_items;
@@ -221,10 +386,10 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
     __syncthreads();  // previous group finished by every wave
     if (tid == 0) *grp_lds = atomicAdd(a.item_ctr, 1u);
     __syncthreads();
-    const uint32_t grp = __builtin_amdgcn_readfirstlane(*grp_lds);
+    const uint32_t grp = uni(*grp_lds);
     const uint32_t base = grp * kItemsPerGroup;
     if (base >= n_items) break;
-    const int set = (int)__builtin_amdgcn_readfirstlane(a.items[base].set);
+    const int set = (int)uni(a.items[base].set);
     const unsigned long long pend = *evals_lds;
     if (set != cur_set || pend > kFlushEvals) {
       if (cur_set >= 0) flush(cur_set);
@@ -234,13 +399,16 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
       __syncthreads();
     }
     const Item it = a.items[base + wv];
-    const uint32_t cnt = __builtin_amdgcn_readfirstlane(it.count);
+    const uint32_t cnt = uni(it.count);
     if (cnt == 0) continue;
-    const uint32_t begin = __builtin_amdgcn_readfirstlane(it.begin);
-    const uint32_t cell = __builtin_amdgcn_readfirstlane(it.cell);
+    const uint32_t begin = uni(it.begin);
+    const uint32_t cell = uni(it.cell);
     const bool valid = (uint32_t)lane < cnt;
+    const unsigned long long vmask = __builtin_amdgcn_ballot_w64(valid);
     const uint32_t mi = begin + (uint32_t)lane;
-    const int4 me = valid ? a.P[mi] : make_int4(0, 0, 0, 0);
+    const int4 raw = valid ? a.P[mi] : make_int4(0, 0, 0, 0);
+    const int4 me = image<MODE>(raw, g);
+    const uint32_t tplus = (uint32_t)(MODE == kModePacked ? me.y : me.z) + g.tmax;
     W.cen[lane] = me;
     wave_sync();
     const int cx = (int)(cell % (uint32_t)g.nx);
@@ -248,7 +416,8 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
     const int cy = (int)(rest % (uint32_t)g.ny);
     const int ct = (int)(rest / (uint32_t)g.ny);
     const uint32_t set_off = (uint32_t)set * g.n_cells;
-    uint32_t qhead = 0, qn = 0;
+    QState q = {0u, 0u, 0u, 0u, 0u, 0u, 0u};
+    Ctx<SYM, MODE> x{W, q, g, hc, hw, S2lo, S2hi, T, lane};
     unsigned long long ev = 0;
     for (int dt = SYM ? 0 : -g.rt; dt <= g.rt; ++dt) {
       const int tt = ct + dt;
@@ -261,8 +430,8 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
         const int xlo = (SYM && home) ? cx : max(cx - g.rs, 0);
         const int xhi = min(cx + g.rs, g.nx - 1);
         const uint32_t row = set_off + (uint32_t)(tt * g.ny + yy) * (uint32_t)g.nx;
-        uint32_t j0 = a.cs[2 * (row + (uint32_t)xlo)];
-        const uint32_t j1 = a.cs[2 * (row + (uint32_t)xhi) + 2];
+        uint32_t j0 = uni(a.cs[2 * (row + (uint32_t)xlo)]);
+        const uint32_t j1 = uni(a.cs[2 * (row + (uint32_t)xhi) + 2]);
         if (home) {
           if (SYM) {
             j0 = begin + 1;
@@ -270,14 +439,18 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
           } else {
             ev += (unsigned long long)cnt * (j1 - j0) - cnt;
           }
-          scan_run<SYM, WIDE, true>(j0, j1, me, valid, mi, lane, W, qhead, qn, a, hc, hw, S2, T);
+          scan_run<SYM, MODE, true>(x, j0, j1, me, tplus, vmask, mi, a.P);
         } else {
           ev += (unsigned long long)cnt * (j1 - j0);
-          scan_run<SYM, WIDE, false>(j0, j1, me, valid, mi, lane, W, qhead, qn, a, hc, hw, S2, T);
+          scan_run<SYM, MODE, false>(x, j0, j1, me, tplus, vmask, mi, a.P);
         }
       }
     }
-    if (qn) drain<SYM>(W, qhead, qn, lane, a, hc, hw, S2, T);
+    if (q.na) drain_oldest(x, q.na);
+    if (q.nb) {
+      drain_b(W, q.hb, q.nb, lane, hw);
+      q.nb = 0;
+    }
     if (lane == 0) atomicAdd(evals_lds, ev);
     evals_total += ev;
   }
@@ -285,34 +458,46 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
   if (lane == 0 && evals_total) atomicAdd(a.n_eval, evals_total);
 }
 
-template <bool SYM, bool WIDE>
+template <bool SYM, int MODE>
 hipError_t launch_t(const PairArgs &a, int grid, hipStream_t s) {
   const int lds = pair_lds_bytes(a.g.n_s * a.g.n_t);
-  hipLaunchKernelGGL((k_pair<SYM, WIDE>), dim3(grid), dim3(kPairThreads), lds, s, a);
+  hipLaunchKernelGGL((k_pair<SYM, MODE>), dim3(grid), dim3(kPairThreads), lds, s, a);
   return hipGetLastError();
 }
 
-template <bool SYM, bool WIDE>
+template <bool SYM, int MODE>
 hipError_t occ_t(int lds, int *per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_pair<SYM, WIDE>, kPairThreads,
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_pair<SYM, MODE>, kPairThreads,
                                                       lds);
+}
+
+template <bool SYM>
+hipError_t occ_mode(int mode, int lds, int *per_cu) {
+  if (mode == kModePacked) return occ_t<SYM, kModePacked>(lds, per_cu);
+  if (mode == kModeU32) return occ_t<SYM, kModeU32>(lds, per_cu);
+  return occ_t<SYM, kModeWide>(lds, per_cu);
+}
+
+template <bool SYM>
+hipError_t launch_mode(const PairArgs &a, int grid, hipStream_t s) {
+  if (a.g.mode == kModePacked) return launch_t<SYM, kModePacked>(a, grid, s);
+  if (a.g.mode == kModeU32) return launch_t<SYM, kModeU32>(a, grid, s);
+  return launch_t<SYM, kModeWide>(a, grid, s);
 }
 
 }  // namespace
 
 int pair_lds_bytes(int n_bins) {
-  return 16 * n_bins + 8 * kMaxSteps + 4 * kMaxSteps + (int)sizeof(WaveLds) * kWaves + 16;
+  return 16 * n_bins + 4 * (3 * kMaxSteps + 64) + (int)sizeof(WaveLds) * kWaves + 16;
 }
 
-hipError_t pair_occupancy(int n_bins, int symmetric, int wide, int *per_cu) {
+hipError_t pair_occupancy(int n_bins, int symmetric, int mode, int *per_cu) {
   const int lds = pair_lds_bytes(n_bins);
-  if (symmetric) return wide ? occ_t<true, true>(lds, per_cu) : occ_t<true, false>(lds, per_cu);
-  return wide ? occ_t<false, true>(lds, per_cu) : occ_t<false, false>(lds, per_cu);
+  return symmetric ? occ_mode<true>(mode, lds, per_cu) : occ_mode<false>(mode, lds, per_cu);
 }
 
 hipError_t launch_pair(const PairArgs &a, int grid, hipStream_t s) {
-  if (a.symmetric) return a.g.wide ? launch_t<true, true>(a, grid, s) : launch_t<true, false>(a, grid, s);
-  return a.g.wide ? launch_t<false, true>(a, grid, s) : launch_t<false, false>(a, grid, s);
+  return a.symmetric ? launch_mode<true>(a, grid, s) : launch_mode<false>(a, grid, s);
 }
 
 }  // namespace ripk

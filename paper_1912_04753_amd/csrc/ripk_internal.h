@@ -12,6 +12,12 @@ constexpr int kItemsPerGroup = 4;  // work items grabbed together by one workgro
 constexpr int kPairThreads = 256;  // workgroup size of the pair kernel (4 wavefronts)
 constexpr int kFracBits = 23;      // fixed-point fraction bits of the weight sums
 
+// Arithmetic of the candidate distance test (chosen per plan from the largest
+// coordinate difference a stencil can hold).
+constexpr int kModePacked = 0;  // 16-bit packed x/y differences, |dx|, |dy| < 2^15
+constexpr int kModeU32 = 1;     // 32-bit squared distances
+constexpr int kModeWide = 2;    // 64-bit squared distances
+
 // Geometry and thresholds shared by the grid and pair kernels (by value).
 struct Geom {
   int32_t x0, y0, x1, y1, t0, t1;  // closed window; all coordinates are int32
@@ -21,7 +27,7 @@ struct Geom {
   uint32_t n_cells;                // nx*ny*nt
   int32_t n_s, n_t;
   uint32_t edge;
-  uint32_t wide;                   // 64-bit squared distances
+  int32_t mode;                    // kModePacked / kModeU32 / kModeWide
   uint64_t s2max;                  // S2[n_s-1]
   uint32_t tmax;                   // T[n_t-1]
   float inv_ds;                    // n_s / s_max
@@ -77,7 +83,7 @@ hipError_t launch_fill_u64(unsigned long long *p, size_t n, unsigned long long v
                            hipStream_t s);
 hipError_t launch_pair(const PairArgs &a, int grid, hipStream_t s);
 int pair_lds_bytes(int n_bins);
-hipError_t pair_occupancy(int n_bins, int symmetric, int wide, int *per_cu);
+hipError_t pair_occupancy(int n_bins, int symmetric, int mode, int *per_cu);
 hipError_t launch_finalize(unsigned long long *binC, unsigned long long *binW,
                            uint32_t n_sets, int n_s, int n_t, double s_max, double t_max,
                            double AD, double N, unsigned long long *C, double *W, double *K,

@@ -52,7 +52,7 @@ class PlanDesc(ctypes.Structure):
 class PlanInfo(ctypes.Structure):
     _fields_ = [("S2", _i64 * 64), ("T", _i64 * 64), ("cell_s", _i64), ("cell_t", _i64),
                 ("nx", _i32), ("ny", _i32), ("nt", _i32), ("reach_s", _i32),
-                ("reach_t", _i32), ("n_cells", _i64), ("wide", _i32), ("n_bins", _i32),
+                ("reach_t", _i32), ("n_cells", _i64), ("dist_mode", _i32), ("n_bins", _i32),
                 ("device_bytes", _i64)]
 
 
@@ -157,7 +157,7 @@ def ripk_plan_check(desc):
     return {"S2": np.array(info.S2[:ns], np.int64), "T": np.array(info.T[:nt], np.int64),
             "cell_s": info.cell_s, "cell_t": info.cell_t, "nx": info.nx, "ny": info.ny,
             "nt": info.nt, "reach_s": info.reach_s, "reach_t": info.reach_t,
-            "n_cells": info.n_cells, "wide": info.wide, "n_bins": info.n_bins,
+            "n_cells": info.n_cells, "dist_mode": info.dist_mode, "n_bins": info.n_bins,
             "device_bytes": info.device_bytes}
 
 

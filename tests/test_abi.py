@@ -48,7 +48,7 @@ def test_plan_geometry_config3():
     info = ripk.ripk_plan_check(desc())
     assert (info["nx"], info["ny"], info["nt"]) == (10, 10, 6)
     assert info["reach_s"] == 1 and info["reach_t"] == 1
-    assert info["wide"] == 0
+    assert info["dist_mode"] == 0          # packed 16-bit differences
     assert info["n_bins"] == 375
     # exact floors: d <= s_k <=> d2 <= S2[k] (Eq. 3)
     for k, v in enumerate(info["S2"], 1):
@@ -63,11 +63,12 @@ def test_plan_geometry_finer_cells_and_wide():
     assert info["reach_s"] == 2 and info["reach_t"] == 3
     w = ripk.ripk_plan_check(ripk.make_desc((0, 0, 200_000, 150_000, 0, 3_000_000), 40_000,
                                             600_000, 20, 12, n_max=10))
-    assert w["wide"] == 1
+    assert w["dist_mode"] == 2
 
 
 @pytest.mark.parametrize("bad", [
     dict(n_s=0), dict(n_t=65), dict(s_max=10_001), dict(t_max=15_552_001),
+    dict(edge=1, window=(0, 0, 20_000, 20_000, 0, 2**31 - 1), t_max=2**30),
     dict(window=(0, 0, 0, 10, 0, 10)), dict(window=(0, 0, 2**24, 10**6, 0, 10**8), s_max=10),
     dict(n_max=1), dict(m_max=-1), dict(n_max=2**26, m_max=64), dict(edge=4),
     dict(norm=2), dict(cell_div=9), dict(s_max=0),

@@ -237,7 +237,7 @@ def test_wide_distances():
     x = rng.integers(0, 200_001, n); y = rng.integers(0, 150_001, n); t = rng.integers(0, 30_000_001, n)
     args = (win, 40_000, 6_000_000, 20, 12)
     info = ripk.ripk_plan_check(ripk.make_desc(*args, n_max=n))
-    assert info["wide"] == 1
+    assert info["dist_mode"] == 2
     say("wide n=%d" % n)
     g = gpu_K(x, y, t, *args)
     r = ref_K(x, y, t, *args)
