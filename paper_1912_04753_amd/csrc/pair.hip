@@ -49,12 +49,13 @@ constexpr unsigned long long kFlushEvals = 1ull << 34;  // bound on candidates b
 constexpr uint32_t kFarTime = 0xC0000000u;  // tile padding: fails every time test
 constexpr uint32_t kClampE = 32767u;         // side distances stored in 15 bits (PACKED)
 
-// LDS image of a point.  PACKED: {x|y<<16 (low 16 bits each), t, ex|ey<<16, -};
-// U32 / WIDE: {x, y, t, min side distance}.  Coordinates are window relative.
+// LDS image of a point.  PACKED: {x|y<<16 (low 16 bits each), t, ex|ey<<16,
+// min(ex,ey)^2}; U32 / WIDE: {x, y, t, min side distance}.  Coordinates are
+// window relative; ex, ey are the distances to the nearer x and y side.
 struct WaveLds {
   int4 tile[2 * kJT];  // two tile slots of neighbour points
   int4 cen[64];        // the wave's centres
-  uint4 qa[kQ];        // in-range pairs: {d2 lo, t_i + t_max - t_j, lane | tile index << 6, d2 hi}
+  uint4 qa[kQ];        // in-range pairs: {d2 lo, t_i + t_max - t_j, lane<<4 | tile index<<14, d2 hi}
   uint4 qb[kQ];        // boundary weights: {bin | halfv << 12 | d2 hi << 13, d2 lo, ex, ey}
 };
 
@@ -80,31 +81,55 @@ __device__ __forceinline__ uint32_t lane_rank(unsigned long long mask, uint32_t 
                                    __builtin_amdgcn_mbcnt_lo((uint32_t)mask, base));
 }
 
-// Isotropic correction on the rectangle in FP32 from the distances ex, ey to the
-// nearer x side and the nearer y side (only these can cut a circle of radius
-// <= min(W, H)/2), complementary-angle form: beta_e = atan2(e, sqrt(d2 - e^2))
-// with d2 - e^2 an exact integer.  One side cut: 1/2 + beta/pi; two sides with
-// the corner outside (or on) the circle: (beta_x + beta_y)/pi; corner inside:
-// 1/4 + (beta_x + beta_y)/(2 pi).  All terms are non-negative.
-__device__ __forceinline__ float omega_f32(uint32_t ex, uint32_t ey, uint64_t d2) {
-  const uint64_t ex2 = (uint64_t)ex * ex, ey2 = (uint64_t)ey * ey;
-  const bool cx = ex2 < d2, cy = ey2 < d2;
-  const float inv_pi = 0.318309886183790671538f;
-  float bx = 0.0f, by = 0.0f;
-  if (cx) bx = atan2f((float)ex, sqrtf((float)(d2 - ex2)));
-  if (cy) by = atan2f((float)ey, sqrtf((float)(d2 - ey2)));
-  if (cx && cy) {
-    if (ex2 + ey2 < d2) return 0.25f + (bx + by) * (0.5f * inv_pi);
-    return (bx + by) * inv_pi;
-  }
-  if (cx) return 0.5f + bx * inv_pi;
-  if (cy) return 0.5f + by * inv_pi;
-  return 1.0f;
+// arctan(z) for z in [0, 1]: z * P(z^2), P of degree 8 in z^2 fitted (near-minimax,
+// iteratively reweighted least squares) to arctan over [0, 1]; largest error of the
+// fit 6e-9, about 1e-7 once evaluated in FP32 with fused multiply-adds.
+__device__ __forceinline__ float atan01(float z) {
+  const float w = z * z;
+  float p = 0.002456706715747714f;
+  p = fmaf(p, w, -0.014401290565729141f);
+  p = fmaf(p, w, 0.0397811196744442f);
+  p = fmaf(p, w, -0.07234849780797958f);
+  p = fmaf(p, w, 0.1049894317984581f);
+  p = fmaf(p, w, -0.14161229133605957f);
+  p = fmaf(p, w, 0.19985906779766083f);
+  p = fmaf(p, w, -0.33332598209381104f);
+  p = fmaf(p, w, 0.9999998807907104f);
+  return p * z;
 }
 
-// Queue B: boundary weights with full lanes (out of line: rare, and large).
+// beta = atan2(e, h) for e, h >= 0, not both 0: the angle between the radius to
+// a side's crossing point and the side itself; pi/2 when the side is not cut.
+__device__ __forceinline__ float beta_angle(float e, float h) {
+  const float lo = fminf(e, h), hi = fmaxf(e, h);
+  float r = __builtin_amdgcn_rcpf(hi);
+  r = fmaf(fmaf(-hi, r, 1.0f), r, r);  // one Newton step: quotient to ~1 ulp
+  const float a = atan01(lo * r);
+  return e > h ? 1.5707963267948966f - a : a;
+}
+
+// Isotropic correction on the rectangle in FP32 from the distances ex, ey to the
+// nearer x side and the nearer y side (only these can cut a circle of radius
+// <= min(W, H)/2).  With beta_e = atan2(e, sqrt(max(d2 - e^2, 0))) (= pi/2 for an
+// uncut side; d2 - e^2 is an exact integer) the excluded half-arcs are
+// pi/2 - beta_e and two cut sides overlap by max(0, pi/2 - beta_x - beta_y),
+// which gives, without branches,
+//   omega = (beta_x + beta_y)/pi + max(0, pi/2 - beta_x - beta_y)/(2 pi):
+// 1 with no cut, 1/2 + beta/pi with one, (beta_x + beta_y)/pi with two and the
+// corner outside the circle, 1/4 + (beta_x + beta_y)/(2 pi) with it inside.
+__device__ __forceinline__ float omega_f32(uint32_t ex, uint32_t ey, uint64_t d2) {
+  const uint64_t ex2 = (uint64_t)ex * ex, ey2 = (uint64_t)ey * ey;
+  const float hx = sqrtf((float)(ex2 < d2 ? d2 - ex2 : 0ull));
+  const float hy = sqrtf((float)(ey2 < d2 ? d2 - ey2 : 0ull));
+  const float bx = beta_angle((float)ex, hx), by = beta_angle((float)ey, hy);
+  const float sum = bx + by;
+  const float inv_pi = 0.318309886183790671538f;
+  return sum * inv_pi + fmaxf(1.5707963267948966f - sum, 0.0f) * (0.5f * inv_pi);
+}
+
+// Queue B: boundary weights with full lanes.
 __device__ __noinline__ void drain_b(WaveLds &W, uint32_t head, uint32_t c, int lane,
-                                     unsigned long long *hw) {
+                                        unsigned long long *hist, uint32_t nb) {
   wave_sync();
   const uint4 r = W.qb[(head + lane) & (kQ - 1)];
   wave_sync();
@@ -116,103 +141,120 @@ __device__ __noinline__ void drain_b(WaveLds &W, uint32_t head, uint32_t c, int 
     const float w = fmaxf(__frcp_rn(om), 1.0f);
     // w >= 1 has at most 23 fraction bits: w * 2^23 is an exact integer
     const uint32_t qv = (uint32_t)(w * (float)(1u << kFracBits)) << half;
-    atomicAdd(&hw[bin], (unsigned long long)qv);
+    atomicAdd(&hist[nb + bin], (unsigned long long)qv);
   }
 }
 
 __device__ __forceinline__ void push_b(WaveLds &W, QState &q, bool need, uint32_t w0,
                                        uint32_t d2lo, uint32_t ex, uint32_t ey, int lane,
-                                       unsigned long long *hw) {
-  const unsigned long long m = __builtin_amdgcn_ballot_w64(need);
+                                       unsigned long long *hist, unsigned long long vmask,
+                                       uint32_t nbins) {
+  const unsigned long long m = __builtin_amdgcn_ballot_w64(need) & vmask;
   if (m) {
     const uint32_t pos = lane_rank(m, q.hb + q.nb) & (kQ - 1);
-    if (need) W.qb[pos] = make_uint4(w0, d2lo, ex, ey);
+    if ((m >> lane) & 1ull) W.qb[pos] = make_uint4(w0, d2lo, ex, ey);
     q.nb += (uint32_t)__popcll(m);
     if (q.nb >= 64) {
-      drain_b(W, q.hb, 64, lane, hw);
+      drain_b(W, q.hb, 64, lane, hist, nbins);
       q.hb = (q.hb + 64) & (kQ - 1);
       q.nb -= 64;
     }
   }
 }
 
-// Time, side distances and squared interior radius of a point's LDS image.
-template <int MODE>
-__device__ __forceinline__ void side_info(const int4 p, const Geom &g, uint32_t &T,
-                                          uint32_t &ex, uint32_t &ey, uint64_t &emin2) {
-  if (MODE == kModePacked) {
-    T = (uint32_t)p.y;
-    ex = (uint32_t)p.z & 0xFFFFu;
-    ey = (uint32_t)p.z >> 16;
-    const uint32_t e = min(ex, ey);
-    emin2 = (uint64_t)(e * e);
-  } else {
-    T = (uint32_t)p.z;
-    ex = (uint32_t)min(p.x, g.x1 - g.x0 - p.x);
-    ey = (uint32_t)min(p.y, g.y1 - g.y0 - p.y);
-    emin2 = (uint64_t)(uint32_t)p.w * (uint32_t)p.w;
-  }
-}
-
-// Queue A: bin, temporal weight and the interior fast path of omega.
+// Queue A: bin, temporal weight and the interior fast path of omega, without
+// branches on per-lane data (lanes past c compute garbage that is never stored).
 template <bool SYM, int MODE>
 __device__ __forceinline__ void drain_a(WaveLds &W, QState &q, uint32_t c, int lane,
-                                        const Geom &g, unsigned long long *hc,
-                                        unsigned long long *hw, const uint32_t *S2lo,
-                                        const uint32_t *S2hi, const uint32_t *T) {
+                                        const Geom &g, unsigned long long *hist,
+                                        const uint32_t *S2lo, const uint32_t *S2hi,
+                                        const uint32_t *T) {
   wave_sync();
   const uint4 r = W.qa[(q.ha + lane) & (kQ - 1)];
   wave_sync();
+  const unsigned long long vmask = c >= 64 ? ~0ull : ((1ull << c) - 1ull);
   const bool v = (uint32_t)lane < c;
-  bool slow_i = false, slow_j = false;
-  uint32_t w0i = 0, w0j = 0, exi = 0, eyi = 0, exj = 0, eyj = 0;
+  // lanes past c hold stale ring slots: point them at entry 0
+  const uint32_t tag = v ? r.z : 0u;
+  const int4 pi = *(const int4 *)((const char *)W.cen + (tag & 0x3F0u));
+  const int4 pj = *(const int4 *)((const char *)W.tile + (tag >> 10));
+  const uint32_t d2lo = r.x;
+  const uint64_t d2 = MODE == kModeWide ? ((uint64_t)r.x | ((uint64_t)r.w << 32)) : (uint64_t)r.x;
+  const int32_t sdt = (int32_t)(r.y - g.tmax);
+  const uint32_t u = (uint32_t)max(sdt, -sdt);
+  // k* = ceil(sqrt(d2) n_s / s_max) exactly (S2[k] = floor(s_k^2), d2 an integer);
+  // the FP32 quotient is within 1e-5 of it, so one comparison on each side of
+  // the estimate restores the exact step.  Same for l* with the T table.
+  const float d2f = MODE == kModeWide ? (float)d2 : (float)d2lo;
+  int k = __builtin_amdgcn_fmed3f(ceilf(__builtin_amdgcn_sqrtf(d2f) * g.inv_ds), 1.0f,
+                                  (float)g.n_s);
+  int l = __builtin_amdgcn_fmed3f(ceilf((float)u * g.inv_dt), 1.0f, (float)g.n_t);
+  const int km2 = max(k - 2, 0), lm2 = max(l - 2, 0);
+  // all four table reads are issued together (no short-circuit loads)
+  const uint32_t sa_lo = S2lo[k - 1], sb_lo = S2lo[km2];
+  const uint32_t ta = T[l - 1], tb = T[lm2];
+  bool up_k, dn_k;
+  if (MODE == kModeWide) {
+    const uint64_t s_a = (uint64_t)sa_lo | ((uint64_t)S2hi[k - 1] << 32);
+    const uint64_t s_b = (uint64_t)sb_lo | ((uint64_t)S2hi[km2] << 32);
+    up_k = d2 > s_a;
+    dn_k = (k > 1) & (d2 <= s_b);
+  } else {
+    up_k = d2lo > sa_lo;
+    dn_k = (k > 1) & (d2lo <= sb_lo);
+  }
+  const bool up_l = u > ta, dn_l = (l > 1) & (u <= tb);
+  // the tables increase, so at most one of up/dn holds
+  k += (int)up_k - (int)dn_k;
+  l += (int)up_l - (int)dn_l;
+  const uint32_t bin = (uint32_t)((min(k, g.n_s) - 1) * g.n_t + (min(l, g.n_t) - 1));
+  const uint32_t D = (uint32_t)(g.t1 - g.t0);
+  const bool sp = (g.edge & 1u) != 0, tp = (g.edge & 2u) != 0;
+  // v = 1/2 when an end of [t-u, t+u] leaves the period: the weight doubles
+  uint32_t Ti, Tj, exi, eyi, exj = 0, eyj = 0;
+  bool slow_i, slow_j = false;
+  if (MODE == kModePacked) {
+    Ti = (uint32_t)pi.y;
+    exi = (uint32_t)pi.z & 0xFFFFu;
+    eyi = (uint32_t)pi.z >> 16;
+    slow_i = d2lo > (uint32_t)pi.w;
+  } else {
+    Ti = (uint32_t)pi.z;
+    exi = (uint32_t)min(pi.x, g.x1 - g.x0 - pi.x);
+    eyi = (uint32_t)min(pi.y, g.y1 - g.y0 - pi.y);
+    slow_i = d2 > (uint64_t)(uint32_t)pi.w * (uint32_t)pi.w;
+  }
+  slow_i = sp && slow_i;
+  const uint32_t hfi = (tp && u > min(Ti, D - Ti)) ? 1u : 0u;
+  uint32_t qsum = slow_i ? 0u : (1u << (kFracBits + hfi));
+  uint32_t hfj = 0;
+  if (SYM) {
+    if (MODE == kModePacked) {
+      Tj = (uint32_t)pj.y;
+      exj = (uint32_t)pj.z & 0xFFFFu;
+      eyj = (uint32_t)pj.z >> 16;
+      slow_j = d2lo > (uint32_t)pj.w;
+    } else {
+      Tj = (uint32_t)pj.z;
+      exj = (uint32_t)min(pj.x, g.x1 - g.x0 - pj.x);
+      eyj = (uint32_t)min(pj.y, g.y1 - g.y0 - pj.y);
+      slow_j = d2 > (uint64_t)(uint32_t)pj.w * (uint32_t)pj.w;
+    }
+    slow_j = sp && slow_j;
+    hfj = (tp && u > min(Tj, D - Tj)) ? 1u : 0u;
+    qsum += slow_j ? 0u : (1u << (kFracBits + hfj));
+  }
   if (v) {
-    const int4 pi = W.cen[r.z & 63u];
-    const int4 pj = W.tile[r.z >> 6];
-    const uint64_t d2 = (uint64_t)r.x | ((uint64_t)r.w << 32);
-    const int32_t sdt = (int32_t)(r.y - g.tmax);
-    const uint32_t u = (uint32_t)(sdt < 0 ? -sdt : sdt);
-    // k* = ceil(sqrt(d2) n_s / s_max) exactly (S2[k] = floor(s_k^2), d2 an
-    // integer); the FP32 quotient is within 1e-5 of it, so one comparison on
-    // each side of the estimate restores the exact step.  Same for l* with T.
-    const float d2f = MODE == kModeWide ? (float)d2 : (float)r.x;
-    int k = min(max((int)ceilf(sqrtf(d2f) * g.inv_ds), 1), g.n_s);
-    int l = min(max((int)ceilf((float)u * g.inv_dt), 1), g.n_t);
-    const int km2 = max(k - 2, 0), lm2 = max(l - 2, 0);
-    uint64_t s_a = S2lo[k - 1], s_b = S2lo[km2];
-    if (MODE == kModeWide) {
-      s_a |= (uint64_t)S2hi[k - 1] << 32;
-      s_b |= (uint64_t)S2hi[km2] << 32;
-    }
-    const uint32_t t_a = T[l - 1], t_b = T[lm2];
-    k += (d2 > s_a) ? 1 : ((k > 1 && d2 <= s_b) ? -1 : 0);
-    l += (u > t_a) ? 1 : ((l > 1 && u <= t_b) ? -1 : 0);
-    const uint32_t bin = (uint32_t)((min(k, g.n_s) - 1) * g.n_t + (min(l, g.n_t) - 1));
-    const uint32_t D = (uint32_t)(g.t1 - g.t0);
-    const bool sp = (g.edge & 1u) != 0, tp = (g.edge & 2u) != 0;
-    uint32_t Ti, Tj;
-    uint64_t e2i, e2j;
-    side_info<MODE>(pi, g, Ti, exi, eyi, e2i);
-    // v = 1/2 when an end of [t-u, t+u] leaves the period: the weight doubles
-    const uint32_t hfi = (tp && (u > Ti || u > D - Ti)) ? 1u : 0u;
-    slow_i = sp && d2 > e2i;
-    uint32_t qsum = slow_i ? 0u : (1u << (kFracBits + hfi));
-    w0i = bin | (hfi << 12) | (r.w << 13);
-    if (SYM) {
-      side_info<MODE>(pj, g, Tj, exj, eyj, e2j);
-      const uint32_t hfj = (tp && (u > Tj || u > D - Tj)) ? 1u : 0u;
-      slow_j = sp && d2 > e2j;
-      qsum += slow_j ? 0u : (1u << (kFracBits + hfj));
-      w0j = bin | (hfj << 12) | (r.w << 13);
-    }
-    atomicAdd(&hc[bin], SYM ? 2ull : 1ull);
-    if (qsum) atomicAdd(&hw[bin], (unsigned long long)qsum);
+    atomicAdd(&hist[bin], SYM ? 2ull : 1ull);
+    atomicAdd(&hist[g.n_s * g.n_t + bin], (unsigned long long)qsum);
   }
   q.ha = (q.ha + c) & (kQ - 1);
   q.na -= c;
   q.drained += c;
-  push_b(W, q, slow_i, w0i, r.x, exi, eyi, lane, hw);
-  if (SYM) push_b(W, q, slow_j, w0j, r.x, exj, eyj, lane, hw);
+  const uint32_t w0 = bin | (r.w << 13);
+  const uint32_t nbins = (uint32_t)(g.n_s * g.n_t);
+  push_b(W, q, slow_i, w0 | (hfi << 12), d2lo, exi, eyi, lane, hist, vmask, nbins);
+  if (SYM) push_b(W, q, slow_j, w0 | (hfj << 12), d2lo, exj, eyj, lane, hist, vmask, nbins);
 }
 
 // LDS image of a sorted point (see WaveLds).
@@ -221,8 +263,9 @@ __device__ __forceinline__ int4 image(const int4 p, const Geom &g) {
   if (MODE == kModePacked) {
     const uint32_t ex = min((uint32_t)min(p.x, g.x1 - g.x0 - p.x), kClampE);
     const uint32_t ey = min((uint32_t)min(p.y, g.y1 - g.y0 - p.y), kClampE);
+    const uint32_t e = min(ex, ey);
     return make_int4((int)(((uint32_t)p.x & 0xFFFFu) | ((uint32_t)p.y << 16)), p.z,
-                     (int)(ex | (ey << 16)), 0);
+                     (int)(ex | (ey << 16)), (int)(e * e));
   }
   return p;
 }
@@ -269,7 +312,7 @@ struct Ctx {
   WaveLds &W;
   QState &q;
   const Geom &g;
-  unsigned long long *hc, *hw;
+  unsigned long long *hist;
   const uint32_t *S2lo, *S2hi, *T;
   int lane;
 };
@@ -277,7 +320,7 @@ struct Ctx {
 // Drain the c oldest entries of queue A.
 template <bool SYM, int MODE>
 __device__ __forceinline__ void drain_oldest(Ctx<SYM, MODE> &x, uint32_t c) {
-  drain_a<SYM, MODE>(x.W, x.q, c, x.lane, x.g, x.hc, x.hw, x.S2lo, x.S2hi, x.T);
+  drain_a<SYM, MODE>(x.W, x.q, c, x.lane, x.g, x.hist, x.S2lo, x.S2hi, x.T);
 }
 
 template <bool SYM, int MODE, bool HOME>
@@ -311,7 +354,7 @@ __device__ __forceinline__ void scan_run(Ctx<SYM, MODE> &x, uint32_t j0, uint32_
       nxt_ok = tn + (uint32_t)lane < j1;
       if (nxt_ok) nxt = P[tn + lane];
     }
-    const uint32_t lane_tag = (uint32_t)lane | (sbase << 6);
+    const uint32_t lane_tag = ((uint32_t)lane << 4) | (sbase << 14);
     for (uint32_t jj = 0; jj < nt; jj += 4) {
       int4 pj[4];
 #pragma unroll
@@ -328,7 +371,7 @@ __device__ __forceinline__ void scan_run(Ctx<SYM, MODE> &x, uint32_t j0, uint32_
         if (mask) {
           const uint32_t pos = lane_rank(mask, q.ha + q.na) & (kQ - 1);
           if (cs && ct && ch && vlane)
-            W.qa[pos] = make_uint4(d2lo, dtp, lane_tag + ((jj + u) << 6), d2hi);
+            W.qa[pos] = make_uint4(d2lo, dtp, lane_tag + ((jj + u) << 14), d2hi);
           q.na += (uint32_t)__popcll(mask);
           if (q.na >= 64) drain_oldest(x, 64);
         }
@@ -342,9 +385,9 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const Geom &g = a.g;
   const int NB = g.n_s * g.n_t;
-  unsigned long long *hc = (unsigned long long *)smem;
-  unsigned long long *hw = hc + NB;
-  uint32_t *S2lo = (uint32_t *)(hw + NB);
+  // counts [0, NB), fixed-point weights [NB, 2 NB)
+  unsigned long long *hist = (unsigned long long *)smem;
+  uint32_t *S2lo = (uint32_t *)(hist + 2 * NB);
   uint32_t *S2hi = S2lo + kMaxSteps;
   uint32_t *T = S2hi + kMaxSteps;
   WaveLds *wl = (WaveLds *)(T + kMaxSteps + 64);
@@ -354,8 +397,8 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   WaveLds &W = wl[wv];
   for (int b = tid; b < NB; b += kPairThreads) {
-    hc[b] = 0;
-    hw[b] = 0;
+    hist[b] = 0;
+    hist[NB + b] = 0;
   }
   if (tid < g.n_s) {
     S2lo[tid] = (uint32_t)a.S2[tid];
@@ -369,15 +412,15 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
 
   auto flush = [&](int set) {
     for (int b = tid; b < NB; b += kPairThreads) {
-      const unsigned long long c = hc[b];
+      const unsigned long long c = hist[b];
       if (c) {
-        const unsigned long long w = hw[b];
+        const unsigned long long w = hist[NB + b];
         const size_t o = (size_t)set * NB + b;
         atomicAdd(&a.binC[o], c);
         const unsigned long long old = atomicAdd(&a.binW[2 * o], w);
         if (old + w < old) atomicAdd(&a.binW[2 * o + 1], 1ull);
-        hc[b] = 0;
-        hw[b] = 0;
+        hist[b] = 0;
+        hist[NB + b] = 0;
       }
     }
   };
@@ -417,7 +460,7 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
     const int ct = (int)(rest / (uint32_t)g.ny);
     const uint32_t set_off = (uint32_t)set * g.n_cells;
     QState q = {0u, 0u, 0u, 0u, 0u, 0u, 0u};
-    Ctx<SYM, MODE> x{W, q, g, hc, hw, S2lo, S2hi, T, lane};
+    Ctx<SYM, MODE> x{W, q, g, hist, S2lo, S2hi, T, lane};
     unsigned long long ev = 0;
     for (int dt = SYM ? 0 : -g.rt; dt <= g.rt; ++dt) {
       const int tt = ct + dt;
@@ -448,7 +491,7 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
     }
     if (q.na) drain_oldest(x, q.na);
     if (q.nb) {
-      drain_b(W, q.hb, q.nb, lane, hw);
+      drain_b(W, q.hb, q.nb, lane, hist, (uint32_t)NB);
       q.nb = 0;
     }
     if (lane == 0) atomicAdd(evals_lds, ev);

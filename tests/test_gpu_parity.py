@@ -318,3 +318,40 @@ def test_errors_are_reported():
         plan.destroy()
     r = ref_K(x[:500], y[:500], t[:500], *cfg_args(c))
     compare(g, r, c["s_max"], c["t_max"], c["n_s"], c["n_t"], where="after errors")
+
+
+def test_single_pair_weights_near_sides_and_corners():
+    """One pair at a time: W at the largest grid point is w_ij + w_ji exactly, so
+    every boundary weight (one side cut, two sides, corner in/out, tangency) is
+    checked on its own against the oracle to 1e-6."""
+    rng = np.random.default_rng(2718)
+    win = (0, 0, 20_000, 16_000, 0, 5_000_000)
+    args = (win, 8000, 1_000_000, 8, 4)
+    plan = make_plan(*args, n_max=2)
+    worst = 0.0
+    try:
+        say("single pairs")
+        for trial in range(1500):
+            x1 = int(rng.choice([rng.integers(0, 3000), rng.integers(17_000, 20_001),
+                                 rng.integers(0, 20_001)]))
+            y1 = int(rng.choice([rng.integers(0, 3000), rng.integers(13_000, 16_001),
+                                 rng.integers(0, 16_001)]))
+            ang = rng.uniform(0, 2 * np.pi)
+            rad = rng.uniform(0, 8000)
+            x2 = int(np.clip(round(x1 + rad * np.cos(ang)), 0, 20_000))
+            y2 = int(np.clip(round(y1 + rad * np.sin(ang)), 0, 16_000))
+            t1 = int(rng.integers(0, 5_000_001))
+            t2 = int(np.clip(t1 + rng.integers(-1_000_000, 1_000_001), 0, 5_000_000))
+            if (x1, y1, t1) == (x2, y2, t2) and trial % 2:
+                continue
+            xs, ys, ts = (np.array(v, np.int32) for v in ((x1, x2), (y1, y2), (t1, t2)))
+            g = ripk.ripk_compute_K(plan, xs, ys, ts)
+            r = ref_K(xs, ys, ts, *args)
+            assert np.array_equal(g["C"], r["C"]), (x1, y1, t1, x2, y2, t2)
+            if r["W"][-1, -1] > 0:
+                rel = abs(g["W"][-1, -1] - r["W"][-1, -1]) / r["W"][-1, -1]
+                worst = max(worst, rel)
+                assert rel <= 1e-6, (x1, y1, t1, x2, y2, t2, g["W"][-1, -1], r["W"][-1, -1])
+    finally:
+        plan.destroy()
+    say("single pairs worst rel weight err %.3g" % worst)
