@@ -20,10 +20,12 @@
 //     stencil, j > i inside the home cell) and adds both weights, since
 //     omega_ij / v_ij depend on the centre while the bin depends on d and u only;
 //   * divergence is removed in two levels: in-range pairs are compacted into a
-//     per-wave LDS queue and binned 64 at a time (integer bin search, temporal
-//     weight, interior fast path for omega); the pairs whose circle crosses the
-//     study boundary are compacted again into a second queue where the
-//     trigonometric weight runs with full lanes.
+//     per-wave LDS queue (4-byte tags naming the centre and the tile entry) and
+//     binned 64 at a time (integer bin search, temporal weight, interior fast
+//     path for omega); the pairs whose circle crosses the study boundary are
+//     compacted again into a second queue where the trigonometric weight runs
+//     with full lanes.  Each queue has one drain site in the scan loop, so the
+//     drains are inlined once rather than at every push.
 //
 // Candidate test (one neighbour against 64 centres), by distance mode:
 //   PACKED: low 16 bits of x and y packed in one word; one packed 16-bit
@@ -42,8 +44,9 @@ namespace ripk {
 
 namespace {
 
-constexpr int kJT = 64;    // points per tile slot (two slots per wave)
-constexpr int kQ = 128;    // ring size of each per-wave queue (>= 2*64)
+constexpr int kJT = 64;     // points per tile slot (two slots per wave)
+constexpr int kQA = 512;    // ring of queue A tags: < 64 + 4*64 pending between drains
+constexpr int kQB = 128;    // ring of queue B records: < 64 + 64 pending between drains
 constexpr int kWaves = kPairThreads / 64;
 constexpr unsigned long long kFlushEvals = 1ull << 34;  // bound on candidates between flushes
 constexpr uint32_t kFarTime = 0xC0000000u;  // tile padding: fails every time test
@@ -55,8 +58,8 @@ constexpr uint32_t kClampE = 32767u;         // side distances stored in 15 bits
 struct WaveLds {
   int4 tile[2 * kJT];  // two tile slots of neighbour points
   int4 cen[64];        // the wave's centres
-  uint4 qa[kQ];        // in-range pairs: {d2 lo, t_i + t_max - t_j, lane<<4 | tile index<<14, d2 hi}
-  uint4 qb[kQ];        // boundary weights: {bin | halfv << 12 | d2 hi << 13, d2 lo, ex, ey}
+  uint32_t qa[kQA];    // in-range pairs: byte offsets cen | tile << 10 (lane<<4 | index<<14)
+  uint4 qb[kQB];       // boundary weights, see drain_b
 };
 
 struct QState {
@@ -117,78 +120,126 @@ __device__ __forceinline__ float beta_angle(float e, float h) {
 //   omega = (beta_x + beta_y)/pi + max(0, pi/2 - beta_x - beta_y)/(2 pi):
 // 1 with no cut, 1/2 + beta/pi with one, (beta_x + beta_y)/pi with two and the
 // corner outside the circle, 1/4 + (beta_x + beta_y)/(2 pi) with it inside.
-__device__ __forceinline__ float omega_f32(uint32_t ex, uint32_t ey, uint64_t d2) {
-  const uint64_t ex2 = (uint64_t)ex * ex, ey2 = (uint64_t)ey * ey;
-  const float hx = sqrtf((float)(ex2 < d2 ? d2 - ex2 : 0ull));
-  const float hy = sqrtf((float)(ey2 < d2 ? d2 - ey2 : 0ull));
-  const float bx = beta_angle((float)ex, hx), by = beta_angle((float)ey, hy);
+__device__ __forceinline__ float omega_from_beta(float bx, float by) {
   const float sum = bx + by;
   const float inv_pi = 0.318309886183790671538f;
   return sum * inv_pi + fmaxf(1.5707963267948966f - sum, 0.0f) * (0.5f * inv_pi);
 }
 
-// Queue B: boundary weights with full lanes.
-__device__ __noinline__ void drain_b(WaveLds &W, uint32_t head, uint32_t c, int lane,
-                                        unsigned long long *hist, uint32_t nb) {
+__device__ __forceinline__ float omega_f32(uint32_t ex, uint32_t ey, uint64_t d2) {
+  const uint64_t ex2 = (uint64_t)ex * ex, ey2 = (uint64_t)ey * ey;
+  const float hx = __builtin_amdgcn_sqrtf((float)(ex2 < d2 ? d2 - ex2 : 0ull));
+  const float hy = __builtin_amdgcn_sqrtf((float)(ey2 < d2 ? d2 - ey2 : 0ull));
+  return omega_from_beta(beta_angle((float)ex, hx), beta_angle((float)ey, hy));
+}
+
+// the same with d2 < 2^31 and ex, ey < 2^15 (all squares exact in 32 bits)
+__device__ __forceinline__ float omega_f32(uint32_t ex, uint32_t ey, uint32_t d2) {
+  const uint32_t ex2 = __umul24(ex, ex), ey2 = __umul24(ey, ey);
+  const float hx = __builtin_amdgcn_sqrtf((float)(ex2 < d2 ? d2 - ex2 : 0u));
+  const float hy = __builtin_amdgcn_sqrtf((float)(ey2 < d2 ? d2 - ey2 : 0u));
+  return omega_from_beta(beta_angle((float)ex, hx), beta_angle((float)ey, hy));
+}
+
+// Queue B: boundary weights with full lanes.  Records:
+//   PACKED: one per pair, {bin | half_i<<12 | half_j<<13 | slow_i<<14 | slow_j<<15,
+//           d2, ex_i|ey_i<<16, ex_j|ey_j<<16}: both sides' weights in one pass;
+//   U32 / WIDE: one per side, {bin | half<<12 | d2 hi<<13, d2 lo, ex, ey}.
+__device__ __forceinline__ uint32_t qweight(float om, uint32_t half) {
+  // w = 1/omega >= 1 has at most 23 fraction bits: w * 2^23 is an exact integer;
+  // the reciprocal is within an ulp, well inside the error budget
+  const float w = fmaxf(__builtin_amdgcn_rcpf(om), 1.0f);
+  return (uint32_t)(w * (float)(1u << kFracBits)) << half;
+}
+
+template <int MODE>
+__device__ __forceinline__ void drain_b(WaveLds &W, QState &q, uint32_t c, int lane,
+                                        unsigned long long *hw) {
   wave_sync();
-  const uint4 r = W.qb[(head + lane) & (kQ - 1)];
+  const uint4 r = W.qb[(q.hb + lane) & (kQB - 1)];
   wave_sync();
-  if ((uint32_t)lane < c) {
-    const uint32_t bin = r.x & 0xFFFu;
-    const uint32_t half = (r.x >> 12) & 1u;
+  const uint32_t bin = r.x & 0xFFFu;
+  uint32_t qv;
+  if (MODE == kModePacked) {
+    // d2 < 2^31 and side distances < 2^15: 32-bit arithmetic throughout
+    const float oi = omega_f32(r.z & 0xFFFFu, r.z >> 16, r.y);
+    const float oj = omega_f32(r.w & 0xFFFFu, r.w >> 16, r.y);
+    qv = (((r.x >> 14) & 1u) ? qweight(oi, (r.x >> 12) & 1u) : 0u) +
+         (((r.x >> 15) & 1u) ? qweight(oj, (r.x >> 13) & 1u) : 0u);
+  } else {
     const uint64_t d2 = (uint64_t)r.y | ((uint64_t)(r.x >> 13) << 32);
-    const float om = omega_f32(r.z, r.w, d2);
-    const float w = fmaxf(__frcp_rn(om), 1.0f);
-    // w >= 1 has at most 23 fraction bits: w * 2^23 is an exact integer
-    const uint32_t qv = (uint32_t)(w * (float)(1u << kFracBits)) << half;
-    atomicAdd(&hist[nb + bin], (unsigned long long)qv);
+    qv = qweight(omega_f32(r.z, r.w, d2), (r.x >> 12) & 1u);
   }
+  if ((uint32_t)lane < c) atomicAdd(&hw[bin], (unsigned long long)qv);
+  q.hb = (q.hb + c) & (kQB - 1);
+  q.nb -= c;
 }
 
-__device__ __forceinline__ void push_b(WaveLds &W, QState &q, bool need, uint32_t w0,
-                                       uint32_t d2lo, uint32_t ex, uint32_t ey, int lane,
-                                       unsigned long long *hist, unsigned long long vmask,
-                                       uint32_t nbins) {
-  const unsigned long long m = __builtin_amdgcn_ballot_w64(need) & vmask;
-  if (m) {
-    const uint32_t pos = lane_rank(m, q.hb + q.nb) & (kQ - 1);
-    if ((m >> lane) & 1ull) W.qb[pos] = make_uint4(w0, d2lo, ex, ey);
-    q.nb += (uint32_t)__popcll(m);
-    if (q.nb >= 64) {
-      drain_b(W, q.hb, 64, lane, hist, nbins);
-      q.hb = (q.hb + 64) & (kQ - 1);
-      q.nb -= 64;
-    }
+struct Side {
+  uint32_t T, ex, ey;
+  bool slow;  // the circle of radius d crosses the study boundary
+};
+
+template <int MODE>
+__device__ __forceinline__ Side side_of(const int4 p, uint32_t d2lo, uint64_t d2, const Geom &g) {
+  Side s;
+  if (MODE == kModePacked) {
+    s.T = (uint32_t)p.y;
+    s.ex = (uint32_t)p.z & 0xFFFFu;
+    s.ey = (uint32_t)p.z >> 16;
+    s.slow = d2lo > (uint32_t)p.w;
+  } else {
+    s.T = (uint32_t)p.z;
+    s.ex = (uint32_t)min(p.x, g.x1 - g.x0 - p.x);
+    s.ey = (uint32_t)min(p.y, g.y1 - g.y0 - p.y);
+    s.slow = d2 > (uint64_t)(uint32_t)p.w * (uint32_t)p.w;
   }
+  s.slow = s.slow && (g.edge & 1u);
+  return s;
 }
 
-// Queue A: bin, temporal weight and the interior fast path of omega, without
-// branches on per-lane data (lanes past c compute garbage that is never stored).
+// Queue A: the c oldest in-range pairs.  Distances are recomputed from the
+// centre and neighbour images; the bin, the temporal weight and the interior
+// fast path of omega are evaluated without branches on per-lane data (lanes
+// past c compute on entry 0 and store nothing); boundary sides go to queue B.
 template <bool SYM, int MODE>
 __device__ __forceinline__ void drain_a(WaveLds &W, QState &q, uint32_t c, int lane,
                                         const Geom &g, unsigned long long *hist,
                                         const uint32_t *S2lo, const uint32_t *S2hi,
                                         const uint32_t *T) {
   wave_sync();
-  const uint4 r = W.qa[(q.ha + lane) & (kQ - 1)];
+  const uint32_t tag0 = W.qa[(q.ha + lane) & (kQA - 1)];
   wave_sync();
-  const unsigned long long vmask = c >= 64 ? ~0ull : ((1ull << c) - 1ull);
   const bool v = (uint32_t)lane < c;
-  // lanes past c hold stale ring slots: point them at entry 0
-  const uint32_t tag = v ? r.z : 0u;
+  const unsigned long long vmask = c >= 64 ? ~0ull : ((1ull << c) - 1ull);
+  const uint32_t tag = v ? tag0 : 0u;
   const int4 pi = *(const int4 *)((const char *)W.cen + (tag & 0x3F0u));
   const int4 pj = *(const int4 *)((const char *)W.tile + (tag >> 10));
-  const uint32_t d2lo = r.x;
-  const uint64_t d2 = MODE == kModeWide ? ((uint64_t)r.x | ((uint64_t)r.w << 32)) : (uint64_t)r.x;
-  const int32_t sdt = (int32_t)(r.y - g.tmax);
-  const uint32_t u = (uint32_t)max(sdt, -sdt);
+  uint32_t d2lo, d2hi = 0, u;
+  if (MODE == kModePacked) {
+    typedef short s2 __attribute__((ext_vector_type(2)));
+    const s2 dd = __builtin_bit_cast(s2, pi.x) - __builtin_bit_cast(s2, pj.x);
+    d2lo = (uint32_t)__builtin_amdgcn_sdot2(dd, dd, 0, false);
+    u = (uint32_t)max(pi.y - pj.y, pj.y - pi.y);
+  } else if (MODE == kModeU32) {
+    const int32_t dx = pi.x - pj.x, dy = pi.y - pj.y;
+    d2lo = (uint32_t)__mul24(dx, dx) + (uint32_t)__mul24(dy, dy);
+    u = (uint32_t)max(pi.z - pj.z, pj.z - pi.z);
+  } else {
+    const int64_t dx = (int64_t)(pi.x - pj.x), dy = (int64_t)(pi.y - pj.y);
+    const uint64_t dd = (uint64_t)(dx * dx + dy * dy);
+    d2lo = (uint32_t)dd;
+    d2hi = (uint32_t)(dd >> 32);
+    u = (uint32_t)max(pi.z - pj.z, pj.z - pi.z);
+  }
+  const uint64_t d2 = ((uint64_t)d2hi << 32) | d2lo;
   // k* = ceil(sqrt(d2) n_s / s_max) exactly (S2[k] = floor(s_k^2), d2 an integer);
   // the FP32 quotient is within 1e-5 of it, so one comparison on each side of
   // the estimate restores the exact step.  Same for l* with the T table.
   const float d2f = MODE == kModeWide ? (float)d2 : (float)d2lo;
-  int k = __builtin_amdgcn_fmed3f(ceilf(__builtin_amdgcn_sqrtf(d2f) * g.inv_ds), 1.0f,
-                                  (float)g.n_s);
-  int l = __builtin_amdgcn_fmed3f(ceilf((float)u * g.inv_dt), 1.0f, (float)g.n_t);
+  int k = (int)__builtin_amdgcn_fmed3f(ceilf(__builtin_amdgcn_sqrtf(d2f) * g.inv_ds), 1.0f,
+                                       (float)g.n_s);
+  int l = (int)__builtin_amdgcn_fmed3f(ceilf((float)u * g.inv_dt), 1.0f, (float)g.n_t);
   const int km2 = max(k - 2, 0), lm2 = max(l - 2, 0);
   // all four table reads are issued together (no short-circuit loads)
   const uint32_t sa_lo = S2lo[k - 1], sb_lo = S2lo[km2];
@@ -209,52 +260,57 @@ __device__ __forceinline__ void drain_a(WaveLds &W, QState &q, uint32_t c, int l
   l += (int)up_l - (int)dn_l;
   const uint32_t bin = (uint32_t)((min(k, g.n_s) - 1) * g.n_t + (min(l, g.n_t) - 1));
   const uint32_t D = (uint32_t)(g.t1 - g.t0);
-  const bool sp = (g.edge & 1u) != 0, tp = (g.edge & 2u) != 0;
+  const bool tp = (g.edge & 2u) != 0;
   // v = 1/2 when an end of [t-u, t+u] leaves the period: the weight doubles
-  uint32_t Ti, Tj, exi, eyi, exj = 0, eyj = 0;
-  bool slow_i, slow_j = false;
-  if (MODE == kModePacked) {
-    Ti = (uint32_t)pi.y;
-    exi = (uint32_t)pi.z & 0xFFFFu;
-    eyi = (uint32_t)pi.z >> 16;
-    slow_i = d2lo > (uint32_t)pi.w;
-  } else {
-    Ti = (uint32_t)pi.z;
-    exi = (uint32_t)min(pi.x, g.x1 - g.x0 - pi.x);
-    eyi = (uint32_t)min(pi.y, g.y1 - g.y0 - pi.y);
-    slow_i = d2 > (uint64_t)(uint32_t)pi.w * (uint32_t)pi.w;
-  }
-  slow_i = sp && slow_i;
-  const uint32_t hfi = (tp && u > min(Ti, D - Ti)) ? 1u : 0u;
-  uint32_t qsum = slow_i ? 0u : (1u << (kFracBits + hfi));
+  const Side si = side_of<MODE>(pi, d2lo, d2, g);
+  const uint32_t hfi = (tp && u > min(si.T, D - si.T)) ? 1u : 0u;
+  uint32_t qsum = si.slow ? 0u : (1u << (kFracBits + hfi));
+  Side sj = si;
+  sj.slow = false;
   uint32_t hfj = 0;
   if (SYM) {
-    if (MODE == kModePacked) {
-      Tj = (uint32_t)pj.y;
-      exj = (uint32_t)pj.z & 0xFFFFu;
-      eyj = (uint32_t)pj.z >> 16;
-      slow_j = d2lo > (uint32_t)pj.w;
-    } else {
-      Tj = (uint32_t)pj.z;
-      exj = (uint32_t)min(pj.x, g.x1 - g.x0 - pj.x);
-      eyj = (uint32_t)min(pj.y, g.y1 - g.y0 - pj.y);
-      slow_j = d2 > (uint64_t)(uint32_t)pj.w * (uint32_t)pj.w;
-    }
-    slow_j = sp && slow_j;
-    hfj = (tp && u > min(Tj, D - Tj)) ? 1u : 0u;
-    qsum += slow_j ? 0u : (1u << (kFracBits + hfj));
+    sj = side_of<MODE>(pj, d2lo, d2, g);
+    hfj = (tp && u > min(sj.T, D - sj.T)) ? 1u : 0u;
+    qsum += sj.slow ? 0u : (1u << (kFracBits + hfj));
   }
+  const uint32_t nbins = (uint32_t)(g.n_s * g.n_t);
   if (v) {
     atomicAdd(&hist[bin], SYM ? 2ull : 1ull);
-    atomicAdd(&hist[g.n_s * g.n_t + bin], (unsigned long long)qsum);
+    atomicAdd(&hist[nbins + bin], (unsigned long long)qsum);
   }
-  q.ha = (q.ha + c) & (kQ - 1);
+  q.ha = (q.ha + c) & (kQA - 1);
   q.na -= c;
   q.drained += c;
-  const uint32_t w0 = bin | (r.w << 13);
-  const uint32_t nbins = (uint32_t)(g.n_s * g.n_t);
-  push_b(W, q, slow_i, w0 | (hfi << 12), d2lo, exi, eyi, lane, hist, vmask, nbins);
-  if (SYM) push_b(W, q, slow_j, w0 | (hfj << 12), d2lo, exj, eyj, lane, hist, vmask, nbins);
+  if (MODE == kModePacked) {
+    // one record per pair with a boundary side
+    const bool need = si.slow || sj.slow;
+    const unsigned long long m = __builtin_amdgcn_ballot_w64(need) & vmask;
+    if (m) {
+      const uint32_t pos = lane_rank(m, q.hb + q.nb) & (kQB - 1);
+      if (need && v)
+        W.qb[pos] = make_uint4(bin | (hfi << 12) | (hfj << 13) | ((uint32_t)si.slow << 14) |
+                                   ((uint32_t)(SYM && sj.slow) << 15),
+                               d2lo, (uint32_t)pi.z, (uint32_t)pj.z);
+      q.nb += (uint32_t)__popcll(m);
+      if (q.nb >= 64) drain_b<MODE>(W, q, 64, lane, hist + nbins);
+    }
+  } else {
+    // one record per boundary side, one side per pass through a single drain site
+    const uint32_t w0 = bin | (d2hi << 13);
+#pragma unroll 1
+    for (int side = 0; side < (SYM ? 2 : 1); ++side) {
+      const bool need = side ? sj.slow : si.slow;
+      const unsigned long long m = __builtin_amdgcn_ballot_w64(need) & vmask;
+      if (m) {
+        const uint32_t pos = lane_rank(m, q.hb + q.nb) & (kQB - 1);
+        if ((m >> lane) & 1ull)
+          W.qb[pos] = make_uint4(w0 | ((side ? hfj : hfi) << 12), d2lo, side ? sj.ex : si.ex,
+                                 side ? sj.ey : si.ey);
+        q.nb += (uint32_t)__popcll(m);
+        if (q.nb >= 64) drain_b<MODE>(W, q, 64, lane, hist + nbins);
+      }
+    }
+  }
 }
 
 // LDS image of a sorted point (see WaveLds).
@@ -280,29 +336,21 @@ __device__ __forceinline__ int4 far_image() {
 // ct = time test (kept apart so that each ballot folds to its compare mask).
 template <int MODE>
 __device__ __forceinline__ void cand(const int4 me, uint32_t tplus, const int4 pj, const Geom &g,
-                                     uint32_t &d2lo, uint32_t &d2hi, uint32_t &dtp, bool &cs,
-                                     bool &ct) {
+                                     bool &cs, bool &ct) {
+  uint32_t dtp;
   if (MODE == kModePacked) {
     typedef short s2 __attribute__((ext_vector_type(2)));
-    const s2 a = __builtin_bit_cast(s2, me.x), b = __builtin_bit_cast(s2, pj.x);
-    const s2 d = a - b;
-    d2lo = (uint32_t)__builtin_amdgcn_sdot2(d, d, 0, false);
-    d2hi = 0;
+    const s2 d = __builtin_bit_cast(s2, me.x) - __builtin_bit_cast(s2, pj.x);
+    cs = (uint32_t)__builtin_amdgcn_sdot2(d, d, 0, false) <= (uint32_t)g.s2max;
     dtp = tplus - (uint32_t)pj.y;
-    cs = d2lo <= (uint32_t)g.s2max;
   } else if (MODE == kModeU32) {
     const int32_t dx = me.x - pj.x, dy = me.y - pj.y;
-    d2lo = (uint32_t)__mul24(dx, dx) + (uint32_t)__mul24(dy, dy);
-    d2hi = 0;
+    cs = (uint32_t)__mul24(dx, dx) + (uint32_t)__mul24(dy, dy) <= (uint32_t)g.s2max;
     dtp = tplus - (uint32_t)pj.z;
-    cs = d2lo <= (uint32_t)g.s2max;
   } else {
     const int64_t dx = (int64_t)(me.x - pj.x), dy = (int64_t)(me.y - pj.y);
-    const uint64_t d2 = (uint64_t)(dx * dx + dy * dy);
-    d2lo = (uint32_t)d2;
-    d2hi = (uint32_t)(d2 >> 32);
+    cs = (uint64_t)(dx * dx + dy * dy) <= g.s2max;
     dtp = tplus - (uint32_t)pj.z;
-    cs = d2 <= g.s2max;
   }
   ct = dtp <= 2u * g.tmax;
 }
@@ -317,18 +365,19 @@ struct Ctx {
   int lane;
 };
 
-// Drain the c oldest entries of queue A.
 template <bool SYM, int MODE>
 __device__ __forceinline__ void drain_oldest(Ctx<SYM, MODE> &x, uint32_t c) {
   drain_a<SYM, MODE>(x.W, x.q, c, x.lane, x.g, x.hist, x.S2lo, x.S2hi, x.T);
 }
 
+// One run of consecutive sorted points [j0, j1) against the wave's centres.
+// HOME: the run holds the centres' own cell (j > i in symmetric mode, j != i
+// otherwise).
 template <bool SYM, int MODE, bool HOME>
 __device__ __forceinline__ void scan_run(Ctx<SYM, MODE> &x, uint32_t j0, uint32_t j1,
                                          const int4 me, uint32_t tplus,
                                          unsigned long long valid, uint32_t mi,
                                          const int4 *__restrict__ P) {
-  const bool vlane = (valid >> x.lane) & 1ull;
   QState &q = x.q;
   WaveLds &W = x.W;
   const int lane = x.lane;
@@ -361,21 +410,19 @@ __device__ __forceinline__ void scan_run(Ctx<SYM, MODE> &x, uint32_t j0, uint32_
       for (int u = 0; u < 4; ++u) pj[u] = W.tile[sbase + jj + u];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        uint32_t d2lo, d2hi, dtp;
         bool cs, ct;
-        cand<MODE>(me, tplus, pj[u], x.g, d2lo, d2hi, dtp, cs, ct);
+        cand<MODE>(me, tplus, pj[u], x.g, cs, ct);
         const uint32_t j = tb + jj + u;
-        const bool ch = HOME ? (SYM ? (j > mi) : (j != mi)) : true;
-        unsigned long long mask = __builtin_amdgcn_ballot_w64(cs) & __builtin_amdgcn_ballot_w64(ct) & valid;
-        if (HOME) mask &= __builtin_amdgcn_ballot_w64(ch);
+        unsigned long long mask =
+            __builtin_amdgcn_ballot_w64(cs) & __builtin_amdgcn_ballot_w64(ct) & valid;
+        if (HOME) mask &= __builtin_amdgcn_ballot_w64(SYM ? (j > mi) : (j != mi));
         if (mask) {
-          const uint32_t pos = lane_rank(mask, q.ha + q.na) & (kQ - 1);
-          if (cs && ct && ch && vlane)
-            W.qa[pos] = make_uint4(d2lo, dtp, lane_tag + ((jj + u) << 14), d2hi);
+          const uint32_t pos = lane_rank(mask, q.ha + q.na) & (kQA - 1);
+          if ((mask >> lane) & 1ull) W.qa[pos] = lane_tag + ((jj + u) << 14);
           q.na += (uint32_t)__popcll(mask);
-          if (q.na >= 64) drain_oldest(x, 64);
         }
       }
+      while (q.na >= 64) drain_oldest(x, 64);
     }
   }
 }
@@ -490,10 +537,7 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
       }
     }
     if (q.na) drain_oldest(x, q.na);
-    if (q.nb) {
-      drain_b(W, q.hb, q.nb, lane, hist, (uint32_t)NB);
-      q.nb = 0;
-    }
+    if (q.nb) drain_b<MODE>(W, q, q.nb, lane, hist + NB);
     if (lane == 0) atomicAdd(evals_lds, ev);
     evals_total += ev;
   }
