@@ -9,8 +9,10 @@ are resident in device memory before timing starts.
 Printed: one JSON line.  ``value`` = ordered in-range pair tests per second
 (N_in over the step, in units of 1e9/s); ``sims_per_s``; ``roofline`` for the
 pair kernel (integer ALU bound: 9 lane-ops per candidate pair against
-256 CU x 64 lanes x 2.4 GHz); ``cpu_baseline`` = the FP64 oracle on the host
-cores over a bounded sample of centres of the observed set.
+256 CU x 64 lanes x 2.4 GHz), with HBM traffic per launch from the stored
+counter summary while the pair kernel is unchanged; ``cpu_baseline`` = the FP64
+oracle on the host cores over the observed set and as many of its simulations
+as fit in about 12 s.
 """
 import argparse
 import json
@@ -27,25 +29,36 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9   # CUs x lanes x clock
 
 
 def cpu_baseline(cfg, x, y, t, target_s):
-    import numpy as np
+    """The FP64 oracle on the host cores: the observed set, then CSR simulations
+    drawn by the oracle's own Philox, until about target_s seconds of work."""
     import oracle
     d = oracle.desc(cfg["window"], cfg["s_max"], cfg["t_max"], cfg["n_s"], cfg["n_t"])
     n = len(x)
     threads = oracle.max_threads()
-    # calibrate on a small sample, then size the timed sample to ~target_s
-    nc = 500
     t0 = oracle.now()
-    oracle.estimate(d, x, y, t, n_centres=nc, threads=threads)
-    dt = max(oracle.now() - t0, 1e-3)
-    nc = int(min(n, max(1000, nc * target_s / dt)))
-    t0 = oracle.now()
-    r = oracle.estimate(d, x, y, t, n_centres=nc, threads=threads)
-    dt = oracle.now() - t0
+    r = oracle.estimate(d, x, y, t, threads=threads)
     n_in = int(r["C"][-1, -1])
+    sets = 1
+    while oracle.now() - t0 < target_s and sets <= cfg["sims"]:
+        xs, ys, ts = oracle.csr_points(d, n, sets - 1, cfg["seed"])
+        r = oracle.estimate(d, xs, ys, ts, threads=threads)
+        n_in += int(r["C"][-1, -1])
+        sets += 1
+    dt = oracle.now() - t0
     return {"value": n_in / dt / 1e9, "unit": "G pair tests/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"observed set of the workload, first {nc} of {n} points as centres "
-                      f"against all {n}; {n_in} in-range ordered pairs in {dt:.2f} s"}
+            "sample": f"observed set of the workload plus {sets - 1} of its {cfg['sims']} CSR "
+                      f"simulations ({sets} sets of {n} points, every ordered pair); "
+                      f"{n_in} in-range ordered pairs in {dt:.2f} s"}
+
+
+def copy_calibration(torch):
+    """A plain device copy of known size, for scaling the HBM byte counters."""
+    from paper_1912_04753_amd.profiling import COPY_BYTES
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
 
 
 def main():
@@ -55,6 +68,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a plain device copy of known size first (counter runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -66,7 +81,9 @@ def main():
     from paper_1912_04753_amd import ripk, workloads
 
     torch.cuda.set_device(0)
-    cfg = workloads.config(3)
+    if args.copy_calibration:
+        copy_calibration(torch)
+    cfg = workloads.workload("uniform-100k-99csr")
     x, y, t = workloads.make_points(cfg)
     n, m = len(x), cfg["sims"]
     dx, dy, dt = (torch.from_numpy(a).cuda() for a in (x, y, t))
@@ -107,6 +124,8 @@ def main():
     avg_us = sum(pair_us) / len(pair_us)
     achieved = OPS_PER_EVAL * (evals / 2) / (avg_us * 1e-6) / 1e12
     peak = PEAK_LANE_OPS / 1e12
+    from paper_1912_04753_amd.profiling import load_traffic
+    tr = load_traffic(os.path.join(ROOT, "profiles", "k_pair_uniform100k_99csr_traffic.json"))
     out = {
         "metric": METRIC,
         "value": round(value, 4),
@@ -120,7 +139,7 @@ def main():
         "vs_baseline": None,
         "dtype": "i32+f32",
         "data": "synthetic",
-        "config": {"workload": "config3: 100k uniform points, 20km x 20km x 180d, "
+        "config": {"workload": "100k uniform points, 20km x 20km x 180d, "
                                "25x15 grid to 2km/30d, observed K + 99 CSR simulations",
                    "n": n, "sims": m, "n_s": cfg["n_s"], "n_t": cfg["n_t"]},
         "sims_per_s": round(m / t_sim, 3),
@@ -130,7 +149,7 @@ def main():
                            "simulations": round(sum(r[1]["us_pair"] for r in recs) / len(recs), 2)},
         "roofline": {"bound": "alu", "achieved": round(achieved, 4), "peak": round(peak, 4),
                      "unit": "T int lane-ops/s", "frac": round(achieved / peak, 4),
-                     "traffic": None,
+                     "traffic": (round(tr["bytes_per_launch"]) if tr else None),
                      "note": f"{OPS_PER_EVAL} lane-ops per candidate pair x candidates per "
                              f"launch / mean pair-kernel launch time ({avg_us:.1f} us)"},
     }

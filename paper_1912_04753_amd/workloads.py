@@ -66,18 +66,18 @@ def thomas_points(rng, n, window, parents, sigma_xy, sigma_t):
 
 # The five workloads.  ``window`` = (x0, y0, x1, y1, t0, t1); isotropic spatial
 # and temporal edge correction (edge = 3) throughout.
-CONFIGS = {
-    1: dict(name="uniform-2k", seed=1, window=(0, 0, 10_000, 10_000, 0, 365 * DAY),
+WORKLOADS = {
+    "uniform-2k": dict(name="uniform-2k", seed=1, window=(0, 0, 10_000, 10_000, 0, 365 * DAY),
             s_max=1_000, n_s=10, t_max=30 * DAY, n_t=10, sims=0,
             parts=[("uniform", 2_000, {})]),
-    2: dict(name="thomas-200k", seed=2, window=(0, 0, 50_000, 50_000, 0, 365 * DAY),
+    "thomas-200k": dict(name="thomas-200k", seed=2, window=(0, 0, 50_000, 50_000, 0, 365 * DAY),
             s_max=5_000, n_s=20, t_max=60 * DAY, n_t=20, sims=0,
             parts=[("thomas", 200_000, dict(parents=500, sigma_xy=200.0,
                                             sigma_t=5.0 * DAY))]),
-    3: dict(name="uniform-100k-99csr", seed=3, window=(0, 0, 20_000, 20_000, 0, 180 * DAY),
+    "uniform-100k-99csr": dict(name="uniform-100k-99csr", seed=3, window=(0, 0, 20_000, 20_000, 0, 180 * DAY),
             s_max=2_000, n_s=25, t_max=30 * DAY, n_t=15, sims=99,
             parts=[("uniform", 100_000, {})]),
-    4: dict(name="mixed-2M-19csr", seed=4, window=(0, 0, 100_000, 100_000, 0, 730 * DAY),
+    "mixed-2M-19csr": dict(name="mixed-2M-19csr", seed=4, window=(0, 0, 100_000, 100_000, 0, 730 * DAY),
             s_max=10_000, n_s=50, t_max=90 * DAY, n_t=30, sims=19,
             parts=[("uniform", 1_000_000, {}),
                    ("thomas", 1_000_000, dict(parents=2_000, sigma_xy=500.0,
@@ -100,8 +100,9 @@ def make_points(cfg):
     return np.concatenate(xs), np.concatenate(ys), np.concatenate(ts)
 
 
-def config(i):
-    return dict(CONFIGS[i])
+def workload(name):
+    """A copy of one of the named workload dicts above."""
+    return dict(WORKLOADS[name])
 
 
 def serving_requests(num=5000, rate=None, seed=5):

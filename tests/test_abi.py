@@ -44,7 +44,7 @@ def desc(**kw):
     return ripk.make_desc(w, **base)
 
 
-def test_plan_geometry_config3():
+def test_plan_geometry_uniform100k():
     info = ripk.ripk_plan_check(desc())
     assert (info["nx"], info["ny"], info["nt"]) == (10, 10, 6)
     assert info["reach_s"] == 1 and info["reach_t"] == 1

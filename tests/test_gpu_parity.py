@@ -47,59 +47,59 @@ def cfg_args(c):
 
 
 # ------------------------------------------------------------ workloads -----
-def test_config1_full():
-    c = workloads.config(1)
+def test_uniform2k_full():
+    c = workloads.workload("uniform-2k")
     x, y, t = workloads.make_points(c)
-    say("config1 n=%d" % len(x))
+    say("uniform2k n=%d" % len(x))
     g = gpu_K(x, y, t, *cfg_args(c))
     r = ref_K(x, y, t, *cfg_args(c))
-    err = compare(g, r, c["s_max"], c["t_max"], c["n_s"], c["n_t"], where="config1")
+    err = compare(g, r, c["s_max"], c["t_max"], c["n_s"], c["n_t"], where="uniform2k")
     assert g["stats"]["n_in"] == int(r["C"][-1, -1])
-    say("config1 worst rel K err %.3g" % err)
+    say("uniform2k worst rel K err %.3g" % err)
 
 
-def test_config2_full_clustered():
-    c = workloads.config(2)
+def test_thomas200k_full_clustered():
+    c = workloads.workload("thomas-200k")
     x, y, t = workloads.make_points(c)
-    say("config2 n=%d" % len(x))
+    say("thomas200k n=%d" % len(x))
     g = gpu_K(x, y, t, *cfg_args(c))
     r = ref_K(x, y, t, *cfg_args(c))
-    err = compare(g, r, c["s_max"], c["t_max"], c["n_s"], c["n_t"], where="config2")
-    say("config2 worst rel K err %.3g" % err)
+    err = compare(g, r, c["s_max"], c["t_max"], c["n_s"], c["n_t"], where="thomas200k")
+    say("thomas200k worst rel K err %.3g" % err)
 
 
 _c3 = {}
 
 
-def _config3_observed():
+def _uniform100k_observed():
     if not _c3:
-        c = workloads.config(3)
+        c = workloads.workload("uniform-100k-99csr")
         x, y, t = workloads.make_points(c)
         _c3.update(c=c, x=x, y=y, t=t, ref=ref_K(x, y, t, *cfg_args(c)))
     return _c3
 
 
-def test_config3_observed_full_and_modes_agree():
-    d = _config3_observed()
+def test_uniform100k_observed_full_and_modes_agree():
+    d = _uniform100k_observed()
     c, x, y, t = d["c"], d["x"], d["y"], d["t"]
-    say("config3 observed symmetric")
+    say("uniform100k observed symmetric")
     g = gpu_K(x, y, t, *cfg_args(c))
-    compare(g, d["ref"], c["s_max"], c["t_max"], c["n_s"], c["n_t"], where="config3")
+    compare(g, d["ref"], c["s_max"], c["t_max"], c["n_s"], c["n_t"], where="uniform100k")
     assert g["stats"]["symmetric"] == 1
-    say("config3 observed ordered")
+    say("uniform100k observed ordered")
     go = gpu_K(x, y, t, *cfg_args(c), flags=ripk.RIPK_PLAN_ORDERED)
     assert go["stats"]["symmetric"] == 0
     # both modes add the same exact integers: identical bits
     assert np.array_equal(go["C"], g["C"]) and np.array_equal(go["W"], g["W"])
-    say("config3 observed finer cells")
+    say("uniform100k observed finer cells")
     gf = gpu_K(x, y, t, *cfg_args(c), cell_div=2, tcell_div=3)
     assert np.array_equal(gf["C"], g["C"]) and np.array_equal(gf["W"], g["W"])
 
 
-def test_config3_simulations_sampled():
-    c = workloads.config(3)
+def test_uniform100k_simulations_sampled():
+    c = workloads.workload("uniform-100k-99csr")
     n, m = 100_000, c["sims"]
-    say("config3 sims m=%d" % m)
+    say("uniform100k sims m=%d" % m)
     plan = make_plan(*cfg_args(c), n_max=n, m_max=m)
     try:
         env = ripk.ripk_simulate_envelope(plan, n, m, seed=c["seed"], per_sim=True)
@@ -111,7 +111,7 @@ def test_config3_simulations_sampled():
         x, y, t = oracle.csr_points(d, n, s, c["seed"])
         r = oracle.estimate(d, x, y, t)
         g = {"C": env["C_sims"][s], "W": env["W_sims"][s], "K": env["K_sims"][s]}
-        compare(g, r, c["s_max"], c["t_max"], c["n_s"], c["n_t"], where=f"config3 sim {s}")
+        compare(g, r, c["s_max"], c["t_max"], c["n_s"], c["n_t"], where=f"uniform100k sim {s}")
     Ks = env["K_sims"]
     assert np.array_equal(env["K_lo"], Ks.min(axis=0))
     assert np.array_equal(env["K_hi"], Ks.max(axis=0))
@@ -133,8 +133,8 @@ def test_config3_simulations_sampled():
     assert np.all(np.abs(z[ok]) < 4.5), np.abs(z[ok]).max()
 
 
-def test_config4_sampled_centres():
-    c = workloads.config(4)
+def test_mixed2m_sampled_centres():
+    c = workloads.workload("mixed-2M-19csr")
     x, y, t = workloads.make_points(c)
     n = len(x)
     rng = np.random.default_rng(44)
@@ -142,25 +142,25 @@ def test_config4_sampled_centres():
     rest = np.setdiff1d(np.arange(n), pick)
     order = np.concatenate([pick, rest])
     xs, ys, ts = x[order], y[order], t[order]
-    say("config4 n=%d sampled centres=%d" % (n, len(pick)))
+    say("mixed2m n=%d sampled centres=%d" % (n, len(pick)))
     g = gpu_K(xs, ys, ts, *cfg_args(c), n_centres=len(pick))
     r = ref_K(xs, ys, ts, *cfg_args(c), n_centres=len(pick))
-    compare(g, r, c["s_max"], c["t_max"], c["n_s"], c["n_t"], where="config4 sample")
+    compare(g, r, c["s_max"], c["t_max"], c["n_s"], c["n_t"], where="mixed2m sample")
 
 
-def test_config4_full_properties_and_sim_path():
-    c = workloads.config(4)
+def test_mixed2m_full_properties_and_sim_path():
+    c = workloads.workload("mixed-2M-19csr")
     x, y, t = workloads.make_points(c)
     n, m = len(x), c["sims"]
-    say("config4 full n=%d" % n)
+    say("mixed2m full n=%d" % n)
     plan = make_plan(*cfg_args(c), n_max=n, m_max=m)
     try:
         full = ripk.ripk_compute_K(plan, x, y, t)
-        say("config4 sims m=%d" % m)
+        say("mixed2m sims m=%d" % m)
         env = ripk.ripk_simulate_envelope(plan, n, m, seed=c["seed"], per_sim=True)
         d = oracle.desc(*cfg_args(c))
         xs, ys, ts = oracle.csr_points(d, n, 7, c["seed"])
-        say("config4 sim 7 through the observed path")
+        say("mixed2m sim 7 through the observed path")
         obs7 = ripk.ripk_compute_K(plan, xs, ys, ts)
     finally:
         plan.destroy()
@@ -246,7 +246,7 @@ def test_wide_distances():
 
 @pytest.mark.parametrize("edge,norm", [(0, 0), (1, 0), (2, 1), (3, 1)])
 def test_edge_and_norm_switches(edge, norm):
-    c = workloads.config(1)
+    c = workloads.workload("uniform-2k")
     x, y, t = workloads.make_points(c)
     say("switches edge=%d norm=%d" % (edge, norm))
     g = gpu_K(x, y, t, *cfg_args(c), edge=edge, norm=norm)
@@ -274,7 +274,7 @@ def test_halo_subset_and_additivity():
 
 def test_device_tensors_and_plan_reuse():
     torch = pytest.importorskip("torch")
-    c = workloads.config(1)
+    c = workloads.workload("uniform-2k")
     x, y, t = workloads.make_points(c)
     plan = make_plan(*cfg_args(c), n_max=len(x))
     try:
@@ -293,7 +293,7 @@ def test_device_tensors_and_plan_reuse():
 
 
 def test_errors_are_reported():
-    c = workloads.config(1)
+    c = workloads.workload("uniform-2k")
     x, y, t = workloads.make_points(c)
     plan = make_plan(*cfg_args(c), n_max=1000, m_max=3)
     try:

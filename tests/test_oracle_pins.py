@@ -307,7 +307,7 @@ def test_literal_larger_grid_non_divisible():
 def test_symmetry_and_monotonicity():
     """Unweighted ordered counts are symmetric in i<->j (all even); C and W are
     non-decreasing in s and t (Eq. 3 is monotone)."""
-    cfg = workloads.config(1)
+    cfg = workloads.workload("uniform-2k")
     x, y, t = workloads.make_points(cfg)
     d = oracle.desc(cfg["window"], cfg["s_max"], cfg["t_max"], cfg["n_s"], cfg["n_t"])
     r = oracle.estimate(d, x, y, t)
@@ -371,7 +371,7 @@ def test_csr_expectation_detects_missing_temporal_correction():
 
 def test_envelope_min_max_semantics():
     """Envelopes are the pointwise min/max over the simulations only (Sec. 3)."""
-    cfg = workloads.config(1)
+    cfg = workloads.workload("uniform-2k")
     d = oracle.desc(cfg["window"], cfg["s_max"], cfg["t_max"], cfg["n_s"], cfg["n_t"])
     env = oracle.envelope(d, 400, 7, seed=1)
     Ks = env["K_sims"]
