@@ -184,6 +184,88 @@ ripk_status ripk_simulate_envelope(ripk_plan_t plan, int64_t n, int32_t m, uint6
 /* Counters and timings of the plan's last compute call. */
 ripk_status ripk_plan_stats(ripk_plan_t plan, ripk_stats *out);
 
+/* ---- Serving ---------------------------------------------------------------
+ *
+ * A server evaluates requests -- an observed set's K and L and, when m > 0, its
+ * m CSR simulations and envelopes (Sec. 3) -- with continuous batching on one
+ * device.  It runs `slots` requests at a time, each on its own HIP stream with
+ * its own device workspace, so their kernels overlap.  Queued requests are
+ * admitted in arrival order as soon as a slot is idle and the request's device
+ * footprint (ripk_plan_info.device_bytes of its descriptor) fits in the HBM
+ * budget beside the workspaces the slots hold; idle slots give their workspaces
+ * back when the budget runs short.  Results are exact integer sums, so a
+ * request's outputs are bit-identical to ripk_compute_K and
+ * ripk_simulate_envelope on a plan of the same descriptor, alone or in a mix.
+ * All server calls are thread-safe, except that ripk_server_destroy must not
+ * overlap any other call on the same server.
+ */
+typedef struct ripk_server_s *ripk_server_t;
+
+typedef struct {
+  int32_t device;            /* HIP device ordinal                                     */
+  int32_t slots;             /* requests evaluated concurrently, 1..16                 */
+  int32_t queue_cap;         /* requests that may wait for admission, >= 1             */
+  int32_t reserved;          /* set to 0                                               */
+  int64_t hbm_budget_bytes;  /* device bytes all slot workspaces may hold together     */
+} ripk_server_desc;
+
+#define RIPK_REQ_KEEP_SIMS (1u << 0) /* keep per-simulation C, W, K for ripk_poll */
+
+/* One request.  plan: window, grid, edge correction, normalisation, flags;
+ * its n_max, m_max and device are ignored (the request's n and m and the
+ * server's device are used).  pts: host points (on_device must be 0), copied
+ * by ripk_submit, so the caller's arrays may be reused as soon as it returns.
+ * m: CSR simulations (0 = K only); seed: Philox key as in
+ * ripk_simulate_envelope.  dL_hi is computed against the request's own L. */
+typedef struct {
+  ripk_plan_desc plan;
+  ripk_points pts;
+  int32_t m;
+  uint32_t flags;            /* RIPK_REQ_* bits                                        */
+  uint64_t seed;
+} ripk_request;
+
+/* Result of ripk_poll.  k and env are input fields: host buffers the caller
+ * provides (n_s*n_t elements, per-simulation arrays m*n_s*n_t and only with
+ * RIPK_REQ_KEEP_SIMS; any may be NULL).  The rest are outputs.  Times are
+ * seconds on the host's CLOCK_MONOTONIC. */
+typedef struct {
+  ripk_K_out k;
+  ripk_env_out env;
+  ripk_status status;        /* the request's status                                   */
+  int32_t slot;              /* slot that evaluated it (-1 if never admitted)          */
+  double t_submit, t_admit, t_done;
+  int64_t n_in;              /* ordered in-range pairs over the observed and simulated sets */
+} ripk_result;
+
+/* Occupancy of a server. */
+typedef struct {
+  int64_t queued;            /* requests waiting for admission                          */
+  int64_t unpolled;          /* requests submitted and not yet collected by ripk_poll   */
+  int64_t device_bytes;      /* device bytes held by slot workspaces                    */
+  int32_t busy_slots;
+  int32_t reserved;
+} ripk_server_state;
+
+/* Create a server: starts `slots` worker threads.  Errors: EINVAL, EDEVICE. */
+ripk_status ripk_server_create(const ripk_server_desc *desc, ripk_server_t *out);
+
+/* Cancel queued requests (ECANCELED), let admitted ones finish, free all. */
+void ripk_server_destroy(ripk_server_t server);
+
+/* Queue a request; never blocks on the device.  *ticket identifies it.
+ * Errors: EINVAL (bad descriptor or points), E2BIG (footprint above the
+ * budget), EAGAIN (queue full), ECANCELED (server shutting down). */
+ripk_status ripk_submit(ripk_server_t server, const ripk_request *req, uint64_t *ticket);
+
+/* Wait up to timeout_ms (0 = do not wait, < 0 = until done) for a request.
+ * Returns RIPK_PENDING if it is not done; otherwise fills *out, forgets the
+ * ticket and returns the request's status (ERANGE, EDEVICE, ENOMEM, ...).
+ * ENOTFOUND for an unknown or already collected ticket. */
+ripk_status ripk_poll(ripk_server_t server, uint64_t ticket, ripk_result *out, int32_t timeout_ms);
+
+ripk_status ripk_server_status(ripk_server_t server, ripk_server_state *out);
+
 const char *ripk_status_str(ripk_status s);
 const char *ripk_last_error(void);
 

@@ -55,7 +55,58 @@ struct Layout {
   ripk_plan_info info;
   Geom g;
   int32_t clamp_e;
+  Caps caps;
 };
+
+}  // namespace
+
+namespace ripk {
+
+Caps caps_for(int64_t S, int64_t n_max, int64_t n_cells, int64_t n_bins) {
+  Caps c;
+  c.S = S;
+  c.N = S * n_max;
+  c.SNC = S * n_cells;
+  c.items = S * (n_max / kChunk + n_cells + kItemsPerGroup);
+  c.SNB = S * n_bins;
+  c.NB = n_bins;
+  return c;
+}
+
+int64_t caps_bytes(const Caps &c) {
+  int64_t bytes = 0;
+  bytes += 3 * 4 * c.N;                       // x, y, t staging / simulated points
+  bytes += 4 * 4 * c.N;                       // keys, vals (double buffered)
+  bytes += (int64_t)radix_sort_temp_bytes((uint32_t)c.N);
+  bytes += 4 * (2 * c.SNC + 1);               // cell starts
+  bytes += 16 * c.N;                          // sorted point records
+  bytes += 4 * c.SNC * 2 + 4 * (c.S + 1) + (int64_t)scan_temp_bytes((uint32_t)c.SNC) + 256;
+  bytes += 16 * c.items;                      // work items
+  bytes += 8 * 3 * c.SNB;                     // bins
+  bytes += 8 * 4 * c.SNB;                     // C, W, K, L
+  bytes += 8 * 6 * c.NB + 8 * 2 * kMaxSteps + 32;
+  return bytes;
+}
+
+bool caps_fit(const Caps &have, const Caps &need) {
+  return need.S <= have.S && need.N <= have.N && need.SNC <= have.SNC &&
+         need.items <= have.items && need.SNB <= have.SNB && need.NB <= have.NB;
+}
+
+Caps caps_max(const Caps &a, const Caps &b) {
+  Caps c;
+  c.S = std::max(a.S, b.S);
+  c.N = std::max(a.N, b.N);
+  c.SNC = std::max(a.SNC, b.SNC);
+  c.items = std::max(a.items, b.items);
+  c.SNB = std::max(a.SNB, b.SNB);
+  c.NB = std::max(a.NB, b.NB);
+  return c;
+}
+
+}  // namespace ripk
+
+namespace {
 
 // Validation and derived geometry; no device access.
 ripk_status derive(const ripk_plan_desc *d, Layout *L) {
@@ -146,21 +197,8 @@ ripk_status derive(const ripk_plan_desc *d, Layout *L) {
   g.inv_dt = (float)((double)d->n_t / (double)d->t_max);
   L->clamp_e = (int32_t)d->s_max;
 
-  // device footprint
-  const int64_t N = S * d->n_max, NB = I.n_bins, NC = I.n_cells;
-  const int64_t items = S * (d->n_max / kChunk + NC + kItemsPerGroup);
-  int64_t bytes = 0;
-  bytes += 3 * 4 * N;                        // x, y, t staging / simulated points
-  bytes += 4 * 4 * N;                        // keys, vals (double buffered)
-  bytes += (int64_t)radix_sort_temp_bytes((uint32_t)N);
-  bytes += 4 * (2 * S * NC + 1);             // cell starts
-  bytes += 16 * N;                           // sorted point records
-  bytes += 4 * (S * NC) * 2 + 4 * (S + 1) + (int64_t)scan_temp_bytes((uint32_t)(S * NC));
-  bytes += 16 * items;                       // work items
-  bytes += 8 * 3 * S * NB;                   // bins
-  bytes += 8 * 4 * S * NB;                   // C, W, K, L
-  bytes += 8 * 6 * NB + 8 * 2 * kMaxSteps + 4096;
-  I.device_bytes = bytes;
+  L->caps = caps_for(S, d->n_max, I.n_cells, I.n_bins);
+  I.device_bytes = caps_bytes(L->caps);
   return RIPK_OK;
 }
 
@@ -171,8 +209,10 @@ struct ripk_plan_s {
   Layout lay;
   int device = 0;
   int cus = 0;
-  int64_t S = 1;     // set capacity
-  int64_t items_cap = 0;
+  size_t lds_max = 0;  // LDS bytes a workgroup may use on this device
+  Caps caps{};         // capacities the device buffers were allocated for
+  uint64_t S2h[kMaxSteps] = {};  // host copies of the threshold tables
+  uint32_t Th[kMaxSteps] = {};
   // device buffers
   int32_t *x = nullptr, *y = nullptr, *t = nullptr;
   uint32_t *keys[2] = {nullptr, nullptr}, *vals[2] = {nullptr, nullptr};
@@ -320,7 +360,104 @@ ripk_status collect_stats(ripk_plan_s *p, hipStream_t st, uint32_t S, uint32_t n
   return RIPK_OK;
 }
 
+ripk_status sync_status(hipError_t e) {
+  if (e != hipSuccess) return fail(RIPK_EDEVICE, "device synchronisation failed: %s", hipGetErrorString(e));
+  return RIPK_OK;
+}
+
 }  // namespace
+
+namespace ripk {
+
+ripk_status plan_validate(const ripk_plan_desc *desc, Caps *caps) {
+  Layout L;
+  ripk_status s = derive(desc, &L);
+  if (s == RIPK_OK && caps) *caps = L.caps;
+  return s;
+}
+
+// Device buffers for the capacities c on `device`; geometry is bound later.
+ripk_status plan_create(int device, const Caps &c, ripk_plan_s **out) {
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
+    return fail(RIPK_EDEVICE, "no HIP device available");
+  if (device < 0 || device >= ndev)
+    return fail(RIPK_EINVAL, "device %d out of range (have %d)", device, ndev);
+  DeviceGuard dg(device);
+  ripk_plan_s *p = new ripk_plan_s();
+  p->device = device;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+    release(p);
+    return fail(RIPK_EDEVICE, "hipGetDeviceProperties failed");
+  }
+  p->cus = prop.multiProcessorCount;
+  p->lds_max = prop.sharedMemPerBlock;
+  p->caps = c;
+  hipError_t e = hipSuccess;
+#define ALLOC(ptr, cnt) \
+  if (e == hipSuccess) e = dalloc(&(ptr), (size_t)(cnt))
+  ALLOC(p->x, c.N); ALLOC(p->y, c.N); ALLOC(p->t, c.N);
+  ALLOC(p->keys[0], c.N); ALLOC(p->keys[1], c.N); ALLOC(p->vals[0], c.N); ALLOC(p->vals[1], c.N);
+  if (e == hipSuccess) e = hipMalloc(&p->sort_temp, radix_sort_temp_bytes((uint32_t)c.N));
+  ALLOC(p->cs, 2 * c.SNC + 1);
+  ALLOC(p->P, c.N);
+  ALLOC(p->chunks, c.SNC); ALLOC(p->offs, c.SNC + 1); ALLOC(p->set_base, c.S + 1);
+  if (e == hipSuccess) e = hipMalloc(&p->scan_temp, scan_temp_bytes((uint32_t)c.SNC) + 256);
+  ALLOC(p->items, c.items);
+  ALLOC(p->binC, c.SNB); ALLOC(p->binW, 2 * c.SNB);
+  ALLOC(p->outC, c.SNB); ALLOC(p->outW, c.SNB); ALLOC(p->outK, c.SNB); ALLOC(p->outL, c.SNB);
+  ALLOC(p->env, 5 * c.NB); ALLOC(p->Lobs, c.NB);
+  ALLOC(p->S2, kMaxSteps); ALLOC(p->T, kMaxSteps);
+  ALLOC(p->scal, 4);
+#undef ALLOC
+  if (e != hipSuccess) {
+    release(p);
+    return fail(e == hipErrorOutOfMemory ? RIPK_ENOMEM : RIPK_EDEVICE, "allocation failed: %s",
+                hipGetErrorString(e));
+  }
+  for (auto &ev : p->ev)
+    if (e == hipSuccess) e = hipEventCreate(&ev);
+  if (e != hipSuccess) {
+    release(p);
+    return fail(RIPK_EDEVICE, "plan set-up failed: %s", hipGetErrorString(e));
+  }
+  *out = p;
+  return RIPK_OK;
+}
+
+// Binds a descriptor to a plan whose buffers hold its capacities; the
+// threshold tables are copied on `stream`.
+ripk_status plan_bind(ripk_plan_s *p, const ripk_plan_desc *desc, hipStream_t stream) {
+  Layout L;
+  ripk_status s = derive(desc, &L);
+  if (s != RIPK_OK) return s;
+  if (desc->device != p->device) return fail(RIPK_EINVAL, "descriptor device differs from the plan's");
+  if (!caps_fit(p->caps, L.caps)) return fail(RIPK_E2BIG, "descriptor exceeds the plan's capacity");
+  const int lds = pair_lds_bytes(L.info.n_bins);
+  if ((size_t)lds > p->lds_max)
+    return fail(RIPK_EINVAL, "grid of %d bins needs %d B of LDS per workgroup, device has %zu",
+                L.info.n_bins, lds, p->lds_max);
+  DeviceGuard dg(p->device);
+  p->desc = *desc;
+  p->lay = L;
+  std::memset(p->S2h, 0, sizeof p->S2h);
+  std::memset(p->Th, 0, sizeof p->Th);
+  for (int k = 0; k < desc->n_s; ++k) p->S2h[k] = (uint64_t)L.info.S2[k];
+  for (int l = 0; l < desc->n_t; ++l) p->Th[l] = (uint32_t)L.info.T[l];
+  HIPCHK(hipMemcpyAsync(p->S2, p->S2h, sizeof p->S2h, hipMemcpyHostToDevice, stream));
+  HIPCHK(hipMemcpyAsync(p->T, p->Th, sizeof p->Th, hipMemcpyHostToDevice, stream));
+  return RIPK_OK;
+}
+
+const Caps &plan_caps(const ripk_plan_s *p) { return p->caps; }
+
+void plan_free(ripk_plan_s *p) { release(p); }
+
+ripk_status set_error(ripk_status s, const char *msg) { return fail(s, "%s", msg); }
+
+}  // namespace ripk
 
 extern "C" {
 
@@ -357,65 +494,14 @@ ripk_status ripk_plan(const ripk_plan_desc *desc, ripk_plan_t *out) {
   Layout L;
   ripk_status s = derive(desc, &L);
   if (s != RIPK_OK) return s;
-  int ndev = 0;
-  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
-    return fail(RIPK_EDEVICE, "no HIP device available");
-  if (desc->device < 0 || desc->device >= ndev)
-    return fail(RIPK_EINVAL, "device %d out of range (have %d)", desc->device, ndev);
-  DeviceGuard dg(desc->device);
-  ripk_plan_s *p = new ripk_plan_s();
-  p->desc = *desc;
-  p->lay = L;
-  p->device = desc->device;
-  hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, p->device) != hipSuccess) {
+  ripk_plan_s *p = nullptr;
+  s = plan_create(desc->device, L.caps, &p);
+  if (s != RIPK_OK) return s;
+  s = plan_bind(p, desc, nullptr);
+  if (s == RIPK_OK) s = sync_status(hipStreamSynchronize(nullptr));
+  if (s != RIPK_OK) {
     release(p);
-    return fail(RIPK_EDEVICE, "hipGetDeviceProperties failed");
-  }
-  p->cus = prop.multiProcessorCount;
-  const int lds = pair_lds_bytes(L.info.n_bins);
-  if ((size_t)lds > prop.sharedMemPerBlock) {
-    release(p);
-    return fail(RIPK_EINVAL, "grid of %d bins needs %d B of LDS per workgroup, device has %zu",
-                L.info.n_bins, lds, (size_t)prop.sharedMemPerBlock);
-  }
-  const int64_t S = std::max<int64_t>(1, desc->m_max);
-  p->S = S;
-  const int64_t N = S * desc->n_max, NB = L.info.n_bins, NC = L.info.n_cells;
-  p->items_cap = S * (desc->n_max / kChunk + NC + kItemsPerGroup);
-  hipError_t e = hipSuccess;
-#define ALLOC(ptr, cnt) \
-  if (e == hipSuccess) e = dalloc(&(ptr), (size_t)(cnt))
-  ALLOC(p->x, N); ALLOC(p->y, N); ALLOC(p->t, N);
-  ALLOC(p->keys[0], N); ALLOC(p->keys[1], N); ALLOC(p->vals[0], N); ALLOC(p->vals[1], N);
-  if (e == hipSuccess) e = hipMalloc(&p->sort_temp, radix_sort_temp_bytes((uint32_t)N));
-  ALLOC(p->cs, 2 * S * NC + 1);
-  ALLOC(p->P, N);
-  ALLOC(p->chunks, S * NC); ALLOC(p->offs, S * NC + 1); ALLOC(p->set_base, S + 1);
-  if (e == hipSuccess) e = hipMalloc(&p->scan_temp, scan_temp_bytes((uint32_t)(S * NC)) + 256);
-  ALLOC(p->items, p->items_cap);
-  ALLOC(p->binC, S * NB); ALLOC(p->binW, 2 * S * NB);
-  ALLOC(p->outC, S * NB); ALLOC(p->outW, S * NB); ALLOC(p->outK, S * NB); ALLOC(p->outL, S * NB);
-  ALLOC(p->env, 5 * NB); ALLOC(p->Lobs, NB);
-  ALLOC(p->S2, kMaxSteps); ALLOC(p->T, kMaxSteps);
-  ALLOC(p->scal, 4);
-#undef ALLOC
-  if (e != hipSuccess) {
-    release(p);
-    return fail(e == hipErrorOutOfMemory ? RIPK_ENOMEM : RIPK_EDEVICE, "allocation failed: %s",
-                hipGetErrorString(e));
-  }
-  uint64_t S2h[kMaxSteps] = {0};
-  uint32_t Th[kMaxSteps] = {0};
-  for (int k = 0; k < desc->n_s; ++k) S2h[k] = (uint64_t)L.info.S2[k];
-  for (int l = 0; l < desc->n_t; ++l) Th[l] = (uint32_t)L.info.T[l];
-  e = hipMemcpy(p->S2, S2h, sizeof S2h, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(p->T, Th, sizeof Th, hipMemcpyHostToDevice);
-  for (auto &ev : p->ev)
-    if (e == hipSuccess) e = hipEventCreate(&ev);
-  if (e != hipSuccess) {
-    release(p);
-    return fail(RIPK_EDEVICE, "plan set-up failed: %s", hipGetErrorString(e));
+    return s;
   }
   *out = p;
   return RIPK_OK;

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/ripk.h"
+
 namespace ripk {
 
 constexpr int kMaxSteps = 64;      // n_s, n_t <= 64
@@ -57,7 +59,28 @@ struct PairArgs {
   int symmetric;
 };
 
-// ---- launchers (kernels.hip) ----------------------------------------------
+// ---- host runtime (api.cpp) -------------------------------------------------
+
+// Buffer capacities of a plan: S sets, N = S*n_max points, SNC = S*n_cells
+// cells, work items, SNB = S*n_bins bins, NB = n_bins.
+struct Caps {
+  int64_t S = 0, N = 0, SNC = 0, items = 0, SNB = 0, NB = 0;
+};
+Caps caps_for(int64_t S, int64_t n_max, int64_t n_cells, int64_t n_bins);
+int64_t caps_bytes(const Caps &c);
+bool caps_fit(const Caps &have, const Caps &need);
+Caps caps_max(const Caps &a, const Caps &b);
+
+// Plans with capacities apart from their geometry (the server keeps one per
+// slot and rebinds it to each request that fits).
+ripk_status plan_validate(const ripk_plan_desc *desc, Caps *caps);
+ripk_status plan_create(int device, const Caps &c, ripk_plan_s **out);
+ripk_status plan_bind(ripk_plan_s *p, const ripk_plan_desc *desc, hipStream_t stream);
+const Caps &plan_caps(const ripk_plan_s *p);
+void plan_free(ripk_plan_s *p);
+ripk_status set_error(ripk_status s, const char *msg);  // sets ripk_last_error()
+
+// launchers (kernels.hip) ----------------------------------------------
 hipError_t launch_keys(const int32_t *x, const int32_t *y, const int32_t *t, uint32_t n,
                        uint32_t n_centres, uint32_t set_base, uint32_t n_sets,
                        const Geom &g, uint32_t *keys, uint32_t *vals, uint32_t *err,

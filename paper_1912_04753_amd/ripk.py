@@ -35,6 +35,7 @@ RIPK_NORM_N2 = 1
 RIPK_SIM_CSR = 0
 RIPK_PLAN_ORDERED = 1
 RIPK_PLAN_TIMING = 2
+RIPK_REQ_KEEP_SIMS = 1
 
 _i64, _i32, _u32, _u64, _f64 = (ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32,
                                 ctypes.c_uint64, ctypes.c_double)
@@ -78,6 +79,26 @@ class Stats(ctypes.Structure):
                 ("us_finalize", _f64)]
 
 
+class ServerDesc(ctypes.Structure):
+    _fields_ = [("device", _i32), ("slots", _i32), ("queue_cap", _i32), ("reserved", _i32),
+                ("hbm_budget_bytes", _i64)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("plan", PlanDesc), ("pts", Points), ("m", _i32), ("flags", _u32),
+                ("seed", _u64)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("k", KOut), ("env", EnvOut), ("status", _i32), ("slot", _i32),
+                ("t_submit", _f64), ("t_admit", _f64), ("t_done", _f64), ("n_in", _i64)]
+
+
+class ServerState(ctypes.Structure):
+    _fields_ = [("queued", _i64), ("unpolled", _i64), ("device_bytes", _i64),
+                ("busy_slots", _i32), ("reserved", _i32)]
+
+
 class RipkError(RuntimeError):
     def __init__(self, status, where):
         self.status = status
@@ -99,6 +120,11 @@ _SIGS = {
     "ripk_simulate_envelope": (_i32, [ctypes.c_void_p, _i64, _i32, _u64, _P(_f64),
                                       ctypes.c_void_p, _P(EnvOut)]),
     "ripk_plan_stats": (_i32, [ctypes.c_void_p, _P(Stats)]),
+    "ripk_server_create": (_i32, [_P(ServerDesc), _P(ctypes.c_void_p)]),
+    "ripk_server_destroy": (None, [ctypes.c_void_p]),
+    "ripk_submit": (_i32, [ctypes.c_void_p, _P(Request), _P(_u64)]),
+    "ripk_poll": (_i32, [ctypes.c_void_p, _u64, _P(Result), _i32]),
+    "ripk_server_status": (_i32, [ctypes.c_void_p, _P(ServerState)]),
     "ripk_status_str": (ctypes.c_char_p, [_i32]),
     "ripk_last_error": (ctypes.c_char_p, []),
 }
@@ -278,3 +304,87 @@ def ripk_plan_stats(plan):
     s = Stats()
     _check(lib().ripk_plan_stats(plan.handle, ctypes.byref(s)), "ripk_plan_stats")
     return {k: getattr(s, k) for k, _ in Stats._fields_}
+
+
+class Server:
+    """Owns a ``ripk_server_t`` and remembers each ticket's output shapes."""
+
+    def __init__(self, handle):
+        self.handle = handle
+        self.pending = {}  # ticket -> (n_s, n_t, m, keep_sims)
+
+    def destroy(self):
+        if self.handle:
+            lib().ripk_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def ripk_server_create(device=0, slots=4, queue_cap=4096, hbm_budget_bytes=64 << 30):
+    d = ServerDesc(int(device), int(slots), int(queue_cap), 0, int(hbm_budget_bytes))
+    h = ctypes.c_void_p()
+    _check(lib().ripk_server_create(ctypes.byref(d), ctypes.byref(h)), "ripk_server_create")
+    return Server(h)
+
+
+def ripk_server_destroy(server):
+    server.destroy()
+
+
+def ripk_submit(server, desc, x, y, t, m=0, seed=0, n_centres=0, keep_sims=False):
+    """Queue a request (host points, copied before return); returns its ticket."""
+    n = len(x)
+    px, _, kx = _coord_ptr(np.asarray(x), n)
+    py, _, ky = _coord_ptr(np.asarray(y), n)
+    pt, _, kt = _coord_ptr(np.asarray(t), n)
+    req = Request(desc, Points(px, py, pt, n, int(n_centres), 0), int(m),
+                  RIPK_REQ_KEEP_SIMS if keep_sims else 0, int(seed) & (2**64 - 1))
+    ticket = _u64()
+    _check(lib().ripk_submit(server.handle, ctypes.byref(req), ctypes.byref(ticket)), "ripk_submit")
+    del kx, ky, kt
+    server.pending[ticket.value] = (desc.n_s, desc.n_t, int(m), bool(keep_sims))
+    return ticket.value
+
+
+def ripk_poll(server, ticket, timeout_ms=-1):
+    """None while the request runs; else a dict of its outputs and timings.
+    Raises RipkError if the request failed."""
+    ns, nt, m, keep = server.pending[ticket]
+    shp = (ns, nt)
+    ptr = lambda a, ct: a.ctypes.data_as(_P(ct))
+    res = {"C": _out(shp, np.uint64), "W": _out(shp, np.float64), "K": _out(shp, np.float64),
+           "L": _out(shp, np.float64)}
+    r = Result()
+    r.k = KOut(ptr(res["C"], _u64), ptr(res["W"], _f64), ptr(res["K"], _f64), ptr(res["L"], _f64))
+    if m > 0:
+        for key in ("K_lo", "K_hi", "L_lo", "L_hi", "dL_hi"):
+            res[key] = _out(shp, np.float64)
+        env = EnvOut(ptr(res["K_lo"], _f64), ptr(res["K_hi"], _f64), ptr(res["L_lo"], _f64),
+                     ptr(res["L_hi"], _f64), ptr(res["dL_hi"], _f64), _P(_u64)(), _P(_f64)(),
+                     _P(_f64)())
+        if keep:
+            res["C_sims"] = _out((m,) + shp, np.uint64)
+            res["W_sims"] = _out((m,) + shp, np.float64)
+            res["K_sims"] = _out((m,) + shp, np.float64)
+            env.C_sims = ptr(res["C_sims"], _u64)
+            env.W_sims = ptr(res["W_sims"], _f64)
+            env.K_sims = ptr(res["K_sims"], _f64)
+        r.env = env
+    st = lib().ripk_poll(server.handle, _u64(ticket), ctypes.byref(r), int(timeout_ms))
+    if st == RIPK_PENDING:
+        return None
+    server.pending.pop(ticket, None)
+    _check(st, "ripk_poll")
+    res.update(slot=r.slot, t_submit=r.t_submit, t_admit=r.t_admit, t_done=r.t_done, n_in=r.n_in)
+    return res
+
+
+def ripk_server_status(server):
+    s = ServerState()
+    _check(lib().ripk_server_status(server.handle, ctypes.byref(s)), "ripk_server_status")
+    return {k: getattr(s, k) for k, _ in ServerState._fields_ if k != "reserved"}

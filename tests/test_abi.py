@@ -88,3 +88,16 @@ def test_plan_allows_large_s_without_spatial_correction():
 def test_status_strings():
     assert ripk.ripk_status_str(ripk.RIPK_ERANGE) == "point outside the study window"
     assert ripk.ripk_status_str(0) == "ok"
+
+
+def test_server_structs_and_argument_checks():
+    assert ctypes.sizeof(ripk.ServerDesc) == 4 * 4 + 8
+    assert ctypes.sizeof(ripk.Request) == ctypes.sizeof(ripk.PlanDesc) + ctypes.sizeof(ripk.Points) + 16
+    assert ctypes.sizeof(ripk.Result) == 4 * 8 + 8 * 8 + 4 + 4 + 3 * 8 + 8
+    for slots in (0, 17):
+        with pytest.raises(ripk.RipkError) as e:
+            ripk.ripk_server_create(slots=slots)
+        assert e.value.status == ripk.RIPK_EINVAL
+    with pytest.raises(ripk.RipkError) as e:
+        ripk.ripk_server_create(hbm_budget_bytes=0)
+    assert e.value.status == ripk.RIPK_EINVAL
