@@ -18,6 +18,7 @@ import argparse
 import json
 import os
 import sys
+import threading
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -52,6 +53,104 @@ def cpu_baseline(cfg, x, y, t, target_s):
                       f"{n_in} in-range ordered pairs in {dt:.2f} s"}
 
 
+def serving(ripk, workloads, n_req, slots, load):
+    """The request stream served two ways on the same arrival schedule: the plain
+    path (one request at a time, in arrival order: a plan, ripk_compute_K and
+    ripk_simulate_envelope each) and the server (continuous batching over
+    `slots` streams).  Arrivals are Poisson at `load` x the plain path's measured
+    capacity; latency = completion - scheduled arrival."""
+    import numpy as np
+    reqs = workloads.serving_requests(num=n_req)
+    pts = [workloads.request_points(r) for r in reqs]
+    descs = [ripk.make_desc(r["window"], r["s_max"], r["t_max"], r["n_s"], r["n_t"],
+                            n_max=len(p[0]), m_max=r["sims"]) for r, p in zip(reqs, pts)]
+
+    def plain_one(i):
+        r, (x, y, t) = reqs[i], pts[i]
+        plan = ripk.ripk_plan(descs[i])
+        try:
+            k = ripk.ripk_compute_K(plan, x, y, t)
+            n_in = ripk.ripk_plan_stats(plan)["n_in"]
+            if r["sims"] > 0:
+                ripk.ripk_simulate_envelope(plan, len(x), r["sims"], r["seed"], L_obs=k["L"])
+                n_in += ripk.ripk_plan_stats(plan)["n_in"]
+        finally:
+            plan.destroy()
+        return n_in
+
+    plain_one(0)  # warm-up
+    t0 = time.monotonic()
+    n_in_total = sum(plain_one(i) for i in range(n_req))
+    capacity = n_req / (time.monotonic() - t0)
+    rate = load * capacity
+    gaps = np.random.Generator(np.random.PCG64(55)).exponential(1.0 / rate, n_req)
+    offs = np.cumsum(gaps) - gaps[0]
+
+    def wait_until(a):
+        d = a - time.monotonic()
+        if d > 0:
+            time.sleep(d)
+
+    # plain path on the arrival schedule
+    start = time.monotonic() + 0.05
+    lat_plain, end_plain = [], start
+    for i in range(n_req):
+        a = start + offs[i]
+        wait_until(a)
+        plain_one(i)
+        end_plain = time.monotonic()
+        lat_plain.append(end_plain - a)
+    span_plain = end_plain - start
+
+    # server on the same schedule
+    sv = ripk.ripk_server_create(slots=slots, queue_cap=n_req, hbm_budget_bytes=64 << 30)
+    tickets = [None] * n_req
+    ready = [threading.Event() for _ in range(n_req)]
+    start = time.monotonic() + 0.05
+
+    def submitter():
+        for i in range(n_req):
+            wait_until(start + offs[i])
+            r, (x, y, t) = reqs[i], pts[i]
+            tickets[i] = ripk.ripk_submit(sv, descs[i], x, y, t, m=r["sims"], seed=r["seed"])
+            ready[i].set()
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    lat_srv, end_srv, n_in_srv = [], start, 0
+    for i in range(n_req):
+        ready[i].wait()
+        res = ripk.ripk_poll(sv, tickets[i], timeout_ms=-1)
+        lat_srv.append(res["t_done"] - (start + offs[i]))
+        end_srv = max(end_srv, res["t_done"])
+        n_in_srv += res["n_in"]
+    th.join()
+    span_srv = end_srv - start
+    assert n_in_srv == n_in_total
+    # capacity of the server: the whole stream submitted at once
+    t_burst = time.monotonic()
+    burst = [ripk.ripk_submit(sv, descs[i], *pts[i], m=reqs[i]["sims"], seed=reqs[i]["seed"])
+             for i in range(n_req)]
+    end_burst = max(ripk.ripk_poll(sv, tk, timeout_ms=-1)["t_done"] for tk in burst)
+    served_capacity = n_req / (end_burst - t_burst)
+    sv.destroy()
+
+    def summary(lat, span):
+        lat = np.sort(np.asarray(lat)) * 1e3
+        return {"p50_ms": round(float(np.percentile(lat, 50)), 2),
+                "p99_ms": round(float(np.percentile(lat, 99)), 2),
+                "pair_tests_per_s_G": round(n_in_total / span / 1e9, 3)}
+
+    return {"requests": n_req, "load": load, "rate_per_s": round(rate, 3),
+            "plain_capacity_per_s": round(capacity, 3),
+            "served_capacity_per_s": round(served_capacity, 3), "slots": slots,
+            "n_in": int(n_in_total),
+            "plain": summary(lat_plain, span_plain), "served": summary(lat_srv, span_srv),
+            "note": "request stream: n log-uniform [1e3, 5e5], uniform or Thomas, own window "
+                    "and grid, 0-99 CSR sims; host points in, H2D included; plain path "
+                    "creates a plan per request"}
+
+
 def copy_calibration(torch):
     """A plain device copy of known size, for scaling the HBM byte counters."""
     from paper_1912_04753_amd.profiling import COPY_BYTES
@@ -68,6 +167,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--serve-requests", type=int, default=300,
+                    help="requests of the serving stream (0 = skip the serving leg)")
+    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-load", type=float, default=0.7)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain device copy of known size first (counter runs)")
     args = ap.parse_args()
@@ -153,6 +256,9 @@ def main():
                      "note": f"{OPS_PER_EVAL} lane-ops per candidate pair x candidates per "
                              f"launch / mean pair-kernel launch time ({avg_us:.1f} us)"},
     }
+    if args.serve_requests > 0:
+        out["serving"] = serving(ripk, workloads, args.serve_requests, args.serve_slots,
+                                 args.serve_load)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, x, y, t, args.cpu_seconds)
     print(json.dumps(out), flush=True)
