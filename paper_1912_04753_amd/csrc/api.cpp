@@ -193,8 +193,10 @@ ripk_status derive(const ripk_plan_desc *d, Layout *L) {
   g.mode = I.dist_mode;
   g.s2max = (uint64_t)I.S2[d->n_s - 1];
   g.tmax = (uint32_t)I.T[d->n_t - 1];
-  g.inv_ds = (float)((double)d->n_s / (double)d->s_max);
-  g.inv_dt = (float)((double)d->n_t / (double)d->t_max);
+  // scaled down by 2^-20 so that the pair kernel's FP32 step estimates never
+  // exceed the exact step (it then corrects upward by at most one)
+  g.inv_ds = (float)((double)d->n_s / (double)d->s_max * (1.0 - 0x1p-20));
+  g.inv_dt = (float)((double)d->n_t / (double)d->t_max * (1.0 - 0x1p-20));
   L->clamp_e = (int32_t)d->s_max;
 
   L->caps = caps_for(S, d->n_max, I.n_cells, I.n_bins);

@@ -58,7 +58,7 @@ constexpr uint32_t kClampE = 32767u;         // side distances stored in 15 bits
 struct WaveLds {
   int4 tile[2 * kJT];  // two tile slots of neighbour points
   int4 cen[64];        // the wave's centres
-  uint32_t qa[kQA];    // in-range pairs: byte offsets cen | tile << 10 (lane<<4 | index<<14)
+  uint32_t qa[kQA];    // in-range pairs: LDS addresses / 16 of centre | neighbour << 16
   uint4 qb[kQB];       // boundary weights, see drain_b
 };
 
@@ -77,6 +77,13 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 __device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// |a - b| of unsigned values in one instruction (sum of absolute differences)
+__device__ __forceinline__ uint32_t absdiff(uint32_t a, uint32_t b) {
+  uint32_t r;
+  asm("v_sad_u32 %0, %1, %2, 0" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
 
 // position of this lane among the set lanes of `mask`, plus `base`
 __device__ __forceinline__ uint32_t lane_rank(unsigned long long mask, uint32_t base) {
@@ -101,36 +108,38 @@ __device__ __forceinline__ float atan01(float z) {
   return p * z;
 }
 
-// beta = atan2(e, h) for e, h >= 0, not both 0: the angle between the radius to
-// a side's crossing point and the side itself; pi/2 when the side is not cut.
-__device__ __forceinline__ float beta_angle(float e, float h) {
-  const float lo = fminf(e, h), hi = fmaxf(e, h);
-  float r = __builtin_amdgcn_rcpf(hi);
-  r = fmaf(fmaf(-hi, r, 1.0f), r, r);  // one Newton step: quotient to ~1 ulp
-  const float a = atan01(lo * r);
-  return e > h ? 1.5707963267948966f - a : a;
-}
-
 // Isotropic correction on the rectangle in FP32 from the distances ex, ey to the
 // nearer x side and the nearer y side (only these can cut a circle of radius
-// <= min(W, H)/2).  With beta_e = atan2(e, sqrt(max(d2 - e^2, 0))) (= pi/2 for an
-// uncut side; d2 - e^2 is an exact integer) the excluded half-arcs are
-// pi/2 - beta_e and two cut sides overlap by max(0, pi/2 - beta_x - beta_y),
-// which gives, without branches,
-//   omega = (beta_x + beta_y)/pi + max(0, pi/2 - beta_x - beta_y)/(2 pi):
-// 1 with no cut, 1/2 + beta/pi with one, (beta_x + beta_y)/pi with two and the
-// corner outside the circle, 1/4 + (beta_x + beta_y)/(2 pi) with it inside.
-__device__ __forceinline__ float omega_from_beta(float bx, float by) {
-  const float sum = bx + by;
+// <= min(W, H)/2).  With h_e = sqrt(max(d2 - e^2, 0)) (d2 - e^2 is an exact
+// integer), the angle beta_e = atan2(e, h_e) between the radius to a side's
+// crossing point and that side is pi/2 for an uncut side; the excluded
+// half-arcs are pi/2 - beta_e and two cut sides overlap by
+// max(0, pi/2 - beta_x - beta_y), so without branches
+//   omega = S/pi + max(0, pi/2 - S)/(2 pi),   S = beta_x + beta_y:
+// 1 with no cut, 1/2 + beta/pi with one, S/pi with two and the corner outside
+// the circle, 1/4 + S/(2 pi) with it inside.  S is the argument of the
+// product (h_x + i e_x)(h_y + i e_y) = (h_x h_y - e_x e_y) + i (e_x h_y + e_y h_x),
+// a vector of length d2 in the upper half plane, so one arctangent gives it:
+// S in [0, pi], the real part rounded with an absolute error near 1e-7 d2.
+__device__ __forceinline__ float omega_hh(float ex, float ey, float hx, float hy) {
+  const float im = fmaf(ex, hy, ey * hx);
+  const float re = fmaf(hx, hy, -(ex * ey));
+  const float are = fabsf(re);
+  const float lo = fminf(im, are), hi = fmaxf(im, are);
+  float r = __builtin_amdgcn_rcpf(hi);
+  r = fmaf(fmaf(-hi, r, 1.0f), r, r);  // one Newton step: quotient to ~1 ulp
+  float a = atan01(lo * r);
+  a = im > are ? 1.5707963267948966f - a : a;
+  const float S = re < 0.0f ? 3.14159265358979323846f - a : a;
   const float inv_pi = 0.318309886183790671538f;
-  return sum * inv_pi + fmaxf(1.5707963267948966f - sum, 0.0f) * (0.5f * inv_pi);
+  return fmaf(S, inv_pi, fmaxf(1.5707963267948966f - S, 0.0f) * (0.5f * inv_pi));
 }
 
 __device__ __forceinline__ float omega_f32(uint32_t ex, uint32_t ey, uint64_t d2) {
   const uint64_t ex2 = (uint64_t)ex * ex, ey2 = (uint64_t)ey * ey;
   const float hx = __builtin_amdgcn_sqrtf((float)(ex2 < d2 ? d2 - ex2 : 0ull));
   const float hy = __builtin_amdgcn_sqrtf((float)(ey2 < d2 ? d2 - ey2 : 0ull));
-  return omega_from_beta(beta_angle((float)ex, hx), beta_angle((float)ey, hy));
+  return omega_hh((float)ex, (float)ey, hx, hy);
 }
 
 // the same with d2 < 2^31 and ex, ey < 2^15 (all squares exact in 32 bits)
@@ -138,7 +147,7 @@ __device__ __forceinline__ float omega_f32(uint32_t ex, uint32_t ey, uint32_t d2
   const uint32_t ex2 = __umul24(ex, ex), ey2 = __umul24(ey, ey);
   const float hx = __builtin_amdgcn_sqrtf((float)(ex2 < d2 ? d2 - ex2 : 0u));
   const float hy = __builtin_amdgcn_sqrtf((float)(ey2 < d2 ? d2 - ey2 : 0u));
-  return omega_from_beta(beta_angle((float)ex, hx), beta_angle((float)ey, hy));
+  return omega_hh((float)ex, (float)ey, hx, hy);
 }
 
 // Queue B: boundary weights with full lanes.  Records:
@@ -203,62 +212,57 @@ __device__ __forceinline__ Side side_of(const int4 p, uint32_t d2lo, uint64_t d2
 // fast path of omega are evaluated without branches on per-lane data (lanes
 // past c compute on entry 0 and store nothing); boundary sides go to queue B.
 template <bool SYM, int MODE>
-__device__ __forceinline__ void drain_a(WaveLds &W, QState &q, uint32_t c, int lane,
-                                        const Geom &g, unsigned long long *hist,
-                                        const uint32_t *S2lo, const uint32_t *S2hi,
-                                        const uint32_t *T) {
+__device__ __forceinline__ void drain_a(const unsigned char *lds, WaveLds &W, QState &q,
+                                        uint32_t c, int lane, const Geom &g,
+                                        unsigned long long *hist, const uint32_t *S2lo,
+                                        const uint32_t *S2hi, const uint32_t *T) {
   wave_sync();
   const uint32_t tag0 = W.qa[(q.ha + lane) & (kQA - 1)];
   wave_sync();
   const bool v = (uint32_t)lane < c;
   const unsigned long long vmask = c >= 64 ? ~0ull : ((1ull << c) - 1ull);
+  // a tag holds the LDS addresses, in 16-byte units, of the centre (low half)
+  // and of the neighbour (high half); lanes past c read address 0 and store
+  // nothing
   const uint32_t tag = v ? tag0 : 0u;
-  const int4 pi = *(const int4 *)((const char *)W.cen + (tag & 0x3F0u));
-  const int4 pj = *(const int4 *)((const char *)W.tile + (tag >> 10));
+  const int4 pi = *(const int4 *)(lds + ((tag & 0xFFFFu) << 4));
+  const int4 pj = *(const int4 *)(lds + ((tag >> 16) << 4));
   uint32_t d2lo, d2hi = 0, u;
   if (MODE == kModePacked) {
     typedef short s2 __attribute__((ext_vector_type(2)));
     const s2 dd = __builtin_bit_cast(s2, pi.x) - __builtin_bit_cast(s2, pj.x);
     d2lo = (uint32_t)__builtin_amdgcn_sdot2(dd, dd, 0, false);
-    u = (uint32_t)max(pi.y - pj.y, pj.y - pi.y);
+    u = absdiff((uint32_t)pi.y, (uint32_t)pj.y);
   } else if (MODE == kModeU32) {
     const int32_t dx = pi.x - pj.x, dy = pi.y - pj.y;
     d2lo = (uint32_t)__mul24(dx, dx) + (uint32_t)__mul24(dy, dy);
-    u = (uint32_t)max(pi.z - pj.z, pj.z - pi.z);
+    u = absdiff((uint32_t)pi.z, (uint32_t)pj.z);
   } else {
     const int64_t dx = (int64_t)(pi.x - pj.x), dy = (int64_t)(pi.y - pj.y);
     const uint64_t dd = (uint64_t)(dx * dx + dy * dy);
     d2lo = (uint32_t)dd;
     d2hi = (uint32_t)(dd >> 32);
-    u = (uint32_t)max(pi.z - pj.z, pj.z - pi.z);
+    u = absdiff((uint32_t)pi.z, (uint32_t)pj.z);
   }
   const uint64_t d2 = ((uint64_t)d2hi << 32) | d2lo;
-  // k* = ceil(sqrt(d2) n_s / s_max) exactly (S2[k] = floor(s_k^2), d2 an integer);
-  // the FP32 quotient is within 1e-5 of it, so one comparison on each side of
-  // the estimate restores the exact step.  Same for l* with the T table.
+  // k* = max(1, ceil(sqrt(d2) n_s / s_max)) exactly (S2[k] = floor(s_k^2) and d2
+  // is an integer).  inv_ds carries a factor 1 - 2^-20, larger than the FP32
+  // error of the quotient, so the estimate never exceeds k* and falls short by
+  // at most one: a single comparison with the table restores the exact step.
+  // Same for l* with the T table.
   const float d2f = MODE == kModeWide ? (float)d2 : (float)d2lo;
   int k = (int)__builtin_amdgcn_fmed3f(ceilf(__builtin_amdgcn_sqrtf(d2f) * g.inv_ds), 1.0f,
                                        (float)g.n_s);
   int l = (int)__builtin_amdgcn_fmed3f(ceilf((float)u * g.inv_dt), 1.0f, (float)g.n_t);
-  const int km2 = max(k - 2, 0), lm2 = max(l - 2, 0);
-  // all four table reads are issued together (no short-circuit loads)
-  const uint32_t sa_lo = S2lo[k - 1], sb_lo = S2lo[km2];
-  const uint32_t ta = T[l - 1], tb = T[lm2];
-  bool up_k, dn_k;
-  if (MODE == kModeWide) {
-    const uint64_t s_a = (uint64_t)sa_lo | ((uint64_t)S2hi[k - 1] << 32);
-    const uint64_t s_b = (uint64_t)sb_lo | ((uint64_t)S2hi[km2] << 32);
-    up_k = d2 > s_a;
-    dn_k = (k > 1) & (d2 <= s_b);
-  } else {
-    up_k = d2lo > sa_lo;
-    dn_k = (k > 1) & (d2lo <= sb_lo);
-  }
-  const bool up_l = u > ta, dn_l = (l > 1) & (u <= tb);
-  // the tables increase, so at most one of up/dn holds
-  k += (int)up_k - (int)dn_k;
-  l += (int)up_l - (int)dn_l;
-  const uint32_t bin = (uint32_t)((min(k, g.n_s) - 1) * g.n_t + (min(l, g.n_t) - 1));
+  const uint32_t sk = S2lo[k - 1], tl = T[l - 1];
+  bool up_k;
+  if (MODE == kModeWide)
+    up_k = d2 > ((uint64_t)sk | ((uint64_t)S2hi[k - 1] << 32));
+  else
+    up_k = d2lo > sk;
+  k += (int)up_k;
+  l += (int)(u > tl);
+  const uint32_t bin = __umul24((uint32_t)k, (uint32_t)g.n_t) + (uint32_t)l - (uint32_t)(g.n_t + 1);
   const uint32_t D = (uint32_t)(g.t1 - g.t0);
   const bool tp = (g.edge & 2u) != 0;
   // v = 1/2 when an end of [t-u, t+u] leaves the period: the weight doubles
@@ -287,11 +291,11 @@ __device__ __forceinline__ void drain_a(WaveLds &W, QState &q, uint32_t c, int l
     const unsigned long long m = __builtin_amdgcn_ballot_w64(need) & vmask;
     if (m) {
       const uint32_t pos = lane_rank(m, q.hb + q.nb) & (kQB - 1);
+      q.nb += (uint32_t)__popcll(m);
       if (need && v)
         W.qb[pos] = make_uint4(bin | (hfi << 12) | (hfj << 13) | ((uint32_t)si.slow << 14) |
                                    ((uint32_t)(SYM && sj.slow) << 15),
                                d2lo, (uint32_t)pi.z, (uint32_t)pj.z);
-      q.nb += (uint32_t)__popcll(m);
       if (q.nb >= 64) drain_b<MODE>(W, q, 64, lane, hist + nbins);
     }
   } else {
@@ -303,10 +307,10 @@ __device__ __forceinline__ void drain_a(WaveLds &W, QState &q, uint32_t c, int l
       const unsigned long long m = __builtin_amdgcn_ballot_w64(need) & vmask;
       if (m) {
         const uint32_t pos = lane_rank(m, q.hb + q.nb) & (kQB - 1);
-        if ((m >> lane) & 1ull)
+        q.nb += (uint32_t)__popcll(m);
+        if (need && v)
           W.qb[pos] = make_uint4(w0 | ((side ? hfj : hfi) << 12), d2lo, side ? sj.ex : si.ex,
                                  side ? sj.ey : si.ey);
-        q.nb += (uint32_t)__popcll(m);
         if (q.nb >= 64) drain_b<MODE>(W, q, 64, lane, hist + nbins);
       }
     }
@@ -357,6 +361,7 @@ __device__ __forceinline__ void cand(const int4 me, uint32_t tplus, const int4 p
 
 template <bool SYM, int MODE>
 struct Ctx {
+  const unsigned char *lds;  // start of the workgroup's LDS (byte address 0)
   WaveLds &W;
   QState &q;
   const Geom &g;
@@ -367,7 +372,7 @@ struct Ctx {
 
 template <bool SYM, int MODE>
 __device__ __forceinline__ void drain_oldest(Ctx<SYM, MODE> &x, uint32_t c) {
-  drain_a<SYM, MODE>(x.W, x.q, c, x.lane, x.g, x.hist, x.S2lo, x.S2hi, x.T);
+  drain_a<SYM, MODE>(x.lds, x.W, x.q, c, x.lane, x.g, x.hist, x.S2lo, x.S2hi, x.T);
 }
 
 // One run of consecutive sorted points [j0, j1) against the wave's centres.
@@ -375,7 +380,7 @@ __device__ __forceinline__ void drain_oldest(Ctx<SYM, MODE> &x, uint32_t c) {
 // otherwise).
 template <bool SYM, int MODE, bool HOME>
 __device__ __forceinline__ void scan_run(Ctx<SYM, MODE> &x, uint32_t j0, uint32_t j1,
-                                         const int4 me, uint32_t tplus,
+                                         const int4 me, uint32_t tplus, bool lv,
                                          unsigned long long valid, uint32_t mi,
                                          const int4 *__restrict__ P) {
   QState &q = x.q;
@@ -403,7 +408,11 @@ __device__ __forceinline__ void scan_run(Ctx<SYM, MODE> &x, uint32_t j0, uint32_
       nxt_ok = tn + (uint32_t)lane < j1;
       if (nxt_ok) nxt = P[tn + lane];
     }
-    const uint32_t lane_tag = ((uint32_t)lane << 4) | (sbase << 14);
+    // LDS addresses (16-byte units; LDS < 1 MiB) of this lane's centre and of
+    // the tile's first entry
+    const uint32_t lane_tag =
+        ((uint32_t)((const unsigned char *)&W.cen[lane] - x.lds) >> 4) |
+        (((uint32_t)((const unsigned char *)&W.tile[sbase] - x.lds) >> 4) << 16);
     for (uint32_t jj = 0; jj < nt; jj += 4) {
       int4 pj[4];
 #pragma unroll
@@ -413,13 +422,16 @@ __device__ __forceinline__ void scan_run(Ctx<SYM, MODE> &x, uint32_t j0, uint32_
         bool cs, ct;
         cand<MODE>(me, tplus, pj[u], x.g, cs, ct);
         const uint32_t j = tb + jj + u;
+        const bool hc = HOME ? (SYM ? (j > mi) : (j != mi)) : true;
+        // separate ballots fold into the compare masks; the per-lane predicate
+        // only steers the store
         unsigned long long mask =
             __builtin_amdgcn_ballot_w64(cs) & __builtin_amdgcn_ballot_w64(ct) & valid;
-        if (HOME) mask &= __builtin_amdgcn_ballot_w64(SYM ? (j > mi) : (j != mi));
+        if (HOME) mask &= __builtin_amdgcn_ballot_w64(hc);
         if (mask) {
-          const uint32_t pos = lane_rank(mask, q.ha + q.na) & (kQA - 1);
-          if ((mask >> lane) & 1ull) W.qa[pos] = lane_tag + ((jj + u) << 14);
+          const uint32_t base = q.ha + q.na;
           q.na += (uint32_t)__popcll(mask);
+          if (cs & ct & lv & hc) W.qa[lane_rank(mask, base) & (kQA - 1)] = lane_tag + ((jj + u) << 16);
         }
       }
       while (q.na >= 64) drain_oldest(x, 64);
@@ -507,7 +519,7 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
     const int ct = (int)(rest / (uint32_t)g.ny);
     const uint32_t set_off = (uint32_t)set * g.n_cells;
     QState q = {0u, 0u, 0u, 0u, 0u, 0u, 0u};
-    Ctx<SYM, MODE> x{W, q, g, hist, S2lo, S2hi, T, lane};
+    Ctx<SYM, MODE> x{smem, W, q, g, hist, S2lo, S2hi, T, lane};
     unsigned long long ev = 0;
     for (int dt = SYM ? 0 : -g.rt; dt <= g.rt; ++dt) {
       const int tt = ct + dt;
@@ -529,10 +541,10 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
           } else {
             ev += (unsigned long long)cnt * (j1 - j0) - cnt;
           }
-          scan_run<SYM, MODE, true>(x, j0, j1, me, tplus, vmask, mi, a.P);
+          scan_run<SYM, MODE, true>(x, j0, j1, me, tplus, valid, vmask, mi, a.P);
         } else {
           ev += (unsigned long long)cnt * (j1 - j0);
-          scan_run<SYM, MODE, false>(x, j0, j1, me, tplus, vmask, mi, a.P);
+          scan_run<SYM, MODE, false>(x, j0, j1, me, tplus, valid, vmask, mi, a.P);
         }
       }
     }

@@ -32,8 +32,8 @@ struct Geom {
   int32_t mode;                    // kModePacked / kModeU32 / kModeWide
   uint64_t s2max;                  // S2[n_s-1]
   uint32_t tmax;                   // T[n_t-1]
-  float inv_ds;                    // n_s / s_max
-  float inv_dt;                    // n_t / t_max
+  float inv_ds;                    // n_s / s_max * (1 - 2^-20)
+  float inv_dt;                    // n_t / t_max * (1 - 2^-20)
 };
 
 // Work item of the pair kernel: up to kChunk centres of one cell of one set.

@@ -244,6 +244,44 @@ def test_wide_distances():
     compare(g, r, *args[1:], where="wide")
 
 
+@pytest.mark.parametrize("case", ["packed", "u32"])
+def test_maximum_grid(case):
+    """The largest grids (64 x 64 and 50 x 50 steps): the LDS histogram then
+    fills most of the workgroup's LDS, pushing the per-wave queues and tiles to
+    high addresses.  Symmetric, ordered and simulated sets against the oracle."""
+    rng = np.random.default_rng(21)
+    if case == "packed":
+        win = (0, 0, 30_000, 30_000, 0, 400 * workloads.DAY)
+        args = (win, 3_000, 40 * workloads.DAY, 64, 64)
+    else:
+        win = (0, 0, 100_000, 90_000, 0, 400 * workloads.DAY)
+        args = (win, 15_000, 60 * workloads.DAY, 50, 50)
+    n = 24_000
+    x = rng.integers(win[0], win[2] + 1, n); y = rng.integers(win[1], win[3] + 1, n)
+    t = rng.integers(win[4], win[5] + 1, n)
+    x, y, t = (np.asarray(a, np.int32) for a in (x, y, t))
+    info = ripk.ripk_plan_check(ripk.make_desc(*args, n_max=n))
+    assert info["dist_mode"] == (0 if case == "packed" else 1)
+    say("maximum grid", case, info["n_bins"], "bins")
+    g = gpu_K(x, y, t, *args)
+    r = ref_K(x, y, t, *args)
+    compare(g, r, *args[1:], where="max grid " + case)
+    go = gpu_K(x, y, t, *args, flags=ripk.RIPK_PLAN_ORDERED)
+    assert np.array_equal(go["C"], g["C"]) and np.array_equal(go["W"], g["W"])
+    m, seed = 3, 99
+    plan = ripk.ripk_plan(ripk.make_desc(*args, n_max=n, m_max=m))
+    try:
+        e = ripk.ripk_simulate_envelope(plan, n, m, seed, per_sim=True)
+    finally:
+        plan.destroy()
+    d = oracle.desc(*args)
+    for sim in range(m):
+        xs, ys, ts = oracle.csr_points(d, n, sim, seed)
+        rs = oracle.estimate(d, xs, ys, ts)
+        assert np.array_equal(e["C_sims"][sim], rs["C"].astype(np.uint64)), f"sim {sim} counts"
+        np.testing.assert_allclose(e["K_sims"][sim], rs["K"], rtol=1e-6, atol=0)
+
+
 @pytest.mark.parametrize("edge,norm", [(0, 0), (1, 0), (2, 1), (3, 1)])
 def test_edge_and_norm_switches(edge, norm):
     c = workloads.workload("uniform-2k")

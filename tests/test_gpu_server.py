@@ -41,7 +41,7 @@ def make_requests(count, seed, n_lo=500, n_hi=40_000, m_hi=8):
                                        sigma_t=float(rng.uniform(2, 8)) * DAY))])
         x, y, t = workloads.make_points(cfg)
         reqs.append(dict(window=cfg["window"], s_max=s_max, t_max=t_max,
-                         n_s=int(rng.integers(5, 40)), n_t=int(rng.integers(5, 40)),
+                         n_s=int(rng.integers(5, 65)), n_t=int(rng.integers(5, 65)),
                          m=int(rng.integers(0, m_hi + 1)), seed=(7 << 32) + r, x=x, y=y, t=t))
     return reqs
 
@@ -55,10 +55,12 @@ def plain(q, keep_sims=False):
     plan = ripk.ripk_plan(desc_of(q))
     try:
         r = ripk.ripk_compute_K(plan, q["x"], q["y"], q["t"])
+        r["n_in"] = ripk.ripk_plan_stats(plan)["n_in"]
         if q["m"] > 0:
             e = ripk.ripk_simulate_envelope(plan, len(q["x"]), q["m"], q["seed"], L_obs=r["L"],
                                             per_sim=keep_sims)
             r.update(e)
+            r["n_in"] += ripk.ripk_plan_stats(plan)["n_in"]
     finally:
         plan.destroy()
     return r
@@ -68,6 +70,8 @@ def same(a, b, where):
     for k in a:
         if k in b and isinstance(a[k], np.ndarray):
             assert np.array_equal(a[k], b[k]), f"{where}: {k} differs"
+    if "n_in" in a and "n_in" in b:
+        assert a["n_in"] == b["n_in"], f"{where}: n_in differs"
 
 
 def run_server(reqs, keep_sims=False, **kw):
