@@ -55,12 +55,25 @@ constexpr uint32_t kClampE = 32767u;         // side distances stored in 15 bits
 // LDS image of a point.  PACKED: {x|y<<16 (low 16 bits each), t, ex|ey<<16,
 // min(ex,ey)^2}; U32 / WIDE: {x, y, t, min side distance}.  Coordinates are
 // window relative; ex, ey are the distances to the nearer x and y side.
+// Images are stored as structures of arrays (component c of entry e at
+// f[c][e]): lanes that read different entries hit consecutive banks, and the
+// scan reads one component of four consecutive neighbours in one access.
 struct WaveLds {
-  int4 tile[2 * kJT];  // two tile slots of neighbour points
-  int4 cen[64];        // the wave's centres
-  uint32_t qa[kQA];    // in-range pairs: LDS addresses / 16 of centre | neighbour << 16
+  uint32_t tile[4][2 * kJT];  // two tile slots of neighbour points
+  uint32_t cen[4][64];        // the wave's centres
+  uint32_t qa[kQA + 64];  // in-range pairs: byte offsets in this block, centre | neighbour << 16;
+                          // the 64 extra entries take a push that crosses the ring's end
   uint4 qb[kQB];       // boundary weights, see drain_b
 };
+
+static_assert(sizeof(WaveLds) % 16 == 0, "the histogram after the wave blocks must stay 16-byte aligned");
+constexpr uint32_t kTileStride = 2 * kJT * 4;  // bytes between components of a tile entry
+constexpr uint32_t kCenStride = 64 * 4;        // bytes between components of a centre
+
+__device__ __forceinline__ int4 load_image(const unsigned char *base, uint32_t stride) {
+  return make_int4(*(const int *)base, *(const int *)(base + stride),
+                   *(const int *)(base + 2 * stride), *(const int *)(base + 3 * stride));
+}
 
 struct QState {
   uint32_t ha, na;      // queue A head and length
@@ -154,6 +167,7 @@ __device__ __forceinline__ float omega_f32(uint32_t ex, uint32_t ey, uint32_t d2
 //   PACKED: one per pair, {bin | half_i<<12 | half_j<<13 | slow_i<<14 | slow_j<<15,
 //           d2, ex_i|ey_i<<16, ex_j|ey_j<<16}: both sides' weights in one pass;
 //   U32 / WIDE: one per side, {bin | half<<12 | d2 hi<<13, d2 lo, ex, ey}.
+// The weight goes to the bin's weight word hw[bin].
 __device__ __forceinline__ uint32_t qweight(float om, uint32_t half) {
   // w = 1/omega >= 1 has at most 23 fraction bits: w * 2^23 is an exact integer;
   // the reciprocal is within an ulp, well inside the error budget
@@ -176,8 +190,8 @@ __device__ __forceinline__ void drain_b(WaveLds &W, QState &q, uint32_t c, int l
     qv = (((r.x >> 14) & 1u) ? qweight(oi, (r.x >> 12) & 1u) : 0u) +
          (((r.x >> 15) & 1u) ? qweight(oj, (r.x >> 13) & 1u) : 0u);
   } else {
-    const uint64_t d2 = (uint64_t)r.y | ((uint64_t)(r.x >> 13) << 32);
-    qv = qweight(omega_f32(r.z, r.w, d2), (r.x >> 12) & 1u);
+    qv = qweight(omega_f32(r.z, r.w, (uint64_t)r.y | ((uint64_t)(r.x >> 13) << 32)),
+                 (r.x >> 12) & 1u);
   }
   if ((uint32_t)lane < c) atomicAdd(&hw[bin], (unsigned long long)qv);
   q.hb = (q.hb + c) & (kQB - 1);
@@ -186,7 +200,9 @@ __device__ __forceinline__ void drain_b(WaveLds &W, QState &q, uint32_t c, int l
 
 struct Side {
   uint32_t T, ex, ey;
-  bool slow;  // the circle of radius d crosses the study boundary
+  bool slow;  // the circle of radius d crosses the study boundary (never true
+              // without spatial correction: the image's interior bound is then
+              // out of reach)
 };
 
 template <int MODE>
@@ -203,7 +219,6 @@ __device__ __forceinline__ Side side_of(const int4 p, uint32_t d2lo, uint64_t d2
     s.ey = (uint32_t)min(p.y, g.y1 - g.y0 - p.y);
     s.slow = d2 > (uint64_t)(uint32_t)p.w * (uint32_t)p.w;
   }
-  s.slow = s.slow && (g.edge & 1u);
   return s;
 }
 
@@ -212,7 +227,7 @@ __device__ __forceinline__ Side side_of(const int4 p, uint32_t d2lo, uint64_t d2
 // fast path of omega are evaluated without branches on per-lane data (lanes
 // past c compute on entry 0 and store nothing); boundary sides go to queue B.
 template <bool SYM, int MODE>
-__device__ __forceinline__ void drain_a(const unsigned char *lds, WaveLds &W, QState &q,
+__device__ __forceinline__ void drain_a(WaveLds &W, QState &q,
                                         uint32_t c, int lane, const Geom &g,
                                         unsigned long long *hist, const uint32_t *S2lo,
                                         const uint32_t *S2hi, const uint32_t *T) {
@@ -221,12 +236,13 @@ __device__ __forceinline__ void drain_a(const unsigned char *lds, WaveLds &W, QS
   wave_sync();
   const bool v = (uint32_t)lane < c;
   const unsigned long long vmask = c >= 64 ? ~0ull : ((1ull << c) - 1ull);
-  // a tag holds the LDS addresses, in 16-byte units, of the centre (low half)
-  // and of the neighbour (high half); lanes past c read address 0 and store
-  // nothing
+  // a tag holds the byte offsets, within the wave's LDS block, of the centre
+  // (low half) and of the neighbour (high half); lanes past c read offset 0
+  // and store nothing
   const uint32_t tag = v ? tag0 : 0u;
-  const int4 pi = *(const int4 *)(lds + ((tag & 0xFFFFu) << 4));
-  const int4 pj = *(const int4 *)(lds + ((tag >> 16) << 4));
+  const unsigned char *wb = (const unsigned char *)&W;
+  const int4 pi = load_image(wb + (tag & 0xFFFFu), kCenStride);
+  const int4 pj = load_image(wb + (tag >> 16), kTileStride);
   uint32_t d2lo, d2hi = 0, u;
   if (MODE == kModePacked) {
     typedef short s2 __attribute__((ext_vector_type(2)));
@@ -245,38 +261,39 @@ __device__ __forceinline__ void drain_a(const unsigned char *lds, WaveLds &W, QS
     u = absdiff((uint32_t)pi.z, (uint32_t)pj.z);
   }
   const uint64_t d2 = ((uint64_t)d2hi << 32) | d2lo;
-  // k* = max(1, ceil(sqrt(d2) n_s / s_max)) exactly (S2[k] = floor(s_k^2) and d2
-  // is an integer).  inv_ds carries a factor 1 - 2^-20, larger than the FP32
-  // error of the quotient, so the estimate never exceeds k* and falls short by
-  // at most one: a single comparison with the table restores the exact step.
-  // Same for l* with the T table.
+  // The step k* = max(1, ceil(x)), x = sqrt(d2) n_s / s_max, is exact in the
+  // tables (S2[k] = floor(s_k^2) and d2 is an integer).  inv_ds carries a
+  // factor 1 - 2^-20, larger than the FP32 error of the quotient, so x' < x
+  // whenever x > 0 and trunc(x') + 1 is k* or k* - 1: one comparison with the
+  // table restores the exact step.  Same for l* with the T table.  kk, ll are
+  // the 0-based steps.
   const float d2f = MODE == kModeWide ? (float)d2 : (float)d2lo;
-  int k = (int)__builtin_amdgcn_fmed3f(ceilf(__builtin_amdgcn_sqrtf(d2f) * g.inv_ds), 1.0f,
-                                       (float)g.n_s);
-  int l = (int)__builtin_amdgcn_fmed3f(ceilf((float)u * g.inv_dt), 1.0f, (float)g.n_t);
-  const uint32_t sk = S2lo[k - 1], tl = T[l - 1];
+  const uint32_t k0 = (uint32_t)(__builtin_amdgcn_sqrtf(d2f) * g.inv_ds);
+  const uint32_t l0 = (uint32_t)((float)u * g.inv_dt);
+  const uint32_t sk = S2lo[k0], tl = T[l0];
   bool up_k;
   if (MODE == kModeWide)
-    up_k = d2 > ((uint64_t)sk | ((uint64_t)S2hi[k - 1] << 32));
+    up_k = d2 > ((uint64_t)sk | ((uint64_t)S2hi[k0] << 32));
   else
     up_k = d2lo > sk;
-  k += (int)up_k;
-  l += (int)(u > tl);
-  const uint32_t bin = __umul24((uint32_t)k, (uint32_t)g.n_t) + (uint32_t)l - (uint32_t)(g.n_t + 1);
+  const uint32_t kk = k0 + (uint32_t)up_k, ll = l0 + (uint32_t)(u > tl);
+  const uint32_t bin = __umul24(kk, (uint32_t)g.n_t) + ll;
   const uint32_t D = (uint32_t)(g.t1 - g.t0);
   const bool tp = (g.edge & 2u) != 0;
   // v = 1/2 when an end of [t-u, t+u] leaves the period: the weight doubles
   const Side si = side_of<MODE>(pi, d2lo, d2, g);
   const uint32_t hfi = (tp && u > min(si.T, D - si.T)) ? 1u : 0u;
-  uint32_t qsum = si.slow ? 0u : (1u << (kFracBits + hfi));
+  uint32_t qsum = si.slow ? 0u : (hfi ? (2u << kFracBits) : (1u << kFracBits));
   Side sj = si;
   sj.slow = false;
   uint32_t hfj = 0;
   if (SYM) {
     sj = side_of<MODE>(pj, d2lo, d2, g);
     hfj = (tp && u > min(sj.T, D - sj.T)) ? 1u : 0u;
-    qsum += sj.slow ? 0u : (1u << (kFracBits + hfj));
+    qsum += sj.slow ? 0u : (hfj ? (2u << kFracBits) : (1u << kFracBits));
   }
+  // counts hist[bin], weights hist[nbins + bin]: separate arrays keep the
+  // 64 lanes' atomics spread over all LDS banks
   const uint32_t nbins = (uint32_t)(g.n_s * g.n_t);
   if (v) {
     atomicAdd(&hist[bin], SYM ? 2ull : 1ull);
@@ -288,7 +305,9 @@ __device__ __forceinline__ void drain_a(const unsigned char *lds, WaveLds &W, QS
   if (MODE == kModePacked) {
     // one record per pair with a boundary side
     const bool need = si.slow || sj.slow;
-    const unsigned long long m = __builtin_amdgcn_ballot_w64(need) & vmask;
+    // separate ballots fold into the compare masks
+    const unsigned long long m =
+        (__builtin_amdgcn_ballot_w64(si.slow) | __builtin_amdgcn_ballot_w64(sj.slow)) & vmask;
     if (m) {
       const uint32_t pos = lane_rank(m, q.hb + q.nb) & (kQB - 1);
       q.nb += (uint32_t)__popcll(m);
@@ -317,17 +336,20 @@ __device__ __forceinline__ void drain_a(const unsigned char *lds, WaveLds &W, QS
   }
 }
 
-// LDS image of a sorted point (see WaveLds).
+// LDS image of a sorted point (see WaveLds).  Without spatial correction the
+// interior bound (min(ex,ey)^2, or the side distance) is set to 2^32 - 1 so
+// that no pair takes the boundary path.
 template <int MODE>
 __device__ __forceinline__ int4 image(const int4 p, const Geom &g) {
+  const bool iso = (g.edge & 1u) != 0;
   if (MODE == kModePacked) {
     const uint32_t ex = min((uint32_t)min(p.x, g.x1 - g.x0 - p.x), kClampE);
     const uint32_t ey = min((uint32_t)min(p.y, g.y1 - g.y0 - p.y), kClampE);
     const uint32_t e = min(ex, ey);
     return make_int4((int)(((uint32_t)p.x & 0xFFFFu) | ((uint32_t)p.y << 16)), p.z,
-                     (int)(ex | (ey << 16)), (int)(e * e));
+                     (int)(ex | (ey << 16)), iso ? (int)(e * e) : -1);
   }
-  return p;
+  return make_int4(p.x, p.y, p.z, iso ? p.w : -1);
 }
 
 template <int MODE>
@@ -361,7 +383,6 @@ __device__ __forceinline__ void cand(const int4 me, uint32_t tplus, const int4 p
 
 template <bool SYM, int MODE>
 struct Ctx {
-  const unsigned char *lds;  // start of the workgroup's LDS (byte address 0)
   WaveLds &W;
   QState &q;
   const Geom &g;
@@ -372,7 +393,7 @@ struct Ctx {
 
 template <bool SYM, int MODE>
 __device__ __forceinline__ void drain_oldest(Ctx<SYM, MODE> &x, uint32_t c) {
-  drain_a<SYM, MODE>(x.lds, x.W, x.q, c, x.lane, x.g, x.hist, x.S2lo, x.S2hi, x.T);
+  drain_a<SYM, MODE>(x.W, x.q, c, x.lane, x.g, x.hist, x.S2lo, x.S2hi, x.T);
 }
 
 // One run of consecutive sorted points [j0, j1) against the wave's centres.
@@ -401,22 +422,39 @@ __device__ __forceinline__ void scan_run(Ctx<SYM, MODE> &x, uint32_t j0, uint32_
     q.prev_mark = q.drained + q.na;
     const uint32_t sbase = q.slot * kJT;
     wave_sync();
-    W.tile[sbase + lane] = nxt_ok ? image<MODE>(nxt, x.g) : far_image<MODE>();
+    {
+      const int4 im = nxt_ok ? image<MODE>(nxt, x.g) : far_image<MODE>();
+      W.tile[0][sbase + lane] = (uint32_t)im.x;
+      W.tile[1][sbase + lane] = (uint32_t)im.y;
+      W.tile[2][sbase + lane] = (uint32_t)im.z;
+      W.tile[3][sbase + lane] = (uint32_t)im.w;
+    }
     wave_sync();
     const uint32_t tn = tb + kJT;
     if (tn < j1) {
       nxt_ok = tn + (uint32_t)lane < j1;
       if (nxt_ok) nxt = P[tn + lane];
     }
-    // LDS addresses (16-byte units; LDS < 1 MiB) of this lane's centre and of
+    // byte offsets, within the wave's LDS block, of this lane's centre and of
     // the tile's first entry
     const uint32_t lane_tag =
-        ((uint32_t)((const unsigned char *)&W.cen[lane] - x.lds) >> 4) |
-        (((uint32_t)((const unsigned char *)&W.tile[sbase] - x.lds) >> 4) << 16);
+        (uint32_t)((const unsigned char *)&W.cen[0][lane] - (const unsigned char *)&W) |
+        ((uint32_t)((const unsigned char *)&W.tile[0][sbase] - (const unsigned char *)&W) << 16);
     for (uint32_t jj = 0; jj < nt; jj += 4) {
       int4 pj[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) pj[u] = W.tile[sbase + jj + u];
+      for (int u = 0; u < 4; ++u) pj[u] = make_int4(0, 0, 0, 0);
+      {
+        // components the candidate test needs, four neighbours per access
+        const uint4 c0 = *(const uint4 *)&W.tile[0][sbase + jj];
+        const uint4 c1 = *(const uint4 *)&W.tile[1][sbase + jj];
+        pj[0].x = (int)c0.x; pj[1].x = (int)c0.y; pj[2].x = (int)c0.z; pj[3].x = (int)c0.w;
+        pj[0].y = (int)c1.x; pj[1].y = (int)c1.y; pj[2].y = (int)c1.z; pj[3].y = (int)c1.w;
+        if (MODE != kModePacked) {
+          const uint4 c2 = *(const uint4 *)&W.tile[2][sbase + jj];
+          pj[0].z = (int)c2.x; pj[1].z = (int)c2.y; pj[2].z = (int)c2.z; pj[3].z = (int)c2.w;
+        }
+      }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         bool cs, ct;
@@ -429,9 +467,17 @@ __device__ __forceinline__ void scan_run(Ctx<SYM, MODE> &x, uint32_t j0, uint32_
             __builtin_amdgcn_ballot_w64(cs) & __builtin_amdgcn_ballot_w64(ct) & valid;
         if (HOME) mask &= __builtin_amdgcn_ballot_w64(hc);
         if (mask) {
-          const uint32_t base = q.ha + q.na;
-          q.na += (uint32_t)__popcll(mask);
-          if (cs & ct & lv & hc) W.qa[lane_rank(mask, base) & (kQA - 1)] = lane_tag + ((jj + u) << 16);
+          const uint32_t base = (q.ha + q.na) & (kQA - 1);
+          const uint32_t cnt = (uint32_t)__popcll(mask);
+          q.na += cnt;
+          if (cs & ct & lv & hc) W.qa[base + lane_rank(mask, 0)] = lane_tag + ((jj + u) << 18);
+          if (base + cnt > kQA) {
+            // the push ran past the ring's end: move the overflow to its start
+            // (those slots were drained long ago: at most 64 + 4*64 pending)
+            wave_sync();
+            if ((uint32_t)lane < base + cnt - kQA) W.qa[lane] = W.qa[kQA + lane];
+            wave_sync();
+          }
         }
       }
       while (q.na >= 64) drain_oldest(x, 64);
@@ -444,21 +490,19 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const Geom &g = a.g;
   const int NB = g.n_s * g.n_t;
-  // counts [0, NB), fixed-point weights [NB, 2 NB)
-  unsigned long long *hist = (unsigned long long *)smem;
+  // LDS: the waves' blocks first (fixed offsets), then the counts [0, NB) and
+  // fixed-point weights [NB, 2 NB), the threshold tables and two scalars
+  WaveLds *wl = (WaveLds *)smem;
+  unsigned long long *hist = (unsigned long long *)(wl + kWaves);
   uint32_t *S2lo = (uint32_t *)(hist + 2 * NB);
   uint32_t *S2hi = S2lo + kMaxSteps;
   uint32_t *T = S2hi + kMaxSteps;
-  WaveLds *wl = (WaveLds *)(T + kMaxSteps + 64);
-  unsigned long long *evals_lds = (unsigned long long *)(wl + kWaves);
+  unsigned long long *evals_lds = (unsigned long long *)(T + kMaxSteps + 64);
   uint32_t *grp_lds = (uint32_t *)(evals_lds + 1);
 
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wv = (int)uni((uint32_t)tid >> 6);
   WaveLds &W = wl[wv];
-  for (int b = tid; b < NB; b += kPairThreads) {
-    hist[b] = 0;
-    hist[NB + b] = 0;
-  }
+  for (int b = tid; b < 2 * NB; b += kPairThreads) hist[b] = 0;
   if (tid < g.n_s) {
     S2lo[tid] = (uint32_t)a.S2[tid];
     S2hi[tid] = (uint32_t)(a.S2[tid] >> 32);
@@ -511,7 +555,10 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
     const int4 raw = valid ? a.P[mi] : make_int4(0, 0, 0, 0);
     const int4 me = image<MODE>(raw, g);
     const uint32_t tplus = (uint32_t)(MODE == kModePacked ? me.y : me.z) + g.tmax;
-    W.cen[lane] = me;
+    W.cen[0][lane] = (uint32_t)me.x;
+    W.cen[1][lane] = (uint32_t)me.y;
+    W.cen[2][lane] = (uint32_t)me.z;
+    W.cen[3][lane] = (uint32_t)me.w;
     wave_sync();
     const int cx = (int)(cell % (uint32_t)g.nx);
     const uint32_t rest = cell / (uint32_t)g.nx;
@@ -519,7 +566,7 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
     const int ct = (int)(rest / (uint32_t)g.ny);
     const uint32_t set_off = (uint32_t)set * g.n_cells;
     QState q = {0u, 0u, 0u, 0u, 0u, 0u, 0u};
-    Ctx<SYM, MODE> x{smem, W, q, g, hist, S2lo, S2hi, T, lane};
+    Ctx<SYM, MODE> x{W, q, g, hist, S2lo, S2hi, T, lane};
     unsigned long long ev = 0;
     for (int dt = SYM ? 0 : -g.rt; dt <= g.rt; ++dt) {
       const int tt = ct + dt;
