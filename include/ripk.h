@@ -68,6 +68,9 @@ enum {
                                     /* every point is a centre; default: each unordered */
                                     /* pair once, both weights added                    */
 #define RIPK_PLAN_TIMING (1u << 1)  /* record per-phase device timings for stats         */
+#define RIPK_PLAN_WIDE_COUNTS (1u << 2) /* 64-bit pair counters in the pair kernel's     */
+                                        /* workgroup histograms (automatic for sets of  */
+                                        /* 2^23 points or more; results are identical)  */
 
 /*
  * Problem statement (the job parameters of Sec. 4.1 and the GUI of Sec. 5:

@@ -314,8 +314,9 @@ ripk_status run_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_centres,
   a.binW = p->binW;
   a.n_eval = p->scal;
   a.symmetric = symmetric ? 1 : 0;
+  a.wide_counts = ((int64_t)n >= kWideCountPoints || (p->desc.flags & RIPK_PLAN_WIDE_COUNTS)) ? 1 : 0;
   int per_cu = 0;
-  HIPCHK(pair_occupancy((int)NB, a.symmetric, g.mode, &per_cu));
+  HIPCHK(pair_occupancy((int)NB, a.wide_counts, a.symmetric, g.mode, &per_cu));
   if (per_cu < 1) return fail(RIPK_EINVAL, "pair kernel does not fit on a compute unit (n_bins=%u)", NB);
   const int64_t groups_cap = ((int64_t)S * (n / kChunk + g.n_cells + kItemsPerGroup)) / kItemsPerGroup + 1;
   const int grid = (int)std::min<int64_t>((int64_t)per_cu * p->cus, groups_cap);
@@ -437,7 +438,8 @@ ripk_status plan_bind(ripk_plan_s *p, const ripk_plan_desc *desc, hipStream_t st
   if (s != RIPK_OK) return s;
   if (desc->device != p->device) return fail(RIPK_EINVAL, "descriptor device differs from the plan's");
   if (!caps_fit(p->caps, L.caps)) return fail(RIPK_E2BIG, "descriptor exceeds the plan's capacity");
-  const int lds = pair_lds_bytes(L.info.n_bins);
+  const int lds = pair_lds_bytes(
+      L.info.n_bins, desc->n_max >= kWideCountPoints || (desc->flags & RIPK_PLAN_WIDE_COUNTS));
   if ((size_t)lds > p->lds_max)
     return fail(RIPK_EINVAL, "grid of %d bins needs %d B of LDS per workgroup, device has %zu",
                 L.info.n_bins, lds, p->lds_max);

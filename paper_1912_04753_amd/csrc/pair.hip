@@ -45,10 +45,15 @@ namespace ripk {
 namespace {
 
 constexpr int kJT = 64;     // points per tile slot (two slots per wave)
-constexpr int kQA = 512;    // ring of queue A tags: < 64 + 4*64 pending between drains
+constexpr uint32_t kQA = 320;  // ring of queue A tags: at most 63 + 4*64 pending between drains
 constexpr int kQB = 128;    // ring of queue B records: < 64 + 64 pending between drains
 constexpr int kWaves = kPairThreads / 64;
-constexpr unsigned long long kFlushEvals = 1ull << 34;  // bound on candidates between flushes
+// Bound on the candidates a workgroup evaluates between histogram flushes
+// (checked before each group of items).  Counts are 32-bit words holding pairs
+// (not doubled in symmetric mode), so a bin stays below 2^31 + (one group's
+// candidates) < 2^32 when a set has fewer than 2^23 points; larger sets use
+// 64-bit count words.
+constexpr unsigned long long kFlushEvals = 1ull << 31;
 constexpr uint32_t kFarTime = 0xC0000000u;  // tile padding: fails every time test
 constexpr uint32_t kClampE = 32767u;         // side distances stored in 15 bits (PACKED)
 
@@ -229,10 +234,12 @@ __device__ __forceinline__ Side side_of(const int4 p, uint32_t d2lo, uint64_t d2
 template <bool SYM, int MODE>
 __device__ __forceinline__ void drain_a(WaveLds &W, QState &q,
                                         uint32_t c, int lane, const Geom &g,
-                                        unsigned long long *hist, const uint32_t *S2lo,
+                                        unsigned long long *hist, uint32_t *histc,
+                                        bool wide_counts, const uint32_t *S2lo,
                                         const uint32_t *S2hi, const uint32_t *T) {
   wave_sync();
-  const uint32_t tag0 = W.qa[(q.ha + lane) & (kQA - 1)];
+  const uint32_t ia = q.ha + (uint32_t)lane;
+  const uint32_t tag0 = W.qa[min(ia, ia - kQA)];  // ring position (q.ha < kQA)
   wave_sync();
   const bool v = (uint32_t)lane < c;
   const unsigned long long vmask = c >= 64 ? ~0ull : ((1ull << c) - 1ull);
@@ -292,14 +299,17 @@ __device__ __forceinline__ void drain_a(WaveLds &W, QState &q,
     hfj = (tp && u > min(sj.T, D - sj.T)) ? 1u : 0u;
     qsum += sj.slow ? 0u : (hfj ? (2u << kFracBits) : (1u << kFracBits));
   }
-  // counts hist[bin], weights hist[nbins + bin]: separate arrays keep the
-  // 64 lanes' atomics spread over all LDS banks
-  const uint32_t nbins = (uint32_t)(g.n_s * g.n_t);
+  // weights hist[bin], pair counts in a separate array (32-bit words unless
+  // the set is large): separate arrays keep the 64 lanes' atomics spread over
+  // all LDS banks
   if (v) {
-    atomicAdd(&hist[bin], SYM ? 2ull : 1ull);
-    atomicAdd(&hist[nbins + bin], (unsigned long long)qsum);
+    atomicAdd(&hist[bin], (unsigned long long)qsum);
+    if (wide_counts)
+      atomicAdd((unsigned long long *)histc + bin, 1ull);
+    else
+      atomicAdd(histc + bin, 1u);
   }
-  q.ha = (q.ha + c) & (kQA - 1);
+  q.ha = q.ha + c >= kQA ? q.ha + c - kQA : q.ha + c;
   q.na -= c;
   q.drained += c;
   if (MODE == kModePacked) {
@@ -315,7 +325,7 @@ __device__ __forceinline__ void drain_a(WaveLds &W, QState &q,
         W.qb[pos] = make_uint4(bin | (hfi << 12) | (hfj << 13) | ((uint32_t)si.slow << 14) |
                                    ((uint32_t)(SYM && sj.slow) << 15),
                                d2lo, (uint32_t)pi.z, (uint32_t)pj.z);
-      if (q.nb >= 64) drain_b<MODE>(W, q, 64, lane, hist + nbins);
+      if (q.nb >= 64) drain_b<MODE>(W, q, 64, lane, hist);
     }
   } else {
     // one record per boundary side, one side per pass through a single drain site
@@ -330,7 +340,7 @@ __device__ __forceinline__ void drain_a(WaveLds &W, QState &q,
         if (need && v)
           W.qb[pos] = make_uint4(w0 | ((side ? hfj : hfi) << 12), d2lo, side ? sj.ex : si.ex,
                                  side ? sj.ey : si.ey);
-        if (q.nb >= 64) drain_b<MODE>(W, q, 64, lane, hist + nbins);
+        if (q.nb >= 64) drain_b<MODE>(W, q, 64, lane, hist);
       }
     }
   }
@@ -386,14 +396,17 @@ struct Ctx {
   WaveLds &W;
   QState &q;
   const Geom &g;
-  unsigned long long *hist;
+  unsigned long long *hist;  // fixed-point weights per bin
+  uint32_t *histc;           // pair counts per bin (32- or 64-bit words)
+  bool wide_counts;
   const uint32_t *S2lo, *S2hi, *T;
   int lane;
 };
 
 template <bool SYM, int MODE>
 __device__ __forceinline__ void drain_oldest(Ctx<SYM, MODE> &x, uint32_t c) {
-  drain_a<SYM, MODE>(x.W, x.q, c, x.lane, x.g, x.hist, x.S2lo, x.S2hi, x.T);
+  drain_a<SYM, MODE>(x.W, x.q, c, x.lane, x.g, x.hist, x.histc, x.wide_counts, x.S2lo, x.S2hi,
+                     x.T);
 }
 
 // One run of consecutive sorted points [j0, j1) against the wave's centres.
@@ -467,13 +480,14 @@ __device__ __forceinline__ void scan_run(Ctx<SYM, MODE> &x, uint32_t j0, uint32_
             __builtin_amdgcn_ballot_w64(cs) & __builtin_amdgcn_ballot_w64(ct) & valid;
         if (HOME) mask &= __builtin_amdgcn_ballot_w64(hc);
         if (mask) {
-          const uint32_t base = (q.ha + q.na) & (kQA - 1);
+          const uint32_t tail = q.ha + q.na;
+          const uint32_t base = tail >= kQA ? tail - kQA : tail;
           const uint32_t cnt = (uint32_t)__popcll(mask);
           q.na += cnt;
           if (cs & ct & lv & hc) W.qa[base + lane_rank(mask, 0)] = lane_tag + ((jj + u) << 18);
           if (base + cnt > kQA) {
             // the push ran past the ring's end: move the overflow to its start
-            // (those slots were drained long ago: at most 64 + 4*64 pending)
+            // (those slots were drained: at most 63 + 4*64 < kQA are pending)
             wave_sync();
             if ((uint32_t)lane < base + cnt - kQA) W.qa[lane] = W.qa[kQA + lane];
             wave_sync();
@@ -490,19 +504,24 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const Geom &g = a.g;
   const int NB = g.n_s * g.n_t;
-  // LDS: the waves' blocks first (fixed offsets), then the counts [0, NB) and
-  // fixed-point weights [NB, 2 NB), the threshold tables and two scalars
+  // LDS: the waves' blocks first (fixed offsets), then the fixed-point
+  // weights, the pair counts (32- or 64-bit words, padded to 16 bytes), the
+  // threshold tables and two scalars (layout in pair_lds_bytes)
+  const bool wide = a.wide_counts != 0;
   WaveLds *wl = (WaveLds *)smem;
   unsigned long long *hist = (unsigned long long *)(wl + kWaves);
-  uint32_t *S2lo = (uint32_t *)(hist + 2 * NB);
+  uint32_t *histc = (uint32_t *)(hist + NB);
+  const int nc_words = ((wide ? 2 * NB : NB) + 3) & ~3;
+  uint32_t *S2lo = histc + nc_words;
   uint32_t *S2hi = S2lo + kMaxSteps;
   uint32_t *T = S2hi + kMaxSteps;
-  unsigned long long *evals_lds = (unsigned long long *)(T + kMaxSteps + 64);
+  unsigned long long *evals_lds = (unsigned long long *)(T + kMaxSteps);
   uint32_t *grp_lds = (uint32_t *)(evals_lds + 1);
 
   const int tid = threadIdx.x, lane = tid & 63, wv = (int)uni((uint32_t)tid >> 6);
   WaveLds &W = wl[wv];
-  for (int b = tid; b < 2 * NB; b += kPairThreads) hist[b] = 0;
+  for (int b = tid; b < NB; b += kPairThreads) hist[b] = 0;
+  for (int b = tid; b < nc_words; b += kPairThreads) histc[b] = 0;
   if (tid < g.n_s) {
     S2lo[tid] = (uint32_t)a.S2[tid];
     S2hi[tid] = (uint32_t)(a.S2[tid] >> 32);
@@ -515,15 +534,19 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
 
   auto flush = [&](int set) {
     for (int b = tid; b < NB; b += kPairThreads) {
-      const unsigned long long c = hist[b];
+      const unsigned long long c =
+          (wide ? ((unsigned long long *)histc)[b] : (unsigned long long)histc[b]) * (SYM ? 2ull : 1ull);
       if (c) {
-        const unsigned long long w = hist[NB + b];
+        const unsigned long long w = hist[b];
         const size_t o = (size_t)set * NB + b;
         atomicAdd(&a.binC[o], c);
         const unsigned long long old = atomicAdd(&a.binW[2 * o], w);
         if (old + w < old) atomicAdd(&a.binW[2 * o + 1], 1ull);
         hist[b] = 0;
-        hist[NB + b] = 0;
+        if (wide)
+          ((unsigned long long *)histc)[b] = 0;
+        else
+          histc[b] = 0;
       }
     }
   };
@@ -566,7 +589,7 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
     const int ct = (int)(rest / (uint32_t)g.ny);
     const uint32_t set_off = (uint32_t)set * g.n_cells;
     QState q = {0u, 0u, 0u, 0u, 0u, 0u, 0u};
-    Ctx<SYM, MODE> x{W, q, g, hist, S2lo, S2hi, T, lane};
+    Ctx<SYM, MODE> x{W, q, g, hist, histc, wide, S2lo, S2hi, T, lane};
     unsigned long long ev = 0;
     for (int dt = SYM ? 0 : -g.rt; dt <= g.rt; ++dt) {
       const int tt = ct + dt;
@@ -596,7 +619,7 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
       }
     }
     if (q.na) drain_oldest(x, q.na);
-    if (q.nb) drain_b<MODE>(W, q, q.nb, lane, hist + NB);
+    if (q.nb) drain_b<MODE>(W, q, q.nb, lane, hist);
     if (lane == 0) atomicAdd(evals_lds, ev);
     evals_total += ev;
   }
@@ -606,7 +629,7 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
 
 template <bool SYM, int MODE>
 hipError_t launch_t(const PairArgs &a, int grid, hipStream_t s) {
-  const int lds = pair_lds_bytes(a.g.n_s * a.g.n_t);
+  const int lds = pair_lds_bytes(a.g.n_s * a.g.n_t, a.wide_counts);
   hipLaunchKernelGGL((k_pair<SYM, MODE>), dim3(grid), dim3(kPairThreads), lds, s, a);
   return hipGetLastError();
 }
@@ -633,12 +656,13 @@ hipError_t launch_mode(const PairArgs &a, int grid, hipStream_t s) {
 
 }  // namespace
 
-int pair_lds_bytes(int n_bins) {
-  return 16 * n_bins + 4 * (3 * kMaxSteps + 64) + (int)sizeof(WaveLds) * kWaves + 16;
+int pair_lds_bytes(int n_bins, int wide_counts) {
+  const int nc_words = ((wide_counts ? 2 * n_bins : n_bins) + 3) & ~3;
+  return (int)sizeof(WaveLds) * kWaves + 8 * n_bins + 4 * nc_words + 4 * 3 * kMaxSteps + 16;
 }
 
-hipError_t pair_occupancy(int n_bins, int symmetric, int mode, int *per_cu) {
-  const int lds = pair_lds_bytes(n_bins);
+hipError_t pair_occupancy(int n_bins, int wide_counts, int symmetric, int mode, int *per_cu) {
+  const int lds = pair_lds_bytes(n_bins, wide_counts);
   return symmetric ? occ_mode<true>(mode, lds, per_cu) : occ_mode<false>(mode, lds, per_cu);
 }
 

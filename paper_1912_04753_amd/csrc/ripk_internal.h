@@ -57,6 +57,7 @@ struct PairArgs {
   unsigned long long *binW;  // [sets][n_bins][2] 128-bit fixed-point weight sums
   unsigned long long *n_eval;  // device scalar
   int symmetric;
+  int wide_counts;             // 64-bit LDS pair counts (sets of 2^23 points or more)
 };
 
 // ---- host runtime (api.cpp) -------------------------------------------------
@@ -105,8 +106,10 @@ hipError_t launch_items(const uint32_t *cs, uint32_t n_sets, const Geom &g, uint
 hipError_t launch_fill_u64(unsigned long long *p, size_t n, unsigned long long v,
                            hipStream_t s);
 hipError_t launch_pair(const PairArgs &a, int grid, hipStream_t s);
-int pair_lds_bytes(int n_bins);
-hipError_t pair_occupancy(int n_bins, int symmetric, int mode, int *per_cu);
+int pair_lds_bytes(int n_bins, int wide_counts);
+hipError_t pair_occupancy(int n_bins, int wide_counts, int symmetric, int mode, int *per_cu);
+// 64-bit LDS pair counts are needed from this many points per set on
+constexpr int64_t kWideCountPoints = 1 << 23;
 hipError_t launch_finalize(unsigned long long *binC, unsigned long long *binW,
                            uint32_t n_sets, int n_s, int n_t, double s_max, double t_max,
                            double AD, double N, unsigned long long *C, double *W, double *K,

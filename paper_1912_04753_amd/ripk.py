@@ -35,6 +35,7 @@ RIPK_NORM_N2 = 1
 RIPK_SIM_CSR = 0
 RIPK_PLAN_ORDERED = 1
 RIPK_PLAN_TIMING = 2
+RIPK_PLAN_WIDE_COUNTS = 4
 RIPK_REQ_KEEP_SIMS = 1
 
 _i64, _i32, _u32, _u64, _f64 = (ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32,

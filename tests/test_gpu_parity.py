@@ -227,6 +227,8 @@ def test_edge_case_sets(case):
     compare(g, r, args[1], args[2], args[3], args[4], where=case)
     go = gpu_K(x, y, t, *args, flags=ripk.RIPK_PLAN_ORDERED)
     assert np.array_equal(go["C"], g["C"]) and np.array_equal(go["W"], g["W"])
+    gw = gpu_K(x, y, t, *args, flags=ripk.RIPK_PLAN_WIDE_COUNTS | ripk.RIPK_PLAN_ORDERED)
+    assert np.array_equal(gw["C"], g["C"]) and np.array_equal(gw["W"], g["W"])
 
 
 def test_wide_distances():
@@ -268,6 +270,8 @@ def test_maximum_grid(case):
     compare(g, r, *args[1:], where="max grid " + case)
     go = gpu_K(x, y, t, *args, flags=ripk.RIPK_PLAN_ORDERED)
     assert np.array_equal(go["C"], g["C"]) and np.array_equal(go["W"], g["W"])
+    gw = gpu_K(x, y, t, *args, flags=ripk.RIPK_PLAN_WIDE_COUNTS)
+    assert np.array_equal(gw["C"], g["C"]) and np.array_equal(gw["W"], g["W"])
     m, seed = 3, 99
     plan = ripk.ripk_plan(ripk.make_desc(*args, n_max=n, m_max=m))
     try:
