@@ -71,6 +71,12 @@ enum {
 #define RIPK_PLAN_WIDE_COUNTS (1u << 2) /* 64-bit pair counters in the pair kernel's     */
                                         /* workgroup histograms (automatic for sets of  */
                                         /* 2^23 points or more; results are identical)  */
+#define RIPK_PLAN_AUTOTUNE (1u << 3)    /* pick the cell grid by timing: the first      */
+                                        /* ripk_compute_K times each candidate cell     */
+                                        /* subdivision on its own input, the first      */
+                                        /* ripk_simulate_envelope on up to 4 of its     */
+                                        /* simulations; cell_div/tcell_div are ignored; */
+                                        /* results do not depend on the cells            */
 
 /*
  * Problem statement (the job parameters of Sec. 4.1 and the GUI of Sec. 5:
@@ -186,6 +192,10 @@ ripk_status ripk_simulate_envelope(ripk_plan_t plan, int64_t n, int32_t m, uint6
 
 /* Counters and timings of the plan's last compute call. */
 ripk_status ripk_plan_stats(ripk_plan_t plan, ripk_stats *out);
+
+/* Geometry the plan's last compute call used (with RIPK_PLAN_AUTOTUNE: the
+ * tuned cells). */
+ripk_status ripk_plan_get_info(ripk_plan_t plan, ripk_plan_info *out);
 
 /* ---- Serving ---------------------------------------------------------------
  *

@@ -206,9 +206,25 @@ ripk_status derive(const ripk_plan_desc *d, Layout *L) {
 
 }  // namespace
 
+// Candidate cell subdivisions (spatial cells per s_max, temporal cells per
+// t_max) the autotuner times.
+constexpr int kTuneCand[][2] = {{1, 1}, {2, 1}, {1, 2}, {2, 2}, {3, 1}, {3, 2}};
+constexpr int kTuneN = (int)(sizeof kTuneCand / sizeof kTuneCand[0]);
+constexpr int kTuneSims = 4;  // simulations per timed candidate
+
+struct TuneState {
+  bool done = false;
+  int32_t cd = 1, td = 1;
+  double us[kTuneN] = {};
+};
+
 struct ripk_plan_s {
-  ripk_plan_desc desc;
+  ripk_plan_desc desc;       // descriptor of the bound geometry
+  ripk_plan_desc user_desc;  // descriptor as given (autotuning varies the cells)
+  TuneState tune[2];         // [0] observed sets, [1] simulations
+  hipEvent_t tev[2] = {};    // autotuner timing
   Layout lay;
+  int32_t bound_cd = 1, bound_td = 1;  // cell subdivisions of the bound geometry
   int device = 0;
   int cus = 0;
   size_t lds_max = 0;  // LDS bytes a workgroup may use on this device
@@ -254,6 +270,8 @@ void release(ripk_plan_s *p) {
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   for (auto &e : p->ev)
+    if (e) (void)hipEventDestroy(e);
+  for (auto &e : p->tev)
     if (e) (void)hipEventDestroy(e);
   (void)hipSetDevice(prev);
   delete p;
@@ -372,10 +390,12 @@ ripk_status sync_status(hipError_t e) {
 
 namespace ripk {
 
+ripk_status plan_caps_all(const ripk_plan_desc *desc, Caps *caps);
+
 ripk_status plan_validate(const ripk_plan_desc *desc, Caps *caps) {
-  Layout L;
-  ripk_status s = derive(desc, &L);
-  if (s == RIPK_OK && caps) *caps = L.caps;
+  Caps c;
+  ripk_status s = plan_caps_all(desc, &c);
+  if (s == RIPK_OK && caps) *caps = c;
   return s;
 }
 
@@ -422,6 +442,8 @@ ripk_status plan_create(int device, const Caps &c, ripk_plan_s **out) {
   }
   for (auto &ev : p->ev)
     if (e == hipSuccess) e = hipEventCreate(&ev);
+  for (auto &ev : p->tev)
+    if (e == hipSuccess) e = hipEventCreate(&ev);
   if (e != hipSuccess) {
     release(p);
     return fail(RIPK_EDEVICE, "plan set-up failed: %s", hipGetErrorString(e));
@@ -430,9 +452,42 @@ ripk_status plan_create(int device, const Caps &c, ripk_plan_s **out) {
   return RIPK_OK;
 }
 
+ripk_status bind_geometry(ripk_plan_s *p, const ripk_plan_desc *desc, hipStream_t stream);
+
 // Binds a descriptor to a plan whose buffers hold its capacities; the
-// threshold tables are copied on `stream`.
+// threshold tables are copied on `stream`.  With RIPK_PLAN_AUTOTUNE the cells
+// are tuned afresh on the next calls.
 ripk_status plan_bind(ripk_plan_s *p, const ripk_plan_desc *desc, hipStream_t stream) {
+  ripk_status s = bind_geometry(p, desc, stream);
+  if (s != RIPK_OK) return s;
+  p->user_desc = *desc;
+  p->tune[0] = TuneState();
+  p->tune[1] = TuneState();
+  return RIPK_OK;
+}
+
+// Capacities for every geometry a descriptor may be bound to (all autotuner
+// candidates with RIPK_PLAN_AUTOTUNE).
+ripk_status plan_caps_all(const ripk_plan_desc *desc, Caps *caps) {
+  Layout L;
+  ripk_status s = derive(desc, &L);
+  if (s != RIPK_OK) return s;
+  Caps c = L.caps;
+  if (desc->flags & RIPK_PLAN_AUTOTUNE) {
+    for (int i = 0; i < kTuneN; ++i) {
+      ripk_plan_desc d = *desc;
+      d.cell_div = kTuneCand[i][0];
+      d.tcell_div = kTuneCand[i][1];
+      s = derive(&d, &L);
+      if (s != RIPK_OK) return s;
+      c = caps_max(c, L.caps);
+    }
+  }
+  *caps = c;
+  return RIPK_OK;
+}
+
+ripk_status bind_geometry(ripk_plan_s *p, const ripk_plan_desc *desc, hipStream_t stream) {
   Layout L;
   ripk_status s = derive(desc, &L);
   if (s != RIPK_OK) return s;
@@ -446,6 +501,8 @@ ripk_status plan_bind(ripk_plan_s *p, const ripk_plan_desc *desc, hipStream_t st
   DeviceGuard dg(p->device);
   p->desc = *desc;
   p->lay = L;
+  p->bound_cd = desc->cell_div ? desc->cell_div : 1;
+  p->bound_td = desc->tcell_div ? desc->tcell_div : 1;
   std::memset(p->S2h, 0, sizeof p->S2h);
   std::memset(p->Th, 0, sizeof p->Th);
   for (int k = 0; k < desc->n_s; ++k) p->S2h[k] = (uint64_t)L.info.S2[k];
@@ -456,6 +513,55 @@ ripk_status plan_bind(ripk_plan_s *p, const ripk_plan_desc *desc, hipStream_t st
 }
 
 const Caps &plan_caps(const ripk_plan_s *p) { return p->caps; }
+
+// Runs run_sets in the geometry tuned for `which` (0 observed sets, 1
+// simulations).  On a plan made with RIPK_PLAN_AUTOTUNE the first such call
+// times every candidate cell subdivision on S_tune sets of the same input
+// (results do not depend on the cells) and keeps the fastest.
+ripk_status run_tuned(ripk_plan_s *p, int which, uint32_t S, uint32_t S_tune, uint32_t n,
+                      uint32_t nc, const int32_t *x, const int32_t *y, const int32_t *t,
+                      bool simulate, uint64_t seed, const double *L_obs, hipStream_t st,
+                      bool sym) {
+  if (p->user_desc.flags & RIPK_PLAN_AUTOTUNE) {
+    TuneState &ts = p->tune[which];
+    ripk_plan_desc d = p->user_desc;
+    if (!ts.done) {
+      double best = 1e300;
+      int bi = 0;
+      for (int i = 0; i < kTuneN; ++i) {
+        d.cell_div = kTuneCand[i][0];
+        d.tcell_div = kTuneCand[i][1];
+        ripk_status s = bind_geometry(p, &d, st);
+        if (s != RIPK_OK) return s;
+        HIPCHK(hipEventRecord(p->tev[0], st));
+        s = run_sets(p, S_tune, n, nc, x, y, t, simulate, seed, nullptr, st, sym);
+        if (s != RIPK_OK) return s;
+        HIPCHK(hipEventRecord(p->tev[1], st));
+        uint32_t err = 0;
+        s = collect_stats(p, st, S_tune, n, &err);
+        if (s != RIPK_OK) return s;
+        if (err) return fail(RIPK_ERANGE, "a point lies outside the study window");
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, p->tev[0], p->tev[1]));
+        ts.us[i] = 1e3 * ms;
+        if (ts.us[i] < best) {
+          best = ts.us[i];
+          bi = i;
+        }
+      }
+      ts.done = true;
+      ts.cd = kTuneCand[bi][0];
+      ts.td = kTuneCand[bi][1];
+    }
+    if (p->bound_cd != ts.cd || p->bound_td != ts.td) {
+      d.cell_div = ts.cd;
+      d.tcell_div = ts.td;
+      ripk_status s = bind_geometry(p, &d, st);
+      if (s != RIPK_OK) return s;
+    }
+  }
+  return run_sets(p, S, n, nc, x, y, t, simulate, seed, L_obs, st, sym);
+}
 
 void plan_free(ripk_plan_s *p) { release(p); }
 
@@ -495,11 +601,11 @@ ripk_status ripk_plan_check(const ripk_plan_desc *desc, ripk_plan_info *info) {
 ripk_status ripk_plan(const ripk_plan_desc *desc, ripk_plan_t *out) {
   if (!out) return fail(RIPK_EINVAL, "null output handle");
   *out = nullptr;
-  Layout L;
-  ripk_status s = derive(desc, &L);
+  Caps caps;
+  ripk_status s = plan_caps_all(desc, &caps);
   if (s != RIPK_OK) return s;
   ripk_plan_s *p = nullptr;
-  s = plan_create(desc->device, L.caps, &p);
+  s = plan_create(desc->device, caps, &p);
   if (s != RIPK_OK) return s;
   s = plan_bind(p, desc, nullptr);
   if (s == RIPK_OK) s = sync_status(hipStreamSynchronize(nullptr));
@@ -532,7 +638,8 @@ ripk_status ripk_compute_K(ripk_plan_t p, const ripk_points *pts, void *stream, 
     x = p->x; y = p->y; t = p->t;
   }
   const bool sym = !(p->desc.flags & RIPK_PLAN_ORDERED) && nc == n;
-  ripk_status s = run_sets(p, 1, (uint32_t)n, (uint32_t)nc, x, y, t, false, 0, nullptr, st, sym);
+  ripk_status s = run_tuned(p, 0, 1, 1, (uint32_t)n, (uint32_t)nc, x, y, t, false, 0, nullptr, st,
+                            sym);
   if (s != RIPK_OK) return s;
   uint32_t err = 0;
   s = collect_stats(p, st, 1, (uint32_t)n, &err);
@@ -560,8 +667,8 @@ ripk_status ripk_simulate_envelope(ripk_plan_t p, int64_t n, int32_t m, uint64_t
   DeviceGuard dg(p->device);
   hipStream_t st = (hipStream_t)stream;
   const bool sym = !(p->desc.flags & RIPK_PLAN_ORDERED);
-  ripk_status s = run_sets(p, (uint32_t)m, (uint32_t)n, (uint32_t)n, nullptr, nullptr, nullptr,
-                           true, seed, L_obs, st, sym);
+  ripk_status s = run_tuned(p, 1, (uint32_t)m, (uint32_t)std::min(m, kTuneSims), (uint32_t)n,
+                            (uint32_t)n, nullptr, nullptr, nullptr, true, seed, L_obs, st, sym);
   if (s != RIPK_OK) return s;
   uint32_t err = 0;
   s = collect_stats(p, st, (uint32_t)m, (uint32_t)n, &err);
@@ -577,6 +684,12 @@ ripk_status ripk_simulate_envelope(ripk_plan_t p, int64_t n, int32_t m, uint64_t
     HIPCHK(hipStreamSynchronize(st));
   }
   p->stats.us_total = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
+  return RIPK_OK;
+}
+
+ripk_status ripk_plan_get_info(ripk_plan_t p, ripk_plan_info *out) {
+  if (!p || !out) return fail(RIPK_EINVAL, "null plan or output");
+  *out = p->lay.info;
   return RIPK_OK;
 }
 

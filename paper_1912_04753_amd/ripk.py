@@ -36,6 +36,7 @@ RIPK_SIM_CSR = 0
 RIPK_PLAN_ORDERED = 1
 RIPK_PLAN_TIMING = 2
 RIPK_PLAN_WIDE_COUNTS = 4
+RIPK_PLAN_AUTOTUNE = 8
 RIPK_REQ_KEEP_SIMS = 1
 
 _i64, _i32, _u32, _u64, _f64 = (ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32,
@@ -121,6 +122,7 @@ _SIGS = {
     "ripk_simulate_envelope": (_i32, [ctypes.c_void_p, _i64, _i32, _u64, _P(_f64),
                                       ctypes.c_void_p, _P(EnvOut)]),
     "ripk_plan_stats": (_i32, [ctypes.c_void_p, _P(Stats)]),
+    "ripk_plan_get_info": (_i32, [ctypes.c_void_p, _P(PlanInfo)]),
     "ripk_server_create": (_i32, [_P(ServerDesc), _P(ctypes.c_void_p)]),
     "ripk_server_destroy": (None, [ctypes.c_void_p]),
     "ripk_submit": (_i32, [ctypes.c_void_p, _P(Request), _P(_u64)]),
@@ -176,16 +178,27 @@ def make_desc(window, s_max, t_max, n_s, n_t, edge=RIPK_EDGE_ISO, norm=RIPK_NORM
                     int(device), int(cell_div), int(tcell_div))
 
 
-def ripk_plan_check(desc):
-    """Validate a descriptor and return its derived geometry (no device use)."""
-    info = PlanInfo()
-    _check(lib().ripk_plan_check(ctypes.byref(desc), ctypes.byref(info)), "ripk_plan_check")
+def _info_dict(info, desc):
     ns, nt = desc.n_s, desc.n_t
     return {"S2": np.array(info.S2[:ns], np.int64), "T": np.array(info.T[:nt], np.int64),
             "cell_s": info.cell_s, "cell_t": info.cell_t, "nx": info.nx, "ny": info.ny,
             "nt": info.nt, "reach_s": info.reach_s, "reach_t": info.reach_t,
             "n_cells": info.n_cells, "dist_mode": info.dist_mode, "n_bins": info.n_bins,
             "device_bytes": info.device_bytes}
+
+
+def ripk_plan_check(desc):
+    """Validate a descriptor and return its derived geometry (no device use)."""
+    info = PlanInfo()
+    _check(lib().ripk_plan_check(ctypes.byref(desc), ctypes.byref(info)), "ripk_plan_check")
+    return _info_dict(info, desc)
+
+
+def ripk_plan_get_info(plan):
+    """Geometry of the plan's last compute call (tuned cells with RIPK_PLAN_AUTOTUNE)."""
+    info = PlanInfo()
+    _check(lib().ripk_plan_get_info(plan.handle, ctypes.byref(info)), "ripk_plan_get_info")
+    return _info_dict(info, plan.desc)
 
 
 class Plan:

@@ -42,6 +42,11 @@ def ref_K(x, y, t, window, s_max, t_max, n_s, n_t, n_centres=None, edge=3, norm=
     return oracle.estimate(d, x, y, t, n_centres=n_centres)
 
 
+def make_desc_for(c, n, m=0, **kw):
+    return ripk.make_desc(c["window"], c["s_max"], c["t_max"], c["n_s"], c["n_t"], n_max=n,
+                          m_max=m, **kw)
+
+
 def cfg_args(c):
     return (c["window"], c["s_max"], c["t_max"], c["n_s"], c["n_t"])
 
@@ -397,3 +402,28 @@ def test_single_pair_weights_near_sides_and_corners():
     finally:
         plan.destroy()
     say("single pairs worst rel weight err %.3g" % worst)
+
+
+@pytest.mark.parametrize("name", ["thomas-200k", "uniform-100k-99csr"])
+def test_autotuned_plan_matches_default(name):
+    """RIPK_PLAN_AUTOTUNE times the candidate cell grids on the first calls and
+    keeps the fastest; counts and weights must not depend on the choice."""
+    c = workloads.workload(name)
+    x, y, t = workloads.make_points(c)
+    n, m, seed = len(x), 6, 17
+    plain = ripk.ripk_plan(make_desc_for(c, n, m))
+    tuned = ripk.ripk_plan(make_desc_for(c, n, m, flags=ripk.RIPK_PLAN_AUTOTUNE))
+    try:
+        r0 = ripk.ripk_compute_K(plain, x, y, t)
+        e0 = ripk.ripk_simulate_envelope(plain, n, m, seed, per_sim=True)
+        for rep in range(2):   # first call tunes, second reuses the choice
+            r1 = ripk.ripk_compute_K(tuned, x, y, t)
+            info = ripk.ripk_plan_get_info(tuned)
+            say(name, "tuned cells", info["cell_s"], info["cell_t"])
+            assert np.array_equal(r1["C"], r0["C"]) and np.array_equal(r1["W"], r0["W"])
+            e1 = ripk.ripk_simulate_envelope(tuned, n, m, seed, per_sim=True)
+            for k in ("C_sims", "W_sims", "K_lo", "K_hi", "L_lo", "L_hi"):
+                assert np.array_equal(e1[k], e0[k]), k
+    finally:
+        plain.destroy()
+        tuned.destroy()
