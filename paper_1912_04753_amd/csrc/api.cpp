@@ -313,7 +313,9 @@ ripk_status run_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_centres,
                     p->sort_temp, st, &alt));
   HIPCHK(launch_cell_bounds(p->keys[alt], N, (uint32_t)n_keys, p->cs, st));
   HIPCHK(launch_gather(p->vals[alt], N, x, y, t, g, p->lay.clamp_e, p->P, st));
-  HIPCHK(launch_items(p->cs, S, g, p->chunks, p->offs, p->set_base, p->items, n_items,
+  // row items need every point to be a centre (no halo entries inside a row)
+  const bool row_items = n_centres == n;
+  HIPCHK(launch_items(p->cs, S, g, row_items, p->chunks, p->offs, p->set_base, p->items, n_items,
                       p->scan_temp, st));
   HIPCHK(launch_fill_u64(p->binC, (size_t)S * NB, 0ull, st));
   HIPCHK(launch_fill_u64(p->binW, (size_t)S * NB * 2, 0ull, st));
@@ -332,6 +334,7 @@ ripk_status run_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_centres,
   a.binW = p->binW;
   a.n_eval = p->scal;
   a.symmetric = symmetric ? 1 : 0;
+  a.row_items = row_items ? 1 : 0;
   a.wide_counts = ((int64_t)n >= kWideCountPoints || (p->desc.flags & RIPK_PLAN_WIDE_COUNTS)) ? 1 : 0;
   int per_cu = 0;
   HIPCHK(pair_occupancy((int)NB, a.wide_counts, a.symmetric, g.mode, &per_cu));

@@ -285,23 +285,27 @@ __global__ void k_gather(const uint32_t *__restrict__ vals, uint32_t n,
   P[r] = make_int4(X, Y, T, e);
 }
 
-__global__ void k_chunks(const uint32_t *__restrict__ cs, uint32_t ncell_total,
+// A unit is the run of cells whose centres a work item may mix: one cell, or a
+// whole x-row of cells (unit = nx) when every point is a centre (no halo
+// entries between the cells).  Units cover cells [g*unit, (g+1)*unit) of the
+// cell array of all sets.
+__global__ void k_chunks(const uint32_t *__restrict__ cs, uint32_t nunit_total, uint32_t unit,
                          uint32_t *__restrict__ chunks) {
   uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= ncell_total) return;
-  uint32_t c = cs[2 * g + 1] - cs[2 * g];
+  if (g >= nunit_total) return;
+  uint32_t c = cs[2 * (g * unit + unit - 1) + 1] - cs[2 * g * unit];
   chunks[g] = (c + kChunk - 1) / kChunk;
 }
 
 // per set: padded item base so that every group of kItemsPerGroup items lies in one set
 __global__ void k_set_base(const uint32_t *__restrict__ offs, uint32_t n_sets,
-                           uint32_t n_cells, uint32_t *__restrict__ set_base,
+                           uint32_t n_units, uint32_t *__restrict__ set_base,
                            uint32_t *__restrict__ n_items) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   uint32_t run = 0;
   for (uint32_t s = 0; s < n_sets; ++s) {
     set_base[s] = run;
-    uint32_t tot = offs[(s + 1) * n_cells] - offs[s * n_cells];
+    uint32_t tot = offs[(s + 1) * n_units] - offs[s * n_units];
     run += (tot + kItemsPerGroup - 1) / kItemsPerGroup * kItemsPerGroup;
   }
   set_base[n_sets] = run;
@@ -309,13 +313,13 @@ __global__ void k_set_base(const uint32_t *__restrict__ offs, uint32_t n_sets,
 }
 
 __global__ void k_emit(const uint32_t *__restrict__ cs, const uint32_t *__restrict__ offs,
-                       const uint32_t *__restrict__ set_base, uint32_t n_sets, uint32_t n_cells,
-                       Item *__restrict__ items) {
+                       const uint32_t *__restrict__ set_base, uint32_t n_sets, uint32_t n_units,
+                       uint32_t unit, Item *__restrict__ items) {
   uint32_t gidx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (gidx >= n_sets * n_cells) return;
-  uint32_t s = gidx / n_cells, c = gidx - s * n_cells;
-  uint32_t o = set_base[s] + offs[gidx] - offs[s * n_cells];
-  uint32_t b = cs[2 * gidx], cnt = cs[2 * gidx + 1] - b;
+  if (gidx >= n_sets * n_units) return;
+  uint32_t s = gidx / n_units, c = gidx - s * n_units;
+  uint32_t o = set_base[s] + offs[gidx] - offs[s * n_units];
+  uint32_t b = cs[2 * gidx * unit], cnt = cs[2 * (gidx * unit + unit - 1) + 1] - b;
   for (uint32_t q = 0; q * kChunk < cnt; ++q) {
     Item it;
     it.set = s;
@@ -324,8 +328,8 @@ __global__ void k_emit(const uint32_t *__restrict__ cs, const uint32_t *__restri
     it.count = min((uint32_t)kChunk, cnt - q * kChunk);
     items[o + q] = it;
   }
-  if (c == n_cells - 1) {
-    uint32_t end = set_base[s] + offs[(s + 1) * n_cells] - offs[s * n_cells];
+  if (c == n_units - 1) {
+    uint32_t end = set_base[s] + offs[(s + 1) * n_units] - offs[s * n_units];
     for (uint32_t p = end; p < set_base[s + 1]; ++p) {
       Item it;
       it.set = s;
@@ -434,18 +438,20 @@ hipError_t launch_gather(const uint32_t *vals, uint32_t n, const int32_t *x, con
   return hipGetLastError();
 }
 
-hipError_t launch_items(const uint32_t *cs, uint32_t n_sets, const Geom &g, uint32_t *chunks,
-                        uint32_t *offs, uint32_t *set_base, Item *items, uint32_t *n_items,
-                        void *scan_temp, hipStream_t s) {
-  uint32_t tot = n_sets * g.n_cells;
+hipError_t launch_items(const uint32_t *cs, uint32_t n_sets, const Geom &g, bool row_items,
+                        uint32_t *chunks, uint32_t *offs, uint32_t *set_base, Item *items,
+                        uint32_t *n_items, void *scan_temp, hipStream_t s) {
+  const uint32_t unit = row_items ? (uint32_t)g.nx : 1u;
+  const uint32_t n_units = g.n_cells / unit;
+  const uint32_t tot = n_sets * n_units;
   hipLaunchKernelGGL(k_chunks, dim3(blocks_for(tot, kThreads)), dim3(kThreads), 0, s, cs, tot,
-                     chunks);
+                     unit, chunks);
   hipError_t e = exclusive_scan(chunks, offs, tot, scan_temp, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_set_base, dim3(1), dim3(64), 0, s, offs, n_sets, g.n_cells, set_base,
+  hipLaunchKernelGGL(k_set_base, dim3(1), dim3(64), 0, s, offs, n_sets, n_units, set_base,
                      n_items);
   hipLaunchKernelGGL(k_emit, dim3(blocks_for(tot, kThreads)), dim3(kThreads), 0, s, cs, offs,
-                     set_base, n_sets, g.n_cells, items);
+                     set_base, n_sets, n_units, unit, items);
   return hipGetLastError();
 }
 

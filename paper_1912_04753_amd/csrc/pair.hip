@@ -8,11 +8,13 @@
 // bins with 64-bit atomics when a workgroup moves on to another point set.
 //
 // Mapping
-//   * workgroup = 4 wavefronts; a work item = up to 64 centres of one cell (one
-//     lane per centre); a workgroup grabs 4 items of one set at a time from a
+//   * workgroup = 4 wavefronts; a work item = up to 64 consecutive centres of
+//     one x-row of cells (or of one cell when some points are not centres), one
+//     lane per centre; a workgroup grabs 4 items of one set at a time from a
 //     global counter (persistent launch, items padded per set);
-//   * neighbours are visited as contiguous runs of the sorted point array (a run
-//     of consecutive x-cells per (y, t) row of the stencil), staged per wave in
+//   * neighbours are visited as contiguous runs of the sorted point array (the
+//     x-cells within reach of the item's first to last centre, per (y, t) row
+//     of the stencil), staged per wave in
 //     two alternating LDS tiles (the next tile is fetched from HBM while the
 //     current one is scanned) and read back as wave-uniform broadcasts, four
 //     neighbours per LDS round trip;
@@ -583,8 +585,19 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
     W.cen[2][lane] = (uint32_t)me.z;
     W.cen[3][lane] = (uint32_t)me.w;
     wave_sync();
-    const int cx = (int)(cell % (uint32_t)g.nx);
-    const uint32_t rest = cell / (uint32_t)g.nx;
+    // the centres' row (t * ny + y) and the x-cells of the first and the last
+    // centre (points are sorted by cell, x fastest)
+    uint32_t rest;
+    int cxa, cxb;
+    if (a.row_items) {
+      const uint32_t cxl = min((uint32_t)raw.x / (uint32_t)g.cell_s, (uint32_t)g.nx - 1u);
+      cxa = (int)uni(cxl);
+      cxb = (int)__builtin_amdgcn_readlane(cxl, (int)cnt - 1);
+      rest = cell;
+    } else {
+      cxa = cxb = (int)(cell % (uint32_t)g.nx);
+      rest = cell / (uint32_t)g.nx;
+    }
     const int cy = (int)(rest % (uint32_t)g.ny);
     const int ct = (int)(rest / (uint32_t)g.ny);
     const uint32_t set_off = (uint32_t)set * g.n_cells;
@@ -599,8 +612,8 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
         const int yy = cy + dy;
         if (yy < 0 || yy >= g.ny) continue;
         const bool home = (dt == 0 && dy == 0);
-        const int xlo = (SYM && home) ? cx : max(cx - g.rs, 0);
-        const int xhi = min(cx + g.rs, g.nx - 1);
+        const int xlo = (SYM && home) ? cxa : max(cxa - g.rs, 0);
+        const int xhi = min(cxb + g.rs, g.nx - 1);
         const uint32_t row = set_off + (uint32_t)(tt * g.ny + yy) * (uint32_t)g.nx;
         uint32_t j0 = uni(a.cs[2 * (row + (uint32_t)xlo)]);
         const uint32_t j1 = uni(a.cs[2 * (row + (uint32_t)xhi) + 2]);

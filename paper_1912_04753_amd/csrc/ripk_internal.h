@@ -36,10 +36,11 @@ struct Geom {
   float inv_dt;                    // n_t / t_max * (1 - 2^-20)
 };
 
-// Work item of the pair kernel: up to kChunk centres of one cell of one set.
+// Work item of the pair kernel: up to kChunk consecutive centres of one unit
+// of one set: a cell, or an x-row of cells (row items).
 struct Item {
   uint32_t set;
-  uint32_t cell;   // cell index within the set
+  uint32_t cell;   // unit index within the set: cell, or row (t * ny + y)
   uint32_t begin;  // first centre, index into the sorted point array
   uint32_t count;  // number of centres (0 = padding)
 };
@@ -57,6 +58,7 @@ struct PairArgs {
   unsigned long long *binW;  // [sets][n_bins][2] 128-bit fixed-point weight sums
   unsigned long long *n_eval;  // device scalar
   int symmetric;
+  int row_items;               // items are chunks of x-rows (else of cells)
   int wide_counts;             // 64-bit LDS pair counts (sets of 2^23 points or more)
 };
 
@@ -100,7 +102,8 @@ hipError_t launch_cell_bounds(const uint32_t *keys, uint32_t n, uint32_t n_keys,
 hipError_t launch_gather(const uint32_t *vals, uint32_t n, const int32_t *x, const int32_t *y,
                          const int32_t *t, const Geom &g, int32_t clamp_e, int4 *P,
                          hipStream_t s);
-hipError_t launch_items(const uint32_t *cs, uint32_t n_sets, const Geom &g, uint32_t *chunks,
+hipError_t launch_items(const uint32_t *cs, uint32_t n_sets, const Geom &g, bool row_items,
+                        uint32_t *chunks,
                         uint32_t *offs, uint32_t *set_base, Item *items, uint32_t *n_items,
                         void *scan_temp, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, size_t n, unsigned long long v,
