@@ -171,6 +171,8 @@ def main():
                     help="requests of the serving stream (0 = skip the serving leg)")
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-load", type=float, default=0.7)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="fixed cells (one per s_max and t_max) instead of the tuned grid")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain device copy of known size first (counter runs)")
     args = ap.parse_args()
@@ -191,21 +193,30 @@ def main():
     n, m = len(x), cfg["sims"]
     dx, dy, dt = (torch.from_numpy(a).cuda() for a in (x, y, t))
     torch.cuda.synchronize()
+    flags = ripk.RIPK_PLAN_TIMING | (0 if args.no_autotune else ripk.RIPK_PLAN_AUTOTUNE)
     desc = ripk.make_desc(cfg["window"], cfg["s_max"], cfg["t_max"], cfg["n_s"], cfg["n_t"],
-                          n_max=n, m_max=m, flags=ripk.RIPK_PLAN_TIMING)
+                          n_max=n, m_max=m, flags=flags)
     plan = ripk.ripk_plan(desc)
     stream = torch.cuda.current_stream().cuda_stream
+
+    cells = {}
 
     def step():
         t0 = time.perf_counter()
         r = ripk.ripk_compute_K(plan, dx, dy, dt, stream=stream)
         s_obs = ripk.ripk_plan_stats(plan)
+        i = ripk.ripk_plan_get_info(plan)
+        cells["observed"] = [i["cell_s"], i["cell_t"]]
         t1 = time.perf_counter()
         ripk.ripk_simulate_envelope(plan, n, m, cfg["seed"], L_obs=r["L"], stream=stream)
         s_sim = ripk.ripk_plan_stats(plan)
+        i = ripk.ripk_plan_get_info(plan)
+        cells["simulations"] = [i["cell_s"], i["cell_t"]]
         t2 = time.perf_counter()
         return s_obs, s_sim, t1 - t0, t2 - t1
 
+    if not args.no_autotune:
+        step()  # plan set-up: the first calls time the candidate cell grids
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -244,7 +255,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "100k uniform points, 20km x 20km x 180d, "
                                "25x15 grid to 2km/30d, observed K + 99 CSR simulations",
-                   "n": n, "sims": m, "n_s": cfg["n_s"], "n_t": cfg["n_t"]},
+                   "n": n, "sims": m, "n_s": cfg["n_s"], "n_t": cfg["n_t"],
+                   "cells_m_s": cells, "autotune": not args.no_autotune},
         "sims_per_s": round(m / t_sim, 3),
         "n_in_per_step": n_in,
         "n_eval_per_step": evals,

@@ -170,9 +170,10 @@ ripk_status derive(const ripk_plan_desc *d, Layout *L) {
   I.reach_t = (int32_t)((d->t_max + ct - 1) / ct);
   I.n_cells = nx * ny * nt;
   // Strict bound on |dx| and |dy| between a centre and any candidate: the
-  // stencil spans reach+1 cells and the last cell of an axis also holds the
-  // remainder of the side.
-  const int64_t span = (I.reach_s + 1) * cs + std::max(W % cs, H % cs);
+  // stencil spans reach+1 cells beyond the centre's cell, a row item's centres
+  // span up to kItemExtent more x-cells, and the last cell of an axis also
+  // holds the remainder of the side.
+  const int64_t span = (I.reach_s + 1 + kItemExtent) * cs + std::max(W % cs, H % cs);
   if (span <= 32768)
     I.dist_mode = kModePacked;  // |dx|, |dy| <= 32767 and dx^2 + dy^2 < 2^31
   else if (2 * (span - 1) * (span - 1) < (1LL << 32))

@@ -288,13 +288,33 @@ __global__ void k_gather(const uint32_t *__restrict__ vals, uint32_t n,
 // A unit is the run of cells whose centres a work item may mix: one cell, or a
 // whole x-row of cells (unit = nx) when every point is a centre (no halo
 // entries between the cells).  Units cover cells [g*unit, (g+1)*unit) of the
-// cell array of all sets.
+// cell array of all sets.  Items are cut greedily: up to kChunk consecutive
+// centres, all within 1 + kItemExtent consecutive cells of the unit (the
+// candidate distance bound of the plan relies on it).  chunk_walk visits the
+// items of unit g in order; emit(begin, count) is called for each.
+template <typename F>
+__device__ __forceinline__ uint32_t chunk_walk(const uint32_t *__restrict__ cs, uint32_t g,
+                                               uint32_t unit, F emit) {
+  const uint32_t c0 = g * unit;
+  uint32_t pos = cs[2 * c0];
+  const uint32_t end = cs[2 * (c0 + unit - 1) + 1];
+  uint32_t c = 0, items = 0;
+  while (pos < end) {
+    while (cs[2 * (c0 + c) + 2] <= pos) ++c;  // cell holding pos (cells end at the next start)
+    const uint32_t last = min(c + (uint32_t)kItemExtent, unit - 1);
+    const uint32_t lim = min(min(pos + (uint32_t)kChunk, end), cs[2 * (c0 + last) + 1]);
+    emit(pos, lim - pos);
+    ++items;
+    pos = lim;
+  }
+  return items;
+}
+
 __global__ void k_chunks(const uint32_t *__restrict__ cs, uint32_t nunit_total, uint32_t unit,
                          uint32_t *__restrict__ chunks) {
   uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= nunit_total) return;
-  uint32_t c = cs[2 * (g * unit + unit - 1) + 1] - cs[2 * g * unit];
-  chunks[g] = (c + kChunk - 1) / kChunk;
+  chunks[g] = chunk_walk(cs, g, unit, [](uint32_t, uint32_t) {});
 }
 
 // per set: padded item base so that every group of kItemsPerGroup items lies in one set
@@ -319,15 +339,14 @@ __global__ void k_emit(const uint32_t *__restrict__ cs, const uint32_t *__restri
   if (gidx >= n_sets * n_units) return;
   uint32_t s = gidx / n_units, c = gidx - s * n_units;
   uint32_t o = set_base[s] + offs[gidx] - offs[s * n_units];
-  uint32_t b = cs[2 * gidx * unit], cnt = cs[2 * (gidx * unit + unit - 1) + 1] - b;
-  for (uint32_t q = 0; q * kChunk < cnt; ++q) {
+  chunk_walk(cs, gidx, unit, [&](uint32_t b, uint32_t cnt) {
     Item it;
     it.set = s;
     it.cell = c;
-    it.begin = b + q * kChunk;
-    it.count = min((uint32_t)kChunk, cnt - q * kChunk);
-    items[o + q] = it;
-  }
+    it.begin = b;
+    it.count = cnt;
+    items[o++] = it;
+  });
   if (c == n_units - 1) {
     uint32_t end = set_base[s] + offs[(s + 1) * n_units] - offs[s * n_units];
     for (uint32_t p = end; p < set_base[s + 1]; ++p) {

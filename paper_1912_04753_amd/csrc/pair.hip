@@ -155,19 +155,24 @@ __device__ __forceinline__ float omega_hh(float ex, float ey, float hx, float hy
   return fmaf(S, inv_pi, fmaxf(1.5707963267948966f - S, 0.0f) * (0.5f * inv_pi));
 }
 
+// An uncut side (e^2 >= d2) enters with h = 0 and e replaced by 1: its angle
+// is pi/2 whatever e is, and with e = 1 the products above are exact, so the
+// result does not depend on how e was stored (clamped in PACKED images).
 __device__ __forceinline__ float omega_f32(uint32_t ex, uint32_t ey, uint64_t d2) {
   const uint64_t ex2 = (uint64_t)ex * ex, ey2 = (uint64_t)ey * ey;
-  const float hx = __builtin_amdgcn_sqrtf((float)(ex2 < d2 ? d2 - ex2 : 0ull));
-  const float hy = __builtin_amdgcn_sqrtf((float)(ey2 < d2 ? d2 - ey2 : 0ull));
-  return omega_hh((float)ex, (float)ey, hx, hy);
+  const bool cx = ex2 < d2, cy = ey2 < d2;
+  const float hx = __builtin_amdgcn_sqrtf((float)(cx ? d2 - ex2 : 0ull));
+  const float hy = __builtin_amdgcn_sqrtf((float)(cy ? d2 - ey2 : 0ull));
+  return omega_hh(cx ? (float)ex : 1.0f, cy ? (float)ey : 1.0f, hx, hy);
 }
 
 // the same with d2 < 2^31 and ex, ey < 2^15 (all squares exact in 32 bits)
 __device__ __forceinline__ float omega_f32(uint32_t ex, uint32_t ey, uint32_t d2) {
   const uint32_t ex2 = __umul24(ex, ex), ey2 = __umul24(ey, ey);
-  const float hx = __builtin_amdgcn_sqrtf((float)(ex2 < d2 ? d2 - ex2 : 0u));
-  const float hy = __builtin_amdgcn_sqrtf((float)(ey2 < d2 ? d2 - ey2 : 0u));
-  return omega_hh((float)ex, (float)ey, hx, hy);
+  const bool cx = ex2 < d2, cy = ey2 < d2;
+  const float hx = __builtin_amdgcn_sqrtf((float)(cx ? d2 - ex2 : 0u));
+  const float hy = __builtin_amdgcn_sqrtf((float)(cy ? d2 - ey2 : 0u));
+  return omega_hh(cx ? (float)ex : 1.0f, cy ? (float)ey : 1.0f, hx, hy);
 }
 
 // Queue B: boundary weights with full lanes.  Records:

@@ -13,6 +13,8 @@ constexpr int kChunk = 64;         // centres per work item = one wavefront
 constexpr int kItemsPerGroup = 4;  // work items grabbed together by one workgroup
 constexpr int kPairThreads = 256;  // workgroup size of the pair kernel (4 wavefronts)
 constexpr int kFracBits = 23;      // fixed-point fraction bits of the weight sums
+constexpr int kItemExtent = 2;     // a row item's centres lie in at most 1 + kItemExtent
+                                   // consecutive x-cells (bounds the candidate |dx|)
 
 // Arithmetic of the candidate distance test (chosen per plan from the largest
 // coordinate difference a stencil can hold).

@@ -34,14 +34,15 @@ def _dispatches(csv_path, counter):
     return [(d, n, v) for d, (n, v) in sorted(agg.items())]
 
 
-def traffic(fetch_csv, write_csv):
-    """HBM bytes per pair-kernel launch (mean over the launches of the run, as the
-    roofline's achieved rate is) from two counter passes."""
+def traffic(fetch_csv, write_csv, last=2):
+    """HBM bytes per pair-kernel launch (mean over the run's last `last` launches,
+    i.e. one benchmark step after the plan's tuning calls, as the roofline's
+    achieved rate is) from two counter passes."""
     res = {"kernel_source_sha256": pair_source_hash()}
     for key, path, counter in (("fetch", fetch_csv, "FETCH_SIZE"), ("write", write_csv, "WRITE_SIZE")):
         rows = _dispatches(path, counter)
         copies = [v for d, n, v in rows if "copy" in n.lower() or "elementwise" in n.lower()]
-        pair = [v for d, n, v in rows if "k_pair" in n]
+        pair = [v for d, n, v in rows if "k_pair" in n][-last:]
         if not copies or not pair:
             raise ValueError(f"{path}: need a copy kernel and a pair kernel in the trace")
         kib_copy = max(copies)
@@ -87,6 +88,48 @@ def kernel_stats(stats_csv, top=12):
     return "\n".join(lines)
 
 
+PROFILE_CMD = ("rocprofv3 --kernel-trace --stats --output-format csv -d $R/gpurun_out/prof -o run -- "
+               "python3 $R/bench.py --steps {steps} --warmup 1 --no-cpu-baseline --serve-requests 0")
+PMC_CMD = ("timeout -s KILL 120 rocprofv3 --pmc {counter} --output-format csv -d $R/gpurun_out/{d} -o {o} "
+           "-- python3 $R/bench.py --steps 1 --warmup 0 --no-cpu-baseline --serve-requests 0 "
+           "--copy-calibration")
+
+
+def summary(title, stats_csv, trace_csv, steps, tr, bench_line=None):
+    """Markdown summary of one profiled benchmark run: the kernel table, the pair
+    kernel's launches of the timed steps, and the traffic record."""
+    launches = pair_launches(trace_csv)
+    timed = launches[-2 * steps:]
+    lines = [f"# {title}", "",
+             f"Pair-kernel source hash (sha256 of `paper_1912_04753_amd/csrc/pair.hip`, first 16 hex): "
+             f"`{tr['kernel_source_sha256']}`.", "",
+             "## Kernel trace (`--kernel-trace --stats`)", "",
+             "Command (from `/tmp`, `TMPDIR=/tmp`, `R` = repository root):", "", "```",
+             PROFILE_CMD.format(steps=steps), "```", "",
+             "The table covers every launch of the run: the plan's tuning calls (each candidate cell grid "
+             "once), the warm-up step and the timed steps.", "", kernel_stats(stats_csv), "",
+             f"Pair-kernel launches of the {steps} timed steps, in order (us; observed set, then the "
+             f"simulations, per step): {' '.join(f'{v:.1f}' for v in timed)}.",
+             f"Mean {sum(timed) / len(timed):.1f} us per launch.", ""]
+    if bench_line:
+        lines += [f"`bench.py`'s own HIP-event mean for the same launches (its timed steps): "
+                  f"{bench_line}.", ""]
+    lines += ["## HBM traffic (`--pmc FETCH_SIZE`, then `--pmc WRITE_SIZE`)", "", "```",
+              PMC_CMD.format(counter="FETCH_SIZE", d="pmcF", o="f"),
+              PMC_CMD.format(counter="WRITE_SIZE", d="pmcW", o="w"),
+              "python paper_1912_04753_amd/profiling.py traffic $R/gpurun_out/pmcF/f_counter_collection.csv "
+              "$R/gpurun_out/pmcW/w_counter_collection.csv", "```", "",
+              f"Calibration: a 256 MiB device copy (`--copy-calibration`) reads {tr['fetch_copy_kib']:.0f} KiB "
+              f"of FETCH_SIZE (scale {tr['fetch_scale']:.4f}) and {tr['write_copy_kib']:.0f} KiB of WRITE_SIZE "
+              f"(scale {tr['write_scale']:.4f}).", "",
+              "| launch (last step) | FETCH_SIZE KiB | WRITE_SIZE KiB |", "|---|---|---|",
+              f"| observed set | {tr['fetch_pair_kib_per_launch'][0]} | {tr['write_pair_kib_per_launch'][0]} |",
+              f"| simulations | {tr['fetch_pair_kib_per_launch'][1]} | {tr['write_pair_kib_per_launch'][1]} |", "",
+              f"Mean scaled bytes per launch: fetch {tr['fetch_bytes'] / 1e6:.1f} MB + write "
+              f"{tr['write_bytes'] / 1e6:.1f} MB = {tr['bytes_per_launch'] / 1e6:.1f} MB.", ""]
+    return "\n".join(lines)
+
+
 def load_traffic(path):
     """Stored traffic record, or None when the pair kernel changed since it was taken."""
     if not os.path.exists(path):
@@ -105,3 +148,12 @@ if __name__ == "__main__":
         print(kernel_stats(sys.argv[2]))
     elif sys.argv[1] == "launches":
         print(" ".join(f"{v:.1f}" for v in pair_launches(sys.argv[2])))
+    elif sys.argv[1] == "summary":
+        # summary <title> <prof dir> <fetch csv> <write csv> <steps> <traffic json out> [bench note]
+        title, prof, fcsv, wcsv, steps, out = sys.argv[2:8]
+        tr = traffic(fcsv, wcsv)
+        with open(out, "w") as f:
+            json.dump(tr, f, indent=1)
+        note = sys.argv[8] if len(sys.argv) > 8 else None
+        print(summary(title, os.path.join(prof, "run_kernel_stats.csv"),
+                      os.path.join(prof, "run_kernel_trace.csv"), int(steps), tr, note))

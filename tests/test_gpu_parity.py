@@ -262,7 +262,7 @@ def test_maximum_grid(case):
         args = (win, 3_000, 40 * workloads.DAY, 64, 64)
     else:
         win = (0, 0, 100_000, 90_000, 0, 400 * workloads.DAY)
-        args = (win, 15_000, 60 * workloads.DAY, 50, 50)
+        args = (win, 10_000, 60 * workloads.DAY, 50, 50)
     n = 24_000
     x = rng.integers(win[0], win[2] + 1, n); y = rng.integers(win[1], win[3] + 1, n)
     t = rng.integers(win[4], win[5] + 1, n)
@@ -427,3 +427,40 @@ def test_autotuned_plan_matches_default(name):
     finally:
         plain.destroy()
         tuned.destroy()
+
+
+def test_sparse_windows_modes_agree_with_oracle():
+    """Sparse sets in large windows (the request stream's geometries): a few
+    points per row of cells, so a work item's centres could spread over many
+    x-cells.  Symmetric, ordered, finer-cell and 64-bit-count runs must agree
+    with each other and with the oracle, observed and simulated."""
+    reqs = [r for r in workloads.serving_requests(num=300) if r["parts"][0][1] <= 7000][:36]
+    assert len(reqs) >= 30
+    for r in reqs:
+        x, y, t = workloads.request_points(r)
+        n, m = len(x), min(r["sims"], 2)
+        args = (r["window"], r["s_max"], r["t_max"], r["n_s"], r["n_t"])
+        out = {}
+        for name, kw in (("sym", {}), ("ord", dict(flags=ripk.RIPK_PLAN_ORDERED)),
+                         ("cd3", dict(cell_div=3, tcell_div=2)),
+                         ("wide", dict(flags=ripk.RIPK_PLAN_WIDE_COUNTS))):
+            plan = ripk.ripk_plan(ripk.make_desc(*args, n_max=n, m_max=max(m, 1), **kw))
+            try:
+                k = ripk.ripk_compute_K(plan, x, y, t)
+                e = ripk.ripk_simulate_envelope(plan, n, m, r["seed"], per_sim=True) if m else None
+            finally:
+                plan.destroy()
+            out[name] = (k, e)
+        ref = ref_K(x, y, t, *args)
+        compare(out["sym"][0], ref, *args[1:], where=f"request {r['id']} n={n}")
+        for name in ("ord", "cd3", "wide"):
+            assert np.array_equal(out[name][0]["C"], out["sym"][0]["C"]), (r["id"], name)
+            assert np.array_equal(out[name][0]["W"], out["sym"][0]["W"]), (r["id"], name)
+            if m:
+                assert np.array_equal(out[name][1]["C_sims"], out["sym"][1]["C_sims"]), (r["id"], name)
+        if m:
+            d = oracle.desc(*args)
+            xs, ys, ts = oracle.csr_points(d, n, 0, r["seed"])
+            rs = oracle.estimate(d, xs, ys, ts)
+            assert np.array_equal(out["sym"][1]["C_sims"][0], rs["C"].astype(np.uint64)), r["id"]
+    say("sparse windows: %d requests agree" % len(reqs))
