@@ -83,7 +83,7 @@ __device__ __forceinline__ int4 load_image(const unsigned char *base, uint32_t s
 }
 
 struct QState {
-  uint32_t ha, na;      // queue A head and length
+  uint32_t ha, ta;      // queue A head and tail positions in [0, kQA)
   uint32_t hb, nb;      // queue B head and length
   uint32_t drained;     // queue A entries drained so far (monotonic)
   uint32_t prev_mark;   // queue A entries pushed before the previous tile began
@@ -97,6 +97,15 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 __device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// dx^2 + dy^2 of two signed 16-bit halves (|dx|, |dy| < 2^15, so the sum fits
+// in 31 bits).  The three-operand dot product takes its zero addend inline;
+// the accumulating two-operand form would need a register cleared each time.
+__device__ __forceinline__ uint32_t sq16x2(uint32_t d) {
+  uint32_t r;
+  asm("v_dot2_i32_i16 %0, %1, %1, 0" : "=v"(r) : "v"(d));
+  return r;
+}
 
 // |a - b| of unsigned values in one instruction (sum of absolute differences)
 __device__ __forceinline__ uint32_t absdiff(uint32_t a, uint32_t b) {
@@ -146,13 +155,14 @@ __device__ __forceinline__ float omega_hh(float ex, float ey, float hx, float hy
   const float re = fmaf(hx, hy, -(ex * ey));
   const float are = fabsf(re);
   const float lo = fminf(im, are), hi = fmaxf(im, are);
-  float r = __builtin_amdgcn_rcpf(hi);
-  r = fmaf(fmaf(-hi, r, 1.0f), r, r);  // one Newton step: quotient to ~1 ulp
-  float a = atan01(lo * r);
+  // quotient from the hardware reciprocal (about 1 ulp): the weight stays
+  // within 3e-7 of the exact one (FP32 emulation against FP64 acos)
+  float a = atan01(lo * __builtin_amdgcn_rcpf(hi));
   a = im > are ? 1.5707963267948966f - a : a;
   const float S = re < 0.0f ? 3.14159265358979323846f - a : a;
+  // S/pi + max(0, pi/2 - S)/(2 pi) = max(S/pi, 1/4 + S/(2 pi)) (equal at S = pi/2)
   const float inv_pi = 0.318309886183790671538f;
-  return fmaf(S, inv_pi, fmaxf(1.5707963267948966f - S, 0.0f) * (0.5f * inv_pi));
+  return fmaxf(S * inv_pi, fmaf(S, 0.5f * inv_pi, 0.25f));
 }
 
 // An uncut side (e^2 >= d2) enters with h = 0 and e replaced by 1: its angle
@@ -210,6 +220,11 @@ __device__ __forceinline__ void drain_b(WaveLds &W, QState &q, uint32_t c, int l
   q.nb -= c;
 }
 
+// pending queue A entries (at most 63 + 4*64 < kQA, so head == tail means none)
+__device__ __forceinline__ uint32_t na_of(const QState &q) {
+  return q.ta >= q.ha ? q.ta - q.ha : q.ta + kQA - q.ha;
+}
+
 struct Side {
   uint32_t T, ex, ey;
   bool slow;  // the circle of radius d crosses the study boundary (never true
@@ -261,7 +276,7 @@ __device__ __forceinline__ void drain_a(WaveLds &W, QState &q,
   if (MODE == kModePacked) {
     typedef short s2 __attribute__((ext_vector_type(2)));
     const s2 dd = __builtin_bit_cast(s2, pi.x) - __builtin_bit_cast(s2, pj.x);
-    d2lo = (uint32_t)__builtin_amdgcn_sdot2(dd, dd, 0, false);
+    d2lo = sq16x2(__builtin_bit_cast(uint32_t, dd));
     u = absdiff((uint32_t)pi.y, (uint32_t)pj.y);
   } else if (MODE == kModeU32) {
     const int32_t dx = pi.x - pj.x, dy = pi.y - pj.y;
@@ -306,6 +321,10 @@ __device__ __forceinline__ void drain_a(WaveLds &W, QState &q,
     hfj = (tp && u > min(sj.T, D - sj.T)) ? 1u : 0u;
     qsum += sj.slow ? 0u : (hfj ? (2u << kFracBits) : (1u << kFracBits));
   }
+  // boundary-queue mask, taken next to the compares (separate ballots fold
+  // into their masks; taken after the branch below they would be rebuilt)
+  const unsigned long long mslow =
+      (__builtin_amdgcn_ballot_w64(si.slow) | (SYM ? __builtin_amdgcn_ballot_w64(sj.slow) : 0ull)) & vmask;
   // weights hist[bin], pair counts in a separate array (32-bit words unless
   // the set is large): separate arrays keep the 64 lanes' atomics spread over
   // all LDS banks
@@ -317,14 +336,11 @@ __device__ __forceinline__ void drain_a(WaveLds &W, QState &q,
       atomicAdd(histc + bin, 1u);
   }
   q.ha = q.ha + c >= kQA ? q.ha + c - kQA : q.ha + c;
-  q.na -= c;
   q.drained += c;
   if (MODE == kModePacked) {
     // one record per pair with a boundary side
     const bool need = si.slow || sj.slow;
-    // separate ballots fold into the compare masks
-    const unsigned long long m =
-        (__builtin_amdgcn_ballot_w64(si.slow) | __builtin_amdgcn_ballot_w64(sj.slow)) & vmask;
+    const unsigned long long m = mslow;
     if (m) {
       const uint32_t pos = lane_rank(m, q.hb + q.nb) & (kQB - 1);
       q.nb += (uint32_t)__popcll(m);
@@ -377,14 +393,16 @@ __device__ __forceinline__ int4 far_image() {
 
 // Candidate test of one neighbour against this lane's centre: cs = space test,
 // ct = time test (kept apart so that each ballot folds to its compare mask).
+// PACKED compares d2 (< 2^31) as a signed value with the lane's own bound:
+// s2max for a centre, -1 for an empty lane, which then never passes.
 template <int MODE>
-__device__ __forceinline__ void cand(const int4 me, uint32_t tplus, const int4 pj, const Geom &g,
-                                     bool &cs, bool &ct) {
+__device__ __forceinline__ void cand(const int4 me, uint32_t tplus, int thr, const int4 pj,
+                                     const Geom &g, bool &cs, bool &ct) {
   uint32_t dtp;
   if (MODE == kModePacked) {
     typedef short s2 __attribute__((ext_vector_type(2)));
     const s2 d = __builtin_bit_cast(s2, me.x) - __builtin_bit_cast(s2, pj.x);
-    cs = (uint32_t)__builtin_amdgcn_sdot2(d, d, 0, false) <= (uint32_t)g.s2max;
+    cs = (int)sq16x2(__builtin_bit_cast(uint32_t, d)) <= thr;
     dtp = tplus - (uint32_t)pj.y;
   } else if (MODE == kModeU32) {
     const int32_t dx = me.x - pj.x, dy = me.y - pj.y;
@@ -421,7 +439,7 @@ __device__ __forceinline__ void drain_oldest(Ctx<SYM, MODE> &x, uint32_t c) {
 // otherwise).
 template <bool SYM, int MODE, bool HOME>
 __device__ __forceinline__ void scan_run(Ctx<SYM, MODE> &x, uint32_t j0, uint32_t j1,
-                                         const int4 me, uint32_t tplus, bool lv,
+                                         const int4 me, uint32_t tplus, int thr, bool lv,
                                          unsigned long long valid, uint32_t mi,
                                          const int4 *__restrict__ P) {
   QState &q = x.q;
@@ -439,7 +457,7 @@ __device__ __forceinline__ void scan_run(Ctx<SYM, MODE> &x, uint32_t j0, uint32_
     // its queue entries are the oldest and must be drained first
     q.slot ^= 1u;
     if (q.prev_mark > q.drained) drain_oldest(x, q.prev_mark - q.drained);
-    q.prev_mark = q.drained + q.na;
+    q.prev_mark = q.drained + na_of(q);
     const uint32_t sbase = q.slot * kJT;
     wave_sync();
     {
@@ -478,30 +496,33 @@ __device__ __forceinline__ void scan_run(Ctx<SYM, MODE> &x, uint32_t j0, uint32_
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         bool cs, ct;
-        cand<MODE>(me, tplus, pj[u], x.g, cs, ct);
+        cand<MODE>(me, tplus, thr, pj[u], x.g, cs, ct);
         const uint32_t j = tb + jj + u;
         const bool hc = HOME ? (SYM ? (j > mi) : (j != mi)) : true;
         // separate ballots fold into the compare masks; the per-lane predicate
-        // only steers the store
-        unsigned long long mask =
-            __builtin_amdgcn_ballot_w64(cs) & __builtin_amdgcn_ballot_w64(ct) & valid;
+        // only steers the store (PACKED: empty lanes already fail cs)
+        unsigned long long mask = __builtin_amdgcn_ballot_w64(cs) & __builtin_amdgcn_ballot_w64(ct);
+        if (MODE != kModePacked) mask &= valid;
         if (HOME) mask &= __builtin_amdgcn_ballot_w64(hc);
         if (mask) {
-          const uint32_t tail = q.ha + q.na;
-          const uint32_t base = tail >= kQA ? tail - kQA : tail;
-          const uint32_t cnt = (uint32_t)__popcll(mask);
-          q.na += cnt;
-          if (cs & ct & lv & hc) W.qa[base + lane_rank(mask, 0)] = lane_tag + ((jj + u) << 18);
-          if (base + cnt > kQA) {
-            // the push ran past the ring's end: move the overflow to its start
-            // (those slots were drained: at most 63 + 4*64 < kQA are pending)
-            wave_sync();
-            if ((uint32_t)lane < base + cnt - kQA) W.qa[lane] = W.qa[kQA + lane];
-            wave_sync();
+          const uint32_t base = q.ta;
+          q.ta = base + (uint32_t)__popcll(mask);
+          const bool pass = MODE == kModePacked ? (cs & ct & hc) : (cs & ct & lv & hc);
+          if (pass) W.qa[base + lane_rank(mask, 0)] = lane_tag + ((jj + u) << 18);
+          if (q.ta >= kQA) {
+            // the push reached the ring's end: move what ran past it to the
+            // start (those slots were drained: at most 63 + 4*64 < kQA pending)
+            const uint32_t over = q.ta - kQA;
+            if (over) {
+              wave_sync();
+              if ((uint32_t)lane < over) W.qa[lane] = W.qa[kQA + lane];
+              wave_sync();
+            }
+            q.ta = over;
           }
         }
       }
-      while (q.na >= 64) drain_oldest(x, 64);
+      for (uint32_t na = na_of(q); na >= 64; na -= 64) drain_oldest(x, 64);
     }
   }
 }
@@ -585,6 +606,7 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
     const int4 raw = valid ? a.P[mi] : make_int4(0, 0, 0, 0);
     const int4 me = image<MODE>(raw, g);
     const uint32_t tplus = (uint32_t)(MODE == kModePacked ? me.y : me.z) + g.tmax;
+    const int thr = valid ? (int)g.s2max : -1;
     W.cen[0][lane] = (uint32_t)me.x;
     W.cen[1][lane] = (uint32_t)me.y;
     W.cen[2][lane] = (uint32_t)me.z;
@@ -629,14 +651,17 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
           } else {
             ev += (unsigned long long)cnt * (j1 - j0) - cnt;
           }
-          scan_run<SYM, MODE, true>(x, j0, j1, me, tplus, valid, vmask, mi, a.P);
+          scan_run<SYM, MODE, true>(x, j0, j1, me, tplus, thr, valid, vmask, mi, a.P);
         } else {
           ev += (unsigned long long)cnt * (j1 - j0);
-          scan_run<SYM, MODE, false>(x, j0, j1, me, tplus, valid, vmask, mi, a.P);
+          scan_run<SYM, MODE, false>(x, j0, j1, me, tplus, thr, valid, vmask, mi, a.P);
         }
       }
     }
-    if (q.na) drain_oldest(x, q.na);
+    {
+      const uint32_t na = na_of(q);
+      if (na) drain_oldest(x, na);
+    }
     if (q.nb) drain_b<MODE>(W, q, q.nb, lane, hist);
     if (lane == 0) atomicAdd(evals_lds, ev);
     evals_total += ev;
