@@ -46,8 +46,16 @@ def cpu_baseline(cfg, x, y, t, target_s):
         n_in += int(r["C"][-1, -1])
         sets += 1
     dt = oracle.now() - t0
+    cpu = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": n_in / dt / 1e9, "unit": "G pair tests/s", "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", "cpu": cpu,
             "sample": f"observed set of the workload plus {sets - 1} of its {cfg['sims']} CSR "
                       f"simulations ({sets} sets of {n} points, every ordered pair); "
                       f"{n_in} in-range ordered pairs in {dt:.2f} s"}
@@ -196,7 +204,10 @@ def main():
     flags = ripk.RIPK_PLAN_TIMING | (0 if args.no_autotune else ripk.RIPK_PLAN_AUTOTUNE)
     desc = ripk.make_desc(cfg["window"], cfg["s_max"], cfg["t_max"], cfg["n_s"], cfg["n_t"],
                           n_max=n, m_max=m, flags=flags)
+    t_cold = time.perf_counter()
     plan = ripk.ripk_plan(desc)
+    torch.cuda.synchronize()
+    plan_ms = 1e3 * (time.perf_counter() - t_cold)
     stream = torch.cuda.current_stream().cuda_stream
 
     cells = {}
@@ -215,8 +226,11 @@ def main():
         t2 = time.perf_counter()
         return s_obs, s_sim, t1 - t0, t2 - t1
 
+    t_tune = time.perf_counter()
     if not args.no_autotune:
         step()  # plan set-up: the first calls time the candidate cell grids
+    torch.cuda.synchronize()
+    first_step_ms = 1e3 * (time.perf_counter() - t_tune)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -226,6 +240,12 @@ def main():
         recs.append(step())
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
+    # end to end with the observed points in host memory (H2D copy inside the call)
+    t_h = time.perf_counter()
+    for _ in range(3):
+        ripk.ripk_compute_K(plan, x, y, t)
+    host_obs_ms = 1e3 * (time.perf_counter() - t_h) / 3
+    n_in_obs = ripk.ripk_plan_stats(plan)["n_in"]
     plan.destroy()
 
     ms = 1e3 * t_total / args.steps
@@ -258,6 +278,11 @@ def main():
                    "n": n, "sims": m, "n_s": cfg["n_s"], "n_t": cfg["n_t"],
                    "cells_m_s": cells, "autotune": not args.no_autotune},
         "sims_per_s": round(m / t_sim, 3),
+        "cold_ms": {"plan": round(plan_ms, 2),
+                    "first_step_with_tuning": round(first_step_ms, 2) if not args.no_autotune else None},
+        "observed_host_input": {"ms": round(host_obs_ms, 3),
+                                "pair_tests_per_s_G": round(n_in_obs / (host_obs_ms * 1e-3) / 1e9, 3),
+                                "note": "ripk_compute_K on host arrays: PCIe copy of 1.2 MB inside the call"},
         "n_in_per_step": n_in,
         "n_eval_per_step": evals,
         "pair_kernel_us": {"observed": round(sum(r[0]["us_pair"] for r in recs) / len(recs), 2),

@@ -14,10 +14,10 @@
 //     global counter (persistent launch, items padded per set);
 //   * neighbours are visited as contiguous runs of the sorted point array (the
 //     x-cells within reach of the item's first to last centre, per (y, t) row
-//     of the stencil), staged per wave in
-//     two alternating LDS tiles (the next tile is fetched from HBM while the
-//     current one is scanned) and read back as wave-uniform broadcasts, four
-//     neighbours per LDS round trip;
+//     of the stencil), staged per wave in an LDS tile of 64 points (the next
+//     tile is fetched into registers while the current one is scanned; pending
+//     pairs are drained before the tile is refilled) and read back as
+//     wave-uniform broadcasts, two neighbours per LDS round trip;
 //   * symmetric mode visits each unordered pair once (forward half of the
 //     stencil, j > i inside the home cell) and adds both weights, since
 //     omega_ij / v_ij depend on the centre while the bin depends on d and u only;
@@ -47,7 +47,9 @@ namespace ripk {
 namespace {
 
 constexpr int kJT = 64;     // points per tile slot (two slots per wave)
-constexpr uint32_t kQA = 320;  // ring of queue A tags: at most 63 + 4*64 pending between drains
+constexpr int kGroup = 2;       // neighbours tested between two drain checks
+// ring of queue A tags: at most 63 + 64 * kGroup are pending at any time
+constexpr uint32_t kQA = 64 * kGroup + 64;
 constexpr int kQB = 128;    // ring of queue B records: < 64 + 64 pending between drains
 constexpr int kWaves = kPairThreads / 64;
 // Bound on the candidates a workgroup evaluates between histogram flushes
@@ -66,7 +68,7 @@ constexpr uint32_t kClampE = 32767u;         // side distances stored in 15 bits
 // f[c][e]): lanes that read different entries hit consecutive banks, and the
 // scan reads one component of four consecutive neighbours in one access.
 struct WaveLds {
-  uint32_t tile[4][2 * kJT];  // two tile slots of neighbour points
+  uint32_t tile[4][kJT];      // the tile of neighbour points being scanned
   uint32_t cen[4][64];        // the wave's centres
   uint32_t qa[kQA + 64];  // in-range pairs: byte offsets in this block, centre | neighbour << 16;
                           // the 64 extra entries take a push that crosses the ring's end
@@ -74,7 +76,7 @@ struct WaveLds {
 };
 
 static_assert(sizeof(WaveLds) % 16 == 0, "the histogram after the wave blocks must stay 16-byte aligned");
-constexpr uint32_t kTileStride = 2 * kJT * 4;  // bytes between components of a tile entry
+constexpr uint32_t kTileStride = kJT * 4;  // bytes between components of a tile entry
 constexpr uint32_t kCenStride = 64 * 4;        // bytes between components of a centre
 
 __device__ __forceinline__ int4 load_image(const unsigned char *base, uint32_t stride) {
@@ -85,9 +87,6 @@ __device__ __forceinline__ int4 load_image(const unsigned char *base, uint32_t s
 struct QState {
   uint32_t ha, ta;      // queue A head and tail positions in [0, kQA)
   uint32_t hb, nb;      // queue B head and length
-  uint32_t drained;     // queue A entries drained so far (monotonic)
-  uint32_t prev_mark;   // queue A entries pushed before the previous tile began
-  uint32_t slot;        // tile slot being scanned
 };
 
 __device__ __forceinline__ void wave_sync() {
@@ -220,7 +219,7 @@ __device__ __forceinline__ void drain_b(WaveLds &W, QState &q, uint32_t c, int l
   q.nb -= c;
 }
 
-// pending queue A entries (at most 63 + 4*64 < kQA, so head == tail means none)
+// pending queue A entries (fewer than kQA, so head == tail means none)
 __device__ __forceinline__ uint32_t na_of(const QState &q) {
   return q.ta >= q.ha ? q.ta - q.ha : q.ta + kQA - q.ha;
 }
@@ -336,7 +335,6 @@ __device__ __forceinline__ void drain_a(WaveLds &W, QState &q,
       atomicAdd(histc + bin, 1u);
   }
   q.ha = q.ha + c >= kQA ? q.ha + c - kQA : q.ha + c;
-  q.drained += c;
   if (MODE == kModePacked) {
     // one record per pair with a boundary side
     const bool need = si.slow || sj.slow;
@@ -453,19 +451,18 @@ __device__ __forceinline__ void scan_run(Ctx<SYM, MODE> &x, uint32_t j0, uint32_
   if (nxt_ok) nxt = P[j0 + lane];
   for (uint32_t tb = j0; tb < j1; tb += kJT) {
     const uint32_t nt = uni(min((uint32_t)kJT, j1 - tb));
-    // the slot about to be refilled last held the tile before the previous one:
-    // its queue entries are the oldest and must be drained first
-    q.slot ^= 1u;
-    if (q.prev_mark > q.drained) drain_oldest(x, q.prev_mark - q.drained);
-    q.prev_mark = q.drained + na_of(q);
-    const uint32_t sbase = q.slot * kJT;
+    // every pending entry refers to the tile about to be overwritten
+    {
+      const uint32_t na = na_of(q);
+      if (na) drain_oldest(x, na);
+    }
     wave_sync();
     {
       const int4 im = nxt_ok ? image<MODE>(nxt, x.g) : far_image<MODE>();
-      W.tile[0][sbase + lane] = (uint32_t)im.x;
-      W.tile[1][sbase + lane] = (uint32_t)im.y;
-      W.tile[2][sbase + lane] = (uint32_t)im.z;
-      W.tile[3][sbase + lane] = (uint32_t)im.w;
+      W.tile[0][lane] = (uint32_t)im.x;
+      W.tile[1][lane] = (uint32_t)im.y;
+      W.tile[2][lane] = (uint32_t)im.z;
+      W.tile[3][lane] = (uint32_t)im.w;
     }
     wave_sync();
     const uint32_t tn = tb + kJT;
@@ -477,24 +474,21 @@ __device__ __forceinline__ void scan_run(Ctx<SYM, MODE> &x, uint32_t j0, uint32_
     // the tile's first entry
     const uint32_t lane_tag =
         (uint32_t)((const unsigned char *)&W.cen[0][lane] - (const unsigned char *)&W) |
-        ((uint32_t)((const unsigned char *)&W.tile[0][sbase] - (const unsigned char *)&W) << 16);
-    for (uint32_t jj = 0; jj < nt; jj += 4) {
-      int4 pj[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) pj[u] = make_int4(0, 0, 0, 0);
+        ((uint32_t)((const unsigned char *)&W.tile[0][0] - (const unsigned char *)&W) << 16);
+    typedef uint32_t gvec __attribute__((ext_vector_type(kGroup)));
+    for (uint32_t jj = 0; jj < nt; jj += kGroup) {
+      int4 pj[kGroup];
       {
-        // components the candidate test needs, four neighbours per access
-        const uint4 c0 = *(const uint4 *)&W.tile[0][sbase + jj];
-        const uint4 c1 = *(const uint4 *)&W.tile[1][sbase + jj];
-        pj[0].x = (int)c0.x; pj[1].x = (int)c0.y; pj[2].x = (int)c0.z; pj[3].x = (int)c0.w;
-        pj[0].y = (int)c1.x; pj[1].y = (int)c1.y; pj[2].y = (int)c1.z; pj[3].y = (int)c1.w;
-        if (MODE != kModePacked) {
-          const uint4 c2 = *(const uint4 *)&W.tile[2][sbase + jj];
-          pj[0].z = (int)c2.x; pj[1].z = (int)c2.y; pj[2].z = (int)c2.z; pj[3].z = (int)c2.w;
-        }
+        // components the candidate test needs, kGroup neighbours per access
+        const gvec c0 = *(const gvec *)&W.tile[0][jj];
+        const gvec c1 = *(const gvec *)&W.tile[1][jj];
+        gvec c2 = c1;
+        if (MODE != kModePacked) c2 = *(const gvec *)&W.tile[2][jj];
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) pj[u] = make_int4((int)c0[u], (int)c1[u], (int)c2[u], 0);
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < kGroup; ++u) {
         bool cs, ct;
         cand<MODE>(me, tplus, thr, pj[u], x.g, cs, ct);
         const uint32_t j = tb + jj + u;
@@ -511,7 +505,7 @@ __device__ __forceinline__ void scan_run(Ctx<SYM, MODE> &x, uint32_t j0, uint32_
           if (pass) W.qa[base + lane_rank(mask, 0)] = lane_tag + ((jj + u) << 18);
           if (q.ta >= kQA) {
             // the push reached the ring's end: move what ran past it to the
-            // start (those slots were drained: at most 63 + 4*64 < kQA pending)
+            // start (those slots were drained: fewer than kQA are pending)
             const uint32_t over = q.ta - kQA;
             if (over) {
               wave_sync();
@@ -628,7 +622,7 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
     const int cy = (int)(rest % (uint32_t)g.ny);
     const int ct = (int)(rest / (uint32_t)g.ny);
     const uint32_t set_off = (uint32_t)set * g.n_cells;
-    QState q = {0u, 0u, 0u, 0u, 0u, 0u, 0u};
+    QState q = {0u, 0u, 0u, 0u};
     Ctx<SYM, MODE> x{W, q, g, hist, histc, wide, S2lo, S2hi, T, lane};
     unsigned long long ev = 0;
     for (int dt = SYM ? 0 : -g.rt; dt <= g.rt; ++dt) {
