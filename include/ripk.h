@@ -77,6 +77,11 @@ enum {
                                         /* ripk_simulate_envelope on up to 4 of its     */
                                         /* simulations; cell_div/tcell_div are ignored; */
                                         /* results do not depend on the cells            */
+#define RIPK_PLAN_GRAPH (1u << 4)       /* on a non-null stream and without             */
+                                        /* RIPK_PLAN_TIMING: capture a call's launch    */
+                                        /* sequence into a HIP graph and replay it      */
+                                        /* while the call shape (sizes, input pointers, */
+                                        /* seed, geometry) repeats                      */
 
 /*
  * Problem statement (the job parameters of Sec. 4.1 and the GUI of Sec. 5:

@@ -226,6 +226,10 @@ struct ripk_plan_s {
   hipEvent_t tev[2] = {};    // autotuner timing
   Layout lay;
   int32_t bound_cd = 1, bound_td = 1;  // cell subdivisions of the bound geometry
+  uint64_t bind_gen = 0;               // bumped whenever a geometry is bound
+  // RIPK_PLAN_GRAPH: the captured launch sequence of the last call shape
+  hipGraphExec_t gexec = nullptr;
+  uint64_t gkey[12] = {};
   int device = 0;
   int cus = 0;
   size_t lds_max = 0;  // LDS bytes a workgroup may use on this device
@@ -274,6 +278,7 @@ void release(ripk_plan_s *p) {
     if (e) (void)hipEventDestroy(e);
   for (auto &e : p->tev)
     if (e) (void)hipEventDestroy(e);
+  if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
   (void)hipSetDevice(prev);
   delete p;
 }
@@ -289,13 +294,15 @@ struct DeviceGuard {
 
 // Runs the whole path over S sets of n points each.  For sims != 0 the points
 // are drawn on the device; otherwise keys come from (x, y, t).
-ripk_status run_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_centres, const int32_t *x,
-                     const int32_t *y, const int32_t *t, bool simulate, uint64_t seed,
-                     const double *L_obs, hipStream_t st, bool symmetric) {
+// Enqueues the launch sequence of one evaluation on st (kernels only, and
+// event records when timing): capturable into a graph.
+ripk_status enqueue_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_centres,
+                         const int32_t *x, const int32_t *y, const int32_t *t, bool simulate,
+                         uint64_t seed, bool has_Lobs, hipStream_t st, bool symmetric,
+                         bool timing) {
   const Geom &g = p->lay.g;
   const uint32_t NB = (uint32_t)p->lay.info.n_bins;
   const uint32_t N = S * n;
-  const bool timing = (p->desc.flags & RIPK_PLAN_TIMING) != 0;
   if (timing) HIPCHK(hipEventRecord(p->ev[0], st));
   uint32_t *err = (uint32_t *)(p->scal + 2);
   uint32_t *n_items = err + 1;
@@ -352,13 +359,53 @@ ripk_status run_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_centres,
   HIPCHK(launch_finalize(p->binC, p->binW, S, g.n_s, g.n_t, (double)p->desc.s_max,
                          (double)p->desc.t_max, AD, Nn, p->outC, p->outW, p->outK, p->outL,
                          p->scal + 1, st));
-  if (simulate) {
-    if (L_obs) HIPCHK(hipMemcpyAsync(p->Lobs, L_obs, sizeof(double) * NB, hipMemcpyHostToDevice, st));
-    HIPCHK(launch_envelope(p->outK, p->outL, S, (int)NB, L_obs ? p->Lobs : nullptr, p->env, st));
-  }
+  if (simulate)
+    HIPCHK(launch_envelope(p->outK, p->outL, S, (int)NB, has_Lobs ? p->Lobs : nullptr, p->env, st));
   if (timing) HIPCHK(hipEventRecord(p->ev[4], st));
   p->stats.pair_grid = grid;
   p->stats.symmetric = symmetric ? 1 : 0;
+  return RIPK_OK;
+}
+
+// One evaluation of S sets: eager launches, or with RIPK_PLAN_GRAPH (on a
+// non-null stream, without per-phase timing) the replay of a graph captured
+// for this call shape -- sizes, inputs, seed and bound geometry; any change
+// captures afresh.
+ripk_status run_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_centres, const int32_t *x,
+                     const int32_t *y, const int32_t *t, bool simulate, uint64_t seed,
+                     const double *L_obs, hipStream_t st, bool symmetric) {
+  const uint32_t NB = (uint32_t)p->lay.info.n_bins;
+  const bool has_Lobs = simulate && L_obs != nullptr;
+  if (has_Lobs) HIPCHK(hipMemcpyAsync(p->Lobs, L_obs, sizeof(double) * NB, hipMemcpyHostToDevice, st));
+  const bool timing = (p->desc.flags & RIPK_PLAN_TIMING) != 0;
+  const bool graph = (p->desc.flags & RIPK_PLAN_GRAPH) && !timing && st != nullptr;
+  if (!graph)
+    return enqueue_sets(p, S, n, n_centres, x, y, t, simulate, seed, has_Lobs, st, symmetric, timing);
+  const uint64_t key[12] = {S, n, n_centres, (uint64_t)simulate, (uint64_t)symmetric,
+                            (uint64_t)(uintptr_t)x, (uint64_t)(uintptr_t)y, (uint64_t)(uintptr_t)t,
+                            seed, (uint64_t)has_Lobs, p->bind_gen, 1};
+  if (!p->gexec || std::memcmp(key, p->gkey, sizeof key) != 0) {
+    if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+    p->gexec = nullptr;
+    HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    const ripk_status s =
+        enqueue_sets(p, S, n, n_centres, x, y, t, simulate, seed, has_Lobs, st, symmetric, false);
+    hipGraph_t gr = nullptr;
+    const hipError_t e = hipStreamEndCapture(st, &gr);
+    if (s != RIPK_OK) {
+      if (gr) (void)hipGraphDestroy(gr);
+      return s;
+    }
+    if (e != hipSuccess) return fail(RIPK_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    const hipError_t ei = hipGraphInstantiate(&p->gexec, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    if (ei != hipSuccess) {
+      p->gexec = nullptr;
+      return fail(RIPK_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(ei));
+    }
+    std::memcpy(p->gkey, key, sizeof key);
+  }
+  HIPCHK(hipGraphLaunch(p->gexec, st));
   return RIPK_OK;
 }
 
@@ -507,6 +554,7 @@ ripk_status bind_geometry(ripk_plan_s *p, const ripk_plan_desc *desc, hipStream_
   p->lay = L;
   p->bound_cd = desc->cell_div ? desc->cell_div : 1;
   p->bound_td = desc->tcell_div ? desc->tcell_div : 1;
+  ++p->bind_gen;
   std::memset(p->S2h, 0, sizeof p->S2h);
   std::memset(p->Th, 0, sizeof p->Th);
   for (int k = 0; k < desc->n_s; ++k) p->S2h[k] = (uint64_t)L.info.S2[k];

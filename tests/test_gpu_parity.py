@@ -464,3 +464,43 @@ def test_sparse_windows_modes_agree_with_oracle():
             rs = oracle.estimate(d, xs, ys, ts)
             assert np.array_equal(out["sym"][1]["C_sims"][0], rs["C"].astype(np.uint64)), r["id"]
     say("sparse windows: %d requests agree" % len(reqs))
+
+
+def test_graph_replays_match_eager():
+    """RIPK_PLAN_GRAPH captures a call's launch sequence and replays it while the
+    call shape repeats.  Every replay, with eager work and synchronisations in
+    between, must equal the eager plan's result; a new seed or new inputs
+    capture afresh."""
+    import torch
+    c = workloads.workload("uniform-100k-99csr")
+    x, y, t = workloads.make_points(c)
+    n, m = len(x), 5
+    dx, dy, dt = (torch.from_numpy(a).cuda() for a in (x, y, t))
+    stream = torch.cuda.Stream()
+    eager = ripk.ripk_plan(make_desc_for(c, n, m))
+    graph = ripk.ripk_plan(make_desc_for(c, n, m, flags=ripk.RIPK_PLAN_GRAPH))
+    try:
+        r0 = ripk.ripk_compute_K(eager, dx, dy, dt)
+        e0 = {s: ripk.ripk_simulate_envelope(eager, n, m, s, L_obs=r0["L"], per_sim=True)
+              for s in (7, 8)}
+        for rep in range(4):
+            with torch.cuda.stream(stream):
+                r1 = ripk.ripk_compute_K(graph, dx, dy, dt, stream=stream.cuda_stream)
+                assert np.array_equal(r1["C"], r0["C"]) and np.array_equal(r1["W"], r0["W"]), rep
+                assert np.array_equal(r1["K"], r0["K"]) and np.array_equal(r1["L"], r0["L"]), rep
+                seed = 7 if rep != 2 else 8   # a different seed captures afresh
+                e1 = ripk.ripk_simulate_envelope(graph, n, m, seed, L_obs=r0["L"],
+                                                 stream=stream.cuda_stream, per_sim=True)
+                for k in ("C_sims", "W_sims", "K_lo", "K_hi", "L_lo", "L_hi", "dL_hi"):
+                    assert np.array_equal(e1[k], e0[seed][k]), (rep, k)
+                # eager work on the same stream between replays
+                z = (dx.to(torch.int64) * 3 - dy.to(torch.int64)).sum().item()
+            torch.cuda.synchronize()
+            assert z == int((x.astype(np.int64) * 3 - y.astype(np.int64)).sum())
+        # host inputs go through the plan's staging copy: also replayable
+        for rep in range(2):
+            r2 = ripk.ripk_compute_K(graph, x, y, t, stream=stream.cuda_stream)
+            assert np.array_equal(r2["C"], r0["C"]) and np.array_equal(r2["W"], r0["W"])
+    finally:
+        eager.destroy()
+        graph.destroy()
