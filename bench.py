@@ -246,6 +246,29 @@ def main():
         ripk.ripk_compute_K(plan, x, y, t)
     host_obs_ms = 1e3 * (time.perf_counter() - t_h) / 3
     n_in_obs = ripk.ripk_plan_stats(plan)["n_in"]
+    # the same step through a plan that replays captured HIP graphs (no per-phase
+    # timing), on a stream of its own, with the tuned cells of the timed plan
+    cd = max(1, round(cfg["s_max"] / cells["simulations"][0]))
+    td = max(1, round(cfg["t_max"] / cells["simulations"][1]))
+    gdesc = ripk.make_desc(cfg["window"], cfg["s_max"], cfg["t_max"], cfg["n_s"], cfg["n_t"],
+                           n_max=n, m_max=m, flags=ripk.RIPK_PLAN_GRAPH, cell_div=cd, tcell_div=td)
+    gplan = ripk.ripk_plan(gdesc)
+    gs = torch.cuda.Stream()
+    gsp = gs.cuda_stream
+
+    def gstep():
+        r = ripk.ripk_compute_K(gplan, dx, dy, dt, stream=gsp)
+        ripk.ripk_simulate_envelope(gplan, n, m, cfg["seed"], L_obs=r["L"], stream=gsp)
+
+    for _ in range(2):
+        gstep()
+    torch.cuda.synchronize()
+    t_g = time.perf_counter()
+    for _ in range(args.steps):
+        gstep()
+    torch.cuda.synchronize()
+    graph_ms = 1e3 * (time.perf_counter() - t_g) / args.steps
+    gplan.destroy()
     plan.destroy()
 
     ms = 1e3 * t_total / args.steps
@@ -278,6 +301,7 @@ def main():
                    "n": n, "sims": m, "n_s": cfg["n_s"], "n_t": cfg["n_t"],
                    "cells_m_s": cells, "autotune": not args.no_autotune},
         "sims_per_s": round(m / t_sim, 3),
+        "graph_ms_per_step": round(graph_ms, 4),
         "cold_ms": {"plan": round(plan_ms, 2),
                     "first_step_with_tuning": round(first_step_ms, 2) if not args.no_autotune else None},
         "observed_host_input": {"ms": round(host_obs_ms, 3),
