@@ -74,7 +74,7 @@ enum {
 #define RIPK_PLAN_AUTOTUNE (1u << 3)    /* pick the cell grid by timing: the first      */
                                         /* ripk_compute_K times each candidate cell     */
                                         /* subdivision on its own input, the first      */
-                                        /* ripk_simulate_envelope on up to 4 of its     */
+                                        /* ripk_simulate_envelope on up to 32 of its    */
                                         /* simulations; cell_div/tcell_div are ignored; */
                                         /* results do not depend on the cells            */
 #define RIPK_PLAN_GRAPH (1u << 4)       /* on a non-null stream and without             */
@@ -166,6 +166,8 @@ typedef struct {
   int64_t n_items;         /* work items of the pair kernel                              */
   int32_t pair_grid;       /* workgroups of the persistent pair kernel                   */
   int32_t symmetric;       /* 1 if unordered pairs were evaluated once                   */
+  int32_t split;           /* parts each work item's stencil rows were split into        */
+  int32_t reserved;
   double us_total;         /* wall time of the call, microseconds                        */
   double us_gen, us_grid, us_pair, us_finalize; /* device phases (RIPK_PLAN_TIMING)      */
 } ripk_stats;

@@ -67,7 +67,8 @@ Caps caps_for(int64_t S, int64_t n_max, int64_t n_cells, int64_t n_bins) {
   c.S = S;
   c.N = S * n_max;
   c.SNC = S * n_cells;
-  c.items = S * (n_max / kChunk + n_cells + kItemsPerGroup);
+  // room for items split kSplitMax ways when a launch holds few sets
+  c.items = std::max<int64_t>(S, kSplitMax) * (n_max / kChunk + n_cells + kItemsPerGroup);
   c.SNB = S * n_bins;
   c.NB = n_bins;
   return c;
@@ -211,7 +212,7 @@ ripk_status derive(const ripk_plan_desc *d, Layout *L) {
 // t_max) the autotuner times.
 constexpr int kTuneCand[][2] = {{1, 1}, {2, 1}, {1, 2}, {2, 2}, {3, 1}, {3, 2}};
 constexpr int kTuneN = (int)(sizeof kTuneCand / sizeof kTuneCand[0]);
-constexpr int kTuneSims = 4;  // simulations per timed candidate
+constexpr int kTuneSims = 32;  // simulations per timed candidate
 
 struct TuneState {
   bool done = false;
@@ -292,14 +293,14 @@ struct DeviceGuard {
   ~DeviceGuard() { (void)hipSetDevice(prev); }
 };
 
-// Runs the whole path over S sets of n points each.  For sims != 0 the points
-// are drawn on the device; otherwise keys come from (x, y, t).
-// Enqueues the launch sequence of one evaluation on st (kernels only, and
-// event records when timing): capturable into a graph.
+// Enqueues the launch sequence of one evaluation of S sets of n points each on
+// st (kernels only, and event records when timing): capturable into a graph.
+// With `simulate` the points are drawn on the device; otherwise keys come from
+// (x, y, t).
 ripk_status enqueue_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_centres,
                          const int32_t *x, const int32_t *y, const int32_t *t, bool simulate,
                          uint64_t seed, bool has_Lobs, hipStream_t st, bool symmetric,
-                         bool timing) {
+                         bool timing, uint32_t S_split) {
   const Geom &g = p->lay.g;
   const uint32_t NB = (uint32_t)p->lay.info.n_bins;
   const uint32_t N = S * n;
@@ -323,8 +324,25 @@ ripk_status enqueue_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_cent
   HIPCHK(launch_gather(p->vals[alt], N, x, y, t, g, p->lay.clamp_e, p->P, st));
   // row items need every point to be a centre (no halo entries inside a row)
   const bool row_items = n_centres == n;
-  HIPCHK(launch_items(p->cs, S, g, row_items, p->chunks, p->offs, p->set_base, p->items, n_items,
-                      p->scan_temp, st));
+  const int wide_counts =
+      ((int64_t)n >= kWideCountPoints || (p->desc.flags & RIPK_PLAN_WIDE_COUNTS)) ? 1 : 0;
+  int per_cu = 0;
+  HIPCHK(pair_occupancy((int)NB, wide_counts, symmetric ? 1 : 0, g.mode, &per_cu));
+  if (per_cu < 1) return fail(RIPK_EINVAL, "pair kernel does not fit on a compute unit (n_bins=%u)", NB);
+  // A launch with fewer groups than about twice the resident workgroups splits
+  // every item's stencil rows into `split` parts taken by different waves.
+  const int64_t slots = (int64_t)per_cu * p->cus;
+  const int64_t items_bound = (int64_t)S * (n / kChunk + g.n_cells + kItemsPerGroup);
+  // (sized for S_split sets: the autotuner times a few sets of a larger call)
+  const int64_t items_est = (int64_t)S_split * (n / kChunk + 1);
+  const uint32_t n_rows = symmetric ? (uint32_t)((g.rs + 1) + g.rt * (2 * g.rs + 1))
+                                    : (uint32_t)((2 * g.rt + 1) * (2 * g.rs + 1));
+  int64_t split = (2 * slots * kItemsPerGroup + items_est - 1) / items_est;
+  split = std::min<int64_t>({split, (int64_t)kSplitMax, (int64_t)n_rows,
+                             p->caps.items / std::max<int64_t>(items_bound, 1)});
+  split = std::max<int64_t>(split, 1);
+  HIPCHK(launch_items(p->cs, S, g, row_items, (uint32_t)split, n_rows, p->chunks, p->offs,
+                      p->set_base, p->items, n_items, p->scan_temp, st));
   HIPCHK(launch_fill_u64(p->binC, (size_t)S * NB, 0ull, st));
   HIPCHK(launch_fill_u64(p->binW, (size_t)S * NB * 2, 0ull, st));
   if (timing) HIPCHK(hipEventRecord(p->ev[2], st));
@@ -343,12 +361,9 @@ ripk_status enqueue_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_cent
   a.n_eval = p->scal;
   a.symmetric = symmetric ? 1 : 0;
   a.row_items = row_items ? 1 : 0;
-  a.wide_counts = ((int64_t)n >= kWideCountPoints || (p->desc.flags & RIPK_PLAN_WIDE_COUNTS)) ? 1 : 0;
-  int per_cu = 0;
-  HIPCHK(pair_occupancy((int)NB, a.wide_counts, a.symmetric, g.mode, &per_cu));
-  if (per_cu < 1) return fail(RIPK_EINVAL, "pair kernel does not fit on a compute unit (n_bins=%u)", NB);
-  const int64_t groups_cap = ((int64_t)S * (n / kChunk + g.n_cells + kItemsPerGroup)) / kItemsPerGroup + 1;
-  const int grid = (int)std::min<int64_t>((int64_t)per_cu * p->cus, groups_cap);
+  a.wide_counts = wide_counts;
+  const int64_t groups_cap = items_bound * split / kItemsPerGroup + 1;
+  const int grid = (int)std::min<int64_t>(slots, groups_cap);
   HIPCHK(launch_pair(a, grid, st));
   if (timing) HIPCHK(hipEventRecord(p->ev[3], st));
 
@@ -363,6 +378,7 @@ ripk_status enqueue_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_cent
     HIPCHK(launch_envelope(p->outK, p->outL, S, (int)NB, has_Lobs ? p->Lobs : nullptr, p->env, st));
   if (timing) HIPCHK(hipEventRecord(p->ev[4], st));
   p->stats.pair_grid = grid;
+  p->stats.split = (int32_t)split;
   p->stats.symmetric = symmetric ? 1 : 0;
   return RIPK_OK;
 }
@@ -373,23 +389,26 @@ ripk_status enqueue_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_cent
 // captures afresh.
 ripk_status run_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_centres, const int32_t *x,
                      const int32_t *y, const int32_t *t, bool simulate, uint64_t seed,
-                     const double *L_obs, hipStream_t st, bool symmetric) {
+                     const double *L_obs, hipStream_t st, bool symmetric, uint32_t S_split = 0) {
+  if (S_split == 0) S_split = S;
   const uint32_t NB = (uint32_t)p->lay.info.n_bins;
   const bool has_Lobs = simulate && L_obs != nullptr;
   if (has_Lobs) HIPCHK(hipMemcpyAsync(p->Lobs, L_obs, sizeof(double) * NB, hipMemcpyHostToDevice, st));
   const bool timing = (p->desc.flags & RIPK_PLAN_TIMING) != 0;
   const bool graph = (p->desc.flags & RIPK_PLAN_GRAPH) && !timing && st != nullptr;
   if (!graph)
-    return enqueue_sets(p, S, n, n_centres, x, y, t, simulate, seed, has_Lobs, st, symmetric, timing);
+    return enqueue_sets(p, S, n, n_centres, x, y, t, simulate, seed, has_Lobs, st, symmetric, timing,
+                        S_split);
   const uint64_t key[12] = {S, n, n_centres, (uint64_t)simulate, (uint64_t)symmetric,
                             (uint64_t)(uintptr_t)x, (uint64_t)(uintptr_t)y, (uint64_t)(uintptr_t)t,
-                            seed, (uint64_t)has_Lobs, p->bind_gen, 1};
+                            seed, (uint64_t)has_Lobs, p->bind_gen, S_split};
   if (!p->gexec || std::memcmp(key, p->gkey, sizeof key) != 0) {
     if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
     p->gexec = nullptr;
     HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     const ripk_status s =
-        enqueue_sets(p, S, n, n_centres, x, y, t, simulate, seed, has_Lobs, st, symmetric, false);
+        enqueue_sets(p, S, n, n_centres, x, y, t, simulate, seed, has_Lobs, st, symmetric, false,
+                     S_split);
     hipGraph_t gr = nullptr;
     const hipError_t e = hipStreamEndCapture(st, &gr);
     if (s != RIPK_OK) {
@@ -586,7 +605,7 @@ ripk_status run_tuned(ripk_plan_s *p, int which, uint32_t S, uint32_t S_tune, ui
         ripk_status s = bind_geometry(p, &d, st);
         if (s != RIPK_OK) return s;
         HIPCHK(hipEventRecord(p->tev[0], st));
-        s = run_sets(p, S_tune, n, nc, x, y, t, simulate, seed, nullptr, st, sym);
+        s = run_sets(p, S_tune, n, nc, x, y, t, simulate, seed, nullptr, st, sym, S);
         if (s != RIPK_OK) return s;
         HIPCHK(hipEventRecord(p->tev[1], st));
         uint32_t err = 0;

@@ -318,8 +318,11 @@ __global__ void k_chunks(const uint32_t *__restrict__ cs, uint32_t nunit_total, 
 }
 
 // per set: padded item base so that every group of kItemsPerGroup items lies in one set
+// Item bases per set (before splitting), each set padded to whole groups; the
+// emitted array holds every item `split` times, once per part of its stencil
+// rows.
 __global__ void k_set_base(const uint32_t *__restrict__ offs, uint32_t n_sets,
-                           uint32_t n_units, uint32_t *__restrict__ set_base,
+                           uint32_t n_units, uint32_t split, uint32_t *__restrict__ set_base,
                            uint32_t *__restrict__ n_items) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   uint32_t run = 0;
@@ -329,27 +332,39 @@ __global__ void k_set_base(const uint32_t *__restrict__ offs, uint32_t n_sets,
     run += (tot + kItemsPerGroup - 1) / kItemsPerGroup * kItemsPerGroup;
   }
   set_base[n_sets] = run;
-  *n_items = run;
+  *n_items = run * split;
+}
+
+// count word of part p of `split` parts of n_rows stencil rows (see Item)
+__device__ __forceinline__ uint32_t item_count(uint32_t cnt, uint32_t p, uint32_t split,
+                                               uint32_t n_rows) {
+  if (split == 1) return cnt;
+  const uint32_t r0 = p * n_rows / split, r1 = (p + 1) * n_rows / split;
+  return cnt | (r0 << 7) | (r1 << 19);
 }
 
 __global__ void k_emit(const uint32_t *__restrict__ cs, const uint32_t *__restrict__ offs,
                        const uint32_t *__restrict__ set_base, uint32_t n_sets, uint32_t n_units,
-                       uint32_t unit, Item *__restrict__ items) {
+                       uint32_t unit, uint32_t split, uint32_t n_rows,
+                       Item *__restrict__ items) {
   uint32_t gidx = blockIdx.x * blockDim.x + threadIdx.x;
   if (gidx >= n_sets * n_units) return;
   uint32_t s = gidx / n_units, c = gidx - s * n_units;
   uint32_t o = set_base[s] + offs[gidx] - offs[s * n_units];
   chunk_walk(cs, gidx, unit, [&](uint32_t b, uint32_t cnt) {
-    Item it;
-    it.set = s;
-    it.cell = c;
-    it.begin = b;
-    it.count = cnt;
-    items[o++] = it;
+    for (uint32_t p = 0; p < split; ++p) {
+      Item it;
+      it.set = s;
+      it.cell = c;
+      it.begin = b;
+      it.count = item_count(cnt, p, split, n_rows);
+      items[o * split + p] = it;
+    }
+    ++o;
   });
   if (c == n_units - 1) {
     uint32_t end = set_base[s] + offs[(s + 1) * n_units] - offs[s * n_units];
-    for (uint32_t p = end; p < set_base[s + 1]; ++p) {
+    for (uint32_t p = end * split; p < set_base[s + 1] * split; ++p) {
       Item it;
       it.set = s;
       it.cell = 0;
@@ -458,8 +473,9 @@ hipError_t launch_gather(const uint32_t *vals, uint32_t n, const int32_t *x, con
 }
 
 hipError_t launch_items(const uint32_t *cs, uint32_t n_sets, const Geom &g, bool row_items,
-                        uint32_t *chunks, uint32_t *offs, uint32_t *set_base, Item *items,
-                        uint32_t *n_items, void *scan_temp, hipStream_t s) {
+                        uint32_t split, uint32_t n_rows, uint32_t *chunks, uint32_t *offs,
+                        uint32_t *set_base, Item *items, uint32_t *n_items, void *scan_temp,
+                        hipStream_t s) {
   const uint32_t unit = row_items ? (uint32_t)g.nx : 1u;
   const uint32_t n_units = g.n_cells / unit;
   const uint32_t tot = n_sets * n_units;
@@ -467,10 +483,10 @@ hipError_t launch_items(const uint32_t *cs, uint32_t n_sets, const Geom &g, bool
                      unit, chunks);
   hipError_t e = exclusive_scan(chunks, offs, tot, scan_temp, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_set_base, dim3(1), dim3(64), 0, s, offs, n_sets, n_units, set_base,
-                     n_items);
+  hipLaunchKernelGGL(k_set_base, dim3(1), dim3(64), 0, s, offs, n_sets, n_units, split,
+                     set_base, n_items);
   hipLaunchKernelGGL(k_emit, dim3(blocks_for(tot, kThreads)), dim3(kThreads), 0, s, cs, offs,
-                     set_base, n_sets, n_units, unit, items);
+                     set_base, n_sets, n_units, unit, split, n_rows, items);
   return hipGetLastError();
 }
 

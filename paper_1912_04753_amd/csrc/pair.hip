@@ -590,8 +590,12 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
       __syncthreads();
     }
     const Item it = a.items[base + wv];
-    const uint32_t cnt = uni(it.count);
+    const uint32_t cw = uni(it.count);
+    const uint32_t cnt = cw & 0x7Fu;
     if (cnt == 0) continue;
+    // the part of the stencil rows this item covers (all when not split)
+    const int r0 = (int)((cw >> 7) & 0xFFFu);
+    const int r1 = (cw >> 19) ? (int)(cw >> 19) : 0x7FFFFFFF;
     const uint32_t begin = uni(it.begin);
     const uint32_t cell = uni(it.cell);
     const bool valid = (uint32_t)lane < cnt;
@@ -625,11 +629,14 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
     QState q = {0u, 0u, 0u, 0u};
     Ctx<SYM, MODE> x{W, q, g, hist, histc, wide, S2lo, S2hi, T, lane};
     unsigned long long ev = 0;
+    int ridx = 0;  // index of the stencil row in visiting order
     for (int dt = SYM ? 0 : -g.rt; dt <= g.rt; ++dt) {
       const int tt = ct + dt;
-      if (tt < 0 || tt >= g.nt) continue;
       for (int dy = -g.rs; dy <= g.rs; ++dy) {
         if (SYM && dt == 0 && dy < 0) continue;
+        const int rid = ridx++;
+        if (rid < r0 || rid >= r1) continue;
+        if (tt < 0 || tt >= g.nt) continue;
         const int yy = cy + dy;
         if (yy < 0 || yy >= g.ny) continue;
         const bool home = (dt == 0 && dy == 0);

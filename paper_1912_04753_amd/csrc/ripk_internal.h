@@ -44,8 +44,11 @@ struct Item {
   uint32_t set;
   uint32_t cell;   // unit index within the set: cell, or row (t * ny + y)
   uint32_t begin;  // first centre, index into the sorted point array
-  uint32_t count;  // number of centres (0 = padding)
+  uint32_t count;  // bits 0-6: number of centres (0 = padding); bits 7-18 and
+                   // 19-30: first and end index of the stencil rows this item
+                   // covers (end 0 = all rows; items split for small launches)
 };
+constexpr int kSplitMax = 8;  // stencil-row parts an item may be split into
 
 struct PairArgs {
   Geom g;
@@ -105,7 +108,7 @@ hipError_t launch_gather(const uint32_t *vals, uint32_t n, const int32_t *x, con
                          const int32_t *t, const Geom &g, int32_t clamp_e, int4 *P,
                          hipStream_t s);
 hipError_t launch_items(const uint32_t *cs, uint32_t n_sets, const Geom &g, bool row_items,
-                        uint32_t *chunks,
+                        uint32_t split, uint32_t n_rows, uint32_t *chunks,
                         uint32_t *offs, uint32_t *set_base, Item *items, uint32_t *n_items,
                         void *scan_temp, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, size_t n, unsigned long long v,
