@@ -71,6 +71,12 @@ def lib():
         L.orc_philox4x64_10.argtypes = [u64p, u64p, u64p]
         L.orc_csr_points.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64, dp,
                                      i32p, i32p, i32p]
+        L.orc_permute_points.argtypes = [i32p, i32p, i32p, ctypes.c_int64, ctypes.c_int64,
+                                         ctypes.c_uint64, i32p, i32p, i32p]
+        L.orc_permute_points.restype = ctypes.c_int
+        L.orc_bootstrap_points.argtypes = [i32p, i32p, i32p, ctypes.c_int64, ctypes.c_int64,
+                                           ctypes.c_uint64, i32p, i32p, i32p]
+        L.orc_bootstrap_points.restype = None
         L.orc_envelope.argtypes = [dp, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64,
                                    ctypes.c_int, f64p, f64p, f64p, f64p, u64p, f64p, f64p]
         L.orc_now.restype = ctypes.c_double
@@ -170,6 +176,39 @@ def csr_points(d, n, sim, seed):
                          _ptr(x, ctypes.c_int32), _ptr(y, ctypes.c_int32),
                          _ptr(t, ctypes.c_int32))
     return x, y, t
+
+
+SIM_CSR, SIM_PERMUTE, SIM_BOOTSTRAP = 0, 1, 2
+
+
+def resampled_points(x, y, t, sim, seed, method):
+    """Simulation ``sim`` drawn from the observed points (Sec. 3): random
+    permutation of the time labels, or a bootstrap sample with replacement."""
+    x, y, t = _soa(x, y, t)
+    n = len(x)
+    xs, ys, ts = (np.zeros(n, np.int32) for _ in range(3))
+    args = (_ptr(x, ctypes.c_int32), _ptr(y, ctypes.c_int32), _ptr(t, ctypes.c_int32), n, int(sim),
+            int(seed) & (2**64 - 1), _ptr(xs, ctypes.c_int32), _ptr(ys, ctypes.c_int32),
+            _ptr(ts, ctypes.c_int32))
+    if method == SIM_PERMUTE:
+        if lib().orc_permute_points(*args):
+            raise MemoryError("orc_permute_points")
+    elif method == SIM_BOOTSTRAP:
+        lib().orc_bootstrap_points(*args)
+    else:
+        raise ValueError(method)
+    return xs, ys, ts
+
+
+def envelope_resampled(d, x, y, t, m, seed, method, threads=0):
+    """Min/max envelopes over m simulations drawn from the observed points."""
+    sims = [estimate(d, *resampled_points(x, y, t, s, seed, method), threads=threads)
+            for s in range(m)]
+    res = {"K_sims": np.stack([r["K"] for r in sims]), "C_sims": np.stack([r["C"] for r in sims]),
+           "W_sims": np.stack([r["W"] for r in sims])}
+    Ls = np.stack([r["L"] for r in sims])
+    res.update(K_lo=res["K_sims"].min(0), K_hi=res["K_sims"].max(0), L_lo=Ls.min(0), L_hi=Ls.max(0))
+    return res
 
 
 def envelope(d, n, m, seed, threads=0, per_sim=True):

@@ -291,6 +291,59 @@ void orc_csr_points(int64_t n, int64_t sim, uint64_t seed, const orc_desc *q, in
   }
 }
 
+/* Random permutation (Sec. 3): a copy of the observed points whose temporal
+ * labels are exchanged at random.  Simulation `sim` keeps every location and
+ * gives point i the time of point order[i], where order lists the points by
+ * increasing u_j = high 32 bits of word 0 of Philox(counter=(j,sim,0,0),
+ * key=(seed,1)), equal u by index. */
+typedef struct {
+  uint32_t u;
+  int64_t i;
+} orc_rank;
+
+static int orc_rank_cmp(const void *a, const void *b) {
+  const orc_rank *p = (const orc_rank *)a, *q = (const orc_rank *)b;
+  if (p->u != q->u) return p->u < q->u ? -1 : 1;
+  return p->i < q->i ? -1 : (p->i > q->i ? 1 : 0);
+}
+
+int orc_permute_points(const int32_t *x, const int32_t *y, const int32_t *t, int64_t n,
+                       int64_t sim, uint64_t seed, int32_t *xs, int32_t *ys, int32_t *ts) {
+  orc_rank *r = (orc_rank *)malloc(sizeof(orc_rank) * (size_t)(n > 0 ? n : 1));
+  if (!r) return -1;
+  const uint64_t key[2] = {seed, 1};
+  for (int64_t j = 0; j < n; ++j) {
+    uint64_t ctr[4] = {(uint64_t)j, (uint64_t)sim, 0, 0}, w[4];
+    orc_philox4x64_10(ctr, key, w);
+    r[j].u = (uint32_t)(w[0] >> 32);
+    r[j].i = j;
+  }
+  qsort(r, (size_t)n, sizeof(orc_rank), orc_rank_cmp);
+  for (int64_t i = 0; i < n; ++i) {
+    xs[i] = x[i];
+    ys[i] = y[i];
+    ts[i] = t[r[i].i];
+  }
+  free(r);
+  return 0;
+}
+
+/* Bootstrap (Sec. 3): points sampled at random with replacement from the
+ * observed points.  Point i of simulation `sim` is observed point
+ * floor(r0 * n / 2^64), r = Philox(counter=(i,sim,0,0), key=(seed,2)). */
+void orc_bootstrap_points(const int32_t *x, const int32_t *y, const int32_t *t, int64_t n,
+                          int64_t sim, uint64_t seed, int32_t *xs, int32_t *ys, int32_t *ts) {
+  const uint64_t key[2] = {seed, 2};
+  for (int64_t i = 0; i < n; ++i) {
+    uint64_t ctr[4] = {(uint64_t)i, (uint64_t)sim, 0, 0}, w[4];
+    orc_philox4x64_10(ctr, key, w);
+    const int64_t j = (int64_t)mulhi64(w[0], (uint64_t)n);
+    xs[i] = x[j];
+    ys[i] = y[j];
+    ts[i] = t[j];
+  }
+}
+
 /* Simulation envelope: for sims 0..m-1, draw the CSR set, estimate K and L,
  * and keep the pointwise minimum and maximum over the simulations (Sec. 3).
  * Per-simulation C, W, K (m*n_s*n_t each) are returned when asked for. */

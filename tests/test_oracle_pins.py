@@ -386,3 +386,80 @@ def test_envelope_min_max_semantics():
     r = oracle.estimate(d, x, y, tt)
     assert np.array_equal(r["C"], env["C_sims"][5])
     assert np.allclose(r["K"], Ks[5], rtol=1e-15, atol=0)
+
+
+# ------------------------------------------------- resampled simulations ----
+def _numpy_block(key, ctr):
+    """Philox4x64-10 block at counter ``ctr`` from numpy's generator (which
+    increments its 256-bit counter before generating, so start one below)."""
+    c = [int(v) for v in ctr]
+    for w in range(4):  # 256-bit decrement with borrow
+        c[w] = (c[w] - 1) % 2**64
+        if c[w] != 2**64 - 1:
+            break
+    bg = np.random.Philox(key=np.array(key, np.uint64), counter=np.array(c, np.uint64))
+    return [int(v) for v in bg.random_raw(4)]
+
+
+def test_permutation_is_the_argsort_of_philox_keys():
+    """Random permutation (Sec. 3): locations kept, time labels exchanged; point i
+    takes the time of the point ranked i-th by the high 32 bits of Philox word 0
+    (key (seed, 1), counter (j, sim, 0, 0)), ties by index."""
+    rng = np.random.default_rng(3)
+    n, seed = 300, 77
+    x = rng.integers(0, 1000, n).astype(np.int32)
+    y = rng.integers(0, 1000, n).astype(np.int32)
+    t = rng.integers(0, 10**6, n).astype(np.int32)
+    for sim in (0, 5):
+        u = np.array([_numpy_block([seed, 1], [j, sim, 0, 0])[0] >> 32 for j in range(n)], np.uint64)
+        order = np.argsort(u, kind="stable")
+        xs, ys, ts = oracle.resampled_points(x, y, t, sim, seed, oracle.SIM_PERMUTE)
+        assert np.array_equal(xs, x) and np.array_equal(ys, y)
+        assert np.array_equal(ts, t[order])
+        assert np.array_equal(np.sort(ts), np.sort(t))
+
+
+def test_bootstrap_indices_follow_philox():
+    """Bootstrap (Sec. 3): point i of simulation sim is observed point
+    floor(r0 * n / 2^64), r = Philox(key (seed, 2), counter (i, sim, 0, 0))."""
+    rng = np.random.default_rng(4)
+    n, seed, sim = 257, 9, 3
+    x = rng.integers(0, 1000, n).astype(np.int32)
+    y = rng.integers(0, 1000, n).astype(np.int32)
+    t = np.arange(n, dtype=np.int32) * 7
+    idx = np.array([(_numpy_block([seed, 2], [i, sim, 0, 0])[0] * n) >> 64 for i in range(n)])
+    xs, ys, ts = oracle.resampled_points(x, y, t, sim, seed, oracle.SIM_BOOTSTRAP)
+    assert np.array_equal(xs, x[idx]) and np.array_equal(ys, y[idx]) and np.array_equal(ts, t[idx])
+    assert len(np.unique(idx)) < n  # with replacement
+
+
+def test_permutation_labels_are_uniform():
+    """Over many simulations each position receives each label equally often."""
+    n, sims = 6, 6000
+    x = np.zeros(n, np.int32); y = np.zeros(n, np.int32); t = np.arange(n, dtype=np.int32)
+    counts = np.zeros((n, n))
+    for s in range(sims):
+        _, _, ts = oracle.resampled_points(x, y, t, s, 123, oracle.SIM_PERMUTE)
+        counts[np.arange(n), ts] += 1
+    e = sims / n
+    chi2 = float(((counts - e) ** 2 / e).sum())
+    assert chi2 < 80.0  # 25 dof; p < 1e-6 otherwise
+
+
+def test_permuted_set_keeps_spatial_counts():
+    """With the temporal threshold covering the whole period, exchanging time
+    labels cannot change which pairs are within s: the last column of C (all u)
+    equals the observed one, while inner columns differ."""
+    rng = np.random.default_rng(5)
+    win = (0, 0, 4000, 4000, 0, 100_000)
+    n = 400
+    x = rng.integers(0, 4001, n).astype(np.int32)
+    y = rng.integers(0, 4001, n).astype(np.int32)
+    t = rng.integers(0, 100_001, n).astype(np.int32)
+    d = oracle.desc(win, 800, 100_000, 8, 5, edge=0)
+    obs = oracle.estimate(d, x, y, t)
+    env = oracle.envelope_resampled(d, x, y, t, 3, 11, oracle.SIM_PERMUTE)
+    for s in range(3):
+        assert np.array_equal(env["C_sims"][s][:, -1], obs["C"][:, -1])
+        assert not np.array_equal(env["C_sims"][s][:, :-1], obs["C"][:, :-1])
+    assert np.all(env["K_lo"] <= env["K_hi"])
