@@ -60,8 +60,18 @@ enum {
 #define RIPK_NORM_NN1 0u
 #define RIPK_NORM_N2 1u
 
-/* simulation method (Sec. 3): Monte Carlo under complete spatio-temporal randomness */
+/* simulation methods (Sec. 3).  CSR: Monte Carlo under complete spatio-temporal
+ * randomness, drawn on the device (see ripk_simulate_envelope).  PERMUTE: a copy
+ * of the observed points with their time labels exchanged at random; set s
+ * gives point k the time of observed point order_s[k], where order_s lists the
+ * points by increasing high 32 bits of word 0 of Philox4x64-10(counter
+ * (j, s, 0, 0), key (seed, 1)), equal values by index.  BOOTSTRAP: points drawn
+ * with replacement; point k of set s is observed point floor(r0 * n / 2^64),
+ * r = Philox4x64-10((k, s, 0, 0), (seed, 2)).  PERMUTE and BOOTSTRAP draw from
+ * the observed set of the plan's last successful ripk_compute_K. */
 #define RIPK_SIM_CSR 0u
+#define RIPK_SIM_PERMUTE 1u
+#define RIPK_SIM_BOOTSTRAP 2u
 
 /* plan flags */
 #define RIPK_PLAN_ORDERED (1u << 0) /* evaluate ordered pairs (full stencil) even when   */
@@ -188,12 +198,14 @@ void ripk_plan_destroy(ripk_plan_t plan);
 ripk_status ripk_compute_K(ripk_plan_t plan, const ripk_points *pts, void *stream,
                            ripk_K_out *out);
 
-/* m Monte Carlo CSR simulations of n points each, drawn on the device with
+/* m simulations of n points each, drawn on the device by the plan's method
+ * and evaluated together, with pointwise min/max envelopes (Sec. 3).  CSR uses
  * Philox4x64-10 (key = (seed, 0), counter = (point, simulation, 0, 0), x from
  * the first output word by a 64x64 multiply-high onto [x0, x1), y and t
- * likewise from the second and third), evaluated together, with pointwise
- * min/max envelopes (Sec. 3).  L_obs (host, n_s*n_t, optional) gives dL_hi.
- * Errors: EINVAL (n < 2, n > n_max, m < 1, m > m_max), EDEVICE. */
+ * likewise from the second and third); PERMUTE and BOOTSTRAP see
+ * RIPK_SIM_PERMUTE.  L_obs (host, n_s*n_t, optional) gives dL_hi.
+ * Errors: EINVAL (n < 2, n > n_max, m < 1, m > m_max; PERMUTE or BOOTSTRAP
+ * without a previous ripk_compute_K of n points), EDEVICE. */
 ripk_status ripk_simulate_envelope(ripk_plan_t plan, int64_t n, int32_t m, uint64_t seed,
                                    const double *L_obs, void *stream, ripk_env_out *out);
 

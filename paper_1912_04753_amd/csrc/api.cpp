@@ -71,6 +71,7 @@ Caps caps_for(int64_t S, int64_t n_max, int64_t n_cells, int64_t n_bins) {
   c.items = std::max<int64_t>(S, kSplitMax) * (n_max / kChunk + n_cells + kItemsPerGroup);
   c.SNB = S * n_bins;
   c.NB = n_bins;
+  c.P = n_max;
   return c;
 }
 
@@ -86,12 +87,14 @@ int64_t caps_bytes(const Caps &c) {
   bytes += 8 * 3 * c.SNB;                     // bins
   bytes += 8 * 4 * c.SNB;                     // C, W, K, L
   bytes += 8 * 6 * c.NB + 8 * 2 * kMaxSteps + 32;
+  bytes += 3 * 4 * c.P;                       // copy of the observed set (resampling)
   return bytes;
 }
 
 bool caps_fit(const Caps &have, const Caps &need) {
   return need.S <= have.S && need.N <= have.N && need.SNC <= have.SNC &&
-         need.items <= have.items && need.SNB <= have.SNB && need.NB <= have.NB;
+         need.items <= have.items && need.SNB <= have.SNB && need.NB <= have.NB &&
+         need.P <= have.P;
 }
 
 Caps caps_max(const Caps &a, const Caps &b) {
@@ -102,6 +105,7 @@ Caps caps_max(const Caps &a, const Caps &b) {
   c.items = std::max(a.items, b.items);
   c.SNB = std::max(a.SNB, b.SNB);
   c.NB = std::max(a.NB, b.NB);
+  c.P = std::max(a.P, b.P);
   return c;
 }
 
@@ -135,7 +139,9 @@ ripk_status derive(const ripk_plan_desc *d, Layout *L) {
   if ((d->edge & RIPK_EDGE_TEMPORAL) && d->t_max > D)
     return fail(RIPK_EINVAL, "temporal correction needs t_max <= t1-t0");
   if (d->norm > RIPK_NORM_N2) return fail(RIPK_EINVAL, "unknown normalisation");
-  if (d->sim_method != RIPK_SIM_CSR) return fail(RIPK_EINVAL, "unknown simulation method");
+  if (d->sim_method != RIPK_SIM_CSR && d->sim_method != RIPK_SIM_PERMUTE &&
+      d->sim_method != RIPK_SIM_BOOTSTRAP)
+    return fail(RIPK_EINVAL, "unknown simulation method");
   if (d->n_max < 2) return fail(RIPK_EINVAL, "n_max must be >= 2");
   if (d->m_max < 0) return fail(RIPK_EINVAL, "m_max must be >= 0");
   const int64_t S = std::max<int64_t>(1, d->m_max);
@@ -239,6 +245,8 @@ struct ripk_plan_s {
   uint32_t Th[kMaxSteps] = {};
   // device buffers
   int32_t *x = nullptr, *y = nullptr, *t = nullptr;
+  int32_t *ox = nullptr, *oy = nullptr, *ot = nullptr;  // last observed set (resampling)
+  int64_t obs_n = 0;
   uint32_t *keys[2] = {nullptr, nullptr}, *vals[2] = {nullptr, nullptr};
   void *sort_temp = nullptr;
   uint32_t *cs = nullptr;
@@ -269,7 +277,8 @@ void release(ripk_plan_s *p) {
   int prev = 0;
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(p->device);
-  void *bufs[] = {p->x, p->y, p->t, p->keys[0], p->keys[1], p->vals[0], p->vals[1],
+  void *bufs[] = {p->x, p->y, p->t, p->ox, p->oy, p->ot, p->keys[0], p->keys[1], p->vals[0],
+                  p->vals[1],
                   p->sort_temp, p->cs, p->P, p->chunks, p->offs, p->set_base, p->scan_temp,
                   p->items, p->binC, p->binW, p->outC, p->outW, p->outK, p->outL, p->env,
                   p->Lobs, p->S2, p->T, p->scal};
@@ -310,7 +319,12 @@ ripk_status enqueue_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_cent
   uint32_t *item_ctr = err + 2;
   HIPCHK(launch_fill_u64(p->scal, 4, 0ull, st));
   if (simulate) {
-    HIPCHK(launch_csr(n, S, seed, g, p->x, p->y, p->t, p->keys[0], p->vals[0], st));
+    if (p->desc.sim_method == RIPK_SIM_CSR)
+      HIPCHK(launch_csr(n, S, seed, g, p->x, p->y, p->t, p->keys[0], p->vals[0], st));
+    else
+      HIPCHK(launch_resample(p->desc.sim_method == RIPK_SIM_PERMUTE ? 1 : 2, n, S, seed, p->ox,
+                             p->oy, p->ot, g, p->x, p->y, p->t, p->keys, p->vals, p->sort_temp,
+                             st));
     x = p->x; y = p->y; t = p->t;
   } else {
     HIPCHK(launch_keys(x, y, t, n, n_centres, 0, 1, g, p->keys[0], p->vals[0], err, st));
@@ -492,6 +506,7 @@ ripk_status plan_create(int device, const Caps &c, ripk_plan_s **out) {
 #define ALLOC(ptr, cnt) \
   if (e == hipSuccess) e = dalloc(&(ptr), (size_t)(cnt))
   ALLOC(p->x, c.N); ALLOC(p->y, c.N); ALLOC(p->t, c.N);
+  ALLOC(p->ox, c.P); ALLOC(p->oy, c.P); ALLOC(p->ot, c.P);
   ALLOC(p->keys[0], c.N); ALLOC(p->keys[1], c.N); ALLOC(p->vals[0], c.N); ALLOC(p->vals[1], c.N);
   if (e == hipSuccess) e = hipMalloc(&p->sort_temp, radix_sort_temp_bytes((uint32_t)c.N));
   ALLOC(p->cs, 2 * c.SNC + 1);
@@ -533,6 +548,7 @@ ripk_status plan_bind(ripk_plan_s *p, const ripk_plan_desc *desc, hipStream_t st
   p->user_desc = *desc;
   p->tune[0] = TuneState();
   p->tune[1] = TuneState();
+  p->obs_n = 0;  // no observed set for resampled simulations yet
   return RIPK_OK;
 }
 
@@ -708,6 +724,13 @@ ripk_status ripk_compute_K(ripk_plan_t p, const ripk_points *pts, void *stream, 
     HIPCHK(hipMemcpyAsync(p->t, t, sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
     x = p->x; y = p->y; t = p->t;
   }
+  if (p->desc.sim_method != RIPK_SIM_CSR) {
+    // resampled simulations draw from this set: keep a copy
+    HIPCHK(hipMemcpyAsync(p->ox, x, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(p->oy, y, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(p->ot, t, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st));
+    p->obs_n = 0;  // set once the call succeeds
+  }
   const bool sym = !(p->desc.flags & RIPK_PLAN_ORDERED) && nc == n;
   ripk_status s = run_tuned(p, 0, 1, 1, (uint32_t)n, (uint32_t)nc, x, y, t, false, 0, nullptr, st,
                             sym);
@@ -716,6 +739,7 @@ ripk_status ripk_compute_K(ripk_plan_t p, const ripk_points *pts, void *stream, 
   s = collect_stats(p, st, 1, (uint32_t)n, &err);
   if (s != RIPK_OK) return s;
   if (err) return fail(RIPK_ERANGE, "a point lies outside the study window");
+  if (p->desc.sim_method != RIPK_SIM_CSR) p->obs_n = n;
   const size_t NB = (size_t)p->lay.info.n_bins;
   if (out) {
     if (out->C) HIPCHK(hipMemcpyAsync(out->C, p->outC, 8 * NB, hipMemcpyDeviceToHost, st));
@@ -734,6 +758,10 @@ ripk_status ripk_simulate_envelope(ripk_plan_t p, int64_t n, int32_t m, uint64_t
   if (n < 2) return fail(RIPK_EINVAL, "need n >= 2 points");
   if (n > p->desc.n_max) return fail(RIPK_EINVAL, "n = %lld exceeds n_max = %lld", (long long)n, (long long)p->desc.n_max);
   if (m < 1 || m > p->desc.m_max) return fail(RIPK_EINVAL, "m = %d outside [1, m_max = %d]", m, p->desc.m_max);
+  if (p->desc.sim_method != RIPK_SIM_CSR && p->obs_n != n)
+    return fail(RIPK_EINVAL,
+                "permutation and bootstrap simulations draw from the plan's last observed set: "
+                "call ripk_compute_K on %lld points first", (long long)n);
   auto t0 = std::chrono::steady_clock::now();
   DeviceGuard dg(p->device);
   hipStream_t st = (hipStream_t)stream;

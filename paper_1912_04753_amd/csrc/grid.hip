@@ -96,6 +96,76 @@ __global__ void k_csr(uint32_t n, uint32_t m, uint64_t seed, Geom g, int32_t *__
   vals[gid] = (uint32_t)gid;
 }
 
+// ---- simulations drawn from the observed points (Sec. 3) --------------------
+// Random permutation keeps every location and exchanges time labels: set s
+// gives point k the time of observed point order_s[k], where order_s lists the
+// points by increasing high 32 bits of word 0 of Philox(counter (j, s, 0, 0),
+// key (seed, 1)), equal values by index.  Bootstrap takes point k of set s
+// from observed point floor(r0 * n / 2^64), r = Philox((k, s, 0, 0), (seed, 2)).
+
+// permutation, stage 1: the random rank key of every (set, point); value = index
+__global__ void k_perm_keys(uint32_t n, uint32_t m, uint64_t seed, uint32_t *__restrict__ keys,
+                            uint32_t *__restrict__ vals) {
+  uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (uint64_t)n * m) return;
+  uint32_t s = (uint32_t)(gid / n), i = (uint32_t)(gid - (uint64_t)s * n);
+  U64x4 c;
+  c.v[0] = i;
+  c.v[1] = s;
+  c.v[2] = 0;
+  c.v[3] = 0;
+  U64x4 r = philox4x64_10(c, seed, 1);
+  keys[gid] = (uint32_t)(r.v[0] >> 32);
+  vals[gid] = (uint32_t)gid;
+}
+
+// permutation, stage 2 key: the set of each entry (a stable sort by it keeps
+// the rank order inside every set)
+__global__ void k_set_of(const uint32_t *__restrict__ vals, uint64_t total, uint32_t n,
+                         uint32_t *__restrict__ keys) {
+  uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= total) return;
+  keys[gid] = vals[gid] / n;
+}
+
+// Assembles the simulated sets (as k_csr does for CSR): points and cell keys.
+// `order` (permutation only) may be the same array as `vals`: each thread reads
+// its own entry before writing it.
+__global__ void k_resample(uint32_t n, uint32_t m, uint64_t seed, int method,
+                           const uint32_t *order, const int32_t *__restrict__ ox,
+                           const int32_t *__restrict__ oy, const int32_t *__restrict__ ot, Geom g,
+                           int32_t *__restrict__ x, int32_t *__restrict__ y,
+                           int32_t *__restrict__ t, uint32_t *__restrict__ keys, uint32_t *vals) {
+  uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (uint64_t)n * m) return;
+  uint32_t s = (uint32_t)(gid / n), k = (uint32_t)(gid - (uint64_t)s * n);
+  int32_t px, py, pt;
+  if (method == 1) {
+    const uint32_t src = order[gid] - s * n;
+    px = ox[k];
+    py = oy[k];
+    pt = ot[src];
+  } else {
+    U64x4 c;
+    c.v[0] = k;
+    c.v[1] = s;
+    c.v[2] = 0;
+    c.v[3] = 0;
+    U64x4 r = philox4x64_10(c, seed, 2);
+    const uint32_t j = (uint32_t)__umul64hi(r.v[0], (uint64_t)n);
+    px = ox[j];
+    py = oy[j];
+    pt = ot[j];
+  }
+  x[gid] = px;
+  y[gid] = py;
+  t[gid] = pt;
+  bool bad;
+  uint32_t cell = cell_of(px, py, pt, g, &bad);
+  keys[gid] = (s * g.n_cells + cell) << 1;
+  vals[gid] = (uint32_t)gid;
+}
+
 // ---- exclusive scan of uint32 (3 phases) ------------------------------------
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kThreads * kScanItems;
@@ -401,6 +471,38 @@ hipError_t launch_csr(uint32_t n, uint32_t m, uint64_t seed, const Geom &g, int3
   if (tot == 0) return hipSuccess;
   hipLaunchKernelGGL(k_csr, dim3(blocks_for(tot, kThreads)), dim3(kThreads), 0, s, n, m, seed,
                      g, x, y, t, keys, vals);
+  return hipGetLastError();
+}
+
+hipError_t launch_resample(int method, uint32_t n, uint32_t m, uint64_t seed, const int32_t *ox,
+                           const int32_t *oy, const int32_t *ot, const Geom &g, int32_t *x,
+                           int32_t *y, int32_t *t, uint32_t *keys[2], uint32_t *vals[2],
+                           void *sort_temp, hipStream_t s) {
+  const uint64_t tot = (uint64_t)n * m;
+  if (tot == 0) return hipSuccess;
+  const dim3 grid(blocks_for(tot, kThreads)), block(kThreads);
+  const uint32_t *order = nullptr;
+  if (method == 1) {
+    hipLaunchKernelGGL(k_perm_keys, grid, block, 0, s, n, m, seed, keys[0], vals[0]);
+    int alt = 0;
+    hipError_t e = radix_sort(keys[0], vals[0], keys[1], vals[1], (uint32_t)tot, 32, sort_temp, s,
+                              &alt);
+    if (e != hipSuccess) return e;
+    int a = alt;  // buffer holding the rank order
+    if (m > 1) {
+      int bits = 0;
+      while ((1u << bits) < m) ++bits;
+      hipLaunchKernelGGL(k_set_of, grid, block, 0, s, vals[a], tot, n, keys[a]);
+      e = radix_sort(keys[a], vals[a], keys[1 - a], vals[1 - a], (uint32_t)tot, bits, sort_temp, s,
+                     &alt);
+      if (e != hipSuccess) return e;
+      if (alt) a = 1 - a;
+    }
+    order = vals[a];
+    // writing keys[0]/vals[0]: when a == 0 each thread reads order[gid] first
+  }
+  hipLaunchKernelGGL(k_resample, grid, block, 0, s, n, m, seed, method, order, ox, oy, ot, g, x,
+                     y, t, keys[0], vals[0]);
   return hipGetLastError();
 }
 

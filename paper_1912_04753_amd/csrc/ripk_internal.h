@@ -70,9 +70,9 @@ struct PairArgs {
 // ---- host runtime (api.cpp) -------------------------------------------------
 
 // Buffer capacities of a plan: S sets, N = S*n_max points, SNC = S*n_cells
-// cells, work items, SNB = S*n_bins bins, NB = n_bins.
+// cells, work items, SNB = S*n_bins bins, NB = n_bins, P = n_max (one set).
 struct Caps {
-  int64_t S = 0, N = 0, SNC = 0, items = 0, SNB = 0, NB = 0;
+  int64_t S = 0, N = 0, SNC = 0, items = 0, SNB = 0, NB = 0, P = 0;
 };
 Caps caps_for(int64_t S, int64_t n_max, int64_t n_cells, int64_t n_bins);
 int64_t caps_bytes(const Caps &c);
@@ -96,6 +96,13 @@ hipError_t launch_keys(const int32_t *x, const int32_t *y, const int32_t *t, uin
 hipError_t launch_csr(uint32_t n, uint32_t m, uint64_t seed, const Geom &g, int32_t *x,
                       int32_t *y, int32_t *t, uint32_t *keys, uint32_t *vals,
                       hipStream_t s);
+// Simulated sets drawn from the observed points ox, oy, ot (n each): method 1
+// random permutation of the time labels, 2 bootstrap; writes x, y, t and the
+// cell keys/values into keys[0], vals[0] (uses both sort buffers).
+hipError_t launch_resample(int method, uint32_t n, uint32_t m, uint64_t seed, const int32_t *ox,
+                           const int32_t *oy, const int32_t *ot, const Geom &g, int32_t *x,
+                           int32_t *y, int32_t *t, uint32_t *keys[2], uint32_t *vals[2],
+                           void *sort_temp, hipStream_t s);
 size_t radix_sort_temp_bytes(uint32_t n);
 hipError_t radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt,
                       uint32_t n, int key_bits, void *temp, hipStream_t s, int *result_in_alt);

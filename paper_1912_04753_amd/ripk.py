@@ -33,6 +33,8 @@ RIPK_EDGE_ISO = 3
 RIPK_NORM_NN1 = 0
 RIPK_NORM_N2 = 1
 RIPK_SIM_CSR = 0
+RIPK_SIM_PERMUTE = 1
+RIPK_SIM_BOOTSTRAP = 2
 RIPK_PLAN_ORDERED = 1
 RIPK_PLAN_TIMING = 2
 RIPK_PLAN_WIDE_COUNTS = 4
@@ -172,11 +174,12 @@ def _check(status, where):
 
 
 def make_desc(window, s_max, t_max, n_s, n_t, edge=RIPK_EDGE_ISO, norm=RIPK_NORM_NN1,
-              n_max=2, m_max=0, flags=0, device=0, cell_div=0, tcell_div=0):
+              n_max=2, m_max=0, flags=0, device=0, cell_div=0, tcell_div=0,
+              sim_method=RIPK_SIM_CSR):
     """Descriptor for a window ``(x0, y0, x1, y1, t0, t1)`` and an (s, t) grid."""
     x0, y0, x1, y1, t0, t1 = (int(v) for v in window)
     return PlanDesc(x0, y0, x1, y1, t0, t1, int(s_max), int(t_max), int(n_s), int(n_t),
-                    int(edge), int(norm), RIPK_SIM_CSR, int(n_max), int(m_max), int(flags),
+                    int(edge), int(norm), int(sim_method), int(n_max), int(m_max), int(flags),
                     int(device), int(cell_div), int(tcell_div))
 
 

@@ -504,3 +504,62 @@ def test_graph_replays_match_eager():
     finally:
         eager.destroy()
         graph.destroy()
+
+
+@pytest.mark.parametrize("method", [ripk.RIPK_SIM_PERMUTE, ripk.RIPK_SIM_BOOTSTRAP])
+def test_resampled_simulations_match_oracle(method):
+    """Random-permutation and bootstrap simulations (Sec. 3) draw from the plan's
+    last observed set; each simulated set against the oracle's own generator."""
+    import torch
+    rng = np.random.default_rng(31 + method)
+    win = (0, 0, 12_000, 9_000, 0, 200 * workloads.DAY)
+    args = (win, 1_500, 20 * workloads.DAY, 12, 9)
+    n, m, seed = 5_000, 6, 4242
+    x = rng.integers(0, 12_001, n); y = rng.integers(0, 9_001, n)
+    t = rng.integers(0, 200 * workloads.DAY + 1, n)
+    x[:2000] = np.clip(3_000 + rng.normal(0, 300, 2000), 0, 12_000)   # a cluster
+    y[:2000] = np.clip(4_000 + rng.normal(0, 300, 2000), 0, 9_000)
+    x, y, t = (np.asarray(a, np.int32) for a in (x, y, t))
+    d = oracle.desc(*args)
+    ref = oracle.envelope_resampled(d, x, y, t, m, seed, method)
+    for flags, dev in ((0, False), (ripk.RIPK_PLAN_ORDERED, False), (0, True)):
+        plan = ripk.ripk_plan(ripk.make_desc(*args, n_max=n, m_max=m, sim_method=method, flags=flags))
+        try:
+            with pytest.raises(ripk.RipkError) as e:   # no observed set yet
+                ripk.ripk_simulate_envelope(plan, n, m, seed)
+            assert e.value.status == ripk.RIPK_EINVAL
+            if dev:
+                ripk.ripk_compute_K(plan, *(torch.from_numpy(a).cuda() for a in (x, y, t)))
+            else:
+                ripk.ripk_compute_K(plan, x, y, t)
+            with pytest.raises(ripk.RipkError):       # n must be the observed set's
+                ripk.ripk_simulate_envelope(plan, n - 1, m, seed)
+            g = ripk.ripk_simulate_envelope(plan, n, m, seed, per_sim=True)
+        finally:
+            plan.destroy()
+        say("resampled", method, flags, dev)
+        assert np.array_equal(g["C_sims"], ref["C_sims"].astype(np.uint64))
+        np.testing.assert_allclose(g["K_sims"], ref["K_sims"], rtol=1e-6, atol=0)
+        np.testing.assert_allclose(g["K_lo"], ref["K_lo"], rtol=1e-6, atol=0)
+        np.testing.assert_allclose(g["K_hi"], ref["K_hi"], rtol=1e-6, atol=0)
+
+
+def test_permutation_batch_sampled_at_full_size():
+    """99 permutations of the 100k uniform set in one call: sampled sets against
+    the oracle, envelopes against the per-set values."""
+    c = workloads.workload("uniform-100k-99csr")
+    x, y, t = workloads.make_points(c)
+    n, m, seed = len(x), 99, 5
+    plan = ripk.ripk_plan(make_desc_for(c, n, m, sim_method=ripk.RIPK_SIM_PERMUTE))
+    try:
+        obs = ripk.ripk_compute_K(plan, x, y, t)
+        g = ripk.ripk_simulate_envelope(plan, n, m, seed, L_obs=obs["L"], per_sim=True)
+    finally:
+        plan.destroy()
+    d = oracle.desc(*cfg_args(c))
+    for s in (0, 57, 98):
+        xs, ys, ts = oracle.resampled_points(x, y, t, s, seed, oracle.SIM_PERMUTE)
+        r = oracle.estimate(d, xs, ys, ts)
+        assert np.array_equal(g["C_sims"][s], r["C"].astype(np.uint64)), s
+        np.testing.assert_allclose(g["K_sims"][s], r["K"], rtol=1e-6, atol=0)
+    assert np.array_equal(g["K_lo"], g["K_sims"].min(0)) and np.array_equal(g["K_hi"], g["K_sims"].max(0))
