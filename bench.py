@@ -269,6 +269,23 @@ def main():
     torch.cuda.synchronize()
     graph_ms = 1e3 * (time.perf_counter() - t_g) / args.steps
     gplan.destroy()
+    # simulations drawn from the observed set: random permutation and bootstrap
+    resampled = {}
+    for name, method in (("permutation", ripk.RIPK_SIM_PERMUTE), ("bootstrap", ripk.RIPK_SIM_BOOTSTRAP)):
+        rdesc = ripk.make_desc(cfg["window"], cfg["s_max"], cfg["t_max"], cfg["n_s"], cfg["n_t"],
+                               n_max=n, m_max=m, cell_div=cd, tcell_div=td, sim_method=method)
+        rplan = ripk.ripk_plan(rdesc)
+        ripk.ripk_compute_K(rplan, dx, dy, dt, stream=stream)
+        ripk.ripk_simulate_envelope(rplan, n, m, cfg["seed"], stream=stream)
+        torch.cuda.synchronize()
+        t_r = time.perf_counter()
+        for _ in range(3):
+            ripk.ripk_simulate_envelope(rplan, n, m, cfg["seed"], stream=stream)
+        torch.cuda.synchronize()
+        dt_r = (time.perf_counter() - t_r) / 3
+        resampled[name] = {"sims_per_s": round(m / dt_r, 3),
+                           "pair_tests_per_s_G": round(ripk.ripk_plan_stats(rplan)["n_in"] / dt_r / 1e9, 3)}
+        rplan.destroy()
     plan.destroy()
 
     ms = 1e3 * t_total / args.steps
@@ -302,6 +319,7 @@ def main():
                    "cells_m_s": cells, "autotune": not args.no_autotune},
         "sims_per_s": round(m / t_sim, 3),
         "graph_ms_per_step": round(graph_ms, 4),
+        "resampled_simulations": resampled,
         "cold_ms": {"plan": round(plan_ms, 2),
                     "first_step_with_tuning": round(first_step_ms, 2) if not args.no_autotune else None},
         "observed_host_input": {"ms": round(host_obs_ms, 3),

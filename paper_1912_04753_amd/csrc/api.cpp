@@ -620,17 +620,20 @@ ripk_status run_tuned(ripk_plan_s *p, int which, uint32_t S, uint32_t S_tune, ui
         d.tcell_div = kTuneCand[i][1];
         ripk_status s = bind_geometry(p, &d, st);
         if (s != RIPK_OK) return s;
-        HIPCHK(hipEventRecord(p->tev[0], st));
-        s = run_sets(p, S_tune, n, nc, x, y, t, simulate, seed, nullptr, st, sym, S);
-        if (s != RIPK_OK) return s;
-        HIPCHK(hipEventRecord(p->tev[1], st));
-        uint32_t err = 0;
-        s = collect_stats(p, st, S_tune, n, &err);
-        if (s != RIPK_OK) return s;
-        if (err) return fail(RIPK_ERANGE, "a point lies outside the study window");
-        float ms = 0;
-        HIPCHK(hipEventElapsedTime(&ms, p->tev[0], p->tev[1]));
-        ts.us[i] = 1e3 * ms;
+        ts.us[i] = 1e300;
+        for (int rep = 0; rep < 2; ++rep) {  // best of two: candidates can be a few % apart
+          HIPCHK(hipEventRecord(p->tev[0], st));
+          s = run_sets(p, S_tune, n, nc, x, y, t, simulate, seed, nullptr, st, sym, S);
+          if (s != RIPK_OK) return s;
+          HIPCHK(hipEventRecord(p->tev[1], st));
+          uint32_t err = 0;
+          s = collect_stats(p, st, S_tune, n, &err);
+          if (s != RIPK_OK) return s;
+          if (err) return fail(RIPK_ERANGE, "a point lies outside the study window");
+          float ms = 0;
+          HIPCHK(hipEventElapsedTime(&ms, p->tev[0], p->tev[1]));
+          ts.us[i] = std::min(ts.us[i], 1e3 * (double)ms);
+        }
         if (ts.us[i] < best) {
           best = ts.us[i];
           bi = i;
