@@ -10,7 +10,8 @@ Contents
   * ``liboracle.so`` (from ``oracle.c``): FP64, O(n^2) over every ordered pair,
     OpenMP over centre points.  Histogram over the smallest containing grid
     step, 2-D prefix sum, K (Eq. 2), L (Eq. 4), Monte Carlo CSR simulations with
-    Philox4x64-10 and min/max envelopes (Sec. 3).
+    Philox4x64-10 and min/max envelopes (Sec. 3); the two-type (cross) estimator
+    named as the first extension in Sec. 7.
   * ``literal``: Eq. 2 evaluated literally, one grid point (s, t) at a time.
   * ``omega_ref``: the isotropic spatial weight by direct arc-union on the
     circle, in FP64 and in 50-digit mpmath.
@@ -68,6 +69,10 @@ def lib():
                                ctypes.c_int, u64p, f64p]
         L.orc_estimate.argtypes = [dp, i32p, i32p, i32p, ctypes.c_int64, ctypes.c_int64,
                                    ctypes.c_int, u64p, f64p, f64p, f64p]
+        L.orc_hist_cross.argtypes = [dp, i32p, i32p, i32p, ctypes.c_int64, ctypes.c_int64,
+                                     ctypes.c_int, u64p, f64p]
+        L.orc_estimate_cross.argtypes = [dp, i32p, i32p, i32p, ctypes.c_int64, ctypes.c_int64,
+                                         ctypes.c_int, u64p, f64p, f64p, f64p]
         L.orc_philox4x64_10.argtypes = [u64p, u64p, u64p]
         L.orc_csr_points.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64, dp,
                                      i32p, i32p, i32p]
@@ -77,6 +82,10 @@ def lib():
         L.orc_bootstrap_points.argtypes = [i32p, i32p, i32p, ctypes.c_int64, ctypes.c_int64,
                                            ctypes.c_uint64, i32p, i32p, i32p]
         L.orc_bootstrap_points.restype = None
+        L.orc_bootstrap_points_typed.argtypes = [i32p, i32p, i32p, ctypes.c_int64, ctypes.c_int64,
+                                                 ctypes.c_int64, ctypes.c_uint64, i32p, i32p,
+                                                 i32p]
+        L.orc_bootstrap_points_typed.restype = None
         L.orc_envelope.argtypes = [dp, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64,
                                    ctypes.c_int, f64p, f64p, f64p, f64p, u64p, f64p, f64p]
         L.orc_now.restype = ctypes.c_double
@@ -157,6 +166,40 @@ def estimate(d, x, y, t, n_centres=None, threads=0):
     return {"C": C.reshape(s), "W": W.reshape(s), "K": K.reshape(s), "L": L.reshape(s)}
 
 
+def hist_cross(d, x, y, t, n1, threads=0):
+    """Per-step histogram (Hc, Hw) over the ordered pairs (i, j) with i of type 1
+    (points [0, n1)) and j of type 2 (points [n1, n)), weights centred on i."""
+    x, y, t = _soa(x, y, t)
+    nb = d.n_s * d.n_t
+    Hc = np.zeros(nb, np.uint64)
+    Hw = np.zeros(nb, np.float64)
+    rc = lib().orc_hist_cross(ctypes.byref(d), _ptr(x, ctypes.c_int32), _ptr(y, ctypes.c_int32),
+                              _ptr(t, ctypes.c_int32), len(x), int(n1), int(threads),
+                              _ptr(Hc, ctypes.c_uint64), _ptr(Hw, ctypes.c_double))
+    if rc:
+        raise ValueError("orc_hist_cross failed")
+    return Hc.reshape(d.n_s, d.n_t), Hw.reshape(d.n_s, d.n_t)
+
+
+def estimate_cross(d, x, y, t, n1, threads=0):
+    """Cross K: C, W, K12 = A*D*W/(n1*n2) and L12 (Eq. 4 applied to K12), each n_s x n_t;
+    type 1 = points [0, n1), type 2 = points [n1, n)."""
+    x, y, t = _soa(x, y, t)
+    nb = d.n_s * d.n_t
+    C = np.zeros(nb, np.uint64)
+    W, K, L = (np.zeros(nb, np.float64) for _ in range(3))
+    with np.errstate(all="ignore"):
+        rc = lib().orc_estimate_cross(ctypes.byref(d), _ptr(x, ctypes.c_int32),
+                                      _ptr(y, ctypes.c_int32), _ptr(t, ctypes.c_int32), len(x),
+                                      int(n1), int(threads), _ptr(C, ctypes.c_uint64),
+                                      _ptr(W, ctypes.c_double), _ptr(K, ctypes.c_double),
+                                      _ptr(L, ctypes.c_double))
+    if rc:
+        raise ValueError("orc_estimate_cross failed")
+    s = (d.n_s, d.n_t)
+    return {"C": C.reshape(s), "W": W.reshape(s), "K": K.reshape(s), "L": L.reshape(s)}
+
+
 def philox4x64_10(counter, key):
     """Philox4x64-10 block function (Salmon et al., SC'11)."""
     c = np.ascontiguousarray(counter, np.uint64)
@@ -181,11 +224,13 @@ def csr_points(d, n, sim, seed):
 SIM_CSR, SIM_PERMUTE, SIM_BOOTSTRAP = 0, 1, 2
 
 
-def resampled_points(x, y, t, sim, seed, method):
+def resampled_points(x, y, t, sim, seed, method, n1=None):
     """Simulation ``sim`` drawn from the observed points (Sec. 3): random
-    permutation of the time labels, or a bootstrap sample with replacement."""
+    permutation of the time labels, or a bootstrap sample with replacement
+    (with two types, points [0, n1) and [n1, n), each type from itself)."""
     x, y, t = _soa(x, y, t)
     n = len(x)
+    n1 = n if n1 is None else int(n1)
     xs, ys, ts = (np.zeros(n, np.int32) for _ in range(3))
     args = (_ptr(x, ctypes.c_int32), _ptr(y, ctypes.c_int32), _ptr(t, ctypes.c_int32), n, int(sim),
             int(seed) & (2**64 - 1), _ptr(xs, ctypes.c_int32), _ptr(ys, ctypes.c_int32),
@@ -194,7 +239,7 @@ def resampled_points(x, y, t, sim, seed, method):
         if lib().orc_permute_points(*args):
             raise MemoryError("orc_permute_points")
     elif method == SIM_BOOTSTRAP:
-        lib().orc_bootstrap_points(*args)
+        lib().orc_bootstrap_points_typed(*args[:4], n1, *args[4:])
     else:
         raise ValueError(method)
     return xs, ys, ts
@@ -204,6 +249,22 @@ def envelope_resampled(d, x, y, t, m, seed, method, threads=0):
     """Min/max envelopes over m simulations drawn from the observed points."""
     sims = [estimate(d, *resampled_points(x, y, t, s, seed, method), threads=threads)
             for s in range(m)]
+    res = {"K_sims": np.stack([r["K"] for r in sims]), "C_sims": np.stack([r["C"] for r in sims]),
+           "W_sims": np.stack([r["W"] for r in sims])}
+    Ls = np.stack([r["L"] for r in sims])
+    res.update(K_lo=res["K_sims"].min(0), K_hi=res["K_sims"].max(0), L_lo=Ls.min(0), L_hi=Ls.max(0))
+    return res
+
+
+def envelope_cross(d, x, y, t, n1, m, seed, method, threads=0):
+    """Cross-K envelopes over m simulations that keep the type split: CSR sets of
+    n points (the first n1 type 1), or sets drawn from the observed points."""
+    n = len(x)
+    sims = []
+    for s in range(m):
+        pts = (csr_points(d, n, s, seed) if method == SIM_CSR
+               else resampled_points(x, y, t, s, seed, method, n1=n1))
+        sims.append(estimate_cross(d, *pts, n1, threads=threads))
     res = {"K_sims": np.stack([r["K"] for r in sims]), "C_sims": np.stack([r["C"] for r in sims]),
            "W_sims": np.stack([r["W"] for r in sims])}
     Ls = np.stack([r["L"] for r in sims])

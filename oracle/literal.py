@@ -10,6 +10,9 @@ histogram/prefix reformulation of ``oracle.c``:
   * omega_ij comes from the arc-union construction in ``omega_ref``;
   * v_ij is the end-point rule of Sec. 3 written out.
 
+With ``n1`` it evaluates the two-type (cross) estimator instead: only ordered
+pairs with i < n1 (type 1) and j >= n1 (type 2) count, and N = n1 * (n - n1).
+
 Cost is O(n_s * n_t * n^2) numpy work plus n^2 arc-union calls, so it is for
 tiny inputs only (n up to a few hundred).
 """
@@ -23,7 +26,7 @@ EDGE_SPATIAL = 1
 EDGE_TEMPORAL = 2
 
 
-def literal_K(window, s_max, t_max, n_s, n_t, x, y, t, edge=3, norm=0):
+def literal_K(window, s_max, t_max, n_s, n_t, x, y, t, edge=3, norm=0, n1=None):
     """Return (Craw, K, L): Craw[k, l] = number of ordered pairs counted at (s_k, t_l)."""
     x0, y0, x1, y1, t0, t1 = (int(v) for v in window)
     x = [int(v) for v in x]
@@ -55,6 +58,10 @@ def literal_K(window, s_max, t_max, n_s, n_t, x, y, t, edge=3, norm=0):
     A = (x1 - x0) * (y1 - y0)
     Dur = t1 - t0
     N = n * n if norm == 1 else n * (n - 1)
+    if n1 is not None:
+        idx = np.arange(n)
+        off = (idx[:, None] < n1) & (idx[None, :] >= n1)
+        N = n1 * (n - n1)
     Craw = np.zeros((n_s, n_t), dtype=np.int64)
     K = np.zeros((n_s, n_t), dtype=np.float64)
     L = np.zeros((n_s, n_t), dtype=np.float64)

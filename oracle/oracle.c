@@ -29,6 +29,13 @@
  * -- and cross-checks against the literal per-(s,t) evaluation of Eq. 2 in the
  * Python test suite.
  *
+ * Cross (bivariate) K, the first extension named in the paper's outlook (Sec. 7),
+ * read as the usual two-type estimator: with type 1 = points [0, n1) and type
+ * 2 = points [n1, n),
+ *   K12^(s,t) = A*D/(n1*n2) * sum_{i in 1} sum_{j in 2} I_{s,t}(d_ij,u_ij) / (omega_ij * v_ij)
+ * with both corrections centred on the type-1 point i, and L12 from K12 as in
+ * Eq. 4.  The histogram loop is the same, with i over type 1 and j over type 2.
+ *
  * Simulations (Sec. 3, Monte Carlo under complete spatio-temporal randomness):
  * n points uniform over the window, drawn from Philox4x64-10 (Salmon, Moraes,
  * Dror, Shaw, "Parallel random numbers: as easy as 1, 2, 3", SC'11) with
@@ -118,13 +125,16 @@ static inline void neumaier(double *sum, double *comp, double v) {
 
 /* ------------------------------------------------------------ O2, O5, O6 */
 /* Histogram over every ordered pair (i, j), i != j, with i < n_centres acting
- * as the centre.  Hc[(k-1)*n_t + (l-1)] counts pairs whose smallest containing
- * grid step is (k, l); Hw holds the matching sum of 1/(omega*v) in FP64 with
- * Neumaier compensation (per thread, then merged).  Returns 0, or -1 on bad
- * arguments / allocation failure. */
-int orc_hist(const orc_desc *q, const int32_t *x, const int32_t *y, const int32_t *t,
-             int64_t n, int64_t n_centres, int nthreads, uint64_t *Hc, double *Hw) {
-  if (!q || q->n_s < 1 || q->n_t < 1 || n < 0 || n_centres < 0 || n_centres > n) return -1;
+ * as the centre and j in [j_begin, n).  Hc[(k-1)*n_t + (l-1)] counts pairs
+ * whose smallest containing grid step is (k, l); Hw holds the matching sum of
+ * 1/(omega*v) in FP64 with Neumaier compensation (per thread, then merged).
+ * Returns 0, or -1 on bad arguments / allocation failure. */
+static int orc_hist_range(const orc_desc *q, const int32_t *x, const int32_t *y,
+                          const int32_t *t, int64_t n, int64_t n_centres, int64_t j_begin,
+                          int nthreads, uint64_t *Hc, double *Hw) {
+  if (!q || q->n_s < 1 || q->n_t < 1 || n < 0 || n_centres < 0 || n_centres > n ||
+      j_begin < 0 || j_begin > n)
+    return -1;
   const int ns = q->n_s, nt = q->n_t, nb = ns * nt;
   int64_t S2[4096], T[4096];
   if (ns > 4096 || nt > 4096) return -1;
@@ -158,7 +168,7 @@ int orc_hist(const orc_desc *q, const int32_t *x, const int32_t *y, const int32_
 #endif
     for (int64_t i = 0; i < n_centres; ++i) {
       const int64_t xi = x[i], yi = y[i], ti = t[i];
-      for (int64_t j = 0; j < n; ++j) {
+      for (int64_t j = j_begin; j < n; ++j) {
         if (j == i) continue;
         int64_t dx = xi - x[j], dy = yi - y[j], dt = ti - t[j];
         int64_t d2 = dx * dx + dy * dy;
@@ -189,6 +199,18 @@ int orc_hist(const orc_desc *q, const int32_t *x, const int32_t *y, const int32_
   return 0;
 }
 
+/* every point a neighbour: the univariate histogram of Eq. 2 */
+int orc_hist(const orc_desc *q, const int32_t *x, const int32_t *y, const int32_t *t,
+             int64_t n, int64_t n_centres, int nthreads, uint64_t *Hc, double *Hw) {
+  return orc_hist_range(q, x, y, t, n, n_centres, 0, nthreads, Hc, Hw);
+}
+
+/* cross histogram: centres i in [0, n1), neighbours j in [n1, n) */
+int orc_hist_cross(const orc_desc *q, const int32_t *x, const int32_t *y, const int32_t *t,
+                   int64_t n, int64_t n1, int nthreads, uint64_t *Hc, double *Hw) {
+  return orc_hist_range(q, x, y, t, n, n1, n1, nthreads, Hc, Hw);
+}
+
 /* ---------------------------------------------------------------- O7 -- */
 /* 2-D inclusive prefix sum in place: C[k][l] = sum_{k'<=k, l'<=l} H[k'][l']. */
 void orc_cumulate(const orc_desc *q, uint64_t *C, double *W) {
@@ -206,12 +228,13 @@ void orc_cumulate(const orc_desc *q, uint64_t *C, double *W) {
 }
 
 /* ------------------------------------------------------------- O8, O9 -- */
-/* K = A*D*W/N (Eq. 2) and L = sqrt(K/(2*pi*t_l)) - s_k (Eq. 4). */
-void orc_normalise(const orc_desc *q, int64_t n, const double *W, double *K, double *L) {
+/* K = A*D*W/N (Eq. 2) and L = sqrt(K/(2*pi*t_l)) - s_k (Eq. 4), for a given
+ * pair-count normaliser N. */
+static void orc_normalise_by(const orc_desc *q, double N, const double *W, double *K,
+                             double *L) {
   const int ns = q->n_s, nt = q->n_t;
   const double A = (double)(q->x1 - q->x0) * (double)(q->y1 - q->y0);
   const double D = (double)(q->t1 - q->t0);
-  const double N = q->norm == 1 ? (double)n * (double)n : (double)n * (double)(n - 1);
   for (int k = 0; k < ns; ++k) {
     const double sk = (double)(k + 1) * (double)q->s_max / (double)ns;
     for (int l = 0; l < nt; ++l) {
@@ -221,6 +244,12 @@ void orc_normalise(const orc_desc *q, int64_t n, const double *W, double *K, dou
       if (L) L[k * nt + l] = sqrt(Kv / (2.0 * M_PI * tl)) - sk;
     }
   }
+}
+
+/* univariate: N = n(n-1), or n^2 with the literal Eq. 2 normalisation */
+void orc_normalise(const orc_desc *q, int64_t n, const double *W, double *K, double *L) {
+  orc_normalise_by(q, q->norm == 1 ? (double)n * (double)n : (double)n * (double)(n - 1), W, K,
+                   L);
 }
 
 /* Whole estimator for one point set: cumulative counts C, cumulative weight
@@ -239,6 +268,29 @@ int orc_estimate(const orc_desc *q, const int32_t *x, const int32_t *y, const in
   if (rc == 0) {
     orc_cumulate(q, c, w);
     orc_normalise(q, n, w, K, L);
+    if (C) memcpy(C, c, sizeof(uint64_t) * nb);
+    if (W) memcpy(W, w, sizeof(double) * nb);
+  }
+  free(c); free(w);
+  return rc;
+}
+
+/* Cross estimator: type 1 = points [0, n1), type 2 = [n1, n); K12 = A*D*W/(n1*n2). */
+int orc_estimate_cross(const orc_desc *q, const int32_t *x, const int32_t *y, const int32_t *t,
+                       int64_t n, int64_t n1, int nthreads, uint64_t *C, double *W, double *K,
+                       double *L) {
+  if (n1 < 1 || n1 >= n) return -1;
+  const int nb = q->n_s * q->n_t;
+  uint64_t *c = (uint64_t *)malloc(sizeof(uint64_t) * nb);
+  double *w = (double *)malloc(sizeof(double) * nb);
+  if (!c || !w) {
+    free(c); free(w);
+    return -1;
+  }
+  int rc = orc_hist_cross(q, x, y, t, n, n1, nthreads, c, w);
+  if (rc == 0) {
+    orc_cumulate(q, c, w);
+    orc_normalise_by(q, (double)n1 * (double)(n - n1), w, K, L);
     if (C) memcpy(C, c, sizeof(uint64_t) * nb);
     if (W) memcpy(W, w, sizeof(double) * nb);
   }
@@ -330,18 +382,28 @@ int orc_permute_points(const int32_t *x, const int32_t *y, const int32_t *t, int
 
 /* Bootstrap (Sec. 3): points sampled at random with replacement from the
  * observed points.  Point i of simulation `sim` is observed point
- * floor(r0 * n / 2^64), r = Philox(counter=(i,sim,0,0), key=(seed,2)). */
-void orc_bootstrap_points(const int32_t *x, const int32_t *y, const int32_t *t, int64_t n,
-                          int64_t sim, uint64_t seed, int32_t *xs, int32_t *ys, int32_t *ts) {
+ * floor(r0 * n / 2^64), r = Philox(counter=(i,sim,0,0), key=(seed,2)).  With
+ * two types (n1 < n) each type is resampled from itself: point i < n1 is
+ * observed point floor(r0 * n1 / 2^64), point i >= n1 is observed point
+ * n1 + floor(r0 * (n - n1) / 2^64). */
+void orc_bootstrap_points_typed(const int32_t *x, const int32_t *y, const int32_t *t, int64_t n,
+                                int64_t n1, int64_t sim, uint64_t seed, int32_t *xs,
+                                int32_t *ys, int32_t *ts) {
   const uint64_t key[2] = {seed, 2};
   for (int64_t i = 0; i < n; ++i) {
     uint64_t ctr[4] = {(uint64_t)i, (uint64_t)sim, 0, 0}, w[4];
     orc_philox4x64_10(ctr, key, w);
-    const int64_t j = (int64_t)mulhi64(w[0], (uint64_t)n);
+    const int64_t j = i < n1 ? (int64_t)mulhi64(w[0], (uint64_t)n1)
+                             : n1 + (int64_t)mulhi64(w[0], (uint64_t)(n - n1));
     xs[i] = x[j];
     ys[i] = y[j];
     ts[i] = t[j];
   }
+}
+
+void orc_bootstrap_points(const int32_t *x, const int32_t *y, const int32_t *t, int64_t n,
+                          int64_t sim, uint64_t seed, int32_t *xs, int32_t *ys, int32_t *ts) {
+  orc_bootstrap_points_typed(x, y, t, n, n, sim, seed, xs, ys, ts);
 }
 
 /* Simulation envelope: for sims 0..m-1, draw the CSR set, estimate K and L,

@@ -463,3 +463,103 @@ def test_permuted_set_keeps_spatial_counts():
         assert np.array_equal(env["C_sims"][s][:, -1], obs["C"][:, -1])
         assert not np.array_equal(env["C_sims"][s][:, :-1], obs["C"][:, :-1])
     assert np.all(env["K_lo"] <= env["K_hi"])
+
+
+# ------------------------------------------------------- cross (bivariate) K ----
+def _two_types(seed, n, n1, win):
+    rng = np.random.default_rng(seed)
+    x0, y0, x1, y1, t0, t1 = win
+    x = rng.integers(x0, x1 + 1, n).astype(np.int32)
+    y = rng.integers(y0, y1 + 1, n).astype(np.int32)
+    t = rng.integers(t0, t1 + 1, n).astype(np.int32)
+    # a few type-2 points on top of type-1 points (coincident pairs across types)
+    k = min(3, n1, n - n1)
+    x[n1:n1 + k] = x[:k]; y[n1:n1 + k] = y[:k]; t[n1:n1 + k] = t[:k]
+    return x, y, t
+
+
+@pytest.mark.parametrize("edge", [3, 1, 2, 0])
+def test_cross_literal_matches_oracle(edge):
+    """Two-type estimator evaluated literally per (s_k, t_l), with the arc-union
+    omega and exact rational indicators, equals the oracle's cross histogram +
+    prefix: counts exactly, K12 to 1e-12, N = n1 * n2."""
+    win = (0, 0, 1000, 1200, 0, 50_000)
+    for n, n1 in ((40, 13), (25, 1), (25, 24)):
+        x, y, t = _two_types(n + n1, n, n1, win)
+        s_max, n_s, t_max, n_t = 450, 6, 9_000, 5
+        Craw, Klit, Llit = literal.literal_K(win, s_max, t_max, n_s, n_t, x, y, t, edge=edge,
+                                             n1=n1)
+        d = oracle.desc(win, s_max, t_max, n_s, n_t, edge=edge)
+        r = oracle.estimate_cross(d, x, y, t, n1)
+        assert np.array_equal(r["C"].astype(np.int64), Craw), (n, n1)
+        assert np.allclose(r["K"], Klit, rtol=1e-12, atol=0), (n, n1)
+        ok = Klit > 0
+        assert np.allclose(r["L"][ok], Llit[ok], rtol=0, atol=1e-9)
+
+
+def test_cross_terms_partition_the_univariate_sum():
+    """The ordered pairs of a two-type set split into type 1 x type 1, type 2 x
+    type 2 and the two cross terms, with weights centred on i in each: the
+    univariate histogram equals the sum of the four (counts exactly)."""
+    win = (0, 0, 3000, 3000, 0, 200_000)
+    n, n1 = 900, 340
+    x, y, t = _two_types(17, n, n1, win)
+    d = oracle.desc(win, 500, 30_000, 8, 6)
+    full = oracle.hist(d, x, y, t)
+    aa = oracle.hist(d, x[:n1], y[:n1], t[:n1])
+    bb = oracle.hist(d, x[n1:], y[n1:], t[n1:])
+    ab = oracle.hist_cross(d, x, y, t, n1)
+    sw = np.concatenate([np.arange(n1, n), np.arange(n1)])
+    ba = oracle.hist_cross(d, x[sw], y[sw], t[sw], n - n1)
+    assert np.array_equal(aa[0] + bb[0] + ab[0] + ba[0], full[0])
+    assert np.allclose(aa[1] + bb[1] + ab[1] + ba[1], full[1], rtol=1e-12)
+    # the indicator is symmetric, the weights are not (centred on type 1 / type 2)
+    assert np.array_equal(ab[0], ba[0])
+    assert not np.allclose(ab[1], ba[1], rtol=1e-6)
+
+
+def test_cross_without_correction_counts_pairs():
+    """With no edge correction every cross weight is 1: W12 = C12 and K12 equals
+    A*D*C12/(n1*n2) exactly as written."""
+    win = (0, 0, 2000, 2000, 0, 100_000)
+    n, n1 = 500, 200
+    x, y, t = _two_types(8, n, n1, win)
+    d = oracle.desc(win, 300, 20_000, 5, 4, edge=0)
+    r = oracle.estimate_cross(d, x, y, t, n1)
+    assert np.array_equal(r["W"], r["C"].astype(np.float64))
+    want = 2000.0 * 2000.0 * 100_000.0 * r["C"].astype(np.float64) / (n1 * (n - n1))
+    assert np.allclose(r["K"], want, rtol=1e-15, atol=0)
+
+
+def test_cross_expectation_independent_types():
+    """Two independent CSR types: E[K12(s,t)] = 2*pi*s^2*t as for one CSR
+    process (the cross pairs of independent uniform sets are uniform)."""
+    win = (0, 0, 2000, 2000, 0, 1_000_000)
+    s_max, n_s, t_max, n_t = 400, 4, 200_000, 4
+    d = oracle.desc(win, s_max, t_max, n_s, n_t)
+    m = 120
+    env = oracle.envelope_cross(d, np.zeros(900, np.int32), np.zeros(900, np.int32),
+                                np.zeros(900, np.int32), 300, m, 21, oracle.SIM_CSR)
+    Ks = env["K_sims"]
+    se = Ks.std(axis=0, ddof=1) / math.sqrt(m)
+    s = (np.arange(1, n_s + 1) * s_max / n_s)[:, None]
+    tt = (np.arange(1, n_t + 1) * t_max / n_t)[None, :]
+    z = (Ks.mean(axis=0) - 2 * np.pi * s ** 2 * tt) / se
+    assert np.all(np.abs(z) < 4.0), z
+
+
+def test_typed_bootstrap_draws_each_type_from_itself():
+    """Bootstrap with two types: point i < n1 is observed point floor(r0*n1/2^64),
+    point i >= n1 is n1 + floor(r0*(n-n1)/2^64), r from Philox (key (seed, 2))."""
+    n, n1, seed, sim = 120, 45, 6, 2
+    x = np.arange(n, dtype=np.int32); y = x * 2; t = x * 3
+    xs, ys, ts = oracle.resampled_points(x, y, t, sim, seed, oracle.SIM_BOOTSTRAP, n1=n1)
+    r0 = [_numpy_block([seed, 2], [i, sim, 0, 0])[0] for i in range(n)]
+    idx = np.array([(r0[i] * n1) >> 64 if i < n1 else n1 + ((r0[i] * (n - n1)) >> 64)
+                    for i in range(n)])
+    assert np.array_equal(xs, x[idx]) and np.array_equal(ts, t[idx])
+    assert np.all(idx[:n1] < n1) and np.all(idx[n1:] >= n1)
+    # one type spanning the set is the untyped bootstrap
+    a = oracle.resampled_points(x, y, t, sim, seed, oracle.SIM_BOOTSTRAP, n1=n)
+    b = oracle.resampled_points(x, y, t, sim, seed, oracle.SIM_BOOTSTRAP)
+    assert all(np.array_equal(u, v) for u, v in zip(a, b))
