@@ -183,6 +183,9 @@ def main():
                     help="fixed cells (one per s_max and t_max) instead of the tuned grid")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain device copy of known size first (counter runs)")
+    ap.add_argument("--main-only", action="store_true",
+                    help="stop after the timed steps: no host-input, graph or resampled legs, so "
+                         "the last pair-kernel launches of a trace are the timed steps")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -240,6 +243,17 @@ def main():
         recs.append(step())
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
+    if args.main_only:
+        plan.destroy()
+        ms = 1e3 * t_total / args.steps
+        n_in = recs[0][0]["n_in"] + recs[0][1]["n_in"]
+        print(json.dumps({"metric": METRIC, "value": round(n_in / (t_total / args.steps) / 1e9, 4),
+                          "unit": "G pair tests/s", "n_gpus": 1, "steps": args.steps,
+                          "warmup": args.warmup, "ms_per_step": round(ms, 4),
+                          "pair_kernel_us": {"observed": [r[0]["us_pair"] for r in recs],
+                                             "simulations": [r[1]["us_pair"] for r in recs]},
+                          "note": "main steps only"}), flush=True)
+        return
     # end to end with the observed points in host memory (H2D copy inside the call)
     t_h = time.perf_counter()
     for _ in range(3):
@@ -286,6 +300,34 @@ def main():
         resampled[name] = {"sims_per_s": round(m / dt_r, 3),
                            "pair_tests_per_s_G": round(ripk.ripk_plan_stats(rplan)["n_in"] / dt_r / 1e9, 3)}
         rplan.destroy()
+    # cross (two-type) K: the same set read as two types of n/2 points each,
+    # observed cross K + m CSR simulations keeping the split, autotuned cells
+    n1 = n // 2
+    xplan = ripk.ripk_plan(ripk.make_desc(cfg["window"], cfg["s_max"], cfg["t_max"], cfg["n_s"],
+                                          cfg["n_t"], n_max=n, m_max=m,
+                                          flags=ripk.RIPK_PLAN_CROSS | ripk.RIPK_PLAN_AUTOTUNE))
+
+    def xstep():
+        ripk.ripk_compute_K(xplan, dx, dy, dt, n_centres=n1, stream=stream)
+        a = ripk.ripk_plan_stats(xplan)["n_in"]
+        t1 = time.perf_counter()
+        ripk.ripk_simulate_envelope(xplan, n, m, cfg["seed"], stream=stream)
+        return a + ripk.ripk_plan_stats(xplan)["n_in"], time.perf_counter() - t1
+
+    xstep()  # tuning
+    xstep()
+    torch.cuda.synchronize()
+    t_x = time.perf_counter()
+    xs = [xstep() for _ in range(3)]
+    torch.cuda.synchronize()
+    x_ms = 1e3 * (time.perf_counter() - t_x) / 3
+    xi = ripk.ripk_plan_get_info(xplan)
+    cross = {"ms_per_step": round(x_ms, 3),
+             "pair_tests_per_s_G": round(xs[0][0] / (x_ms * 1e-3) / 1e9, 3),
+             "sims_per_s": round(m / (sum(v[1] for v in xs) / 3), 3),
+             "cells_m_s": [xi["cell_s"], xi["cell_t"]],
+             "note": "types = first and second half of the set; ordered cross pairs"}
+    xplan.destroy()
     plan.destroy()
 
     ms = 1e3 * t_total / args.steps
@@ -320,6 +362,7 @@ def main():
         "sims_per_s": round(m / t_sim, 3),
         "graph_ms_per_step": round(graph_ms, 4),
         "resampled_simulations": resampled,
+        "cross_k": cross,
         "cold_ms": {"plan": round(plan_ms, 2),
                     "first_step_with_tuning": round(first_step_ms, 2) if not args.no_autotune else None},
         "observed_host_input": {"ms": round(host_obs_ms, 3),

@@ -69,6 +69,8 @@ enum {
  * with replacement; point k of set s is observed point floor(r0 * n / 2^64),
  * r = Philox4x64-10((k, s, 0, 0), (seed, 2)).  PERMUTE and BOOTSTRAP draw from
  * the observed set of the plan's last successful ripk_compute_K. */
+/* With RIPK_PLAN_CROSS, BOOTSTRAP point k < n1 is observed point
+ * floor(r0 * n1 / 2^64) and point k >= n1 is n1 + floor(r0 * (n - n1) / 2^64). */
 #define RIPK_SIM_CSR 0u
 #define RIPK_SIM_PERMUTE 1u
 #define RIPK_SIM_BOOTSTRAP 2u
@@ -92,6 +94,21 @@ enum {
                                         /* sequence into a HIP graph and replay it      */
                                         /* while the call shape (sizes, input pointers, */
                                         /* seed, geometry) repeats                      */
+#define RIPK_PLAN_CROSS (1u << 5)       /* two-type (cross, bivariate) K, the first     */
+                                        /* extension named in Sec. 7: see below         */
+
+/*
+ * Cross K.  With RIPK_PLAN_CROSS the points of ripk_compute_K carry two types:
+ * type 1 = points [0, n_centres) (1 <= n_centres < n), type 2 = the rest, and
+ *   K12(s,t) = A*D/(n1*n2) * sum_{i in 1} sum_{j in 2} I(d_ij <= s, u_ij <= t) / (omega_ij v_ij)
+ * with both corrections centred on the type-1 point i (the weights of Eq. 2);
+ * L12 follows from K12 as in Eq. 4 and C counts the ordered cross pairs.  The
+ * norm field is ignored (the normaliser is n1*n2).  ripk_simulate_envelope
+ * keeps the type split of the plan's last successful ripk_compute_K (RIPK_EINVAL
+ * before one, or for another n): CSR sets take their first n1 points as type 1,
+ * PERMUTE exchanges time labels over all points (types stay with locations),
+ * BOOTSTRAP draws each type from itself (see RIPK_SIM_BOOTSTRAP).
+ */
 
 /*
  * Problem statement (the job parameters of Sec. 4.1 and the GUI of Sec. 5:

@@ -139,6 +139,9 @@ ripk_status derive(const ripk_plan_desc *d, Layout *L) {
   if ((d->edge & RIPK_EDGE_TEMPORAL) && d->t_max > D)
     return fail(RIPK_EINVAL, "temporal correction needs t_max <= t1-t0");
   if (d->norm > RIPK_NORM_N2) return fail(RIPK_EINVAL, "unknown normalisation");
+  if (d->flags & ~(RIPK_PLAN_ORDERED | RIPK_PLAN_TIMING | RIPK_PLAN_WIDE_COUNTS |
+                   RIPK_PLAN_AUTOTUNE | RIPK_PLAN_GRAPH | RIPK_PLAN_CROSS))
+    return fail(RIPK_EINVAL, "unknown plan flags");
   if (d->sim_method != RIPK_SIM_CSR && d->sim_method != RIPK_SIM_PERMUTE &&
       d->sim_method != RIPK_SIM_BOOTSTRAP)
     return fail(RIPK_EINVAL, "unknown simulation method");
@@ -204,7 +207,13 @@ ripk_status derive(const ripk_plan_desc *d, Layout *L) {
   // scaled down by 2^-20 so that the pair kernel's FP32 step estimates never
   // exceed the exact step (it then corrects upward by at most one)
   g.inv_ds = (float)((double)d->n_s / (double)d->s_max * (1.0 - 0x1p-20));
-  g.inv_dt = (float)((double)d->n_t / (double)d->t_max * (1.0 - 0x1p-20));
+  {
+    uint32_t sh = 0;
+    while ((int64_t)d->n_t > ((int64_t)d->t_max << sh)) ++sh;
+    const uint64_t num = (uint64_t)d->n_t << (32 - sh);
+    g.tmul = (uint32_t)((num + (uint64_t)d->t_max - 1) / (uint64_t)d->t_max - 1);
+    g.tsh = sh;
+  }
   L->clamp_e = (int32_t)d->s_max;
 
   L->caps = caps_for(S, d->n_max, I.n_cells, I.n_bins);
@@ -247,6 +256,7 @@ struct ripk_plan_s {
   int32_t *x = nullptr, *y = nullptr, *t = nullptr;
   int32_t *ox = nullptr, *oy = nullptr, *ot = nullptr;  // last observed set (resampling)
   int64_t obs_n = 0;
+  int64_t split_n = 0, split_n1 = 0;  // cross K: n and n1 of the last observed set
   uint32_t *keys[2] = {nullptr, nullptr}, *vals[2] = {nullptr, nullptr};
   void *sort_temp = nullptr;
   uint32_t *cs = nullptr;
@@ -318,13 +328,14 @@ ripk_status enqueue_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_cent
   uint32_t *n_items = err + 1;
   uint32_t *item_ctr = err + 2;
   HIPCHK(launch_fill_u64(p->scal, 4, 0ull, st));
+  const bool cross = (p->desc.flags & RIPK_PLAN_CROSS) != 0;
   if (simulate) {
     if (p->desc.sim_method == RIPK_SIM_CSR)
-      HIPCHK(launch_csr(n, S, seed, g, p->x, p->y, p->t, p->keys[0], p->vals[0], st));
+      HIPCHK(launch_csr(n, n_centres, S, seed, g, p->x, p->y, p->t, p->keys[0], p->vals[0], st));
     else
-      HIPCHK(launch_resample(p->desc.sim_method == RIPK_SIM_PERMUTE ? 1 : 2, n, S, seed, p->ox,
-                             p->oy, p->ot, g, p->x, p->y, p->t, p->keys, p->vals, p->sort_temp,
-                             st));
+      HIPCHK(launch_resample(p->desc.sim_method == RIPK_SIM_PERMUTE ? 1 : 2, n, n_centres, S,
+                             seed, p->ox, p->oy, p->ot, g, p->x, p->y, p->t, p->keys, p->vals,
+                             p->sort_temp, st));
     x = p->x; y = p->y; t = p->t;
   } else {
     HIPCHK(launch_keys(x, y, t, n, n_centres, 0, 1, g, p->keys[0], p->vals[0], err, st));
@@ -335,7 +346,9 @@ ripk_status enqueue_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_cent
   HIPCHK(radix_sort(p->keys[0], p->vals[0], p->keys[1], p->vals[1], N, ceil_log2(n_keys),
                     p->sort_temp, st, &alt));
   HIPCHK(launch_cell_bounds(p->keys[alt], N, (uint32_t)n_keys, p->cs, st));
-  HIPCHK(launch_gather(p->vals[alt], N, x, y, t, g, p->lay.clamp_e, p->P, st));
+  // cross K: type-1 records (the centres) are marked as no neighbour
+  HIPCHK(launch_gather(p->vals[alt], p->keys[alt], cross ? 1 : 0, N, x, y, t, g, p->lay.clamp_e,
+                       p->P, st));
   // row items need every point to be a centre (no halo entries inside a row)
   const bool row_items = n_centres == n;
   const int wide_counts =
@@ -383,8 +396,9 @@ ripk_status enqueue_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_cent
 
   const double AD = (double)(p->desc.x1 - p->desc.x0) * (double)(p->desc.y1 - p->desc.y0) *
                     (double)(p->desc.t1 - p->desc.t0);
-  const double Nn = p->desc.norm == RIPK_NORM_N2 ? (double)n * (double)n
-                                                 : (double)n * (double)(n - 1);
+  const double Nn = cross ? (double)n_centres * (double)(n - n_centres)
+                    : p->desc.norm == RIPK_NORM_N2 ? (double)n * (double)n
+                                                   : (double)n * (double)(n - 1);
   HIPCHK(launch_finalize(p->binC, p->binW, S, g.n_s, g.n_t, (double)p->desc.s_max,
                          (double)p->desc.t_max, AD, Nn, p->outC, p->outW, p->outK, p->outL,
                          p->scal + 1, st));
@@ -549,6 +563,7 @@ ripk_status plan_bind(ripk_plan_s *p, const ripk_plan_desc *desc, hipStream_t st
   p->tune[0] = TuneState();
   p->tune[1] = TuneState();
   p->obs_n = 0;  // no observed set for resampled simulations yet
+  p->split_n = p->split_n1 = 0;
   return RIPK_OK;
 }
 
@@ -716,6 +731,9 @@ ripk_status ripk_compute_K(ripk_plan_t p, const ripk_points *pts, void *stream, 
   if (n < 2) return fail(RIPK_EINVAL, "need n >= 2 points (n(n-1) = 0 otherwise)");
   if (n > p->desc.n_max) return fail(RIPK_EINVAL, "n = %lld exceeds n_max = %lld", (long long)n, (long long)p->desc.n_max);
   if (nc < 0 || nc > n) return fail(RIPK_EINVAL, "n_centres must be in [0, n]");
+  const bool cross = (p->desc.flags & RIPK_PLAN_CROSS) != 0;
+  if (cross && (pts->n_centres < 1 || pts->n_centres >= n))
+    return fail(RIPK_EINVAL, "cross K needs 1 <= n_centres < n (type 1 = points [0, n_centres))");
   if (!pts->x || !pts->y || !pts->t) return fail(RIPK_EINVAL, "null coordinate array");
   auto t0 = std::chrono::steady_clock::now();
   DeviceGuard dg(p->device);
@@ -734,6 +752,7 @@ ripk_status ripk_compute_K(ripk_plan_t p, const ripk_points *pts, void *stream, 
     HIPCHK(hipMemcpyAsync(p->ot, t, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st));
     p->obs_n = 0;  // set once the call succeeds
   }
+  p->split_n = p->split_n1 = 0;
   const bool sym = !(p->desc.flags & RIPK_PLAN_ORDERED) && nc == n;
   ripk_status s = run_tuned(p, 0, 1, 1, (uint32_t)n, (uint32_t)nc, x, y, t, false, 0, nullptr, st,
                             sym);
@@ -743,6 +762,10 @@ ripk_status ripk_compute_K(ripk_plan_t p, const ripk_points *pts, void *stream, 
   if (s != RIPK_OK) return s;
   if (err) return fail(RIPK_ERANGE, "a point lies outside the study window");
   if (p->desc.sim_method != RIPK_SIM_CSR) p->obs_n = n;
+  if (cross) {
+    p->split_n = n;
+    p->split_n1 = nc;
+  }
   const size_t NB = (size_t)p->lay.info.n_bins;
   if (out) {
     if (out->C) HIPCHK(hipMemcpyAsync(out->C, p->outC, 8 * NB, hipMemcpyDeviceToHost, st));
@@ -765,12 +788,18 @@ ripk_status ripk_simulate_envelope(ripk_plan_t p, int64_t n, int32_t m, uint64_t
     return fail(RIPK_EINVAL,
                 "permutation and bootstrap simulations draw from the plan's last observed set: "
                 "call ripk_compute_K on %lld points first", (long long)n);
+  const bool cross = (p->desc.flags & RIPK_PLAN_CROSS) != 0;
+  if (cross && p->split_n != n)
+    return fail(RIPK_EINVAL,
+                "cross K simulations keep the type split of the plan's last observed set: "
+                "call ripk_compute_K on %lld points first", (long long)n);
   auto t0 = std::chrono::steady_clock::now();
   DeviceGuard dg(p->device);
   hipStream_t st = (hipStream_t)stream;
-  const bool sym = !(p->desc.flags & RIPK_PLAN_ORDERED);
+  const bool sym = !(p->desc.flags & RIPK_PLAN_ORDERED) && !cross;
+  const uint32_t nc = cross ? (uint32_t)p->split_n1 : (uint32_t)n;
   ripk_status s = run_tuned(p, 1, (uint32_t)m, (uint32_t)std::min(m, kTuneSims), (uint32_t)n,
-                            (uint32_t)n, nullptr, nullptr, nullptr, true, seed, L_obs, st, sym);
+                            nc, nullptr, nullptr, nullptr, true, seed, L_obs, st, sym);
   if (s != RIPK_OK) return s;
   uint32_t err = 0;
   s = collect_stats(p, st, (uint32_t)m, (uint32_t)n, &err);

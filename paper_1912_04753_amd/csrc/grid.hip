@@ -71,7 +71,8 @@ __device__ __forceinline__ U64x4 philox4x64_10(U64x4 c, uint64_t k0, uint64_t k1
 // Simulation s, point i: counter (i, s, 0, 0), key (seed, 0).  Coordinates on
 // the half-open window by 64x64 multiply-high.  Writes the SoA points and the
 // (key, value) pairs for the sort, sets ordered simulation-major.
-__global__ void k_csr(uint32_t n, uint32_t m, uint64_t seed, Geom g, int32_t *__restrict__ x,
+__global__ void k_csr(uint32_t n, uint32_t n_centres, uint32_t m, uint64_t seed, Geom g,
+                      int32_t *__restrict__ x,
                       int32_t *__restrict__ y, int32_t *__restrict__ t,
                       uint32_t *__restrict__ keys, uint32_t *__restrict__ vals) {
   uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -92,7 +93,7 @@ __global__ void k_csr(uint32_t n, uint32_t m, uint64_t seed, Geom g, int32_t *__
   t[gid] = pt;
   bool bad;
   uint32_t cell = cell_of(px, py, pt, g, &bad);
-  keys[gid] = (s * g.n_cells + cell) << 1;
+  keys[gid] = ((s * g.n_cells + cell) << 1) | (i >= n_centres ? 1u : 0u);
   vals[gid] = (uint32_t)gid;
 }
 
@@ -101,7 +102,10 @@ __global__ void k_csr(uint32_t n, uint32_t m, uint64_t seed, Geom g, int32_t *__
 // gives point k the time of observed point order_s[k], where order_s lists the
 // points by increasing high 32 bits of word 0 of Philox(counter (j, s, 0, 0),
 // key (seed, 1)), equal values by index.  Bootstrap takes point k of set s
-// from observed point floor(r0 * n / 2^64), r = Philox((k, s, 0, 0), (seed, 2)).
+// from observed point floor(r0 * n / 2^64), r = Philox((k, s, 0, 0), (seed, 2));
+// with two types (n_centres < n) each type draws from itself: point k <
+// n_centres from floor(r0 * n_centres / 2^64), the others from n_centres +
+// floor(r0 * (n - n_centres) / 2^64).
 
 // permutation, stage 1: the random rank key of every (set, point); value = index
 __global__ void k_perm_keys(uint32_t n, uint32_t m, uint64_t seed, uint32_t *__restrict__ keys,
@@ -131,7 +135,7 @@ __global__ void k_set_of(const uint32_t *__restrict__ vals, uint64_t total, uint
 // Assembles the simulated sets (as k_csr does for CSR): points and cell keys.
 // `order` (permutation only) may be the same array as `vals`: each thread reads
 // its own entry before writing it.
-__global__ void k_resample(uint32_t n, uint32_t m, uint64_t seed, int method,
+__global__ void k_resample(uint32_t n, uint32_t n_centres, uint32_t m, uint64_t seed, int method,
                            const uint32_t *order, const int32_t *__restrict__ ox,
                            const int32_t *__restrict__ oy, const int32_t *__restrict__ ot, Geom g,
                            int32_t *__restrict__ x, int32_t *__restrict__ y,
@@ -152,7 +156,9 @@ __global__ void k_resample(uint32_t n, uint32_t m, uint64_t seed, int method,
     c.v[2] = 0;
     c.v[3] = 0;
     U64x4 r = philox4x64_10(c, seed, 2);
-    const uint32_t j = (uint32_t)__umul64hi(r.v[0], (uint64_t)n);
+    const uint32_t j = k < n_centres
+                           ? (uint32_t)__umul64hi(r.v[0], (uint64_t)n_centres)
+                           : n_centres + (uint32_t)__umul64hi(r.v[0], (uint64_t)(n - n_centres));
     px = ox[j];
     py = oy[j];
     pt = ot[j];
@@ -162,7 +168,7 @@ __global__ void k_resample(uint32_t n, uint32_t m, uint64_t seed, int method,
   t[gid] = pt;
   bool bad;
   uint32_t cell = cell_of(px, py, pt, g, &bad);
-  keys[gid] = (s * g.n_cells + cell) << 1;
+  keys[gid] = ((s * g.n_cells + cell) << 1) | (k >= n_centres ? 1u : 0u);
   vals[gid] = (uint32_t)gid;
 }
 
@@ -342,7 +348,8 @@ __global__ void k_cell_bounds(const uint32_t *__restrict__ keys, uint32_t n, uin
 
 // Sorted point records: window-relative coordinates (all >= 0) and the distance
 // to the nearest side clamped to s_max (a circle no larger than that is whole).
-__global__ void k_gather(const uint32_t *__restrict__ vals, uint32_t n,
+__global__ void k_gather(const uint32_t *__restrict__ vals, const uint32_t *__restrict__ keys,
+                         int mark, uint32_t n,
                          const int32_t *__restrict__ x, const int32_t *__restrict__ y,
                          const int32_t *__restrict__ t, Geom g, int32_t clamp_e,
                          int4 *__restrict__ P) {
@@ -352,6 +359,7 @@ __global__ void k_gather(const uint32_t *__restrict__ vals, uint32_t n,
   int32_t X = x[i] - g.x0, Y = y[i] - g.y0, T = t[i] - g.t0;
   int32_t e = min(min(X, g.x1 - g.x0 - X), min(Y, g.y1 - g.y0 - Y));
   e = min(max(e, 0), clamp_e);
+  if (mark && !(keys[r] & 1u)) e = (int32_t)((uint32_t)e | 0x80000000u);
   P[r] = make_int4(X, Y, T, e);
 }
 
@@ -465,16 +473,18 @@ hipError_t launch_keys(const int32_t *x, const int32_t *y, const int32_t *t, uin
   return hipGetLastError();
 }
 
-hipError_t launch_csr(uint32_t n, uint32_t m, uint64_t seed, const Geom &g, int32_t *x,
-                      int32_t *y, int32_t *t, uint32_t *keys, uint32_t *vals, hipStream_t s) {
+hipError_t launch_csr(uint32_t n, uint32_t n_centres, uint32_t m, uint64_t seed, const Geom &g,
+                      int32_t *x, int32_t *y, int32_t *t, uint32_t *keys, uint32_t *vals,
+                      hipStream_t s) {
   uint64_t tot = (uint64_t)n * m;
   if (tot == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_csr, dim3(blocks_for(tot, kThreads)), dim3(kThreads), 0, s, n, m, seed,
-                     g, x, y, t, keys, vals);
+  hipLaunchKernelGGL(k_csr, dim3(blocks_for(tot, kThreads)), dim3(kThreads), 0, s, n, n_centres,
+                     m, seed, g, x, y, t, keys, vals);
   return hipGetLastError();
 }
 
-hipError_t launch_resample(int method, uint32_t n, uint32_t m, uint64_t seed, const int32_t *ox,
+hipError_t launch_resample(int method, uint32_t n, uint32_t n_centres, uint32_t m, uint64_t seed,
+                           const int32_t *ox,
                            const int32_t *oy, const int32_t *ot, const Geom &g, int32_t *x,
                            int32_t *y, int32_t *t, uint32_t *keys[2], uint32_t *vals[2],
                            void *sort_temp, hipStream_t s) {
@@ -501,8 +511,8 @@ hipError_t launch_resample(int method, uint32_t n, uint32_t m, uint64_t seed, co
     order = vals[a];
     // writing keys[0]/vals[0]: when a == 0 each thread reads order[gid] first
   }
-  hipLaunchKernelGGL(k_resample, grid, block, 0, s, n, m, seed, method, order, ox, oy, ot, g, x,
-                     y, t, keys[0], vals[0]);
+  hipLaunchKernelGGL(k_resample, grid, block, 0, s, n, n_centres, m, seed, method, order, ox, oy,
+                     ot, g, x, y, t, keys[0], vals[0]);
   return hipGetLastError();
 }
 
@@ -565,12 +575,12 @@ hipError_t launch_cell_bounds(const uint32_t *keys, uint32_t n, uint32_t n_keys,
   return hipGetLastError();
 }
 
-hipError_t launch_gather(const uint32_t *vals, uint32_t n, const int32_t *x, const int32_t *y,
-                         const int32_t *t, const Geom &g, int32_t clamp_e, int4 *P,
-                         hipStream_t s) {
+hipError_t launch_gather(const uint32_t *vals, const uint32_t *keys, int mark, uint32_t n,
+                         const int32_t *x, const int32_t *y, const int32_t *t, const Geom &g,
+                         int32_t clamp_e, int4 *P, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gather, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, s, vals, n, x,
-                     y, t, g, clamp_e, P);
+  hipLaunchKernelGGL(k_gather, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, s, vals, keys,
+                     mark, n, x, y, t, g, clamp_e, P);
   return hipGetLastError();
 }
 

@@ -85,7 +85,9 @@ __device__ __forceinline__ int4 load_image(const unsigned char *base, uint32_t s
 }
 
 struct QState {
-  uint32_t ha, ta;      // queue A head and tail positions in [0, kQA)
+  uint32_t ha, ta;      // queue A head and tail positions in [0, kQA); the head is a
+                        // multiple of 64 (full drains take 64 entries, and a partial
+                        // drain empties the queue and restarts it at 0)
   uint32_t hb, nb;      // queue B head and length
 };
 
@@ -259,8 +261,7 @@ __device__ __forceinline__ void drain_a(WaveLds &W, QState &q,
                                         bool wide_counts, const uint32_t *S2lo,
                                         const uint32_t *S2hi, const uint32_t *T) {
   wave_sync();
-  const uint32_t ia = q.ha + (uint32_t)lane;
-  const uint32_t tag0 = W.qa[min(ia, ia - kQA)];  // ring position (q.ha < kQA)
+  const uint32_t tag0 = W.qa[q.ha + (uint32_t)lane];  // q.ha + 63 < kQA: no wrap
   wave_sync();
   const bool v = (uint32_t)lane < c;
   const unsigned long long vmask = c >= 64 ? ~0ull : ((1ull << c) - 1ull);
@@ -293,11 +294,13 @@ __device__ __forceinline__ void drain_a(WaveLds &W, QState &q,
   // tables (S2[k] = floor(s_k^2) and d2 is an integer).  inv_ds carries a
   // factor 1 - 2^-20, larger than the FP32 error of the quotient, so x' < x
   // whenever x > 0 and trunc(x') + 1 is k* or k* - 1: one comparison with the
-  // table restores the exact step.  Same for l* with the T table.  kk, ll are
+  // table restores the exact step.  The time estimate is an integer product
+  // high word with the same two properties (below u n_t / t_max by less than
+  // 1/4, strictly below it for u > 0), corrected with the T table.  kk, ll are
   // the 0-based steps.
   const float d2f = MODE == kModeWide ? (float)d2 : (float)d2lo;
   const uint32_t k0 = (uint32_t)(__builtin_amdgcn_sqrtf(d2f) * g.inv_ds);
-  const uint32_t l0 = (uint32_t)((float)u * g.inv_dt);
+  const uint32_t l0 = __umulhi(u << g.tsh, g.tmul);
   const uint32_t sk = S2lo[k0], tl = T[l0];
   bool up_k;
   if (MODE == kModeWide)
@@ -334,7 +337,13 @@ __device__ __forceinline__ void drain_a(WaveLds &W, QState &q,
     else
       atomicAdd(histc + bin, 1u);
   }
-  q.ha = q.ha + c >= kQA ? q.ha + c - kQA : q.ha + c;
+  if (c == 64) {
+    q.ha = q.ha + 64 == kQA ? 0u : q.ha + 64;
+  } else {
+    // a partial drain takes every pending entry
+    q.ha = 0;
+    q.ta = 0;
+  }
   if (MODE == kModePacked) {
     // one record per pair with a boundary side
     const bool need = si.slow || sj.slow;
@@ -369,18 +378,21 @@ __device__ __forceinline__ void drain_a(WaveLds &W, QState &q,
 
 // LDS image of a sorted point (see WaveLds).  Without spatial correction the
 // interior bound (min(ex,ey)^2, or the side distance) is set to 2^32 - 1 so
-// that no pair takes the boundary path.
+// that no pair takes the boundary path.  A record marked as no neighbour (bit
+// 31 of its edge distance: a type-1 point of a cross-K set) takes the padding
+// time, so it fails every time test; centres clear the mark before this.
 template <int MODE>
 __device__ __forceinline__ int4 image(const int4 p, const Geom &g) {
   const bool iso = (g.edge & 1u) != 0;
+  const int tm = p.w < 0 ? (int)kFarTime : p.z;
   if (MODE == kModePacked) {
     const uint32_t ex = min((uint32_t)min(p.x, g.x1 - g.x0 - p.x), kClampE);
     const uint32_t ey = min((uint32_t)min(p.y, g.y1 - g.y0 - p.y), kClampE);
     const uint32_t e = min(ex, ey);
-    return make_int4((int)(((uint32_t)p.x & 0xFFFFu) | ((uint32_t)p.y << 16)), p.z,
+    return make_int4((int)(((uint32_t)p.x & 0xFFFFu) | ((uint32_t)p.y << 16)), tm,
                      (int)(ex | (ey << 16)), iso ? (int)(e * e) : -1);
   }
-  return make_int4(p.x, p.y, p.z, iso ? p.w : -1);
+  return make_int4(p.x, p.y, tm, iso ? p.w : -1);
 }
 
 template <int MODE>
@@ -601,7 +613,8 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
     const bool valid = (uint32_t)lane < cnt;
     const unsigned long long vmask = __builtin_amdgcn_ballot_w64(valid);
     const uint32_t mi = begin + (uint32_t)lane;
-    const int4 raw = valid ? a.P[mi] : make_int4(0, 0, 0, 0);
+    int4 raw = valid ? a.P[mi] : make_int4(0, 0, 0, 0);
+    raw.w &= 0x7FFFFFFF;  // a centre is always evaluated (cross K: its neighbour mark)
     const int4 me = image<MODE>(raw, g);
     const uint32_t tplus = (uint32_t)(MODE == kModePacked ? me.y : me.z) + g.tmax;
     const int thr = valid ? (int)g.s2max : -1;

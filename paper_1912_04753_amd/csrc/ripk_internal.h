@@ -35,7 +35,10 @@ struct Geom {
   uint64_t s2max;                  // S2[n_s-1]
   uint32_t tmax;                   // T[n_t-1]
   float inv_ds;                    // n_s / s_max * (1 - 2^-20)
-  float inv_dt;                    // n_t / t_max * (1 - 2^-20)
+  // time step estimate l0 = mulhi(u << tsh, tmul): tmul = ceil(2^(32-tsh) n_t / t_max) - 1
+  // (tsh = 0 unless n_t > t_max), so that u n_t / t_max - 1/4 < l0 <= u n_t / t_max, with
+  // the second inequality strict for u > 0
+  uint32_t tmul, tsh;
 };
 
 // Work item of the pair kernel: up to kChunk consecutive centres of one unit
@@ -93,13 +96,17 @@ hipError_t launch_keys(const int32_t *x, const int32_t *y, const int32_t *t, uin
                        uint32_t n_centres, uint32_t set_base, uint32_t n_sets,
                        const Geom &g, uint32_t *keys, uint32_t *vals, uint32_t *err,
                        hipStream_t s);
-hipError_t launch_csr(uint32_t n, uint32_t m, uint64_t seed, const Geom &g, int32_t *x,
-                      int32_t *y, int32_t *t, uint32_t *keys, uint32_t *vals,
+// m CSR sets of n points; points k >= n_centres of each set take the halo slot
+// of their cell (type 2 of a cross-K plan; n_centres = n otherwise)
+hipError_t launch_csr(uint32_t n, uint32_t n_centres, uint32_t m, uint64_t seed, const Geom &g,
+                      int32_t *x, int32_t *y, int32_t *t, uint32_t *keys, uint32_t *vals,
                       hipStream_t s);
 // Simulated sets drawn from the observed points ox, oy, ot (n each): method 1
-// random permutation of the time labels, 2 bootstrap; writes x, y, t and the
-// cell keys/values into keys[0], vals[0] (uses both sort buffers).
-hipError_t launch_resample(int method, uint32_t n, uint32_t m, uint64_t seed, const int32_t *ox,
+// random permutation of the time labels, 2 bootstrap (each of the types
+// [0, n_centres) and [n_centres, n) from itself); writes x, y, t and the cell
+// keys/values into keys[0], vals[0] (uses both sort buffers).
+hipError_t launch_resample(int method, uint32_t n, uint32_t n_centres, uint32_t m, uint64_t seed,
+                           const int32_t *ox,
                            const int32_t *oy, const int32_t *ot, const Geom &g, int32_t *x,
                            int32_t *y, int32_t *t, uint32_t *keys[2], uint32_t *vals[2],
                            void *sort_temp, hipStream_t s);
@@ -111,9 +118,12 @@ hipError_t exclusive_scan(const uint32_t *in, uint32_t *out, uint32_t n, void *t
                           hipStream_t s);
 hipError_t launch_cell_bounds(const uint32_t *keys, uint32_t n, uint32_t n_keys,
                               uint32_t *cs, hipStream_t s);
-hipError_t launch_gather(const uint32_t *vals, uint32_t n, const int32_t *x, const int32_t *y,
-                         const int32_t *t, const Geom &g, int32_t clamp_e, int4 *P,
-                         hipStream_t s);
+// Sorted records {x, y, t, edge distance}; with `mark`, records whose key is a
+// centre slot (halo bit clear) get bit 31 of the edge distance set: in a
+// cross-K plan they are type 1 and no neighbour of anything.
+hipError_t launch_gather(const uint32_t *vals, const uint32_t *keys, int mark, uint32_t n,
+                         const int32_t *x, const int32_t *y, const int32_t *t, const Geom &g,
+                         int32_t clamp_e, int4 *P, hipStream_t s);
 hipError_t launch_items(const uint32_t *cs, uint32_t n_sets, const Geom &g, bool row_items,
                         uint32_t split, uint32_t n_rows, uint32_t *chunks,
                         uint32_t *offs, uint32_t *set_base, Item *items, uint32_t *n_items,

@@ -89,9 +89,9 @@ def kernel_stats(stats_csv, top=12):
 
 
 PROFILE_CMD = ("rocprofv3 --kernel-trace --stats --output-format csv -d $R/gpurun_out/prof -o run -- "
-               "python3 $R/bench.py --steps {steps} --warmup 1 --no-cpu-baseline --serve-requests 0")
+               "python3 $R/bench.py --steps {steps} --warmup 1 --main-only")
 PMC_CMD = ("timeout -s KILL 120 rocprofv3 --pmc {counter} --output-format csv -d $R/gpurun_out/{d} -o {o} "
-           "-- python3 $R/bench.py --steps 1 --warmup 0 --no-cpu-baseline --serve-requests 0 "
+           "-- python3 $R/bench.py --steps 1 --warmup 0 --main-only "
            "--copy-calibration")
 
 
