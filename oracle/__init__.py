@@ -42,6 +42,7 @@ class OrcDesc(ctypes.Structure):
         ("s_max", ctypes.c_int64), ("t_max", ctypes.c_int64),
         ("n_s", ctypes.c_int32), ("n_t", ctypes.c_int32),
         ("edge", ctypes.c_uint32), ("norm", ctypes.c_uint32),
+        ("poly", ctypes.POINTER(ctypes.c_int32)), ("poly_n", ctypes.c_int32),
     ]
 
 
@@ -63,6 +64,10 @@ def lib():
         L.orc_thresholds.argtypes = [dp, i64p, i64p]
         L.orc_omega.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, dp]
         L.orc_omega.restype = ctypes.c_double
+        L.orc_poly_contains.argtypes = [dp, ctypes.c_int64, ctypes.c_int64]
+        L.orc_poly_contains.restype = ctypes.c_int
+        L.orc_poly_area.argtypes = [dp]
+        L.orc_poly_area.restype = ctypes.c_double
         L.orc_vt.argtypes = [ctypes.c_int64, ctypes.c_int64, dp]
         L.orc_vt.restype = ctypes.c_double
         L.orc_hist.argtypes = [dp, i32p, i32p, i32p, ctypes.c_int64, ctypes.c_int64,
@@ -94,11 +99,30 @@ def lib():
     return _lib
 
 
-def desc(window, s_max, t_max, n_s, n_t, edge=EDGE_ISO, norm=NORM_NN1):
-    """Pack a study window ``(x0, y0, x1, y1, t0, t1)`` and grid into OrcDesc."""
+def desc(window, s_max, t_max, n_s, n_t, edge=EDGE_ISO, norm=NORM_NN1, poly=None):
+    """Pack a study window ``(x0, y0, x1, y1, t0, t1)`` and grid into OrcDesc.
+    ``poly``: optional polygon study area, an (k, 2) array of integer vertices
+    (the rectangle then bounds it and fixes the period only)."""
     x0, y0, x1, y1, t0, t1 = (int(v) for v in window)
-    return OrcDesc(x0, y0, x1, y1, t0, t1, int(s_max), int(t_max), int(n_s), int(n_t),
-                   int(edge), int(norm))
+    d = OrcDesc(x0, y0, x1, y1, t0, t1, int(s_max), int(t_max), int(n_s), int(n_t),
+                int(edge), int(norm))
+    if poly is not None:
+        v = np.ascontiguousarray(np.asarray(poly, np.int32).reshape(-1, 2))
+        d.poly = v.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        d.poly_n = len(v)
+        d.keep = v  # the vertex array lives as long as the descriptor
+    return d
+
+
+def poly_contains(d, x, y):
+    """1 where (x, y) lies strictly inside the descriptor's polygon."""
+    return np.array([lib().orc_poly_contains(ctypes.byref(d), int(a), int(b))
+                     for a, b in zip(np.atleast_1d(x), np.atleast_1d(y))], np.int32)
+
+
+def poly_area(d):
+    """Shoelace area of the descriptor's polygon."""
+    return lib().orc_poly_area(ctypes.byref(d))
 
 
 def _ptr(a, ct):

@@ -36,6 +36,14 @@
  * with both corrections centred on the type-1 point i, and L12 from K12 as in
  * Eq. 4.  The histogram loop is the same, with i over type 1 and j over type 2.
  *
+ * Polygon study areas (the general case of the isotropic correction, Sec. 3 and
+ * the boundary-vertex cost of Sec. 4.4): A is the polygon's area, points lie
+ * strictly inside it, omega is the share of the circle's circumference inside
+ * it (arcs between crossing points, each classified by its midpoint), and the
+ * spatial weight 1/omega is capped at 64.  CSR points are drawn by rejection:
+ * attempt a of point i uses counter (i, sim, a, 0) and the first attempt
+ * strictly inside is kept.
+ *
  * Simulations (Sec. 3, Monte Carlo under complete spatio-temporal randomness):
  * n points uniform over the window, drawn from Philox4x64-10 (Salmon, Moraes,
  * Dror, Shaw, "Parallel random numbers: as easy as 1, 2, 3", SC'11) with
@@ -62,7 +70,12 @@ typedef struct {
   int32_t n_s, n_t;       /* grid steps                                   */
   uint32_t edge;          /* bit 0: isotropic spatial, bit 1: temporal    */
   uint32_t norm;          /* 0: n(n-1), 1: n^2                            */
+  const int32_t *poly;    /* optional polygon study area: vertex k at     */
+                          /* (poly[2k], poly[2k+1]), closed implicitly    */
+  int32_t poly_n;         /* vertex count; below 3: the rectangle         */
 } orc_desc;
+
+#define ORC_MAX_SWEIGHT 64.0 /* cap of the spatial weight 1/omega (polygons) */
 
 /* ---------------------------------------------------------------- O1 -- */
 /* Integer thresholds: S2[k-1] = floor((k*s_max)^2 / n_s^2), T[l-1] =
@@ -84,8 +97,11 @@ void orc_thresholds(const orc_desc *q, int64_t *S2, int64_t *T) {
  * (a_p + a_q - pi/2), which is added back once.  Valid while no two opposite
  * sides are both cut, which holds for r <= min(W, H)/2.  A zero radius gives
  * omega = 1.  (Sec. 3, isotropic correction) */
+double orc_omega_poly(int64_t x, int64_t y, int64_t d2, const orc_desc *q);
+
 double orc_omega(int64_t x, int64_t y, int64_t d2, const orc_desc *q) {
   if (!(q->edge & ORC_EDGE_SPATIAL)) return 1.0;
+  if (q->poly_n >= 3) return orc_omega_poly(x, y, d2, q);
   int64_t e[4] = {x - q->x0, q->x1 - x, y - q->y0, q->y1 - y};
   int cut[4];
   double a[4];
@@ -104,6 +120,120 @@ double orc_omega(int64_t x, int64_t y, int64_t d2, const orc_desc *q) {
       excluded -= (a[p] + a[s] - M_PI / 2.0);
   }
   return 1.0 - excluded / (2.0 * M_PI);
+}
+
+/* ------------------------------------------------------------ O3 poly -- */
+/* Polygon study area.  Exact integer tests for points; FP64 for the circle. */
+static void orc_vertex(const orc_desc *q, int k, int64_t *x, int64_t *y) {
+  k %= q->poly_n;
+  *x = q->poly[2 * k];
+  *y = q->poly[2 * k + 1];
+}
+
+/* 1 if (px, py) lies strictly inside the polygon (crossing number along +x with
+ * the half-open rule; a point on an edge is not inside), else 0. */
+int orc_poly_contains(const orc_desc *q, int64_t px, int64_t py) {
+  int inside = 0;
+  for (int k = 0; k < q->poly_n; ++k) {
+    int64_t ax, ay, bx, by;
+    orc_vertex(q, k, &ax, &ay);
+    orc_vertex(q, k + 1, &bx, &by);
+    const int64_t cr = (bx - ax) * (py - ay) - (by - ay) * (px - ax);
+    if (cr == 0 && px >= (ax < bx ? ax : bx) && px <= (ax > bx ? ax : bx) &&
+        py >= (ay < by ? ay : by) && py <= (ay > by ? ay : by))
+      return 0; /* on the boundary */
+    if ((ay > py) != (by > py)) {
+      /* crossing x = ax + (py - ay)(bx - ax)/(by - ay); px < crossing ? */
+      const int64_t num = (py - ay) * (bx - ax), den = by - ay;
+      const int64_t lhs = (px - ax) * den;
+      if (den > 0 ? lhs < num : lhs > num) inside ^= 1;
+    }
+  }
+  return inside;
+}
+
+/* the same crossing-number rule for a point with real coordinates */
+static int orc_poly_contains_f(const orc_desc *q, double px, double py) {
+  int inside = 0;
+  for (int k = 0; k < q->poly_n; ++k) {
+    int64_t ax, ay, bx, by;
+    orc_vertex(q, k, &ax, &ay);
+    orc_vertex(q, k + 1, &bx, &by);
+    if (((double)ay > py) != ((double)by > py)) {
+      const double xc = (double)ax + (py - (double)ay) * (double)(bx - ax) / (double)(by - ay);
+      if (px < xc) inside ^= 1;
+    }
+  }
+  return inside;
+}
+
+/* area by the shoelace formula */
+double orc_poly_area(const orc_desc *q) {
+  int64_t x0, y0, acc = 0;
+  orc_vertex(q, 0, &x0, &y0);
+  for (int k = 0; k < q->poly_n; ++k) {
+    int64_t ax, ay, bx, by;
+    orc_vertex(q, k, &ax, &ay);
+    orc_vertex(q, k + 1, &bx, &by);
+    acc += (ax - x0) * (by - y0) - (bx - x0) * (ay - y0);
+  }
+  return 0.5 * (double)(acc < 0 ? -acc : acc);
+}
+
+static int orc_dbl_cmp(const void *a, const void *b) {
+  const double u = *(const double *)a, v = *(const double *)b;
+  return u < v ? -1 : (u > v ? 1 : 0);
+}
+
+/* Share of the circle centred on (x, y) with radius sqrt(d2) inside the
+ * polygon: every crossing of the circle with an edge (closed segment; the
+ * discriminant exact in 128-bit integers), sorted by angle; each arc between
+ * consecutive crossings counts when its midpoint is inside. */
+double orc_omega_poly(int64_t x, int64_t y, int64_t d2, const orc_desc *q) {
+  if (d2 == 0) return 1.0;
+  const double r = sqrt((double)d2);
+  int cap = 2 * q->poly_n + 2, m = 0;
+  double *ang = (double *)malloc(sizeof(double) * (size_t)cap);
+  if (!ang) return -1.0;
+  for (int k = 0; k < q->poly_n; ++k) {
+    int64_t ax, ay, bx, by;
+    orc_vertex(q, k, &ax, &ay);
+    orc_vertex(q, k + 1, &bx, &by);
+    const int64_t Ax = ax - x, Ay = ay - y, Ex = bx - ax, Ey = by - ay;
+    /* |A + s E|^2 = d2:  ee s^2 + 2 ae s + (aa - d2) = 0 */
+    const __int128 ee = (__int128)Ex * Ex + (__int128)Ey * Ey;
+    const __int128 ae = (__int128)Ax * Ex + (__int128)Ay * Ey;
+    const __int128 aa = (__int128)Ax * Ax + (__int128)Ay * Ay;
+    if (ee == 0) continue;
+    const __int128 disc = ae * ae - ee * (aa - d2);
+    if (disc < 0) continue;
+    const long double sq = sqrtl((long double)disc);
+    for (int sg = -1; sg <= 1; sg += 2) {
+      const long double sp = (-(long double)ae + sg * sq) / (long double)ee;
+      if (sp < -1e-12L || sp > 1.0L + 1e-12L) continue;
+      const double cx = (double)((long double)Ax + sp * (long double)Ex);
+      const double cy = (double)((long double)Ay + sp * (long double)Ey);
+      double th = atan2(cy, cx);
+      if (th < 0) th += 2.0 * M_PI;
+      ang[m++] = th;
+      if (disc == 0) break;
+    }
+  }
+  double inside = 0.0;
+  if (m == 0) {
+    inside = orc_poly_contains_f(q, (double)x + r, (double)y) ? 2.0 * M_PI : 0.0;
+  } else {
+    qsort(ang, (size_t)m, sizeof(double), orc_dbl_cmp);
+    for (int k = 0; k < m; ++k) {
+      const double a0 = ang[k], a1 = (k + 1 < m) ? ang[k + 1] : ang[0] + 2.0 * M_PI;
+      if (a1 - a0 <= 0.0) continue;
+      const double mid = 0.5 * (a0 + a1);
+      if (orc_poly_contains_f(q, (double)x + r * cos(mid), (double)y + r * sin(mid)))
+        inside += a1 - a0;
+    }
+  }
+  free(ang);
+  return inside / (2.0 * M_PI);
 }
 
 /* ---------------------------------------------------------------- O4 -- */
@@ -178,7 +308,10 @@ static int orc_hist_range(const orc_desc *q, const int32_t *x, const int32_t *y,
         while (d2 > S2[k]) ++k; /* smallest k with d2 <= S2[k] */
         int l = 0;
         while (u > T[l]) ++l;
-        double w = 1.0 / (orc_omega(xi, yi, d2, q) * orc_vt(ti, u, q));
+        /* spatial weight 1/omega, capped (omega >= 1/4 on a rectangle) */
+        double om = orc_omega(xi, yi, d2, q);
+        if (om < 1.0 / ORC_MAX_SWEIGHT) om = 1.0 / ORC_MAX_SWEIGHT;
+        double w = 1.0 / (om * orc_vt(ti, u, q));
         c[k * nt + l] += 1;
         neumaier(&s[k * nt + l], &e[k * nt + l], w);
       }
@@ -233,7 +366,8 @@ void orc_cumulate(const orc_desc *q, uint64_t *C, double *W) {
 static void orc_normalise_by(const orc_desc *q, double N, const double *W, double *K,
                              double *L) {
   const int ns = q->n_s, nt = q->n_t;
-  const double A = (double)(q->x1 - q->x0) * (double)(q->y1 - q->y0);
+  const double A = q->poly_n >= 3 ? orc_poly_area(q)
+                                  : (double)(q->x1 - q->x0) * (double)(q->y1 - q->y0);
   const double D = (double)(q->t1 - q->t0);
   for (int k = 0; k < ns; ++k) {
     const double sk = (double)(k + 1) * (double)q->s_max / (double)ns;
@@ -328,18 +462,22 @@ void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t ou
 
 /* CSR simulation `sim` of n points: point i takes Philox(counter=(i,sim,0,0),
  * key=(seed,0)); x = x0 + floor(r0*(x1-x0)/2^64), likewise y with r1 and t
- * with r2 over [t0, t1). */
+ * with r2 over [t0, t1).  With a polygon, attempts a = 0, 1, ... use counter
+ * (i, sim, a, 0) until the point lies strictly inside. */
 void orc_csr_points(int64_t n, int64_t sim, uint64_t seed, const orc_desc *q, int32_t *x,
                     int32_t *y, int32_t *t) {
   const uint64_t W = (uint64_t)(q->x1 - q->x0), H = (uint64_t)(q->y1 - q->y0),
                  D = (uint64_t)(q->t1 - q->t0);
   const uint64_t key[2] = {seed, 0};
   for (int64_t i = 0; i < n; ++i) {
-    uint64_t ctr[4] = {(uint64_t)i, (uint64_t)sim, 0, 0}, r[4];
-    orc_philox4x64_10(ctr, key, r);
-    x[i] = (int32_t)(q->x0 + (int64_t)mulhi64(r[0], W));
-    y[i] = (int32_t)(q->y0 + (int64_t)mulhi64(r[1], H));
-    t[i] = (int32_t)(q->t0 + (int64_t)mulhi64(r[2], D));
+    for (uint64_t a = 0;; ++a) {
+      uint64_t ctr[4] = {(uint64_t)i, (uint64_t)sim, a, 0}, r[4];
+      orc_philox4x64_10(ctr, key, r);
+      x[i] = (int32_t)(q->x0 + (int64_t)mulhi64(r[0], W));
+      y[i] = (int32_t)(q->y0 + (int64_t)mulhi64(r[1], H));
+      t[i] = (int32_t)(q->t0 + (int64_t)mulhi64(r[2], D));
+      if (q->poly_n < 3 || orc_poly_contains(q, x[i], y[i])) break;
+    }
   }
 }
 

@@ -17,6 +17,11 @@ recipes stand in for them:
   floored to integers.  It stands in for the strongly skewed POI data the
   paper describes (Sec. 6.2).
 
+* ``polygon``  -- a seeded star-shaped simple polygon with dents (concave
+  vertices) standing in for the administrative boundaries of the paper's
+  experiments (a Hubei province boundary and an 85-vertex simplified US
+  boundary, Sec. 6 and the appendix), with points uniform strictly inside it.
+
 Sizes and grids bracket the paper's experiments (10k-500k points, 10-20 grid
 steps per axis; Sec. 6.1, Table 5, appendix Table A).  Units: metres and
 seconds; a day is 86,400 s.
@@ -64,6 +69,66 @@ def thomas_points(rng, n, window, parents, sigma_xy, sigma_t):
             np.floor(t).astype(np.int32))
 
 
+def star_polygon(rng, window, n_vertices, dent=0.45):
+    """Integer vertices (n_vertices, 2) of a simple polygon, star-shaped about
+    the window centre: vertex k at angle 2*pi*(k + jitter_k)/v (jitter in
+    (-0.3, 0.3), so angles increase) and radius R*(1 - dent*f_k), where
+    R = 0.48*min(W, H) and f in [0, 1] is a sum of six random Fourier modes
+    rescaled to [0, 1]."""
+    x0, y0, x1, y1 = window[:4]
+    cx, cy = 0.5 * (x0 + x1), 0.5 * (y0 + y1)
+    R = 0.48 * min(x1 - x0, y1 - y0)
+    v = int(n_vertices)
+    th = 2 * math.pi * (np.arange(v) + rng.uniform(-0.3, 0.3, v)) / v
+    f = np.zeros(v)
+    for h in range(1, 7):
+        f += rng.normal(0, 1.0 / h) * np.cos(h * th + rng.uniform(0, 2 * math.pi))
+    f = (f - f.min()) / max(f.max() - f.min(), 1e-12)
+    r = R * (1.0 - dent * f)
+    px = np.clip(np.rint(cx + r * np.cos(th)), x0, x1).astype(np.int64)
+    py = np.clip(np.rint(cy + r * np.sin(th)), y0, y1).astype(np.int64)
+    return np.stack([px, py], axis=1).astype(np.int32)
+
+
+def _strictly_inside(poly, x, y):
+    """Crossing number along +x with the half-open rule, on integers; points on
+    an edge are not inside.  For drawing inputs only."""
+    P = np.asarray(poly, np.int64)
+    ax, ay = P[:, 0][None, :], P[:, 1][None, :]
+    bx, by = np.roll(P[:, 0], -1)[None, :], np.roll(P[:, 1], -1)[None, :]
+    X = np.asarray(x, np.int64)[:, None]
+    Y = np.asarray(y, np.int64)[:, None]
+    cr = (bx - ax) * (Y - ay) - (by - ay) * (X - ax)
+    on = ((cr == 0) & (X >= np.minimum(ax, bx)) & (X <= np.maximum(ax, bx)) &
+          (Y >= np.minimum(ay, by)) & (Y <= np.maximum(ay, by))).any(axis=1)
+    straddle = (ay > Y) != (by > Y)
+    den = by - ay
+    lhs = (X - ax) * den
+    num = (Y - ay) * (bx - ax)
+    left = np.where(den > 0, lhs < num, lhs > num)
+    inside = (np.count_nonzero(straddle & left, axis=1) % 2) == 1
+    return inside & ~on
+
+
+def polygon_points(rng, n, window, poly):
+    """n points uniform on the integer grid strictly inside the polygon (by
+    rejection from the window), times uniform on [t0, t1)."""
+    xs, ys = [], []
+    got = 0
+    while got < n:
+        k = max(1024, 2 * (n - got))
+        x, y, _ = uniform_points(rng, k, window)
+        ok = np.zeros(k, bool)
+        for a in range(0, k, 8192):
+            ok[a:a + 8192] = _strictly_inside(poly, x[a:a + 8192], y[a:a + 8192])
+        xs.append(x[ok]); ys.append(y[ok])
+        got += int(ok.sum())
+    x = np.concatenate(xs)[:n]
+    y = np.concatenate(ys)[:n]
+    t = rng.integers(window[4], window[5], size=n, dtype=np.int64).astype(np.int32)
+    return x, y, t
+
+
 # The five workloads.  ``window`` = (x0, y0, x1, y1, t0, t1); isotropic spatial
 # and temporal edge correction (edge = 3) throughout.
 WORKLOADS = {
@@ -77,6 +142,9 @@ WORKLOADS = {
     "uniform-100k-99csr": dict(name="uniform-100k-99csr", seed=3, window=(0, 0, 20_000, 20_000, 0, 180 * DAY),
             s_max=2_000, n_s=25, t_max=30 * DAY, n_t=15, sims=99,
             parts=[("uniform", 100_000, {})]),
+    "polygon-100k-99csr": dict(name="polygon-100k-99csr", seed=6,
+            window=(0, 0, 20_000, 20_000, 0, 180 * DAY), s_max=2_000, n_s=25, t_max=30 * DAY, n_t=15,
+            sims=99, polygon=85, parts=[("polygon", 100_000, {})]),
     "mixed-2M-19csr": dict(name="mixed-2M-19csr", seed=4, window=(0, 0, 100_000, 100_000, 0, 730 * DAY),
             s_max=10_000, n_s=50, t_max=90 * DAY, n_t=30, sims=19,
             parts=[("uniform", 1_000_000, {}),
@@ -90,7 +158,9 @@ def make_points(cfg):
     rng = _rng(cfg["seed"])
     xs, ys, ts = [], [], []
     for kind, n, kw in cfg["parts"]:
-        if kind == "uniform":
+        if kind == "polygon":
+            x, y, t = polygon_points(rng, n, cfg["window"], polygon_of(cfg))
+        elif kind == "uniform":
             x, y, t = uniform_points(rng, n, cfg["window"])
         elif kind == "thomas":
             x, y, t = thomas_points(rng, n, cfg["window"], **kw)
@@ -98,6 +168,14 @@ def make_points(cfg):
             raise ValueError(kind)
         xs.append(x); ys.append(y); ts.append(t)
     return np.concatenate(xs), np.concatenate(ys), np.concatenate(ts)
+
+
+def polygon_of(cfg):
+    """The workload's study polygon (None for a rectangle): drawn from its own
+    stream (seed + 1000) so the points do not depend on how it was drawn."""
+    if not cfg.get("polygon"):
+        return None
+    return star_polygon(_rng(cfg["seed"] + 1000), cfg["window"], cfg["polygon"])
 
 
 def workload(name):

@@ -563,3 +563,142 @@ def test_typed_bootstrap_draws_each_type_from_itself():
     a = oracle.resampled_points(x, y, t, sim, seed, oracle.SIM_BOOTSTRAP, n1=n)
     b = oracle.resampled_points(x, y, t, sim, seed, oracle.SIM_BOOTSTRAP)
     assert all(np.array_equal(u, v) for u, v in zip(a, b))
+
+
+# ----------------------------------------------------- polygon study area ----
+L_SHAPE = [(0, 0), (2000, 0), (2000, 1000), (1000, 1000), (1000, 2000), (0, 2000)]
+
+
+def _inside_np(poly, px, py):
+    """Crossing number of real points (vectorised), written for these tests."""
+    P = np.asarray(poly, np.float64)
+    ax, ay = P[:, 0], P[:, 1]
+    bx, by = np.roll(ax, -1), np.roll(ay, -1)
+    X, Y = px[:, None], py[:, None]
+    st = (ay > Y) != (by > Y)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        xc = ax + (Y - ay) * (bx - ax) / (by - ay)
+    return (np.count_nonzero(st & (X < xc), axis=1) % 2) == 1
+
+
+def test_polygon_rectangle_reduces_to_rectangle():
+    """A polygon that is the window rectangle (either orientation) gives the
+    rectangle's closed-form omega, area and whole estimate."""
+    win = (0, 0, 3000, 2000, 0, 100_000)
+    rect = [(0, 0), (3000, 0), (3000, 2000), (0, 2000)]
+    dr = oracle.desc(win, 900, 20_000, 6, 4)
+    rng = np.random.default_rng(21)
+    for poly in (rect, rect[::-1]):
+        dp = oracle.desc(win, 900, 20_000, 6, 4, poly=poly)
+        assert oracle.poly_area(dp) == 6e6
+        for _ in range(400):
+            x, y = int(rng.integers(1, 3000)), int(rng.integers(1, 2000))
+            d2 = int(rng.integers(0, 1000 ** 2))
+            assert abs(oracle.omega(x, y, d2, dp) - oracle.omega(x, y, d2, dr)) < 1e-12
+    n = 400
+    x = rng.integers(1, 3000, n); y = rng.integers(1, 2000, n); t = rng.integers(0, 100_001, n)
+    a = oracle.estimate(dr, x, y, t)
+    b = oracle.estimate(oracle.desc(win, 900, 20_000, 6, 4, poly=rect), x, y, t)
+    assert np.array_equal(a["C"], b["C"])
+    assert np.allclose(a["K"], b["K"], rtol=1e-12, atol=0)
+
+
+def test_polygon_omega_hand_derived_reflex_corner():
+    """L-shaped area, centre (1100, 900) at distance 100 from both lines of the
+    reflex corner (1000, 1000).  The circle of radius r leaves the area where
+    x > 1000 and y > 1000, i.e. sin(th) > a and cos(th) > -a with a = 100/r:
+    th from arcsin(a) to min(pi - arcsin(a), pi/2 + arcsin(a)).  For
+    r >= 100*sqrt(2) that is an arc of pi/2 (omega = 3/4, until the sides 900
+    away are reached); for 100 < r < 100*sqrt(2) it is pi - 2*arcsin(a); below
+    r = 100 the circle stays inside (omega = 1)."""
+    d = oracle.desc((0, 0, 2000, 2000, 0, 1000), 600, 100, 3, 2, poly=L_SHAPE)
+    for r2 in (2 * 100 ** 2, 200 ** 2, 400 ** 2, 890 ** 2):
+        assert abs(oracle.omega(1100, 900, r2, d) - 0.75) < 1e-12, r2
+    for r2 in (101 ** 2, 120 ** 2, 141 ** 2):
+        want = 1 - (math.pi - 2 * math.asin(100 / math.sqrt(r2))) / (2 * math.pi)
+        assert abs(oracle.omega(1100, 900, r2, d) - want) < 1e-12, r2
+    assert oracle.omega(1100, 900, 99 ** 2, d) == 1.0
+    # a convex corner of the L: quarter of the circle inside at the vertex limit
+    assert abs(oracle.omega(1, 1, 500 ** 2, d) - 0.25) < 2e-3
+    assert oracle.poly_area(d) == 3e6
+
+
+def test_polygon_omega_against_angle_sampling():
+    """The 85-vertex synthetic boundary: omega against the share of 200,000
+    equally spaced points of the circle that lie inside (an independent
+    crossing-number test); the sampling error is a few crossings / 200,000."""
+    c = workloads.workload("polygon-100k-99csr")
+    P = workloads.polygon_of(c)
+    d = oracle.desc(c["window"], c["s_max"], c["t_max"], c["n_s"], c["n_t"], poly=P)
+    rng = np.random.default_rng(8)
+    x, y, _ = workloads.polygon_points(rng, 60, c["window"], P)
+    th = (np.arange(200_000) + 0.5) * (2 * np.pi / 200_000)
+    checked = 0
+    for i in range(60):
+        d2 = int(rng.integers(1, 3_000 ** 2))
+        r = math.sqrt(d2)
+        share = _inside_np(P, x[i] + r * np.cos(th), y[i] + r * np.sin(th)).mean()
+        om = oracle.omega(int(x[i]), int(y[i]), d2, d)
+        assert abs(om - share) < 1e-4, (i, om, share)
+        checked += om < 1.0
+    assert checked >= 10  # many circles actually cross the boundary
+
+
+def test_polygon_containment_and_area():
+    d = oracle.desc((0, 0, 2000, 2000, 0, 1000), 600, 100, 3, 2, poly=L_SHAPE)
+    pts = [(500, 500, 1), (1500, 500, 1), (1500, 1500, 0), (0, 500, 0), (1000, 1500, 0),
+           (1000, 1000, 0), (999, 1500, 1), (2000, 2000, 0), (1999, 999, 1), (1999, 1000, 0)]
+    got = oracle.poly_contains(d, [p[0] for p in pts], [p[1] for p in pts])
+    assert got.tolist() == [p[2] for p in pts]
+    d2 = oracle.desc((0, 0, 2000, 2000, 0, 1000), 600, 100, 3, 2, poly=L_SHAPE[::-1])
+    assert oracle.poly_area(d2) == 3e6
+
+
+def test_polygon_csr_rejection_follows_philox():
+    """CSR in a polygon: attempt a of point i uses Philox counter (i, sim, a, 0)
+    (key (seed, 0)); the first attempt strictly inside is kept."""
+    win = (0, 0, 2000, 2000, 0, 1000)
+    d = oracle.desc(win, 600, 100, 3, 2, poly=L_SHAPE)
+    n, sim, seed = 300, 2, 13
+    x, y, t = oracle.csr_points(d, n, sim, seed)
+    assert oracle.poly_contains(d, x, y).all()
+    for i in range(n):
+        for a in range(64):
+            r = _numpy_block([seed, 0], [i, sim, a, 0])
+            px, py = (r[0] * 2000) >> 64, (r[1] * 2000) >> 64
+            if oracle.poly_contains(d, px, py)[0]:
+                assert (x[i], y[i], t[i]) == (px, py, (r[2] * 1000) >> 64), i
+                break
+
+
+def test_polygon_csr_expectation():
+    """CSR inside the L-shaped area with the polygon correction and area:
+    mean K over 120 simulations within 4 standard errors of 2*pi*s^2*t."""
+    win = (0, 0, 2000, 2000, 0, 1_000_000)
+    s_max, n_s, t_max, n_t = 300, 3, 200_000, 4
+    d = oracle.desc(win, s_max, t_max, n_s, n_t, poly=L_SHAPE)
+    m = 120
+    env = oracle.envelope(d, 700, m, seed=5)
+    Ks = env["K_sims"]
+    se = Ks.std(axis=0, ddof=1) / math.sqrt(m)
+    s = (np.arange(1, n_s + 1) * s_max / n_s)[:, None]
+    tt = (np.arange(1, n_t + 1) * t_max / n_t)[None, :]
+    z = (Ks.mean(axis=0) - 2 * np.pi * s ** 2 * tt) / se
+    assert np.all(np.abs(z) < 4.0), z
+
+
+def test_polygon_weight_cap():
+    """A thin spike: a centre near its tip sees less than 1/64 of the circle
+    inside at a radius beyond the spike's width; the spatial weight is capped
+    at 64, so the one ordered pair weighs exactly 64."""
+    spike = [(0, 0), (4000, 0), (4000, 100), (1000, 100), (1000, 4000), (0, 4000)]
+    win = (0, 0, 4000, 4000, 0, 1000)
+    d = oracle.desc(win, 1500, 100, 1, 1, edge=oracle.EDGE_SPATIAL, poly=spike)
+    x = np.array([3990, 2600], np.int32); y = np.array([50, 50], np.int32)
+    t = np.array([10, 10], np.int32)
+    om = oracle.omega(3990, 50, 1390 ** 2, d)
+    assert 0 < om < 1 / 64
+    Hc, Hw = oracle.hist(d, x, y, t)
+    assert Hc[0, 0] == 2
+    w_back = 1.0 / oracle.omega(2600, 50, 1390 ** 2, d)
+    assert abs(Hw[0, 0] - (64.0 + min(w_back, 64.0))) < 1e-9
