@@ -136,7 +136,29 @@ typedef struct {
   int32_t device;         /* HIP device ordinal                                    */
   int32_t cell_div;       /* spatial cells per s_max (0 = library default)         */
   int32_t tcell_div;      /* temporal cells per t_max (0 = library default)        */
+  const int32_t *poly;    /* optional polygon study area, see below (NULL: none)   */
+  int32_t poly_n;         /* its vertex count (0: the rectangle is the study area) */
+  int32_t reserved;       /* 0                                                     */
 } ripk_plan_desc;
+
+/*
+ * Polygon study areas (Sec. 3 defines omega for any study area; the cost of a
+ * weight grows with the boundary's vertex count, Sec. 4.4).  With poly_n >= 3,
+ * vertex k is (poly[2k], poly[2k+1]), the boundary closes from the last vertex
+ * to the first, and the polygon replaces the rectangle as the study area:
+ *   - it must be simple (edges meet only at shared vertices), lie inside the
+ *     rectangle [x0,x1] x [y0,y1], have at most 4096 vertices and an area of at
+ *     least 1/1024 of the rectangle's (RIPK_EINVAL otherwise);
+ *   - A in Eq. 2 is its area (shoelace); every point must lie strictly inside
+ *     it (RIPK_ERANGE otherwise);
+ *   - omega_ij is the share of the circle centred on point i with radius d_ij
+ *     that lies inside the polygon, and the spatial weight 1/omega_ij is capped
+ *     at 64; the rule 2*s_max <= min(x1-x0, y1-y0) does not apply;
+ *   - CSR simulations draw by rejection: attempt a of point k of set s uses the
+ *     Philox counter (k, s, a, 0) and the first attempt strictly inside is kept.
+ * The vertex array is read during ripk_plan_check, ripk_plan and ripk_submit
+ * and copied; the caller keeps ownership.
+ */
 
 typedef struct ripk_plan_s *ripk_plan_t;
 

@@ -11,10 +11,12 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "../../include/ripk.h"
 #include "ripk_internal.h"
@@ -56,14 +58,142 @@ struct Layout {
   Geom g;
   int32_t clamp_e;
   Caps caps;
+  double area = 0;          // study area A of Eq. 2 (rectangle or polygon)
+  std::vector<int2> V;      // polygon vertices, window-relative (empty: rectangle)
 };
+
+int64_t orient(int2 p, int2 q, int2 r) {
+  const int64_t v = (int64_t)(q.x - p.x) * (r.y - p.y) - (int64_t)(q.y - p.y) * (r.x - p.x);
+  return v > 0 ? 1 : (v < 0 ? -1 : 0);
+}
+
+bool on_segment(int2 p, int2 q, int2 r) {  // r on the closed segment pq (collinear given)
+  return r.x >= std::min(p.x, q.x) && r.x <= std::max(p.x, q.x) && r.y >= std::min(p.y, q.y) &&
+         r.y <= std::max(p.y, q.y);
+}
+
+bool segments_meet(int2 a, int2 b, int2 c, int2 d) {
+  const int64_t o1 = orient(a, b, c), o2 = orient(a, b, d), o3 = orient(c, d, a),
+                o4 = orient(c, d, b);
+  if (o1 * o2 < 0 && o3 * o4 < 0) return true;
+  return (o1 == 0 && on_segment(a, b, c)) || (o2 == 0 && on_segment(a, b, d)) ||
+         (o3 == 0 && on_segment(c, d, a)) || (o4 == 0 && on_segment(c, d, b));
+}
+
+// Polygon of a descriptor: window-relative vertices, exact doubled signed
+// area; checks that it is simple and inside the rectangle.
+ripk_status read_polygon(const ripk_plan_desc *d, std::vector<int2> *V, int64_t *area2) {
+  const int n = d->poly_n;
+  if (n < 3 || n > kMaxPoly || !d->poly)
+    return fail(RIPK_EINVAL, "a polygon needs 3 to %d vertices and a vertex array", kMaxPoly);
+  V->resize((size_t)n);
+  for (int k = 0; k < n; ++k) {
+    const int64_t x = d->poly[2 * k], y = d->poly[2 * k + 1];
+    if (x < d->x0 || x > d->x1 || y < d->y0 || y > d->y1)
+      return fail(RIPK_EINVAL, "polygon vertex %d lies outside the rectangle", k);
+    (*V)[(size_t)k] = make_int2((int)(x - d->x0), (int)(y - d->y0));
+  }
+  int64_t a2 = 0;
+  for (int k = 0; k < n; ++k) {
+    const int2 a = (*V)[(size_t)k], b = (*V)[(size_t)((k + 1) % n)];
+    if (a.x == b.x && a.y == b.y) return fail(RIPK_EINVAL, "polygon edge %d has zero length", k);
+    a2 += (int64_t)a.x * b.y - (int64_t)b.x * a.y;
+  }
+  // simple: edges that do not share a vertex do not meet; edges that do share
+  // one do not fold back onto each other
+  for (int i = 0; i < n; ++i) {
+    const int2 a = (*V)[(size_t)i], b = (*V)[(size_t)((i + 1) % n)];
+    for (int j = i + 1; j < n; ++j) {
+      const int2 c = (*V)[(size_t)j], e = (*V)[(size_t)((j + 1) % n)];
+      const bool next = j == i + 1, prev = (j + 1) % n == i;
+      if (next || prev) {
+        // shared vertex s, other ends p (of edge i) and q (of edge j)
+        const int2 sv = next ? b : a, pv = next ? a : b, qv = next ? e : c;
+        if (orient(sv, pv, qv) == 0 &&
+            (int64_t)(pv.x - sv.x) * (qv.x - sv.x) + (int64_t)(pv.y - sv.y) * (qv.y - sv.y) > 0)
+          return fail(RIPK_EINVAL, "polygon edges %d and %d overlap", i, j);
+        continue;
+      }
+      if (segments_meet(a, b, c, e))
+        return fail(RIPK_EINVAL, "polygon edges %d and %d intersect (not a simple polygon)", i, j);
+    }
+  }
+  *area2 = a2;
+  return RIPK_OK;
+}
+
+// squared distance from a point to a closed segment (FP64)
+double seg_point_d2(double ax, double ay, double bx, double by, double px, double py) {
+  const double ex = bx - ax, ey = by - ay, ee = ex * ex + ey * ey;
+  const double s = ee > 0 ? std::min(std::max(((px - ax) * ex + (py - ay) * ey) / ee, 0.0), 1.0) : 0.0;
+  const double dx = px - ax - s * ex, dy = py - ay - s * ey;
+  return dx * dx + dy * dy;
+}
+
+// Per xy-cell lists of the edges within s_max (plus a margin) of the cell's
+// rectangle (the last cell of an axis reaches the window's side).
+void build_near(const Layout &L, int64_t s_max, std::vector<uint16_t> *out) {
+  const Geom &g = L.g;
+  const int nv = (int)L.V.size();
+  const int64_t W = (int64_t)g.x1 - g.x0, H = (int64_t)g.y1 - g.y0, cs = g.cell_s;
+  out->assign((size_t)g.nx * g.ny * (kNearMax + 1), 0);
+  const double reach = (double)s_max + 2.0;
+  for (int k = 0; k < nv; ++k) {
+    const int2 a = L.V[(size_t)k], b = L.V[(size_t)((k + 1) % nv)];
+    const double lox = std::min(a.x, b.x) - reach, hix = std::max(a.x, b.x) + reach;
+    const double loy = std::min(a.y, b.y) - reach, hiy = std::max(a.y, b.y) + reach;
+    const int cx0 = (int)std::max<int64_t>(0, (int64_t)std::floor(lox / cs));
+    const int cx1 = (int)std::min<int64_t>(g.nx - 1, (int64_t)std::floor(hix / cs));
+    const int cy0 = (int)std::max<int64_t>(0, (int64_t)std::floor(loy / cs));
+    const int cy1 = (int)std::min<int64_t>(g.ny - 1, (int64_t)std::floor(hiy / cs));
+    for (int cy = cy0; cy <= cy1; ++cy)
+      for (int cx = cx0; cx <= cx1; ++cx) {
+        const double x0 = (double)cx * cs, x1 = cx == g.nx - 1 ? (double)W : (double)(cx + 1) * cs;
+        const double y0 = (double)cy * cs, y1 = cy == g.ny - 1 ? (double)H : (double)(cy + 1) * cs;
+        // distance between the segment and the cell rectangle
+        double d2;
+        const bool a_in = a.x >= x0 && a.x <= x1 && a.y >= y0 && a.y <= y1;
+        const bool b_in = b.x >= x0 && b.x <= x1 && b.y >= y0 && b.y <= y1;
+        if (a_in || b_in) {
+          d2 = 0.0;
+        } else {
+          auto pr = [&](double px, double py) {
+            const double dx = std::max({x0 - px, 0.0, px - x1}), dy = std::max({y0 - py, 0.0, py - y1});
+            return dx * dx + dy * dy;
+          };
+          d2 = std::min(pr(a.x, a.y), pr(b.x, b.y));
+          const double cxs[4] = {x0, x1, x1, x0}, cys[4] = {y0, y0, y1, y1};
+          for (int q = 0; q < 4; ++q) d2 = std::min(d2, seg_point_d2(a.x, a.y, b.x, b.y, cxs[q], cys[q]));
+          // a segment crossing the rectangle with both ends outside: it meets
+          // one of the rectangle's sides
+          const int2 r0 = make_int2((int)x0, (int)y0), r1 = make_int2((int)x1, (int)y0),
+                     r2 = make_int2((int)x1, (int)y1), r3 = make_int2((int)x0, (int)y1);
+          if (segments_meet(a, b, r0, r1) || segments_meet(a, b, r1, r2) ||
+              segments_meet(a, b, r2, r3) || segments_meet(a, b, r3, r0))
+            d2 = 0.0;
+        }
+        if (d2 > reach * reach) continue;
+        uint16_t *lst = out->data() + ((size_t)cy * g.nx + cx) * (kNearMax + 1);
+        if (lst[0] == kNearAll) continue;
+        if (lst[0] == kNearMax) {
+          lst[0] = kNearAll;
+          continue;
+        }
+        lst[1 + lst[0]] = (uint16_t)k;
+        ++lst[0];
+      }
+  }
+}
 
 }  // namespace
 
 namespace ripk {
 
-Caps caps_for(int64_t S, int64_t n_max, int64_t n_cells, int64_t n_bins) {
+Caps caps_for(int64_t S, int64_t n_max, int64_t n_cells, int64_t n_bins, int64_t V,
+              int64_t NXY) {
   Caps c;
+  c.V = V;
+  c.NXY = NXY;
   c.S = S;
   c.N = S * n_max;
   c.SNC = S * n_cells;
@@ -88,13 +218,14 @@ int64_t caps_bytes(const Caps &c) {
   bytes += 8 * 4 * c.SNB;                     // C, W, K, L
   bytes += 8 * 6 * c.NB + 8 * 2 * kMaxSteps + 32;
   bytes += 3 * 4 * c.P;                       // copy of the observed set (resampling)
+  bytes += 8 * c.V + 2 * (kNearMax + 1) * c.NXY;  // polygon and its per-cell edge lists
   return bytes;
 }
 
 bool caps_fit(const Caps &have, const Caps &need) {
   return need.S <= have.S && need.N <= have.N && need.SNC <= have.SNC &&
          need.items <= have.items && need.SNB <= have.SNB && need.NB <= have.NB &&
-         need.P <= have.P;
+         need.P <= have.P && need.V <= have.V && need.NXY <= have.NXY;
 }
 
 Caps caps_max(const Caps &a, const Caps &b) {
@@ -106,6 +237,8 @@ Caps caps_max(const Caps &a, const Caps &b) {
   c.SNB = std::max(a.SNB, b.SNB);
   c.NB = std::max(a.NB, b.NB);
   c.P = std::max(a.P, b.P);
+  c.V = std::max(a.V, b.V);
+  c.NXY = std::max(a.NXY, b.NXY);
   return c;
 }
 
@@ -132,7 +265,16 @@ ripk_status derive(const ripk_plan_desc *d, Layout *L) {
   if (d->s_max >= (1LL << 23)) return fail(RIPK_EINVAL, "s_max must be below 2^23");
   if (d->t_max >= (1LL << 30)) return fail(RIPK_EINVAL, "t_max must be below 2^30");
   if (d->edge & ~RIPK_EDGE_ISO) return fail(RIPK_EINVAL, "unknown edge-correction bits");
-  if ((d->edge & RIPK_EDGE_SPATIAL_ISO) && 2 * d->s_max > std::min(W, H))
+  if (d->reserved != 0) return fail(RIPK_EINVAL, "reserved descriptor field must be 0");
+  int64_t area2 = 0;
+  L->V.clear();
+  if (d->poly_n != 0) {
+    ripk_status ps = read_polygon(d, &L->V, &area2);
+    if (ps != RIPK_OK) return ps;
+    if (std::llabs(area2) * 512 < W * H)
+      return fail(RIPK_EINVAL, "polygon area must be at least 1/1024 of the rectangle's");
+  }
+  if ((d->edge & RIPK_EDGE_SPATIAL_ISO) && d->poly_n == 0 && 2 * d->s_max > std::min(W, H))
     return fail(RIPK_EINVAL,
                 "isotropic spatial correction needs 2*s_max <= min(width, height) "
                 "(the weight would reach 0 beyond that)");
@@ -215,8 +357,14 @@ ripk_status derive(const ripk_plan_desc *d, Layout *L) {
     g.tsh = sh;
   }
   L->clamp_e = (int32_t)d->s_max;
+  g.poly = nullptr;
+  g.near = nullptr;
+  g.poly_n = (int32_t)L->V.size();
+  g.poly_sign = area2 < 0 ? -1 : 1;
+  L->area = L->V.empty() ? (double)W * (double)H : 0.5 * (double)std::llabs(area2);
 
-  L->caps = caps_for(S, d->n_max, I.n_cells, I.n_bins);
+  L->caps = caps_for(S, d->n_max, I.n_cells, I.n_bins, (int64_t)L->V.size(),
+                     L->V.empty() ? 0 : nx * ny);
   I.device_bytes = caps_bytes(L->caps);
   return RIPK_OK;
 }
@@ -270,6 +418,9 @@ struct ripk_plan_s {
   double *env = nullptr, *Lobs = nullptr;
   uint64_t *S2 = nullptr;
   uint32_t *T = nullptr;
+  int2 *poly = nullptr;        // polygon vertices (window-relative)
+  uint16_t *near = nullptr;    // per xy-cell edge lists of the bound geometry
+  std::vector<uint16_t> nearh; // host copy of the lists (source of the upload)
   unsigned long long *scal = nullptr;  // [0] n_eval, [1] n_in, [2] err|n_items|item_ctr (u32s)
   hipEvent_t ev[6] = {};
   ripk_stats stats{};
@@ -291,7 +442,7 @@ void release(ripk_plan_s *p) {
                   p->vals[1],
                   p->sort_temp, p->cs, p->P, p->chunks, p->offs, p->set_base, p->scan_temp,
                   p->items, p->binC, p->binW, p->outC, p->outW, p->outK, p->outL, p->env,
-                  p->Lobs, p->S2, p->T, p->scal};
+                  p->Lobs, p->S2, p->T, p->poly, p->near, p->scal};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   for (auto &e : p->ev)
@@ -331,7 +482,8 @@ ripk_status enqueue_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_cent
   const bool cross = (p->desc.flags & RIPK_PLAN_CROSS) != 0;
   if (simulate) {
     if (p->desc.sim_method == RIPK_SIM_CSR)
-      HIPCHK(launch_csr(n, n_centres, S, seed, g, p->x, p->y, p->t, p->keys[0], p->vals[0], st));
+      HIPCHK(launch_csr(n, n_centres, S, seed, g, p->x, p->y, p->t, p->keys[0], p->vals[0], err,
+                        st));
     else
       HIPCHK(launch_resample(p->desc.sim_method == RIPK_SIM_PERMUTE ? 1 : 2, n, n_centres, S,
                              seed, p->ox, p->oy, p->ot, g, p->x, p->y, p->t, p->keys, p->vals,
@@ -354,7 +506,7 @@ ripk_status enqueue_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_cent
   const int wide_counts =
       ((int64_t)n >= kWideCountPoints || (p->desc.flags & RIPK_PLAN_WIDE_COUNTS)) ? 1 : 0;
   int per_cu = 0;
-  HIPCHK(pair_occupancy((int)NB, wide_counts, symmetric ? 1 : 0, g.mode, &per_cu));
+  HIPCHK(pair_occupancy((int)NB, wide_counts, symmetric ? 1 : 0, g.mode, pair_poly(g), &per_cu));
   if (per_cu < 1) return fail(RIPK_EINVAL, "pair kernel does not fit on a compute unit (n_bins=%u)", NB);
   // A launch with fewer groups than about twice the resident workgroups splits
   // every item's stencil rows into `split` parts taken by different waves.
@@ -394,8 +546,7 @@ ripk_status enqueue_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_cent
   HIPCHK(launch_pair(a, grid, st));
   if (timing) HIPCHK(hipEventRecord(p->ev[3], st));
 
-  const double AD = (double)(p->desc.x1 - p->desc.x0) * (double)(p->desc.y1 - p->desc.y0) *
-                    (double)(p->desc.t1 - p->desc.t0);
+  const double AD = p->lay.area * (double)(p->desc.t1 - p->desc.t0);
   const double Nn = cross ? (double)n_centres * (double)(n - n_centres)
                     : p->desc.norm == RIPK_NORM_N2 ? (double)n * (double)n
                                                    : (double)n * (double)(n - 1);
@@ -479,6 +630,13 @@ ripk_status collect_stats(ripk_plan_s *p, hipStream_t st, uint32_t S, uint32_t n
   return RIPK_OK;
 }
 
+// the device error word: bit 0 a point outside the study area, bit 1 a CSR
+// point that found no attempt inside the polygon
+ripk_status err_status(uint32_t err) {
+  if (err & 1u) return fail(RIPK_ERANGE, "a point lies outside the study area");
+  return fail(RIPK_EDEVICE, "rejection sampling found no point inside the polygon");
+}
+
 ripk_status sync_status(hipError_t e) {
   if (e != hipSuccess) return fail(RIPK_EDEVICE, "device synchronisation failed: %s", hipGetErrorString(e));
   return RIPK_OK;
@@ -532,6 +690,7 @@ ripk_status plan_create(int device, const Caps &c, ripk_plan_s **out) {
   ALLOC(p->outC, c.SNB); ALLOC(p->outW, c.SNB); ALLOC(p->outK, c.SNB); ALLOC(p->outL, c.SNB);
   ALLOC(p->env, 5 * c.NB); ALLOC(p->Lobs, c.NB);
   ALLOC(p->S2, kMaxSteps); ALLOC(p->T, kMaxSteps);
+  ALLOC(p->poly, c.V); ALLOC(p->near, (kNearMax + 1) * c.NXY);
   ALLOC(p->scal, 4);
 #undef ALLOC
   if (e != hipSuccess) {
@@ -611,6 +770,17 @@ ripk_status bind_geometry(ripk_plan_s *p, const ripk_plan_desc *desc, hipStream_
   for (int l = 0; l < desc->n_t; ++l) p->Th[l] = (uint32_t)L.info.T[l];
   HIPCHK(hipMemcpyAsync(p->S2, p->S2h, sizeof p->S2h, hipMemcpyHostToDevice, stream));
   HIPCHK(hipMemcpyAsync(p->T, p->Th, sizeof p->Th, hipMemcpyHostToDevice, stream));
+  if (!p->lay.V.empty()) {
+    build_near(p->lay, desc->s_max, &p->nearh);
+    HIPCHK(hipMemcpyAsync(p->poly, p->lay.V.data(), sizeof(int2) * p->lay.V.size(),
+                          hipMemcpyHostToDevice, stream));
+    HIPCHK(hipMemcpyAsync(p->near, p->nearh.data(), sizeof(uint16_t) * p->nearh.size(),
+                          hipMemcpyHostToDevice, stream));
+    // the host sources are replaced by the next bind: let the copies finish
+    HIPCHK(hipStreamSynchronize(stream));
+    p->lay.g.poly = p->poly;
+    p->lay.g.near = p->near;
+  }
   return RIPK_OK;
 }
 
@@ -644,7 +814,7 @@ ripk_status run_tuned(ripk_plan_s *p, int which, uint32_t S, uint32_t S_tune, ui
           uint32_t err = 0;
           s = collect_stats(p, st, S_tune, n, &err);
           if (s != RIPK_OK) return s;
-          if (err) return fail(RIPK_ERANGE, "a point lies outside the study window");
+          if (err) return err_status(err);
           float ms = 0;
           HIPCHK(hipEventElapsedTime(&ms, p->tev[0], p->tev[1]));
           ts.us[i] = std::min(ts.us[i], 1e3 * (double)ms);
@@ -760,7 +930,7 @@ ripk_status ripk_compute_K(ripk_plan_t p, const ripk_points *pts, void *stream, 
   uint32_t err = 0;
   s = collect_stats(p, st, 1, (uint32_t)n, &err);
   if (s != RIPK_OK) return s;
-  if (err) return fail(RIPK_ERANGE, "a point lies outside the study window");
+  if (err) return err_status(err);
   if (p->desc.sim_method != RIPK_SIM_CSR) p->obs_n = n;
   if (cross) {
     p->split_n = n;
@@ -804,6 +974,7 @@ ripk_status ripk_simulate_envelope(ripk_plan_t p, int64_t n, int32_t m, uint64_t
   uint32_t err = 0;
   s = collect_stats(p, st, (uint32_t)m, (uint32_t)n, &err);
   if (s != RIPK_OK) return s;
+  if (err) return err_status(err);
   const size_t NB = (size_t)p->lay.info.n_bins;
   if (out) {
     double *rows[5] = {out->K_lo, out->K_hi, out->L_lo, out->L_hi, L_obs ? out->dL_hi : nullptr};

@@ -5,6 +5,7 @@
 // The uniform space-time cell grid stands in for the paper's R-tree (Sec. 4.2):
 // with cells at least s_max wide in x and y and t_max long in t, every neighbour
 // of a centre within (s_max, t_max) lies in the 3x3x3 block of cells around it.
+#include "poly.h"
 #include "ripk_internal.h"
 
 namespace ripk {
@@ -39,6 +40,8 @@ __global__ void k_keys(const int32_t *__restrict__ x, const int32_t *__restrict_
   if (i >= n) return;
   bool bad;
   uint32_t c = cell_of(x[i], y[i], t[i], g, &bad);
+  // a polygon study area holds its points strictly inside
+  if (!bad && g.poly_n && !poly_inside(g.poly, g.poly_n, x[i] - g.x0, y[i] - g.y0)) bad = true;
   if (bad) atomicOr(err, 1u);
   keys[i] = ((set_base * g.n_cells + c) << 1) | (i >= n_centres ? 1u : 0u);
   vals[i] = i;
@@ -69,25 +72,40 @@ __device__ __forceinline__ U64x4 philox4x64_10(U64x4 c, uint64_t k0, uint64_t k1
 }
 
 // Simulation s, point i: counter (i, s, 0, 0), key (seed, 0).  Coordinates on
-// the half-open window by 64x64 multiply-high.  Writes the SoA points and the
-// (key, value) pairs for the sort, sets ordered simulation-major.
+// the half-open window by 64x64 multiply-high.  In a polygon, attempt a uses
+// counter (i, s, a, 0) until the point lies strictly inside (the polygon covers
+// at least 1/1024 of the window, so 2^16 attempts all failing has probability
+// below e^-64; it sets bit 1 of *err).  Writes the SoA points and the (key,
+// value) pairs for the sort, sets ordered simulation-major.
+constexpr uint32_t kMaxAttempts = 1u << 16;
+
 __global__ void k_csr(uint32_t n, uint32_t n_centres, uint32_t m, uint64_t seed, Geom g,
                       int32_t *__restrict__ x,
                       int32_t *__restrict__ y, int32_t *__restrict__ t,
-                      uint32_t *__restrict__ keys, uint32_t *__restrict__ vals) {
+                      uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
+                      uint32_t *__restrict__ err) {
   uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= (uint64_t)n * m) return;
   uint32_t s = (uint32_t)(gid / n), i = (uint32_t)(gid - (uint64_t)s * n);
-  U64x4 c;
-  c.v[0] = i;
-  c.v[1] = s;
-  c.v[2] = 0;
-  c.v[3] = 0;
-  U64x4 r = philox4x64_10(c, seed, 0);
-  uint64_t W = (uint64_t)(g.x1 - g.x0), H = (uint64_t)(g.y1 - g.y0), D = (uint64_t)(g.t1 - g.t0);
-  int32_t px = g.x0 + (int32_t)__umul64hi(r.v[0], W);
-  int32_t py = g.y0 + (int32_t)__umul64hi(r.v[1], H);
-  int32_t pt = g.t0 + (int32_t)__umul64hi(r.v[2], D);
+  const uint64_t W = (uint64_t)(g.x1 - g.x0), H = (uint64_t)(g.y1 - g.y0),
+                 D = (uint64_t)(g.t1 - g.t0);
+  int32_t px, py, pt;
+  for (uint32_t a = 0;; ++a) {
+    U64x4 c;
+    c.v[0] = i;
+    c.v[1] = s;
+    c.v[2] = a;
+    c.v[3] = 0;
+    const U64x4 r = philox4x64_10(c, seed, 0);
+    px = g.x0 + (int32_t)__umul64hi(r.v[0], W);
+    py = g.y0 + (int32_t)__umul64hi(r.v[1], H);
+    pt = g.t0 + (int32_t)__umul64hi(r.v[2], D);
+    if (!g.poly_n || poly_inside(g.poly, g.poly_n, px - g.x0, py - g.y0)) break;
+    if (a + 1 == kMaxAttempts) {
+      atomicOr(err, 2u);
+      break;
+    }
+  }
   x[gid] = px;
   y[gid] = py;
   t[gid] = pt;
@@ -357,8 +375,13 @@ __global__ void k_gather(const uint32_t *__restrict__ vals, const uint32_t *__re
   if (r >= n) return;
   uint32_t i = vals[r];
   int32_t X = x[i] - g.x0, Y = y[i] - g.y0, T = t[i] - g.t0;
-  int32_t e = min(min(X, g.x1 - g.x0 - X), min(Y, g.y1 - g.y0 - Y));
-  e = min(max(e, 0), clamp_e);
+  int32_t e;
+  if (g.poly_n) {
+    e = poly_edist(g, X, Y, clamp_e);
+  } else {
+    e = min(min(X, g.x1 - g.x0 - X), min(Y, g.y1 - g.y0 - Y));
+    e = min(max(e, 0), clamp_e);
+  }
   if (mark && !(keys[r] & 1u)) e = (int32_t)((uint32_t)e | 0x80000000u);
   P[r] = make_int4(X, Y, T, e);
 }
@@ -475,11 +498,11 @@ hipError_t launch_keys(const int32_t *x, const int32_t *y, const int32_t *t, uin
 
 hipError_t launch_csr(uint32_t n, uint32_t n_centres, uint32_t m, uint64_t seed, const Geom &g,
                       int32_t *x, int32_t *y, int32_t *t, uint32_t *keys, uint32_t *vals,
-                      hipStream_t s) {
+                      uint32_t *err, hipStream_t s) {
   uint64_t tot = (uint64_t)n * m;
   if (tot == 0) return hipSuccess;
   hipLaunchKernelGGL(k_csr, dim3(blocks_for(tot, kThreads)), dim3(kThreads), 0, s, n, n_centres,
-                     m, seed, g, x, y, t, keys, vals);
+                     m, seed, g, x, y, t, keys, vals, err);
   return hipGetLastError();
 }
 

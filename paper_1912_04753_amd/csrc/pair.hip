@@ -40,6 +40,7 @@
 //
 // Weights are FP32: w = 1/omega * 1/v lies in [1, 8], so w * 2^23 is an exact
 // integer and the fixed-point sums are exact and order independent.
+#include "poly.h"
 #include "ripk_internal.h"
 
 namespace ripk {
@@ -78,6 +79,10 @@ struct WaveLds {
 static_assert(sizeof(WaveLds) % 16 == 0, "the histogram after the wave blocks must stay 16-byte aligned");
 constexpr uint32_t kTileStride = kJT * 4;  // bytes between components of a tile entry
 constexpr uint32_t kCenStride = 64 * 4;        // bytes between components of a centre
+constexpr uint32_t kTileOff = 0;               // byte offsets of tile and cen in WaveLds
+constexpr uint32_t kCenOff = 4 * kJT * 4;
+static_assert(offsetof(WaveLds, tile) == kTileOff && offsetof(WaveLds, cen) == kCenOff,
+              "tag decoding assumes the WaveLds layout");
 
 __device__ __forceinline__ int4 load_image(const unsigned char *base, uint32_t stride) {
   return make_int4(*(const int *)base, *(const int *)(base + stride),
@@ -198,15 +203,39 @@ __device__ __forceinline__ uint32_t qweight(float om, uint32_t half) {
   return (uint32_t)(w * (float)(1u << kFracBits)) << half;
 }
 
-template <int MODE>
+// Polygon weight: 1/omega capped at 64 (omega from FP64 angles), rounded to the
+// fixed-point grid: below 2^29 per side, so two sides fit 32 bits.
+__device__ __forceinline__ uint32_t qweight_poly(double om, uint32_t half) {
+  const double w = om * 64.0 > 1.0 ? 1.0 / om : 64.0;
+  return (uint32_t)rint(w * (double)(1u << kFracBits)) << half;
+}
+
+// Polygon records (every distance mode): {bin | half_i<<12 | half_j<<13 |
+// slow_i<<14 | slow_j<<15 | d2 hi<<16, d2 lo, i, j} with i, j the sorted-record
+// indices of the two points.
+template <int MODE, bool POLY>
 __device__ __forceinline__ void drain_b(WaveLds &W, QState &q, uint32_t c, int lane,
-                                        unsigned long long *hw) {
+                                        unsigned long long *hw, const Geom &g,
+                                        const int4 *__restrict__ P) {
   wave_sync();
   const uint4 r = W.qb[(q.hb + lane) & (kQB - 1)];
   wave_sync();
   const uint32_t bin = r.x & 0xFFFu;
   uint32_t qv;
-  if (MODE == kModePacked) {
+  if (POLY) {
+    const uint64_t d2 = (uint64_t)r.y | ((uint64_t)(r.x >> 16) << 32);
+    qv = 0;
+    if ((uint32_t)lane < c) {
+      if ((r.x >> 14) & 1u) {
+        const int4 pi = P[r.z];
+        qv += qweight_poly(poly_omega(g, pi.x, pi.y, d2), (r.x >> 12) & 1u);
+      }
+      if ((r.x >> 15) & 1u) {
+        const int4 pj = P[r.w];
+        qv += qweight_poly(poly_omega(g, pj.x, pj.y, d2), (r.x >> 13) & 1u);
+      }
+    }
+  } else if (MODE == kModePacked) {
     // d2 < 2^31 and side distances < 2^15: 32-bit arithmetic throughout
     const float oi = omega_f32(r.z & 0xFFFFu, r.z >> 16, r.y);
     const float oj = omega_f32(r.w & 0xFFFFu, r.w >> 16, r.y);
@@ -254,12 +283,14 @@ __device__ __forceinline__ Side side_of(const int4 p, uint32_t d2lo, uint64_t d2
 // centre and neighbour images; the bin, the temporal weight and the interior
 // fast path of omega are evaluated without branches on per-lane data (lanes
 // past c compute on entry 0 and store nothing); boundary sides go to queue B.
-template <bool SYM, int MODE>
+// (POLY: `begin` is the first centre's record index, `tb` the tile's.)
+template <bool SYM, int MODE, bool POLY>
 __device__ __forceinline__ void drain_a(WaveLds &W, QState &q,
                                         uint32_t c, int lane, const Geom &g,
                                         unsigned long long *hist, uint32_t *histc,
                                         bool wide_counts, const uint32_t *S2lo,
-                                        const uint32_t *S2hi, const uint32_t *T) {
+                                        const uint32_t *S2hi, const uint32_t *T,
+                                        uint32_t begin, uint32_t tb, const int4 *P) {
   wave_sync();
   const uint32_t tag0 = W.qa[q.ha + (uint32_t)lane];  // q.ha + 63 < kQA: no wrap
   wave_sync();
@@ -344,7 +375,21 @@ __device__ __forceinline__ void drain_a(WaveLds &W, QState &q,
     q.ha = 0;
     q.ta = 0;
   }
-  if (MODE == kModePacked) {
+  if (POLY) {
+    // one record per pair with a boundary side, naming both points
+    const bool need = si.slow || sj.slow;
+    const unsigned long long m = mslow;
+    if (m) {
+      const uint32_t pos = lane_rank(m, q.hb + q.nb) & (kQB - 1);
+      q.nb += (uint32_t)__popcll(m);
+      if (need && v)
+        W.qb[pos] = make_uint4(bin | (hfi << 12) | (hfj << 13) | ((uint32_t)si.slow << 14) |
+                                   ((uint32_t)(SYM && sj.slow) << 15) | (d2hi << 16),
+                               d2lo, begin + (((tag & 0xFFFFu) - kCenOff) >> 2),
+                               tb + (((tag >> 16) - kTileOff) >> 2));
+      if (q.nb >= 64) drain_b<MODE, POLY>(W, q, 64, lane, hist, g, P);
+    }
+  } else if (MODE == kModePacked) {
     // one record per pair with a boundary side
     const bool need = si.slow || sj.slow;
     const unsigned long long m = mslow;
@@ -355,7 +400,7 @@ __device__ __forceinline__ void drain_a(WaveLds &W, QState &q,
         W.qb[pos] = make_uint4(bin | (hfi << 12) | (hfj << 13) | ((uint32_t)si.slow << 14) |
                                    ((uint32_t)(SYM && sj.slow) << 15),
                                d2lo, (uint32_t)pi.z, (uint32_t)pj.z);
-      if (q.nb >= 64) drain_b<MODE>(W, q, 64, lane, hist);
+      if (q.nb >= 64) drain_b<MODE, POLY>(W, q, 64, lane, hist, g, P);
     }
   } else {
     // one record per boundary side, one side per pass through a single drain site
@@ -370,7 +415,7 @@ __device__ __forceinline__ void drain_a(WaveLds &W, QState &q,
         if (need && v)
           W.qb[pos] = make_uint4(w0 | ((side ? hfj : hfi) << 12), d2lo, side ? sj.ex : si.ex,
                                  side ? sj.ey : si.ey);
-        if (q.nb >= 64) drain_b<MODE>(W, q, 64, lane, hist);
+        if (q.nb >= 64) drain_b<MODE, POLY>(W, q, 64, lane, hist, g, P);
       }
     }
   }
@@ -381,14 +426,15 @@ __device__ __forceinline__ void drain_a(WaveLds &W, QState &q,
 // that no pair takes the boundary path.  A record marked as no neighbour (bit
 // 31 of its edge distance: a type-1 point of a cross-K set) takes the padding
 // time, so it fails every time test; centres clear the mark before this.
-template <int MODE>
+// (POLY: the interior bound is the record's distance to the polygon.)
+template <int MODE, bool POLY>
 __device__ __forceinline__ int4 image(const int4 p, const Geom &g) {
   const bool iso = (g.edge & 1u) != 0;
   const int tm = p.w < 0 ? (int)kFarTime : p.z;
   if (MODE == kModePacked) {
     const uint32_t ex = min((uint32_t)min(p.x, g.x1 - g.x0 - p.x), kClampE);
     const uint32_t ey = min((uint32_t)min(p.y, g.y1 - g.y0 - p.y), kClampE);
-    const uint32_t e = min(ex, ey);
+    const uint32_t e = POLY ? (uint32_t)(p.w & 0x7FFFFFFF) : min(ex, ey);
     return make_int4((int)(((uint32_t)p.x & 0xFFFFu) | ((uint32_t)p.y << 16)), tm,
                      (int)(ex | (ey << 16)), iso ? (int)(e * e) : -1);
   }
@@ -426,7 +472,7 @@ __device__ __forceinline__ void cand(const int4 me, uint32_t tplus, int thr, con
   ct = dtp <= 2u * g.tmax;
 }
 
-template <bool SYM, int MODE>
+template <bool SYM, int MODE, bool POLY>
 struct Ctx {
   WaveLds &W;
   QState &q;
@@ -436,19 +482,22 @@ struct Ctx {
   bool wide_counts;
   const uint32_t *S2lo, *S2hi, *T;
   int lane;
+  uint32_t begin;  // record index of the item's first centre
+  uint32_t tb;     // record index of the first entry of the tile in LDS
+  const int4 *P;   // sorted records
 };
 
-template <bool SYM, int MODE>
-__device__ __forceinline__ void drain_oldest(Ctx<SYM, MODE> &x, uint32_t c) {
-  drain_a<SYM, MODE>(x.W, x.q, c, x.lane, x.g, x.hist, x.histc, x.wide_counts, x.S2lo, x.S2hi,
-                     x.T);
+template <bool SYM, int MODE, bool POLY>
+__device__ __forceinline__ void drain_oldest(Ctx<SYM, MODE, POLY> &x, uint32_t c) {
+  drain_a<SYM, MODE, POLY>(x.W, x.q, c, x.lane, x.g, x.hist, x.histc, x.wide_counts, x.S2lo,
+                           x.S2hi, x.T, x.begin, x.tb, x.P);
 }
 
 // One run of consecutive sorted points [j0, j1) against the wave's centres.
 // HOME: the run holds the centres' own cell (j > i in symmetric mode, j != i
 // otherwise).
-template <bool SYM, int MODE, bool HOME>
-__device__ __forceinline__ void scan_run(Ctx<SYM, MODE> &x, uint32_t j0, uint32_t j1,
+template <bool SYM, int MODE, bool POLY, bool HOME>
+__device__ __forceinline__ void scan_run(Ctx<SYM, MODE, POLY> &x, uint32_t j0, uint32_t j1,
                                          const int4 me, uint32_t tplus, int thr, bool lv,
                                          unsigned long long valid, uint32_t mi,
                                          const int4 *__restrict__ P) {
@@ -468,9 +517,10 @@ __device__ __forceinline__ void scan_run(Ctx<SYM, MODE> &x, uint32_t j0, uint32_
       const uint32_t na = na_of(q);
       if (na) drain_oldest(x, na);
     }
+    x.tb = tb;
     wave_sync();
     {
-      const int4 im = nxt_ok ? image<MODE>(nxt, x.g) : far_image<MODE>();
+      const int4 im = nxt_ok ? image<MODE, POLY>(nxt, x.g) : far_image<MODE>();
       W.tile[0][lane] = (uint32_t)im.x;
       W.tile[1][lane] = (uint32_t)im.y;
       W.tile[2][lane] = (uint32_t)im.z;
@@ -533,7 +583,7 @@ __device__ __forceinline__ void scan_run(Ctx<SYM, MODE> &x, uint32_t j0, uint32_
   }
 }
 
-template <bool SYM, int MODE>
+template <bool SYM, int MODE, bool POLY>
 __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const Geom &g = a.g;
@@ -615,7 +665,7 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
     const uint32_t mi = begin + (uint32_t)lane;
     int4 raw = valid ? a.P[mi] : make_int4(0, 0, 0, 0);
     raw.w &= 0x7FFFFFFF;  // a centre is always evaluated (cross K: its neighbour mark)
-    const int4 me = image<MODE>(raw, g);
+    const int4 me = image<MODE, POLY>(raw, g);
     const uint32_t tplus = (uint32_t)(MODE == kModePacked ? me.y : me.z) + g.tmax;
     const int thr = valid ? (int)g.s2max : -1;
     W.cen[0][lane] = (uint32_t)me.x;
@@ -640,7 +690,7 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
     const int ct = (int)(rest / (uint32_t)g.ny);
     const uint32_t set_off = (uint32_t)set * g.n_cells;
     QState q = {0u, 0u, 0u, 0u};
-    Ctx<SYM, MODE> x{W, q, g, hist, histc, wide, S2lo, S2hi, T, lane};
+    Ctx<SYM, MODE, POLY> x{W, q, g, hist, histc, wide, S2lo, S2hi, T, lane, begin, 0u, a.P};
     unsigned long long ev = 0;
     int ridx = 0;  // index of the stencil row in visiting order
     for (int dt = SYM ? 0 : -g.rt; dt <= g.rt; ++dt) {
@@ -665,10 +715,10 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
           } else {
             ev += (unsigned long long)cnt * (j1 - j0) - cnt;
           }
-          scan_run<SYM, MODE, true>(x, j0, j1, me, tplus, thr, valid, vmask, mi, a.P);
+          scan_run<SYM, MODE, POLY, true>(x, j0, j1, me, tplus, thr, valid, vmask, mi, a.P);
         } else {
           ev += (unsigned long long)cnt * (j1 - j0);
-          scan_run<SYM, MODE, false>(x, j0, j1, me, tplus, thr, valid, vmask, mi, a.P);
+          scan_run<SYM, MODE, POLY, false>(x, j0, j1, me, tplus, thr, valid, vmask, mi, a.P);
         }
       }
     }
@@ -676,7 +726,7 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
       const uint32_t na = na_of(q);
       if (na) drain_oldest(x, na);
     }
-    if (q.nb) drain_b<MODE>(W, q, q.nb, lane, hist);
+    if (q.nb) drain_b<MODE, POLY>(W, q, q.nb, lane, hist, g, a.P);
     if (lane == 0) atomicAdd(evals_lds, ev);
     evals_total += ev;
   }
@@ -684,31 +734,31 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
   if (lane == 0 && evals_total) atomicAdd(a.n_eval, evals_total);
 }
 
-template <bool SYM, int MODE>
+template <bool SYM, int MODE, bool POLY>
 hipError_t launch_t(const PairArgs &a, int grid, hipStream_t s) {
   const int lds = pair_lds_bytes(a.g.n_s * a.g.n_t, a.wide_counts);
-  hipLaunchKernelGGL((k_pair<SYM, MODE>), dim3(grid), dim3(kPairThreads), lds, s, a);
+  hipLaunchKernelGGL((k_pair<SYM, MODE, POLY>), dim3(grid), dim3(kPairThreads), lds, s, a);
   return hipGetLastError();
 }
 
-template <bool SYM, int MODE>
+template <bool SYM, int MODE, bool POLY>
 hipError_t occ_t(int lds, int *per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_pair<SYM, MODE>, kPairThreads,
-                                                      lds);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_pair<SYM, MODE, POLY>,
+                                                      kPairThreads, lds);
 }
 
-template <bool SYM>
+template <bool SYM, bool POLY>
 hipError_t occ_mode(int mode, int lds, int *per_cu) {
-  if (mode == kModePacked) return occ_t<SYM, kModePacked>(lds, per_cu);
-  if (mode == kModeU32) return occ_t<SYM, kModeU32>(lds, per_cu);
-  return occ_t<SYM, kModeWide>(lds, per_cu);
+  if (mode == kModePacked) return occ_t<SYM, kModePacked, POLY>(lds, per_cu);
+  if (mode == kModeU32) return occ_t<SYM, kModeU32, POLY>(lds, per_cu);
+  return occ_t<SYM, kModeWide, POLY>(lds, per_cu);
 }
 
-template <bool SYM>
+template <bool SYM, bool POLY>
 hipError_t launch_mode(const PairArgs &a, int grid, hipStream_t s) {
-  if (a.g.mode == kModePacked) return launch_t<SYM, kModePacked>(a, grid, s);
-  if (a.g.mode == kModeU32) return launch_t<SYM, kModeU32>(a, grid, s);
-  return launch_t<SYM, kModeWide>(a, grid, s);
+  if (a.g.mode == kModePacked) return launch_t<SYM, kModePacked, POLY>(a, grid, s);
+  if (a.g.mode == kModeU32) return launch_t<SYM, kModeU32, POLY>(a, grid, s);
+  return launch_t<SYM, kModeWide, POLY>(a, grid, s);
 }
 
 }  // namespace
@@ -718,13 +768,22 @@ int pair_lds_bytes(int n_bins, int wide_counts) {
   return (int)sizeof(WaveLds) * kWaves + 8 * n_bins + 4 * nc_words + 4 * 3 * kMaxSteps + 16;
 }
 
-hipError_t pair_occupancy(int n_bins, int wide_counts, int symmetric, int mode, int *per_cu) {
+bool pair_poly(const Geom &g) { return g.poly_n >= 3 && (g.edge & 1u); }
+
+hipError_t pair_occupancy(int n_bins, int wide_counts, int symmetric, int mode, bool poly,
+                          int *per_cu) {
   const int lds = pair_lds_bytes(n_bins, wide_counts);
-  return symmetric ? occ_mode<true>(mode, lds, per_cu) : occ_mode<false>(mode, lds, per_cu);
+  if (poly)
+    return symmetric ? occ_mode<true, true>(mode, lds, per_cu)
+                     : occ_mode<false, true>(mode, lds, per_cu);
+  return symmetric ? occ_mode<true, false>(mode, lds, per_cu)
+                   : occ_mode<false, false>(mode, lds, per_cu);
 }
 
 hipError_t launch_pair(const PairArgs &a, int grid, hipStream_t s) {
-  return a.symmetric ? launch_mode<true>(a, grid, s) : launch_mode<false>(a, grid, s);
+  if (pair_poly(a.g))
+    return a.symmetric ? launch_mode<true, true>(a, grid, s) : launch_mode<false, true>(a, grid, s);
+  return a.symmetric ? launch_mode<true, false>(a, grid, s) : launch_mode<false, false>(a, grid, s);
 }
 
 }  // namespace ripk

@@ -39,7 +39,16 @@ struct Geom {
   // (tsh = 0 unless n_t > t_max), so that u n_t / t_max - 1/4 < l0 <= u n_t / t_max, with
   // the second inequality strict for u > 0
   uint32_t tmul, tsh;
+  // polygon study area (poly_n = 0: the rectangle): window-relative vertices,
+  // per xy-cell lists of the edges within s_max (see poly.h), orientation sign
+  const int2 *poly;
+  const uint16_t *near;
+  int32_t poly_n;
+  int32_t poly_sign;  // +1 counter-clockwise, -1 clockwise
 };
+constexpr int kMaxPoly = 4096;       // vertices of a polygon study area
+constexpr int kNearMax = 32;         // edges listed per cell (more: every edge is scanned)
+constexpr uint16_t kNearAll = 0xFFFF;
 
 // Work item of the pair kernel: up to kChunk consecutive centres of one unit
 // of one set: a cell, or an x-row of cells (row items).
@@ -73,11 +82,13 @@ struct PairArgs {
 // ---- host runtime (api.cpp) -------------------------------------------------
 
 // Buffer capacities of a plan: S sets, N = S*n_max points, SNC = S*n_cells
-// cells, work items, SNB = S*n_bins bins, NB = n_bins, P = n_max (one set).
+// cells, work items, SNB = S*n_bins bins, NB = n_bins, P = n_max (one set),
+// V polygon vertices, NXY xy-cells with edge lists (0 without a polygon).
 struct Caps {
-  int64_t S = 0, N = 0, SNC = 0, items = 0, SNB = 0, NB = 0, P = 0;
+  int64_t S = 0, N = 0, SNC = 0, items = 0, SNB = 0, NB = 0, P = 0, V = 0, NXY = 0;
 };
-Caps caps_for(int64_t S, int64_t n_max, int64_t n_cells, int64_t n_bins);
+Caps caps_for(int64_t S, int64_t n_max, int64_t n_cells, int64_t n_bins, int64_t V = 0,
+              int64_t NXY = 0);
 int64_t caps_bytes(const Caps &c);
 bool caps_fit(const Caps &have, const Caps &need);
 Caps caps_max(const Caps &a, const Caps &b);
@@ -98,9 +109,11 @@ hipError_t launch_keys(const int32_t *x, const int32_t *y, const int32_t *t, uin
                        hipStream_t s);
 // m CSR sets of n points; points k >= n_centres of each set take the halo slot
 // of their cell (type 2 of a cross-K plan; n_centres = n otherwise)
+// (polygon: rejection sampling; a point that finds no attempt inside sets bit 1
+// of *err)
 hipError_t launch_csr(uint32_t n, uint32_t n_centres, uint32_t m, uint64_t seed, const Geom &g,
                       int32_t *x, int32_t *y, int32_t *t, uint32_t *keys, uint32_t *vals,
-                      hipStream_t s);
+                      uint32_t *err, hipStream_t s);
 // Simulated sets drawn from the observed points ox, oy, ot (n each): method 1
 // random permutation of the time labels, 2 bootstrap (each of the types
 // [0, n_centres) and [n_centres, n) from itself); writes x, y, t and the cell
@@ -132,7 +145,10 @@ hipError_t launch_fill_u64(unsigned long long *p, size_t n, unsigned long long v
                            hipStream_t s);
 hipError_t launch_pair(const PairArgs &a, int grid, hipStream_t s);
 int pair_lds_bytes(int n_bins, int wide_counts);
-hipError_t pair_occupancy(int n_bins, int wide_counts, int symmetric, int mode, int *per_cu);
+// the pair kernel takes the polygon weight path (a polygon and spatial correction)
+bool pair_poly(const Geom &g);
+hipError_t pair_occupancy(int n_bins, int wide_counts, int symmetric, int mode, bool poly,
+                          int *per_cu);
 // 64-bit LDS pair counts are needed from this many points per set on
 constexpr int64_t kWideCountPoints = 1 << 23;
 hipError_t launch_finalize(unsigned long long *binC, unsigned long long *binW,

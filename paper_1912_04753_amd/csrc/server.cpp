@@ -50,6 +50,7 @@ struct Request {
   uint32_t flags = 0;
   uint64_t seed = 0;
   std::vector<int32_t> xyt;  // x | y | t, n each
+  std::vector<int32_t> poly; // the descriptor's polygon (desc.poly points here)
   // results
   bool done = false;
   ripk_status status = RIPK_PENDING;
@@ -345,6 +346,10 @@ ripk_status ripk_submit(ripk_server_t sv, const ripk_request *req, uint64_t *tic
   r->desc.n_max = p.n;
   r->desc.m_max = req->m;
   r->desc.device = sv->desc.device;
+  if (req->plan.poly_n > 0 && req->plan.poly) {
+    r->poly.assign(req->plan.poly, req->plan.poly + 2 * (size_t)std::min(req->plan.poly_n, kMaxPoly));
+    r->desc.poly = r->poly.data();
+  }
   ripk_status st = plan_validate(&r->desc, &r->caps);
   if (st != RIPK_OK) {
     delete r;

@@ -53,7 +53,8 @@ class PlanDesc(ctypes.Structure):
                 ("t0", _i64), ("t1", _i64), ("s_max", _i64), ("t_max", _i64),
                 ("n_s", _i32), ("n_t", _i32), ("edge", _u32), ("norm", _u32),
                 ("sim_method", _u32), ("n_max", _i64), ("m_max", _i32), ("flags", _u32),
-                ("device", _i32), ("cell_div", _i32), ("tcell_div", _i32)]
+                ("device", _i32), ("cell_div", _i32), ("tcell_div", _i32),
+                ("poly", ctypes.POINTER(_i32)), ("poly_n", _i32), ("reserved", _i32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -176,12 +177,19 @@ def _check(status, where):
 
 def make_desc(window, s_max, t_max, n_s, n_t, edge=RIPK_EDGE_ISO, norm=RIPK_NORM_NN1,
               n_max=2, m_max=0, flags=0, device=0, cell_div=0, tcell_div=0,
-              sim_method=RIPK_SIM_CSR):
-    """Descriptor for a window ``(x0, y0, x1, y1, t0, t1)`` and an (s, t) grid."""
+              sim_method=RIPK_SIM_CSR, poly=None):
+    """Descriptor for a window ``(x0, y0, x1, y1, t0, t1)`` and an (s, t) grid;
+    ``poly``: optional (k, 2) integer vertices of a polygon study area."""
     x0, y0, x1, y1, t0, t1 = (int(v) for v in window)
-    return PlanDesc(x0, y0, x1, y1, t0, t1, int(s_max), int(t_max), int(n_s), int(n_t),
-                    int(edge), int(norm), int(sim_method), int(n_max), int(m_max), int(flags),
-                    int(device), int(cell_div), int(tcell_div))
+    d = PlanDesc(x0, y0, x1, y1, t0, t1, int(s_max), int(t_max), int(n_s), int(n_t),
+                 int(edge), int(norm), int(sim_method), int(n_max), int(m_max), int(flags),
+                 int(device), int(cell_div), int(tcell_div))
+    if poly is not None:
+        v = np.ascontiguousarray(np.asarray(poly, np.int32).reshape(-1, 2))
+        d.poly = v.ctypes.data_as(ctypes.POINTER(_i32))
+        d.poly_n = len(v)
+        d.keep = v  # the vertex array lives as long as the descriptor
+    return d
 
 
 def _info_dict(info, desc):

@@ -30,10 +30,35 @@ def test_binding_covers_every_declared_symbol():
     assert set(declared_functions()) <= set(ripk._SIGS) | {"ripk_plan_destroy"}
 
 
-def test_struct_sizes_match_header_layout():
-    # 8 int64 + 2 int32 + 3 uint32 + pad + int64 + int32 + uint32 + 3 int32 (+ pad)
-    assert ctypes.sizeof(ripk.PlanDesc) == 8 * 8 + 4 * 2 + 4 * 3 + 4 + 8 + 4 * 5 + 4
-    assert ctypes.sizeof(ripk.Points) == 3 * 8 + 8 + 8 + 8
+def test_struct_layouts_match_the_c_compiler(tmp_path):
+    """Every field offset and struct size of the binding equals what the C
+    compiler makes of include/ripk.h."""
+    import shutil
+    import subprocess
+    if not shutil.which("gcc"):
+        pytest.skip("no C compiler")
+    structs = {"ripk_plan_desc": ripk.PlanDesc, "ripk_points": ripk.Points,
+               "ripk_plan_info": ripk.PlanInfo, "ripk_stats": ripk.Stats,
+               "ripk_server_desc": ripk.ServerDesc, "ripk_request": ripk.Request,
+               "ripk_result": ripk.Result, "ripk_server_state": ripk.ServerState,
+               "ripk_K_out": ripk.KOut, "ripk_env_out": ripk.EnvOut}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ripk.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f in py._fields_:
+            lines.append(f'printf("{cname} {f[0]} %zu\\n", offsetof({cname}, {f[0]}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run(["gcc", "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    for line in out.splitlines():
+        cname, field, val = line.split()
+        py = structs[cname]
+        want = ctypes.sizeof(py) if field == "size" else getattr(py, field).offset
+        assert int(val) == want, (cname, field, int(val), want)
 
 
 def desc(**kw):

@@ -1,0 +1,192 @@
+"""GPU parity for polygon study areas against the FP64 oracle.
+
+The oracle sorts every crossing of the circle with the boundary and classifies
+arcs by their midpoints; the library sums signed crossing angles over the edges
+near the centre's cell.  Counts bit for bit, W, K and L within the tolerances of
+``tests/parity.py``.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1912_04753_amd import ripk, workloads
+from parity import compare
+
+pytestmark = pytest.mark.gpu
+DAY = workloads.DAY
+L_SHAPE = [(0, 0), (2000, 0), (2000, 1000), (1000, 1000), (1000, 2000), (0, 2000)]
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+def _star():
+    c = workloads.workload("polygon-100k-99csr")
+    return c, workloads.polygon_of(c)
+
+
+def _lattice_L(n, seed):
+    """Points on a 50 m lattice inside the L-shape: many pair distances equal
+    centre-vertex distances, so circles pass exactly through vertices."""
+    rng = np.random.default_rng(seed)
+    cand = [(x, y) for x in range(50, 2000, 50) for y in range(50, 2000, 50)
+            if not (x >= 1000 and y >= 1000)]
+    pick = rng.choice(len(cand), n, replace=True)
+    x = np.array([cand[i][0] for i in pick], np.int32)
+    y = np.array([cand[i][1] for i in pick], np.int32)
+    t = rng.integers(0, 100 * DAY, n).astype(np.int32)
+    return x, y, t
+
+
+def _clustered_in(poly, win, n, seed):
+    """Clusters centred on boundary vertices, kept strictly inside."""
+    rng = np.random.default_rng(seed)
+    P = np.asarray(poly)
+    xs, ys = [], []
+    while sum(len(a) for a in xs) < n:
+        v = P[rng.integers(0, len(P), 4096)]
+        x = np.rint(v[:, 0] + rng.normal(0, 300, len(v))).astype(np.int64)
+        y = np.rint(v[:, 1] + rng.normal(0, 300, len(v))).astype(np.int64)
+        ok = (x >= win[0]) & (x <= win[2]) & (y >= win[1]) & (y <= win[3])
+        x, y = x[ok], y[ok]
+        ok = workloads._strictly_inside(P, x, y)
+        xs.append(x[ok]); ys.append(y[ok])
+    x = np.concatenate(xs)[:n].astype(np.int32)
+    y = np.concatenate(ys)[:n].astype(np.int32)
+    t = rng.integers(win[4], win[5], n).astype(np.int32)
+    return x, y, t
+
+
+def _gpu(args, poly, x, y, t, n_centres=0, **kw):
+    plan = ripk.ripk_plan(ripk.make_desc(*args, n_max=len(x), poly=poly, **kw))
+    try:
+        r = ripk.ripk_compute_K(plan, x, y, t, n_centres=n_centres)
+        r["stats"] = ripk.ripk_plan_stats(plan)
+        r["info"] = ripk.ripk_plan_get_info(plan)
+        return r
+    finally:
+        plan.destroy()
+
+
+def _case(name):
+    c, star = _star()
+    win = c["window"]
+    if name in ("star85", "star85_cw", "ordered", "autotune", "temporal_only", "no_correction"):
+        poly = star if name != "star85_cw" else star[::-1]
+        x, y, t = workloads.polygon_points(np.random.default_rng(61), 3000, win, star)
+        args = (win, 2000, 30 * DAY, 25, 15)
+    elif name == "clustered_boundary":
+        poly = star
+        x, y, t = _clustered_in(star, win, 4000, 62)
+        args = (win, 1500, 20 * DAY, 12, 10)
+    elif name == "lattice_L":
+        poly = L_SHAPE
+        win = (0, 0, 2000, 2000, 0, 100 * DAY)
+        x, y, t = _lattice_L(2500, 63)
+        args = (win, 700, 30 * DAY, 14, 6)
+    elif name == "u32":
+        win = (0, 0, 100_000, 80_000, 0, 400 * DAY)
+        poly = workloads.star_polygon(np.random.default_rng(64), win, 40)
+        x, y, t = workloads.polygon_points(np.random.default_rng(65), 3000, win, poly)
+        args = (win, 10_000, 40 * DAY, 10, 8)
+    else:
+        raise KeyError(name)
+    edge = {"temporal_only": 2, "no_correction": 0}.get(name, 3)
+    flags = {"ordered": ripk.RIPK_PLAN_ORDERED, "autotune": ripk.RIPK_PLAN_AUTOTUNE}.get(name, 0)
+    return args, poly, x, y, t, edge, flags
+
+
+CASES = ["star85", "star85_cw", "clustered_boundary", "lattice_L", "u32", "temporal_only",
+         "no_correction", "ordered", "autotune"]
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_polygon_k_matches_oracle(name):
+    args, poly, x, y, t, edge, flags = _case(name)
+    say("polygon", name, "n=%d v=%d" % (len(x), len(poly)))
+    g = _gpu(args, poly, x, y, t, edge=edge, flags=flags)
+    r = oracle.estimate(oracle.desc(*args, edge=edge, poly=poly), x, y, t)
+    compare(g, r, args[1], args[2], args[3], args[4], where="polygon " + name)
+    assert g["stats"]["n_in"] == int(r["C"][-1, -1])
+    if name == "u32":
+        assert g["info"]["dist_mode"] == 1
+
+
+def test_polygon_simulations_match_oracle():
+    """CSR simulations inside the polygon: counter-based rejection, each set
+    against the oracle's own draw."""
+    c, star = _star()
+    args = (c["window"], 2000, 30 * DAY, 10, 6)
+    n, m, seed = 1500, 3, 99
+    x, y, t = workloads.polygon_points(np.random.default_rng(66), n, c["window"], star)
+    ref = oracle.envelope(oracle.desc(*args, poly=star), n, m, seed)
+    plan = ripk.ripk_plan(ripk.make_desc(*args, n_max=n, m_max=m, poly=star))
+    try:
+        obs = ripk.ripk_compute_K(plan, x, y, t)
+        g = ripk.ripk_simulate_envelope(plan, n, m, seed, L_obs=obs["L"], per_sim=True)
+    finally:
+        plan.destroy()
+    say("polygon sims")
+    assert np.array_equal(g["C_sims"], ref["C_sims"].astype(np.uint64))
+    np.testing.assert_allclose(g["K_sims"], ref["K_sims"], rtol=1e-6, atol=0)
+    np.testing.assert_allclose(g["L_lo"], ref["L_lo"], rtol=0, atol=1e-6 * np.abs(ref["L_lo"]).max())
+
+
+def test_polygon_points_outside_are_rejected():
+    """Points outside the polygon, or on its boundary, are RIPK_ERANGE."""
+    win = (0, 0, 2000, 2000, 0, 1000)
+    args = (win, 600, 100, 3, 2)
+    good = (np.array([500, 600], np.int32), np.array([500, 700], np.int32), np.array([1, 2], np.int32))
+    assert _gpu(args, L_SHAPE, *good)["C"][-1, -1] == 2
+    for px, py in ((1500, 1500), (1000, 1500), (0, 500), (2000, 1000)):
+        with pytest.raises(ripk.RipkError) as e:
+            _gpu(args, L_SHAPE, np.array([500, px], np.int32), np.array([500, py], np.int32),
+                 np.array([1, 2], np.int32))
+        assert e.value.status == ripk.RIPK_ERANGE, (px, py)
+
+
+def test_polygon_full_size_sampled_and_symmetric():
+    """The 100k workload in its 85-vertex boundary: 600 sampled centres (all
+    points as neighbours) against the oracle; the symmetric and ordered plans
+    agree on the whole set bit for bit."""
+    c, star = _star()
+    x, y, t = workloads.make_points(c)
+    n = len(x)
+    args = (c["window"], c["s_max"], c["t_max"], c["n_s"], c["n_t"])
+    rng = np.random.default_rng(67)
+    pick = rng.choice(n, 600, replace=False)
+    order = np.concatenate([pick, np.setdiff1d(np.arange(n), pick)])
+    xs, ys, ts = x[order], y[order], t[order]
+    say("polygon sampled 100k")
+    g = _gpu(args, star, xs, ys, ts, n_centres=600)
+    r = oracle.estimate(oracle.desc(*args, poly=star), xs, ys, ts, n_centres=600)
+    compare(g, r, c["s_max"], c["t_max"], c["n_s"], c["n_t"], where="polygon sampled")
+    say("polygon 100k symmetric vs ordered")
+    a = _gpu(args, star, x, y, t)
+    b = _gpu(args, star, x, y, t, flags=ripk.RIPK_PLAN_ORDERED)
+    assert np.array_equal(a["C"], b["C"]) and np.array_equal(a["W"], b["W"])
+    assert a["stats"]["symmetric"] == 1 and b["stats"]["symmetric"] == 0
+
+
+def test_polygon_request_through_server():
+    c, star = _star()
+    args = (c["window"], 2000, 30 * DAY, 10, 6)
+    n, m, seed = 2000, 2, 7
+    x, y, t = workloads.polygon_points(np.random.default_rng(68), n, c["window"], star)
+    desc = ripk.make_desc(*args, n_max=n, m_max=m, poly=star)
+    plan = ripk.ripk_plan(desc)
+    try:
+        obs = ripk.ripk_compute_K(plan, x, y, t)
+        env = ripk.ripk_simulate_envelope(plan, n, m, seed)
+    finally:
+        plan.destroy()
+    srv = ripk.ripk_server_create(slots=2)
+    try:
+        tk = ripk.ripk_submit(srv, desc, x, y, t, m=m, seed=seed)
+        res = ripk.ripk_poll(srv, tk, timeout_ms=-1)
+    finally:
+        ripk.ripk_server_destroy(srv)
+    say("polygon server")
+    assert np.array_equal(res["C"], obs["C"]) and np.array_equal(res["W"], obs["W"])
+    assert np.array_equal(res["L_hi"], env["L_hi"])
