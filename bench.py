@@ -328,6 +328,42 @@ def main():
              "cells_m_s": [xi["cell_s"], xi["cell_t"]],
              "note": "types = first and second half of the set; ordered cross pairs"}
     xplan.destroy()
+    # polygon study area: 100k points uniform inside an 85-vertex boundary of the
+    # same window, observed K + m CSR simulations (rejection inside the polygon)
+    pc = workloads.workload("polygon-100k-99csr")
+    poly = workloads.polygon_of(pc)
+    px, py, pt = (torch.from_numpy(a).cuda() for a in workloads.make_points(pc))
+    pn, pm = len(px), pc["sims"]
+    pplan = ripk.ripk_plan(ripk.make_desc(pc["window"], pc["s_max"], pc["t_max"], pc["n_s"],
+                                          pc["n_t"], n_max=pn, m_max=pm, poly=poly,
+                                          flags=ripk.RIPK_PLAN_AUTOTUNE | ripk.RIPK_PLAN_TIMING))
+
+    def pstep():
+        r = ripk.ripk_compute_K(pplan, px, py, pt, stream=stream)
+        a = ripk.ripk_plan_stats(pplan)
+        t1 = time.perf_counter()
+        ripk.ripk_simulate_envelope(pplan, pn, pm, pc["seed"], L_obs=r["L"], stream=stream)
+        b = ripk.ripk_plan_stats(pplan)
+        return a["n_in"] + b["n_in"], time.perf_counter() - t1, a["us_pair"], b["us_pair"]
+
+    pstep()  # tuning
+    pstep()
+    torch.cuda.synchronize()
+    t_p = time.perf_counter()
+    ps = [pstep() for _ in range(3)]
+    torch.cuda.synchronize()
+    p_ms = 1e3 * (time.perf_counter() - t_p) / 3
+    pi_ = ripk.ripk_plan_get_info(pplan)
+    polygon = {"ms_per_step": round(p_ms, 3),
+               "pair_tests_per_s_G": round(ps[0][0] / (p_ms * 1e-3) / 1e9, 3),
+               "sims_per_s": round(pm / (sum(v[1] for v in ps) / 3), 3),
+               "pair_kernel_us": {"observed": round(sum(v[2] for v in ps) / 3, 2),
+                                  "simulations": round(sum(v[3] for v in ps) / 3, 2)},
+               "cells_m_s": [pi_["cell_s"], pi_["cell_t"]],
+               "note": "100k uniform points inside an 85-vertex star-shaped boundary "
+                       "(46% of the 20 km x 20 km window), 180 d, 25x15 grid to 2 km/30 d, "
+                       "observed K + 99 CSR simulations"}
+    pplan.destroy()
     plan.destroy()
 
     ms = 1e3 * t_total / args.steps
@@ -363,6 +399,7 @@ def main():
         "graph_ms_per_step": round(graph_ms, 4),
         "resampled_simulations": resampled,
         "cross_k": cross,
+        "polygon": polygon,
         "cold_ms": {"plan": round(plan_ms, 2),
                     "first_step_with_tuning": round(first_step_ms, 2) if not args.no_autotune else None},
         "observed_host_input": {"ms": round(host_obs_ms, 3),

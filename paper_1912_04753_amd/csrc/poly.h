@@ -4,7 +4,8 @@
 // isotropic weight of Sec. 3 for a general study area).
 //
 // Vertices are window-relative int32 (coordinates below 2^24), so every vector
-// product below is exact in 64 bits and the circle-edge discriminant in 128.
+// product below is an integer below 2^52, exact in FP64, and the circle-edge
+// discriminant is exact in 128-bit integers where its sign is in doubt.
 // Edges are (V[k], V[k+1 mod n]).  Each xy-cell of the grid lists the edges
 // within s_max of the cell ({count, index...}, kNearMax + 1 u16 words; count
 // kNearAll = every edge): a circle of radius <= s_max centred in the cell meets
@@ -75,9 +76,39 @@ __device__ __forceinline__ int32_t poly_edist(const Geom &g, int px, int py, int
   return (int32_t)fmax(floor(sqrt(best * (1.0 - 1e-12))) - 1.0, 0.0);
 }
 
+// Angle of (x, y) in [0, 2 pi), FP64, within a few ulp: octant reduction to
+// z = min/max in [0, 1], then atan z = pi/6 + atan((sqrt(3) z - 1)/(z + sqrt(3)))
+// for z > tan(pi/12), and the Taylor series of atan to z^25 on
+// [0, tan(pi/12)] (remainder below 2e-16 there).  Light on registers, unlike a
+// general-purpose atan2.
 __device__ __forceinline__ double poly_angle(double x, double y) {
-  const double a = atan2(y, x);
-  return a < 0.0 ? a + 6.283185307179586476925 : a;
+  const double ax = fabs(x), ay = fabs(y);
+  const double lo = fmin(ax, ay), hi = fmax(ax, ay);
+  if (hi == 0.0) return 0.0;
+  double z = lo / hi, base = 0.0;
+  if (z > 0.26794919243112270) {  // tan(pi/12)
+    z = (z * 1.7320508075688772 - 1.0) / (z + 1.7320508075688772);
+    base = 0.52359877559829887;  // pi/6
+  }
+  const double w = z * z;
+  double p = 1.0 / 25.0;
+  p = fma(p, w, -1.0 / 23.0);
+  p = fma(p, w, 1.0 / 21.0);
+  p = fma(p, w, -1.0 / 19.0);
+  p = fma(p, w, 1.0 / 17.0);
+  p = fma(p, w, -1.0 / 15.0);
+  p = fma(p, w, 1.0 / 13.0);
+  p = fma(p, w, -1.0 / 11.0);
+  p = fma(p, w, 1.0 / 9.0);
+  p = fma(p, w, -1.0 / 7.0);
+  p = fma(p, w, 1.0 / 5.0);
+  p = fma(p, w, -1.0 / 3.0);
+  p = fma(p, w, 1.0);
+  double a = fma(z, p, base);
+  if (ay > ax) a = 1.5707963267948966 - a;
+  if (x < 0.0) a = 3.1415926535897932 - a;
+  if (y < 0.0) a = 6.2831853071795865 - a;
+  return a;
 }
 
 // Share of the circle centred on the window-relative point (px, py), strictly
@@ -98,43 +129,54 @@ __device__ __forceinline__ double poly_angle(double x, double y) {
 // disk); an edge tangent inside its span (zero discriminant) counts nothing.
 // With no net crossing the circle is wholly inside unless the polygon lies
 // within it (some vertex strictly inside the disk).  Only the angles are
-// floating point (FP64).
+// floating point (FP64); the integer quantities are carried in FP64 registers,
+// where they are exact.
 __device__ __forceinline__ double poly_omega(const Geom &g, int px, int py, uint64_t d2u) {
   if (d2u == 0) return 1.0;
   const int2 *__restrict__ V = g.poly;
   const int nv = g.poly_n;
-  const long long d2 = (long long)d2u;
+  // every quantity below is an integer of at most 52 bits, exact in FP64
+  const double d2 = (double)d2u;
+  const int R = (int)sqrt(d2) + 1;  // R^2 > d2: edges whose box misses [-R, R]^2 miss the circle
   const double sg = (double)g.poly_sign;
   double S = 0.0;
   bool vin = false;
   poly_for_near(g, px, py, [&](int k) {
     const int2 a = V[k], b = V[k + 1 == nv ? 0 : k + 1];
-    const long long Ax = (long long)a.x - px, Ay = (long long)a.y - py;
-    const long long Bx = (long long)b.x - px, By = (long long)b.y - py;
-    const long long Ex = Bx - Ax, Ey = By - Ay;
-    const long long ee = Ex * Ex + Ey * Ey, ae = Ax * Ex + Ay * Ey;
-    const long long aa = Ax * Ax + Ay * Ay, bb = Bx * Bx + By * By;
+    const int Ax = a.x - px, Ay = a.y - py, Bx = b.x - px, By = b.y - py;
+    if (min(Ax, Bx) > R || max(Ax, Bx) < -R || min(Ay, By) > R || max(Ay, By) < -R) return;
+    const double ax = (double)Ax, ay = (double)Ay, bx = (double)Bx, by = (double)By;
+    const double ex = bx - ax, ey = by - ay;
+    const double ee = fma(ex, ex, ey * ey), ae = fma(ax, ex, ay * ey);
+    const double aa = fma(ax, ax, ay * ay), bb = fma(bx, bx, by * by);
     vin = vin || aa < d2 || bb < d2;
-    if (ee == 0) return;
+    if (ee == 0.0) return;
     // a vertex on the circle: half a crossing, signed by the side of the
     // circle the edge lies on next to the vertex (E.(vertex - c) > 0: outside
     // beyond a, inside before b); an edge tangent there (zero product) lies
     // outside the disk
-    if (aa == d2) S += (ae >= 0 ? -0.5 : 0.5) * sg * poly_angle((double)Ax, (double)Ay);
-    if (bb == d2) S += (ae + ee > 0 ? -0.5 : 0.5) * sg * poly_angle((double)Bx, (double)By);
-    const __int128 disc = (__int128)ae * ae - (__int128)ee * (aa - d2);
-    if (disc > 0) {
-      const double sq = sqrt((double)disc);
-      const double dae = (double)ae, dee = (double)ee;
+    if (aa == d2) S += (ae >= 0.0 ? -0.5 : 0.5) * sg * poly_angle(ax, ay);
+    if (bb == d2) S += (ae + ee > 0.0 ? -0.5 : 0.5) * sg * poly_angle(bx, by);
+    // discriminant ae^2 - ee (aa - d2): its sign from FP64 when clear of the
+    // rounding bound, else from exact 128-bit integers
+    const double t1 = ae * ae, t2 = ee * (aa - d2);
+    double disc = t1 - t2;
+    if (fabs(disc) <= 0x1p-50 * (fabs(t1) + fabs(t2))) {
+      const long long iae = (long long)ae, iee = (long long)ee, iad = (long long)(aa - d2);
+      const __int128 e = (__int128)iae * iae - (__int128)iee * iad;
+      disc = e > 0 ? (double)e : 0.0;
+    }
+    if (disc > 0.0) {
+      const double sq = sqrt(disc);
       // smaller root strictly inside the edge: an exit (counter-clockwise)
-      if (ae < 0 && aa > d2 && (ae + ee > 0 || bb < d2)) {
-        const double s = (-dae - sq) / dee;
-        S += sg * poly_angle((double)Ax + s * (double)Ex, (double)Ay + s * (double)Ey);
+      if (ae < 0.0 && aa > d2 && (ae + ee > 0.0 || bb < d2)) {
+        const double sm = (-ae - sq) / ee;
+        S += sg * poly_angle(fma(sm, ex, ax), fma(sm, ey, ay));
       }
       // larger root strictly inside the edge: an entry
-      if ((ae < 0 || aa < d2) && ae + ee > 0 && bb > d2) {
-        const double s = (-dae + sq) / dee;
-        S -= sg * poly_angle((double)Ax + s * (double)Ex, (double)Ay + s * (double)Ey);
+      if ((ae < 0.0 || aa < d2) && ae + ee > 0.0 && bb > d2) {
+        const double sp = (-ae + sq) / ee;
+        S -= sg * poly_angle(fma(sp, ex, ax), fma(sp, ey, ay));
       }
     }
   });
