@@ -482,15 +482,15 @@ ripk_status enqueue_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_cent
   const bool cross = (p->desc.flags & RIPK_PLAN_CROSS) != 0;
   if (simulate) {
     if (p->desc.sim_method == RIPK_SIM_CSR)
-      HIPCHK(launch_csr(n, n_centres, S, seed, g, p->x, p->y, p->t, p->keys[0], p->vals[0], err,
+      HIPCHK(launch_csr(n, n_centres, S, seed, g, cross, p->x, p->y, p->t, p->keys[0], p->vals[0], err,
                         st));
     else
       HIPCHK(launch_resample(p->desc.sim_method == RIPK_SIM_PERMUTE ? 1 : 2, n, n_centres, S,
-                             seed, p->ox, p->oy, p->ot, g, p->x, p->y, p->t, p->keys, p->vals,
+                             seed, cross, p->ox, p->oy, p->ot, g, p->x, p->y, p->t, p->keys, p->vals,
                              p->sort_temp, st));
     x = p->x; y = p->y; t = p->t;
   } else {
-    HIPCHK(launch_keys(x, y, t, n, n_centres, 0, 1, g, p->keys[0], p->vals[0], err, st));
+    HIPCHK(launch_keys(x, y, t, n, n_centres, 0, 1, g, cross, p->keys[0], p->vals[0], err, st));
   }
   if (timing) HIPCHK(hipEventRecord(p->ev[1], st));
   const uint64_t n_keys = (uint64_t)S * g.n_cells * 2;
@@ -498,11 +498,14 @@ ripk_status enqueue_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_cent
   HIPCHK(radix_sort(p->keys[0], p->vals[0], p->keys[1], p->vals[1], N, ceil_log2(n_keys),
                     p->sort_temp, st, &alt));
   HIPCHK(launch_cell_bounds(p->keys[alt], N, (uint32_t)n_keys, p->cs, st));
-  // cross K: type-1 records (the centres) are marked as no neighbour
-  HIPCHK(launch_gather(p->vals[alt], p->keys[alt], cross ? 1 : 0, N, x, y, t, g, p->lay.clamp_e,
+  // cross K sets are sorted in blocked order (each type one cell-sorted block):
+  // centres come from the type-1 block and neighbour runs from the type-2
+  // block, so no record needs the no-neighbour mark
+  HIPCHK(launch_gather(p->vals[alt], p->keys[alt], 0, N, x, y, t, g, p->lay.clamp_e,
                        p->P, st));
-  // row items need every point to be a centre (no halo entries inside a row)
-  const bool row_items = n_centres == n;
+  // row items need rows without halo entries: every point a centre, or the
+  // type-1 block of a cross-K set
+  const bool row_items = n_centres == n || cross;
   const int wide_counts =
       ((int64_t)n >= kWideCountPoints || (p->desc.flags & RIPK_PLAN_WIDE_COUNTS)) ? 1 : 0;
   int per_cu = 0;
@@ -520,7 +523,7 @@ ripk_status enqueue_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_cent
   split = std::min<int64_t>({split, (int64_t)kSplitMax, (int64_t)n_rows,
                              p->caps.items / std::max<int64_t>(items_bound, 1)});
   split = std::max<int64_t>(split, 1);
-  HIPCHK(launch_items(p->cs, S, g, row_items, (uint32_t)split, n_rows, p->chunks, p->offs,
+  HIPCHK(launch_items(p->cs, S, g, row_items, cross, (uint32_t)split, n_rows, p->chunks, p->offs,
                       p->set_base, p->items, n_items, p->scan_temp, st));
   HIPCHK(launch_fill_u64(p->binC, (size_t)S * NB, 0ull, st));
   HIPCHK(launch_fill_u64(p->binW, (size_t)S * NB * 2, 0ull, st));
@@ -540,6 +543,7 @@ ripk_status enqueue_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_cent
   a.n_eval = p->scal;
   a.symmetric = symmetric ? 1 : 0;
   a.row_items = row_items ? 1 : 0;
+  a.blocked = cross ? 1 : 0;
   a.wide_counts = wide_counts;
   const int64_t groups_cap = items_bound * split / kItemsPerGroup + 1;
   const int grid = (int)std::min<int64_t>(slots, groups_cap);

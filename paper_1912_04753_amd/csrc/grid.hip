@@ -31,10 +31,19 @@ __device__ __forceinline__ uint32_t cell_of(int32_t x, int32_t y, int32_t t, con
   return (ct * (uint32_t)g.ny + cy) * (uint32_t)g.nx + cx;
 }
 
-// key = ((set * n_cells + cell) << 1) | halo ; val = global point index
+// Sort key of a point: interleaved ((set * n_cells + cell) << 1) | halo, so
+// that a cell's centres precede its halo points; blocked (two-type sets)
+// (2 * set + type) * n_cells + cell, so that each type of a set is one
+// cell-sorted block.
+__device__ __forceinline__ uint32_t sort_key(uint32_t set, uint32_t cell, uint32_t halo,
+                                             const Geom &g, bool blocked) {
+  return blocked ? (2u * set + halo) * g.n_cells + cell : ((set * g.n_cells + cell) << 1) | halo;
+}
+
+// val = global point index
 __global__ void k_keys(const int32_t *__restrict__ x, const int32_t *__restrict__ y,
                        const int32_t *__restrict__ t, uint32_t n, uint32_t n_centres,
-                       uint32_t set_base, Geom g, uint32_t *__restrict__ keys,
+                       uint32_t set_base, Geom g, int blocked, uint32_t *__restrict__ keys,
                        uint32_t *__restrict__ vals, uint32_t *__restrict__ err) {
   uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -43,7 +52,7 @@ __global__ void k_keys(const int32_t *__restrict__ x, const int32_t *__restrict_
   // a polygon study area holds its points strictly inside
   if (!bad && g.poly_n && !poly_inside(g.poly, g.poly_n, x[i] - g.x0, y[i] - g.y0)) bad = true;
   if (bad) atomicOr(err, 1u);
-  keys[i] = ((set_base * g.n_cells + c) << 1) | (i >= n_centres ? 1u : 0u);
+  keys[i] = sort_key(set_base, c, i >= n_centres ? 1u : 0u, g, blocked != 0);
   vals[i] = i;
 }
 
@@ -80,7 +89,7 @@ __device__ __forceinline__ U64x4 philox4x64_10(U64x4 c, uint64_t k0, uint64_t k1
 constexpr uint32_t kMaxAttempts = 1u << 16;
 
 __global__ void k_csr(uint32_t n, uint32_t n_centres, uint32_t m, uint64_t seed, Geom g,
-                      int32_t *__restrict__ x,
+                      int blocked, int32_t *__restrict__ x,
                       int32_t *__restrict__ y, int32_t *__restrict__ t,
                       uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
                       uint32_t *__restrict__ err) {
@@ -111,7 +120,7 @@ __global__ void k_csr(uint32_t n, uint32_t n_centres, uint32_t m, uint64_t seed,
   t[gid] = pt;
   bool bad;
   uint32_t cell = cell_of(px, py, pt, g, &bad);
-  keys[gid] = ((s * g.n_cells + cell) << 1) | (i >= n_centres ? 1u : 0u);
+  keys[gid] = sort_key(s, cell, i >= n_centres ? 1u : 0u, g, blocked != 0);
   vals[gid] = (uint32_t)gid;
 }
 
@@ -156,7 +165,7 @@ __global__ void k_set_of(const uint32_t *__restrict__ vals, uint64_t total, uint
 __global__ void k_resample(uint32_t n, uint32_t n_centres, uint32_t m, uint64_t seed, int method,
                            const uint32_t *order, const int32_t *__restrict__ ox,
                            const int32_t *__restrict__ oy, const int32_t *__restrict__ ot, Geom g,
-                           int32_t *__restrict__ x, int32_t *__restrict__ y,
+                           int blocked, int32_t *__restrict__ x, int32_t *__restrict__ y,
                            int32_t *__restrict__ t, uint32_t *__restrict__ keys, uint32_t *vals) {
   uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= (uint64_t)n * m) return;
@@ -186,7 +195,7 @@ __global__ void k_resample(uint32_t n, uint32_t n_centres, uint32_t m, uint64_t 
   t[gid] = pt;
   bool bad;
   uint32_t cell = cell_of(px, py, pt, g, &bad);
-  keys[gid] = ((s * g.n_cells + cell) << 1) | (k >= n_centres ? 1u : 0u);
+  keys[gid] = sort_key(s, cell, k >= n_centres ? 1u : 0u, g, blocked != 0);
   vals[gid] = (uint32_t)gid;
 }
 
@@ -393,17 +402,28 @@ __global__ void k_gather(const uint32_t *__restrict__ vals, const uint32_t *__re
 // centres, all within 1 + kItemExtent consecutive cells of the unit (the
 // candidate distance bound of the plan relies on it).  chunk_walk visits the
 // items of unit g in order; emit(begin, count) is called for each.
+// Centre entries of cell X (set-major index set * n_cells + cell) span
+// [cs[k(X) * st], cs[k(X) * st + 1]): interleaved keys k(X) = X, st = 2;
+// blocked keys k(X) = X + set * n_cells (the set's type-1 block), st = 1.
+struct CentreIdx {
+  uint32_t nc;
+  bool blocked;
+  __device__ __forceinline__ uint32_t at(uint32_t X) const {
+    return blocked ? X + (X / nc) * nc : 2u * X;
+  }
+};
+
 template <typename F>
 __device__ __forceinline__ uint32_t chunk_walk(const uint32_t *__restrict__ cs, uint32_t g,
-                                               uint32_t unit, F emit) {
+                                               uint32_t unit, CentreIdx ci, F emit) {
   const uint32_t c0 = g * unit;
-  uint32_t pos = cs[2 * c0];
-  const uint32_t end = cs[2 * (c0 + unit - 1) + 1];
+  uint32_t pos = cs[ci.at(c0)];
+  const uint32_t end = cs[ci.at(c0 + unit - 1) + 1];
   uint32_t c = 0, items = 0;
   while (pos < end) {
-    while (cs[2 * (c0 + c) + 2] <= pos) ++c;  // cell holding pos (cells end at the next start)
+    while (cs[ci.at(c0 + c) + 1] <= pos) ++c;  // cell holding pos (row units: no halo entries)
     const uint32_t last = min(c + (uint32_t)kItemExtent, unit - 1);
-    const uint32_t lim = min(min(pos + (uint32_t)kChunk, end), cs[2 * (c0 + last) + 1]);
+    const uint32_t lim = min(min(pos + (uint32_t)kChunk, end), cs[ci.at(c0 + last) + 1]);
     emit(pos, lim - pos);
     ++items;
     pos = lim;
@@ -412,10 +432,10 @@ __device__ __forceinline__ uint32_t chunk_walk(const uint32_t *__restrict__ cs, 
 }
 
 __global__ void k_chunks(const uint32_t *__restrict__ cs, uint32_t nunit_total, uint32_t unit,
-                         uint32_t *__restrict__ chunks) {
+                         CentreIdx ci, uint32_t *__restrict__ chunks) {
   uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= nunit_total) return;
-  chunks[g] = chunk_walk(cs, g, unit, [](uint32_t, uint32_t) {});
+  chunks[g] = chunk_walk(cs, g, unit, ci, [](uint32_t, uint32_t) {});
 }
 
 // per set: padded item base so that every group of kItemsPerGroup items lies in one set
@@ -446,13 +466,13 @@ __device__ __forceinline__ uint32_t item_count(uint32_t cnt, uint32_t p, uint32_
 
 __global__ void k_emit(const uint32_t *__restrict__ cs, const uint32_t *__restrict__ offs,
                        const uint32_t *__restrict__ set_base, uint32_t n_sets, uint32_t n_units,
-                       uint32_t unit, uint32_t split, uint32_t n_rows,
+                       uint32_t unit, uint32_t split, uint32_t n_rows, CentreIdx ci,
                        Item *__restrict__ items) {
   uint32_t gidx = blockIdx.x * blockDim.x + threadIdx.x;
   if (gidx >= n_sets * n_units) return;
   uint32_t s = gidx / n_units, c = gidx - s * n_units;
   uint32_t o = set_base[s] + offs[gidx] - offs[s * n_units];
-  chunk_walk(cs, gidx, unit, [&](uint32_t b, uint32_t cnt) {
+  chunk_walk(cs, gidx, unit, ci, [&](uint32_t b, uint32_t cnt) {
     for (uint32_t p = 0; p < split; ++p) {
       Item it;
       it.set = s;
@@ -488,26 +508,27 @@ inline uint32_t blocks_for(uint64_t n, int per) { return (uint32_t)((n + per - 1
 
 hipError_t launch_keys(const int32_t *x, const int32_t *y, const int32_t *t, uint32_t n,
                        uint32_t n_centres, uint32_t set_base, uint32_t n_sets, const Geom &g,
-                       uint32_t *keys, uint32_t *vals, uint32_t *err, hipStream_t s) {
+                       int blocked, uint32_t *keys, uint32_t *vals, uint32_t *err,
+                       hipStream_t s) {
   (void)n_sets;
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_keys, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, s, x, y, t, n,
-                     n_centres, set_base, g, keys, vals, err);
+                     n_centres, set_base, g, blocked, keys, vals, err);
   return hipGetLastError();
 }
 
 hipError_t launch_csr(uint32_t n, uint32_t n_centres, uint32_t m, uint64_t seed, const Geom &g,
-                      int32_t *x, int32_t *y, int32_t *t, uint32_t *keys, uint32_t *vals,
-                      uint32_t *err, hipStream_t s) {
+                      int blocked, int32_t *x, int32_t *y, int32_t *t, uint32_t *keys,
+                      uint32_t *vals, uint32_t *err, hipStream_t s) {
   uint64_t tot = (uint64_t)n * m;
   if (tot == 0) return hipSuccess;
   hipLaunchKernelGGL(k_csr, dim3(blocks_for(tot, kThreads)), dim3(kThreads), 0, s, n, n_centres,
-                     m, seed, g, x, y, t, keys, vals, err);
+                     m, seed, g, blocked, x, y, t, keys, vals, err);
   return hipGetLastError();
 }
 
 hipError_t launch_resample(int method, uint32_t n, uint32_t n_centres, uint32_t m, uint64_t seed,
-                           const int32_t *ox,
+                           int blocked, const int32_t *ox,
                            const int32_t *oy, const int32_t *ot, const Geom &g, int32_t *x,
                            int32_t *y, int32_t *t, uint32_t *keys[2], uint32_t *vals[2],
                            void *sort_temp, hipStream_t s) {
@@ -535,7 +556,7 @@ hipError_t launch_resample(int method, uint32_t n, uint32_t n_centres, uint32_t 
     // writing keys[0]/vals[0]: when a == 0 each thread reads order[gid] first
   }
   hipLaunchKernelGGL(k_resample, grid, block, 0, s, n, n_centres, m, seed, method, order, ox, oy,
-                     ot, g, x, y, t, keys[0], vals[0]);
+                     ot, g, blocked, x, y, t, keys[0], vals[0]);
   return hipGetLastError();
 }
 
@@ -608,20 +629,21 @@ hipError_t launch_gather(const uint32_t *vals, const uint32_t *keys, int mark, u
 }
 
 hipError_t launch_items(const uint32_t *cs, uint32_t n_sets, const Geom &g, bool row_items,
-                        uint32_t split, uint32_t n_rows, uint32_t *chunks, uint32_t *offs,
-                        uint32_t *set_base, Item *items, uint32_t *n_items, void *scan_temp,
-                        hipStream_t s) {
+                        bool blocked, uint32_t split, uint32_t n_rows, uint32_t *chunks,
+                        uint32_t *offs, uint32_t *set_base, Item *items, uint32_t *n_items,
+                        void *scan_temp, hipStream_t s) {
   const uint32_t unit = row_items ? (uint32_t)g.nx : 1u;
   const uint32_t n_units = g.n_cells / unit;
   const uint32_t tot = n_sets * n_units;
+  const CentreIdx ci{g.n_cells, blocked};
   hipLaunchKernelGGL(k_chunks, dim3(blocks_for(tot, kThreads)), dim3(kThreads), 0, s, cs, tot,
-                     unit, chunks);
+                     unit, ci, chunks);
   hipError_t e = exclusive_scan(chunks, offs, tot, scan_temp, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_set_base, dim3(1), dim3(64), 0, s, offs, n_sets, n_units, split,
                      set_base, n_items);
   hipLaunchKernelGGL(k_emit, dim3(blocks_for(tot, kThreads)), dim3(kThreads), 0, s, cs, offs,
-                     set_base, n_sets, n_units, unit, split, n_rows, items);
+                     set_base, n_sets, n_units, unit, split, n_rows, ci, items);
   return hipGetLastError();
 }
 

@@ -688,7 +688,11 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
     }
     const int cy = (int)(rest % (uint32_t)g.ny);
     const int ct = (int)(rest / (uint32_t)g.ny);
-    const uint32_t set_off = (uint32_t)set * g.n_cells;
+    // cell starts of the neighbour rows: interleaved keys (stride 2, the set's
+    // cells), or the set's type-2 block of blocked keys (stride 1)
+    const bool blocked = a.blocked != 0;
+    const uint32_t cst = blocked ? 1u : 2u;
+    const uint32_t nb_off = blocked ? (2u * (uint32_t)set + 1u) * g.n_cells : (uint32_t)set * g.n_cells;
     QState q = {0u, 0u, 0u, 0u};
     Ctx<SYM, MODE, POLY> x{W, q, g, hist, histc, wide, S2lo, S2hi, T, lane, begin, 0u, a.P};
     unsigned long long ev = 0;
@@ -702,12 +706,14 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
         if (tt < 0 || tt >= g.nt) continue;
         const int yy = cy + dy;
         if (yy < 0 || yy >= g.ny) continue;
-        const bool home = (dt == 0 && dy == 0);
+        // (blocked: the neighbours are the other type's block, never the
+        // centres' own cell)
+        const bool home = (dt == 0 && dy == 0) && !blocked;
         const int xlo = (SYM && home) ? cxa : max(cxa - g.rs, 0);
         const int xhi = min(cxb + g.rs, g.nx - 1);
-        const uint32_t row = set_off + (uint32_t)(tt * g.ny + yy) * (uint32_t)g.nx;
-        uint32_t j0 = uni(a.cs[2 * (row + (uint32_t)xlo)]);
-        const uint32_t j1 = uni(a.cs[2 * (row + (uint32_t)xhi) + 2]);
+        const uint32_t row = nb_off + (uint32_t)(tt * g.ny + yy) * (uint32_t)g.nx;
+        uint32_t j0 = uni(a.cs[cst * (row + (uint32_t)xlo)]);
+        const uint32_t j1 = uni(a.cs[cst * (row + (uint32_t)xhi + 1u)]);
         if (home) {
           if (SYM) {
             j0 = begin + 1;

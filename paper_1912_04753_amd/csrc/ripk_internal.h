@@ -76,6 +76,8 @@ struct PairArgs {
   unsigned long long *n_eval;  // device scalar
   int symmetric;
   int row_items;               // items are chunks of x-rows (else of cells)
+  int blocked;                 // two-type sets in blocked key order: centres from the
+                               // type-1 block, neighbours from the type-2 block
   int wide_counts;             // 64-bit LDS pair counts (sets of 2^23 points or more)
 };
 
@@ -103,23 +105,25 @@ void plan_free(ripk_plan_s *p);
 ripk_status set_error(ripk_status s, const char *msg);  // sets ripk_last_error()
 
 // launchers (kernels.hip) ----------------------------------------------
+// Sort keys: interleaved ((set*n_cells + cell) << 1 | halo) or, with
+// `blocked` (two-type sets), (2*set + type)*n_cells + cell.
 hipError_t launch_keys(const int32_t *x, const int32_t *y, const int32_t *t, uint32_t n,
                        uint32_t n_centres, uint32_t set_base, uint32_t n_sets,
-                       const Geom &g, uint32_t *keys, uint32_t *vals, uint32_t *err,
-                       hipStream_t s);
+                       const Geom &g, int blocked, uint32_t *keys, uint32_t *vals,
+                       uint32_t *err, hipStream_t s);
 // m CSR sets of n points; points k >= n_centres of each set take the halo slot
 // of their cell (type 2 of a cross-K plan; n_centres = n otherwise)
 // (polygon: rejection sampling; a point that finds no attempt inside sets bit 1
 // of *err)
 hipError_t launch_csr(uint32_t n, uint32_t n_centres, uint32_t m, uint64_t seed, const Geom &g,
-                      int32_t *x, int32_t *y, int32_t *t, uint32_t *keys, uint32_t *vals,
-                      uint32_t *err, hipStream_t s);
+                      int blocked, int32_t *x, int32_t *y, int32_t *t, uint32_t *keys,
+                      uint32_t *vals, uint32_t *err, hipStream_t s);
 // Simulated sets drawn from the observed points ox, oy, ot (n each): method 1
 // random permutation of the time labels, 2 bootstrap (each of the types
 // [0, n_centres) and [n_centres, n) from itself); writes x, y, t and the cell
 // keys/values into keys[0], vals[0] (uses both sort buffers).
 hipError_t launch_resample(int method, uint32_t n, uint32_t n_centres, uint32_t m, uint64_t seed,
-                           const int32_t *ox,
+                           int blocked, const int32_t *ox,
                            const int32_t *oy, const int32_t *ot, const Geom &g, int32_t *x,
                            int32_t *y, int32_t *t, uint32_t *keys[2], uint32_t *vals[2],
                            void *sort_temp, hipStream_t s);
@@ -138,7 +142,7 @@ hipError_t launch_gather(const uint32_t *vals, const uint32_t *keys, int mark, u
                          const int32_t *x, const int32_t *y, const int32_t *t, const Geom &g,
                          int32_t clamp_e, int4 *P, hipStream_t s);
 hipError_t launch_items(const uint32_t *cs, uint32_t n_sets, const Geom &g, bool row_items,
-                        uint32_t split, uint32_t n_rows, uint32_t *chunks,
+                        bool blocked, uint32_t split, uint32_t n_rows, uint32_t *chunks,
                         uint32_t *offs, uint32_t *set_base, Item *items, uint32_t *n_items,
                         void *scan_temp, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, size_t n, unsigned long long v,
