@@ -78,6 +78,8 @@ def lib():
                                      ctypes.c_int, u64p, f64p]
         L.orc_estimate_cross.argtypes = [dp, i32p, i32p, i32p, ctypes.c_int64, ctypes.c_int64,
                                          ctypes.c_int, u64p, f64p, f64p, f64p]
+        L.orc_estimate_inhom.argtypes = [dp, i32p, i32p, i32p, f64p, ctypes.c_int64,
+                                         ctypes.c_int, u64p, f64p, f64p, f64p]
         L.orc_philox4x64_10.argtypes = [u64p, u64p, u64p]
         L.orc_csr_points.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64, dp,
                                      i32p, i32p, i32p]
@@ -220,6 +222,26 @@ def estimate_cross(d, x, y, t, n1, threads=0):
                                       _ptr(L, ctypes.c_double))
     if rc:
         raise ValueError("orc_estimate_cross failed")
+    s = (d.n_s, d.n_t)
+    return {"C": C.reshape(s), "W": W.reshape(s), "K": K.reshape(s), "L": L.reshape(s)}
+
+
+def estimate_inhom(d, x, y, t, lam, threads=0):
+    """Inhomogeneous K: C, W = sum of I/(omega v lambda_i lambda_j), K_I = W/(A*D)
+    and L_I (Eq. 4 applied to K_I), each n_s x n_t; ``lam`` = intensity per point."""
+    x, y, t = _soa(x, y, t)
+    lam = np.ascontiguousarray(lam, np.float64)
+    nb = d.n_s * d.n_t
+    C = np.zeros(nb, np.uint64)
+    W, K, L = (np.zeros(nb, np.float64) for _ in range(3))
+    with np.errstate(all="ignore"):
+        rc = lib().orc_estimate_inhom(ctypes.byref(d), _ptr(x, ctypes.c_int32),
+                                      _ptr(y, ctypes.c_int32), _ptr(t, ctypes.c_int32),
+                                      _ptr(lam, ctypes.c_double), len(x), int(threads),
+                                      _ptr(C, ctypes.c_uint64), _ptr(W, ctypes.c_double),
+                                      _ptr(K, ctypes.c_double), _ptr(L, ctypes.c_double))
+    if rc:
+        raise ValueError("orc_estimate_inhom failed")
     s = (d.n_s, d.n_t)
     return {"C": C.reshape(s), "W": W.reshape(s), "K": K.reshape(s), "L": L.reshape(s)}
 

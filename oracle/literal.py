@@ -10,6 +10,8 @@ histogram/prefix reformulation of ``oracle.c``:
   * omega_ij comes from the arc-union construction in ``omega_ref``;
   * v_ij is the end-point rule of Sec. 3 written out.
 
+With ``lam`` (an intensity per point) it evaluates the inhomogeneous
+estimator: each pair weighs 1/(omega v lambda_i lambda_j) and K = W/(A*D).
 With ``n1`` it evaluates the two-type (cross) estimator instead: only ordered
 pairs with i < n1 (type 1) and j >= n1 (type 2) count, and N = n1 * (n - n1).
 
@@ -26,7 +28,7 @@ EDGE_SPATIAL = 1
 EDGE_TEMPORAL = 2
 
 
-def literal_K(window, s_max, t_max, n_s, n_t, x, y, t, edge=3, norm=0, n1=None):
+def literal_K(window, s_max, t_max, n_s, n_t, x, y, t, edge=3, norm=0, n1=None, lam=None):
     """Return (Craw, K, L): Craw[k, l] = number of ordered pairs counted at (s_k, t_l)."""
     x0, y0, x1, y1, t0, t1 = (int(v) for v in window)
     x = [int(v) for v in x]
@@ -54,10 +56,14 @@ def literal_K(window, s_max, t_max, n_s, n_t, x, y, t, edge=3, norm=0, n1=None):
             if edge & EDGE_TEMPORAL:
                 v = 1.0 if (t[i] - u >= t0 and t[i] + u <= t1) else 0.5
             Wt[i, j] = 1.0 / (om * v)
+            if lam is not None:
+                Wt[i, j] /= float(lam[i]) * float(lam[j])
     off = ~np.eye(n, dtype=bool)
     A = (x1 - x0) * (y1 - y0)
     Dur = t1 - t0
     N = n * n if norm == 1 else n * (n - 1)
+    if lam is not None:
+        N = (A * Dur) ** 2   # K_I = W/(A*D)
     if n1 is not None:
         idx = np.arange(n)
         off = (idx[:, None] < n1) & (idx[None, :] >= n1)

@@ -36,6 +36,13 @@
  * with both corrections centred on the type-1 point i, and L12 from K12 as in
  * Eq. 4.  The histogram loop is the same, with i over type 1 and j over type 2.
  *
+ * Inhomogeneous K, the second extension named in Sec. 7 (after Baddeley,
+ * Moller and Waagepetersen's estimator, in its space-time form): with an
+ * intensity lambda_i > 0 given for every point,
+ *   K_I^(s,t) = 1/(A*D) * sum_i sum_{j!=i} I_{s,t}(d_ij,u_ij) / (omega_ij v_ij lambda_i lambda_j),
+ * L_I from K_I as in Eq. 4.  With lambda_i = n/(A*D) for all i it is Eq. 2 with
+ * N = n^2.
+ *
  * Polygon study areas (the general case of the isotropic correction, Sec. 3 and
  * the boundary-vertex cost of Sec. 4.4): A is the polygon's area, points lie
  * strictly inside it, omega is the share of the circle's circumference inside
@@ -260,8 +267,8 @@ static inline void neumaier(double *sum, double *comp, double v) {
  * 1/(omega*v) in FP64 with Neumaier compensation (per thread, then merged).
  * Returns 0, or -1 on bad arguments / allocation failure. */
 static int orc_hist_range(const orc_desc *q, const int32_t *x, const int32_t *y,
-                          const int32_t *t, int64_t n, int64_t n_centres, int64_t j_begin,
-                          int nthreads, uint64_t *Hc, double *Hw) {
+                          const int32_t *t, const double *rho, int64_t n, int64_t n_centres,
+                          int64_t j_begin, int nthreads, uint64_t *Hc, double *Hw) {
   if (!q || q->n_s < 1 || q->n_t < 1 || n < 0 || n_centres < 0 || n_centres > n ||
       j_begin < 0 || j_begin > n)
     return -1;
@@ -312,6 +319,7 @@ static int orc_hist_range(const orc_desc *q, const int32_t *x, const int32_t *y,
         double om = orc_omega(xi, yi, d2, q);
         if (om < 1.0 / ORC_MAX_SWEIGHT) om = 1.0 / ORC_MAX_SWEIGHT;
         double w = 1.0 / (om * orc_vt(ti, u, q));
+        if (rho) w *= rho[i] * rho[j]; /* inhomogeneous: 1/(lambda_i lambda_j) */
         c[k * nt + l] += 1;
         neumaier(&s[k * nt + l], &e[k * nt + l], w);
       }
@@ -335,13 +343,13 @@ static int orc_hist_range(const orc_desc *q, const int32_t *x, const int32_t *y,
 /* every point a neighbour: the univariate histogram of Eq. 2 */
 int orc_hist(const orc_desc *q, const int32_t *x, const int32_t *y, const int32_t *t,
              int64_t n, int64_t n_centres, int nthreads, uint64_t *Hc, double *Hw) {
-  return orc_hist_range(q, x, y, t, n, n_centres, 0, nthreads, Hc, Hw);
+  return orc_hist_range(q, x, y, t, NULL, n, n_centres, 0, nthreads, Hc, Hw);
 }
 
 /* cross histogram: centres i in [0, n1), neighbours j in [n1, n) */
 int orc_hist_cross(const orc_desc *q, const int32_t *x, const int32_t *y, const int32_t *t,
                    int64_t n, int64_t n1, int nthreads, uint64_t *Hc, double *Hw) {
-  return orc_hist_range(q, x, y, t, n, n1, n1, nthreads, Hc, Hw);
+  return orc_hist_range(q, x, y, t, NULL, n, n1, n1, nthreads, Hc, Hw);
 }
 
 /* ---------------------------------------------------------------- O7 -- */
@@ -429,6 +437,34 @@ int orc_estimate_cross(const orc_desc *q, const int32_t *x, const int32_t *y, co
     if (W) memcpy(W, w, sizeof(double) * nb);
   }
   free(c); free(w);
+  return rc;
+}
+
+/* Inhomogeneous estimator: every ordered pair weighted by 1/(lambda_i lambda_j);
+ * K_I = W/(A*D) (Eq. 2 with A*D/N replaced by 1/(A*D)). */
+int orc_estimate_inhom(const orc_desc *q, const int32_t *x, const int32_t *y, const int32_t *t,
+                       const double *lambda, int64_t n, int nthreads, uint64_t *C, double *W,
+                       double *K, double *L) {
+  const int nb = q->n_s * q->n_t;
+  uint64_t *c = (uint64_t *)malloc(sizeof(uint64_t) * nb);
+  double *w = (double *)malloc(sizeof(double) * nb);
+  double *rho = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+  int rc = (c && w && rho) ? 0 : -1;
+  for (int64_t i = 0; rc == 0 && i < n; ++i) {
+    if (!(lambda[i] > 0.0)) rc = -1;
+    rho[i] = 1.0 / lambda[i];
+  }
+  if (rc == 0) rc = orc_hist_range(q, x, y, t, rho, n, n, 0, nthreads, c, w);
+  if (rc == 0) {
+    orc_cumulate(q, c, w);
+    const double A = q->poly_n >= 3 ? orc_poly_area(q)
+                                    : (double)(q->x1 - q->x0) * (double)(q->y1 - q->y0);
+    const double AD = A * (double)(q->t1 - q->t0);
+    orc_normalise_by(q, AD * AD, w, K, L);
+    if (C) memcpy(C, c, sizeof(uint64_t) * nb);
+    if (W) memcpy(W, w, sizeof(double) * nb);
+  }
+  free(c); free(w); free(rho);
   return rc;
 }
 

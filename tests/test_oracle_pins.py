@@ -702,3 +702,65 @@ def test_polygon_weight_cap():
     assert Hc[0, 0] == 2
     w_back = 1.0 / oracle.omega(2600, 50, 1390 ** 2, d)
     assert abs(Hw[0, 0] - (64.0 + min(w_back, 64.0))) < 1e-9
+
+
+# -------------------------------------------------------- inhomogeneous K ----
+def test_inhom_constant_intensity_is_the_n2_estimate():
+    """With lambda_i = n/(A*D) for every point the inhomogeneous estimator is
+    Eq. 2 with N = n^2; any constant c*lambda scales K by 1/c^2."""
+    cfg = workloads.workload("uniform-2k")
+    x, y, t = workloads.make_points(cfg)
+    n = len(x)
+    args = (cfg["window"], cfg["s_max"], cfg["t_max"], cfg["n_s"], cfg["n_t"])
+    AD = 10_000.0 * 10_000.0 * 365 * 86400
+    r2 = oracle.estimate(oracle.desc(*args, norm=oracle.NORM_N2), x, y, t)
+    ri = oracle.estimate_inhom(oracle.desc(*args), x, y, t, np.full(n, n / AD))
+    assert np.array_equal(ri["C"], r2["C"])
+    assert np.allclose(ri["K"], r2["K"], rtol=1e-12, atol=0)
+    r3 = oracle.estimate_inhom(oracle.desc(*args), x, y, t, np.full(n, 3.0 * n / AD))
+    assert np.allclose(r3["K"], r2["K"] / 9.0, rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("edge", [3, 0])
+def test_inhom_literal_matches_oracle(edge):
+    """Literal per-step evaluation with 1/(lambda_i lambda_j) weights."""
+    rng = np.random.default_rng(71)
+    win = (0, 0, 1500, 1200, 0, 60_000)
+    n = 45
+    x = rng.integers(0, 1501, n); y = rng.integers(0, 1201, n); t = rng.integers(0, 60_001, n)
+    lam = rng.uniform(0.5, 4.0, n) * n / (1500 * 1200 * 60_000)
+    args = (win, 500, 9_000, 5, 4)
+    Craw, Klit, _ = literal.literal_K(*args, x, y, t, edge=edge, lam=lam)
+    r = oracle.estimate_inhom(oracle.desc(*args, edge=edge), x, y, t, lam)
+    assert np.array_equal(r["C"].astype(np.int64), Craw)
+    assert np.allclose(r["K"], Klit, rtol=1e-12, atol=0)
+
+
+def test_inhom_expectation_under_inhomogeneous_poisson():
+    """A Poisson process with intensity lambda(x) = lam0 * (0.2 + 1.6 x/W)
+    (drawn by thinning, Poisson count): with the true intensity, the mean of
+    K_I over 150 draws is 2*pi*s^2*t within 4 standard errors; the homogeneous
+    estimator of the same draws is biased upwards."""
+    win = (0, 0, 2000, 2000, 0, 1_000_000)
+    s_max, n_s, t_max, n_t = 300, 3, 200_000, 4
+    d = oracle.desc(win, s_max, t_max, n_s, n_t)
+    AD = 2000.0 * 2000.0 * 1_000_000
+    lam0 = 800 / AD
+    rng = np.random.default_rng(72)
+    Ks, Kh = [], []
+    for _ in range(150):
+        m = rng.poisson(800 * 1.8)   # candidates at the peak intensity, thinned
+        x = rng.integers(0, 2000, m); y = rng.integers(0, 2000, m); t = rng.integers(0, 1_000_000, m)
+        f = 0.2 + 1.6 * x / 2000.0
+        keep = rng.uniform(0, 1.8, m) < f
+        x, y, t = x[keep], y[keep], t[keep]
+        Ks.append(oracle.estimate_inhom(d, x, y, t, lam0 * (0.2 + 1.6 * x / 2000.0))["K"])
+        Kh.append(oracle.estimate(d, x, y, t)["K"])
+    Ks, Kh = np.array(Ks), np.array(Kh)
+    se = Ks.std(axis=0, ddof=1) / math.sqrt(len(Ks))
+    s = (np.arange(1, n_s + 1) * s_max / n_s)[:, None]
+    tt = (np.arange(1, n_t + 1) * t_max / n_t)[None, :]
+    want = 2 * np.pi * s ** 2 * tt
+    z = (Ks.mean(axis=0) - want) / se
+    assert np.all(np.abs(z) < 4.0), z
+    assert Kh.mean(axis=0)[-1, -1] > 1.1 * want[-1, -1]
