@@ -96,6 +96,23 @@ enum {
                                         /* seed, geometry) repeats                      */
 #define RIPK_PLAN_CROSS (1u << 5)       /* two-type (cross, bivariate) K, the first     */
                                         /* extension named in Sec. 7: see below         */
+#define RIPK_PLAN_INHOM (1u << 6)       /* inhomogeneous K, the second extension named  */
+                                        /* in Sec. 7: see below                         */
+
+/*
+ * Inhomogeneous K.  With RIPK_PLAN_INHOM, ripk_compute_K reads an intensity
+ * lambda_i > 0 (finite) for every point (ripk_points.lambda; RIPK_EINVAL when
+ * NULL, RIPK_ERANGE when a value is not positive and finite) and computes
+ *   K_I(s,t) = 1/(A*D) * sum_i sum_{j!=i} I(d_ij <= s, u_ij <= t) / (omega_ij v_ij lambda_i lambda_j),
+ * which is Eq. 2 with N = n^2 when lambda is the constant n/(A*D); L_I follows
+ * as in Eq. 4, and C counts pairs as usual.  The norm field is ignored.  The
+ * weighted sums are FP64 (device atomics in an order that varies from run to
+ * run, so W, K and L may differ in their last bits between runs; counts are
+ * exact).  Such plans take a rectangle (no polygon), one point type (no
+ * RIPK_PLAN_CROSS) and no simulations: the null model, a Poisson process of
+ * intensity lambda, needs the intensity as a function, not at the points
+ * (ripk_simulate_envelope returns RIPK_EINVAL).
+ */
 
 /*
  * Cross K.  With RIPK_PLAN_CROSS the points of ripk_compute_K carry two types:
@@ -179,13 +196,16 @@ typedef struct {
 /* A point set in structure-of-arrays form.  Points [0, n_centres) act as
  * centres i of Eq. 2; points [n_centres, n) are neighbours j only (a halo,
  * as when one shard of a larger set is evaluated).  n_centres = 0 means all.
- * on_device = 1: x, y, t are device pointers on the plan's device, ordered on
- * the call's stream; 0: host pointers. */
+ * on_device = 1: x, y, t (and lambda) are device pointers on the plan's
+ * device, ordered on the call's stream; 0: host pointers.  lambda: the
+ * intensity at every point (points per m^2 per s), read by plans made with
+ * RIPK_PLAN_INHOM only (NULL otherwise). */
 typedef struct {
   const int32_t *x, *y, *t;
   int64_t n;
   int64_t n_centres;
   int32_t on_device;
+  const double *lambda;
 } ripk_points;
 
 /* Outputs of ripk_compute_K: host buffers of n_s*n_t elements each, any may

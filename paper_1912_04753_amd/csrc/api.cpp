@@ -190,10 +190,11 @@ void build_near(const Layout &L, int64_t s_max, std::vector<uint16_t> *out) {
 namespace ripk {
 
 Caps caps_for(int64_t S, int64_t n_max, int64_t n_cells, int64_t n_bins, int64_t V,
-              int64_t NXY) {
+              int64_t NXY, int64_t R) {
   Caps c;
   c.V = V;
   c.NXY = NXY;
+  c.R = R;
   c.S = S;
   c.N = S * n_max;
   c.SNC = S * n_cells;
@@ -219,13 +220,14 @@ int64_t caps_bytes(const Caps &c) {
   bytes += 8 * 6 * c.NB + 8 * 2 * kMaxSteps + 32;
   bytes += 3 * 4 * c.P;                       // copy of the observed set (resampling)
   bytes += 8 * c.V + 2 * (kNearMax + 1) * c.NXY;  // polygon and its per-cell edge lists
+  bytes += 16 * c.R;                          // intensities and their sorted reciprocals
   return bytes;
 }
 
 bool caps_fit(const Caps &have, const Caps &need) {
   return need.S <= have.S && need.N <= have.N && need.SNC <= have.SNC &&
          need.items <= have.items && need.SNB <= have.SNB && need.NB <= have.NB &&
-         need.P <= have.P && need.V <= have.V && need.NXY <= have.NXY;
+         need.P <= have.P && need.V <= have.V && need.NXY <= have.NXY && need.R <= have.R;
 }
 
 Caps caps_max(const Caps &a, const Caps &b) {
@@ -239,6 +241,7 @@ Caps caps_max(const Caps &a, const Caps &b) {
   c.P = std::max(a.P, b.P);
   c.V = std::max(a.V, b.V);
   c.NXY = std::max(a.NXY, b.NXY);
+  c.R = std::max(a.R, b.R);
   return c;
 }
 
@@ -282,8 +285,10 @@ ripk_status derive(const ripk_plan_desc *d, Layout *L) {
     return fail(RIPK_EINVAL, "temporal correction needs t_max <= t1-t0");
   if (d->norm > RIPK_NORM_N2) return fail(RIPK_EINVAL, "unknown normalisation");
   if (d->flags & ~(RIPK_PLAN_ORDERED | RIPK_PLAN_TIMING | RIPK_PLAN_WIDE_COUNTS |
-                   RIPK_PLAN_AUTOTUNE | RIPK_PLAN_GRAPH | RIPK_PLAN_CROSS))
+                   RIPK_PLAN_AUTOTUNE | RIPK_PLAN_GRAPH | RIPK_PLAN_CROSS | RIPK_PLAN_INHOM))
     return fail(RIPK_EINVAL, "unknown plan flags");
+  if ((d->flags & RIPK_PLAN_INHOM) && ((d->flags & RIPK_PLAN_CROSS) || d->poly_n != 0))
+    return fail(RIPK_EINVAL, "inhomogeneous K plans take one point type and the rectangle");
   if (d->sim_method != RIPK_SIM_CSR && d->sim_method != RIPK_SIM_PERMUTE &&
       d->sim_method != RIPK_SIM_BOOTSTRAP)
     return fail(RIPK_EINVAL, "unknown simulation method");
@@ -364,7 +369,7 @@ ripk_status derive(const ripk_plan_desc *d, Layout *L) {
   L->area = L->V.empty() ? (double)W * (double)H : 0.5 * (double)std::llabs(area2);
 
   L->caps = caps_for(S, d->n_max, I.n_cells, I.n_bins, (int64_t)L->V.size(),
-                     L->V.empty() ? 0 : nx * ny);
+                     L->V.empty() ? 0 : nx * ny, (d->flags & RIPK_PLAN_INHOM) ? d->n_max : 0);
   I.device_bytes = caps_bytes(L->caps);
   return RIPK_OK;
 }
@@ -393,7 +398,7 @@ struct ripk_plan_s {
   uint64_t bind_gen = 0;               // bumped whenever a geometry is bound
   // RIPK_PLAN_GRAPH: the captured launch sequence of the last call shape
   hipGraphExec_t gexec = nullptr;
-  uint64_t gkey[12] = {};
+  uint64_t gkey[13] = {};
   int device = 0;
   int cus = 0;
   size_t lds_max = 0;  // LDS bytes a workgroup may use on this device
@@ -418,6 +423,9 @@ struct ripk_plan_s {
   double *env = nullptr, *Lobs = nullptr;
   uint64_t *S2 = nullptr;
   uint32_t *T = nullptr;
+  double *lam = nullptr;       // intensities of the observed set (host input staged here)
+  double *rho = nullptr;       // 1/lambda per sorted record
+  const double *cur_lam = nullptr;  // intensities of the current call (device)
   int2 *poly = nullptr;        // polygon vertices (window-relative)
   uint16_t *near = nullptr;    // per xy-cell edge lists of the bound geometry
   std::vector<uint16_t> nearh; // host copy of the lists (source of the upload)
@@ -442,7 +450,7 @@ void release(ripk_plan_s *p) {
                   p->vals[1],
                   p->sort_temp, p->cs, p->P, p->chunks, p->offs, p->set_base, p->scan_temp,
                   p->items, p->binC, p->binW, p->outC, p->outW, p->outK, p->outL, p->env,
-                  p->Lobs, p->S2, p->T, p->poly, p->near, p->scal};
+                  p->Lobs, p->S2, p->T, p->poly, p->near, p->lam, p->rho, p->scal};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   for (auto &e : p->ev)
@@ -503,13 +511,16 @@ ripk_status enqueue_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_cent
   // block, so no record needs the no-neighbour mark
   HIPCHK(launch_gather(p->vals[alt], p->keys[alt], 0, N, x, y, t, g, p->lay.clamp_e,
                        p->P, st));
+  const bool inhom = (p->desc.flags & RIPK_PLAN_INHOM) != 0 && !simulate;
+  if (inhom) HIPCHK(launch_gather_rho(p->vals[alt], N, p->cur_lam, p->rho, err, st));
   // row items need rows without halo entries: every point a centre, or the
   // type-1 block of a cross-K set
   const bool row_items = n_centres == n || cross;
   const int wide_counts =
       ((int64_t)n >= kWideCountPoints || (p->desc.flags & RIPK_PLAN_WIDE_COUNTS)) ? 1 : 0;
   int per_cu = 0;
-  HIPCHK(pair_occupancy((int)NB, wide_counts, symmetric ? 1 : 0, g.mode, pair_poly(g), &per_cu));
+  HIPCHK(pair_occupancy((int)NB, wide_counts, symmetric ? 1 : 0, g.mode,
+                        inhom ? 2 : (pair_poly(g) ? 1 : 0), &per_cu));
   if (per_cu < 1) return fail(RIPK_EINVAL, "pair kernel does not fit on a compute unit (n_bins=%u)", NB);
   // A launch with fewer groups than about twice the resident workgroups splits
   // every item's stencil rows into `split` parts taken by different waves.
@@ -544,19 +555,23 @@ ripk_status enqueue_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_cent
   a.symmetric = symmetric ? 1 : 0;
   a.row_items = row_items ? 1 : 0;
   a.blocked = cross ? 1 : 0;
+  a.rho = inhom ? p->rho : nullptr;
   a.wide_counts = wide_counts;
   const int64_t groups_cap = items_bound * split / kItemsPerGroup + 1;
   const int grid = (int)std::min<int64_t>(slots, groups_cap);
   HIPCHK(launch_pair(a, grid, st));
   if (timing) HIPCHK(hipEventRecord(p->ev[3], st));
 
-  const double AD = p->lay.area * (double)(p->desc.t1 - p->desc.t0);
-  const double Nn = cross ? (double)n_centres * (double)(n - n_centres)
+  // K = AD * W / Nn; inhomogeneous K is W / (A D)
+  const double vol = p->lay.area * (double)(p->desc.t1 - p->desc.t0);
+  const double AD = inhom ? 1.0 : vol;
+  const double Nn = inhom ? vol
+                    : cross ? (double)n_centres * (double)(n - n_centres)
                     : p->desc.norm == RIPK_NORM_N2 ? (double)n * (double)n
                                                    : (double)n * (double)(n - 1);
   HIPCHK(launch_finalize(p->binC, p->binW, S, g.n_s, g.n_t, (double)p->desc.s_max,
                          (double)p->desc.t_max, AD, Nn, p->outC, p->outW, p->outK, p->outL,
-                         p->scal + 1, st));
+                         p->scal + 1, st, inhom));
   if (simulate)
     HIPCHK(launch_envelope(p->outK, p->outL, S, (int)NB, has_Lobs ? p->Lobs : nullptr, p->env, st));
   if (timing) HIPCHK(hipEventRecord(p->ev[4], st));
@@ -582,9 +597,10 @@ ripk_status run_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_centres,
   if (!graph)
     return enqueue_sets(p, S, n, n_centres, x, y, t, simulate, seed, has_Lobs, st, symmetric, timing,
                         S_split);
-  const uint64_t key[12] = {S, n, n_centres, (uint64_t)simulate, (uint64_t)symmetric,
+  const uint64_t key[13] = {S, n, n_centres, (uint64_t)simulate, (uint64_t)symmetric,
                             (uint64_t)(uintptr_t)x, (uint64_t)(uintptr_t)y, (uint64_t)(uintptr_t)t,
-                            seed, (uint64_t)has_Lobs, p->bind_gen, S_split};
+                            seed, (uint64_t)has_Lobs, p->bind_gen, S_split,
+                            (uint64_t)(uintptr_t)p->cur_lam};
   if (!p->gexec || std::memcmp(key, p->gkey, sizeof key) != 0) {
     if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
     p->gexec = nullptr;
@@ -638,6 +654,7 @@ ripk_status collect_stats(ripk_plan_s *p, hipStream_t st, uint32_t S, uint32_t n
 // point that found no attempt inside the polygon
 ripk_status err_status(uint32_t err) {
   if (err & 1u) return fail(RIPK_ERANGE, "a point lies outside the study area");
+  if (err & 4u) return fail(RIPK_ERANGE, "an intensity is not positive and finite");
   return fail(RIPK_EDEVICE, "rejection sampling found no point inside the polygon");
 }
 
@@ -695,6 +712,7 @@ ripk_status plan_create(int device, const Caps &c, ripk_plan_s **out) {
   ALLOC(p->env, 5 * c.NB); ALLOC(p->Lobs, c.NB);
   ALLOC(p->S2, kMaxSteps); ALLOC(p->T, kMaxSteps);
   ALLOC(p->poly, c.V); ALLOC(p->near, (kNearMax + 1) * c.NXY);
+  ALLOC(p->lam, c.R); ALLOC(p->rho, c.R);
   ALLOC(p->scal, 4);
 #undef ALLOC
   if (e != hipSuccess) {
@@ -906,6 +924,10 @@ ripk_status ripk_compute_K(ripk_plan_t p, const ripk_points *pts, void *stream, 
   if (n > p->desc.n_max) return fail(RIPK_EINVAL, "n = %lld exceeds n_max = %lld", (long long)n, (long long)p->desc.n_max);
   if (nc < 0 || nc > n) return fail(RIPK_EINVAL, "n_centres must be in [0, n]");
   const bool cross = (p->desc.flags & RIPK_PLAN_CROSS) != 0;
+  const bool inhom = (p->desc.flags & RIPK_PLAN_INHOM) != 0;
+  if (inhom && !pts->lambda)
+    return fail(RIPK_EINVAL, "an inhomogeneous K plan needs the intensity of every point");
+  if (inhom && nc != n) return fail(RIPK_EINVAL, "inhomogeneous K takes every point as a centre");
   if (cross && (pts->n_centres < 1 || pts->n_centres >= n))
     return fail(RIPK_EINVAL, "cross K needs 1 <= n_centres < n (type 1 = points [0, n_centres))");
   if (!pts->x || !pts->y || !pts->t) return fail(RIPK_EINVAL, "null coordinate array");
@@ -913,6 +935,15 @@ ripk_status ripk_compute_K(ripk_plan_t p, const ripk_points *pts, void *stream, 
   DeviceGuard dg(p->device);
   hipStream_t st = (hipStream_t)stream;
   const int32_t *x = pts->x, *y = pts->y, *t = pts->t;
+  p->cur_lam = nullptr;
+  if (inhom) {
+    if (pts->on_device) {
+      p->cur_lam = pts->lambda;
+    } else {
+      HIPCHK(hipMemcpyAsync(p->lam, pts->lambda, sizeof(double) * n, hipMemcpyHostToDevice, st));
+      p->cur_lam = p->lam;
+    }
+  }
   if (!pts->on_device) {
     HIPCHK(hipMemcpyAsync(p->x, x, sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(p->y, y, sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
@@ -963,6 +994,10 @@ ripk_status ripk_simulate_envelope(ripk_plan_t p, int64_t n, int32_t m, uint64_t
                 "permutation and bootstrap simulations draw from the plan's last observed set: "
                 "call ripk_compute_K on %lld points first", (long long)n);
   const bool cross = (p->desc.flags & RIPK_PLAN_CROSS) != 0;
+  if (p->desc.flags & RIPK_PLAN_INHOM)
+    return fail(RIPK_EINVAL,
+                "inhomogeneous K plans take no simulations (the null model needs the "
+                "intensity as a function)");
   if (cross && p->split_n != n)
     return fail(RIPK_EINVAL,
                 "cross K simulations keep the type split of the plan's last observed set: "

@@ -20,13 +20,21 @@ __device__ __forceinline__ void add128(unsigned long long &lo, unsigned long lon
   lo = r;
 }
 
+// FP64 sums (inhomogeneous K) sit in the first word of each 128-bit bin
+__device__ __forceinline__ double as_f64(unsigned long long v) {
+  return __longlong_as_double((long long)v);
+}
+__device__ __forceinline__ unsigned long long as_u64(double v) {
+  return (unsigned long long)__double_as_longlong(v);
+}
+
 // One workgroup per set.  binC/binW are cumulated in place.
 __global__ void k_finalize(unsigned long long *__restrict__ binC,
                            unsigned long long *__restrict__ binW, int n_s, int n_t,
                            double s_max, double t_max, double AD, double N,
                            unsigned long long *__restrict__ C, double *__restrict__ W,
                            double *__restrict__ K, double *__restrict__ L,
-                           unsigned long long *__restrict__ n_in) {
+                           unsigned long long *__restrict__ n_in, int fp) {
   const int set = blockIdx.x;
   const int nb = n_s * n_t;
   unsigned long long *c = binC + (size_t)set * nb;
@@ -34,13 +42,19 @@ __global__ void k_finalize(unsigned long long *__restrict__ binC,
   // prefix along t within each s row
   for (int k = threadIdx.x; k < n_s; k += blockDim.x) {
     unsigned long long rc = 0, rlo = 0, rhi = 0;
+    double rf = 0.0;
     for (int l = 0; l < n_t; ++l) {
       int b = k * n_t + l;
       rc += c[b];
-      add128(rlo, rhi, w[2 * b], w[2 * b + 1]);
       c[b] = rc;
-      w[2 * b] = rlo;
-      w[2 * b + 1] = rhi;
+      if (fp) {
+        rf += as_f64(w[2 * b]);
+        w[2 * b] = as_u64(rf);
+      } else {
+        add128(rlo, rhi, w[2 * b], w[2 * b + 1]);
+        w[2 * b] = rlo;
+        w[2 * b + 1] = rhi;
+      }
     }
   }
   __threadfence_block();
@@ -48,13 +62,19 @@ __global__ void k_finalize(unsigned long long *__restrict__ binC,
   // prefix along s within each t column
   for (int l = threadIdx.x; l < n_t; l += blockDim.x) {
     unsigned long long rc = 0, rlo = 0, rhi = 0;
+    double rf = 0.0;
     for (int k = 0; k < n_s; ++k) {
       int b = k * n_t + l;
       rc += c[b];
-      add128(rlo, rhi, w[2 * b], w[2 * b + 1]);
       c[b] = rc;
-      w[2 * b] = rlo;
-      w[2 * b + 1] = rhi;
+      if (fp) {
+        rf += as_f64(w[2 * b]);
+        w[2 * b] = as_u64(rf);
+      } else {
+        add128(rlo, rhi, w[2 * b], w[2 * b + 1]);
+        w[2 * b] = rlo;
+        w[2 * b + 1] = rhi;
+      }
     }
   }
   __threadfence_block();
@@ -63,7 +83,9 @@ __global__ void k_finalize(unsigned long long *__restrict__ binC,
   for (int b = threadIdx.x; b < nb; b += blockDim.x) {
     int k = b / n_t, l = b - k * n_t;
     // W = (hi * 2^64 + lo) * 2^-23
-    double wv = ldexp((double)w[2 * b + 1], 64 - kFracBits) + ldexp((double)w[2 * b], -kFracBits);
+    // fixed point: W = (hi * 2^64 + lo) * 2^-23; FP64 bins hold the weight sums as they are
+    double wv = fp ? as_f64(w[2 * b])
+                   : ldexp((double)w[2 * b + 1], 64 - kFracBits) + ldexp((double)w[2 * b], -kFracBits);
     double Kv = AD * wv / N;
     double sk = (double)(k + 1) * s_max / (double)n_s;
     double tl = (double)(l + 1) * t_max / (double)n_t;
@@ -102,9 +124,9 @@ __global__ void k_envelope(const double *__restrict__ K, const double *__restric
 hipError_t launch_finalize(unsigned long long *binC, unsigned long long *binW, uint32_t n_sets,
                            int n_s, int n_t, double s_max, double t_max, double AD, double N,
                            unsigned long long *C, double *W, double *K, double *L,
-                           unsigned long long *n_in, hipStream_t s) {
+                           unsigned long long *n_in, hipStream_t s, bool fp) {
   hipLaunchKernelGGL(k_finalize, dim3(n_sets), dim3(256), 0, s, binC, binW, n_s, n_t, s_max,
-                     t_max, AD, N, C, W, K, L, n_in);
+                     t_max, AD, N, C, W, K, L, n_in, fp ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -395,6 +395,18 @@ __global__ void k_gather(const uint32_t *__restrict__ vals, const uint32_t *__re
   P[r] = make_int4(X, Y, T, e);
 }
 
+// 1/lambda of the sorted records (inhomogeneous K)
+__global__ void k_gather_rho(const uint32_t *__restrict__ vals, uint32_t n,
+                             const double *__restrict__ lambda, double *__restrict__ rho,
+                             uint32_t *__restrict__ err) {
+  uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const double l = lambda[vals[r]];
+  const bool ok = l > 0.0 && l < __builtin_inf();
+  if (!ok) atomicOr(err, 4u);
+  rho[r] = ok ? 1.0 / l : 0.0;
+}
+
 // A unit is the run of cells whose centres a work item may mix: one cell, or a
 // whole x-row of cells (unit = nx) when every point is a centre (no halo
 // entries between the cells).  Units cover cells [g*unit, (g+1)*unit) of the
@@ -625,6 +637,14 @@ hipError_t launch_gather(const uint32_t *vals, const uint32_t *keys, int mark, u
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_gather, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, s, vals, keys,
                      mark, n, x, y, t, g, clamp_e, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_rho(const uint32_t *vals, uint32_t n, const double *lambda, double *rho,
+                             uint32_t *err, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_rho, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, s, vals, n,
+                     lambda, rho, err);
   return hipGetLastError();
 }
 

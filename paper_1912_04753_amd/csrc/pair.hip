@@ -213,15 +213,38 @@ __device__ __forceinline__ uint32_t qweight_poly(double om, uint32_t half) {
 // Polygon records (every distance mode): {bin | half_i<<12 | half_j<<13 |
 // slow_i<<14 | slow_j<<15 | d2 hi<<16, d2 lo, i, j} with i, j the sorted-record
 // indices of the two points.
-template <int MODE, bool POLY>
+// INHOM: the same records as POLY; the rectangle's weight times
+// 1/(lambda_i lambda_j) = rho_i rho_j, added to FP64 bins.
+template <int MODE, bool POLY, bool INHOM>
 __device__ __forceinline__ void drain_b(WaveLds &W, QState &q, uint32_t c, int lane,
                                         unsigned long long *hw, const Geom &g,
-                                        const int4 *__restrict__ P) {
+                                        const int4 *__restrict__ P,
+                                        const double *__restrict__ rho) {
   wave_sync();
   const uint4 r = W.qb[(q.hb + lane) & (kQB - 1)];
   wave_sync();
   const uint32_t bin = r.x & 0xFFFu;
   uint32_t qv;
+  if (INHOM) {
+    const uint64_t d2 = (uint64_t)r.y | ((uint64_t)(r.x >> 16) << 32);
+    if ((uint32_t)lane < c) {
+      double wsum = 0.0;
+#pragma unroll 1
+      for (uint32_t side = 0; side < 2; ++side) {
+        if ((r.x >> (14 + side)) & 1u) {
+          const int4 p = P[side ? r.w : r.z];
+          const uint32_t ex = (uint32_t)min(p.x, g.x1 - g.x0 - p.x);
+          const uint32_t ey = (uint32_t)min(p.y, g.y1 - g.y0 - p.y);
+          const float w = fmaxf(__builtin_amdgcn_rcpf(omega_f32(ex, ey, d2)), 1.0f);
+          wsum += (double)w * (double)(1u << ((r.x >> (12 + side)) & 1u));
+        }
+      }
+      atomicAdd((double *)&hw[bin], wsum * (rho[r.z] * rho[r.w]));
+    }
+    q.hb = (q.hb + c) & (kQB - 1);
+    q.nb -= c;
+    return;
+  }
   if (POLY) {
     const uint64_t d2 = (uint64_t)r.y | ((uint64_t)(r.x >> 16) << 32);
     qv = 0;
@@ -284,13 +307,15 @@ __device__ __forceinline__ Side side_of(const int4 p, uint32_t d2lo, uint64_t d2
 // fast path of omega are evaluated without branches on per-lane data (lanes
 // past c compute on entry 0 and store nothing); boundary sides go to queue B.
 // (POLY: `begin` is the first centre's record index, `tb` the tile's.)
-template <bool SYM, int MODE, bool POLY>
+template <bool SYM, int MODE, bool POLY, bool INHOM>
 __device__ __forceinline__ void drain_a(WaveLds &W, QState &q,
                                         uint32_t c, int lane, const Geom &g,
                                         unsigned long long *hist, uint32_t *histc,
                                         bool wide_counts, const uint32_t *S2lo,
                                         const uint32_t *S2hi, const uint32_t *T,
-                                        uint32_t begin, uint32_t tb, const int4 *P) {
+                                        uint32_t begin, uint32_t tb, const int4 *P,
+                                        const double *rho, const double *rho_c,
+                                        const double *rho_t) {
   wave_sync();
   const uint32_t tag0 = W.qa[q.ha + (uint32_t)lane];  // q.ha + 63 < kQA: no wrap
   wave_sync();
@@ -361,8 +386,15 @@ __device__ __forceinline__ void drain_a(WaveLds &W, QState &q,
   // weights hist[bin], pair counts in a separate array (32-bit words unless
   // the set is large): separate arrays keep the 64 lanes' atomics spread over
   // all LDS banks
+  if (INHOM) {
+    // fast-path sides in units of 2^23 times rho_i rho_j (FP64 bins)
+    const uint32_t ci = v ? ((tag & 0xFFFFu) - kCenOff) >> 2 : 0u;
+    const uint32_t tj = v ? ((tag >> 16) - kTileOff) >> 2 : 0u;
+    const double rr = rho_c[ci] * rho_t[tj];
+    if (v) atomicAdd((double *)&hist[bin], (double)(qsum >> kFracBits) * rr);
+  }
   if (v) {
-    atomicAdd(&hist[bin], (unsigned long long)qsum);
+    if (!INHOM) atomicAdd(&hist[bin], (unsigned long long)qsum);
     if (wide_counts)
       atomicAdd((unsigned long long *)histc + bin, 1ull);
     else
@@ -375,7 +407,7 @@ __device__ __forceinline__ void drain_a(WaveLds &W, QState &q,
     q.ha = 0;
     q.ta = 0;
   }
-  if (POLY) {
+  if (POLY || INHOM) {
     // one record per pair with a boundary side, naming both points
     const bool need = si.slow || sj.slow;
     const unsigned long long m = mslow;
@@ -387,7 +419,7 @@ __device__ __forceinline__ void drain_a(WaveLds &W, QState &q,
                                    ((uint32_t)(SYM && sj.slow) << 15) | (d2hi << 16),
                                d2lo, begin + (((tag & 0xFFFFu) - kCenOff) >> 2),
                                tb + (((tag >> 16) - kTileOff) >> 2));
-      if (q.nb >= 64) drain_b<MODE, POLY>(W, q, 64, lane, hist, g, P);
+      if (q.nb >= 64) drain_b<MODE, POLY, INHOM>(W, q, 64, lane, hist, g, P, rho);
     }
   } else if (MODE == kModePacked) {
     // one record per pair with a boundary side
@@ -400,7 +432,7 @@ __device__ __forceinline__ void drain_a(WaveLds &W, QState &q,
         W.qb[pos] = make_uint4(bin | (hfi << 12) | (hfj << 13) | ((uint32_t)si.slow << 14) |
                                    ((uint32_t)(SYM && sj.slow) << 15),
                                d2lo, (uint32_t)pi.z, (uint32_t)pj.z);
-      if (q.nb >= 64) drain_b<MODE, POLY>(W, q, 64, lane, hist, g, P);
+      if (q.nb >= 64) drain_b<MODE, POLY, INHOM>(W, q, 64, lane, hist, g, P, rho);
     }
   } else {
     // one record per boundary side, one side per pass through a single drain site
@@ -415,7 +447,7 @@ __device__ __forceinline__ void drain_a(WaveLds &W, QState &q,
         if (need && v)
           W.qb[pos] = make_uint4(w0 | ((side ? hfj : hfi) << 12), d2lo, side ? sj.ex : si.ex,
                                  side ? sj.ey : si.ey);
-        if (q.nb >= 64) drain_b<MODE, POLY>(W, q, 64, lane, hist, g, P);
+        if (q.nb >= 64) drain_b<MODE, POLY, INHOM>(W, q, 64, lane, hist, g, P, rho);
       }
     }
   }
@@ -472,7 +504,7 @@ __device__ __forceinline__ void cand(const int4 me, uint32_t tplus, int thr, con
   ct = dtp <= 2u * g.tmax;
 }
 
-template <bool SYM, int MODE, bool POLY>
+template <bool SYM, int MODE, bool POLY, bool INHOM>
 struct Ctx {
   WaveLds &W;
   QState &q;
@@ -485,19 +517,22 @@ struct Ctx {
   uint32_t begin;  // record index of the item's first centre
   uint32_t tb;     // record index of the first entry of the tile in LDS
   const int4 *P;   // sorted records
+  const double *rho;            // INHOM: 1/lambda per sorted record
+  double *rho_c, *rho_t;        // INHOM: rho of the wave's centres and tile (LDS)
 };
 
-template <bool SYM, int MODE, bool POLY>
-__device__ __forceinline__ void drain_oldest(Ctx<SYM, MODE, POLY> &x, uint32_t c) {
-  drain_a<SYM, MODE, POLY>(x.W, x.q, c, x.lane, x.g, x.hist, x.histc, x.wide_counts, x.S2lo,
-                           x.S2hi, x.T, x.begin, x.tb, x.P);
+template <bool SYM, int MODE, bool POLY, bool INHOM>
+__device__ __forceinline__ void drain_oldest(Ctx<SYM, MODE, POLY, INHOM> &x, uint32_t c) {
+  drain_a<SYM, MODE, POLY, INHOM>(x.W, x.q, c, x.lane, x.g, x.hist, x.histc, x.wide_counts,
+                                  x.S2lo, x.S2hi, x.T, x.begin, x.tb, x.P, x.rho, x.rho_c,
+                                  x.rho_t);
 }
 
 // One run of consecutive sorted points [j0, j1) against the wave's centres.
 // HOME: the run holds the centres' own cell (j > i in symmetric mode, j != i
 // otherwise).
-template <bool SYM, int MODE, bool POLY, bool HOME>
-__device__ __forceinline__ void scan_run(Ctx<SYM, MODE, POLY> &x, uint32_t j0, uint32_t j1,
+template <bool SYM, int MODE, bool POLY, bool INHOM, bool HOME>
+__device__ __forceinline__ void scan_run(Ctx<SYM, MODE, POLY, INHOM> &x, uint32_t j0, uint32_t j1,
                                          const int4 me, uint32_t tplus, int thr, bool lv,
                                          unsigned long long valid, uint32_t mi,
                                          const int4 *__restrict__ P) {
@@ -508,8 +543,12 @@ __device__ __forceinline__ void scan_run(Ctx<SYM, MODE, POLY> &x, uint32_t j0, u
   // raw record of the next tile; converted to its LDS image only when stored,
   // so that the load stays in flight while the current tile is scanned
   int4 nxt = make_int4(0, 0, 0, 0);
+  double nxt_rho = 0.0;
   bool nxt_ok = j0 + (uint32_t)lane < j1;
-  if (nxt_ok) nxt = P[j0 + lane];
+  if (nxt_ok) {
+    nxt = P[j0 + lane];
+    if (INHOM) nxt_rho = x.rho[j0 + lane];
+  }
   for (uint32_t tb = j0; tb < j1; tb += kJT) {
     const uint32_t nt = uni(min((uint32_t)kJT, j1 - tb));
     // every pending entry refers to the tile about to be overwritten
@@ -525,12 +564,16 @@ __device__ __forceinline__ void scan_run(Ctx<SYM, MODE, POLY> &x, uint32_t j0, u
       W.tile[1][lane] = (uint32_t)im.y;
       W.tile[2][lane] = (uint32_t)im.z;
       W.tile[3][lane] = (uint32_t)im.w;
+      if (INHOM) x.rho_t[lane] = nxt_ok ? nxt_rho : 0.0;
     }
     wave_sync();
     const uint32_t tn = tb + kJT;
     if (tn < j1) {
       nxt_ok = tn + (uint32_t)lane < j1;
-      if (nxt_ok) nxt = P[tn + lane];
+      if (nxt_ok) {
+        nxt = P[tn + lane];
+        if (INHOM) nxt_rho = x.rho[tn + lane];
+      }
     }
     // byte offsets, within the wave's LDS block, of this lane's centre and of
     // the tile's first entry
@@ -583,7 +626,7 @@ __device__ __forceinline__ void scan_run(Ctx<SYM, MODE, POLY> &x, uint32_t j0, u
   }
 }
 
-template <bool SYM, int MODE, bool POLY>
+template <bool SYM, int MODE, bool POLY, bool INHOM>
 __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const Geom &g = a.g;
@@ -601,9 +644,12 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
   uint32_t *T = S2hi + kMaxSteps;
   unsigned long long *evals_lds = (unsigned long long *)(T + kMaxSteps);
   uint32_t *grp_lds = (uint32_t *)(evals_lds + 1);
+  // INHOM: rho of the centres and of the tile entries, per wave
+  double *rho_lds = (double *)(evals_lds + 2);
 
   const int tid = threadIdx.x, lane = tid & 63, wv = (int)uni((uint32_t)tid >> 6);
   WaveLds &W = wl[wv];
+  double *rho_c = rho_lds + wv * 64, *rho_t = rho_lds + (kWaves + wv) * 64;
   for (int b = tid; b < NB; b += kPairThreads) hist[b] = 0;
   for (int b = tid; b < nc_words; b += kPairThreads) histc[b] = 0;
   if (tid < g.n_s) {
@@ -624,8 +670,12 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
         const unsigned long long w = hist[b];
         const size_t o = (size_t)set * NB + b;
         atomicAdd(&a.binC[o], c);
-        const unsigned long long old = atomicAdd(&a.binW[2 * o], w);
-        if (old + w < old) atomicAdd(&a.binW[2 * o + 1], 1ull);
+        if (INHOM) {
+          atomicAdd((double *)&a.binW[2 * o], __longlong_as_double((long long)w));
+        } else {
+          const unsigned long long old = atomicAdd(&a.binW[2 * o], w);
+          if (old + w < old) atomicAdd(&a.binW[2 * o + 1], 1ull);
+        }
         hist[b] = 0;
         if (wide)
           ((unsigned long long *)histc)[b] = 0;
@@ -672,6 +722,7 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
     W.cen[1][lane] = (uint32_t)me.y;
     W.cen[2][lane] = (uint32_t)me.z;
     W.cen[3][lane] = (uint32_t)me.w;
+    if (INHOM) rho_c[lane] = valid ? a.rho[mi] : 0.0;
     wave_sync();
     // the centres' row (t * ny + y) and the x-cells of the first and the last
     // centre (points are sorted by cell, x fastest)
@@ -694,7 +745,8 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
     const uint32_t cst = blocked ? 1u : 2u;
     const uint32_t nb_off = blocked ? (2u * (uint32_t)set + 1u) * g.n_cells : (uint32_t)set * g.n_cells;
     QState q = {0u, 0u, 0u, 0u};
-    Ctx<SYM, MODE, POLY> x{W, q, g, hist, histc, wide, S2lo, S2hi, T, lane, begin, 0u, a.P};
+    Ctx<SYM, MODE, POLY, INHOM> x{W,     q,     g,    hist, histc,  wide,  S2lo,  S2hi, T,
+                                  lane,  begin, 0u,   a.P,  a.rho,  rho_c, rho_t};
     unsigned long long ev = 0;
     int ridx = 0;  // index of the stencil row in visiting order
     for (int dt = SYM ? 0 : -g.rt; dt <= g.rt; ++dt) {
@@ -721,10 +773,10 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
           } else {
             ev += (unsigned long long)cnt * (j1 - j0) - cnt;
           }
-          scan_run<SYM, MODE, POLY, true>(x, j0, j1, me, tplus, thr, valid, vmask, mi, a.P);
+          scan_run<SYM, MODE, POLY, INHOM, true>(x, j0, j1, me, tplus, thr, valid, vmask, mi, a.P);
         } else {
           ev += (unsigned long long)cnt * (j1 - j0);
-          scan_run<SYM, MODE, POLY, false>(x, j0, j1, me, tplus, thr, valid, vmask, mi, a.P);
+          scan_run<SYM, MODE, POLY, INHOM, false>(x, j0, j1, me, tplus, thr, valid, vmask, mi, a.P);
         }
       }
     }
@@ -732,7 +784,7 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
       const uint32_t na = na_of(q);
       if (na) drain_oldest(x, na);
     }
-    if (q.nb) drain_b<MODE, POLY>(W, q, q.nb, lane, hist, g, a.P);
+    if (q.nb) drain_b<MODE, POLY, INHOM>(W, q, q.nb, lane, hist, g, a.P, a.rho);
     if (lane == 0) atomicAdd(evals_lds, ev);
     evals_total += ev;
   }
@@ -740,56 +792,67 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
   if (lane == 0 && evals_total) atomicAdd(a.n_eval, evals_total);
 }
 
-template <bool SYM, int MODE, bool POLY>
+template <bool SYM, int MODE, bool POLY, bool INHOM>
 hipError_t launch_t(const PairArgs &a, int grid, hipStream_t s) {
-  const int lds = pair_lds_bytes(a.g.n_s * a.g.n_t, a.wide_counts);
-  hipLaunchKernelGGL((k_pair<SYM, MODE, POLY>), dim3(grid), dim3(kPairThreads), lds, s, a);
+  const int lds = pair_lds_bytes(a.g.n_s * a.g.n_t, a.wide_counts, INHOM);
+  hipLaunchKernelGGL((k_pair<SYM, MODE, POLY, INHOM>), dim3(grid), dim3(kPairThreads), lds, s, a);
   return hipGetLastError();
 }
 
-template <bool SYM, int MODE, bool POLY>
+template <bool SYM, int MODE, bool POLY, bool INHOM>
 hipError_t occ_t(int lds, int *per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_pair<SYM, MODE, POLY>,
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_pair<SYM, MODE, POLY, INHOM>,
                                                       kPairThreads, lds);
 }
 
-template <bool SYM, bool POLY>
+// variants: rectangle, polygon (POLY), inhomogeneous on the rectangle (INHOM)
+template <bool SYM, bool POLY, bool INHOM>
 hipError_t occ_mode(int mode, int lds, int *per_cu) {
-  if (mode == kModePacked) return occ_t<SYM, kModePacked, POLY>(lds, per_cu);
-  if (mode == kModeU32) return occ_t<SYM, kModeU32, POLY>(lds, per_cu);
-  return occ_t<SYM, kModeWide, POLY>(lds, per_cu);
+  if (mode == kModePacked) return occ_t<SYM, kModePacked, POLY, INHOM>(lds, per_cu);
+  if (mode == kModeU32) return occ_t<SYM, kModeU32, POLY, INHOM>(lds, per_cu);
+  return occ_t<SYM, kModeWide, POLY, INHOM>(lds, per_cu);
 }
 
-template <bool SYM, bool POLY>
+template <bool SYM, bool POLY, bool INHOM>
 hipError_t launch_mode(const PairArgs &a, int grid, hipStream_t s) {
-  if (a.g.mode == kModePacked) return launch_t<SYM, kModePacked, POLY>(a, grid, s);
-  if (a.g.mode == kModeU32) return launch_t<SYM, kModeU32, POLY>(a, grid, s);
-  return launch_t<SYM, kModeWide, POLY>(a, grid, s);
+  if (a.g.mode == kModePacked) return launch_t<SYM, kModePacked, POLY, INHOM>(a, grid, s);
+  if (a.g.mode == kModeU32) return launch_t<SYM, kModeU32, POLY, INHOM>(a, grid, s);
+  return launch_t<SYM, kModeWide, POLY, INHOM>(a, grid, s);
+}
+
+template <bool SYM>
+hipError_t occ_var(int var, int mode, int lds, int *per_cu) {
+  if (var == 1) return occ_mode<SYM, true, false>(mode, lds, per_cu);
+  if (var == 2) return occ_mode<SYM, false, true>(mode, lds, per_cu);
+  return occ_mode<SYM, false, false>(mode, lds, per_cu);
+}
+
+template <bool SYM>
+hipError_t launch_var(int var, const PairArgs &a, int grid, hipStream_t s) {
+  if (var == 1) return launch_mode<SYM, true, false>(a, grid, s);
+  if (var == 2) return launch_mode<SYM, false, true>(a, grid, s);
+  return launch_mode<SYM, false, false>(a, grid, s);
 }
 
 }  // namespace
 
-int pair_lds_bytes(int n_bins, int wide_counts) {
+int pair_lds_bytes(int n_bins, int wide_counts, bool inhom) {
   const int nc_words = ((wide_counts ? 2 * n_bins : n_bins) + 3) & ~3;
-  return (int)sizeof(WaveLds) * kWaves + 8 * n_bins + 4 * nc_words + 4 * 3 * kMaxSteps + 16;
+  return (int)sizeof(WaveLds) * kWaves + 8 * n_bins + 4 * nc_words + 4 * 3 * kMaxSteps + 16 +
+         (inhom ? 2 * kWaves * 64 * 8 : 0);
 }
 
 bool pair_poly(const Geom &g) { return g.poly_n >= 3 && (g.edge & 1u); }
 
-hipError_t pair_occupancy(int n_bins, int wide_counts, int symmetric, int mode, bool poly,
+hipError_t pair_occupancy(int n_bins, int wide_counts, int symmetric, int mode, int var,
                           int *per_cu) {
-  const int lds = pair_lds_bytes(n_bins, wide_counts);
-  if (poly)
-    return symmetric ? occ_mode<true, true>(mode, lds, per_cu)
-                     : occ_mode<false, true>(mode, lds, per_cu);
-  return symmetric ? occ_mode<true, false>(mode, lds, per_cu)
-                   : occ_mode<false, false>(mode, lds, per_cu);
+  const int lds = pair_lds_bytes(n_bins, wide_counts, var == 2);
+  return symmetric ? occ_var<true>(var, mode, lds, per_cu) : occ_var<false>(var, mode, lds, per_cu);
 }
 
 hipError_t launch_pair(const PairArgs &a, int grid, hipStream_t s) {
-  if (pair_poly(a.g))
-    return a.symmetric ? launch_mode<true, true>(a, grid, s) : launch_mode<false, true>(a, grid, s);
-  return a.symmetric ? launch_mode<true, false>(a, grid, s) : launch_mode<false, false>(a, grid, s);
+  const int var = a.rho ? 2 : (pair_poly(a.g) ? 1 : 0);
+  return a.symmetric ? launch_var<true>(var, a, grid, s) : launch_var<false>(var, a, grid, s);
 }
 
 }  // namespace ripk

@@ -78,6 +78,7 @@ struct PairArgs {
   int row_items;               // items are chunks of x-rows (else of cells)
   int blocked;                 // two-type sets in blocked key order: centres from the
                                // type-1 block, neighbours from the type-2 block
+  const double *rho;           // inhomogeneous K: 1/lambda per sorted record (else null)
   int wide_counts;             // 64-bit LDS pair counts (sets of 2^23 points or more)
 };
 
@@ -85,12 +86,13 @@ struct PairArgs {
 
 // Buffer capacities of a plan: S sets, N = S*n_max points, SNC = S*n_cells
 // cells, work items, SNB = S*n_bins bins, NB = n_bins, P = n_max (one set),
-// V polygon vertices, NXY xy-cells with edge lists (0 without a polygon).
+// V polygon vertices, NXY xy-cells with edge lists (0 without a polygon), R
+// intensities (inhomogeneous plans).
 struct Caps {
-  int64_t S = 0, N = 0, SNC = 0, items = 0, SNB = 0, NB = 0, P = 0, V = 0, NXY = 0;
+  int64_t S = 0, N = 0, SNC = 0, items = 0, SNB = 0, NB = 0, P = 0, V = 0, NXY = 0, R = 0;
 };
 Caps caps_for(int64_t S, int64_t n_max, int64_t n_cells, int64_t n_bins, int64_t V = 0,
-              int64_t NXY = 0);
+              int64_t NXY = 0, int64_t R = 0);
 int64_t caps_bytes(const Caps &c);
 bool caps_fit(const Caps &have, const Caps &need);
 Caps caps_max(const Caps &a, const Caps &b);
@@ -141,6 +143,10 @@ hipError_t launch_cell_bounds(const uint32_t *keys, uint32_t n, uint32_t n_keys,
 hipError_t launch_gather(const uint32_t *vals, const uint32_t *keys, int mark, uint32_t n,
                          const int32_t *x, const int32_t *y, const int32_t *t, const Geom &g,
                          int32_t clamp_e, int4 *P, hipStream_t s);
+// rho[r] = 1 / lambda[vals[r]] for the sorted records; a value that is not
+// positive and finite sets bit 2 of *err
+hipError_t launch_gather_rho(const uint32_t *vals, uint32_t n, const double *lambda, double *rho,
+                             uint32_t *err, hipStream_t s);
 hipError_t launch_items(const uint32_t *cs, uint32_t n_sets, const Geom &g, bool row_items,
                         bool blocked, uint32_t split, uint32_t n_rows, uint32_t *chunks,
                         uint32_t *offs, uint32_t *set_base, Item *items, uint32_t *n_items,
@@ -148,17 +154,20 @@ hipError_t launch_items(const uint32_t *cs, uint32_t n_sets, const Geom &g, bool
 hipError_t launch_fill_u64(unsigned long long *p, size_t n, unsigned long long v,
                            hipStream_t s);
 hipError_t launch_pair(const PairArgs &a, int grid, hipStream_t s);
-int pair_lds_bytes(int n_bins, int wide_counts);
+int pair_lds_bytes(int n_bins, int wide_counts, bool inhom = false);
 // the pair kernel takes the polygon weight path (a polygon and spatial correction)
 bool pair_poly(const Geom &g);
-hipError_t pair_occupancy(int n_bins, int wide_counts, int symmetric, int mode, bool poly,
+// kernel variant: 0 rectangle, 1 polygon, 2 inhomogeneous (rectangle)
+hipError_t pair_occupancy(int n_bins, int wide_counts, int symmetric, int mode, int var,
                           int *per_cu);
 // 64-bit LDS pair counts are needed from this many points per set on
 constexpr int64_t kWideCountPoints = 1 << 23;
+// fp: the weight bins hold FP64 sums (inhomogeneous K) instead of 128-bit
+// fixed point
 hipError_t launch_finalize(unsigned long long *binC, unsigned long long *binW,
                            uint32_t n_sets, int n_s, int n_t, double s_max, double t_max,
                            double AD, double N, unsigned long long *C, double *W, double *K,
-                           double *L, unsigned long long *n_in, hipStream_t s);
+                           double *L, unsigned long long *n_in, hipStream_t s, bool fp = false);
 hipError_t launch_envelope(const double *K, const double *L, uint32_t m, int n_bins,
                            const double *L_obs, double *env, hipStream_t s);
 

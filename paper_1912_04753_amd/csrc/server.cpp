@@ -51,6 +51,7 @@ struct Request {
   uint64_t seed = 0;
   std::vector<int32_t> xyt;  // x | y | t, n each
   std::vector<int32_t> poly; // the descriptor's polygon (desc.poly points here)
+  std::vector<double> lam;   // intensities (inhomogeneous plans)
   // results
   bool done = false;
   ripk_status status = RIPK_PENDING;
@@ -159,7 +160,8 @@ ripk_status run_request(Slot &s, Request *r) {
   r->W.assign(NB, 0.0);
   r->K.assign(NB, 0.0);
   r->L.assign(NB, 0.0);
-  ripk_points pts{s.stage, s.stage + n, s.stage + 2 * n, n, r->n_centres, 0};
+  ripk_points pts{s.stage, s.stage + n, s.stage + 2 * n, n, r->n_centres, 0,
+                  r->lam.empty() ? nullptr : r->lam.data()};
   ripk_K_out ko{r->C.data(), r->W.data(), r->K.data(), r->L.data()};
   st = ripk_compute_K(s.plan, &pts, s.stream, &ko);
   if (st != RIPK_OK) return st;
@@ -368,6 +370,7 @@ ripk_status ripk_submit(ripk_server_t sv, const ripk_request *req, uint64_t *tic
   std::copy(p.x, p.x + p.n, r->xyt.begin());
   std::copy(p.y, p.y + p.n, r->xyt.begin() + p.n);
   std::copy(p.t, p.t + p.n, r->xyt.begin() + 2 * p.n);
+  if (p.lambda) r->lam.assign(p.lambda, p.lambda + p.n);
   std::lock_guard<std::mutex> lk(sv->mu);
   if (sv->stop) {
     delete r;

@@ -41,6 +41,7 @@ RIPK_PLAN_WIDE_COUNTS = 4
 RIPK_PLAN_AUTOTUNE = 8
 RIPK_PLAN_GRAPH = 16
 RIPK_PLAN_CROSS = 32
+RIPK_PLAN_INHOM = 64
 RIPK_REQ_KEEP_SIMS = 1
 
 _i64, _i32, _u32, _u64, _f64 = (ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32,
@@ -66,7 +67,7 @@ class PlanInfo(ctypes.Structure):
 
 class Points(ctypes.Structure):
     _fields_ = [("x", _P(_i32)), ("y", _P(_i32)), ("t", _P(_i32)), ("n", _i64),
-                ("n_centres", _i64), ("on_device", _i32)]
+                ("n_centres", _i64), ("on_device", _i32), ("lambda", _P(_f64))]
 
 
 class KOut(ctypes.Structure):
@@ -273,19 +274,36 @@ def _coord_ptr(a, n):
     return arr.ctypes.data_as(_P(_i32)), False, arr
 
 
+def _lambda_ptr(a, n):
+    """Intensities: contiguous float64, host or device (None: no array)."""
+    if a is None:
+        return _P(_f64)(), None, None
+    if _is_torch(a):
+        import torch
+        if a.dtype != torch.float64 or not a.is_contiguous() or a.numel() != n:
+            raise ValueError("lambda must be a contiguous float64 tensor of length n")
+        return ctypes.cast(ctypes.c_void_p(a.data_ptr()), _P(_f64)), bool(a.is_cuda), a
+    arr = np.ascontiguousarray(a, dtype=np.float64)
+    if arr.shape != (n,):
+        raise ValueError("lambda must be 1-D of length n")
+    return arr.ctypes.data_as(_P(_f64)), False, arr
+
+
 def _out(shape, dtype):
     return np.zeros(shape, dtype)
 
 
-def ripk_compute_K(plan, x, y, t, n_centres=0, stream=None):
-    """K, L of one point set (Eq. 2-4).  Returns numpy arrays C, W, K, L of shape (n_s, n_t)."""
+def ripk_compute_K(plan, x, y, t, n_centres=0, stream=None, lam=None):
+    """K, L of one point set (Eq. 2-4).  Returns numpy arrays C, W, K, L of shape (n_s, n_t).
+    ``lam``: intensity per point (float64), for plans made with RIPK_PLAN_INHOM."""
     n = len(x)
     px, dx, kx = _coord_ptr(x, n)
     py, dy, ky = _coord_ptr(y, n)
     pt, dt, kt = _coord_ptr(t, n)
-    if not (dx == dy == dt):
-        raise ValueError("coordinates must all be on the host or all on the device")
-    pts = Points(px, py, pt, n, int(n_centres), 1 if dx else 0)
+    pl, dl, kl = _lambda_ptr(lam, n)
+    if not (dx == dy == dt) or (lam is not None and dl != dx):
+        raise ValueError("coordinates (and lambda) must all be on the host or all on the device")
+    pts = Points(px, py, pt, n, int(n_centres), 1 if dx else 0, pl)
     shp = plan.shape
     C = _out(shp, np.uint64)
     W = _out(shp, np.float64)
@@ -296,7 +314,7 @@ def ripk_compute_K(plan, x, y, t, n_centres=0, stream=None):
     st = _stream_for([x, y, t], stream)
     _check(lib().ripk_compute_K(plan.handle, ctypes.byref(pts), st, ctypes.byref(out)),
            "ripk_compute_K")
-    del kx, ky, kt
+    del kx, ky, kt, kl
     return {"C": C, "W": W, "K": K, "L": L}
 
 
@@ -364,17 +382,18 @@ def ripk_server_destroy(server):
     server.destroy()
 
 
-def ripk_submit(server, desc, x, y, t, m=0, seed=0, n_centres=0, keep_sims=False):
+def ripk_submit(server, desc, x, y, t, m=0, seed=0, n_centres=0, keep_sims=False, lam=None):
     """Queue a request (host points, copied before return); returns its ticket."""
     n = len(x)
     px, _, kx = _coord_ptr(np.asarray(x), n)
     py, _, ky = _coord_ptr(np.asarray(y), n)
     pt, _, kt = _coord_ptr(np.asarray(t), n)
-    req = Request(desc, Points(px, py, pt, n, int(n_centres), 0), int(m),
+    pl, _, kl = _lambda_ptr(None if lam is None else np.asarray(lam), n)
+    req = Request(desc, Points(px, py, pt, n, int(n_centres), 0, pl), int(m),
                   RIPK_REQ_KEEP_SIMS if keep_sims else 0, int(seed) & (2**64 - 1))
     ticket = _u64()
     _check(lib().ripk_submit(server.handle, ctypes.byref(req), ctypes.byref(ticket)), "ripk_submit")
-    del kx, ky, kt
+    del kx, ky, kt, kl
     server.pending[ticket.value] = (desc.n_s, desc.n_t, int(m), bool(keep_sims))
     return ticket.value
 

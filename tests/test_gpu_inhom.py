@@ -1,0 +1,151 @@
+"""GPU parity of the inhomogeneous K estimator against the FP64 oracle.
+
+Each pair weighs 1/(omega v lambda_i lambda_j) and K_I = W/(A*D).  Counts bit for
+bit; W, K and L within the tolerances of ``tests/parity.py`` (the FP32 weights
+times FP64 reciprocal intensities, summed in FP64 on the device).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1912_04753_amd import ripk, workloads
+from parity import compare
+
+pytestmark = pytest.mark.gpu
+DAY = workloads.DAY
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+def _gpu(args, x, y, t, lam, flags=0, edge=3, dev=False):
+    plan = ripk.ripk_plan(ripk.make_desc(*args, n_max=len(x), edge=edge,
+                                         flags=flags | ripk.RIPK_PLAN_INHOM))
+    try:
+        if dev:
+            import torch
+            xs, ys, ts = (torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (x, y, t))
+            r = ripk.ripk_compute_K(plan, xs, ys, ts, lam=torch.from_numpy(lam).cuda())
+        else:
+            r = ripk.ripk_compute_K(plan, x, y, t, lam=lam)
+        r["stats"] = ripk.ripk_plan_stats(plan)
+        r["info"] = ripk.ripk_plan_get_info(plan)
+        return r
+    finally:
+        plan.destroy()
+
+
+def _density_lambda(x, y, t, win, sigma):
+    """A smooth intensity: n/(A*D) times a Gaussian-bump modulation in space."""
+    x0, y0, x1, y1, t0, t1 = win
+    AD = (x1 - x0) * (y1 - y0) * float(t1 - t0)
+    cx, cy = 0.5 * (x0 + x1), 0.5 * (y0 + y1)
+    f = 0.3 + 2.0 * np.exp(-((x - cx) ** 2 + (y - cy) ** 2) / (2 * sigma ** 2))
+    return (len(x) / AD) * f / f.mean()
+
+
+CASES = {
+    # name: (window, s_max, t_max, n_s, n_t, n, clustered, edge, flags, device)
+    "uniform": ((0, 0, 10_000, 10_000, 0, 365 * DAY), 1_000, 30 * DAY, 10, 10, 4_000, False, 3, 0, False),
+    "clustered": ((0, 0, 20_000, 15_000, 0, 200 * DAY), 2_000, 20 * DAY, 16, 12, 8_000, True, 3, 0, False),
+    "no_correction": ((0, 0, 10_000, 10_000, 0, 365 * DAY), 1_000, 30 * DAY, 10, 10, 3_000, False, 0, 0, False),
+    "temporal_only": ((0, 0, 10_000, 10_000, 0, 365 * DAY), 1_000, 30 * DAY, 7, 9, 3_000, True, 2, 0, False),
+    "ordered": ((0, 0, 10_000, 10_000, 0, 365 * DAY), 1_000, 30 * DAY, 10, 10, 3_000, True, 3,
+                ripk.RIPK_PLAN_ORDERED, False),
+    "u32_device": ((0, 0, 100_000, 80_000, 0, 400 * DAY), 10_000, 40 * DAY, 12, 10, 5_000, True, 3, 0, True),
+}
+
+
+def _points(name, n, win, clustered):
+    rng = np.random.default_rng(len(name) * 11 + n)
+    x0, y0, x1, y1, t0, t1 = win
+    if clustered:
+        x, y, t = workloads.thomas_points(rng, n, win, 12, (x1 - x0) / 30, (t1 - t0) / 30)
+    else:
+        x, y, t = workloads.uniform_points(rng, n, win)
+    return x, y, t
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_inhom_k_matches_oracle(name):
+    win, s_max, t_max, n_s, n_t, n, clustered, edge, flags, dev = CASES[name]
+    x, y, t = _points(name, n, win, clustered)
+    lam = _density_lambda(x, y, t, win, (win[2] - win[0]) / 5)
+    say("inhom", name, "n=%d" % n)
+    args = (win, s_max, t_max, n_s, n_t)
+    g = _gpu(args, x, y, t, lam, flags=flags, edge=edge, dev=dev)
+    r = oracle.estimate_inhom(oracle.desc(*args, edge=edge), x, y, t, lam)
+    compare(g, r, s_max, t_max, n_s, n_t, where="inhom " + name)
+    if name == "u32_device":
+        assert g["info"]["dist_mode"] == 1
+
+
+def test_inhom_constant_intensity_is_the_n2_estimate_at_full_size():
+    """The 100k workload with lambda = n/(A*D): the inhomogeneous plan equals the
+    homogeneous plan with N = n^2 (counts exactly, K to FP64 rounding); two runs
+    agree on counts and to rounding on K."""
+    c = workloads.workload("uniform-100k-99csr")
+    x, y, t = workloads.make_points(c)
+    n = len(x)
+    args = (c["window"], c["s_max"], c["t_max"], c["n_s"], c["n_t"])
+    AD = 20_000.0 * 20_000.0 * (180 * DAY)
+    say("inhom constant 100k")
+    g = _gpu(args, x, y, t, np.full(n, n / AD))
+    g2 = _gpu(args, x, y, t, np.full(n, n / AD))
+    plan = ripk.ripk_plan(ripk.make_desc(*args, n_max=n, norm=ripk.RIPK_NORM_N2))
+    try:
+        h = ripk.ripk_compute_K(plan, x, y, t)
+    finally:
+        plan.destroy()
+    assert np.array_equal(g["C"], h["C"]) and np.array_equal(g2["C"], g["C"])
+    np.testing.assert_allclose(g["K"], h["K"], rtol=1e-12, atol=0)
+    np.testing.assert_allclose(g2["K"], g["K"], rtol=1e-12, atol=0)
+
+
+def test_inhom_errors():
+    win = (0, 0, 5_000, 5_000, 0, 100 * DAY)
+    args = (win, 800, 20 * DAY, 8, 8)
+    x, y, t = workloads.uniform_points(np.random.default_rng(3), 500, win)
+    lam = np.full(500, 1e-9)
+    plan = ripk.ripk_plan(ripk.make_desc(*args, n_max=500, m_max=2, flags=ripk.RIPK_PLAN_INHOM))
+    try:
+        with pytest.raises(ripk.RipkError) as e:
+            ripk.ripk_compute_K(plan, x, y, t)                   # no intensities
+        assert e.value.status == ripk.RIPK_EINVAL
+        for bad in (0.0, -1e-9, np.nan, np.inf):
+            b = lam.copy()
+            b[17] = bad
+            with pytest.raises(ripk.RipkError) as e:
+                ripk.ripk_compute_K(plan, x, y, t, lam=b)
+            assert e.value.status == ripk.RIPK_ERANGE, bad
+        ripk.ripk_compute_K(plan, x, y, t, lam=lam)
+        with pytest.raises(ripk.RipkError) as e:                 # no simulations
+            ripk.ripk_simulate_envelope(plan, 500, 2, 1)
+        assert e.value.status == ripk.RIPK_EINVAL
+    finally:
+        plan.destroy()
+    for kw in (dict(flags=ripk.RIPK_PLAN_INHOM | ripk.RIPK_PLAN_CROSS),
+               dict(flags=ripk.RIPK_PLAN_INHOM, poly=[(0, 0), (5000, 0), (0, 5000)])):
+        with pytest.raises(ripk.RipkError) as e:
+            ripk.ripk_plan_check(ripk.make_desc(*args, n_max=500, **kw))
+        assert e.value.status == ripk.RIPK_EINVAL
+    say("inhom errors")
+
+
+def test_inhom_request_through_server():
+    win = (0, 0, 10_000, 10_000, 0, 365 * DAY)
+    args = (win, 1_000, 30 * DAY, 10, 10)
+    x, y, t = _points("server", 3_000, win, True)
+    lam = _density_lambda(x, y, t, win, 2_000)
+    desc = ripk.make_desc(*args, n_max=3_000, flags=ripk.RIPK_PLAN_INHOM)
+    direct = _gpu(args, x, y, t, lam)
+    srv = ripk.ripk_server_create(slots=2)
+    try:
+        tk = ripk.ripk_submit(srv, desc, x, y, t, lam=lam)
+        res = ripk.ripk_poll(srv, tk, timeout_ms=-1)
+    finally:
+        ripk.ripk_server_destroy(srv)
+    say("inhom server")
+    assert np.array_equal(res["C"], direct["C"])
+    np.testing.assert_allclose(res["K"], direct["K"], rtol=1e-12, atol=0)
