@@ -365,6 +365,27 @@ def main():
                        "(46% of the 20 km x 20 km window), 180 d, 25x15 grid to 2 km/30 d, "
                        "observed K + 99 CSR simulations"}
     pplan.destroy()
+    # inhomogeneous K: the same 100k points with an intensity per point (a smooth
+    # bump about the window centre, mean n/(A*D)); observed K_I only
+    AD = (cfg["window"][2] - cfg["window"][0]) * (cfg["window"][3] - cfg["window"][1]) * \
+        float(cfg["window"][5] - cfg["window"][4])
+    fx = 0.3 + 2.0 * np.exp(-((x - 10_000.0) ** 2 + (y - 10_000.0) ** 2) / (2 * 4_000.0 ** 2))
+    dlam = torch.from_numpy((n / AD) * fx / fx.mean()).cuda()
+    iplan = ripk.ripk_plan(ripk.make_desc(cfg["window"], cfg["s_max"], cfg["t_max"], cfg["n_s"],
+                                          cfg["n_t"], n_max=n,
+                                          flags=ripk.RIPK_PLAN_INHOM | ripk.RIPK_PLAN_AUTOTUNE))
+    for _ in range(2):
+        ripk.ripk_compute_K(iplan, dx, dy, dt, stream=stream, lam=dlam)
+    torch.cuda.synchronize()
+    t_i = time.perf_counter()
+    for _ in range(5):
+        ripk.ripk_compute_K(iplan, dx, dy, dt, stream=stream, lam=dlam)
+    torch.cuda.synchronize()
+    i_ms = 1e3 * (time.perf_counter() - t_i) / 5
+    inhom = {"ms_per_call": round(i_ms, 3),
+             "pair_tests_per_s_G": round(ripk.ripk_plan_stats(iplan)["n_in"] / (i_ms * 1e-3) / 1e9, 3),
+             "note": "observed K_I of the 100k set, intensity per point (device), autotuned cells"}
+    iplan.destroy()
     plan.destroy()
 
     ms = 1e3 * t_total / args.steps
@@ -403,6 +424,7 @@ def main():
         "resampled_simulations": resampled,
         "cross_k": cross,
         "polygon": polygon,
+        "inhomogeneous_k": inhom,
         "cold_ms": {"plan": round(plan_ms, 2),
                     "first_step_with_tuning": round(first_step_ms, 2) if not args.no_autotune else None},
         "observed_host_input": {"ms": round(host_obs_ms, 3),
