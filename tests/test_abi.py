@@ -126,3 +126,63 @@ def test_server_structs_and_argument_checks():
     with pytest.raises(ripk.RipkError) as e:
         ripk.ripk_server_create(hbm_budget_bytes=0)
     assert e.value.status == ripk.RIPK_EINVAL
+
+
+def _simple_brute(P):
+    """Independent check that a closed polygon is simple: non-adjacent edges do
+    not meet, adjacent edges share only their common vertex."""
+    n = len(P)
+
+    def orient(a, b, c):
+        v = (b[0] - a[0]) * (c[1] - a[1]) - (b[1] - a[1]) * (c[0] - a[0])
+        return (v > 0) - (v < 0)
+
+    def on_seg(a, b, c):
+        return min(a[0], b[0]) <= c[0] <= max(a[0], b[0]) and min(a[1], b[1]) <= c[1] <= max(a[1], b[1])
+
+    def meet(a, b, c, d):
+        o1, o2, o3, o4 = orient(a, b, c), orient(a, b, d), orient(c, d, a), orient(c, d, b)
+        if o1 * o2 < 0 and o3 * o4 < 0:
+            return True
+        return ((o1 == 0 and on_seg(a, b, c)) or (o2 == 0 and on_seg(a, b, d)) or
+                (o3 == 0 and on_seg(c, d, a)) or (o4 == 0 and on_seg(c, d, b)))
+
+    E = [(P[k], P[(k + 1) % n]) for k in range(n)]
+    if any(a == b for a, b in E):
+        return False
+    for i in range(n):
+        for j in range(i + 1, n):
+            a, b = E[i]
+            c, d = E[j]
+            if j == i + 1 or (j + 1) % n == i:
+                # shared vertex s; the other ends must not fold back onto it
+                s, p, q = (b, a, d) if j == i + 1 else (a, b, c)
+                dot = (p[0] - s[0]) * (q[0] - s[0]) + (p[1] - s[1]) * (q[1] - s[1])
+                if orient(s, p, q) == 0 and dot > 0:
+                    return False
+                continue
+            if meet(a, b, c, d):
+                return False
+    return True
+
+
+def test_polygon_validation_matches_brute_force():
+    """Random polygons on a coarse lattice (many self-intersecting, touching or
+    degenerate): the plan accepts exactly the simple ones with enough area."""
+    rng = np.random.default_rng(9)
+    win = (0, 0, 1000, 1000, 0, 100)
+    seen = {True: 0, False: 0}
+    for trial in range(400):
+        k = int(rng.integers(3, 9))
+        P = [tuple(int(v) for v in rng.integers(0, 11, 2) * 100) for _ in range(k)]
+        area2 = abs(sum(P[i][0] * P[(i + 1) % k][1] - P[(i + 1) % k][0] * P[i][1] for i in range(k)))
+        want = _simple_brute(P) and area2 * 512 >= 1000 * 1000
+        try:
+            ripk.ripk_plan_check(ripk.make_desc(win, 100, 10, 2, 2, n_max=10, poly=P))
+            got = True
+        except ripk.RipkError as e:
+            assert e.status == ripk.RIPK_EINVAL
+            got = False
+        assert got == want, (trial, P)
+        seen[want] += 1
+    assert seen[True] > 30 and seen[False] > 30
