@@ -776,7 +776,8 @@ ripk_status bind_geometry(ripk_plan_s *p, const ripk_plan_desc *desc, hipStream_
   if (desc->device != p->device) return fail(RIPK_EINVAL, "descriptor device differs from the plan's");
   if (!caps_fit(p->caps, L.caps)) return fail(RIPK_E2BIG, "descriptor exceeds the plan's capacity");
   const int lds = pair_lds_bytes(
-      L.info.n_bins, desc->n_max >= kWideCountPoints || (desc->flags & RIPK_PLAN_WIDE_COUNTS));
+      L.info.n_bins, desc->n_max >= kWideCountPoints || (desc->flags & RIPK_PLAN_WIDE_COUNTS),
+      (desc->flags & RIPK_PLAN_INHOM) != 0);
   if ((size_t)lds > p->lds_max)
     return fail(RIPK_EINVAL, "grid of %d bins needs %d B of LDS per workgroup, device has %zu",
                 L.info.n_bins, lds, p->lds_max);
