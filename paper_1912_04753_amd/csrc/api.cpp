@@ -506,11 +506,9 @@ ripk_status enqueue_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_cent
   HIPCHK(radix_sort(p->keys[0], p->vals[0], p->keys[1], p->vals[1], N, ceil_log2(n_keys),
                     p->sort_temp, st, &alt));
   HIPCHK(launch_cell_bounds(p->keys[alt], N, (uint32_t)n_keys, p->cs, st));
-  // cross K sets are sorted in blocked order (each type one cell-sorted block):
-  // centres come from the type-1 block and neighbour runs from the type-2
-  // block, so no record needs the no-neighbour mark
-  HIPCHK(launch_gather(p->vals[alt], p->keys[alt], 0, N, x, y, t, g, p->lay.clamp_e,
-                       p->P, st));
+  // (cross K sets are sorted in blocked order, each type one cell-sorted block:
+  // centres come from the type-1 block and neighbour runs from the type-2 block)
+  HIPCHK(launch_gather(p->vals[alt], N, x, y, t, g, p->lay.clamp_e, p->P, st));
   const bool inhom = (p->desc.flags & RIPK_PLAN_INHOM) != 0 && !simulate;
   if (inhom) HIPCHK(launch_gather_rho(p->vals[alt], N, p->cur_lam, p->rho, err, st));
   // row items need rows without halo entries: every point a centre, or the

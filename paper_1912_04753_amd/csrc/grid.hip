@@ -375,8 +375,7 @@ __global__ void k_cell_bounds(const uint32_t *__restrict__ keys, uint32_t n, uin
 
 // Sorted point records: window-relative coordinates (all >= 0) and the distance
 // to the nearest side clamped to s_max (a circle no larger than that is whole).
-__global__ void k_gather(const uint32_t *__restrict__ vals, const uint32_t *__restrict__ keys,
-                         int mark, uint32_t n,
+__global__ void k_gather(const uint32_t *__restrict__ vals, uint32_t n,
                          const int32_t *__restrict__ x, const int32_t *__restrict__ y,
                          const int32_t *__restrict__ t, Geom g, int32_t clamp_e,
                          int4 *__restrict__ P) {
@@ -391,7 +390,6 @@ __global__ void k_gather(const uint32_t *__restrict__ vals, const uint32_t *__re
     e = min(min(X, g.x1 - g.x0 - X), min(Y, g.y1 - g.y0 - Y));
     e = min(max(e, 0), clamp_e);
   }
-  if (mark && !(keys[r] & 1u)) e = (int32_t)((uint32_t)e | 0x80000000u);
   P[r] = make_int4(X, Y, T, e);
 }
 
@@ -631,12 +629,12 @@ hipError_t launch_cell_bounds(const uint32_t *keys, uint32_t n, uint32_t n_keys,
   return hipGetLastError();
 }
 
-hipError_t launch_gather(const uint32_t *vals, const uint32_t *keys, int mark, uint32_t n,
-                         const int32_t *x, const int32_t *y, const int32_t *t, const Geom &g,
-                         int32_t clamp_e, int4 *P, hipStream_t s) {
+hipError_t launch_gather(const uint32_t *vals, uint32_t n, const int32_t *x, const int32_t *y,
+                         const int32_t *t, const Geom &g, int32_t clamp_e, int4 *P,
+                         hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gather, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, s, vals, keys,
-                     mark, n, x, y, t, g, clamp_e, P);
+  hipLaunchKernelGGL(k_gather, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, s, vals, n, x,
+                     y, t, g, clamp_e, P);
   return hipGetLastError();
 }
 

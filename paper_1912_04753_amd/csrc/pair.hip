@@ -455,22 +455,19 @@ __device__ __forceinline__ void drain_a(WaveLds &W, QState &q,
 
 // LDS image of a sorted point (see WaveLds).  Without spatial correction the
 // interior bound (min(ex,ey)^2, or the side distance) is set to 2^32 - 1 so
-// that no pair takes the boundary path.  A record marked as no neighbour (bit
-// 31 of its edge distance: a type-1 point of a cross-K set) takes the padding
-// time, so it fails every time test; centres clear the mark before this.
-// (POLY: the interior bound is the record's distance to the polygon.)
+// that no pair takes the boundary path.  (POLY: the interior bound is the
+// record's distance to the polygon.)
 template <int MODE, bool POLY>
 __device__ __forceinline__ int4 image(const int4 p, const Geom &g) {
   const bool iso = (g.edge & 1u) != 0;
-  const int tm = p.w < 0 ? (int)kFarTime : p.z;
   if (MODE == kModePacked) {
     const uint32_t ex = min((uint32_t)min(p.x, g.x1 - g.x0 - p.x), kClampE);
     const uint32_t ey = min((uint32_t)min(p.y, g.y1 - g.y0 - p.y), kClampE);
-    const uint32_t e = POLY ? (uint32_t)(p.w & 0x7FFFFFFF) : min(ex, ey);
-    return make_int4((int)(((uint32_t)p.x & 0xFFFFu) | ((uint32_t)p.y << 16)), tm,
+    const uint32_t e = POLY ? (uint32_t)p.w : min(ex, ey);
+    return make_int4((int)(((uint32_t)p.x & 0xFFFFu) | ((uint32_t)p.y << 16)), p.z,
                      (int)(ex | (ey << 16)), iso ? (int)(e * e) : -1);
   }
-  return make_int4(p.x, p.y, tm, iso ? p.w : -1);
+  return make_int4(p.x, p.y, p.z, iso ? p.w : -1);
 }
 
 template <int MODE>
@@ -713,8 +710,7 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
     const bool valid = (uint32_t)lane < cnt;
     const unsigned long long vmask = __builtin_amdgcn_ballot_w64(valid);
     const uint32_t mi = begin + (uint32_t)lane;
-    int4 raw = valid ? a.P[mi] : make_int4(0, 0, 0, 0);
-    raw.w &= 0x7FFFFFFF;  // a centre is always evaluated (cross K: its neighbour mark)
+    const int4 raw = valid ? a.P[mi] : make_int4(0, 0, 0, 0);
     const int4 me = image<MODE, POLY>(raw, g);
     const uint32_t tplus = (uint32_t)(MODE == kModePacked ? me.y : me.z) + g.tmax;
     const int thr = valid ? (int)g.s2max : -1;

@@ -137,12 +137,10 @@ hipError_t exclusive_scan(const uint32_t *in, uint32_t *out, uint32_t n, void *t
                           hipStream_t s);
 hipError_t launch_cell_bounds(const uint32_t *keys, uint32_t n, uint32_t n_keys,
                               uint32_t *cs, hipStream_t s);
-// Sorted records {x, y, t, edge distance}; with `mark`, records whose key is a
-// centre slot (halo bit clear) get bit 31 of the edge distance set: in a
-// cross-K plan they are type 1 and no neighbour of anything.
-hipError_t launch_gather(const uint32_t *vals, const uint32_t *keys, int mark, uint32_t n,
-                         const int32_t *x, const int32_t *y, const int32_t *t, const Geom &g,
-                         int32_t clamp_e, int4 *P, hipStream_t s);
+// Sorted records {x, y, t, distance to the study area's boundary, clamped to s_max}
+hipError_t launch_gather(const uint32_t *vals, uint32_t n, const int32_t *x, const int32_t *y,
+                         const int32_t *t, const Geom &g, int32_t clamp_e, int4 *P,
+                         hipStream_t s);
 // rho[r] = 1 / lambda[vals[r]] for the sorted records; a value that is not
 // positive and finite sets bit 2 of *err
 hipError_t launch_gather_rho(const uint32_t *vals, uint32_t n, const double *lambda, double *rho,
