@@ -76,20 +76,20 @@ __device__ __forceinline__ int32_t poly_edist(const Geom &g, int px, int py, int
   return (int32_t)fmax(floor(sqrt(best * (1.0 - 1e-12))) - 1.0, 0.0);
 }
 
-// Angle of (x, y) in [0, 2 pi), FP64, within a few ulp: octant reduction to
-// z = min/max in [0, 1], then atan z = pi/6 + atan((sqrt(3) z - 1)/(z + sqrt(3)))
-// for z > tan(pi/12), and the Taylor series of atan to z^25 on
-// [0, tan(pi/12)] (remainder below 2e-16 there).  Light on registers, unlike a
-// general-purpose atan2.
+// Angle of (x, y) in [0, 2 pi), FP64, within a few ulp (depends only on the
+// direction of (x, y)): octant reduction to z = min/max in [0, 1], then
+// atan z = pi/6 + atan((sqrt(3) z - 1)/(z + sqrt(3))) for z > tan(pi/12) (one
+// quotient of min and max either way), and the Taylor series of atan to z^25
+// on [0, tan(pi/12)] (remainder below 2e-16 there).  Light on registers,
+// unlike a general-purpose atan2.
 __device__ __forceinline__ double poly_angle(double x, double y) {
   const double ax = fabs(x), ay = fabs(y);
   const double lo = fmin(ax, ay), hi = fmax(ax, ay);
   if (hi == 0.0) return 0.0;
-  double z = lo / hi, base = 0.0;
-  if (z > 0.26794919243112270) {  // tan(pi/12)
-    z = (z * 1.7320508075688772 - 1.0) / (z + 1.7320508075688772);
-    base = 0.52359877559829887;  // pi/6
-  }
+  const bool red = lo > 0.26794919243112270 * hi;  // tan(pi/12)
+  const double z = red ? (lo * 1.7320508075688772 - hi) / (lo + hi * 1.7320508075688772)
+                       : lo / hi;
+  const double base = red ? 0.52359877559829887 : 0.0;  // pi/6
   const double w = z * z;
   double p = 1.0 / 25.0;
   p = fma(p, w, -1.0 / 23.0);
@@ -168,15 +168,17 @@ __device__ __forceinline__ double poly_omega(const Geom &g, int px, int py, uint
     }
     if (disc > 0.0) {
       const double sq = sqrt(disc);
+      // the crossing A + s E with s = (-ae -+ sq)/ee, scaled by ee > 0 (the
+      // angle depends on the direction only)
       // smaller root strictly inside the edge: an exit (counter-clockwise)
       if (ae < 0.0 && aa > d2 && (ae + ee > 0.0 || bb < d2)) {
-        const double sm = (-ae - sq) / ee;
-        S += sg * poly_angle(fma(sm, ex, ax), fma(sm, ey, ay));
+        const double sm = -ae - sq;
+        S += sg * poly_angle(fma(sm, ex, ee * ax), fma(sm, ey, ee * ay));
       }
       // larger root strictly inside the edge: an entry
       if ((ae < 0.0 || aa < d2) && ae + ee > 0.0 && bb > d2) {
-        const double sp = (-ae + sq) / ee;
-        S -= sg * poly_angle(fma(sp, ex, ax), fma(sp, ey, ay));
+        const double sp = -ae + sq;
+        S -= sg * poly_angle(fma(sp, ex, ee * ax), fma(sp, ey, ee * ay));
       }
     }
   });

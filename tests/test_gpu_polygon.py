@@ -190,3 +190,36 @@ def test_polygon_request_through_server():
     say("polygon server")
     assert np.array_equal(res["C"], obs["C"]) and np.array_equal(res["W"], obs["W"])
     assert np.array_equal(res["L_hi"], env["L_hi"])
+
+
+def test_polygon_with_cross_k_and_resampled_simulations():
+    """Extensions combined: cross K inside the 85-vertex boundary, and
+    permutation / bootstrap simulations of a polygon set, against the oracle."""
+    c, star = _star()
+    args = (c["window"], 1500, 20 * DAY, 10, 6)
+    n, n1, m, seed = 2500, 900, 2, 44
+    x, y, t = workloads.polygon_points(np.random.default_rng(69), n, c["window"], star)
+    d = oracle.desc(*args, poly=star)
+    say("polygon cross")
+    plan = ripk.ripk_plan(ripk.make_desc(*args, n_max=n, m_max=m, poly=star,
+                                         flags=ripk.RIPK_PLAN_CROSS))
+    try:
+        g = ripk.ripk_compute_K(plan, x, y, t, n_centres=n1)
+        gs = ripk.ripk_simulate_envelope(plan, n, m, seed, per_sim=True)
+    finally:
+        plan.destroy()
+    compare(g, oracle.estimate_cross(d, x, y, t, n1), *args[1:], where="polygon cross")
+    ref = oracle.envelope_cross(d, x, y, t, n1, m, seed, oracle.SIM_CSR)
+    assert np.array_equal(gs["C_sims"], ref["C_sims"].astype(np.uint64))
+    np.testing.assert_allclose(gs["K_sims"], ref["K_sims"], rtol=1e-6, atol=0)
+    for method in (ripk.RIPK_SIM_PERMUTE, ripk.RIPK_SIM_BOOTSTRAP):
+        say("polygon resampled", method)
+        plan = ripk.ripk_plan(ripk.make_desc(*args, n_max=n, m_max=m, poly=star, sim_method=method))
+        try:
+            ripk.ripk_compute_K(plan, x, y, t)
+            gs = ripk.ripk_simulate_envelope(plan, n, m, seed, per_sim=True)
+        finally:
+            plan.destroy()
+        ref = oracle.envelope_resampled(d, x, y, t, m, seed, method)
+        assert np.array_equal(gs["C_sims"], ref["C_sims"].astype(np.uint64))
+        np.testing.assert_allclose(gs["K_sims"], ref["K_sims"], rtol=1e-6, atol=0)
