@@ -3,9 +3,10 @@
 //
 // One evaluation of S point sets of n points each (S = 1 for an observed set,
 // S = m for Monte Carlo simulations, Sec. 3) runs, on the caller's stream:
-//   keys (or on-device CSR draw) -> radix sort by (set, cell, halo) -> cell
-//   bounds -> sorted point records -> work items -> pair kernel (persistent)
-//   -> per-set prefix sums, K (Eq. 2) and L (Eq. 4) -> envelopes -> copies out.
+//   keys (or on-device CSR / resampling draw) -> radix sort by (set, cell,
+//   halo) or, for two-type sets, (set, type, cell) -> cell bounds -> sorted
+//   point records -> work items -> pair kernel (persistent) -> per-set prefix
+//   sums, K (Eq. 2) and L (Eq. 4) -> envelopes -> copies out.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

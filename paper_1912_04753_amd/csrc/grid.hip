@@ -406,8 +406,8 @@ __global__ void k_gather_rho(const uint32_t *__restrict__ vals, uint32_t n,
 }
 
 // A unit is the run of cells whose centres a work item may mix: one cell, or a
-// whole x-row of cells (unit = nx) when every point is a centre (no halo
-// entries between the cells).  Units cover cells [g*unit, (g+1)*unit) of the
+// whole x-row of cells (unit = nx) when no halo entries lie between the cells
+// (every point a centre, or the type-1 block of blocked keys).  Units cover cells [g*unit, (g+1)*unit) of the
 // cell array of all sets.  Items are cut greedily: up to kChunk consecutive
 // centres, all within 1 + kItemExtent consecutive cells of the unit (the
 // candidate distance bound of the plan relies on it).  chunk_walk visits the

@@ -113,8 +113,9 @@ hipError_t launch_keys(const int32_t *x, const int32_t *y, const int32_t *t, uin
                        uint32_t n_centres, uint32_t set_base, uint32_t n_sets,
                        const Geom &g, int blocked, uint32_t *keys, uint32_t *vals,
                        uint32_t *err, hipStream_t s);
-// m CSR sets of n points; points k >= n_centres of each set take the halo slot
-// of their cell (type 2 of a cross-K plan; n_centres = n otherwise)
+// m CSR sets of n points; points k >= n_centres of each set are type 2 of a
+// cross-K plan (halo slot, or the type-2 block of blocked keys; n_centres = n
+// otherwise)
 // (polygon: rejection sampling; a point that finds no attempt inside sets bit 1
 // of *err)
 hipError_t launch_csr(uint32_t n, uint32_t n_centres, uint32_t m, uint64_t seed, const Geom &g,
