@@ -386,6 +386,40 @@ def main():
              "pair_tests_per_s_G": round(ripk.ripk_plan_stats(iplan)["n_in"] / (i_ms * 1e-3) / 1e9, 3),
              "note": "observed K_I of the 100k set, intensity per point (device), autotuned cells"}
     iplan.destroy()
+    # the two larger workloads, autotuned: 200k clustered points (observed K), and
+    # 1M uniform + 1M clustered points with 19 CSR simulations
+    larger = {}
+    for wname, reps in (("thomas-200k", 3), ("mixed-2M-19csr", 2)):
+        wc = workloads.workload(wname)
+        wx, wy, wt = (torch.from_numpy(a).cuda() for a in workloads.make_points(wc))
+        wn, wm = len(wx), wc["sims"]
+        wplan = ripk.ripk_plan(ripk.make_desc(wc["window"], wc["s_max"], wc["t_max"], wc["n_s"],
+                                              wc["n_t"], n_max=wn, m_max=wm,
+                                              flags=ripk.RIPK_PLAN_AUTOTUNE))
+
+        def wstep():
+            r = ripk.ripk_compute_K(wplan, wx, wy, wt, stream=stream)
+            a = ripk.ripk_plan_stats(wplan)["n_in"]
+            if wm == 0:
+                return a, 0.0
+            t1 = time.perf_counter()
+            ripk.ripk_simulate_envelope(wplan, wn, wm, wc["seed"], L_obs=r["L"], stream=stream)
+            return a + ripk.ripk_plan_stats(wplan)["n_in"], time.perf_counter() - t1
+
+        wstep()  # tuning
+        torch.cuda.synchronize()
+        t_w = time.perf_counter()
+        ws = [wstep() for _ in range(reps)]
+        torch.cuda.synchronize()
+        w_ms = 1e3 * (time.perf_counter() - t_w) / reps
+        wi = ripk.ripk_plan_get_info(wplan)
+        larger[wname] = {"ms_per_step": round(w_ms, 3),
+                         "pair_tests_per_s_G": round(ws[0][0] / (w_ms * 1e-3) / 1e9, 3),
+                         "n_in_per_step": ws[0][0],
+                         "sims_per_s": round(wm / (sum(v[1] for v in ws) / reps), 3) if wm else None,
+                         "cells_m_s": [wi["cell_s"], wi["cell_t"]]}
+        wplan.destroy()
+        del wx, wy, wt
     plan.destroy()
 
     ms = 1e3 * t_total / args.steps
@@ -425,6 +459,7 @@ def main():
         "cross_k": cross,
         "polygon": polygon,
         "inhomogeneous_k": inhom,
+        "larger_workloads": larger,
         "cold_ms": {"plan": round(plan_ms, 2),
                     "first_step_with_tuning": round(first_step_ms, 2) if not args.no_autotune else None},
         "observed_host_input": {"ms": round(host_obs_ms, 3),

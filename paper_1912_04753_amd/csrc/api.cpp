@@ -430,7 +430,9 @@ struct ripk_plan_s {
   int2 *poly = nullptr;        // polygon vertices (window-relative)
   uint16_t *near = nullptr;    // per xy-cell edge lists of the bound geometry
   std::vector<uint16_t> nearh; // host copy of the lists (source of the upload)
-  unsigned long long *scal = nullptr;  // [0] n_eval, [1] n_in, [2] err|n_items|item_ctr (u32s)
+  // [0] n_eval, [1] n_in, [2] err|n_items (u32s); from word kQueueStride on,
+  // the pair kernel's kQueues work-queue blocks
+  unsigned long long *scal = nullptr;
   hipEvent_t ev[6] = {};
   ripk_stats stats{};
 };
@@ -486,8 +488,8 @@ ripk_status enqueue_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_cent
   if (timing) HIPCHK(hipEventRecord(p->ev[0], st));
   uint32_t *err = (uint32_t *)(p->scal + 2);
   uint32_t *n_items = err + 1;
-  uint32_t *item_ctr = err + 2;
-  HIPCHK(launch_fill_u64(p->scal, 4, 0ull, st));
+  unsigned long long *queues = p->scal + kQueueStride;
+  HIPCHK(launch_fill_u64(p->scal, (size_t)(kQueues + 1) * kQueueStride, 0ull, st));
   const bool cross = (p->desc.flags & RIPK_PLAN_CROSS) != 0;
   if (simulate) {
     if (p->desc.sim_method == RIPK_SIM_CSR)
@@ -545,12 +547,11 @@ ripk_status enqueue_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_cent
   a.cs = p->cs;
   a.items = p->items;
   a.n_items = n_items;
-  a.item_ctr = item_ctr;
+  a.queues = queues;
   a.S2 = p->S2;
   a.T = p->T;
   a.binC = p->binC;
   a.binW = p->binW;
-  a.n_eval = p->scal;
   a.symmetric = symmetric ? 1 : 0;
   a.row_items = row_items ? 1 : 0;
   a.blocked = cross ? 1 : 0;
@@ -570,7 +571,7 @@ ripk_status enqueue_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_cent
                                                    : (double)n * (double)(n - 1);
   HIPCHK(launch_finalize(p->binC, p->binW, S, g.n_s, g.n_t, (double)p->desc.s_max,
                          (double)p->desc.t_max, AD, Nn, p->outC, p->outW, p->outK, p->outL,
-                         p->scal + 1, st, inhom));
+                         queues, p->scal, st, inhom));
   if (simulate)
     HIPCHK(launch_envelope(p->outK, p->outL, S, (int)NB, has_Lobs ? p->Lobs : nullptr, p->env, st));
   if (timing) HIPCHK(hipEventRecord(p->ev[4], st));
@@ -712,7 +713,7 @@ ripk_status plan_create(int device, const Caps &c, ripk_plan_s **out) {
   ALLOC(p->S2, kMaxSteps); ALLOC(p->T, kMaxSteps);
   ALLOC(p->poly, c.V); ALLOC(p->near, (kNearMax + 1) * c.NXY);
   ALLOC(p->lam, c.R); ALLOC(p->rho, c.R);
-  ALLOC(p->scal, 4);
+  ALLOC(p->scal, (kQueues + 1) * kQueueStride);
 #undef ALLOC
   if (e != hipSuccess) {
     release(p);

@@ -5,7 +5,8 @@
 // s and t and the weights do not depend on the threshold, the sums of Eq. 2 at
 // every grid point are the 2-D inclusive prefix sums of that histogram.  This
 // file forms them (exact integers: counts in u64, weights in 128-bit fixed point
-// with 23 fraction bits), then K = A*D*W/N (Eq. 2) and L = sqrt(K/(2 pi t)) - s
+// with 23 fraction bits, assembled from the pair kernel's two sums of 32-bit
+// halves), then K = A*D*W/N (Eq. 2) and L = sqrt(K/(2 pi t)) - s
 // (Eq. 4) in FP64, and the pointwise min/max envelopes over simulations (Sec. 3).
 #include "ripk_internal.h"
 
@@ -34,12 +35,19 @@ __global__ void k_finalize(unsigned long long *__restrict__ binC,
                            double s_max, double t_max, double AD, double N,
                            unsigned long long *__restrict__ C, double *__restrict__ W,
                            double *__restrict__ K, double *__restrict__ L,
-                           unsigned long long *__restrict__ n_in, int fp) {
+                           const unsigned long long *__restrict__ queues,
+                           unsigned long long *__restrict__ scal, int fp) {
   const int set = blockIdx.x;
   const int nb = n_s * n_t;
   unsigned long long *c = binC + (size_t)set * nb;
   unsigned long long *w = binW + (size_t)set * nb * 2;
-  // prefix along t within each s row
+  if (set == 0 && threadIdx.x == 0) {
+    unsigned long long ev = 0;
+    for (int q = 0; q < kQueues; ++q) ev += queues[q * kQueueStride + 1];
+    scal[0] = ev;
+  }
+  // prefix along t within each s row (fixed point: lo + hi * 2^32 of the
+  // split sums first, as a 128-bit value)
   for (int k = threadIdx.x; k < n_s; k += blockDim.x) {
     unsigned long long rc = 0, rlo = 0, rhi = 0;
     double rf = 0.0;
@@ -51,7 +59,9 @@ __global__ void k_finalize(unsigned long long *__restrict__ binC,
         rf += as_f64(w[2 * b]);
         w[2 * b] = as_u64(rf);
       } else {
-        add128(rlo, rhi, w[2 * b], w[2 * b + 1]);
+        const unsigned long long s_lo = w[2 * b], s_hi = w[2 * b + 1];
+        add128(rlo, rhi, s_hi << 32, s_hi >> 32);
+        add128(rlo, rhi, s_lo, 0ull);
         w[2 * b] = rlo;
         w[2 * b + 1] = rhi;
       }
@@ -95,7 +105,7 @@ __global__ void k_finalize(unsigned long long *__restrict__ binC,
     K[o] = Kv;
     L[o] = sqrt(Kv / (two_pi * tl)) - sk;
   }
-  if (threadIdx.x == 0) atomicAdd(n_in, c[nb - 1]);
+  if (threadIdx.x == 0) atomicAdd(scal + 1, c[nb - 1]);
 }
 
 // env rows: K_lo, K_hi, L_lo, L_hi, dL_hi
@@ -124,9 +134,10 @@ __global__ void k_envelope(const double *__restrict__ K, const double *__restric
 hipError_t launch_finalize(unsigned long long *binC, unsigned long long *binW, uint32_t n_sets,
                            int n_s, int n_t, double s_max, double t_max, double AD, double N,
                            unsigned long long *C, double *W, double *K, double *L,
-                           unsigned long long *n_in, hipStream_t s, bool fp) {
+                           const unsigned long long *queues, unsigned long long *scal,
+                           hipStream_t s, bool fp) {
   hipLaunchKernelGGL(k_finalize, dim3(n_sets), dim3(256), 0, s, binC, binW, n_s, n_t, s_max,
-                     t_max, AD, N, C, W, K, L, n_in, fp ? 1 : 0);
+                     t_max, AD, N, C, W, K, L, queues, scal, fp ? 1 : 0);
   return hipGetLastError();
 }
 

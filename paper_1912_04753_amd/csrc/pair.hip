@@ -659,6 +659,8 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
   int cur_set = -1;
   unsigned long long evals_total = 0;
 
+  // (no atomic here returns a value: the 64-bit weight sum goes out as its
+  // two 32-bit halves, added to two 64-bit sums)
   auto flush = [&](int set) {
     for (int b = tid; b < NB; b += kPairThreads) {
       const unsigned long long c =
@@ -670,8 +672,8 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
         if (INHOM) {
           atomicAdd((double *)&a.binW[2 * o], __longlong_as_double((long long)w));
         } else {
-          const unsigned long long old = atomicAdd(&a.binW[2 * o], w);
-          if (old + w < old) atomicAdd(&a.binW[2 * o + 1], 1ull);
+          atomicAdd(&a.binW[2 * o], w & 0xFFFFFFFFull);
+          if (w >> 32) atomicAdd(&a.binW[2 * o + 1], w >> 32);
         }
         hist[b] = 0;
         if (wide)
@@ -682,13 +684,38 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
     }
   };
 
+  // Work queue: partition q of the groups is [q*G/kQueues, (q+1)*G/kQueues)
+  // with its own counter.  A workgroup starts in partition blockIdx % kQueues
+  // (its XCD under round-robin dispatch, so neighbouring groups share an L2)
+  // and moves to the next partition when one runs dry; a plain read of the
+  // counter first spares the atomic on a partition already handed out.
+  const uint32_t n_groups = n_items / kItemsPerGroup;
+  const int home = (int)(blockIdx.x % kQueues);
+  int qp = home, q_left = kQueues;
   for (;;) {
     __syncthreads();  // previous group finished by every wave
-    if (tid == 0) *grp_lds = atomicAdd(a.item_ctr, 1u);
+    if (tid == 0) {
+      uint32_t got = 0xFFFFFFFFu;
+      while (q_left > 0) {
+        const uint32_t lo = (uint32_t)((uint64_t)qp * n_groups / kQueues);
+        const uint32_t hi = (uint32_t)((uint64_t)(qp + 1) * n_groups / kQueues);
+        uint32_t *ctr = (uint32_t *)(a.queues + (size_t)qp * kQueueStride);
+        if (lo + __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < hi) {
+          const uint32_t gq = lo + atomicAdd(ctr, 1u);
+          if (gq < hi) {
+            got = gq;
+            break;
+          }
+        }
+        qp = qp + 1 == kQueues ? 0 : qp + 1;
+        --q_left;
+      }
+      *grp_lds = got;
+    }
     __syncthreads();
     const uint32_t grp = uni(*grp_lds);
+    if (grp == 0xFFFFFFFFu) break;
     const uint32_t base = grp * kItemsPerGroup;
-    if (base >= n_items) break;
     const int set = (int)uni(a.items[base].set);
     const unsigned long long pend = *evals_lds;
     if (set != cur_set || pend > kFlushEvals) {
@@ -785,7 +812,7 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
     evals_total += ev;
   }
   if (cur_set >= 0) flush(cur_set);
-  if (lane == 0 && evals_total) atomicAdd(a.n_eval, evals_total);
+  if (lane == 0 && evals_total) atomicAdd(a.queues + (size_t)home * kQueueStride + 1, evals_total);
 }
 
 template <bool SYM, int MODE, bool POLY, bool INHOM>

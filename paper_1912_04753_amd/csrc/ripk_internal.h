@@ -61,6 +61,13 @@ struct Item {
                    // covers (end 0 = all rows; items split for small launches)
 };
 constexpr int kSplitMax = 8;  // stencil-row parts an item may be split into
+// The pair kernel's work queue is cut into kQueues contiguous partitions of
+// item groups, one per XCD, each with its own counter kQueueStride words
+// (4 KB) from the next: returning atomics on one address serialise across the
+// chip, so one counter for every workgroup would cost tens of microseconds per
+// launch.
+constexpr int kQueues = 8;
+constexpr int kQueueStride = 512;
 
 struct PairArgs {
   Geom g;
@@ -68,12 +75,18 @@ struct PairArgs {
   const uint32_t *cs;     // cell starts: 2*n_cells*n_sets + 1 entries
   const Item *items;
   const uint32_t *n_items;  // device scalar
-  uint32_t *item_ctr;       // device scalar, zeroed before launch
+  // kQueues blocks of kQueueStride words, zeroed before launch: word 0 counts
+  // the groups handed out of that partition of the work queue, word 1 sums
+  // the candidates examined by the workgroups whose home it is
+  unsigned long long *queues;
   const uint64_t *S2;       // n_s thresholds (device)
   const uint32_t *T;        // n_t thresholds (device)
   unsigned long long *binC;  // [sets][n_bins] counts
-  unsigned long long *binW;  // [sets][n_bins][2] 128-bit fixed-point weight sums
-  unsigned long long *n_eval;  // device scalar
+  // [sets][n_bins][2] fixed-point weight sums, split so that no flush needs
+  // the old value: the sums of the low and of the high 32-bit halves of the
+  // workgroups' 64-bit partial sums (the weight is word0 + word1 * 2^32); FP64
+  // sums in word 0 for inhomogeneous K
+  unsigned long long *binW;
   int symmetric;
   int row_items;               // items are chunks of x-rows (else of cells)
   int blocked;                 // two-type sets in blocked key order: centres from the
@@ -161,12 +174,14 @@ hipError_t pair_occupancy(int n_bins, int wide_counts, int symmetric, int mode, 
                           int *per_cu);
 // 64-bit LDS pair counts are needed from this many points per set on
 constexpr int64_t kWideCountPoints = 1 << 23;
-// fp: the weight bins hold FP64 sums (inhomogeneous K) instead of 128-bit
-// fixed point
+// fp: the weight bins hold FP64 sums (inhomogeneous K) instead of split
+// fixed point.  scal[0] receives the candidates summed over the work-queue
+// partitions `queues`, scal[1] the in-range pairs over all sets.
 hipError_t launch_finalize(unsigned long long *binC, unsigned long long *binW,
                            uint32_t n_sets, int n_s, int n_t, double s_max, double t_max,
                            double AD, double N, unsigned long long *C, double *W, double *K,
-                           double *L, unsigned long long *n_in, hipStream_t s, bool fp = false);
+                           double *L, const unsigned long long *queues,
+                           unsigned long long *scal, hipStream_t s, bool fp = false);
 hipError_t launch_envelope(const double *K, const double *L, uint32_t m, int n_bins,
                            const double *L_obs, double *env, hipStream_t s);
 
