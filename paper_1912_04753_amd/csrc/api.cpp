@@ -433,6 +433,10 @@ struct ripk_plan_s {
   // [0] n_eval, [1] n_in, [2] err|n_items (u32s); from word kQueueStride on,
   // the pair kernel's kQueues work-queue blocks
   unsigned long long *scal = nullptr;
+  // a call's scalars and result rows, packed on the device and brought to
+  // pinned host memory in one copy (kScalWords + kPackRows * n_bins words)
+  unsigned long long *dstage = nullptr;
+  unsigned long long *hstage = nullptr;
   hipEvent_t ev[6] = {};
   ripk_stats stats{};
 };
@@ -453,9 +457,10 @@ void release(ripk_plan_s *p) {
                   p->vals[1],
                   p->sort_temp, p->cs, p->P, p->chunks, p->offs, p->set_base, p->scan_temp,
                   p->items, p->binC, p->binW, p->outC, p->outW, p->outK, p->outL, p->env,
-                  p->Lobs, p->S2, p->T, p->poly, p->near, p->lam, p->rho, p->scal};
+                  p->Lobs, p->S2, p->T, p->poly, p->near, p->lam, p->rho, p->scal, p->dstage};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
+  if (p->hstage) (void)hipHostFree(p->hstage);
   for (auto &e : p->ev)
     if (e) (void)hipEventDestroy(e);
   for (auto &e : p->tev)
@@ -627,11 +632,22 @@ ripk_status run_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_centres,
   return RIPK_OK;
 }
 
+// Waits for the call and reads its scalars; with `rows`, those result rows of
+// n_bins words come along in the same copy, at p->hstage + kScalWords + r*n_bins.
 ripk_status collect_stats(ripk_plan_s *p, hipStream_t st, uint32_t S, uint32_t n,
-                          uint32_t *err_out) {
-  unsigned long long sc[4];
-  HIPCHK(hipMemcpyAsync(sc, p->scal, sizeof sc, hipMemcpyDeviceToHost, st));
+                          uint32_t *err_out, const PackRows *rows = nullptr) {
+  const int NB = (int)p->lay.info.n_bins;
+  PackRows none = {};
+  int last = -1;
+  if (rows)
+    for (int r = 0; r < kPackRows; ++r)
+      if (rows->p[r]) last = r;
+  HIPCHK(launch_pack(p->scal, rows ? *rows : none, NB, p->dstage, st));
+  const size_t words = kScalWords + (size_t)(last + 1) * NB;
+  HIPCHK(hipMemcpyAsync(p->hstage, p->dstage, sizeof(unsigned long long) * words,
+                        hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
+  const unsigned long long *sc = p->hstage;
   const uint32_t *w = (const uint32_t *)(sc + 2);
   *err_out = w[0];
   p->stats.n_eval = (int64_t)sc[0];
@@ -714,7 +730,11 @@ ripk_status plan_create(int device, const Caps &c, ripk_plan_s **out) {
   ALLOC(p->poly, c.V); ALLOC(p->near, (kNearMax + 1) * c.NXY);
   ALLOC(p->lam, c.R); ALLOC(p->rho, c.R);
   ALLOC(p->scal, (kQueues + 1) * kQueueStride);
+  ALLOC(p->dstage, kScalWords + kPackRows * c.NB);
 #undef ALLOC
+  if (e == hipSuccess)
+    e = hipHostMalloc((void **)&p->hstage, sizeof(unsigned long long) * (kScalWords + kPackRows * c.NB),
+                      hipHostMallocDefault);
   if (e != hipSuccess) {
     release(p);
     return fail(e == hipErrorOutOfMemory ? RIPK_ENOMEM : RIPK_EDEVICE, "allocation failed: %s",
@@ -964,7 +984,12 @@ ripk_status ripk_compute_K(ripk_plan_t p, const ripk_points *pts, void *stream, 
                             sym);
   if (s != RIPK_OK) return s;
   uint32_t err = 0;
-  s = collect_stats(p, st, 1, (uint32_t)n, &err);
+  PackRows rows = {};
+  if (out)
+    rows = {{out->C ? p->outC : nullptr, out->W ? (const unsigned long long *)p->outW : nullptr,
+             out->K ? (const unsigned long long *)p->outK : nullptr,
+             out->L ? (const unsigned long long *)p->outL : nullptr, nullptr}};
+  s = collect_stats(p, st, 1, (uint32_t)n, &err, &rows);
   if (s != RIPK_OK) return s;
   if (err) return err_status(err);
   if (p->desc.sim_method != RIPK_SIM_CSR) p->obs_n = n;
@@ -974,11 +999,9 @@ ripk_status ripk_compute_K(ripk_plan_t p, const ripk_points *pts, void *stream, 
   }
   const size_t NB = (size_t)p->lay.info.n_bins;
   if (out) {
-    if (out->C) HIPCHK(hipMemcpyAsync(out->C, p->outC, 8 * NB, hipMemcpyDeviceToHost, st));
-    if (out->W) HIPCHK(hipMemcpyAsync(out->W, p->outW, 8 * NB, hipMemcpyDeviceToHost, st));
-    if (out->K) HIPCHK(hipMemcpyAsync(out->K, p->outK, 8 * NB, hipMemcpyDeviceToHost, st));
-    if (out->L) HIPCHK(hipMemcpyAsync(out->L, p->outL, 8 * NB, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
+    void *dst[4] = {out->C, out->W, out->K, out->L};
+    for (int r = 0; r < 4; ++r)
+      if (dst[r]) std::memcpy(dst[r], p->hstage + kScalWords + r * NB, 8 * NB);
   }
   p->stats.us_total = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
   return RIPK_OK;
@@ -1012,18 +1035,26 @@ ripk_status ripk_simulate_envelope(ripk_plan_t p, int64_t n, int32_t m, uint64_t
                             nc, nullptr, nullptr, nullptr, true, seed, L_obs, st, sym);
   if (s != RIPK_OK) return s;
   uint32_t err = 0;
-  s = collect_stats(p, st, (uint32_t)m, (uint32_t)n, &err);
+  const size_t NB = (size_t)p->lay.info.n_bins;
+  double *dst[kPackRows] = {};
+  PackRows rows = {};
+  if (out) {
+    double *d[kPackRows] = {out->K_lo, out->K_hi, out->L_lo, out->L_hi, L_obs ? out->dL_hi : nullptr};
+    for (int r = 0; r < kPackRows; ++r) {
+      dst[r] = d[r];
+      rows.p[r] = d[r] ? (const unsigned long long *)(p->env + r * NB) : nullptr;
+    }
+  }
+  s = collect_stats(p, st, (uint32_t)m, (uint32_t)n, &err, &rows);
   if (s != RIPK_OK) return s;
   if (err) return err_status(err);
-  const size_t NB = (size_t)p->lay.info.n_bins;
   if (out) {
-    double *rows[5] = {out->K_lo, out->K_hi, out->L_lo, out->L_hi, L_obs ? out->dL_hi : nullptr};
-    for (int r = 0; r < 5; ++r)
-      if (rows[r]) HIPCHK(hipMemcpyAsync(rows[r], p->env + r * NB, 8 * NB, hipMemcpyDeviceToHost, st));
+    for (int r = 0; r < kPackRows; ++r)
+      if (dst[r]) std::memcpy(dst[r], p->hstage + kScalWords + r * NB, 8 * NB);
     if (out->C_sims) HIPCHK(hipMemcpyAsync(out->C_sims, p->outC, 8 * NB * m, hipMemcpyDeviceToHost, st));
     if (out->W_sims) HIPCHK(hipMemcpyAsync(out->W_sims, p->outW, 8 * NB * m, hipMemcpyDeviceToHost, st));
     if (out->K_sims) HIPCHK(hipMemcpyAsync(out->K_sims, p->outK, 8 * NB * m, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
+    if (out->C_sims || out->W_sims || out->K_sims) HIPCHK(hipStreamSynchronize(st));
   }
   p->stats.us_total = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
   return RIPK_OK;

@@ -129,7 +129,24 @@ __global__ void k_envelope(const double *__restrict__ K, const double *__restric
   env[4 * nb + b] = L_obs ? L_obs[b] - lhi : 0.0;
 }
 
+// The call's scalars and up to kPackRows output rows of nb words, one after
+// another, so that one copy brings them to the host.
+__global__ void k_pack(const unsigned long long *__restrict__ scal, PackRows rows, int nb,
+                       unsigned long long *__restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < kScalWords) out[i] = scal[i];
+  for (int r = 0; r < kPackRows; ++r)
+    if (rows.p[r] && i < nb) out[kScalWords + r * nb + i] = rows.p[r][i];
+}
+
 }  // namespace
+
+hipError_t launch_pack(const unsigned long long *scal, const PackRows &rows, int nb,
+                       unsigned long long *out, hipStream_t s) {
+  const int n = nb > kScalWords ? nb : kScalWords;
+  hipLaunchKernelGGL(k_pack, dim3((n + 255) / 256), dim3(256), 0, s, scal, rows, nb, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_finalize(unsigned long long *binC, unsigned long long *binW, uint32_t n_sets,
                            int n_s, int n_t, double s_max, double t_max, double AD, double N,

@@ -184,5 +184,15 @@ hipError_t launch_finalize(unsigned long long *binC, unsigned long long *binW,
                            unsigned long long *scal, hipStream_t s, bool fp = false);
 hipError_t launch_envelope(const double *K, const double *L, uint32_t m, int n_bins,
                            const double *L_obs, double *env, hipStream_t s);
+// Results of a call brought to the host in one copy: kScalWords words of
+// scal, then each non-null row of nb 8-byte words at its slot (row r at
+// kScalWords + r*nb).
+constexpr int kScalWords = 4;
+constexpr int kPackRows = 5;
+struct PackRows {
+  const unsigned long long *p[kPackRows];
+};
+hipError_t launch_pack(const unsigned long long *scal, const PackRows &rows, int nb,
+                       unsigned long long *out, hipStream_t s);
 
 }  // namespace ripk
