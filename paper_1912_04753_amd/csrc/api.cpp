@@ -528,15 +528,17 @@ ripk_status enqueue_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_cent
   HIPCHK(pair_occupancy((int)NB, wide_counts, symmetric ? 1 : 0, g.mode,
                         inhom ? 2 : (pair_poly(g) ? 1 : 0), &per_cu));
   if (per_cu < 1) return fail(RIPK_EINVAL, "pair kernel does not fit on a compute unit (n_bins=%u)", NB);
-  // A launch with fewer groups than about twice the resident workgroups splits
-  // every item's stencil rows into `split` parts taken by different waves.
+  // A launch with fewer groups than about 16 times the resident workgroups
+  // splits every item's stencil rows into `split` parts taken by different
+  // waves: a single set's items then come in pieces small enough for the
+  // queue to even out dense clusters.
   const int64_t slots = (int64_t)per_cu * p->cus;
   const int64_t items_bound = (int64_t)S * (n / kChunk + g.n_cells + kItemsPerGroup);
   // (sized for S_split sets: the autotuner times a few sets of a larger call)
   const int64_t items_est = (int64_t)S_split * (n / kChunk + 1);
   const uint32_t n_rows = symmetric ? (uint32_t)((g.rs + 1) + g.rt * (2 * g.rs + 1))
                                     : (uint32_t)((2 * g.rt + 1) * (2 * g.rs + 1));
-  int64_t split = (2 * slots * kItemsPerGroup + items_est - 1) / items_est;
+  int64_t split = (16 * slots * kItemsPerGroup + items_est - 1) / items_est;
   split = std::min<int64_t>({split, (int64_t)kSplitMax, (int64_t)n_rows,
                              p->caps.items / std::max<int64_t>(items_bound, 1)});
   split = std::max<int64_t>(split, 1);

@@ -474,6 +474,18 @@ __device__ __forceinline__ uint32_t item_count(uint32_t cnt, uint32_t p, uint32_
   return cnt | (r0 << 7) | (r1 << 19);
 }
 
+// Slot of part p of item o (o counts items over all sets, each set padded to
+// whole groups starting at sb = set_base of its set).  A group holds part p of
+// kItemsPerGroup consecutive items, not the parts of one item: the waves of a
+// workgroup then take stencil parts of the same index, alike in cost (split
+// items of clustered sets differ most between parts, rows near the centres'
+// own time cell holding the clusters).
+__device__ __forceinline__ uint32_t item_slot(uint32_t sb, uint32_t o, uint32_t p,
+                                              uint32_t split) {
+  const uint32_t q = o - sb;
+  return sb * split + ((q / kItemsPerGroup) * split + p) * kItemsPerGroup + q % kItemsPerGroup;
+}
+
 __global__ void k_emit(const uint32_t *__restrict__ cs, const uint32_t *__restrict__ offs,
                        const uint32_t *__restrict__ set_base, uint32_t n_sets, uint32_t n_units,
                        uint32_t unit, uint32_t split, uint32_t n_rows, CentreIdx ci,
@@ -481,7 +493,8 @@ __global__ void k_emit(const uint32_t *__restrict__ cs, const uint32_t *__restri
   uint32_t gidx = blockIdx.x * blockDim.x + threadIdx.x;
   if (gidx >= n_sets * n_units) return;
   uint32_t s = gidx / n_units, c = gidx - s * n_units;
-  uint32_t o = set_base[s] + offs[gidx] - offs[s * n_units];
+  const uint32_t sb = set_base[s];
+  uint32_t o = sb + offs[gidx] - offs[s * n_units];
   chunk_walk(cs, gidx, unit, ci, [&](uint32_t b, uint32_t cnt) {
     for (uint32_t p = 0; p < split; ++p) {
       Item it;
@@ -489,20 +502,21 @@ __global__ void k_emit(const uint32_t *__restrict__ cs, const uint32_t *__restri
       it.cell = c;
       it.begin = b;
       it.count = item_count(cnt, p, split, n_rows);
-      items[o * split + p] = it;
+      items[item_slot(sb, o, p, split)] = it;
     }
     ++o;
   });
   if (c == n_units - 1) {
-    uint32_t end = set_base[s] + offs[(s + 1) * n_units] - offs[s * n_units];
-    for (uint32_t p = end * split; p < set_base[s + 1] * split; ++p) {
-      Item it;
-      it.set = s;
-      it.cell = 0;
-      it.begin = 0;
-      it.count = 0;
-      items[p] = it;
-    }
+    uint32_t end = sb + offs[(s + 1) * n_units] - offs[s * n_units];
+    for (uint32_t q = end; q < set_base[s + 1]; ++q)
+      for (uint32_t p = 0; p < split; ++p) {
+        Item it;
+        it.set = s;
+        it.cell = 0;
+        it.begin = 0;
+        it.count = 0;
+        items[item_slot(sb, q, p, split)] = it;
+      }
   }
 }
 

@@ -60,7 +60,7 @@ struct Item {
                    // 19-30: first and end index of the stencil rows this item
                    // covers (end 0 = all rows; items split for small launches)
 };
-constexpr int kSplitMax = 8;  // stencil-row parts an item may be split into
+constexpr int kSplitMax = 32;  // stencil-row parts an item may be split into
 // The pair kernel's work queue is cut into kQueues contiguous partitions of
 // item groups, one per XCD, each with its own counter kQueueStride words
 // (4 KB) from the next: returning atomics on one address serialise across the
