@@ -236,7 +236,9 @@ typedef struct {
   int32_t pair_grid;       /* workgroups of the persistent pair kernel                   */
   int32_t symmetric;       /* 1 if unordered pairs were evaluated once                   */
   int32_t split;           /* parts each work item's stencil rows were split into        */
-  int32_t reserved;
+  int32_t bin_layout;      /* LDS bins of the pair kernel: 0 count and interior weight
+                              in one word, 1 weight + 32-bit count, 2 weight + 64-bit
+                              count                                                      */
   double us_total;         /* wall time of the call, microseconds                        */
   double us_gen, us_grid, us_pair, us_finalize; /* device phases (RIPK_PLAN_TIMING)      */
 } ripk_stats;

@@ -522,11 +522,20 @@ ripk_status enqueue_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_cent
   // row items need rows without halo entries: every point a centre, or the
   // type-1 block of a cross-K set
   const bool row_items = n_centres == n || cross;
-  const int wide_counts =
-      ((int64_t)n >= kWideCountPoints || (p->desc.flags & RIPK_PLAN_WIDE_COUNTS)) ? 1 : 0;
+  // bin layout: packed (one LDS atomic per pair) unless the set is large, the
+  // weights are FP64 or the extra 4 bytes per bin would lower the occupancy
+  const int var = inhom ? 2 : (pair_poly(g) ? 1 : 0);
+  int bins = ((int64_t)n >= kWideCountPoints || (p->desc.flags & RIPK_PLAN_WIDE_COUNTS))
+                 ? kBinsSplit64
+                 : kBinsSplit32;
   int per_cu = 0;
-  HIPCHK(pair_occupancy((int)NB, wide_counts, symmetric ? 1 : 0, g.mode,
-                        inhom ? 2 : (pair_poly(g) ? 1 : 0), &per_cu));
+  HIPCHK(pair_occupancy(g.n_s, g.n_t, bins, symmetric ? 1 : 0, g.mode, var, &per_cu));
+  if (bins == kBinsSplit32 && !inhom && (int64_t)n < kPackedPoints) {
+    int per_cu_packed = 0;
+    HIPCHK(pair_occupancy(g.n_s, g.n_t, kBinsPacked, symmetric ? 1 : 0, g.mode, var,
+                          &per_cu_packed));
+    if (per_cu_packed >= per_cu) bins = kBinsPacked;
+  }
   if (per_cu < 1) return fail(RIPK_EINVAL, "pair kernel does not fit on a compute unit (n_bins=%u)", NB);
   // A launch with fewer groups than about 16 times the resident workgroups
   // splits every item's stencil rows into `split` parts taken by different
@@ -563,7 +572,7 @@ ripk_status enqueue_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_cent
   a.row_items = row_items ? 1 : 0;
   a.blocked = cross ? 1 : 0;
   a.rho = inhom ? p->rho : nullptr;
-  a.wide_counts = wide_counts;
+  a.bins = bins;
   const int64_t groups_cap = items_bound * split / kItemsPerGroup + 1;
   const int grid = (int)std::min<int64_t>(slots, groups_cap);
   HIPCHK(launch_pair(a, grid, st));
@@ -584,6 +593,7 @@ ripk_status enqueue_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_cent
   if (timing) HIPCHK(hipEventRecord(p->ev[4], st));
   p->stats.pair_grid = grid;
   p->stats.split = (int32_t)split;
+  p->stats.bin_layout = bins;
   p->stats.symmetric = symmetric ? 1 : 0;
   return RIPK_OK;
 }
@@ -797,8 +807,12 @@ ripk_status bind_geometry(ripk_plan_s *p, const ripk_plan_desc *desc, hipStream_
   if (s != RIPK_OK) return s;
   if (desc->device != p->device) return fail(RIPK_EINVAL, "descriptor device differs from the plan's");
   if (!caps_fit(p->caps, L.caps)) return fail(RIPK_E2BIG, "descriptor exceeds the plan's capacity");
+  // (the split layout of the plan's largest sets; packed bins are taken only
+  // where they fit as well)
   const int lds = pair_lds_bytes(
-      L.info.n_bins, desc->n_max >= kWideCountPoints || (desc->flags & RIPK_PLAN_WIDE_COUNTS),
+      desc->n_s, desc->n_t,
+      desc->n_max >= kWideCountPoints || (desc->flags & RIPK_PLAN_WIDE_COUNTS) ? kBinsSplit64
+                                                                               : kBinsSplit32,
       (desc->flags & RIPK_PLAN_INHOM) != 0);
   if ((size_t)lds > p->lds_max)
     return fail(RIPK_EINVAL, "grid of %d bins needs %d B of LDS per workgroup, device has %zu",

@@ -54,11 +54,16 @@ constexpr uint32_t kQA = 64 * kGroup + 64;
 constexpr int kQB = 128;    // ring of queue B records: < 64 + 64 pending between drains
 constexpr int kWaves = kPairThreads / 64;
 // Bound on the candidates a workgroup evaluates between histogram flushes
-// (checked before each group of items).  Counts are 32-bit words holding pairs
-// (not doubled in symmetric mode), so a bin stays below 2^31 + (one group's
-// candidates) < 2^32 when a set has fewer than 2^23 points; larger sets use
-// 64-bit count words.
+// (checked before each group of items).  Counts hold pairs (not doubled in
+// symmetric mode), and one group examines fewer than 256 n candidates.  Split
+// bins: a 32-bit count stays below 2^31 + 2^31 when a set has fewer than 2^23
+// points (larger sets use 64-bit count words).  Packed bins: a count stays
+// below 2^29 + 2^29 = 2^30 when a set has fewer than 2^21 points, and the
+// interior weight field (at most 4 units of 2^23 per pair) below 2^32.
 constexpr unsigned long long kFlushEvals = 1ull << 31;
+constexpr unsigned long long kFlushEvalsPacked = 1ull << 29;
+constexpr int kCountShift = 34;
+constexpr unsigned long long kUnitMask = (1ull << kCountShift) - 1ull;
 constexpr uint32_t kFarTime = 0xC0000000u;  // tile padding: fails every time test
 constexpr uint32_t kClampE = 32767u;         // side distances stored in 15 bits (PACKED)
 
@@ -310,12 +315,14 @@ __device__ __forceinline__ Side side_of(const int4 p, uint32_t d2lo, uint64_t d2
 template <bool SYM, int MODE, bool POLY, bool INHOM>
 __device__ __forceinline__ void drain_a(WaveLds &W, QState &q,
                                         uint32_t c, int lane, const Geom &g,
-                                        unsigned long long *hist, uint32_t *histc,
-                                        bool wide_counts, const uint32_t *S2lo,
+                                        unsigned long long *hist, void *aux, int bins,
+                                        const uint32_t *S2lo,
                                         const uint32_t *S2hi, const uint32_t *T,
                                         uint32_t begin, uint32_t tb, const int4 *P,
                                         const double *rho, const double *rho_c,
                                         const double *rho_t) {
+  // boundary weights: their own words with packed bins, else the weight words
+  unsigned long long *hw = (!INHOM && bins == kBinsPacked) ? (unsigned long long *)aux : hist;
   wave_sync();
   const uint32_t tag0 = W.qa[q.ha + (uint32_t)lane];  // q.ha + 63 < kQA: no wrap
   wave_sync();
@@ -383,9 +390,9 @@ __device__ __forceinline__ void drain_a(WaveLds &W, QState &q,
   // into their masks; taken after the branch below they would be rebuilt)
   const unsigned long long mslow =
       (__builtin_amdgcn_ballot_w64(si.slow) | (SYM ? __builtin_amdgcn_ballot_w64(sj.slow) : 0ull)) & vmask;
-  // weights hist[bin], pair counts in a separate array (32-bit words unless
-  // the set is large): separate arrays keep the 64 lanes' atomics spread over
-  // all LDS banks
+  // packed bins: the count and the interior weights in one atomic; split
+  // bins: weights hist[bin], counts in the aux array (32-bit words unless the
+  // set is large)
   if (INHOM) {
     // fast-path sides in units of 2^23 times rho_i rho_j (FP64 bins)
     const uint32_t ci = v ? ((tag & 0xFFFFu) - kCenOff) >> 2 : 0u;
@@ -394,11 +401,15 @@ __device__ __forceinline__ void drain_a(WaveLds &W, QState &q,
     if (v) atomicAdd((double *)&hist[bin], (double)(qsum >> kFracBits) * rr);
   }
   if (v) {
-    if (!INHOM) atomicAdd(&hist[bin], (unsigned long long)qsum);
-    if (wide_counts)
-      atomicAdd((unsigned long long *)histc + bin, 1ull);
-    else
-      atomicAdd(histc + bin, 1u);
+    if (!INHOM && bins == kBinsPacked) {
+      atomicAdd(&hist[bin], (1ull << kCountShift) | (unsigned long long)(qsum >> kFracBits));
+    } else {
+      if (!INHOM) atomicAdd(&hist[bin], (unsigned long long)qsum);
+      if (bins == kBinsSplit64)
+        atomicAdd((unsigned long long *)aux + bin, 1ull);
+      else
+        atomicAdd((uint32_t *)aux + bin, 1u);
+    }
   }
   if (c == 64) {
     q.ha = q.ha + 64 == kQA ? 0u : q.ha + 64;
@@ -419,7 +430,7 @@ __device__ __forceinline__ void drain_a(WaveLds &W, QState &q,
                                    ((uint32_t)(SYM && sj.slow) << 15) | (d2hi << 16),
                                d2lo, begin + (((tag & 0xFFFFu) - kCenOff) >> 2),
                                tb + (((tag >> 16) - kTileOff) >> 2));
-      if (q.nb >= 64) drain_b<MODE, POLY, INHOM>(W, q, 64, lane, hist, g, P, rho);
+      if (q.nb >= 64) drain_b<MODE, POLY, INHOM>(W, q, 64, lane, hw, g, P, rho);
     }
   } else if (MODE == kModePacked) {
     // one record per pair with a boundary side
@@ -432,7 +443,7 @@ __device__ __forceinline__ void drain_a(WaveLds &W, QState &q,
         W.qb[pos] = make_uint4(bin | (hfi << 12) | (hfj << 13) | ((uint32_t)si.slow << 14) |
                                    ((uint32_t)(SYM && sj.slow) << 15),
                                d2lo, (uint32_t)pi.z, (uint32_t)pj.z);
-      if (q.nb >= 64) drain_b<MODE, POLY, INHOM>(W, q, 64, lane, hist, g, P, rho);
+      if (q.nb >= 64) drain_b<MODE, POLY, INHOM>(W, q, 64, lane, hw, g, P, rho);
     }
   } else {
     // one record per boundary side, one side per pass through a single drain site
@@ -447,7 +458,7 @@ __device__ __forceinline__ void drain_a(WaveLds &W, QState &q,
         if (need && v)
           W.qb[pos] = make_uint4(w0 | ((side ? hfj : hfi) << 12), d2lo, side ? sj.ex : si.ex,
                                  side ? sj.ey : si.ey);
-        if (q.nb >= 64) drain_b<MODE, POLY, INHOM>(W, q, 64, lane, hist, g, P, rho);
+        if (q.nb >= 64) drain_b<MODE, POLY, INHOM>(W, q, 64, lane, hw, g, P, rho);
       }
     }
   }
@@ -506,9 +517,9 @@ struct Ctx {
   WaveLds &W;
   QState &q;
   const Geom &g;
-  unsigned long long *hist;  // fixed-point weights per bin
-  uint32_t *histc;           // pair counts per bin (32- or 64-bit words)
-  bool wide_counts;
+  unsigned long long *hist;  // packed count and weight, or the weight, per bin
+  void *aux;                 // boundary weights (packed) or pair counts (split)
+  int bins;                  // bin layout
   const uint32_t *S2lo, *S2hi, *T;
   int lane;
   uint32_t begin;  // record index of the item's first centre
@@ -520,7 +531,7 @@ struct Ctx {
 
 template <bool SYM, int MODE, bool POLY, bool INHOM>
 __device__ __forceinline__ void drain_oldest(Ctx<SYM, MODE, POLY, INHOM> &x, uint32_t c) {
-  drain_a<SYM, MODE, POLY, INHOM>(x.W, x.q, c, x.lane, x.g, x.hist, x.histc, x.wide_counts,
+  drain_a<SYM, MODE, POLY, INHOM>(x.W, x.q, c, x.lane, x.g, x.hist, x.aux, x.bins,
                                   x.S2lo, x.S2hi, x.T, x.begin, x.tb, x.P, x.rho, x.rho_c,
                                   x.rho_t);
 }
@@ -628,18 +639,20 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const Geom &g = a.g;
   const int NB = g.n_s * g.n_t;
-  // LDS: the waves' blocks first (fixed offsets), then the fixed-point
-  // weights, the pair counts (32- or 64-bit words, padded to 16 bytes), the
-  // threshold tables and two scalars (layout in pair_lds_bytes)
-  const bool wide = a.wide_counts != 0;
+  // LDS: the waves' blocks first (fixed offsets), then the bin words, the aux
+  // words (boundary weights or pair counts, see kBinsPacked), the threshold
+  // tables (n_s, n_s and n_t words, each padded to 16 bytes) and two scalars
+  // (layout in pair_lds_bytes)
+  const int bins = INHOM && a.bins == kBinsPacked ? kBinsSplit32 : a.bins;
+  const bool packed = !INHOM && bins == kBinsPacked;
   WaveLds *wl = (WaveLds *)smem;
   unsigned long long *hist = (unsigned long long *)(wl + kWaves);
-  uint32_t *histc = (uint32_t *)(hist + NB);
-  const int nc_words = ((wide ? 2 * NB : NB) + 3) & ~3;
-  uint32_t *S2lo = histc + nc_words;
-  uint32_t *S2hi = S2lo + kMaxSteps;
-  uint32_t *T = S2hi + kMaxSteps;
-  unsigned long long *evals_lds = (unsigned long long *)(T + kMaxSteps);
+  void *aux = (void *)(hist + NB);
+  const int aux_words = bins == kBinsSplit32 ? ((NB + 3) & ~3) : 2 * NB;  // 32-bit words
+  uint32_t *S2lo = (uint32_t *)aux + aux_words;
+  uint32_t *S2hi = S2lo + ((g.n_s + 3) & ~3);
+  uint32_t *T = S2hi + ((g.n_s + 3) & ~3);
+  unsigned long long *evals_lds = (unsigned long long *)(T + ((g.n_t + 3) & ~3));
   uint32_t *grp_lds = (uint32_t *)(evals_lds + 1);
   // INHOM: rho of the centres and of the tile entries, per wave
   double *rho_lds = (double *)(evals_lds + 2);
@@ -648,7 +661,7 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
   WaveLds &W = wl[wv];
   double *rho_c = rho_lds + wv * 64, *rho_t = rho_lds + (kWaves + wv) * 64;
   for (int b = tid; b < NB; b += kPairThreads) hist[b] = 0;
-  for (int b = tid; b < nc_words; b += kPairThreads) histc[b] = 0;
+  for (int b = tid; b < aux_words; b += kPairThreads) ((uint32_t *)aux)[b] = 0;
   if (tid < g.n_s) {
     S2lo[tid] = (uint32_t)a.S2[tid];
     S2hi[tid] = (uint32_t)(a.S2[tid] >> 32);
@@ -663,10 +676,19 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
   // two 32-bit halves, added to two 64-bit sums)
   auto flush = [&](int set) {
     for (int b = tid; b < NB; b += kPairThreads) {
-      const unsigned long long c =
-          (wide ? ((unsigned long long *)histc)[b] : (unsigned long long)histc[b]) * (SYM ? 2ull : 1ull);
+      const unsigned long long hb = hist[b];
+      unsigned long long c, w;
+      if (packed) {
+        // interior units of 2^23 plus the boundary weights: below 2^55 + 2^57
+        c = hb >> kCountShift;
+        w = ((hb & kUnitMask) << kFracBits) + ((unsigned long long *)aux)[b];
+      } else {
+        c = bins == kBinsSplit64 ? ((unsigned long long *)aux)[b]
+                                 : (unsigned long long)((uint32_t *)aux)[b];
+        w = hb;
+      }
+      c *= SYM ? 2ull : 1ull;
       if (c) {
-        const unsigned long long w = hist[b];
         const size_t o = (size_t)set * NB + b;
         atomicAdd(&a.binC[o], c);
         if (INHOM) {
@@ -676,10 +698,10 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
           if (w >> 32) atomicAdd(&a.binW[2 * o + 1], w >> 32);
         }
         hist[b] = 0;
-        if (wide)
-          ((unsigned long long *)histc)[b] = 0;
+        if (bins == kBinsSplit32)
+          ((uint32_t *)aux)[b] = 0;
         else
-          histc[b] = 0;
+          ((unsigned long long *)aux)[b] = 0;
       }
     }
   };
@@ -718,7 +740,7 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
     const uint32_t base = grp * kItemsPerGroup;
     const int set = (int)uni(a.items[base].set);
     const unsigned long long pend = *evals_lds;
-    if (set != cur_set || pend > kFlushEvals) {
+    if (set != cur_set || pend > (packed ? kFlushEvalsPacked : kFlushEvals)) {
       if (cur_set >= 0) flush(cur_set);
       cur_set = set;
       __syncthreads();
@@ -768,7 +790,7 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
     const uint32_t cst = blocked ? 1u : 2u;
     const uint32_t nb_off = blocked ? (2u * (uint32_t)set + 1u) * g.n_cells : (uint32_t)set * g.n_cells;
     QState q = {0u, 0u, 0u, 0u};
-    Ctx<SYM, MODE, POLY, INHOM> x{W,     q,     g,    hist, histc,  wide,  S2lo,  S2hi, T,
+    Ctx<SYM, MODE, POLY, INHOM> x{W,     q,     g,    hist, aux,    bins,  S2lo,  S2hi, T,
                                   lane,  begin, 0u,   a.P,  a.rho,  rho_c, rho_t};
     unsigned long long ev = 0;
     int ridx = 0;  // index of the stencil row in visiting order
@@ -807,7 +829,9 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
       const uint32_t na = na_of(q);
       if (na) drain_oldest(x, na);
     }
-    if (q.nb) drain_b<MODE, POLY, INHOM>(W, q, q.nb, lane, hist, g, a.P, a.rho);
+    if (q.nb)
+      drain_b<MODE, POLY, INHOM>(W, q, q.nb, lane, packed ? (unsigned long long *)aux : hist, g,
+                                 a.P, a.rho);
     if (lane == 0) atomicAdd(evals_lds, ev);
     evals_total += ev;
   }
@@ -817,7 +841,7 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
 
 template <bool SYM, int MODE, bool POLY, bool INHOM>
 hipError_t launch_t(const PairArgs &a, int grid, hipStream_t s) {
-  const int lds = pair_lds_bytes(a.g.n_s * a.g.n_t, a.wide_counts, INHOM);
+  const int lds = pair_lds_bytes(a.g.n_s, a.g.n_t, a.bins, INHOM);
   hipLaunchKernelGGL((k_pair<SYM, MODE, POLY, INHOM>), dim3(grid), dim3(kPairThreads), lds, s, a);
   return hipGetLastError();
 }
@@ -859,17 +883,20 @@ hipError_t launch_var(int var, const PairArgs &a, int grid, hipStream_t s) {
 
 }  // namespace
 
-int pair_lds_bytes(int n_bins, int wide_counts, bool inhom) {
-  const int nc_words = ((wide_counts ? 2 * n_bins : n_bins) + 3) & ~3;
-  return (int)sizeof(WaveLds) * kWaves + 8 * n_bins + 4 * nc_words + 4 * 3 * kMaxSteps + 16 +
+int pair_lds_bytes(int n_s, int n_t, int bins, bool inhom) {
+  const int n_bins = n_s * n_t;
+  if (inhom && bins == kBinsPacked) bins = kBinsSplit32;
+  const int aux_words = bins == kBinsSplit32 ? ((n_bins + 3) & ~3) : 2 * n_bins;
+  const int tables = 2 * ((n_s + 3) & ~3) + ((n_t + 3) & ~3);
+  return (int)sizeof(WaveLds) * kWaves + 8 * n_bins + 4 * aux_words + 4 * tables + 16 +
          (inhom ? 2 * kWaves * 64 * 8 : 0);
 }
 
 bool pair_poly(const Geom &g) { return g.poly_n >= 3 && (g.edge & 1u); }
 
-hipError_t pair_occupancy(int n_bins, int wide_counts, int symmetric, int mode, int var,
+hipError_t pair_occupancy(int n_s, int n_t, int bins, int symmetric, int mode, int var,
                           int *per_cu) {
-  const int lds = pair_lds_bytes(n_bins, wide_counts, var == 2);
+  const int lds = pair_lds_bytes(n_s, n_t, bins, var == 2);
   return symmetric ? occ_var<true>(var, mode, lds, per_cu) : occ_var<false>(var, mode, lds, per_cu);
 }
 

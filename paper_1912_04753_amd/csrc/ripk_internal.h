@@ -92,7 +92,7 @@ struct PairArgs {
   int blocked;                 // two-type sets in blocked key order: centres from the
                                // type-1 block, neighbours from the type-2 block
   const double *rho;           // inhomogeneous K: 1/lambda per sorted record (else null)
-  int wide_counts;             // 64-bit LDS pair counts (sets of 2^23 points or more)
+  int bins;                    // LDS bin layout (kBinsPacked, kBinsSplit32, kBinsSplit64)
 };
 
 // ---- host runtime (api.cpp) -------------------------------------------------
@@ -166,11 +166,19 @@ hipError_t launch_items(const uint32_t *cs, uint32_t n_sets, const Geom &g, bool
 hipError_t launch_fill_u64(unsigned long long *p, size_t n, unsigned long long v,
                            hipStream_t s);
 hipError_t launch_pair(const PairArgs &a, int grid, hipStream_t s);
-int pair_lds_bytes(int n_bins, int wide_counts, bool inhom = false);
+// LDS bin layouts of the pair kernel.  Packed: one 64-bit word per bin holds
+// the pair count (bits 34-63) and the interior-path weights in units of 2^23
+// (bits 0-33), so a pair costs one LDS atomic; boundary weights go to a second
+// word.  Split: a fixed-point weight word and a 32- or 64-bit count word.
+// Packed needs fewer than 2^30 pending pairs per bin (sets below 2^21 points,
+// flushes every 2^29 candidates); 32-bit counts need sets below 2^23 points.
+constexpr int kBinsPacked = 0, kBinsSplit32 = 1, kBinsSplit64 = 2;
+constexpr int64_t kPackedPoints = 1 << 21;
+int pair_lds_bytes(int n_s, int n_t, int bins, bool inhom = false);
 // the pair kernel takes the polygon weight path (a polygon and spatial correction)
 bool pair_poly(const Geom &g);
 // kernel variant: 0 rectangle, 1 polygon, 2 inhomogeneous (rectangle)
-hipError_t pair_occupancy(int n_bins, int wide_counts, int symmetric, int mode, int var,
+hipError_t pair_occupancy(int n_s, int n_t, int bins, int symmetric, int mode, int var,
                           int *per_cu);
 // 64-bit LDS pair counts are needed from this many points per set on
 constexpr int64_t kWideCountPoints = 1 << 23;

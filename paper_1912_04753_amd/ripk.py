@@ -83,7 +83,7 @@ class EnvOut(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("n_sets", _i64), ("n_points", _i64), ("n_in", _i64), ("n_eval", _i64),
                 ("n_items", _i64), ("pair_grid", _i32), ("symmetric", _i32), ("split", _i32),
-                ("reserved", _i32),
+                ("bin_layout", _i32),
                 ("us_total", _f64), ("us_gen", _f64), ("us_grid", _f64), ("us_pair", _f64),
                 ("us_finalize", _f64)]
 

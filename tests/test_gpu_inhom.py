@@ -79,6 +79,7 @@ def test_inhom_k_matches_oracle(name):
     compare(g, r, s_max, t_max, n_s, n_t, where="inhom " + name)
     if name == "u32_device":
         assert g["info"]["dist_mode"] == 1
+    assert g["stats"]["bin_layout"] == 1  # FP64 weights: weight + count words
 
 
 def test_inhom_constant_intensity_is_the_n2_estimate_at_full_size():

@@ -234,6 +234,8 @@ def test_edge_case_sets(case):
     assert np.array_equal(go["C"], g["C"]) and np.array_equal(go["W"], g["W"])
     gw = gpu_K(x, y, t, *args, flags=ripk.RIPK_PLAN_WIDE_COUNTS | ripk.RIPK_PLAN_ORDERED)
     assert np.array_equal(gw["C"], g["C"]) and np.array_equal(gw["W"], g["W"])
+    # count and interior weight in one LDS word, then weight + 64-bit count
+    assert g["stats"]["bin_layout"] == 0 and gw["stats"]["bin_layout"] == 2
 
 
 def test_wide_distances():
@@ -277,6 +279,8 @@ def test_maximum_grid(case):
     assert np.array_equal(go["C"], g["C"]) and np.array_equal(go["W"], g["W"])
     gw = gpu_K(x, y, t, *args, flags=ripk.RIPK_PLAN_WIDE_COUNTS)
     assert np.array_equal(gw["C"], g["C"]) and np.array_equal(gw["W"], g["W"])
+    if case == "packed":  # 4096 bins: one word per bin would cost occupancy
+        assert g["stats"]["bin_layout"] == 1 and gw["stats"]["bin_layout"] == 2
     m, seed = 3, 99
     plan = ripk.ripk_plan(ripk.make_desc(*args, n_max=n, m_max=m))
     try:
