@@ -218,7 +218,9 @@ int64_t caps_bytes(const Caps &c) {
   bytes += 16 * c.items;                      // work items
   bytes += 8 * 3 * c.SNB;                     // bins
   bytes += 8 * 4 * c.SNB;                     // C, W, K, L
-  bytes += 8 * 6 * c.NB + 8 * 2 * kMaxSteps + 32;
+  bytes += 8 * 6 * c.NB + 8 * 2 * kMaxSteps;  // envelopes, L_obs, thresholds
+  bytes += 8 * (kQueues + 1) * kQueueStride;   // scalars and work-queue blocks
+  bytes += 8 * (kScalWords + kPackRows * c.NB);  // result staging
   bytes += 3 * 4 * c.P;                       // copy of the observed set (resampling)
   bytes += 8 * c.V + 2 * (kNearMax + 1) * c.NXY;  // polygon and its per-cell edge lists
   bytes += 16 * c.R;                          // intensities and their sorted reciprocals

@@ -4,14 +4,16 @@
 // decides the indicator of Eq. 3 (d_ij <= s_max and u_ij <= t_max, exact
 // integers), finds the smallest grid step (k, l) that contains the pair, and
 // adds the count and the edge-corrected weight 1/(omega_ij v_ij) of Sec. 3 to
-// an (s, t) histogram held in LDS.  Histograms are merged into 128-bit global
-// bins with 64-bit atomics when a workgroup moves on to another point set.
+// an (s, t) histogram held in LDS.  Histograms are merged into the set's global
+// fixed-point bins with 64-bit atomics when a workgroup moves on to another
+// point set.
 //
 // Mapping
 //   * workgroup = 4 wavefronts; a work item = up to 64 consecutive centres of
 //     one x-row of cells (or of one cell when some points are not centres), one
 //     lane per centre; a workgroup grabs 4 items of one set at a time from a
-//     global counter (persistent launch, items padded per set);
+//     work queue in one partition per XCD (persistent launch, items padded per
+//     set);
 //   * neighbours are visited as contiguous runs of the sorted point array (the
 //     x-cells within reach of the item's first to last centre, per (y, t) row
 //     of the stencil), staged per wave in an LDS tile of 64 points (the next
