@@ -2,9 +2,12 @@
 
 One step = the whole path over the batched-envelope workload: K/L of the
 observed set (100,000 uniform points in 20 km x 20 km x 180 d, 25 x 15 grid to
-2 km / 30 d, isotropic spatial + temporal correction) followed by the envelope
-of 99 Monte Carlo CSR simulations of the same size drawn on the device.  Inputs
-are resident in device memory before timing starts.
+2 km / 30 d, isotropic spatial + temporal correction) and the envelope of 99
+Monte Carlo CSR simulations of the same size drawn on the device, in one
+``ripk_compute_K_envelope`` call (the observed set is one more set of the
+simulations' launch).  Inputs are resident in device memory before timing
+starts.  ``two_calls`` times the same step as ``ripk_compute_K`` followed by
+``ripk_simulate_envelope``.
 
 Printed: one JSON line.  ``value`` = ordered in-range pair tests per second
 (N_in over the step, in units of 1e9/s); ``sims_per_s``; ``roofline`` for the
@@ -218,17 +221,21 @@ def main():
 
     def step():
         t0 = time.perf_counter()
+        ripk.ripk_compute_K_envelope(plan, dx, dy, dt, m, cfg["seed"], stream=stream)
+        st_ = ripk.ripk_plan_stats(plan)
+        i = ripk.ripk_plan_get_info(plan)
+        cells["step"] = [i["cell_s"], i["cell_t"]]
+        return st_, time.perf_counter() - t0
+
+    def step2():
+        # the same step as two calls: observed set, then the simulations
+        t0 = time.perf_counter()
         r = ripk.ripk_compute_K(plan, dx, dy, dt, stream=stream)
         s_obs = ripk.ripk_plan_stats(plan)
-        i = ripk.ripk_plan_get_info(plan)
-        cells["observed"] = [i["cell_s"], i["cell_t"]]
         t1 = time.perf_counter()
         ripk.ripk_simulate_envelope(plan, n, m, cfg["seed"], L_obs=r["L"], stream=stream)
         s_sim = ripk.ripk_plan_stats(plan)
-        i = ripk.ripk_plan_get_info(plan)
-        cells["simulations"] = [i["cell_s"], i["cell_t"]]
-        t2 = time.perf_counter()
-        return s_obs, s_sim, t1 - t0, t2 - t1
+        return s_obs, s_sim, t1 - t0, time.perf_counter() - t1
 
     t_tune = time.perf_counter()
     if not args.no_autotune:
@@ -247,14 +254,26 @@ def main():
     if args.main_only:
         plan.destroy()
         ms = 1e3 * t_total / args.steps
-        n_in = recs[0][0]["n_in"] + recs[0][1]["n_in"]
+        n_in = recs[0][0]["n_in"]
         print(json.dumps({"metric": METRIC, "value": round(n_in / (t_total / args.steps) / 1e9, 4),
                           "unit": "G pair tests/s", "n_gpus": 1, "steps": args.steps,
                           "warmup": args.warmup, "ms_per_step": round(ms, 4),
-                          "pair_kernel_us": {"observed": [r[0]["us_pair"] for r in recs],
-                                             "simulations": [r[1]["us_pair"] for r in recs]},
+                          "pair_kernel_us": [r[0]["us_pair"] for r in recs],
                           "note": "main steps only"}), flush=True)
         return
+    # the same step as two calls
+    step2()  # tunes the observed call's cells
+    torch.cuda.synchronize()
+    t_2 = time.perf_counter()
+    recs2 = [step2() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    two_ms = 1e3 * (time.perf_counter() - t_2) / args.steps
+    two_calls = {"ms_per_step": round(two_ms, 4),
+                 "pair_tests_per_s_G": round((recs2[0][0]["n_in"] + recs2[0][1]["n_in"]) /
+                                             (two_ms * 1e-3) / 1e9, 3),
+                 "sims_per_s": round(m / (sum(r[3] for r in recs2) / len(recs2)), 3),
+                 "pair_kernel_us": {"observed": round(sum(r[0]["us_pair"] for r in recs2) / len(recs2), 2),
+                                    "simulations": round(sum(r[1]["us_pair"] for r in recs2) / len(recs2), 2)}}
     # end to end with the observed points in host memory (H2D copy inside the call)
     t_h = time.perf_counter()
     for _ in range(3):
@@ -263,8 +282,8 @@ def main():
     n_in_obs = ripk.ripk_plan_stats(plan)["n_in"]
     # the same step through a plan that replays captured HIP graphs (no per-phase
     # timing), on a stream of its own, with the tuned cells of the timed plan
-    cd = max(1, round(cfg["s_max"] / cells["simulations"][0]))
-    td = max(1, round(cfg["t_max"] / cells["simulations"][1]))
+    cd = max(1, round(cfg["s_max"] / cells["step"][0]))
+    td = max(1, round(cfg["t_max"] / cells["step"][1]))
     gdesc = ripk.make_desc(cfg["window"], cfg["s_max"], cfg["t_max"], cfg["n_s"], cfg["n_t"],
                            n_max=n, m_max=m, flags=ripk.RIPK_PLAN_GRAPH, cell_div=cd, tcell_div=td)
     gplan = ripk.ripk_plan(gdesc)
@@ -272,8 +291,7 @@ def main():
     gsp = gs.cuda_stream
 
     def gstep():
-        r = ripk.ripk_compute_K(gplan, dx, dy, dt, stream=gsp)
-        ripk.ripk_simulate_envelope(gplan, n, m, cfg["seed"], L_obs=r["L"], stream=gsp)
+        ripk.ripk_compute_K_envelope(gplan, dx, dy, dt, m, cfg["seed"], stream=gsp)
 
     for _ in range(2):
         gstep()
@@ -309,11 +327,9 @@ def main():
                                           flags=ripk.RIPK_PLAN_CROSS | ripk.RIPK_PLAN_AUTOTUNE))
 
     def xstep():
-        ripk.ripk_compute_K(xplan, dx, dy, dt, n_centres=n1, stream=stream)
-        a = ripk.ripk_plan_stats(xplan)["n_in"]
         t1 = time.perf_counter()
-        ripk.ripk_simulate_envelope(xplan, n, m, cfg["seed"], stream=stream)
-        return a + ripk.ripk_plan_stats(xplan)["n_in"], time.perf_counter() - t1
+        ripk.ripk_compute_K_envelope(xplan, dx, dy, dt, m, cfg["seed"], n_centres=n1, stream=stream)
+        return ripk.ripk_plan_stats(xplan)["n_in"], time.perf_counter() - t1
 
     xstep()  # tuning
     xstep()
@@ -340,12 +356,10 @@ def main():
                                           flags=ripk.RIPK_PLAN_AUTOTUNE | ripk.RIPK_PLAN_TIMING))
 
     def pstep():
-        r = ripk.ripk_compute_K(pplan, px, py, pt, stream=stream)
-        a = ripk.ripk_plan_stats(pplan)
         t1 = time.perf_counter()
-        ripk.ripk_simulate_envelope(pplan, pn, pm, pc["seed"], L_obs=r["L"], stream=stream)
+        ripk.ripk_compute_K_envelope(pplan, px, py, pt, pm, pc["seed"], stream=stream)
         b = ripk.ripk_plan_stats(pplan)
-        return a["n_in"] + b["n_in"], time.perf_counter() - t1, a["us_pair"], b["us_pair"]
+        return b["n_in"], time.perf_counter() - t1, b["us_pair"]
 
     pstep()  # tuning
     pstep()
@@ -358,8 +372,7 @@ def main():
     polygon = {"ms_per_step": round(p_ms, 3),
                "pair_tests_per_s_G": round(ps[0][0] / (p_ms * 1e-3) / 1e9, 3),
                "sims_per_s": round(pm / (sum(v[1] for v in ps) / 3), 3),
-               "pair_kernel_us": {"observed": round(sum(v[2] for v in ps) / 3, 2),
-                                  "simulations": round(sum(v[3] for v in ps) / 3, 2)},
+               "pair_kernel_us": round(sum(v[2] for v in ps) / 3, 2),
                "cells_m_s": [pi_["cell_s"], pi_["cell_t"]],
                "note": "100k uniform points inside an 85-vertex star-shaped boundary "
                        "(46% of the 20 km x 20 km window), 180 d, 25x15 grid to 2 km/30 d, "
@@ -398,13 +411,12 @@ def main():
                                               flags=ripk.RIPK_PLAN_AUTOTUNE))
 
         def wstep():
-            r = ripk.ripk_compute_K(wplan, wx, wy, wt, stream=stream)
-            a = ripk.ripk_plan_stats(wplan)["n_in"]
-            if wm == 0:
-                return a, 0.0
             t1 = time.perf_counter()
-            ripk.ripk_simulate_envelope(wplan, wn, wm, wc["seed"], L_obs=r["L"], stream=stream)
-            return a + ripk.ripk_plan_stats(wplan)["n_in"], time.perf_counter() - t1
+            if wm == 0:
+                ripk.ripk_compute_K(wplan, wx, wy, wt, stream=stream)
+            else:
+                ripk.ripk_compute_K_envelope(wplan, wx, wy, wt, wm, wc["seed"], stream=stream)
+            return ripk.ripk_plan_stats(wplan)["n_in"], time.perf_counter() - t1
 
         wstep()  # tuning
         torch.cuda.synchronize()
@@ -423,16 +435,17 @@ def main():
     plan.destroy()
 
     ms = 1e3 * t_total / args.steps
-    n_in = recs[0][0]["n_in"] + recs[0][1]["n_in"]
+    n_in = recs[0][0]["n_in"]
     value = n_in / (t_total / args.steps) / 1e9
-    t_sim = sum(r[3] for r in recs) / len(recs)
-    # dominant kernel: the persistent pair kernel, two launches per step
-    pair_us = [r[0]["us_pair"] for r in recs] + [r[1]["us_pair"] for r in recs]
-    evals = recs[0][0]["n_eval"] + recs[0][1]["n_eval"]
+    t_step = sum(r[1] for r in recs) / len(recs)
+    # dominant kernel: the persistent pair kernel, one launch per step (the
+    # observed set and the simulations)
+    pair_us = [r[0]["us_pair"] for r in recs]
+    evals = recs[0][0]["n_eval"]
     avg_us = sum(pair_us) / len(pair_us)
-    achieved = OPS_PER_EVAL * (evals / 2) / (avg_us * 1e-6) / 1e12
+    achieved = OPS_PER_EVAL * evals / (avg_us * 1e-6) / 1e12
     # the same with the binning work of the in-range pairs counted as well
-    achieved_all = (OPS_PER_EVAL * evals + OPS_PER_IN * n_in) / 2 / (avg_us * 1e-6) / 1e12
+    achieved_all = (OPS_PER_EVAL * evals + OPS_PER_IN * n_in) / (avg_us * 1e-6) / 1e12
     peak = PEAK_LANE_OPS / 1e12
     from paper_1912_04753_amd.profiling import load_traffic
     tr = load_traffic(os.path.join(ROOT, "profiles", "k_pair_uniform100k_99csr_traffic.json"))
@@ -453,7 +466,8 @@ def main():
                                "25x15 grid to 2km/30d, observed K + 99 CSR simulations",
                    "n": n, "sims": m, "n_s": cfg["n_s"], "n_t": cfg["n_t"],
                    "cells_m_s": cells, "autotune": not args.no_autotune},
-        "sims_per_s": round(m / t_sim, 3),
+        "sims_per_s": round(m / t_step, 3),
+        "two_calls": two_calls,
         "graph_ms_per_step": round(graph_ms, 4),
         "resampled_simulations": resampled,
         "cross_k": cross,
@@ -467,8 +481,7 @@ def main():
                                 "note": "ripk_compute_K on host arrays: PCIe copy of 1.2 MB inside the call"},
         "n_in_per_step": n_in,
         "n_eval_per_step": evals,
-        "pair_kernel_us": {"observed": round(sum(r[0]["us_pair"] for r in recs) / len(recs), 2),
-                           "simulations": round(sum(r[1]["us_pair"] for r in recs) / len(recs), 2)},
+        "pair_kernel_us": round(avg_us, 2),
         "roofline": {"bound": "alu", "achieved": round(achieved, 4), "peak": round(peak, 4),
                      "unit": "T int lane-ops/s", "frac": round(achieved / peak, 4),
                      "traffic": (round(tr["bytes_per_launch"]) if tr else None),

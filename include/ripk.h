@@ -270,6 +270,21 @@ ripk_status ripk_compute_K(ripk_plan_t plan, const ripk_points *pts, void *strea
 ripk_status ripk_simulate_envelope(ripk_plan_t plan, int64_t n, int32_t m, uint64_t seed,
                                    const double *L_obs, void *stream, ripk_env_out *out);
 
+/* One Monte Carlo test as the paper's job runs it (Sec. 3 and 4): K, L of the
+ * observed set and the envelopes of m simulations of n = pts->n points, with
+ * dL_hi against the observed L.  Results equal ripk_compute_K followed by
+ * ripk_simulate_envelope(..., L_obs = the observed L, ...) bit for bit.  With
+ * CSR simulations the observed set is set 0 of the simulations' launch (one
+ * sort, one pair-kernel launch, one copy back); PERMUTE and BOOTSTRAP plans,
+ * and centre subsets without RIPK_PLAN_CROSS, run the two calls.  Either
+ * output may be NULL; C_sims, W_sims, K_sims of env_out cover the m
+ * simulations.  The plan's stats cover the m + 1 sets (two-call cases: the
+ * simulations).  Errors: those of the two calls; EINVAL for inhomogeneous
+ * plans (no simulations). */
+ripk_status ripk_compute_K_envelope(ripk_plan_t plan, const ripk_points *pts, int32_t m,
+                                    uint64_t seed, void *stream, ripk_K_out *k_out,
+                                    ripk_env_out *env_out);
+
 /* Counters and timings of the plan's last compute call. */
 ripk_status ripk_plan_stats(ripk_plan_t plan, ripk_stats *out);
 

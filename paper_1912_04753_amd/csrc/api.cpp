@@ -2,7 +2,8 @@
 // pool, the launch sequence of one evaluation, and the exported entry points.
 //
 // One evaluation of S point sets of n points each (S = 1 for an observed set,
-// S = m for Monte Carlo simulations, Sec. 3) runs, on the caller's stream:
+// S = m for Monte Carlo simulations, Sec. 3, S = m + 1 for an observed set and
+// its simulations together) runs, on the caller's stream:
 //   keys (or on-device CSR / resampling draw) -> radix sort by (set, cell,
 //   halo) or, for two-type sets, (set, type, cell) -> cell bounds -> sorted
 //   point records -> work items -> pair kernel (persistent) -> per-set prefix
@@ -297,8 +298,11 @@ ripk_status derive(const ripk_plan_desc *d, Layout *L) {
     return fail(RIPK_EINVAL, "unknown simulation method");
   if (d->n_max < 2) return fail(RIPK_EINVAL, "n_max must be >= 2");
   if (d->m_max < 0) return fail(RIPK_EINVAL, "m_max must be >= 0");
-  const int64_t S = std::max<int64_t>(1, d->m_max);
-  if (S * d->n_max >= (1LL << 31)) return fail(RIPK_EINVAL, "(m_max)*n_max must be below 2^31");
+  // sets per launch: the simulations, plus the observed set that
+  // ripk_compute_K_envelope evaluates in the same launch
+  const int64_t S = d->m_max > 0 ? (int64_t)d->m_max + 1 : 1;
+  if ((int64_t)(d->m_max + 1) * d->n_max >= (1LL << 31))
+    return fail(RIPK_EINVAL, "(m_max + 1)*n_max must be below 2^31");
   if (d->cell_div < 0 || d->cell_div > 8 || d->tcell_div < 0 || d->tcell_div > 8)
     return fail(RIPK_EINVAL, "cell_div and tcell_div must be in [0, 8]");
 
@@ -401,7 +405,7 @@ struct ripk_plan_s {
   uint64_t bind_gen = 0;               // bumped whenever a geometry is bound
   // RIPK_PLAN_GRAPH: the captured launch sequence of the last call shape
   hipGraphExec_t gexec = nullptr;
-  uint64_t gkey[13] = {};
+  uint64_t gkey[14] = {};
   int device = 0;
   int cus = 0;
   size_t lds_max = 0;  // LDS bytes a workgroup may use on this device
@@ -485,10 +489,13 @@ struct DeviceGuard {
 // st (kernels only, and event records when timing): capturable into a graph.
 // With `simulate` the points are drawn on the device; otherwise keys come from
 // (x, y, t).
+// with_obs (CSR simulations only): set 0 is the observed set, already in
+// p->x, p->y, p->t [0, n), and sets 1..S-1 are the simulations; the envelope
+// covers those and takes set 0's L as L_obs.
 ripk_status enqueue_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_centres,
                          const int32_t *x, const int32_t *y, const int32_t *t, bool simulate,
                          uint64_t seed, bool has_Lobs, hipStream_t st, bool symmetric,
-                         bool timing, uint32_t S_split) {
+                         bool timing, uint32_t S_split, bool with_obs = false) {
   const Geom &g = p->lay.g;
   const uint32_t NB = (uint32_t)p->lay.info.n_bins;
   const uint32_t N = S * n;
@@ -498,10 +505,14 @@ ripk_status enqueue_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_cent
   unsigned long long *queues = p->scal + kQueueStride;
   HIPCHK(launch_fill_u64(p->scal, (size_t)(kQueues + 1) * kQueueStride, 0ull, st));
   const bool cross = (p->desc.flags & RIPK_PLAN_CROSS) != 0;
+  const uint32_t so = with_obs ? 1u : 0u;  // sets before the first simulation
   if (simulate) {
+    if (with_obs)
+      HIPCHK(launch_keys(p->x, p->y, p->t, n, n_centres, 0, 1, g, cross, p->keys[0], p->vals[0],
+                         err, st));
     if (p->desc.sim_method == RIPK_SIM_CSR)
-      HIPCHK(launch_csr(n, n_centres, S, seed, g, cross, p->x, p->y, p->t, p->keys[0], p->vals[0], err,
-                        st));
+      HIPCHK(launch_csr(n, n_centres, S - so, seed, g, cross, p->x, p->y, p->t, p->keys[0],
+                        p->vals[0], err, so, st));
     else
       HIPCHK(launch_resample(p->desc.sim_method == RIPK_SIM_PERMUTE ? 1 : 2, n, n_centres, S,
                              seed, cross, p->ox, p->oy, p->ot, g, p->x, p->y, p->t, p->keys, p->vals,
@@ -590,7 +601,9 @@ ripk_status enqueue_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_cent
   HIPCHK(launch_finalize(p->binC, p->binW, S, g.n_s, g.n_t, (double)p->desc.s_max,
                          (double)p->desc.t_max, AD, Nn, p->outC, p->outW, p->outK, p->outL,
                          queues, p->scal, st, inhom));
-  if (simulate)
+  if (simulate && with_obs)
+    HIPCHK(launch_envelope(p->outK + NB, p->outL + NB, S - 1, (int)NB, p->outL, p->env, st));
+  else if (simulate)
     HIPCHK(launch_envelope(p->outK, p->outL, S, (int)NB, has_Lobs ? p->Lobs : nullptr, p->env, st));
   if (timing) HIPCHK(hipEventRecord(p->ev[4], st));
   p->stats.pair_grid = grid;
@@ -606,7 +619,8 @@ ripk_status enqueue_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_cent
 // captures afresh.
 ripk_status run_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_centres, const int32_t *x,
                      const int32_t *y, const int32_t *t, bool simulate, uint64_t seed,
-                     const double *L_obs, hipStream_t st, bool symmetric, uint32_t S_split = 0) {
+                     const double *L_obs, hipStream_t st, bool symmetric, uint32_t S_split = 0,
+                     bool with_obs = false) {
   if (S_split == 0) S_split = S;
   const uint32_t NB = (uint32_t)p->lay.info.n_bins;
   const bool has_Lobs = simulate && L_obs != nullptr;
@@ -615,18 +629,18 @@ ripk_status run_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_centres,
   const bool graph = (p->desc.flags & RIPK_PLAN_GRAPH) && !timing && st != nullptr;
   if (!graph)
     return enqueue_sets(p, S, n, n_centres, x, y, t, simulate, seed, has_Lobs, st, symmetric, timing,
-                        S_split);
-  const uint64_t key[13] = {S, n, n_centres, (uint64_t)simulate, (uint64_t)symmetric,
+                        S_split, with_obs);
+  const uint64_t key[14] = {S, n, n_centres, (uint64_t)simulate, (uint64_t)symmetric,
                             (uint64_t)(uintptr_t)x, (uint64_t)(uintptr_t)y, (uint64_t)(uintptr_t)t,
                             seed, (uint64_t)has_Lobs, p->bind_gen, S_split,
-                            (uint64_t)(uintptr_t)p->cur_lam};
+                            (uint64_t)(uintptr_t)p->cur_lam, (uint64_t)with_obs};
   if (!p->gexec || std::memcmp(key, p->gkey, sizeof key) != 0) {
     if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
     p->gexec = nullptr;
     HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     const ripk_status s =
         enqueue_sets(p, S, n, n_centres, x, y, t, simulate, seed, has_Lobs, st, symmetric, false,
-                     S_split);
+                     S_split, with_obs);
     hipGraph_t gr = nullptr;
     const hipError_t e = hipStreamEndCapture(st, &gr);
     if (s != RIPK_OK) {
@@ -854,7 +868,7 @@ const Caps &plan_caps(const ripk_plan_s *p) { return p->caps; }
 ripk_status run_tuned(ripk_plan_s *p, int which, uint32_t S, uint32_t S_tune, uint32_t n,
                       uint32_t nc, const int32_t *x, const int32_t *y, const int32_t *t,
                       bool simulate, uint64_t seed, const double *L_obs, hipStream_t st,
-                      bool sym) {
+                      bool sym, bool with_obs = false) {
   if (p->user_desc.flags & RIPK_PLAN_AUTOTUNE) {
     TuneState &ts = p->tune[which];
     ripk_plan_desc d = p->user_desc;
@@ -869,7 +883,7 @@ ripk_status run_tuned(ripk_plan_s *p, int which, uint32_t S, uint32_t S_tune, ui
         ts.us[i] = 1e300;
         for (int rep = 0; rep < 2; ++rep) {  // best of two: candidates can be a few % apart
           HIPCHK(hipEventRecord(p->tev[0], st));
-          s = run_sets(p, S_tune, n, nc, x, y, t, simulate, seed, nullptr, st, sym, S);
+          s = run_sets(p, S_tune, n, nc, x, y, t, simulate, seed, nullptr, st, sym, S, with_obs);
           if (s != RIPK_OK) return s;
           HIPCHK(hipEventRecord(p->tev[1], st));
           uint32_t err = 0;
@@ -896,7 +910,7 @@ ripk_status run_tuned(ripk_plan_s *p, int which, uint32_t S, uint32_t S_tune, ui
       if (s != RIPK_OK) return s;
     }
   }
-  return run_sets(p, S, n, nc, x, y, t, simulate, seed, L_obs, st, sym);
+  return run_sets(p, S, n, nc, x, y, t, simulate, seed, L_obs, st, sym, 0, with_obs);
 }
 
 void plan_free(ripk_plan_s *p) { release(p); }
@@ -1073,6 +1087,91 @@ ripk_status ripk_simulate_envelope(ripk_plan_t p, int64_t n, int32_t m, uint64_t
     if (out->W_sims) HIPCHK(hipMemcpyAsync(out->W_sims, p->outW, 8 * NB * m, hipMemcpyDeviceToHost, st));
     if (out->K_sims) HIPCHK(hipMemcpyAsync(out->K_sims, p->outK, 8 * NB * m, hipMemcpyDeviceToHost, st));
     if (out->C_sims || out->W_sims || out->K_sims) HIPCHK(hipStreamSynchronize(st));
+  }
+  p->stats.us_total = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
+  return RIPK_OK;
+}
+
+ripk_status ripk_compute_K_envelope(ripk_plan_t p, const ripk_points *pts, int32_t m,
+                                    uint64_t seed, void *stream, ripk_K_out *kout,
+                                    ripk_env_out *eout) {
+  if (!p || !pts) return fail(RIPK_EINVAL, "null plan or points");
+  if (p->desc.flags & RIPK_PLAN_INHOM)
+    return fail(RIPK_EINVAL,
+                "inhomogeneous K plans take no simulations (the null model needs the "
+                "intensity as a function)");
+  if (m < 1 || m > p->desc.m_max) return fail(RIPK_EINVAL, "m = %d outside [1, m_max = %d]", m, p->desc.m_max);
+  const int64_t n = pts->n;
+  const int64_t nc = pts->n_centres ? pts->n_centres : n;
+  const bool cross = (p->desc.flags & RIPK_PLAN_CROSS) != 0;
+  const size_t NB = (size_t)p->lay.info.n_bins;
+  if (p->desc.sim_method != RIPK_SIM_CSR || (!cross && nc != n)) {
+    // simulations drawn from the observed set, or a centre subset: the two calls
+    std::vector<double> Lh(NB);
+    ripk_K_out ko = kout ? *kout : ripk_K_out{};
+    if (!ko.L) ko.L = Lh.data();
+    ripk_status s = ripk_compute_K(p, pts, stream, &ko);
+    if (s != RIPK_OK) return s;
+    return ripk_simulate_envelope(p, n, m, seed, ko.L, stream, eout);
+  }
+  if (n < 2) return fail(RIPK_EINVAL, "need n >= 2 points (n(n-1) = 0 otherwise)");
+  if (n > p->desc.n_max) return fail(RIPK_EINVAL, "n = %lld exceeds n_max = %lld", (long long)n, (long long)p->desc.n_max);
+  if (cross && (pts->n_centres < 1 || pts->n_centres >= n))
+    return fail(RIPK_EINVAL, "cross K needs 1 <= n_centres < n (type 1 = points [0, n_centres))");
+  if (!pts->x || !pts->y || !pts->t) return fail(RIPK_EINVAL, "null coordinate array");
+  auto t0 = std::chrono::steady_clock::now();
+  DeviceGuard dg(p->device);
+  hipStream_t st = (hipStream_t)stream;
+  // the observed points become set 0 of the simulation launch
+  const hipMemcpyKind kind = pts->on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  HIPCHK(hipMemcpyAsync(p->x, pts->x, sizeof(int32_t) * n, kind, st));
+  HIPCHK(hipMemcpyAsync(p->y, pts->y, sizeof(int32_t) * n, kind, st));
+  HIPCHK(hipMemcpyAsync(p->t, pts->t, sizeof(int32_t) * n, kind, st));
+  p->cur_lam = nullptr;
+  p->split_n = p->split_n1 = 0;
+  const bool sym = !(p->desc.flags & RIPK_PLAN_ORDERED) && !cross;
+  ripk_status s = run_tuned(p, 1, (uint32_t)m + 1, (uint32_t)std::min(m + 1, kTuneSims),
+                            (uint32_t)n, (uint32_t)nc, p->x, p->y, p->t, true, seed, nullptr, st,
+                            sym, true);
+  if (s != RIPK_OK) return s;
+  // rows 0-3: C, W, K, L of the observed set; rows 4-8: the envelopes
+  PackRows rows = {};
+  double *dst[kPackRows] = {};
+  if (kout) {
+    void *k[4] = {kout->C, kout->W, kout->K, kout->L};
+    const unsigned long long *src[4] = {p->outC, (const unsigned long long *)p->outW,
+                                        (const unsigned long long *)p->outK,
+                                        (const unsigned long long *)p->outL};
+    for (int r = 0; r < 4; ++r) {
+      dst[r] = (double *)k[r];
+      rows.p[r] = k[r] ? src[r] : nullptr;
+    }
+  }
+  if (eout) {
+    double *e[5] = {eout->K_lo, eout->K_hi, eout->L_lo, eout->L_hi, eout->dL_hi};
+    for (int r = 0; r < 5; ++r) {
+      dst[4 + r] = e[r];
+      rows.p[4 + r] = e[r] ? (const unsigned long long *)(p->env + r * NB) : nullptr;
+    }
+  }
+  uint32_t err = 0;
+  s = collect_stats(p, st, (uint32_t)m + 1, (uint32_t)n, &err, &rows);
+  if (s != RIPK_OK) return s;
+  if (err) return err_status(err);
+  if (cross) {
+    p->split_n = n;
+    p->split_n1 = nc;
+  }
+  for (int r = 0; r < kPackRows; ++r)
+    if (dst[r]) std::memcpy(dst[r], p->hstage + kScalWords + r * NB, 8 * NB);
+  if (eout && (eout->C_sims || eout->W_sims || eout->K_sims)) {
+    if (eout->C_sims)
+      HIPCHK(hipMemcpyAsync(eout->C_sims, p->outC + NB, 8 * NB * m, hipMemcpyDeviceToHost, st));
+    if (eout->W_sims)
+      HIPCHK(hipMemcpyAsync(eout->W_sims, p->outW + NB, 8 * NB * m, hipMemcpyDeviceToHost, st));
+    if (eout->K_sims)
+      HIPCHK(hipMemcpyAsync(eout->K_sims, p->outK + NB, 8 * NB * m, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
   }
   p->stats.us_total = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
   return RIPK_OK;

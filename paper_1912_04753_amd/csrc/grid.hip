@@ -85,14 +85,15 @@ __device__ __forceinline__ U64x4 philox4x64_10(U64x4 c, uint64_t k0, uint64_t k1
 // counter (i, s, a, 0) until the point lies strictly inside (the polygon covers
 // at least 1/1024 of the window, so 2^16 attempts all failing has probability
 // below e^-64; it sets bit 1 of *err).  Writes the SoA points and the (key,
-// value) pairs for the sort, sets ordered simulation-major.
+// value) pairs for the sort, sets ordered simulation-major; simulation s is
+// stored as set s + set_off (entries from set_off * n on), its draws unchanged.
 constexpr uint32_t kMaxAttempts = 1u << 16;
 
 __global__ void k_csr(uint32_t n, uint32_t n_centres, uint32_t m, uint64_t seed, Geom g,
                       int blocked, int32_t *__restrict__ x,
                       int32_t *__restrict__ y, int32_t *__restrict__ t,
                       uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
-                      uint32_t *__restrict__ err) {
+                      uint32_t *__restrict__ err, uint32_t set_off) {
   uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= (uint64_t)n * m) return;
   uint32_t s = (uint32_t)(gid / n), i = (uint32_t)(gid - (uint64_t)s * n);
@@ -115,13 +116,14 @@ __global__ void k_csr(uint32_t n, uint32_t n_centres, uint32_t m, uint64_t seed,
       break;
     }
   }
-  x[gid] = px;
-  y[gid] = py;
-  t[gid] = pt;
+  const uint64_t w = gid + (uint64_t)set_off * n;
+  x[w] = px;
+  y[w] = py;
+  t[w] = pt;
   bool bad;
   uint32_t cell = cell_of(px, py, pt, g, &bad);
-  keys[gid] = sort_key(s, cell, i >= n_centres ? 1u : 0u, g, blocked != 0);
-  vals[gid] = (uint32_t)gid;
+  keys[w] = sort_key(s + set_off, cell, i >= n_centres ? 1u : 0u, g, blocked != 0);
+  vals[w] = (uint32_t)w;
 }
 
 // ---- simulations drawn from the observed points (Sec. 3) --------------------
@@ -543,11 +545,11 @@ hipError_t launch_keys(const int32_t *x, const int32_t *y, const int32_t *t, uin
 
 hipError_t launch_csr(uint32_t n, uint32_t n_centres, uint32_t m, uint64_t seed, const Geom &g,
                       int blocked, int32_t *x, int32_t *y, int32_t *t, uint32_t *keys,
-                      uint32_t *vals, uint32_t *err, hipStream_t s) {
+                      uint32_t *vals, uint32_t *err, uint32_t set_off, hipStream_t s) {
   uint64_t tot = (uint64_t)n * m;
   if (tot == 0) return hipSuccess;
   hipLaunchKernelGGL(k_csr, dim3(blocks_for(tot, kThreads)), dim3(kThreads), 0, s, n, n_centres,
-                     m, seed, g, blocked, x, y, t, keys, vals, err);
+                     m, seed, g, blocked, x, y, t, keys, vals, err, set_off);
   return hipGetLastError();
 }
 

@@ -130,10 +130,11 @@ hipError_t launch_keys(const int32_t *x, const int32_t *y, const int32_t *t, uin
 // cross-K plan (halo slot, or the type-2 block of blocked keys; n_centres = n
 // otherwise)
 // (polygon: rejection sampling; a point that finds no attempt inside sets bit 1
-// of *err)
+// of *err).  Simulation s is stored as set s + set_off: x, y, t, keys and vals
+// are the arrays of all sets, written from entry set_off * n on.
 hipError_t launch_csr(uint32_t n, uint32_t n_centres, uint32_t m, uint64_t seed, const Geom &g,
                       int blocked, int32_t *x, int32_t *y, int32_t *t, uint32_t *keys,
-                      uint32_t *vals, uint32_t *err, hipStream_t s);
+                      uint32_t *vals, uint32_t *err, uint32_t set_off, hipStream_t s);
 // Simulated sets drawn from the observed points ox, oy, ot (n each): method 1
 // random permutation of the time labels, 2 bootstrap (each of the types
 // [0, n_centres) and [n_centres, n) from itself); writes x, y, t and the cell
@@ -196,7 +197,7 @@ hipError_t launch_envelope(const double *K, const double *L, uint32_t m, int n_b
 // scal, then each non-null row of nb 8-byte words at its slot (row r at
 // kScalWords + r*nb).
 constexpr int kScalWords = 4;
-constexpr int kPackRows = 5;
+constexpr int kPackRows = 9;
 struct PackRows {
   const unsigned long long *p[kPackRows];
 };

@@ -34,7 +34,12 @@ def _dispatches(csv_path, counter):
     return [(d, n, v) for d, (n, v) in sorted(agg.items())]
 
 
-def traffic(fetch_csv, write_csv, last=2):
+# pair-kernel launches per benchmark step: the observed set and the
+# simulations share one launch
+LAUNCHES_PER_STEP = 1
+
+
+def traffic(fetch_csv, write_csv, last=LAUNCHES_PER_STEP):
     """HBM bytes per pair-kernel launch (mean over the run's last `last` launches,
     i.e. one benchmark step after the plan's tuning calls, as the roofline's
     achieved rate is) from two counter passes."""
@@ -99,7 +104,7 @@ def summary(title, stats_csv, trace_csv, steps, tr, bench_line=None):
     """Markdown summary of one profiled benchmark run: the kernel table, the pair
     kernel's launches of the timed steps, and the traffic record."""
     launches = pair_launches(trace_csv)
-    timed = launches[-2 * steps:]
+    timed = launches[-LAUNCHES_PER_STEP * steps:]
     lines = [f"# {title}", "",
              f"Pair-kernel source hash (sha256 of `paper_1912_04753_amd/csrc/pair.hip`, first 16 hex): "
              f"`{tr['kernel_source_sha256']}`.", "",
@@ -108,8 +113,8 @@ def summary(title, stats_csv, trace_csv, steps, tr, bench_line=None):
              PROFILE_CMD.format(steps=steps), "```", "",
              "The table covers every launch of the run: the plan's tuning calls (each candidate cell grid "
              "once), the warm-up step and the timed steps.", "", kernel_stats(stats_csv), "",
-             f"Pair-kernel launches of the {steps} timed steps, in order (us; observed set, then the "
-             f"simulations, per step): {' '.join(f'{v:.1f}' for v in timed)}.",
+             f"Pair-kernel launches of the {steps} timed steps, in order (us; one per step, the "
+             f"observed set and the simulations together): {' '.join(f'{v:.1f}' for v in timed)}.",
              f"Mean {sum(timed) / len(timed):.1f} us per launch.", ""]
     if bench_line:
         lines += [f"`bench.py`'s own HIP-event mean for the same launches (its timed steps): "
@@ -122,9 +127,9 @@ def summary(title, stats_csv, trace_csv, steps, tr, bench_line=None):
               f"Calibration: a 256 MiB device copy (`--copy-calibration`) reads {tr['fetch_copy_kib']:.0f} KiB "
               f"of FETCH_SIZE (scale {tr['fetch_scale']:.4f}) and {tr['write_copy_kib']:.0f} KiB of WRITE_SIZE "
               f"(scale {tr['write_scale']:.4f}).", "",
-              "| launch (last step) | FETCH_SIZE KiB | WRITE_SIZE KiB |", "|---|---|---|",
-              f"| observed set | {tr['fetch_pair_kib_per_launch'][0]} | {tr['write_pair_kib_per_launch'][0]} |",
-              f"| simulations | {tr['fetch_pair_kib_per_launch'][1]} | {tr['write_pair_kib_per_launch'][1]} |", "",
+              "| launch (last step) | FETCH_SIZE KiB | WRITE_SIZE KiB |", "|---|---|---|"] + [
+              f"| {i + 1} | {f} | {w} |" for i, (f, w) in enumerate(
+                  zip(tr['fetch_pair_kib_per_launch'], tr['write_pair_kib_per_launch']))] + ["",
               f"Mean scaled bytes per launch: fetch {tr['fetch_bytes'] / 1e6:.1f} MB + write "
               f"{tr['write_bytes'] / 1e6:.1f} MB = {tr['bytes_per_launch'] / 1e6:.1f} MB.", ""]
     return "\n".join(lines)

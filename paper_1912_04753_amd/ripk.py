@@ -128,6 +128,8 @@ _SIGS = {
     "ripk_compute_K": (_i32, [ctypes.c_void_p, _P(Points), ctypes.c_void_p, _P(KOut)]),
     "ripk_simulate_envelope": (_i32, [ctypes.c_void_p, _i64, _i32, _u64, _P(_f64),
                                       ctypes.c_void_p, _P(EnvOut)]),
+    "ripk_compute_K_envelope": (_i32, [ctypes.c_void_p, _P(Points), _i32, _u64, ctypes.c_void_p,
+                                       _P(KOut), _P(EnvOut)]),
     "ripk_plan_stats": (_i32, [ctypes.c_void_p, _P(Stats)]),
     "ripk_plan_get_info": (_i32, [ctypes.c_void_p, _P(PlanInfo)]),
     "ripk_server_create": (_i32, [_P(ServerDesc), _P(ctypes.c_void_p)]),
@@ -343,6 +345,40 @@ def ripk_simulate_envelope(plan, n, m, seed, L_obs=None, stream=None, per_sim=Fa
     _check(lib().ripk_simulate_envelope(plan.handle, int(n), int(m), int(seed) & (2**64 - 1),
                                         ptr(lobs, _f64) if lobs is not None else null_d, st,
                                         ctypes.byref(out)), "ripk_simulate_envelope")
+    return res
+
+
+def ripk_compute_K_envelope(plan, x, y, t, m, seed, n_centres=0, stream=None, per_sim=False):
+    """K, L of the observed set and the envelopes of m simulations in one call
+    (the observed set evaluated beside CSR simulations).  Returns the keys of
+    ``ripk_compute_K`` and of ``ripk_simulate_envelope`` (with dL_hi)."""
+    n = len(x)
+    px, dx, kx = _coord_ptr(x, n)
+    py, dy, ky = _coord_ptr(y, n)
+    pt, dt, kt = _coord_ptr(t, n)
+    if not (dx == dy == dt):
+        raise ValueError("coordinates must all be on the host or all on the device")
+    pts = Points(px, py, pt, n, int(n_centres), 1 if dx else 0, _P(_f64)())
+    shp = plan.shape
+    res = {"C": _out(shp, np.uint64)}
+    for k in ("W", "K", "L", "K_lo", "K_hi", "L_lo", "L_hi", "dL_hi"):
+        res[k] = _out(shp, np.float64)
+    if per_sim:
+        res["C_sims"] = _out((m,) + shp, np.uint64)
+        res["W_sims"] = _out((m,) + shp, np.float64)
+        res["K_sims"] = _out((m,) + shp, np.float64)
+    ptr = lambda a, ct: a.ctypes.data_as(_P(ct))
+    kout = KOut(ptr(res["C"], _u64), ptr(res["W"], _f64), ptr(res["K"], _f64), ptr(res["L"], _f64))
+    eout = EnvOut(ptr(res["K_lo"], _f64), ptr(res["K_hi"], _f64), ptr(res["L_lo"], _f64),
+                  ptr(res["L_hi"], _f64), ptr(res["dL_hi"], _f64),
+                  ptr(res["C_sims"], _u64) if per_sim else _P(_u64)(),
+                  ptr(res["W_sims"], _f64) if per_sim else _P(_f64)(),
+                  ptr(res["K_sims"], _f64) if per_sim else _P(_f64)())
+    st = _stream_for([x, y, t], stream)
+    _check(lib().ripk_compute_K_envelope(plan.handle, ctypes.byref(pts), int(m),
+                                         int(seed) & (2**64 - 1), st, ctypes.byref(kout),
+                                         ctypes.byref(eout)), "ripk_compute_K_envelope")
+    del kx, ky, kt
     return res
 
 
