@@ -163,11 +163,18 @@ ripk_status run_request(Slot &s, Request *r) {
   ripk_points pts{s.stage, s.stage + n, s.stage + 2 * n, n, r->n_centres, 0,
                   r->lam.empty() ? nullptr : r->lam.data()};
   ripk_K_out ko{r->C.data(), r->W.data(), r->K.data(), r->L.data()};
-  st = ripk_compute_K(s.plan, &pts, s.stream, &ko);
-  if (st != RIPK_OK) return st;
+  // CSR simulations of every point (or of two types): the observed set and
+  // the simulations in one launch
+  const bool one_launch =
+      r->m > 0 && r->desc.sim_method == RIPK_SIM_CSR &&
+      ((r->desc.flags & RIPK_PLAN_CROSS) || r->n_centres == 0 || r->n_centres == n);
   ripk_stats stats;
-  ripk_plan_stats(s.plan, &stats);
-  r->n_in = stats.n_in;
+  if (!one_launch) {
+    st = ripk_compute_K(s.plan, &pts, s.stream, &ko);
+    if (st != RIPK_OK) return st;
+    ripk_plan_stats(s.plan, &stats);
+    r->n_in = stats.n_in;
+  }
   if (r->m > 0) {
     r->env.assign(5 * NB, 0.0);
     ripk_env_out eo{};
@@ -184,10 +191,17 @@ ripk_status run_request(Slot &s, Request *r) {
       eo.W_sims = r->W_sims.data();
       eo.K_sims = r->K_sims.data();
     }
-    st = ripk_simulate_envelope(s.plan, n, r->m, r->seed, r->L.data(), s.stream, &eo);
-    if (st != RIPK_OK) return st;
-    ripk_plan_stats(s.plan, &stats);
-    r->n_in += stats.n_in;
+    if (one_launch) {
+      st = ripk_compute_K_envelope(s.plan, &pts, r->m, r->seed, s.stream, &ko, &eo);
+      if (st != RIPK_OK) return st;
+      ripk_plan_stats(s.plan, &stats);
+      r->n_in = stats.n_in;
+    } else {
+      st = ripk_simulate_envelope(s.plan, n, r->m, r->seed, r->L.data(), s.stream, &eo);
+      if (st != RIPK_OK) return st;
+      ripk_plan_stats(s.plan, &stats);
+      r->n_in += stats.n_in;
+    }
   }
   return RIPK_OK;
 }
