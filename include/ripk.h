@@ -248,7 +248,9 @@ typedef struct {
 ripk_status ripk_plan_check(const ripk_plan_desc *desc, ripk_plan_info *info);
 
 /* Create a plan: validate, derive thresholds and the cell grid, and allocate
- * every device buffer for n_max points and m_max simulations on desc->device.
+ * every device buffer for n_max points and m_max simulations on desc->device
+ * (m_max + 1 sets when m_max > 0: ripk_compute_K_envelope evaluates the
+ * observed set in the simulations' launch).
  * Errors: EINVAL, ENOMEM, EDEVICE.  Free with ripk_plan_destroy. */
 ripk_status ripk_plan(const ripk_plan_desc *desc, ripk_plan_t *out);
 void ripk_plan_destroy(ripk_plan_t plan);
