@@ -212,7 +212,7 @@ int64_t caps_bytes(const Caps &c) {
   int64_t bytes = 0;
   bytes += 3 * 4 * c.N;                       // x, y, t staging / simulated points
   bytes += 4 * 4 * c.N;                       // keys, vals (double buffered)
-  bytes += (int64_t)radix_sort_temp_bytes((uint32_t)c.N);
+  bytes += (int64_t)radix_sort_temp_bytes((uint32_t)c.N, (uint32_t)c.S);
   bytes += 4 * (2 * c.SNC + 1);               // cell starts
   bytes += 16 * c.N;                          // sorted point records
   bytes += 4 * c.SNC * 2 + 4 * (c.S + 1) + (int64_t)scan_temp_bytes((uint32_t)c.SNC) + 256;
@@ -503,7 +503,10 @@ ripk_status enqueue_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_cent
   uint32_t *err = (uint32_t *)(p->scal + 2);
   uint32_t *n_items = err + 1;
   unsigned long long *queues = p->scal + kQueueStride;
-  HIPCHK(launch_fill_u64(p->scal, (size_t)(kQueues + 1) * kQueueStride, 0ull, st));
+  // the scalars and work queue, and every set's bins
+  HIPCHK(launch_zero3(Zero3{{p->scal, p->binC, p->binW},
+                            {(size_t)(kQueues + 1) * kQueueStride, (size_t)S * NB, (size_t)S * NB * 2}},
+                      st));
   const bool cross = (p->desc.flags & RIPK_PLAN_CROSS) != 0;
   const uint32_t so = with_obs ? 1u : 0u;  // sets before the first simulation
   if (simulate) {
@@ -524,12 +527,16 @@ ripk_status enqueue_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_cent
   if (timing) HIPCHK(hipEventRecord(p->ev[1], st));
   const uint64_t n_keys = (uint64_t)S * g.n_cells * 2;
   int alt = 0;
-  HIPCHK(radix_sort(p->keys[0], p->vals[0], p->keys[1], p->vals[1], N, ceil_log2(n_keys),
-                    p->sort_temp, st, &alt));
-  HIPCHK(launch_cell_bounds(p->keys[alt], N, (uint32_t)n_keys, p->cs, st));
+  // every set's entries are contiguous and its keys span 2 * n_cells values
+  // (interleaved: (set * n_cells + cell) * 2 + halo; blocked: (2 * set + type)
+  // * n_cells + cell), so each set is sorted on its own
+  const uint32_t set_keys = 2u * (uint32_t)g.n_cells;
+  HIPCHK(radix_sort(p->keys[0], p->vals[0], p->keys[1], p->vals[1], N, ceil_log2(set_keys),
+                    p->sort_temp, st, &alt, S, set_keys));
   // (cross K sets are sorted in blocked order, each type one cell-sorted block:
   // centres come from the type-1 block and neighbour runs from the type-2 block)
-  HIPCHK(launch_gather(p->vals[alt], N, x, y, t, g, p->lay.clamp_e, p->P, st));
+  HIPCHK(launch_bounds_gather(p->keys[alt], p->vals[alt], N, (uint32_t)n_keys, p->cs, x, y, t, g,
+                              p->lay.clamp_e, p->P, st));
   const bool inhom = (p->desc.flags & RIPK_PLAN_INHOM) != 0 && !simulate;
   if (inhom) HIPCHK(launch_gather_rho(p->vals[alt], N, p->cur_lam, p->rho, err, st));
   // row items need rows without halo entries: every point a centre, or the
@@ -566,8 +573,7 @@ ripk_status enqueue_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_cent
   split = std::max<int64_t>(split, 1);
   HIPCHK(launch_items(p->cs, S, g, row_items, cross, (uint32_t)split, n_rows, p->chunks, p->offs,
                       p->set_base, p->items, n_items, p->scan_temp, st));
-  HIPCHK(launch_fill_u64(p->binC, (size_t)S * NB, 0ull, st));
-  HIPCHK(launch_fill_u64(p->binW, (size_t)S * NB * 2, 0ull, st));
+
   if (timing) HIPCHK(hipEventRecord(p->ev[2], st));
 
   PairArgs a;
@@ -745,7 +751,8 @@ ripk_status plan_create(int device, const Caps &c, ripk_plan_s **out) {
   ALLOC(p->x, c.N); ALLOC(p->y, c.N); ALLOC(p->t, c.N);
   ALLOC(p->ox, c.P); ALLOC(p->oy, c.P); ALLOC(p->ot, c.P);
   ALLOC(p->keys[0], c.N); ALLOC(p->keys[1], c.N); ALLOC(p->vals[0], c.N); ALLOC(p->vals[1], c.N);
-  if (e == hipSuccess) e = hipMalloc(&p->sort_temp, radix_sort_temp_bytes((uint32_t)c.N));
+  if (e == hipSuccess)
+    e = hipMalloc(&p->sort_temp, radix_sort_temp_bytes((uint32_t)c.N, (uint32_t)c.S));
   ALLOC(p->cs, 2 * c.SNC + 1);
   ALLOC(p->P, c.N);
   ALLOC(p->chunks, c.SNC); ALLOC(p->offs, c.SNC + 1); ALLOC(p->set_base, c.S + 1);

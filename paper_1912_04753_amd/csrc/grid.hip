@@ -266,11 +266,21 @@ __global__ void k_scan_partials(uint32_t *part, uint32_t nb) {
   if (threadIdx.x == 0) part[nb] = tot;
 }
 
+// Down-sweep: each block first adds up the tile sums before it (a few hundred
+// at most, read by all threads at once), so no separate pass scans them.
 __global__ void k_scan_down(const uint32_t *__restrict__ in, uint32_t n,
                             const uint32_t *__restrict__ part, uint32_t *__restrict__ out) {
   __shared__ uint32_t lds[kThreads / 64 + 1];
   __shared__ uint32_t tile[kScanTile];
+  __shared__ uint32_t before;
   uint32_t base = blockIdx.x * kScanTile;
+  {
+    uint32_t s = 0;
+    for (uint32_t b = threadIdx.x; b < blockIdx.x; b += kThreads) s += part[b];
+    uint32_t tot;
+    block_exclusive_scan(s, lds, &tot);
+    if (threadIdx.x == 0) before = tot;
+  }
   for (int k = 0; k < kScanItems; ++k) {
     uint32_t i = base + k * kThreads + threadIdx.x;
     tile[k * kThreads + threadIdx.x] = i < n ? in[i] : 0u;
@@ -284,7 +294,7 @@ __global__ void k_scan_down(const uint32_t *__restrict__ in, uint32_t n,
     s += loc[k];
   }
   uint32_t tot;
-  uint32_t run = block_exclusive_scan(s, lds, &tot) + part[blockIdx.x];
+  uint32_t run = block_exclusive_scan(s, lds, &tot) + before;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     tile[threadIdx.x * kScanItems + k] = run;
@@ -295,49 +305,73 @@ __global__ void k_scan_down(const uint32_t *__restrict__ in, uint32_t n,
     uint32_t i = base + k * kThreads + threadIdx.x;
     if (i < n) out[i] = tile[k * kThreads + threadIdx.x];
   }
-  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = part[gridDim.x];
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = before + tot;
 }
 
 // ---- stable LSD radix sort, 8-bit digits --------------------------------------
+// Segmented: segment g holds entries [g*len, (g+1)*len), its keys lie in
+// [g*stride, (g+1)*stride), and the segments are already in order, so only the
+// offset within the segment (key - g*stride) is sorted, and tiles never
+// straddle a segment.  Digit counts are laid out (segment, digit, tile), so
+// their exclusive scan gives each tile's start for each digit.  One segment
+// with stride 0 is a plain sort.
 constexpr int kSortItems = 16;
 constexpr int kSortTile = kThreads * kSortItems;
 
-__global__ void k_sort_hist(const uint32_t *__restrict__ keys, uint32_t n, int shift,
-                            uint32_t mask, uint32_t nblocks, uint32_t *__restrict__ counts) {
+struct SortTile {
+  uint32_t seg, t, base, end, key0;
+};
+
+__device__ __forceinline__ SortTile sort_tile(const SortSeg &sg, uint32_t b) {
+  SortTile r;
+  r.seg = b / sg.tiles;
+  r.t = b - r.seg * sg.tiles;
+  r.base = r.seg * sg.len + r.t * kSortTile;
+  r.end = min(r.base + (uint32_t)kSortTile, (r.seg + 1) * sg.len);
+  r.key0 = r.seg * sg.stride;
+  return r;
+}
+
+__device__ __forceinline__ uint32_t count_slot(const SortSeg &sg, const SortTile &tl, uint32_t d) {
+  return (tl.seg * 256u + d) * sg.tiles + tl.t;
+}
+
+__global__ void k_sort_hist(const uint32_t *__restrict__ keys, SortSeg sg, int shift,
+                            uint32_t mask, uint32_t *__restrict__ counts) {
   __shared__ uint32_t h[256];
+  const SortTile tl = sort_tile(sg, blockIdx.x);
   h[threadIdx.x] = 0;
   __syncthreads();
-  uint32_t base = blockIdx.x * kSortTile;
   for (int k = 0; k < kSortItems; ++k) {
-    uint32_t i = base + k * kThreads + threadIdx.x;
-    if (i < n) atomicAdd(&h[(keys[i] >> shift) & mask], 1u);
+    uint32_t i = tl.base + k * kThreads + threadIdx.x;
+    if (i < tl.end) atomicAdd(&h[((keys[i] - tl.key0) >> shift) & mask], 1u);
   }
   __syncthreads();
-  counts[threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+  counts[count_slot(sg, tl, threadIdx.x)] = h[threadIdx.x];
 }
 
 // Tile order is round-major (round k holds items base + k*256 + tid), so a key's
 // stable rank is: keys of its digit in earlier rounds + in earlier waves of the
 // same round + in lower lanes of the same wave.
 __global__ void k_sort_scatter(const uint32_t *__restrict__ keys,
-                               const uint32_t *__restrict__ vals, uint32_t n, int shift,
-                               int nbits, uint32_t nblocks, const uint32_t *__restrict__ offs,
+                               const uint32_t *__restrict__ vals, SortSeg sg, int shift,
+                               int nbits, const uint32_t *__restrict__ offs,
                                uint32_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out) {
   __shared__ uint32_t run[256];
   __shared__ uint32_t wc[kThreads / 64][256];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint32_t mask = (1u << nbits) - 1u;
-  run[threadIdx.x] = offs[threadIdx.x * nblocks + blockIdx.x];
+  const SortTile tl = sort_tile(sg, blockIdx.x);
+  run[threadIdx.x] = offs[count_slot(sg, tl, threadIdx.x)];
   for (int q = 0; q < kThreads / 64; ++q) wc[q][threadIdx.x] = 0;
   __syncthreads();
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  uint32_t base = blockIdx.x * kSortTile;
   for (int k = 0; k < kSortItems; ++k) {
-    uint32_t i = base + k * kThreads + threadIdx.x;
-    bool valid = i < n;
+    uint32_t i = tl.base + k * kThreads + threadIdx.x;
+    bool valid = i < tl.end;
     uint32_t key = valid ? keys[i] : 0u;
     uint32_t val = valid ? vals[i] : 0u;
-    uint32_t d = (key >> shift) & mask;
+    uint32_t d = ((key - tl.key0) >> shift) & mask;
     uint64_t peers = __ballot(valid);
     for (int b = 0; b < nbits; ++b) {
       uint64_t bb = __ballot((d >> b) & 1u);
@@ -365,24 +399,21 @@ __global__ void k_sort_scatter(const uint32_t *__restrict__ keys,
   }
 }
 
-// cs[k] = first index whose key >= k, for k in [0, n_keys]
-__global__ void k_cell_bounds(const uint32_t *__restrict__ keys, uint32_t n, uint32_t n_keys,
-                              uint32_t *__restrict__ cs) {
-  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i > n) return;
-  int64_t prev = (i == 0) ? -1 : (int64_t)keys[i - 1];
-  int64_t cur = (i == n) ? (int64_t)n_keys : (int64_t)keys[i];
-  for (int64_t k = prev + 1; k <= cur; ++k) cs[k] = i;
-}
-
-// Sorted point records: window-relative coordinates (all >= 0) and the distance
-// to the nearest side clamped to s_max (a circle no larger than that is whole).
-__global__ void k_gather(const uint32_t *__restrict__ vals, uint32_t n,
-                         const int32_t *__restrict__ x, const int32_t *__restrict__ y,
-                         const int32_t *__restrict__ t, Geom g, int32_t clamp_e,
-                         int4 *__restrict__ P) {
-  uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n) return;
+// One pass over the sorted keys: the cell bounds cs[k] = first index whose
+// key >= k, for k in [0, n_keys], and the sorted point records: window-relative
+// coordinates (all >= 0) and the distance to the nearest side clamped to s_max
+// (a circle no larger than that is whole).
+__global__ void k_bounds_gather(const uint32_t *__restrict__ keys,
+                                const uint32_t *__restrict__ vals, uint32_t n, uint32_t n_keys,
+                                uint32_t *__restrict__ cs, const int32_t *__restrict__ x,
+                                const int32_t *__restrict__ y, const int32_t *__restrict__ t,
+                                Geom g, int32_t clamp_e, int4 *__restrict__ P) {
+  const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r > n) return;
+  const int64_t prev = (r == 0) ? -1 : (int64_t)keys[r - 1];
+  const int64_t cur = (r == n) ? (int64_t)n_keys : (int64_t)keys[r];
+  for (int64_t k = prev + 1; k <= cur; ++k) cs[k] = r;
+  if (r == n) return;
   uint32_t i = vals[r];
   int32_t X = x[i] - g.x0, Y = y[i] - g.y0, T = t[i] - g.t0;
   int32_t e;
@@ -450,22 +481,33 @@ __global__ void k_chunks(const uint32_t *__restrict__ cs, uint32_t nunit_total, 
   chunks[g] = chunk_walk(cs, g, unit, ci, [](uint32_t, uint32_t) {});
 }
 
-// per set: padded item base so that every group of kItemsPerGroup items lies in one set
 // Item bases per set (before splitting), each set padded to whole groups; the
 // emitted array holds every item `split` times, once per part of its stencil
 // rows.
 __global__ void k_set_base(const uint32_t *__restrict__ offs, uint32_t n_sets,
                            uint32_t n_units, uint32_t split, uint32_t *__restrict__ set_base,
                            uint32_t *__restrict__ n_items) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  uint32_t run = 0;
-  for (uint32_t s = 0; s < n_sets; ++s) {
-    set_base[s] = run;
-    uint32_t tot = offs[(s + 1) * n_units] - offs[s * n_units];
-    run += (tot + kItemsPerGroup - 1) / kItemsPerGroup * kItemsPerGroup;
+  // one block: each thread pads the item counts of a run of sets, then one
+  // block-wide scan places the runs
+  __shared__ uint32_t lds[kThreads / 64 + 1];
+  const uint32_t per = (n_sets + kThreads - 1) / kThreads;
+  const uint32_t s0 = threadIdx.x * per;
+  auto padded = [&](uint32_t s) {
+    const uint32_t tot = offs[(s + 1) * n_units] - offs[s * n_units];
+    return (tot + kItemsPerGroup - 1) / kItemsPerGroup * kItemsPerGroup;
+  };
+  uint32_t sum = 0;
+  for (uint32_t k = 0; k < per && s0 + k < n_sets; ++k) sum += padded(s0 + k);
+  uint32_t total;
+  uint32_t run = block_exclusive_scan(sum, lds, &total);
+  for (uint32_t k = 0; k < per && s0 + k < n_sets; ++k) {
+    set_base[s0 + k] = run;
+    run += padded(s0 + k);
   }
-  set_base[n_sets] = run;
-  *n_items = run * split;
+  if (threadIdx.x == 0) {
+    set_base[n_sets] = total;
+    *n_items = total * split;
+  }
 }
 
 // count word of part p of `split` parts of n_rows stencil rows (see Item)
@@ -522,10 +564,12 @@ __global__ void k_emit(const uint32_t *__restrict__ cs, const uint32_t *__restri
   }
 }
 
-__global__ void k_fill_u64(unsigned long long *p, size_t n, unsigned long long v) {
-  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  size_t stride = (size_t)gridDim.x * blockDim.x;
-  for (; i < n; i += stride) p[i] = v;
+// zeroes up to three ranges in one launch
+__global__ void k_zero3(Zero3 z) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (int r = 0; r < 3; ++r)
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < z.n[r]; i += stride)
+      z.p[r][i] = 0ull;
 }
 
 inline uint32_t blocks_for(uint64_t n, int per) { return (uint32_t)((n + per - 1) / per); }
@@ -599,22 +643,28 @@ hipError_t exclusive_scan(const uint32_t *in, uint32_t *out, uint32_t n, void *t
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kThreads), 0, s, in, n, part);
-  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kThreads), 0, s, part, nb);
   hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kThreads), 0, s, in, n, part, out);
   return hipGetLastError();
 }
 
-size_t radix_sort_temp_bytes(uint32_t n) {
-  size_t nb = blocks_for(n > 0 ? n : 1, kSortTile);
+size_t radix_sort_temp_bytes(uint32_t n, uint32_t n_segs) {
+  // tiles: at most one partial tile per segment beyond the whole ones
+  size_t nb = blocks_for(n > 0 ? n : 1, kSortTile) + n_segs;
   size_t cnt = 256 * nb;
   return sizeof(uint32_t) * (2 * cnt + 1) + scan_temp_bytes((uint32_t)cnt) + 256;
 }
 
 hipError_t radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt,
-                      uint32_t n, int key_bits, void *temp, hipStream_t s, int *result_in_alt) {
+                      uint32_t n, int key_bits, void *temp, hipStream_t s, int *result_in_alt,
+                      uint32_t n_segs, uint32_t seg_stride) {
   *result_in_alt = 0;
   if (n <= 1 || key_bits <= 0) return hipSuccess;
-  uint32_t nb = blocks_for(n, kSortTile);
+  if (n_segs == 0 || n % n_segs != 0) return hipErrorInvalidValue;
+  SortSeg sg;
+  sg.len = n / n_segs;
+  sg.tiles = blocks_for(sg.len, kSortTile);
+  sg.stride = n_segs > 1 ? seg_stride : 0u;
+  const uint32_t nb = n_segs * sg.tiles;
   size_t cnt = 256 * (size_t)nb;
   uint32_t *counts = (uint32_t *)temp;
   uint32_t *offs = counts + cnt;
@@ -624,12 +674,11 @@ hipError_t radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32
   for (int shift = 0; shift < key_bits; shift += 8) {
     int nbits = key_bits - shift < 8 ? key_bits - shift : 8;
     uint32_t mask = (1u << nbits) - 1u;
-    hipLaunchKernelGGL(k_sort_hist, dim3(nb), dim3(kThreads), 0, s, ka, n, shift, mask, nb,
-                       counts);
+    hipLaunchKernelGGL(k_sort_hist, dim3(nb), dim3(kThreads), 0, s, ka, sg, shift, mask, counts);
     hipError_t e = exclusive_scan(counts, offs, (uint32_t)cnt, stemp, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sort_scatter, dim3(nb), dim3(kThreads), 0, s, ka, va, n, shift, nbits,
-                       nb, offs, kb, vb);
+    hipLaunchKernelGGL(k_sort_scatter, dim3(nb), dim3(kThreads), 0, s, ka, va, sg, shift, nbits,
+                       offs, kb, vb);
     uint32_t *tk = ka, *tv = va;
     ka = kb; va = vb; kb = tk; vb = tv;
     alt ^= 1;
@@ -638,19 +687,12 @@ hipError_t radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32
   return hipGetLastError();
 }
 
-hipError_t launch_cell_bounds(const uint32_t *keys, uint32_t n, uint32_t n_keys, uint32_t *cs,
-                              hipStream_t s) {
-  hipLaunchKernelGGL(k_cell_bounds, dim3(blocks_for((uint64_t)n + 1, kThreads)), dim3(kThreads),
-                     0, s, keys, n, n_keys, cs);
-  return hipGetLastError();
-}
-
-hipError_t launch_gather(const uint32_t *vals, uint32_t n, const int32_t *x, const int32_t *y,
-                         const int32_t *t, const Geom &g, int32_t clamp_e, int4 *P,
-                         hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gather, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, s, vals, n, x,
-                     y, t, g, clamp_e, P);
+hipError_t launch_bounds_gather(const uint32_t *keys, const uint32_t *vals, uint32_t n,
+                                uint32_t n_keys, uint32_t *cs, const int32_t *x, const int32_t *y,
+                                const int32_t *t, const Geom &g, int32_t clamp_e, int4 *P,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(k_bounds_gather, dim3(blocks_for((uint64_t)n + 1, kThreads)), dim3(kThreads),
+                     0, s, keys, vals, n, n_keys, cs, x, y, t, g, clamp_e, P);
   return hipGetLastError();
 }
 
@@ -674,19 +716,19 @@ hipError_t launch_items(const uint32_t *cs, uint32_t n_sets, const Geom &g, bool
                      unit, ci, chunks);
   hipError_t e = exclusive_scan(chunks, offs, tot, scan_temp, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_set_base, dim3(1), dim3(64), 0, s, offs, n_sets, n_units, split,
+  hipLaunchKernelGGL(k_set_base, dim3(1), dim3(kThreads), 0, s, offs, n_sets, n_units, split,
                      set_base, n_items);
   hipLaunchKernelGGL(k_emit, dim3(blocks_for(tot, kThreads)), dim3(kThreads), 0, s, cs, offs,
                      set_base, n_sets, n_units, unit, split, n_rows, ci, items);
   return hipGetLastError();
 }
 
-hipError_t launch_fill_u64(unsigned long long *p, size_t n, unsigned long long v,
-                           hipStream_t s) {
+hipError_t launch_zero3(const Zero3 &z, hipStream_t s) {
+  const size_t n = std::max(z.n[0], std::max(z.n[1], z.n[2]));
   if (n == 0) return hipSuccess;
   uint32_t nb = blocks_for(n, kThreads);
   if (nb > 4096) nb = 4096;
-  hipLaunchKernelGGL(k_fill_u64, dim3(nb), dim3(kThreads), 0, s, p, n, v);
+  hipLaunchKernelGGL(k_zero3, dim3(nb), dim3(kThreads), 0, s, z);
   return hipGetLastError();
 }
 

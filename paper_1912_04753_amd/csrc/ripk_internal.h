@@ -144,18 +144,27 @@ hipError_t launch_resample(int method, uint32_t n, uint32_t n_centres, uint32_t 
                            const int32_t *oy, const int32_t *ot, const Geom &g, int32_t *x,
                            int32_t *y, int32_t *t, uint32_t *keys[2], uint32_t *vals[2],
                            void *sort_temp, hipStream_t s);
-size_t radix_sort_temp_bytes(uint32_t n);
+// Stable LSD radix sort of (key, value) by the low key_bits bits.  With
+// n_segs > 1 the n entries are n_segs segments of n / n_segs entries, already
+// in segment order, segment g holding keys in [g*seg_stride, (g+1)*seg_stride):
+// each segment is sorted by key - g*seg_stride, key_bits covering seg_stride.
+struct SortSeg {
+  uint32_t len, tiles, stride;
+};
+size_t radix_sort_temp_bytes(uint32_t n, uint32_t n_segs = 1);
 hipError_t radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt,
-                      uint32_t n, int key_bits, void *temp, hipStream_t s, int *result_in_alt);
+                      uint32_t n, int key_bits, void *temp, hipStream_t s, int *result_in_alt,
+                      uint32_t n_segs = 1, uint32_t seg_stride = 0);
 size_t scan_temp_bytes(uint32_t n);
 hipError_t exclusive_scan(const uint32_t *in, uint32_t *out, uint32_t n, void *temp,
                           hipStream_t s);
-hipError_t launch_cell_bounds(const uint32_t *keys, uint32_t n, uint32_t n_keys,
-                              uint32_t *cs, hipStream_t s);
-// Sorted records {x, y, t, distance to the study area's boundary, clamped to s_max}
-hipError_t launch_gather(const uint32_t *vals, uint32_t n, const int32_t *x, const int32_t *y,
-                         const int32_t *t, const Geom &g, int32_t clamp_e, int4 *P,
-                         hipStream_t s);
+// From the sorted keys and values: the cell bounds cs[k] (first index whose key
+// >= k, k in [0, n_keys]) and the sorted records {x, y, t, distance to the
+// study area's boundary, clamped to s_max}
+hipError_t launch_bounds_gather(const uint32_t *keys, const uint32_t *vals, uint32_t n,
+                                uint32_t n_keys, uint32_t *cs, const int32_t *x, const int32_t *y,
+                                const int32_t *t, const Geom &g, int32_t clamp_e, int4 *P,
+                                hipStream_t s);
 // rho[r] = 1 / lambda[vals[r]] for the sorted records; a value that is not
 // positive and finite sets bit 2 of *err
 hipError_t launch_gather_rho(const uint32_t *vals, uint32_t n, const double *lambda, double *rho,
@@ -164,8 +173,12 @@ hipError_t launch_items(const uint32_t *cs, uint32_t n_sets, const Geom &g, bool
                         bool blocked, uint32_t split, uint32_t n_rows, uint32_t *chunks,
                         uint32_t *offs, uint32_t *set_base, Item *items, uint32_t *n_items,
                         void *scan_temp, hipStream_t s);
-hipError_t launch_fill_u64(unsigned long long *p, size_t n, unsigned long long v,
-                           hipStream_t s);
+// zeroes the ranges (p[r], n[r]) in one launch (a kernel, not memset nodes)
+struct Zero3 {
+  unsigned long long *p[3];
+  size_t n[3];
+};
+hipError_t launch_zero3(const Zero3 &z, hipStream_t s);
 hipError_t launch_pair(const PairArgs &a, int grid, hipStream_t s);
 // LDS bin layouts of the pair kernel.  Packed: one 64-bit word per bin holds
 // the pair count (bits 34-63) and the interior-path weights in units of 2^23
