@@ -636,8 +636,10 @@ __device__ __forceinline__ void scan_run(Ctx<SYM, MODE, POLY, INHOM> &x, uint32_
   }
 }
 
+// (the polygon variants are held to 128 VGPRs: 4 waves per SIMD)
 template <bool SYM, int MODE, bool POLY, bool INHOM>
-__global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
+__global__ void __launch_bounds__(kPairThreads) __attribute__((amdgpu_waves_per_eu(POLY ? 4 : 1)))
+k_pair(PairArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const Geom &g = a.g;
   const int NB = g.n_s * g.n_t;

@@ -117,7 +117,12 @@ __device__ __forceinline__ double poly_angle(double x, double y) {
 // Walking the circle counter-clockwise, the inside length is the sum of the
 // exit angles minus the sum of the entry angles, plus 2 pi when the walk
 // starts inside (angles in [0, 2 pi)); the sum alone is then negative, so its
-// sign decides.  Which edges the circle crosses, and where, is decided on
+// sign decides, and with any crossing the length is that sum modulo 2 pi.
+// Crossings through the interior of an edge enter as a product of their
+// direction vectors (conjugated for subtracted angles) kept at unit scale by
+// powers of two, whose angle is taken once at the end: the lanes of a wave
+// hold different circles, so some lane crosses at almost every edge and a
+// per-crossing arctangent would cost every lane that much.  Which edges the circle crosses, and where, is decided on
 // exact integers: with A = a - c, E = b - a, the crossing parameters solve
 // |A + s E|^2 = d2, i.e. ee s^2 + 2 ae s + (aa - d2) = 0, and the root
 // conditions 0 < s < 1 reduce to signs of ae, ae + ee and to comparisons of
@@ -139,8 +144,18 @@ __device__ __forceinline__ double poly_omega(const Geom &g, int px, int py, uint
   const double d2 = (double)d2u;
   const int R = (int)sqrt(d2) + 1;  // R^2 > d2: edges whose box misses [-R, R]^2 miss the circle
   const double sg = (double)g.poly_sign;
-  double S = 0.0;
+  double S = 0.0;              // half crossings at vertices
+  double Px = 1.0, Py = 0.0;   // product of the other crossings' directions
+  bool crossed = false;
   bool vin = false;
+  // P <- P (x + i y), rescaled so that its larger component lies in [1, 2)
+  auto turn = [&](double x, double y) {
+    const double nx = fma(Px, x, -Py * y), ny = fma(Px, y, Py * x);
+    const int e = ilogb(fmax(fabs(nx), fabs(ny)));
+    Px = ldexp(nx, -e);
+    Py = ldexp(ny, -e);
+    crossed = true;
+  };
   poly_for_near(g, px, py, [&](int k) {
     const int2 a = V[k], b = V[k + 1 == nv ? 0 : k + 1];
     const int Ax = a.x - px, Ay = a.y - py, Bx = b.x - px, By = b.y - py;
@@ -171,19 +186,26 @@ __device__ __forceinline__ double poly_omega(const Geom &g, int px, int py, uint
       // the crossing A + s E with s = (-ae -+ sq)/ee, scaled by ee > 0 (the
       // angle depends on the direction only)
       // smaller root strictly inside the edge: an exit (counter-clockwise)
+      // (its angle is added with the orientation's sign: direction (x, sg y))
       if (ae < 0.0 && aa > d2 && (ae + ee > 0.0 || bb < d2)) {
         const double sm = -ae - sq;
-        S += sg * poly_angle(fma(sm, ex, ee * ax), fma(sm, ey, ee * ay));
+        turn(fma(sm, ex, ee * ax), sg * fma(sm, ey, ee * ay));
       }
-      // larger root strictly inside the edge: an entry
+      // larger root strictly inside the edge: an entry (angle subtracted)
       if ((ae < 0.0 || aa < d2) && ae + ee > 0.0 && bb > d2) {
         const double sp = -ae + sq;
-        S -= sg * poly_angle(fma(sp, ex, ee * ax), fma(sp, ey, ee * ay));
+        turn(fma(sp, ex, ee * ax), -sg * fma(sp, ey, ee * ay));
       }
     }
   });
   const double two_pi = 6.283185307179586476925;
-  const double L = S > 0.0 ? S : (S < 0.0 ? S + two_pi : (vin ? 0.0 : two_pi));
+  double L;
+  if (crossed) {
+    L = poly_angle(Px, Py) + S;
+    L -= two_pi * floor(L / two_pi);
+  } else {
+    L = S > 0.0 ? S : (S < 0.0 ? S + two_pi : (vin ? 0.0 : two_pi));
+  }
   return L / two_pi;
 }
 
