@@ -223,3 +223,32 @@ def test_polygon_with_cross_k_and_resampled_simulations():
         ref = oracle.envelope_resampled(d, x, y, t, m, seed, method)
         assert np.array_equal(gs["C_sims"], ref["C_sims"].astype(np.uint64))
         np.testing.assert_allclose(gs["K_sims"], ref["K_sims"], rtol=1e-6, atol=0)
+
+
+def _comb(teeth, W=20_000, H=20_000, base=4_000, tooth=12_000):
+    """A comb: a base strip along the bottom with `teeth` narrow teeth rising
+    from it (4 * teeth + 4 vertices, counter-clockwise)."""
+    w = W // (2 * teeth)  # tooth and gap width
+    top = [(W, 0 + base)]
+    for k in range(teeth - 1, -1, -1):
+        xr = (2 * k + 1) * w + w
+        xl = 2 * k * w + w
+        top += [(xr, base), (xr, base + tooth), (xl, base + tooth), (xl, base)]
+    return [(0, 0), (W, 0)] + top[:1] + top[1:] + [(0, base)]
+
+
+def test_polygon_many_crossings_against_oracle():
+    """A comb of 150 teeth (604 vertices, 66 m teeth and gaps): circles up to
+    1.5 km cross dozens of edges, so the running direction product takes many
+    factors and many cells list more than 32 edges (every edge is scanned)."""
+    poly = _comb(150)
+    win = (0, 0, 20_000, 20_000, 0, 200 * DAY)
+    assert len(poly) == 604
+    x, y, t = workloads.polygon_points(np.random.default_rng(71), 4_000, win, poly)
+    args = (win, 1_500, 20 * DAY, 10, 8)
+    say("polygon comb v=%d n=%d" % (len(poly), len(x)))
+    g = _gpu(args, poly, x, y, t)
+    r = oracle.estimate(oracle.desc(*args, poly=poly), x, y, t)
+    compare(g, r, *args[1:], where="polygon comb")
+    go = _gpu(args, poly, x, y, t, flags=ripk.RIPK_PLAN_ORDERED)
+    assert np.array_equal(go["C"], g["C"]) and np.array_equal(go["W"], g["W"])
