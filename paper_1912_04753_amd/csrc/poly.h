@@ -118,11 +118,11 @@ __device__ __forceinline__ double poly_angle(double x, double y) {
 // exit angles minus the sum of the entry angles, plus 2 pi when the walk
 // starts inside (angles in [0, 2 pi)); the sum alone is then negative, so its
 // sign decides, and with any crossing the length is that sum modulo 2 pi.
-// Crossings through the interior of an edge enter as a product of their
-// direction vectors (conjugated for subtracted angles) kept at unit scale by
-// powers of two, whose angle is taken once at the end: the lanes of a wave
-// hold different circles, so some lane crosses at almost every edge and a
-// per-crossing arctangent would cost every lane that much.  Which edges the circle crosses, and where, is decided on
+// The crossings enter as a product of their direction vectors (conjugated for
+// subtracted angles) kept at unit scale by powers of two, whose angle is taken
+// once at the end: the lanes of a wave hold different circles, so some lane
+// crosses at almost every edge and a per-crossing arctangent would cost every
+// lane that much.  Which edges the circle crosses, and where, is decided on
 // exact integers: with A = a - c, E = b - a, the crossing parameters solve
 // |A + s E|^2 = d2, i.e. ee s^2 + 2 ae s + (aa - d2) = 0, and the root
 // conditions 0 < s < 1 reduce to signs of ae, ae + ee and to comparisons of
@@ -131,7 +131,9 @@ __device__ __forceinline__ double poly_angle(double x, double y) {
 // exit otherwise.  A vertex on the circle counts half for each of its two
 // edges, so a circle through a vertex crossing the boundary counts once and one
 // only touching it cancels (an edge tangent at the vertex counts as leaving the
-// disk); an edge tangent inside its span (zero discriminant) counts nothing.
+// disk); the two halves are added at the edge the vertex starts, so a vertex
+// is one crossing or none.  An edge tangent inside its span (zero
+// discriminant) counts nothing.
 // With no net crossing the circle is wholly inside unless the polygon lies
 // within it (some vertex strictly inside the disk).  Only the angles are
 // floating point (FP64); the integer quantities are carried in FP64 registers,
@@ -144,8 +146,7 @@ __device__ __forceinline__ double poly_omega(const Geom &g, int px, int py, uint
   const double d2 = (double)d2u;
   const int R = (int)sqrt(d2) + 1;  // R^2 > d2: edges whose box misses [-R, R]^2 miss the circle
   const double sg = (double)g.poly_sign;
-  double S = 0.0;              // half crossings at vertices
-  double Px = 1.0, Py = 0.0;   // product of the other crossings' directions
+  double Px = 1.0, Py = 0.0;   // product of the crossings' directions
   bool crossed = false;
   bool vin = false;
   // P <- P (x + i y), rescaled so that its larger component lies in [1, 2)
@@ -166,12 +167,18 @@ __device__ __forceinline__ double poly_omega(const Geom &g, int px, int py, uint
     const double aa = fma(ax, ax, ay * ay), bb = fma(bx, bx, by * by);
     vin = vin || aa < d2 || bb < d2;
     if (ee == 0.0) return;
-    // a vertex on the circle: half a crossing, signed by the side of the
-    // circle the edge lies on next to the vertex (E.(vertex - c) > 0: outside
-    // beyond a, inside before b); an edge tangent there (zero product) lies
-    // outside the disk
-    if (aa == d2) S += (ae >= 0.0 ? -0.5 : 0.5) * sg * poly_angle(ax, ay);
-    if (bb == d2) S += (ae + ee > 0.0 ? -0.5 : 0.5) * sg * poly_angle(bx, by);
+    // vertex a on the circle: its halves from this edge (a-end) and from the
+    // previous one (b-end), each signed by the side of the circle the edge
+    // lies on next to the vertex (this edge: E.A > 0 lies outside beyond a;
+    // the previous edge, F = a - prev: F.A > 0 lies inside before a), an edge
+    // tangent there (zero product) lying outside the disk; +-1/2 each, exact
+    // integer products
+    if (aa == d2) {
+      const int2 pv = V[k == 0 ? nv - 1 : k - 1];
+      const double fx = (double)(a.x - pv.x), fy = (double)(a.y - pv.y);
+      const int h = (ae >= 0.0 ? -1 : 1) + (fma(fx, ax, fy * ay) > 0.0 ? -1 : 1);
+      if (h != 0) turn(ax, (h > 0 ? sg : -sg) * ay);
+    }
     // discriminant ae^2 - ee (aa - d2): its sign from FP64 when clear of the
     // rounding bound, else from exact 128-bit integers
     const double t1 = ae * ae, t2 = ee * (aa - d2);
@@ -199,13 +206,7 @@ __device__ __forceinline__ double poly_omega(const Geom &g, int px, int py, uint
     }
   });
   const double two_pi = 6.283185307179586476925;
-  double L;
-  if (crossed) {
-    L = poly_angle(Px, Py) + S;
-    L -= two_pi * floor(L / two_pi);
-  } else {
-    L = S > 0.0 ? S : (S < 0.0 ? S + two_pi : (vin ? 0.0 : two_pi));
-  }
+  const double L = crossed ? poly_angle(Px, Py) : (vin ? 0.0 : two_pi);
   return L / two_pi;
 }
 
