@@ -111,6 +111,15 @@ __device__ __forceinline__ double poly_angle(double x, double y) {
   return a;
 }
 
+// Square root of x > 0 to a few ulp (4e-15 relative measured over 1 .. 2^104):
+// the hardware reciprocal square root and one Newton step.  It only places a
+// crossing's direction; which edges cross is decided on integers.
+__device__ __forceinline__ double poly_sqrt(double x) {
+  const double r = __builtin_amdgcn_rsq(x);
+  const double s = x * r;
+  return fma(fma(-s, s, x), 0.5 * r, s);
+}
+
 // Share of the circle centred on the window-relative point (px, py), strictly
 // inside the polygon, with radius sqrt(d2) inside the polygon.
 //
@@ -189,7 +198,7 @@ __device__ __forceinline__ double poly_omega(const Geom &g, int px, int py, uint
       disc = e > 0 ? (double)e : 0.0;
     }
     if (disc > 0.0) {
-      const double sq = sqrt(disc);
+      const double sq = poly_sqrt(disc);
       // the crossing A + s E with s = (-ae -+ sq)/ee, scaled by ee > 0 (the
       // angle depends on the direction only)
       // smaller root strictly inside the edge: an exit (counter-clockwise)
