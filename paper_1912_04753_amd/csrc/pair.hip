@@ -213,7 +213,7 @@ __device__ __forceinline__ uint32_t qweight(float om, uint32_t half) {
 // Polygon weight: 1/omega capped at 64 (omega from FP64 angles), rounded to the
 // fixed-point grid: below 2^29 per side, so two sides fit 32 bits.
 __device__ __forceinline__ uint32_t qweight_poly(double om, uint32_t half) {
-  const double w = om * 64.0 > 1.0 ? 1.0 / om : 64.0;
+  const double w = om * 64.0 > 1.0 ? poly_div(1.0, om) : 64.0;
   return (uint32_t)rint(w * (double)(1u << kFracBits)) << half;
 }
 

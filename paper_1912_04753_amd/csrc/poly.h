@@ -76,6 +76,16 @@ __device__ __forceinline__ int32_t poly_edist(const Geom &g, int px, int py, int
   return (int32_t)fmax(floor(sqrt(best * (1.0 - 1e-12))) - 1.0, 0.0);
 }
 
+// a / b from the hardware reciprocal, one Newton step on it and one on the
+// quotient (equal to the IEEE quotient on 2^20 random pairs with exponents in
+// +-60): a few instructions instead of the IEEE division sequence
+__device__ __forceinline__ double poly_div(double a, double b) {
+  double r = __builtin_amdgcn_rcp(b);
+  r = fma(fma(-b, r, 1.0), r, r);
+  const double q = a * r;
+  return fma(fma(-b, q, a), r, q);
+}
+
 // Angle of (x, y) in [0, 2 pi), FP64, within a few ulp (depends only on the
 // direction of (x, y)): octant reduction to z = min/max in [0, 1], then
 // atan z = pi/6 + atan((sqrt(3) z - 1)/(z + sqrt(3))) for z > tan(pi/12) (one
@@ -87,8 +97,8 @@ __device__ __forceinline__ double poly_angle(double x, double y) {
   const double lo = fmin(ax, ay), hi = fmax(ax, ay);
   if (hi == 0.0) return 0.0;
   const bool red = lo > 0.26794919243112270 * hi;  // tan(pi/12)
-  const double z = red ? (lo * 1.7320508075688772 - hi) / (lo + hi * 1.7320508075688772)
-                       : lo / hi;
+  const double z = red ? poly_div(lo * 1.7320508075688772 - hi, lo + hi * 1.7320508075688772)
+                       : poly_div(lo, hi);
   const double base = red ? 0.52359877559829887 : 0.0;  // pi/6
   const double w = z * z;
   double p = 1.0 / 25.0;
