@@ -429,7 +429,8 @@ def main():
                          "pair_tests_per_s_G": round(ws[0][0] / (w_ms * 1e-3) / 1e9, 3),
                          "n_in_per_step": ws[0][0],
                          "sims_per_s": round(wm / (sum(v[1] for v in ws) / reps), 3) if wm else None,
-                         "cells_m_s": [wi["cell_s"], wi["cell_t"]]}
+                         "cells_m_s": [wi["cell_s"], wi["cell_t"]],
+                         "split": ripk.ripk_plan_stats(wplan)["split"]}
         wplan.destroy()
         del wx, wy, wt
     plan.destroy()

@@ -98,6 +98,12 @@ enum {
                                         /* extension named in Sec. 7: see below         */
 #define RIPK_PLAN_INHOM (1u << 6)       /* inhomogeneous K, the second extension named  */
                                         /* in Sec. 7: see below                         */
+#define RIPK_PLAN_SPLIT_RUNS (1u << 7)  /* a single-set launch that wants more work     */
+                                        /* items than stencil rows also cuts each row's */
+                                        /* neighbour run into equal fractions (uneven,  */
+                                        /* clustered sets); with RIPK_PLAN_AUTOTUNE the */
+                                        /* first ripk_compute_K tries both; results do  */
+                                        /* not depend on it                             */
 
 /*
  * Inhomogeneous K.  With RIPK_PLAN_INHOM, ripk_compute_K reads an intensity

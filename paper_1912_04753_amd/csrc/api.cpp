@@ -289,7 +289,8 @@ ripk_status derive(const ripk_plan_desc *d, Layout *L) {
     return fail(RIPK_EINVAL, "temporal correction needs t_max <= t1-t0");
   if (d->norm > RIPK_NORM_N2) return fail(RIPK_EINVAL, "unknown normalisation");
   if (d->flags & ~(RIPK_PLAN_ORDERED | RIPK_PLAN_TIMING | RIPK_PLAN_WIDE_COUNTS |
-                   RIPK_PLAN_AUTOTUNE | RIPK_PLAN_GRAPH | RIPK_PLAN_CROSS | RIPK_PLAN_INHOM))
+                   RIPK_PLAN_AUTOTUNE | RIPK_PLAN_GRAPH | RIPK_PLAN_CROSS | RIPK_PLAN_INHOM |
+                   RIPK_PLAN_SPLIT_RUNS))
     return fail(RIPK_EINVAL, "unknown plan flags");
   if ((d->flags & RIPK_PLAN_INHOM) && ((d->flags & RIPK_PLAN_CROSS) || d->poly_n != 0))
     return fail(RIPK_EINVAL, "inhomogeneous K plans take one point type and the rectangle");
@@ -389,10 +390,12 @@ constexpr int kTuneCand[][2] = {{1, 1}, {2, 1}, {1, 2}, {2, 2}, {3, 1}, {3, 2}};
 constexpr int kTuneN = (int)(sizeof kTuneCand / sizeof kTuneCand[0]);
 constexpr int kTuneSims = 32;  // simulations per timed candidate
 
+// (observed single sets also time every cell grid with run fractions)
 struct TuneState {
   bool done = false;
   int32_t cd = 1, td = 1;
-  double us[kTuneN] = {};
+  bool split_runs = false;
+  double us[2 * kTuneN] = {};
 };
 
 struct ripk_plan_s {
@@ -402,10 +405,11 @@ struct ripk_plan_s {
   hipEvent_t tev[2] = {};    // autotuner timing
   Layout lay;
   int32_t bound_cd = 1, bound_td = 1;  // cell subdivisions of the bound geometry
+  bool split_runs = false;             // run fractions for this call's launch
   uint64_t bind_gen = 0;               // bumped whenever a geometry is bound
   // RIPK_PLAN_GRAPH: the captured launch sequence of the last call shape
   hipGraphExec_t gexec = nullptr;
-  uint64_t gkey[14] = {};
+  uint64_t gkey[15] = {};
   int device = 0;
   int cus = 0;
   size_t lds_max = 0;  // LDS bytes a workgroup may use on this device
@@ -567,9 +571,16 @@ ripk_status enqueue_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_cent
   const int64_t items_est = (int64_t)S_split * (n / kChunk + 1);
   const uint32_t n_rows = symmetric ? (uint32_t)((g.rs + 1) + g.rt * (2 * g.rs + 1))
                                     : (uint32_t)((2 * g.rt + 1) * (2 * g.rs + 1));
-  int64_t split = (16 * slots * kItemsPerGroup + items_est - 1) / items_est;
-  split = std::min<int64_t>({split, (int64_t)kSplitMax, (int64_t)n_rows,
-                             p->caps.items / std::max<int64_t>(items_bound, 1)});
+  // With run fractions (RIPK_PLAN_SPLIT_RUNS, or chosen by the autotuner), a
+  // launch that wants more parts than rows cuts each row's run into k equal
+  // fractions: n_rows * k parts.
+  const int64_t want = (16 * slots * kItemsPerGroup + items_est - 1) / items_est;
+  const int64_t room = std::min<int64_t>(kSplitMax, p->caps.items / std::max<int64_t>(items_bound, 1));
+  int64_t split = std::min<int64_t>({want, (int64_t)n_rows, room});
+  if (p->split_runs && want > (int64_t)n_rows) {
+    const int64_t k = std::min<int64_t>({(want + n_rows - 1) / n_rows, kMaxFractions, room / n_rows});
+    if (k >= 2) split = (int64_t)n_rows * k;
+  }
   split = std::max<int64_t>(split, 1);
   HIPCHK(launch_items(p->cs, S, g, row_items, cross, (uint32_t)split, n_rows, p->chunks, p->offs,
                       p->set_base, p->items, n_items, p->scan_temp, st));
@@ -636,10 +647,11 @@ ripk_status run_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_centres,
   if (!graph)
     return enqueue_sets(p, S, n, n_centres, x, y, t, simulate, seed, has_Lobs, st, symmetric, timing,
                         S_split, with_obs);
-  const uint64_t key[14] = {S, n, n_centres, (uint64_t)simulate, (uint64_t)symmetric,
+  const uint64_t key[15] = {S, n, n_centres, (uint64_t)simulate, (uint64_t)symmetric,
                             (uint64_t)(uintptr_t)x, (uint64_t)(uintptr_t)y, (uint64_t)(uintptr_t)t,
                             seed, (uint64_t)has_Lobs, p->bind_gen, S_split,
-                            (uint64_t)(uintptr_t)p->cur_lam, (uint64_t)with_obs};
+                            (uint64_t)(uintptr_t)p->cur_lam, (uint64_t)with_obs,
+                            (uint64_t)p->split_runs};
   if (!p->gexec || std::memcmp(key, p->gkey, sizeof key) != 0) {
     if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
     p->gexec = nullptr;
@@ -879,12 +891,17 @@ ripk_status run_tuned(ripk_plan_s *p, int which, uint32_t S, uint32_t S_tune, ui
   if (p->user_desc.flags & RIPK_PLAN_AUTOTUNE) {
     TuneState &ts = p->tune[which];
     ripk_plan_desc d = p->user_desc;
+    // observed single sets: every cell grid without and with run fractions
+    // (with them only, when the plan forces them)
+    const bool forced = (p->user_desc.flags & RIPK_PLAN_SPLIT_RUNS) != 0;
+    const int n_cand = (which == 0 && S == 1 && !forced) ? 2 * kTuneN : kTuneN;
     if (!ts.done) {
       double best = 1e300;
       int bi = 0;
-      for (int i = 0; i < kTuneN; ++i) {
-        d.cell_div = kTuneCand[i][0];
-        d.tcell_div = kTuneCand[i][1];
+      for (int i = 0; i < n_cand; ++i) {
+        d.cell_div = kTuneCand[i % kTuneN][0];
+        d.tcell_div = kTuneCand[i % kTuneN][1];
+        p->split_runs = forced || i >= kTuneN;
         ripk_status s = bind_geometry(p, &d, st);
         if (s != RIPK_OK) return s;
         ts.us[i] = 1e300;
@@ -907,15 +924,19 @@ ripk_status run_tuned(ripk_plan_s *p, int which, uint32_t S, uint32_t S_tune, ui
         }
       }
       ts.done = true;
-      ts.cd = kTuneCand[bi][0];
-      ts.td = kTuneCand[bi][1];
+      ts.cd = kTuneCand[bi % kTuneN][0];
+      ts.td = kTuneCand[bi % kTuneN][1];
+      ts.split_runs = forced || bi >= kTuneN;
     }
+    p->split_runs = ts.split_runs;
     if (p->bound_cd != ts.cd || p->bound_td != ts.td) {
       d.cell_div = ts.cd;
       d.tcell_div = ts.td;
       ripk_status s = bind_geometry(p, &d, st);
       if (s != RIPK_OK) return s;
     }
+  } else {
+    p->split_runs = (p->user_desc.flags & RIPK_PLAN_SPLIT_RUNS) != 0;
   }
   return run_sets(p, S, n, nc, x, y, t, simulate, seed, L_obs, st, sym, 0, with_obs);
 }

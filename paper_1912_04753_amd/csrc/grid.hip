@@ -514,6 +514,10 @@ __global__ void k_set_base(const uint32_t *__restrict__ offs, uint32_t n_sets,
 __device__ __forceinline__ uint32_t item_count(uint32_t cnt, uint32_t p, uint32_t split,
                                                uint32_t n_rows) {
   if (split == 1) return cnt;
+  if (split > n_rows) {  // split = n_rows * k: row p / k, fraction p % k of its run
+    const uint32_t k = split / n_rows;
+    return cnt | ((p / k) << 7) | ((p % k) << 19) | (k << 25) | 0x80000000u;
+  }
   const uint32_t r0 = p * n_rows / split, r1 = (p + 1) * n_rows / split;
   return cnt | (r0 << 7) | (r1 << 19);
 }

@@ -755,9 +755,12 @@ k_pair(PairArgs a) {
     const uint32_t cw = uni(it.count);
     const uint32_t cnt = cw & 0x7Fu;
     if (cnt == 0) continue;
-    // the part of the stencil rows this item covers (all when not split)
+    // the part of the stencil rows this item covers (all when not split), or
+    // one row and a fraction fr of kf of its neighbour run
+    const bool frm = (cw >> 31) != 0;
     const int r0 = (int)((cw >> 7) & 0xFFFu);
-    const int r1 = (cw >> 19) ? (int)(cw >> 19) : 0x7FFFFFFF;
+    const int r1 = frm ? r0 + 1 : ((cw >> 19) ? (int)(cw >> 19) : 0x7FFFFFFF);
+    const uint32_t fr = frm ? ((cw >> 19) & 63u) : 0u, kf = frm ? ((cw >> 25) & 63u) : 1u;
     const uint32_t begin = uni(it.begin);
     const uint32_t cell = uni(it.cell);
     const bool valid = (uint32_t)lane < cnt;
@@ -815,6 +818,33 @@ k_pair(PairArgs a) {
         const uint32_t row = nb_off + (uint32_t)(tt * g.ny + yy) * (uint32_t)g.nx;
         uint32_t j0 = uni(a.cs[cst * (row + (uint32_t)xlo)]);
         const uint32_t j1 = uni(a.cs[cst * (row + (uint32_t)xhi + 1u)]);
+        if (kf > 1) {
+          // fraction fr of the run (in the symmetric home row, of j > the
+          // first centre); candidates counted exactly
+          const uint32_t a0 = (home && SYM) ? begin + 1 : j0;
+          const uint32_t len = j1 > a0 ? j1 - a0 : 0u;
+          const uint32_t s0 = a0 + (uint32_t)((uint64_t)len * fr / kf);
+          const uint32_t s1 = a0 + (uint32_t)((uint64_t)len * (fr + 1) / kf);
+          if (home) {
+            if (SYM) {
+              // each j pairs with the centres below it: j - begin of them, at most cnt
+              const uint32_t m = begin + cnt;
+              const uint32_t ta = min(s1, m), tb = max(s0, m);
+              if (ta > s0)
+                ev += (unsigned long long)(ta - s0) *
+                      ((unsigned long long)s0 + ta - 1 - 2ull * begin) / 2;
+              if (s1 > tb) ev += (unsigned long long)cnt * (s1 - tb);
+            } else {
+              const uint32_t lo = max(s0, begin), hi = min(s1, begin + cnt);
+              ev += (unsigned long long)cnt * (s1 - s0) - (hi > lo ? hi - lo : 0u);
+            }
+            scan_run<SYM, MODE, POLY, INHOM, true>(x, s0, s1, me, tplus, thr, valid, vmask, mi, a.P);
+          } else {
+            ev += (unsigned long long)cnt * (s1 - s0);
+            scan_run<SYM, MODE, POLY, INHOM, false>(x, s0, s1, me, tplus, thr, valid, vmask, mi, a.P);
+          }
+          continue;
+        }
         if (home) {
           if (SYM) {
             j0 = begin + 1;

@@ -58,9 +58,12 @@ struct Item {
   uint32_t begin;  // first centre, index into the sorted point array
   uint32_t count;  // bits 0-6: number of centres (0 = padding); bits 7-18 and
                    // 19-30: first and end index of the stencil rows this item
-                   // covers (end 0 = all rows; items split for small launches)
+                   // covers (end 0 = all rows; items split for small launches);
+                   // with bit 31 set, one row (bits 7-18) and fraction f (bits
+                   // 19-24) of k (bits 25-30) of its neighbour run
 };
-constexpr int kSplitMax = 32;  // stencil-row parts an item may be split into
+constexpr int kSplitMax = 64;  // parts an item may be split into
+constexpr int kMaxFractions = 8;  // fractions a row's run may be cut into
 // The pair kernel's work queue is cut into kQueues contiguous partitions of
 // item groups, one per XCD, each with its own counter kQueueStride words
 // (4 KB) from the next: returning atomics on one address serialise across the

@@ -42,6 +42,7 @@ RIPK_PLAN_AUTOTUNE = 8
 RIPK_PLAN_GRAPH = 16
 RIPK_PLAN_CROSS = 32
 RIPK_PLAN_INHOM = 64
+RIPK_PLAN_SPLIT_RUNS = 128
 RIPK_REQ_KEEP_SIMS = 1
 
 _i64, _i32, _u32, _u64, _f64 = (ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32,
