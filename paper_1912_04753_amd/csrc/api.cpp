@@ -256,7 +256,7 @@ namespace {
 // Validation and derived geometry; no device access.
 ripk_status derive(const ripk_plan_desc *d, Layout *L) {
   if (!d || !L) return fail(RIPK_EINVAL, "null descriptor");
-  std::memset(L, 0, sizeof *L);
+  *L = Layout{};  // every field zero, the polygon vertices released
   ripk_plan_info &I = L->info;
   const int64_t W = d->x1 - d->x0, H = d->y1 - d->y0, D = d->t1 - d->t0;
   if (d->x0 < kI32Min || d->x1 > kI32Max || d->y0 < kI32Min || d->y1 > kI32Max ||
