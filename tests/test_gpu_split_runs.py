@@ -76,3 +76,28 @@ def test_autotuned_clustered_set_matches_fixed_cells():
     b = _run(x, y, t, flags=ripk.RIPK_PLAN_AUTOTUNE)
     say("autotuned clustered, split", b["stats"]["split"])
     assert np.array_equal(a["C"], b["C"]) and np.array_equal(a["W"], b["W"])
+
+
+@pytest.mark.parametrize("n", [2, 65, 64 * 37 + 29])
+@pytest.mark.parametrize("ordered", [False, True])
+def test_split_runs_small_and_ragged_sets_match_oracle(n, ordered):
+    """Small sets want far more parts than rows, so most fractions hold empty
+    or one-point runs; a ragged last chunk and points on the window's sides
+    and corners are included."""
+    win = (0, 0, 6_000, 6_000, 0, 90 * DAY)
+    args = (win, 900, 15 * DAY, 9, 7)
+    x, y, t = workloads.uniform_points(np.random.default_rng(1000 + n), n, win)
+    x[:2], y[:2], t[:2] = (0, 6_000), (6_000, 0), (0, 90 * DAY)  # corners and period ends
+    flags = ripk.RIPK_PLAN_SPLIT_RUNS | (ripk.RIPK_PLAN_ORDERED if ordered else 0)
+    plan = ripk.ripk_plan(ripk.make_desc(*args, n_max=n, flags=flags))
+    try:
+        g = ripk.ripk_compute_K(plan, x, y, t)
+        st = ripk.ripk_plan_stats(plan)
+    finally:
+        plan.destroy()
+    say("split runs small n=%d ordered=%d split=%d" % (n, ordered, st["split"]))
+    compare(g, oracle.estimate(oracle.desc(*args), x, y, t), *args[1:], where="split runs n=%d" % n)
+    rows = 9 if ordered else 5  # stencil rows at one cell per s_max and t_max
+    assert st["split"] >= 2 * rows, st["split"]  # at least two fractions per row
+    nn = n * (n - 1)
+    assert st["n_eval"] <= nn if ordered else st["n_eval"] <= nn // 2
