@@ -93,6 +93,28 @@ def kernel_stats(stats_csv, top=12):
     return "\n".join(lines)
 
 
+def kernel_resources(trace_csv, match="k_pair"):
+    """Per kernel variant of a kernel trace: launch count, duration spread,
+    scratch (spill) bytes and the workgroup counts it was launched with.  The
+    trace's register and LDS columns are left out: they are not the compiler's
+    VGPR count, and LDS sized at launch is not in them."""
+    agg = {}
+    for r in csv.DictReader(open(trace_csv)):
+        if match not in r["Kernel_Name"]:
+            continue
+        a = agg.setdefault(_short_name(r["Kernel_Name"]), {"us": [], "grids": set(), "r": r})
+        a["us"].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+        a["grids"].add(int(r["Grid_Size_X"]) // max(int(r["Workgroup_Size_X"]), 1))
+    lines = ["| kernel | calls | min us | median us | max us | scratch bytes | threads per WG | workgroups |",
+             "|---|---|---|---|---|---|---|---|"]
+    for name, a in sorted(agg.items(), key=lambda kv: -sum(kv[1]["us"])):
+        us, r = sorted(a["us"]), a["r"]
+        wg = ", ".join(str(g) for g in sorted(a["grids"]))
+        lines.append(f"| `{name}` | {len(us)} | {us[0]:.1f} | {us[len(us) // 2]:.1f} | {us[-1]:.1f} | "
+                     f"{r['Scratch_Size']} | {r['Workgroup_Size_X']} | {wg} |")
+    return "\n".join(lines)
+
+
 PROFILE_CMD = ("rocprofv3 --kernel-trace --stats --output-format csv -d $R/gpurun_out/prof -o run -- "
                "python3 $R/bench.py --steps {steps} --warmup 1 --main-only")
 PMC_CMD = ("timeout -s KILL 120 rocprofv3 --pmc {counter} --output-format csv -d $R/gpurun_out/{d} -o {o} "
@@ -151,6 +173,8 @@ if __name__ == "__main__":
         print(json.dumps(traffic(sys.argv[2], sys.argv[3]), indent=1))
     elif sys.argv[1] == "stats":
         print(kernel_stats(sys.argv[2]))
+    elif sys.argv[1] == "resources":
+        print(kernel_resources(sys.argv[2], *(sys.argv[3:4] or ["k_pair"])))
     elif sys.argv[1] == "launches":
         print(" ".join(f"{v:.1f}" for v in pair_launches(sys.argv[2])))
     elif sys.argv[1] == "summary":
