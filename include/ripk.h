@@ -101,9 +101,11 @@ enum {
 #define RIPK_PLAN_SPLIT_RUNS (1u << 7)  /* a single-set launch that wants more work     */
                                         /* items than stencil rows also cuts each row's */
                                         /* neighbour run into equal fractions (uneven,  */
-                                        /* clustered sets); with RIPK_PLAN_AUTOTUNE the */
-                                        /* first ripk_compute_K tries both; results do  */
-                                        /* not depend on it                             */
+                                        /* clustered sets).  Without this flag, an      */
+                                        /* autotuned plan times its first single-set    */
+                                        /* ripk_compute_K with and without fractions    */
+                                        /* and keeps the faster; results do not depend  */
+                                        /* on it                                        */
 
 /*
  * Inhomogeneous K.  With RIPK_PLAN_INHOM, ripk_compute_K reads an intensity
