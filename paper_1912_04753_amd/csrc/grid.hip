@@ -322,6 +322,17 @@ struct SortTile {
   uint32_t seg, t, base, end, key0;
 };
 
+// Workgroups go to the chip's 8 XCDs in turn (hardware block b to XCD b % 8).
+// For a grid padded to a multiple of 8, the logical block (b % 8) * (grid / 8)
+// + b / 8 hands each XCD one contiguous eighth of the logical blocks, so the
+// sets one XCD gathers from stay in its own L2 (k_bounds_gather; the radix
+// scatter measured slower with it).  A bijection of [0, grid): logical blocks
+// past the real grid do nothing.
+constexpr uint32_t kXcds = 8;
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t grid) {
+  return (b % kXcds) * (grid / kXcds) + b / kXcds;
+}
+
 __device__ __forceinline__ SortTile sort_tile(const SortSeg &sg, uint32_t b) {
   SortTile r;
   r.seg = b / sg.tiles;
@@ -408,7 +419,7 @@ __global__ void k_bounds_gather(const uint32_t *__restrict__ keys,
                                 uint32_t *__restrict__ cs, const int32_t *__restrict__ x,
                                 const int32_t *__restrict__ y, const int32_t *__restrict__ t,
                                 Geom g, int32_t clamp_e, int4 *__restrict__ P) {
-  const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t r = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (r > n) return;
   const int64_t prev = (r == 0) ? -1 : (int64_t)keys[r - 1];
   const int64_t cur = (r == n) ? (int64_t)n_keys : (int64_t)keys[r];
@@ -577,6 +588,8 @@ __global__ void k_zero3(Zero3 z) {
 }
 
 inline uint32_t blocks_for(uint64_t n, int per) { return (uint32_t)((n + per - 1) / per); }
+// a grid of at least `blocks` workgroups, a multiple of the XCD count (see xcd_block)
+inline uint32_t xcd_grid(uint32_t blocks) { return (blocks + kXcds - 1) / kXcds * kXcds; }
 
 }  // namespace
 
@@ -695,8 +708,8 @@ hipError_t launch_bounds_gather(const uint32_t *keys, const uint32_t *vals, uint
                                 uint32_t n_keys, uint32_t *cs, const int32_t *x, const int32_t *y,
                                 const int32_t *t, const Geom &g, int32_t clamp_e, int4 *P,
                                 hipStream_t s) {
-  hipLaunchKernelGGL(k_bounds_gather, dim3(blocks_for((uint64_t)n + 1, kThreads)), dim3(kThreads),
-                     0, s, keys, vals, n, n_keys, cs, x, y, t, g, clamp_e, P);
+  hipLaunchKernelGGL(k_bounds_gather, dim3(xcd_grid(blocks_for((uint64_t)n + 1, kThreads))),
+                     dim3(kThreads), 0, s, keys, vals, n, n_keys, cs, x, y, t, g, clamp_e, P);
   return hipGetLastError();
 }
 
