@@ -688,8 +688,12 @@ hipError_t radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32
   void *stemp = (void *)(((uintptr_t)(offs + cnt + 1) + 255) & ~(uintptr_t)255);
   uint32_t *ka = keys, *va = vals, *kb = keys_alt, *vb = vals_alt;
   int alt = 0;
-  for (int shift = 0; shift < key_bits; shift += 8) {
-    int nbits = key_bits - shift < 8 ? key_bits - shift : 8;
+  // as many passes as 8-bit digits need, with the bits spread evenly over
+  // them: the first pass's scatter runs are then longer (13-bit keys: 7 + 6
+  // bits, not 8 + 5)
+  const int passes = (key_bits + 7) / 8, per = (key_bits + passes - 1) / passes;
+  for (int shift = 0; shift < key_bits; shift += per) {
+    int nbits = key_bits - shift < per ? key_bits - shift : per;
     uint32_t mask = (1u << nbits) - 1u;
     hipLaunchKernelGGL(k_sort_hist, dim3(nb), dim3(kThreads), 0, s, ka, sg, shift, mask, counts);
     hipError_t e = exclusive_scan(counts, offs, (uint32_t)cnt, stemp, s);
