@@ -100,3 +100,25 @@ def test_kernel_names_are_shortened():
         == "k_pair<true, 0>"
     assert profiling._short_name("ripk::(anonymous namespace)::k_gather(unsigned int const*, int)") \
         == "k_gather"
+
+
+def test_kernel_resources_table(tmp_path):
+    """Per-variant rows: launch count, min / median / max duration, scratch
+    bytes and the distinct workgroup counts, longest total first."""
+    path = tmp_path / "trace.csv"
+    cols = ["Kernel_Name", "Start_Timestamp", "End_Timestamp", "Scratch_Size", "Workgroup_Size_X",
+            "Grid_Size_X"]
+    rows = [("void ripk::(anonymous namespace)::k_pair<true, 0, false, false>(ripk::PairArgs)", 0, 3000, 0, 256, 1536 * 256),
+            ("void ripk::(anonymous namespace)::k_pair<true, 0, false, false>(ripk::PairArgs)", 5000, 6000, 0, 256, 1024 * 256),
+            ("void ripk::(anonymous namespace)::k_pair<true, 0, false, false>(ripk::PairArgs)", 7000, 9000, 0, 256, 1536 * 256),
+            ("void ripk::(anonymous namespace)::k_pair<true, 0, true, false>(ripk::PairArgs)", 0, 500, 16, 256, 1024 * 256),
+            ("ripk::k_csr(unsigned int)", 0, 100000, 0, 256, 256)]
+    with open(path, "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(cols)
+        w.writerows(rows)
+    lines = profiling.kernel_resources(str(path)).splitlines()
+    assert len(lines) == 4  # header, rule, two pair variants (k_csr filtered out)
+    assert lines[2] == "| `k_pair<true, 0, false, false>` | 3 | 1.0 | 2.0 | 3.0 | 0 | 256 | 1024, 1536 |"
+    assert lines[3] == "| `k_pair<true, 0, true, false>` | 1 | 0.5 | 0.5 | 0.5 | 16 | 256 | 1024 |"
+    assert "k_csr" in profiling.kernel_resources(str(path), "k_")
