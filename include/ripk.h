@@ -295,6 +295,38 @@ ripk_status ripk_compute_K_envelope(ripk_plan_t plan, const ripk_points *pts, in
                                     uint64_t seed, void *stream, ripk_K_out *k_out,
                                     ripk_env_out *env_out);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the K and L
+ * of one observed set, as ripk_compute_K computes them on a plan made from
+ * `desc`, with no plan and no allocation.  Every device buffer of the call is
+ * cut from one static device array of RIPK_NOALLOC_SCRATCH_BYTES bytes, which
+ * each device the library runs on holds from the library's first use on it
+ * until the process ends.  Its contents stay from one call to the next; the
+ * call clears what it needs cleared.
+ *
+ *  - desc: a rectangle study area (poly_n = 0), one point type, no
+ *    intensities: flags may hold RIPK_PLAN_ORDERED, RIPK_PLAN_WIDE_COUNTS and
+ *    RIPK_PLAN_SPLIT_RUNS only; cell_div/tcell_div as in ripk_plan (no
+ *    autotuning); n_max and m_max are ignored (the call is sized by pts->n).
+ *  - pts: as for ripk_compute_K (host or device coordinates; n_centres as
+ *    there; lambda ignored).
+ *  - out: DEVICE buffers of n_s*n_t elements on desc->device (any may be
+ *    NULL), written on `stream` only when the call succeeds; the call returns
+ *    after they are written.
+ *  - Results are bit-identical to ripk_compute_K on a plan of the same
+ *    descriptor (exact integer sums; the same FP64 finalisation).
+ *  - Errors: EINVAL (as ripk_compute_K, and for a polygon, intensities,
+ *    RIPK_PLAN_CROSS or other flags), E2BIG when the call's buffers (about
+ *    52 bytes per point plus 1 KiB per cell of the grid) exceed the scratch
+ *    array, ERANGE, EDEVICE.  Nothing is allocated on any path.
+ *  - Calls that overlap on one device (from several threads, or on several
+ *    streams without ordering) share the array and race: serialise them.
+ */
+#define RIPK_NOALLOC_SCRATCH_BYTES (64ull << 20)
+ripk_status ripk_compute_K_noalloc(const ripk_plan_desc *desc, const ripk_points *pts,
+                                   void *stream, ripk_K_out *out);
+
 /* Counters and timings of the plan's last compute call. */
 ripk_status ripk_plan_stats(ripk_plan_t plan, ripk_stats *out);
 

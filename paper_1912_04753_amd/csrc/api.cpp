@@ -27,16 +27,16 @@ using namespace ripk;
 
 namespace {
 
-thread_local std::string g_err;
+// detail of the calling thread's last error (a fixed buffer: recording an
+// error allocates nothing)
+thread_local char g_err[512];
 
 ripk_status fail(ripk_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 ripk_status fail(ripk_status s, const char *fmt, ...) {
-  char buf[512];
   va_list ap;
   va_start(ap, fmt);
-  vsnprintf(buf, sizeof buf, fmt, ap);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
   va_end(ap);
-  g_err = buf;
   return s;
 }
 
@@ -945,6 +945,133 @@ void plan_free(ripk_plan_s *p) { release(p); }
 
 ripk_status set_error(ripk_status s, const char *msg) { return fail(s, "%s", msg); }
 
+namespace {
+
+// Hands out 256-byte aligned pieces of one region (base null: sizes only).
+struct Carve {
+  unsigned char *base;
+  size_t off = 0;
+  template <typename T>
+  T *take(size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    T *p = base ? (T *)(base + off) : nullptr;
+    off += std::max<size_t>(count, 1) * sizeof(T);
+    return p;
+  }
+};
+
+// The device buffers one observed set needs, cut from `base` (plan buffers
+// the call does not use stay null); returns the bytes taken.
+size_t carve_observed(ripk_plan_s *p, const Caps &c, bool host_points, unsigned char *base) {
+  Carve k{base};
+  p->scal = k.take<unsigned long long>((size_t)(kQueues + 1) * kQueueStride);
+  p->binC = k.take<unsigned long long>(c.SNB);
+  p->binW = k.take<unsigned long long>(2 * c.SNB);
+  for (int b = 0; b < 2; ++b) {
+    p->keys[b] = k.take<uint32_t>(c.N);
+    p->vals[b] = k.take<uint32_t>(c.N);
+  }
+  p->sort_temp = k.take<unsigned char>(radix_sort_temp_bytes((uint32_t)c.N, (uint32_t)c.S));
+  p->cs = k.take<uint32_t>(2 * c.SNC + 1);
+  p->P = k.take<int4>(c.N);
+  p->chunks = k.take<uint32_t>(c.SNC);
+  p->offs = k.take<uint32_t>(c.SNC + 1);
+  p->set_base = k.take<uint32_t>(c.S + 1);
+  p->scan_temp = k.take<unsigned char>(scan_temp_bytes((uint32_t)c.SNC) + 256);
+  p->items = k.take<Item>(c.items);
+  p->outC = k.take<unsigned long long>(c.SNB);
+  p->outW = k.take<double>(c.SNB);
+  p->outK = k.take<double>(c.SNB);
+  p->outL = k.take<double>(c.SNB);
+  p->S2 = k.take<uint64_t>(kMaxSteps);
+  p->T = k.take<uint32_t>(kMaxSteps);
+  if (host_points) {
+    p->x = k.take<int32_t>(c.N);
+    p->y = k.take<int32_t>(c.N);
+    p->t = k.take<int32_t>(c.N);
+  }
+  return k.off;
+}
+
+}  // namespace
+
+// ripk_compute_K for a rectangle, one point type and no intensities, with
+// every device buffer cut from the caller's region `scratch` (no allocation):
+// the plan lives on the stack, the thresholds are copied from it, and the
+// results go to the device buffers of `out` once the call has succeeded.
+ripk_status compute_K_in_scratch(const ripk_plan_desc *desc, const ripk_points *pts,
+                                 hipStream_t st, unsigned char *scratch, size_t scratch_bytes,
+                                 ripk_K_out *out) {
+  if (!desc || !pts) return fail(RIPK_EINVAL, "null descriptor or points");
+  if (desc->poly_n != 0 || desc->poly)
+    return fail(RIPK_EINVAL, "the allocation-free call takes the rectangle (no polygon)");
+  if (desc->flags & ~(RIPK_PLAN_ORDERED | RIPK_PLAN_WIDE_COUNTS | RIPK_PLAN_SPLIT_RUNS))
+    return fail(RIPK_EINVAL,
+                "the allocation-free call takes RIPK_PLAN_ORDERED, RIPK_PLAN_WIDE_COUNTS and "
+                "RIPK_PLAN_SPLIT_RUNS only");
+  const int64_t n = pts->n;
+  const int64_t nc = pts->n_centres ? pts->n_centres : n;
+  if (n < 2) return fail(RIPK_EINVAL, "need n >= 2 points (n(n-1) = 0 otherwise)");
+  if (nc < 0 || nc > n) return fail(RIPK_EINVAL, "n_centres must be in [0, n]");
+  if (n >= (1LL << 31)) return fail(RIPK_EINVAL, "n must be below 2^31");
+  if (!pts->x || !pts->y || !pts->t) return fail(RIPK_EINVAL, "null coordinate array");
+  // sized for this call's n; no simulations
+  ripk_plan_desc d = *desc;
+  d.n_max = n;
+  d.m_max = 0;
+  Layout L;
+  ripk_status s = derive(&d, &L);
+  if (s != RIPK_OK) return s;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || d.device < 0 || d.device >= ndev)
+    return fail(RIPK_EINVAL, "device %d out of range", d.device);
+  DeviceGuard dg(d.device);
+  ripk_plan_s p;
+  p.device = d.device;
+  int cus = 0, lds = 0;
+  HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, d.device));
+  HIPCHK(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, d.device));
+  p.cus = cus;
+  p.lds_max = (size_t)lds;
+  p.caps = L.caps;
+  const bool host_points = !pts->on_device;
+  const size_t need = carve_observed(&p, p.caps, host_points, nullptr);
+  if (need > scratch_bytes)
+    return fail(RIPK_E2BIG,
+                "%lld points on %lld cells need %zu bytes of scratch; the allocation-free call "
+                "has %zu",
+                (long long)n, (long long)L.info.n_cells, need, scratch_bytes);
+  carve_observed(&p, p.caps, host_points, scratch);
+  s = bind_geometry(&p, &d, st);
+  if (s != RIPK_OK) return s;
+  p.user_desc = d;
+  p.split_runs = (d.flags & RIPK_PLAN_SPLIT_RUNS) != 0;
+  const int32_t *x = pts->x, *y = pts->y, *t = pts->t;
+  if (host_points) {
+    HIPCHK(hipMemcpyAsync(p.x, x, sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(p.y, y, sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(p.t, t, sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
+    x = p.x; y = p.y; t = p.t;
+  }
+  const bool sym = !(d.flags & RIPK_PLAN_ORDERED) && nc == n;
+  s = enqueue_sets(&p, 1, (uint32_t)n, (uint32_t)nc, x, y, t, false, 0, false, st, sym, false, 1);
+  if (s != RIPK_OK) return s;
+  unsigned long long sc[3] = {0, 0, 0};
+  HIPCHK(hipMemcpyAsync(sc, p.scal, sizeof sc, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  const uint32_t err = (uint32_t)sc[2];
+  if (err) return err_status(err);
+  if (out) {
+    const size_t bytes = 8 * (size_t)L.info.n_bins;
+    void *dst[4] = {out->C, out->W, out->K, out->L};
+    const void *src[4] = {p.outC, p.outW, p.outK, p.outL};
+    for (int r = 0; r < 4; ++r)
+      if (dst[r]) HIPCHK(hipMemcpyAsync(dst[r], src[r], bytes, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  return RIPK_OK;
+}
+
 }  // namespace ripk
 
 extern "C" {
@@ -966,7 +1093,7 @@ const char *ripk_status_str(ripk_status s) {
   }
 }
 
-const char *ripk_last_error(void) { return g_err.c_str(); }
+const char *ripk_last_error(void) { return g_err; }
 
 ripk_status ripk_plan_check(const ripk_plan_desc *desc, ripk_plan_info *info) {
   Layout L;

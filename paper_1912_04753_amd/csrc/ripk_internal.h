@@ -121,6 +121,12 @@ ripk_status plan_bind(ripk_plan_s *p, const ripk_plan_desc *desc, hipStream_t st
 const Caps &plan_caps(const ripk_plan_s *p);
 void plan_free(ripk_plan_s *p);
 ripk_status set_error(ripk_status s, const char *msg);  // sets ripk_last_error()
+// ripk_compute_K of one rectangle set with every device buffer cut from the
+// region [scratch, scratch + scratch_bytes) of the descriptor's device;
+// outputs are device buffers (api.cpp)
+ripk_status compute_K_in_scratch(const ripk_plan_desc *desc, const ripk_points *pts,
+                                 hipStream_t st, unsigned char *scratch, size_t scratch_bytes,
+                                 ripk_K_out *out);
 
 // launchers (kernels.hip) ----------------------------------------------
 // Sort keys: interleaved ((set*n_cells + cell) << 1 | halo) or, with

@@ -131,6 +131,7 @@ _SIGS = {
                                       ctypes.c_void_p, _P(EnvOut)]),
     "ripk_compute_K_envelope": (_i32, [ctypes.c_void_p, _P(Points), _i32, _u64, ctypes.c_void_p,
                                        _P(KOut), _P(EnvOut)]),
+    "ripk_compute_K_noalloc": (_i32, [_P(PlanDesc), _P(Points), ctypes.c_void_p, _P(KOut)]),
     "ripk_plan_stats": (_i32, [ctypes.c_void_p, _P(Stats)]),
     "ripk_plan_get_info": (_i32, [ctypes.c_void_p, _P(PlanInfo)]),
     "ripk_server_create": (_i32, [_P(ServerDesc), _P(ctypes.c_void_p)]),
@@ -381,6 +382,38 @@ def ripk_compute_K_envelope(plan, x, y, t, m, seed, n_centres=0, stream=None, pe
                                          ctypes.byref(eout)), "ripk_compute_K_envelope")
     del kx, ky, kt
     return res
+
+
+RIPK_NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def ripk_compute_K_noalloc(desc, x, y, t, out, n_centres=0, stream=None):
+    """The allocation-free K, L of one observed set: ``out`` is a dict of torch
+    CUDA tensors "C" (uint64 or int64), "W", "K", "L" (float64), each of
+    n_s*n_t elements (any may be missing), written on success."""
+    n = len(x)
+    px, dx, kx = _coord_ptr(x, n)
+    py, dy, ky = _coord_ptr(y, n)
+    pt, dt, kt = _coord_ptr(t, n)
+    if not (dx == dy == dt):
+        raise ValueError("coordinates must all be on the host or all on the device")
+    nb = desc.n_s * desc.n_t
+
+    def dptr(key, ct):
+        a = out.get(key)
+        if a is None:
+            return _P(ct)()
+        if not (_is_torch(a) and a.is_cuda and a.is_contiguous() and a.numel() == nb
+                and a.element_size() == 8):
+            raise ValueError(f"out[{key!r}] must be a contiguous 8-byte CUDA tensor of n_s*n_t")
+        return ctypes.cast(ctypes.c_void_p(a.data_ptr()), _P(ct))
+
+    pts = Points(px, py, pt, n, int(n_centres), 1 if dx else 0, _P(_f64)())
+    kout = KOut(dptr("C", _u64), dptr("W", _f64), dptr("K", _f64), dptr("L", _f64))
+    st = _stream_for([x, y, t] + [v for v in out.values() if v is not None], stream)
+    _check(lib().ripk_compute_K_noalloc(ctypes.byref(desc), ctypes.byref(pts), st,
+                                        ctypes.byref(kout)), "ripk_compute_K_noalloc")
+    del kx, ky, kt
 
 
 def ripk_plan_stats(plan):
