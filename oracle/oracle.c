@@ -47,7 +47,9 @@
  * the boundary-vertex cost of Sec. 4.4): A is the polygon's area, points lie
  * strictly inside it, omega is the share of the circle's circumference inside
  * it (arcs between crossing points, each classified by its midpoint), and the
- * spatial weight 1/omega is capped at 64.  CSR points are drawn by rejection:
+ * spatial weight is 1/omega with no bound: omega > 0 for every pair, since the
+ * neighbour j lies strictly inside the area and on the circle, so an arc about
+ * j is inside.  CSR points are drawn by rejection:
  * attempt a of point i uses counter (i, sim, a, 0) and the first attempt
  * strictly inside is kept.
  *
@@ -81,8 +83,6 @@ typedef struct {
                           /* (poly[2k], poly[2k+1]), closed implicitly    */
   int32_t poly_n;         /* vertex count; below 3: the rectangle         */
 } orc_desc;
-
-#define ORC_MAX_SWEIGHT 64.0 /* cap of the spatial weight 1/omega (polygons) */
 
 /* ---------------------------------------------------------------- O1 -- */
 /* Integer thresholds: S2[k-1] = floor((k*s_max)^2 / n_s^2), T[l-1] =
@@ -315,9 +315,8 @@ static int orc_hist_range(const orc_desc *q, const int32_t *x, const int32_t *y,
         while (d2 > S2[k]) ++k; /* smallest k with d2 <= S2[k] */
         int l = 0;
         while (u > T[l]) ++l;
-        /* spatial weight 1/omega, capped (omega >= 1/4 on a rectangle) */
-        double om = orc_omega(xi, yi, d2, q);
-        if (om < 1.0 / ORC_MAX_SWEIGHT) om = 1.0 / ORC_MAX_SWEIGHT;
+        /* spatial weight 1/omega (Sec. 3; omega >= 1/4 on a rectangle) */
+        const double om = orc_omega(xi, yi, d2, q);
         double w = 1.0 / (om * orc_vt(ti, u, q));
         if (rho) w *= rho[i] * rho[j]; /* inhomogeneous: 1/(lambda_i lambda_j) */
         c[k * nt + l] += 1;

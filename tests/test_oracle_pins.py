@@ -687,21 +687,34 @@ def test_polygon_csr_expectation():
     assert np.all(np.abs(z) < 4.0), z
 
 
-def test_polygon_weight_cap():
-    """A thin spike: a centre near its tip sees less than 1/64 of the circle
-    inside at a radius beyond the spike's width; the spatial weight is capped
-    at 64, so the one ordered pair weighs exactly 64."""
-    spike = [(0, 0), (4000, 0), (4000, 100), (1000, 100), (1000, 4000), (0, 4000)]
+def test_polygon_weight_uncapped_spike():
+    """Sec. 3's spatial weight 1/omega has no bound: on the thin arm of an L
+    (y in [0, w], x in [1000, 4000]) a circle of radius r about a centre at
+    height w/2 stays inside only where |sin(th)| <= (w/2)/r and x lies on the
+    arm.  Centre (3990, w/2), r = 1390: one such arc (near th = pi), so
+    omega = asin(w/2r)/pi (1/omega = 87.3 for w = 100, 873 for w = 10); centre
+    (2600, w/2): two arcs, omega = 2 asin(w/2r)/pi.  The two-point set weighs
+    exactly the sum of both inverses, far beyond 64; angle sampling of the
+    circle agrees."""
     win = (0, 0, 4000, 4000, 0, 1000)
-    d = oracle.desc(win, 1500, 100, 1, 1, edge=oracle.EDGE_SPATIAL, poly=spike)
-    x = np.array([3990, 2600], np.int32); y = np.array([50, 50], np.int32)
-    t = np.array([10, 10], np.int32)
-    om = oracle.omega(3990, 50, 1390 ** 2, d)
-    assert 0 < om < 1 / 64
-    Hc, Hw = oracle.hist(d, x, y, t)
-    assert Hc[0, 0] == 2
-    w_back = 1.0 / oracle.omega(2600, 50, 1390 ** 2, d)
-    assert abs(Hw[0, 0] - (64.0 + min(w_back, 64.0))) < 1e-9
+    for w in (100, 10):
+        spike = [(0, 0), (4000, 0), (4000, w), (1000, w), (1000, 4000), (0, 4000)]
+        d = oracle.desc(win, 1500, 100, 1, 1, edge=oracle.EDGE_SPATIAL, poly=spike)
+        a = math.asin((w / 2) / 1390)
+        om_i = oracle.omega(3990, w // 2, 1390 ** 2, d)
+        om_j = oracle.omega(2600, w // 2, 1390 ** 2, d)
+        assert abs(om_i - a / math.pi) < 1e-13 * (a / math.pi) + 1e-15, (w, om_i)
+        assert abs(om_j - 2 * a / math.pi) < 1e-13 * (a / math.pi) + 1e-15, (w, om_j)
+        assert 1 / om_i > 64
+        th = (np.arange(2_000_000) + 0.5) * (2 * np.pi / 2_000_000)
+        share = _inside_np(spike, 3990 + 1390 * np.cos(th), w / 2 + 1390 * np.sin(th)).mean()
+        assert abs(share - om_i) < 2e-6, (w, share, om_i)
+        x = np.array([3990, 2600], np.int32); y = np.array([w // 2, w // 2], np.int32)
+        t = np.array([10, 10], np.int32)
+        Hc, Hw = oracle.hist(d, x, y, t)
+        assert Hc[0, 0] == 2
+        want = math.pi / a * 1.5
+        assert abs(Hw[0, 0] - want) < 1e-12 * want, (w, Hw[0, 0], want)
 
 
 # -------------------------------------------------------- inhomogeneous K ----
