@@ -113,10 +113,16 @@ enum {
  * NULL, RIPK_ERANGE when a value is not positive and finite) and computes
  *   K_I(s,t) = 1/(A*D) * sum_i sum_{j!=i} I(d_ij <= s, u_ij <= t) / (omega_ij v_ij lambda_i lambda_j),
  * which is Eq. 2 with N = n^2 when lambda is the constant n/(A*D); L_I follows
- * as in Eq. 4, and C counts pairs as usual.  The norm field is ignored.  The
- * weighted sums are FP64 (device atomics in an order that varies from run to
- * run, so W, K and L may differ in their last bits between runs; counts are
- * exact).  Such plans take a rectangle (no polygon), one point type (no
+ * as in Eq. 4, and C counts pairs as usual.  The norm field is ignored.  Every
+ * lambda must lie in [2^-400, 2^400] (RIPK_ERANGE otherwise).  Each side's
+ * weight w/(lambda_i lambda_j) (w the FP32 weight of the homogeneous path) is
+ * rounded in FP64 to a multiple of 2^-F and the multiples are summed exactly,
+ * so W, K and L are bitwise identical across runs, launch shapes and symmetric
+ * or ordered evaluation.  F is taken per call from the largest 1/lambda, so
+ * that one pair stays below 2^B units with B = min(93, 126 - ceil(log2(n(n-1))))
+ * (B >= 82 for n < 2^22): the rounding adds a relative error below
+ * 2^(5-B) (lambda_max/lambda_min)^2 to a bin.  n_max must be below 2^22.
+ * Such plans take a rectangle (no polygon), one point type (no
  * RIPK_PLAN_CROSS) and no simulations: the null model, a Poisson process of
  * intensity lambda, needs the intensity as a function, not at the points
  * (ripk_simulate_envelope returns RIPK_EINVAL).
@@ -177,8 +183,13 @@ typedef struct {
  *   - A in Eq. 2 is its area (shoelace); every point must lie strictly inside
  *     it (RIPK_ERANGE otherwise);
  *   - omega_ij is the share of the circle centred on point i with radius d_ij
- *     that lies inside the polygon, and the spatial weight 1/omega_ij is capped
- *     at 64; the rule 2*s_max <= min(x1-x0, y1-y0) does not apply;
+ *     that lies inside the polygon, and the spatial weight is 1/omega_ij with
+ *     no cap: j lies strictly inside and on the circle, so omega_ij > 0, and
+ *     on the integer lattice 1/omega_ij < pi*|E|*s_max < 2^49.2 (|E| the
+ *     longest edge); each side's weight is rounded to a multiple of 2^-23 and
+ *     summed exactly in 128-bit fixed point; the rule
+ *     2*s_max <= min(x1-x0, y1-y0) does not apply;
+ *   - with RIPK_EDGE_SPATIAL_ISO, n_max must be below 2^22 (RIPK_EINVAL);
  *   - CSR simulations draw by rejection: attempt a of point k of set s uses the
  *     Philox counter (k, s, a, 0) and the first attempt strictly inside is kept.
  * The vertex array is read during ripk_plan_check, ripk_plan and ripk_submit
@@ -246,7 +257,8 @@ typedef struct {
   int32_t split;           /* parts each work item's stencil rows were split into        */
   int32_t bin_layout;      /* LDS bins of the pair kernel: 0 count and interior weight
                               in one word, 1 weight + 32-bit count, 2 weight + 64-bit
-                              count                                                      */
+                              count, 3 count + three words of 32-bit weight pieces
+                              (polygon weights, inhomogeneous K)                         */
   double us_total;         /* wall time of the call, microseconds                        */
   double us_gen, us_grid, us_pair, us_finalize; /* device phases (RIPK_PLAN_TIMING)      */
 } ripk_stats;

@@ -217,7 +217,7 @@ int64_t caps_bytes(const Caps &c) {
   bytes += 16 * c.N;                          // sorted point records
   bytes += 4 * c.SNC * 2 + 4 * (c.S + 1) + (int64_t)scan_temp_bytes((uint32_t)c.SNC) + 256;
   bytes += 16 * c.items;                      // work items
-  bytes += 8 * 3 * c.SNB;                     // bins
+  bytes += 8 * (1 + kBinWords) * c.SNB;       // bins
   bytes += 8 * 4 * c.SNB;                     // C, W, K, L
   bytes += 8 * 6 * c.NB + 8 * 2 * kMaxSteps;  // envelopes, L_obs, thresholds
   bytes += 8 * (kQueues + 1) * kQueueStride;   // scalars and work-queue blocks
@@ -294,6 +294,12 @@ ripk_status derive(const ripk_plan_desc *d, Layout *L) {
     return fail(RIPK_EINVAL, "unknown plan flags");
   if ((d->flags & RIPK_PLAN_INHOM) && ((d->flags & RIPK_PLAN_CROSS) || d->poly_n != 0))
     return fail(RIPK_EINVAL, "inhomogeneous K plans take one point type and the rectangle");
+  // polygon weights and inhomogeneous weights are summed in wide fixed point,
+  // whose LDS piece sums are bounded for sets below kWidePoints
+  if (((d->poly_n != 0 && (d->edge & RIPK_EDGE_SPATIAL_ISO)) || (d->flags & RIPK_PLAN_INHOM)) &&
+      d->n_max >= kWidePoints)
+    return fail(RIPK_EINVAL,
+                "polygon (with spatial correction) and inhomogeneous plans take n_max below 2^22");
   if (d->sim_method != RIPK_SIM_CSR && d->sim_method != RIPK_SIM_PERMUTE &&
       d->sim_method != RIPK_SIM_BOOTSTRAP)
     return fail(RIPK_EINVAL, "unknown simulation method");
@@ -489,6 +495,16 @@ struct DeviceGuard {
   ~DeviceGuard() { (void)hipSetDevice(prev); }
 };
 
+// Bit budget of one pair's fixed-point weight in an inhomogeneous launch of
+// sets of n points: below 2^93 (three 32-bit pieces per side with room), and
+// n(n-1) ordered pairs below 2^budget each sum below 2^126.
+int wide_budget(uint32_t n) {
+  const uint64_t pairs = (uint64_t)n * (n > 0 ? n - 1 : 0);
+  int lg = 0;
+  while (lg < 64 && (1ull << lg) < pairs) ++lg;  // ceil(log2(pairs))
+  return std::min(93, 126 - lg);
+}
+
 // Enqueues the launch sequence of one evaluation of S sets of n points each on
 // st (kernels only, and event records when timing): capturable into a graph.
 // With `simulate` the points are drawn on the device; otherwise keys come from
@@ -509,7 +525,8 @@ ripk_status enqueue_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_cent
   unsigned long long *queues = p->scal + kQueueStride;
   // the scalars and work queue, and every set's bins
   HIPCHK(launch_zero3(Zero3{{p->scal, p->binC, p->binW},
-                            {(size_t)(kQueues + 1) * kQueueStride, (size_t)S * NB, (size_t)S * NB * 2}},
+                            {(size_t)(kQueues + 1) * kQueueStride, (size_t)S * NB,
+                             (size_t)S * NB * kBinWords}},
                       st));
   const bool cross = (p->desc.flags & RIPK_PLAN_CROSS) != 0;
   const uint32_t so = with_obs ? 1u : 0u;  // sets before the first simulation
@@ -542,19 +559,23 @@ ripk_status enqueue_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_cent
   HIPCHK(launch_bounds_gather(p->keys[alt], p->vals[alt], N, (uint32_t)n_keys, p->cs, x, y, t, g,
                               p->lay.clamp_e, p->P, st));
   const bool inhom = (p->desc.flags & RIPK_PLAN_INHOM) != 0 && !simulate;
-  if (inhom) HIPCHK(launch_gather_rho(p->vals[alt], N, p->cur_lam, p->rho, err, st));
+  // (scal[3]: the largest 1/lambda of an inhomogeneous launch, as its bits)
+  unsigned long long *rho_max = p->scal + 3;
+  if (inhom) HIPCHK(launch_gather_rho(p->vals[alt], N, p->cur_lam, p->rho, err, rho_max, st));
   // row items need rows without halo entries: every point a centre, or the
   // type-1 block of a cross-K set
   const bool row_items = n_centres == n || cross;
-  // bin layout: packed (one LDS atomic per pair) unless the set is large, the
-  // weights are FP64 or the extra 4 bytes per bin would lower the occupancy
+  // bin layout: wide for polygon weights and inhomogeneous K; otherwise packed
+  // (one LDS atomic per pair) unless the set is large or the extra 4 bytes
+  // per bin would lower the occupancy
   const int var = inhom ? 2 : (pair_poly(g) ? 1 : 0);
-  int bins = ((int64_t)n >= kWideCountPoints || (p->desc.flags & RIPK_PLAN_WIDE_COUNTS))
-                 ? kBinsSplit64
-                 : kBinsSplit32;
+  int bins = pair_bins_for_var(
+      var, ((int64_t)n >= kWideCountPoints || (p->desc.flags & RIPK_PLAN_WIDE_COUNTS))
+               ? kBinsSplit64
+               : kBinsSplit32);
   int per_cu = 0;
   HIPCHK(pair_occupancy(g.n_s, g.n_t, bins, symmetric ? 1 : 0, g.mode, var, &per_cu));
-  if (bins == kBinsSplit32 && !inhom && (int64_t)n < kPackedPoints) {
+  if (bins == kBinsSplit32 && (int64_t)n < kPackedPoints) {
     int per_cu_packed = 0;
     HIPCHK(pair_occupancy(g.n_s, g.n_t, kBinsPacked, symmetric ? 1 : 0, g.mode, var,
                           &per_cu_packed));
@@ -602,6 +623,8 @@ ripk_status enqueue_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_cent
   a.row_items = row_items ? 1 : 0;
   a.blocked = cross ? 1 : 0;
   a.rho = inhom ? p->rho : nullptr;
+  a.rho_max = inhom ? rho_max : nullptr;
+  a.wbudget = inhom ? wide_budget(n) : 0;
   a.bins = bins;
   const int64_t groups_cap = items_bound * split / kItemsPerGroup + 1;
   const int grid = (int)std::min<int64_t>(slots, groups_cap);
@@ -617,7 +640,7 @@ ripk_status enqueue_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_cent
                                                    : (double)n * (double)(n - 1);
   HIPCHK(launch_finalize(p->binC, p->binW, S, g.n_s, g.n_t, (double)p->desc.s_max,
                          (double)p->desc.t_max, AD, Nn, p->outC, p->outW, p->outK, p->outL,
-                         queues, p->scal, st, inhom));
+                         queues, p->scal, st, a.rho_max, a.wbudget));
   if (simulate && with_obs)
     HIPCHK(launch_envelope(p->outK + NB, p->outL + NB, S - 1, (int)NB, p->outL, p->env, st));
   else if (simulate)
@@ -716,7 +739,7 @@ ripk_status collect_stats(ripk_plan_s *p, hipStream_t st, uint32_t S, uint32_t n
 // point that found no attempt inside the polygon
 ripk_status err_status(uint32_t err) {
   if (err & 1u) return fail(RIPK_ERANGE, "a point lies outside the study area");
-  if (err & 4u) return fail(RIPK_ERANGE, "an intensity is not positive and finite");
+  if (err & 4u) return fail(RIPK_ERANGE, "an intensity lies outside [2^-400, 2^400]");
   return fail(RIPK_EDEVICE, "rejection sampling found no point inside the polygon");
 }
 
@@ -770,7 +793,7 @@ ripk_status plan_create(int device, const Caps &c, ripk_plan_s **out) {
   ALLOC(p->chunks, c.SNC); ALLOC(p->offs, c.SNC + 1); ALLOC(p->set_base, c.S + 1);
   if (e == hipSuccess) e = hipMalloc(&p->scan_temp, scan_temp_bytes((uint32_t)c.SNC) + 256);
   ALLOC(p->items, c.items);
-  ALLOC(p->binC, c.SNB); ALLOC(p->binW, 2 * c.SNB);
+  ALLOC(p->binC, c.SNB); ALLOC(p->binW, kBinWords * c.SNB);
   ALLOC(p->outC, c.SNB); ALLOC(p->outW, c.SNB); ALLOC(p->outK, c.SNB); ALLOC(p->outL, c.SNB);
   ALLOC(p->env, 5 * c.NB); ALLOC(p->Lobs, c.NB);
   ALLOC(p->S2, kMaxSteps); ALLOC(p->T, kMaxSteps);
@@ -844,11 +867,15 @@ ripk_status bind_geometry(ripk_plan_s *p, const ripk_plan_desc *desc, hipStream_
   if (!caps_fit(p->caps, L.caps)) return fail(RIPK_E2BIG, "descriptor exceeds the plan's capacity");
   // (the split layout of the plan's largest sets; packed bins are taken only
   // where they fit as well)
+  const bool inhom = (desc->flags & RIPK_PLAN_INHOM) != 0;
+  const int var = inhom ? 2 : (pair_poly(L.g) ? 1 : 0);
   const int lds = pair_lds_bytes(
       desc->n_s, desc->n_t,
-      desc->n_max >= kWideCountPoints || (desc->flags & RIPK_PLAN_WIDE_COUNTS) ? kBinsSplit64
-                                                                               : kBinsSplit32,
-      (desc->flags & RIPK_PLAN_INHOM) != 0);
+      pair_bins_for_var(var, desc->n_max >= kWideCountPoints ||
+                                     (desc->flags & RIPK_PLAN_WIDE_COUNTS)
+                                 ? kBinsSplit64
+                                 : kBinsSplit32),
+      inhom);
   if ((size_t)lds > p->lds_max)
     return fail(RIPK_EINVAL, "grid of %d bins needs %d B of LDS per workgroup, device has %zu",
                 L.info.n_bins, lds, p->lds_max);
@@ -966,7 +993,7 @@ size_t carve_observed(ripk_plan_s *p, const Caps &c, bool host_points, unsigned 
   Carve k{base};
   p->scal = k.take<unsigned long long>((size_t)(kQueues + 1) * kQueueStride);
   p->binC = k.take<unsigned long long>(c.SNB);
-  p->binW = k.take<unsigned long long>(2 * c.SNB);
+  p->binW = k.take<unsigned long long>(kBinWords * c.SNB);
   for (int b = 0; b < 2; ++b) {
     p->keys[b] = k.take<uint32_t>(c.N);
     p->vals[b] = k.take<uint32_t>(c.N);

@@ -5,8 +5,9 @@
 // s and t and the weights do not depend on the threshold, the sums of Eq. 2 at
 // every grid point are the 2-D inclusive prefix sums of that histogram.  This
 // file forms them (exact integers: counts in u64, weights in 128-bit fixed point
-// with 23 fraction bits, assembled from the pair kernel's two sums of 32-bit
-// halves), then K = A*D*W/N (Eq. 2) and L = sqrt(K/(2 pi t)) - s
+// with 23 fraction bits, or the launch's scale for inhomogeneous K, assembled
+// from the pair kernel's four sums of 32-bit pieces), then K = A*D*W/N (Eq. 2)
+// and L = sqrt(K/(2 pi t)) - s
 // (Eq. 4) in FP64, and the pointwise min/max envelopes over simulations (Sec. 3).
 #include "ripk_internal.h"
 
@@ -21,50 +22,42 @@ __device__ __forceinline__ void add128(unsigned long long &lo, unsigned long lon
   lo = r;
 }
 
-// FP64 sums (inhomogeneous K) sit in the first word of each 128-bit bin
-__device__ __forceinline__ double as_f64(unsigned long long v) {
-  return __longlong_as_double((long long)v);
-}
-__device__ __forceinline__ unsigned long long as_u64(double v) {
-  return (unsigned long long)__double_as_longlong(v);
-}
-
-// One workgroup per set.  binC/binW are cumulated in place.
+// One workgroup per set.  binC/binW are cumulated in place (each bin's first
+// two weight words then hold the 128-bit value, low word first).
 __global__ void k_finalize(unsigned long long *__restrict__ binC,
                            unsigned long long *__restrict__ binW, int n_s, int n_t,
                            double s_max, double t_max, double AD, double N,
                            unsigned long long *__restrict__ C, double *__restrict__ W,
                            double *__restrict__ K, double *__restrict__ L,
                            const unsigned long long *__restrict__ queues,
-                           unsigned long long *__restrict__ scal, int fp) {
+                           unsigned long long *__restrict__ scal,
+                           const unsigned long long *__restrict__ rho_max, int wbudget) {
   const int set = blockIdx.x;
   const int nb = n_s * n_t;
   unsigned long long *c = binC + (size_t)set * nb;
-  unsigned long long *w = binW + (size_t)set * nb * 2;
+  unsigned long long *w = binW + (size_t)set * nb * kBinWords;
+  const int fbits = rho_max ? wide_fbits(*rho_max, wbudget) : kFracBits;
   if (set == 0 && threadIdx.x == 0) {
     unsigned long long ev = 0;
     for (int q = 0; q < kQueues; ++q) ev += queues[q * kQueueStride + 1];
     scal[0] = ev;
   }
-  // prefix along t within each s row (fixed point: lo + hi * 2^32 of the
-  // split sums first, as a 128-bit value)
+  // prefix along t within each s row (fixed point: the sums of 32-bit pieces
+  // first assembled as a 128-bit value, sum_k w_k 2^(32 k) mod 2^128)
   for (int k = threadIdx.x; k < n_s; k += blockDim.x) {
     unsigned long long rc = 0, rlo = 0, rhi = 0;
-    double rf = 0.0;
     for (int l = 0; l < n_t; ++l) {
       int b = k * n_t + l;
       rc += c[b];
       c[b] = rc;
-      if (fp) {
-        rf += as_f64(w[2 * b]);
-        w[2 * b] = as_u64(rf);
-      } else {
-        const unsigned long long s_lo = w[2 * b], s_hi = w[2 * b + 1];
-        add128(rlo, rhi, s_hi << 32, s_hi >> 32);
-        add128(rlo, rhi, s_lo, 0ull);
-        w[2 * b] = rlo;
-        w[2 * b + 1] = rhi;
-      }
+      unsigned long long *wb = w + (size_t)kBinWords * b;
+      const unsigned long long s0 = wb[0], s1 = wb[1], s2 = wb[2], s3 = wb[3];
+      add128(rlo, rhi, s0, 0ull);
+      add128(rlo, rhi, s1 << 32, s1 >> 32);
+      add128(rlo, rhi, 0ull, s2);
+      add128(rlo, rhi, 0ull, s3 << 32);
+      wb[0] = rlo;
+      wb[1] = rhi;
     }
   }
   __threadfence_block();
@@ -72,19 +65,14 @@ __global__ void k_finalize(unsigned long long *__restrict__ binC,
   // prefix along s within each t column
   for (int l = threadIdx.x; l < n_t; l += blockDim.x) {
     unsigned long long rc = 0, rlo = 0, rhi = 0;
-    double rf = 0.0;
     for (int k = 0; k < n_s; ++k) {
       int b = k * n_t + l;
       rc += c[b];
       c[b] = rc;
-      if (fp) {
-        rf += as_f64(w[2 * b]);
-        w[2 * b] = as_u64(rf);
-      } else {
-        add128(rlo, rhi, w[2 * b], w[2 * b + 1]);
-        w[2 * b] = rlo;
-        w[2 * b + 1] = rhi;
-      }
+      unsigned long long *wb = w + (size_t)kBinWords * b;
+      add128(rlo, rhi, wb[0], wb[1]);
+      wb[0] = rlo;
+      wb[1] = rhi;
     }
   }
   __threadfence_block();
@@ -92,10 +80,9 @@ __global__ void k_finalize(unsigned long long *__restrict__ binC,
   const double two_pi = 6.283185307179586476925286766559;
   for (int b = threadIdx.x; b < nb; b += blockDim.x) {
     int k = b / n_t, l = b - k * n_t;
-    // W = (hi * 2^64 + lo) * 2^-23
-    // fixed point: W = (hi * 2^64 + lo) * 2^-23; FP64 bins hold the weight sums as they are
-    double wv = fp ? as_f64(w[2 * b])
-                   : ldexp((double)w[2 * b + 1], 64 - kFracBits) + ldexp((double)w[2 * b], -kFracBits);
+    // fixed point: W = (hi * 2^64 + lo) * 2^-F
+    const unsigned long long *wb = w + (size_t)kBinWords * b;
+    double wv = ldexp((double)wb[1], 64 - fbits) + ldexp((double)wb[0], -fbits);
     double Kv = AD * wv / N;
     double sk = (double)(k + 1) * s_max / (double)n_s;
     double tl = (double)(l + 1) * t_max / (double)n_t;
@@ -152,9 +139,9 @@ hipError_t launch_finalize(unsigned long long *binC, unsigned long long *binW, u
                            int n_s, int n_t, double s_max, double t_max, double AD, double N,
                            unsigned long long *C, double *W, double *K, double *L,
                            const unsigned long long *queues, unsigned long long *scal,
-                           hipStream_t s, bool fp) {
+                           hipStream_t s, const unsigned long long *rho_max, int wbudget) {
   hipLaunchKernelGGL(k_finalize, dim3(n_sets), dim3(256), 0, s, binC, binW, n_s, n_t, s_max,
-                     t_max, AD, N, C, W, K, L, queues, scal, fp ? 1 : 0);
+                     t_max, AD, N, C, W, K, L, queues, scal, rho_max, wbudget);
   return hipGetLastError();
 }
 

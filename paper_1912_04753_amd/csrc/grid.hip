@@ -438,15 +438,28 @@ __global__ void k_bounds_gather(const uint32_t *__restrict__ keys,
 }
 
 // 1/lambda of the sorted records (inhomogeneous K)
+// (lambda must lie in [2^-400, 2^400], so that the fixed-point scale 2^F of
+// the weight sums and every rho_i rho_j 2^F are normal doubles)
 __global__ void k_gather_rho(const uint32_t *__restrict__ vals, uint32_t n,
                              const double *__restrict__ lambda, double *__restrict__ rho,
-                             uint32_t *__restrict__ err) {
-  uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n) return;
-  const double l = lambda[vals[r]];
-  const bool ok = l > 0.0 && l < __builtin_inf();
-  if (!ok) atomicOr(err, 4u);
-  rho[r] = ok ? 1.0 / l : 0.0;
+                             uint32_t *__restrict__ err, unsigned long long *__restrict__ rho_max) {
+  const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  double v = 0.0;
+  if (r < n) {
+    const double l = lambda[vals[r]];
+    const bool ok = l >= 0x1p-400 && l <= 0x1p400;
+    if (!ok) atomicOr(err, 4u);
+    v = ok ? 1.0 / l : 0.0;
+    rho[r] = v;
+  }
+  // positive doubles order as their bit patterns: a wave maximum, then one
+  // atomic per wave
+  unsigned long long m = (unsigned long long)__double_as_longlong(v);
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long y = __shfl_xor(m, o);
+    m = y > m ? y : m;
+  }
+  if ((threadIdx.x & 63) == 0 && m) atomicMax(rho_max, m);
 }
 
 // A unit is the run of cells whose centres a work item may mix: one cell, or a
@@ -718,10 +731,10 @@ hipError_t launch_bounds_gather(const uint32_t *keys, const uint32_t *vals, uint
 }
 
 hipError_t launch_gather_rho(const uint32_t *vals, uint32_t n, const double *lambda, double *rho,
-                             uint32_t *err, hipStream_t s) {
+                             uint32_t *err, unsigned long long *rho_max, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_gather_rho, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, s, vals, n,
-                     lambda, rho, err);
+                     lambda, rho, err, rho_max);
   return hipGetLastError();
 }
 

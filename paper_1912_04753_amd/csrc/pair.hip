@@ -41,7 +41,10 @@
 // unsigned 32-bit values (t_max < 2^30).
 //
 // Weights are FP32: w = 1/omega * 1/v lies in [1, 8], so w * 2^23 is an exact
-// integer and the fixed-point sums are exact and order independent.
+// integer and the fixed-point sums are exact and order independent.  Polygon
+// weights (1/omega has no fixed bound there) and inhomogeneous weights are
+// rounded per side to a fixed-point integer below 2^96 in FP64 and summed as
+// three 32-bit pieces, equally exact and order independent.
 #include "poly.h"
 #include "ripk_internal.h"
 
@@ -61,7 +64,9 @@ constexpr int kWaves = kPairThreads / 64;
 // bins: a 32-bit count stays below 2^31 + 2^31 when a set has fewer than 2^23
 // points (larger sets use 64-bit count words).  Packed bins: a count stays
 // below 2^29 + 2^29 = 2^30 when a set has fewer than 2^21 points, and the
-// interior weight field (at most 4 units of 2^23 per pair) below 2^32.
+// interior weight field (at most 4 units of 2^23 per pair) below 2^32.  Wide
+// bins take the packed bound: with sets below 2^22 points fewer than 2^31
+// pairs are pending per bin, each adding below 2^33 to a piece sum.
 constexpr unsigned long long kFlushEvals = 1ull << 31;
 constexpr unsigned long long kFlushEvalsPacked = 1ull << 29;
 constexpr int kCountShift = 34;
@@ -210,62 +215,82 @@ __device__ __forceinline__ uint32_t qweight(float om, uint32_t half) {
   return (uint32_t)(w * (float)(1u << kFracBits)) << half;
 }
 
-// Polygon weight: 1/omega capped at 64 (omega from FP64 angles), rounded to the
-// fixed-point grid: below 2^29 per side, so two sides fit 32 bits.
-__device__ __forceinline__ uint32_t qweight_poly(double om, uint32_t half) {
-  const double w = om * 64.0 > 1.0 ? poly_div(1.0, om) : 64.0;
-  return (uint32_t)rint(w * (double)(1u << kFracBits)) << half;
+// Wide weights: x, a non-negative integer below 2^96 held exactly in a double,
+// added to the sums p0, p1, p2 of its three 32-bit pieces (the differences
+// below are exact, so is each piece).
+struct Pieces {
+  unsigned long long p0 = 0, p1 = 0, p2 = 0;
+  __device__ __forceinline__ void add(double x) {
+    const double hi = floor(x * 0x1p-64);
+    const double r1 = fma(hi, -0x1p64, x);
+    const double mid = floor(r1 * 0x1p-32);
+    const double r0 = fma(mid, -0x1p32, r1);
+    p0 += (uint32_t)r0;
+    p1 += (uint32_t)mid;
+    p2 += (uint32_t)hi;
+  }
+  // into the bin's three LDS words (pieces that are zero cost no atomic)
+  __device__ __forceinline__ void commit(unsigned long long *w3) const {
+    if (p0) atomicAdd(&w3[0], p0);
+    if (p1) atomicAdd(&w3[1], p1);
+    if (p2) atomicAdd(&w3[2], p2);
+  }
+};
+
+// Polygon weight of one side: 1/omega (omega from FP64 angles) times 2^(23 +
+// half), rounded to an integer.  A neighbour j lies strictly inside the polygon
+// and on the circle, at least 1/|E| from every edge line on the integer
+// lattice (|E| < 2^24.5), so omega >= 1/(pi |E| s_max) and the value stays
+// below 2^75.
+__device__ __forceinline__ double qweight_poly(double om, uint32_t half) {
+  return rint(poly_div(1.0, om) * (double)(1u << (kFracBits + half)));
 }
 
 // Polygon records (every distance mode): {bin | half_i<<12 | half_j<<13 |
 // slow_i<<14 | slow_j<<15 | d2 hi<<16, d2 lo, i, j} with i, j the sorted-record
-// indices of the two points.
-// INHOM: the same records as POLY; the rectangle's weight times
-// 1/(lambda_i lambda_j) = rho_i rho_j, added to FP64 bins.
+// indices of the two points; each side's weight goes to the bin's three wide
+// words hw[3 bin ..] (see Pieces).
+// INHOM: the same records as POLY; per side the rectangle's weight w times
+// 1/(lambda_i lambda_j) = rho_i rho_j, scaled by 2^F (wscale) and 2^half and
+// rounded: round(((w rho_i rho_j) 2^F) 2^half), which is the interior path's
+// value when w = 1.
 template <int MODE, bool POLY, bool INHOM>
 __device__ __forceinline__ void drain_b(WaveLds &W, QState &q, uint32_t c, int lane,
                                         unsigned long long *hw, const Geom &g,
                                         const int4 *__restrict__ P,
-                                        const double *__restrict__ rho) {
+                                        const double *__restrict__ rho, double wscale) {
   wave_sync();
   const uint4 r = W.qb[(q.hb + lane) & (kQB - 1)];
   wave_sync();
   const uint32_t bin = r.x & 0xFFFu;
-  uint32_t qv;
-  if (INHOM) {
+  if (POLY || INHOM) {
     const uint64_t d2 = (uint64_t)r.y | ((uint64_t)(r.x >> 16) << 32);
     if ((uint32_t)lane < c) {
-      double wsum = 0.0;
+      Pieces pc;
+      const double rr = INHOM ? rho[r.z] * rho[r.w] : 0.0;
 #pragma unroll 1
       for (uint32_t side = 0; side < 2; ++side) {
         if ((r.x >> (14 + side)) & 1u) {
           const int4 p = P[side ? r.w : r.z];
-          const uint32_t ex = (uint32_t)min(p.x, g.x1 - g.x0 - p.x);
-          const uint32_t ey = (uint32_t)min(p.y, g.y1 - g.y0 - p.y);
-          const float w = fmaxf(__builtin_amdgcn_rcpf(omega_f32(ex, ey, d2)), 1.0f);
-          wsum += (double)w * (double)(1u << ((r.x >> (12 + side)) & 1u));
+          const uint32_t half = (r.x >> (12 + side)) & 1u;
+          if (POLY) {
+            pc.add(qweight_poly(poly_omega(g, p.x, p.y, d2), half));
+          } else {
+            const uint32_t ex = (uint32_t)min(p.x, g.x1 - g.x0 - p.x);
+            const uint32_t ey = (uint32_t)min(p.y, g.y1 - g.y0 - p.y);
+            const float w = fmaxf(__builtin_amdgcn_rcpf(omega_f32(ex, ey, d2)), 1.0f);
+            pc.add(rint((((double)w * rr) * wscale) * (double)(1u << half)));
+          }
         }
       }
-      atomicAdd((double *)&hw[bin], wsum * (rho[r.z] * rho[r.w]));
+      pc.commit(hw + 3 * bin);
     }
     q.hb = (q.hb + c) & (kQB - 1);
     q.nb -= c;
     return;
   }
-  if (POLY) {
-    const uint64_t d2 = (uint64_t)r.y | ((uint64_t)(r.x >> 16) << 32);
-    qv = 0;
-    if ((uint32_t)lane < c) {
-      if ((r.x >> 14) & 1u) {
-        const int4 pi = P[r.z];
-        qv += qweight_poly(poly_omega(g, pi.x, pi.y, d2), (r.x >> 12) & 1u);
-      }
-      if ((r.x >> 15) & 1u) {
-        const int4 pj = P[r.w];
-        qv += qweight_poly(poly_omega(g, pj.x, pj.y, d2), (r.x >> 13) & 1u);
-      }
-    }
-  } else if (MODE == kModePacked) {
+  uint32_t qv;
+  if (MODE == kModePacked) {
     // d2 < 2^31 and side distances < 2^15: 32-bit arithmetic throughout
     const float oi = omega_f32(r.z & 0xFFFFu, r.z >> 16, r.y);
     const float oj = omega_f32(r.w & 0xFFFFu, r.w >> 16, r.y);
@@ -322,9 +347,11 @@ __device__ __forceinline__ void drain_a(WaveLds &W, QState &q,
                                         const uint32_t *S2hi, const uint32_t *T,
                                         uint32_t begin, uint32_t tb, const int4 *P,
                                         const double *rho, const double *rho_c,
-                                        const double *rho_t) {
-  // boundary weights: their own words with packed bins, else the weight words
-  unsigned long long *hw = (!INHOM && bins == kBinsPacked) ? (unsigned long long *)aux : hist;
+                                        const double *rho_t, double wscale) {
+  // boundary weights: their own words with packed or wide bins, else the
+  // weight words
+  unsigned long long *hw =
+      (POLY || INHOM || bins == kBinsPacked) ? (unsigned long long *)aux : hist;
   wave_sync();
   const uint32_t tag0 = W.qa[q.ha + (uint32_t)lane];  // q.ha + 63 < kQA: no wrap
   wave_sync();
@@ -394,19 +421,30 @@ __device__ __forceinline__ void drain_a(WaveLds &W, QState &q,
       (__builtin_amdgcn_ballot_w64(si.slow) | (SYM ? __builtin_amdgcn_ballot_w64(sj.slow) : 0ull)) & vmask;
   // packed bins: the count and the interior weights in one atomic; split
   // bins: weights hist[bin], counts in the aux array (32-bit words unless the
-  // set is large)
-  if (INHOM) {
-    // fast-path sides in units of 2^23 times rho_i rho_j (FP64 bins)
-    const uint32_t ci = v ? ((tag & 0xFFFFu) - kCenOff) >> 2 : 0u;
-    const uint32_t tj = v ? ((tag >> 16) - kTileOff) >> 2 : 0u;
-    const double rr = rho_c[ci] * rho_t[tj];
-    if (v) atomicAdd((double *)&hist[bin], (double)(qsum >> kFracBits) * rr);
-  }
-  if (v) {
-    if (!INHOM && bins == kBinsPacked) {
+  // set is large); wide bins (POLY, INHOM): counts hist[bin], weights in the
+  // three words aux[3 bin ..]
+  if (POLY || INHOM) {
+    if (v) {
+      atomicAdd(&hist[bin], 1ull);
+      unsigned long long *w3 = (unsigned long long *)aux + 3 * bin;
+      if (INHOM) {
+        // interior sides: round((rho_i rho_j 2^F) 2^half) each
+        const uint32_t ci = ((tag & 0xFFFFu) - kCenOff) >> 2;
+        const uint32_t tj = ((tag >> 16) - kTileOff) >> 2;
+        const double r = (rho_c[ci] * rho_t[tj]) * wscale;
+        Pieces pc;
+        if (!si.slow) pc.add(rint(r * (double)(1u << hfi)));
+        if (SYM && !sj.slow) pc.add(rint(r * (double)(1u << hfj)));
+        pc.commit(w3);
+      } else if (qsum) {
+        atomicAdd(w3, (unsigned long long)qsum);
+      }
+    }
+  } else if (v) {
+    if (bins == kBinsPacked) {
       atomicAdd(&hist[bin], (1ull << kCountShift) | (unsigned long long)(qsum >> kFracBits));
     } else {
-      if (!INHOM) atomicAdd(&hist[bin], (unsigned long long)qsum);
+      atomicAdd(&hist[bin], (unsigned long long)qsum);
       if (bins == kBinsSplit64)
         atomicAdd((unsigned long long *)aux + bin, 1ull);
       else
@@ -432,7 +470,7 @@ __device__ __forceinline__ void drain_a(WaveLds &W, QState &q,
                                    ((uint32_t)(SYM && sj.slow) << 15) | (d2hi << 16),
                                d2lo, begin + (((tag & 0xFFFFu) - kCenOff) >> 2),
                                tb + (((tag >> 16) - kTileOff) >> 2));
-      if (q.nb >= 64) drain_b<MODE, POLY, INHOM>(W, q, 64, lane, hw, g, P, rho);
+      if (q.nb >= 64) drain_b<MODE, POLY, INHOM>(W, q, 64, lane, hw, g, P, rho, wscale);
     }
   } else if (MODE == kModePacked) {
     // one record per pair with a boundary side
@@ -445,7 +483,7 @@ __device__ __forceinline__ void drain_a(WaveLds &W, QState &q,
         W.qb[pos] = make_uint4(bin | (hfi << 12) | (hfj << 13) | ((uint32_t)si.slow << 14) |
                                    ((uint32_t)(SYM && sj.slow) << 15),
                                d2lo, (uint32_t)pi.z, (uint32_t)pj.z);
-      if (q.nb >= 64) drain_b<MODE, POLY, INHOM>(W, q, 64, lane, hw, g, P, rho);
+      if (q.nb >= 64) drain_b<MODE, POLY, INHOM>(W, q, 64, lane, hw, g, P, rho, wscale);
     }
   } else {
     // one record per boundary side, one side per pass through a single drain site
@@ -460,7 +498,7 @@ __device__ __forceinline__ void drain_a(WaveLds &W, QState &q,
         if (need && v)
           W.qb[pos] = make_uint4(w0 | ((side ? hfj : hfi) << 12), d2lo, side ? sj.ex : si.ex,
                                  side ? sj.ey : si.ey);
-        if (q.nb >= 64) drain_b<MODE, POLY, INHOM>(W, q, 64, lane, hw, g, P, rho);
+        if (q.nb >= 64) drain_b<MODE, POLY, INHOM>(W, q, 64, lane, hw, g, P, rho, wscale);
       }
     }
   }
@@ -519,8 +557,9 @@ struct Ctx {
   WaveLds &W;
   QState &q;
   const Geom &g;
-  unsigned long long *hist;  // packed count and weight, or the weight, per bin
-  void *aux;                 // boundary weights (packed) or pair counts (split)
+  unsigned long long *hist;  // packed count and weight, the weight, or the count per bin
+  void *aux;                 // boundary weights (packed), pair counts (split) or the
+                             // three piece sums of the weights (wide)
   int bins;                  // bin layout
   const uint32_t *S2lo, *S2hi, *T;
   int lane;
@@ -529,13 +568,14 @@ struct Ctx {
   const int4 *P;   // sorted records
   const double *rho;            // INHOM: 1/lambda per sorted record
   double *rho_c, *rho_t;        // INHOM: rho of the wave's centres and tile (LDS)
+  double wscale;                // INHOM: 2^F of the fixed-point weights
 };
 
 template <bool SYM, int MODE, bool POLY, bool INHOM>
 __device__ __forceinline__ void drain_oldest(Ctx<SYM, MODE, POLY, INHOM> &x, uint32_t c) {
   drain_a<SYM, MODE, POLY, INHOM>(x.W, x.q, c, x.lane, x.g, x.hist, x.aux, x.bins,
                                   x.S2lo, x.S2hi, x.T, x.begin, x.tb, x.P, x.rho, x.rho_c,
-                                  x.rho_t);
+                                  x.rho_t, x.wscale);
 }
 
 // One run of consecutive sorted points [j0, j1) against the wave's centres.
@@ -647,12 +687,14 @@ k_pair(PairArgs a) {
   // words (boundary weights or pair counts, see kBinsPacked), the threshold
   // tables (n_s, n_s and n_t words, each padded to 16 bytes) and two scalars
   // (layout in pair_lds_bytes)
-  const int bins = INHOM && a.bins == kBinsPacked ? kBinsSplit32 : a.bins;
-  const bool packed = !INHOM && bins == kBinsPacked;
+  constexpr bool WIDE = POLY || INHOM;  // the host passes kBinsWide for these
+  const int bins = WIDE ? kBinsWide : a.bins;
+  const bool packed = bins == kBinsPacked;
   WaveLds *wl = (WaveLds *)smem;
   unsigned long long *hist = (unsigned long long *)(wl + kWaves);
   void *aux = (void *)(hist + NB);
-  const int aux_words = bins == kBinsSplit32 ? ((NB + 3) & ~3) : 2 * NB;  // 32-bit words
+  const int aux_words = WIDE ? 6 * NB
+                             : bins == kBinsSplit32 ? ((NB + 3) & ~3) : 2 * NB;  // 32-bit words
   uint32_t *S2lo = (uint32_t *)aux + aux_words;
   uint32_t *S2hi = S2lo + ((g.n_s + 3) & ~3);
   uint32_t *T = S2hi + ((g.n_s + 3) & ~3);
@@ -673,16 +715,21 @@ k_pair(PairArgs a) {
   if (tid < g.n_t) T[tid] = a.T[tid];
   if (tid == 0) *evals_lds = 0;
   const uint32_t n_items = *a.n_items;
+  // 2^F of the inhomogeneous fixed-point weights (the same F in k_finalize)
+  const double wscale = INHOM ? ldexp(1.0, wide_fbits(*a.rho_max, a.wbudget)) : 0.0;
   int cur_set = -1;
   unsigned long long evals_total = 0;
 
-  // (no atomic here returns a value: the 64-bit weight sum goes out as its
-  // two 32-bit halves, added to two 64-bit sums)
+  // (no atomic here returns a value: each weight sum goes out as 32-bit
+  // pieces, word k of the global bin summing the pieces of weight 2^(32 k))
   auto flush = [&](int set) {
+    constexpr unsigned long long M = 0xFFFFFFFFull;
     for (int b = tid; b < NB; b += kPairThreads) {
       const unsigned long long hb = hist[b];
-      unsigned long long c, w;
-      if (packed) {
+      unsigned long long c, w = 0;
+      if (WIDE) {
+        c = hb;
+      } else if (packed) {
         // interior units of 2^23 plus the boundary weights: below 2^55 + 2^57
         c = hb >> kCountShift;
         w = ((hb & kUnitMask) << kFracBits) + ((unsigned long long *)aux)[b];
@@ -694,18 +741,28 @@ k_pair(PairArgs a) {
       c *= SYM ? 2ull : 1ull;
       if (c) {
         const size_t o = (size_t)set * NB + b;
+        unsigned long long *gw = a.binW + (size_t)kBinWords * o;
         atomicAdd(&a.binC[o], c);
-        if (INHOM) {
-          atomicAdd((double *)&a.binW[2 * o], __longlong_as_double((long long)w));
-        } else {
-          atomicAdd(&a.binW[2 * o], w & 0xFFFFFFFFull);
-          if (w >> 32) atomicAdd(&a.binW[2 * o + 1], w >> 32);
-        }
         hist[b] = 0;
-        if (bins == kBinsSplit32)
-          ((uint32_t *)aux)[b] = 0;
-        else
-          ((unsigned long long *)aux)[b] = 0;
+        if (WIDE) {
+          // three sums of 32-bit pieces (each below 2^64) -> four words
+          unsigned long long *w3 = (unsigned long long *)aux + 3 * b;
+          const unsigned long long A = w3[0], B = w3[1], C = w3[2];
+          if (A & M) atomicAdd(&gw[0], A & M);
+          if ((A >> 32) + (B & M)) atomicAdd(&gw[1], (A >> 32) + (B & M));
+          if ((B >> 32) + (C & M)) atomicAdd(&gw[2], (B >> 32) + (C & M));
+          if (C >> 32) atomicAdd(&gw[3], C >> 32);
+          w3[0] = 0;
+          w3[1] = 0;
+          w3[2] = 0;
+        } else {
+          atomicAdd(&gw[0], w & M);
+          if (w >> 32) atomicAdd(&gw[1], w >> 32);
+          if (bins == kBinsSplit32)
+            ((uint32_t *)aux)[b] = 0;
+          else
+            ((unsigned long long *)aux)[b] = 0;
+        }
       }
     }
   };
@@ -744,7 +801,7 @@ k_pair(PairArgs a) {
     const uint32_t base = grp * kItemsPerGroup;
     const int set = (int)uni(a.items[base].set);
     const unsigned long long pend = *evals_lds;
-    if (set != cur_set || pend > (packed ? kFlushEvalsPacked : kFlushEvals)) {
+    if (set != cur_set || pend > ((packed || WIDE) ? kFlushEvalsPacked : kFlushEvals)) {
       if (cur_set >= 0) flush(cur_set);
       cur_set = set;
       __syncthreads();
@@ -797,8 +854,8 @@ k_pair(PairArgs a) {
     const uint32_t cst = blocked ? 1u : 2u;
     const uint32_t nb_off = blocked ? (2u * (uint32_t)set + 1u) * g.n_cells : (uint32_t)set * g.n_cells;
     QState q = {0u, 0u, 0u, 0u};
-    Ctx<SYM, MODE, POLY, INHOM> x{W,     q,     g,    hist, aux,    bins,  S2lo,  S2hi, T,
-                                  lane,  begin, 0u,   a.P,  a.rho,  rho_c, rho_t};
+    Ctx<SYM, MODE, POLY, INHOM> x{W,    q,     g,   hist,  aux,   bins,  S2lo,  S2hi, T,
+                                  lane, begin, 0u,  a.P,   a.rho, rho_c, rho_t, wscale};
     unsigned long long ev = 0;
     int ridx = 0;  // index of the stencil row in visiting order
     for (int dt = SYM ? 0 : -g.rt; dt <= g.rt; ++dt) {
@@ -864,8 +921,9 @@ k_pair(PairArgs a) {
       if (na) drain_oldest(x, na);
     }
     if (q.nb)
-      drain_b<MODE, POLY, INHOM>(W, q, q.nb, lane, packed ? (unsigned long long *)aux : hist, g,
-                                 a.P, a.rho);
+      drain_b<MODE, POLY, INHOM>(W, q, q.nb, lane,
+                                 (WIDE || packed) ? (unsigned long long *)aux : hist, g, a.P,
+                                 a.rho, wscale);
     if (lane == 0) atomicAdd(evals_lds, ev);
     evals_total += ev;
   }
@@ -919,8 +977,9 @@ hipError_t launch_var(int var, const PairArgs &a, int grid, hipStream_t s) {
 
 int pair_lds_bytes(int n_s, int n_t, int bins, bool inhom) {
   const int n_bins = n_s * n_t;
-  if (inhom && bins == kBinsPacked) bins = kBinsSplit32;
-  const int aux_words = bins == kBinsSplit32 ? ((n_bins + 3) & ~3) : 2 * n_bins;
+  const int aux_words = bins == kBinsWide      ? 6 * n_bins
+                        : bins == kBinsSplit32 ? ((n_bins + 3) & ~3)
+                                               : 2 * n_bins;
   const int tables = 2 * ((n_s + 3) & ~3) + ((n_t + 3) & ~3);
   return (int)sizeof(WaveLds) * kWaves + 8 * n_bins + 4 * aux_words + 4 * tables + 16 +
          (inhom ? 2 * kWaves * 64 * 8 : 0);

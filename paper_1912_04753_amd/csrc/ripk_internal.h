@@ -85,18 +85,44 @@ struct PairArgs {
   const uint64_t *S2;       // n_s thresholds (device)
   const uint32_t *T;        // n_t thresholds (device)
   unsigned long long *binC;  // [sets][n_bins] counts
-  // [sets][n_bins][2] fixed-point weight sums, split so that no flush needs
-  // the old value: the sums of the low and of the high 32-bit halves of the
-  // workgroups' 64-bit partial sums (the weight is word0 + word1 * 2^32); FP64
-  // sums in word 0 for inhomogeneous K
+  // [sets][n_bins][kBinWords] fixed-point weight sums, split so that no flush
+  // needs the old value: word k sums the k-th 32-bit pieces of the
+  // workgroups' partial sums (each addend below 2^34), and the weight is
+  // sum_k word_k * 2^(32 k) mod 2^128 times 2^-F (F = kFracBits, or the
+  // launch's scale for inhomogeneous K)
   unsigned long long *binW;
   int symmetric;
   int row_items;               // items are chunks of x-rows (else of cells)
   int blocked;                 // two-type sets in blocked key order: centres from the
                                // type-1 block, neighbours from the type-2 block
   const double *rho;           // inhomogeneous K: 1/lambda per sorted record (else null)
-  int bins;                    // LDS bin layout (kBinsPacked, kBinsSplit32, kBinsSplit64)
+  // inhomogeneous K: bit pattern of the largest rho of the launch (device
+  // word) and the bit budget of one pair's fixed-point weight (see wide_fbits)
+  const unsigned long long *rho_max;
+  int wbudget;
+  int bins;                    // LDS bin layout (kBinsPacked, kBinsSplit32, kBinsSplit64,
+                               // kBinsWide)
 };
+
+// Words per bin of the global weight sums (see PairArgs::binW).
+constexpr int kBinWords = 4;
+
+// Fraction bits of the fixed-point weight of an inhomogeneous launch: with
+// rho_max < 2^e (frexp exponent) one ordered pair weighs at most
+// 8 rho_max^2 (omega >= 1/4, v >= 1/2) and a symmetric pair twice that, so
+// 2^F times it stays below 2^budget.  The host sets budget so that one pair
+// fits three 32-bit pieces and the sum over n(n-1) ordered pairs fits 128
+// bits.
+__host__ __device__ inline int wide_fbits(unsigned long long rho_max_bits, int budget) {
+  union {
+    unsigned long long u;
+    double d;
+  } v;
+  v.u = rho_max_bits;
+  int e = 0;
+  (void)frexp(v.d, &e);
+  return budget - 4 - 2 * e;
+}
 
 // ---- host runtime (api.cpp) -------------------------------------------------
 
@@ -174,10 +200,12 @@ hipError_t launch_bounds_gather(const uint32_t *keys, const uint32_t *vals, uint
                                 uint32_t n_keys, uint32_t *cs, const int32_t *x, const int32_t *y,
                                 const int32_t *t, const Geom &g, int32_t clamp_e, int4 *P,
                                 hipStream_t s);
-// rho[r] = 1 / lambda[vals[r]] for the sorted records; a value that is not
-// positive and finite sets bit 2 of *err
+// rho[r] = 1 / lambda[vals[r]] for the sorted records, and the largest rho
+// as its bit pattern in *rho_max (zeroed before; positive doubles order as
+// their bit patterns); a value that is not positive and finite sets bit 2 of
+// *err
 hipError_t launch_gather_rho(const uint32_t *vals, uint32_t n, const double *lambda, double *rho,
-                             uint32_t *err, hipStream_t s);
+                             uint32_t *err, unsigned long long *rho_max, hipStream_t s);
 hipError_t launch_items(const uint32_t *cs, uint32_t n_sets, const Geom &g, bool row_items,
                         bool blocked, uint32_t split, uint32_t n_rows, uint32_t *chunks,
                         uint32_t *offs, uint32_t *set_base, Item *items, uint32_t *n_items,
@@ -195,9 +223,17 @@ hipError_t launch_pair(const PairArgs &a, int grid, hipStream_t s);
 // word.  Split: a fixed-point weight word and a 32- or 64-bit count word.
 // Packed needs fewer than 2^30 pending pairs per bin (sets below 2^21 points,
 // flushes every 2^29 candidates); 32-bit counts need sets below 2^23 points.
-constexpr int kBinsPacked = 0, kBinsSplit32 = 1, kBinsSplit64 = 2;
+// Wide (polygon weights, whose 1/omega has no fixed bound, and inhomogeneous
+// K): a 64-bit count word and three words summing the 32-bit pieces of each
+// side's fixed-point weight (below 2^96); the sums stay below 2^63 while
+// fewer than 2^31 pairs are pending per bin: sets below 2^22 points (one
+// group examines fewer than 256 n candidates), flushes every 2^29 candidates.
+constexpr int kBinsPacked = 0, kBinsSplit32 = 1, kBinsSplit64 = 2, kBinsWide = 3;
 constexpr int64_t kPackedPoints = 1 << 21;
+constexpr int64_t kWidePoints = 1 << 22;
 int pair_lds_bytes(int n_s, int n_t, int bins, bool inhom = false);
+// the bin layout of polygon-weight and inhomogeneous launches
+inline int pair_bins_for_var(int var, int bins) { return var ? kBinsWide : bins; }
 // the pair kernel takes the polygon weight path (a polygon and spatial correction)
 bool pair_poly(const Geom &g);
 // kernel variant: 0 rectangle, 1 polygon, 2 inhomogeneous (rectangle)
@@ -205,14 +241,16 @@ hipError_t pair_occupancy(int n_s, int n_t, int bins, int symmetric, int mode, i
                           int *per_cu);
 // 64-bit LDS pair counts are needed from this many points per set on
 constexpr int64_t kWideCountPoints = 1 << 23;
-// fp: the weight bins hold FP64 sums (inhomogeneous K) instead of split
-// fixed point.  scal[0] receives the candidates summed over the work-queue
-// partitions `queues`, scal[1] the in-range pairs over all sets.
+// The weight sums have kFracBits fraction bits, or with rho_max (inhomogeneous
+// K) wide_fbits(*rho_max, wbudget).  scal[0] receives the candidates summed
+// over the work-queue partitions `queues`, scal[1] the in-range pairs over
+// all sets.
 hipError_t launch_finalize(unsigned long long *binC, unsigned long long *binW,
                            uint32_t n_sets, int n_s, int n_t, double s_max, double t_max,
                            double AD, double N, unsigned long long *C, double *W, double *K,
                            double *L, const unsigned long long *queues,
-                           unsigned long long *scal, hipStream_t s, bool fp = false);
+                           unsigned long long *scal, hipStream_t s,
+                           const unsigned long long *rho_max = nullptr, int wbudget = 0);
 hipError_t launch_envelope(const double *K, const double *L, uint32_t m, int n_bins,
                            const double *L_obs, double *env, hipStream_t s);
 // Results of a call brought to the host in one copy: kScalWords words of

@@ -2,7 +2,9 @@
 
 Each pair weighs 1/(omega v lambda_i lambda_j) and K_I = W/(A*D).  Counts bit for
 bit; W, K and L within the tolerances of ``tests/parity.py`` (the FP32 weights
-times FP64 reciprocal intensities, summed in FP64 on the device).
+times FP64 reciprocal intensities, each side rounded to a fixed-point integer
+on a per-launch scale and summed exactly, so that runs, launch shapes and
+symmetric or ordered evaluation agree bit for bit).
 """
 import numpy as np
 import pytest
@@ -79,13 +81,13 @@ def test_inhom_k_matches_oracle(name):
     compare(g, r, s_max, t_max, n_s, n_t, where="inhom " + name)
     if name == "u32_device":
         assert g["info"]["dist_mode"] == 1
-    assert g["stats"]["bin_layout"] == 1  # FP64 weights: weight + count words
+    assert g["stats"]["bin_layout"] == 3  # wide fixed-point weight words
 
 
 def test_inhom_constant_intensity_is_the_n2_estimate_at_full_size():
     """The 100k workload with lambda = n/(A*D): the inhomogeneous plan equals the
     homogeneous plan with N = n^2 (counts exactly, K to FP64 rounding); two runs
-    agree on counts and to rounding on K."""
+    agree bit for bit."""
     c = workloads.workload("uniform-100k-99csr")
     x, y, t = workloads.make_points(c)
     n = len(x)
@@ -101,7 +103,30 @@ def test_inhom_constant_intensity_is_the_n2_estimate_at_full_size():
         plan.destroy()
     assert np.array_equal(g["C"], h["C"]) and np.array_equal(g2["C"], g["C"])
     np.testing.assert_allclose(g["K"], h["K"], rtol=1e-12, atol=0)
-    np.testing.assert_allclose(g2["K"], g["K"], rtol=1e-12, atol=0)
+    for k in ("W", "K", "L"):
+        assert np.array_equal(g2[k], g[k]), k
+
+
+def test_inhom_deterministic_across_runs_and_modes():
+    """A clustered set with a smooth intensity (weights spread over two orders
+    of magnitude): W, K and L bit-identical over repeated runs, symmetric and
+    ordered evaluation, fixed and autotuned cells and host or device inputs;
+    and within the parity tolerance of the oracle."""
+    win = (0, 0, 20_000, 15_000, 0, 200 * DAY)
+    x, y, t = _points("determinism", 20_000, win, True)
+    lam = _density_lambda(x, y, t, win, 2_000)
+    args = (win, 2_000, 20 * DAY, 16, 12)
+    say("inhom determinism")
+    runs = [_gpu(args, x, y, t, lam), _gpu(args, x, y, t, lam),
+            _gpu(args, x, y, t, lam, flags=ripk.RIPK_PLAN_ORDERED),
+            _gpu(args, x, y, t, lam, flags=ripk.RIPK_PLAN_AUTOTUNE),
+            _gpu(args, x, y, t, lam, dev=True)]
+    assert runs[2]["stats"]["symmetric"] == 0 and runs[0]["stats"]["symmetric"] == 1
+    for r in runs[1:]:
+        for k in ("C", "W", "K", "L"):
+            assert np.array_equal(r[k], runs[0][k]), k
+    ref = oracle.estimate_inhom(oracle.desc(*args), x, y, t, lam)
+    compare(runs[0], ref, *args[1:], where="inhom determinism")
 
 
 def test_inhom_errors():
@@ -114,7 +139,7 @@ def test_inhom_errors():
         with pytest.raises(ripk.RipkError) as e:
             ripk.ripk_compute_K(plan, x, y, t)                   # no intensities
         assert e.value.status == ripk.RIPK_EINVAL
-        for bad in (0.0, -1e-9, np.nan, np.inf):
+        for bad in (0.0, -1e-9, np.nan, np.inf, 1e-200, 1e200):
             b = lam.copy()
             b[17] = bad
             with pytest.raises(ripk.RipkError) as e:

@@ -252,3 +252,50 @@ def test_polygon_many_crossings_against_oracle():
     compare(g, r, *args[1:], where="polygon comb")
     go = _gpu(args, poly, x, y, t, flags=ripk.RIPK_PLAN_ORDERED)
     assert np.array_equal(go["C"], g["C"]) and np.array_equal(go["W"], g["W"])
+
+
+@pytest.mark.parametrize("width", [100, 10])
+@pytest.mark.parametrize("ordered", [False, True])
+def test_polygon_spike_weights_beyond_64(width, ordered):
+    """A thin arm of an L-shaped area (y in [0, width], x in [1000, 4000]):
+    centres near the arm's tip see a small share of their circles inside,
+    1/omega = 87 (width 100) or 873 (width 10) for the pair (3990, w/2) -
+    (2600, w/2) (closed form in the oracle's pins), and more for others.  The
+    weight has no cap (Sec. 3): parity with the oracle, and the wide weight
+    words the polygon path sums them in."""
+    spike = [(0, 0), (4000, 0), (4000, width), (1000, width), (1000, 4000), (0, 4000)]
+    win = (0, 0, 4000, 4000, 0, 200 * DAY)
+    rng = np.random.default_rng(70 + width)
+    n_arm, n_body = 600, 900
+    xa = rng.integers(1001, 4000, n_arm)
+    ya = rng.integers(1, width, n_arm)
+    xb = rng.integers(1, 1000, n_body)
+    yb = rng.integers(1, 4000, n_body)
+    x = np.concatenate([[3990, 2600], xa, xb]).astype(np.int32)
+    y = np.concatenate([[width // 2, width // 2], ya, yb]).astype(np.int32)
+    t = rng.integers(0, 200 * DAY, len(x)).astype(np.int32)
+    t[:2] = 100 * DAY
+    args = (win, 1500, 20 * DAY, 15, 4)
+    d = oracle.desc(*args, poly=spike)
+    assert 1.0 / oracle.omega(3990, width // 2, 1390 ** 2, d) > 64
+    say("polygon spike", width, "ordered" if ordered else "symmetric")
+    g = _gpu(args, spike, x, y, t, flags=ripk.RIPK_PLAN_ORDERED if ordered else 0)
+    r = oracle.estimate(d, x, y, t)
+    compare(g, r, args[1], args[2], args[3], args[4], where="spike %d" % width)
+    assert g["stats"]["bin_layout"] == 3
+    # the heavy pairs carry a large share of the sums
+    Hc, Hw = oracle.hist(d, x, y, t)
+    assert Hw.sum() > 5.0 * Hc.sum()
+
+
+def test_polygon_plan_size_limit():
+    """Polygon weights are summed in wide fixed point, bounded for sets below
+    2^22 points: larger polygon plans with spatial correction are EINVAL, and
+    without spatial correction (rectangle kernel) they are accepted."""
+    win = (0, 0, 2000, 2000, 0, 1000)
+    args = (win, 600, 100, 3, 2)
+    with pytest.raises(ripk.RipkError) as e:
+        ripk.ripk_plan_check(ripk.make_desc(*args, n_max=1 << 22, poly=L_SHAPE))
+    assert e.value.status == ripk.RIPK_EINVAL
+    ripk.ripk_plan_check(ripk.make_desc(*args, n_max=(1 << 22) - 1, poly=L_SHAPE))
+    ripk.ripk_plan_check(ripk.make_desc(*args, n_max=1 << 22, poly=L_SHAPE, edge=2))
