@@ -346,6 +346,18 @@ ripk_status ripk_plan_stats(ripk_plan_t plan, ripk_stats *out);
  * tuned cells). */
 ripk_status ripk_plan_get_info(ripk_plan_t plan, ripk_plan_info *out);
 
+/* Test hook for the pair kernel's histogram flush (the merge of each
+ * workgroup's LDS bins into a set's global bins).  A workgroup flushes when
+ * it moves on to another point set and, within a set, once it has examined
+ * more candidate pairs than a bound (checked before each group of work
+ * items): 2^29 or 2^31 by default, set by the fields of the LDS bins.  This
+ * call lowers that bound to `candidates` for the plan's later calls (0, or
+ * 2^29 and more, select the default), so that small
+ * sets run the mid-set flush that only sets of millions of points reach
+ * otherwise.  Results do not depend on it.  RIPK_EINVAL for a null plan or a
+ * negative bound. */
+ripk_status ripk_plan_set_flush_bound(ripk_plan_t plan, int64_t candidates);
+
 /* ---- Serving ---------------------------------------------------------------
  *
  * A server evaluates requests -- an observed set's K and L and, when m > 0, its

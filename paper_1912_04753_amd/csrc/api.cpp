@@ -412,6 +412,7 @@ struct ripk_plan_s {
   Layout lay;
   int32_t bound_cd = 1, bound_td = 1;  // cell subdivisions of the bound geometry
   bool split_runs = false;             // run fractions for this call's launch
+  uint64_t flush_evals = 0;            // ripk_plan_set_flush_bound (0: default)
   uint64_t bind_gen = 0;               // bumped whenever a geometry is bound
   // RIPK_PLAN_GRAPH: the captured launch sequence of the last call shape
   hipGraphExec_t gexec = nullptr;
@@ -626,6 +627,7 @@ ripk_status enqueue_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_cent
   a.rho_max = inhom ? rho_max : nullptr;
   a.wbudget = inhom ? wide_budget(n) : 0;
   a.bins = bins;
+  a.flush_evals = p->flush_evals;
   const int64_t groups_cap = items_bound * split / kItemsPerGroup + 1;
   const int grid = (int)std::min<int64_t>(slots, groups_cap);
   HIPCHK(launch_pair(a, grid, st));
@@ -1368,6 +1370,15 @@ ripk_status ripk_plan_get_info(ripk_plan_t p, ripk_plan_info *out) {
 ripk_status ripk_plan_stats(ripk_plan_t p, ripk_stats *out) {
   if (!p || !out) return fail(RIPK_EINVAL, "null plan or output");
   *out = p->stats;
+  return RIPK_OK;
+}
+
+ripk_status ripk_plan_set_flush_bound(ripk_plan_t p, int64_t candidates) {
+  if (!p) return fail(RIPK_EINVAL, "null plan");
+  if (candidates < 0) return fail(RIPK_EINVAL, "flush bound must be >= 0");
+  // (a bound at or above the smallest default selects the layout's default)
+  p->flush_evals = candidates >= (1LL << 29) ? 0u : (uint64_t)candidates;
+  ++p->bind_gen;  // a captured graph holds the old bound
   return RIPK_OK;
 }
 

@@ -715,6 +715,8 @@ k_pair(PairArgs a) {
   if (tid < g.n_t) T[tid] = a.T[tid];
   if (tid == 0) *evals_lds = 0;
   const uint32_t n_items = *a.n_items;
+  const unsigned long long flush_bound =
+      a.flush_evals ? a.flush_evals : ((packed || WIDE) ? kFlushEvalsPacked : kFlushEvals);
   // 2^F of the inhomogeneous fixed-point weights (the same F in k_finalize)
   const double wscale = INHOM ? ldexp(1.0, wide_fbits(*a.rho_max, a.wbudget)) : 0.0;
   int cur_set = -1;
@@ -801,7 +803,7 @@ k_pair(PairArgs a) {
     const uint32_t base = grp * kItemsPerGroup;
     const int set = (int)uni(a.items[base].set);
     const unsigned long long pend = *evals_lds;
-    if (set != cur_set || pend > ((packed || WIDE) ? kFlushEvalsPacked : kFlushEvals)) {
+    if (set != cur_set || pend > flush_bound) {
       if (cur_set >= 0) flush(cur_set);
       cur_set = set;
       __syncthreads();

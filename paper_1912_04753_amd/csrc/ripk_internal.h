@@ -102,6 +102,9 @@ struct PairArgs {
   int wbudget;
   int bins;                    // LDS bin layout (kBinsPacked, kBinsSplit32, kBinsSplit64,
                                // kBinsWide)
+  // candidates a workgroup examines before it flushes its LDS bins within a
+  // set (0: the layout's own bound)
+  unsigned long long flush_evals;
 };
 
 // Words per bin of the global weight sums (see PairArgs::binW).

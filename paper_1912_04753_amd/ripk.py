@@ -134,6 +134,7 @@ _SIGS = {
     "ripk_compute_K_noalloc": (_i32, [_P(PlanDesc), _P(Points), ctypes.c_void_p, _P(KOut)]),
     "ripk_plan_stats": (_i32, [ctypes.c_void_p, _P(Stats)]),
     "ripk_plan_get_info": (_i32, [ctypes.c_void_p, _P(PlanInfo)]),
+    "ripk_plan_set_flush_bound": (_i32, [ctypes.c_void_p, ctypes.c_int64]),
     "ripk_server_create": (_i32, [_P(ServerDesc), _P(ctypes.c_void_p)]),
     "ripk_server_destroy": (None, [ctypes.c_void_p]),
     "ripk_submit": (_i32, [ctypes.c_void_p, _P(Request), _P(_u64)]),
@@ -414,6 +415,11 @@ def ripk_compute_K_noalloc(desc, x, y, t, out, n_centres=0, stream=None):
     _check(lib().ripk_compute_K_noalloc(ctypes.byref(desc), ctypes.byref(pts), st,
                                         ctypes.byref(kout)), "ripk_compute_K_noalloc")
     del kx, ky, kt
+
+
+def ripk_plan_set_flush_bound(plan, candidates):
+    _check(lib().ripk_plan_set_flush_bound(plan.handle, int(candidates)),
+           "ripk_plan_set_flush_bound")
 
 
 def ripk_plan_stats(plan):
