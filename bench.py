@@ -12,10 +12,12 @@ starts.  ``two_calls`` times the same step as ``ripk_compute_K`` followed by
 Printed: one JSON line.  ``value`` = ordered in-range pair tests per second
 (N_in over the step, in units of 1e9/s); ``sims_per_s``; ``roofline`` for the
 pair kernel (integer ALU bound: 9 lane-ops per candidate pair against
-256 CU x 64 lanes x 2.4 GHz), with HBM traffic per launch from the stored
-counter summary while the pair kernel is unchanged; ``cpu_baseline`` = the FP64
-oracle on the host cores over the observed set and as many of its simulations
-as fit in about 12 s.
+compute units x 64 lanes x peak engine clock, read from the device), with HBM
+traffic per launch from the stored counter summary while the pair kernel is
+unchanged, and the same fraction for every other leg; ``cpu_baseline`` = the
+FP64 oracle on the host cores over the observed set and as many of its
+simulations as fit in about 12 s, plus one thread on the 2k set and on a
+sample of centres of the 200k clustered set.
 """
 import argparse
 import json
@@ -30,7 +32,15 @@ sys.path.insert(0, ROOT)
 METRIC = "G space-time pair tests/s + sims/s at 1 GPU; served p50/p99 latency vs plain path"
 OPS_PER_EVAL = 9            # minimal integer test of one candidate pair (lane-ops)
 OPS_PER_IN = 10             # bin (6) + fast-path weight (4) of one in-range ordered pair
-PEAK_LANE_OPS = 256 * 64 * 2.4e9   # CUs x lanes x clock
+PEAK = {"lane_ops": 256 * 64 * 2.4e9}   # CUs x lanes x clock, replaced by the device's figures
+
+
+def leg_roof(stats, us_pair):
+    """Candidates, mean pair-kernel time and roofline fraction of a leg."""
+    ev = int(stats["n_eval"])
+    return {"n_eval": ev, "pair_kernel_us": round(us_pair, 2),
+            "frac": round(OPS_PER_EVAL * ev / (us_pair * 1e-6) / PEAK["lane_ops"], 4)
+            if us_pair > 0 else None}
 
 
 def cpu_baseline(cfg, x, y, t, target_s):
@@ -58,11 +68,28 @@ def cpu_baseline(cfg, x, y, t, target_s):
                 break
     except OSError:
         pass
+    # one thread: the 2k set whole, and 4,000 centres of the 200k clustered set
+    # against all its points
+    from paper_1912_04753_amd import workloads
+    one = {}
+    for wname, nc in (("uniform-2k", None), ("thomas-200k", 4000)):
+        wc = workloads.workload(wname)
+        wx, wy, wt = workloads.make_points(wc)
+        wd = oracle.desc(wc["window"], wc["s_max"], wc["t_max"], wc["n_s"], wc["n_t"])
+        t1 = oracle.now()
+        r1 = oracle.estimate(wd, wx, wy, wt, n_centres=nc, threads=1)
+        d1 = oracle.now() - t1
+        one[wname] = {"value": round(int(r1["C"][-1, -1]) / d1 / 1e9, 6),
+                      "seconds": round(d1, 3),
+                      "sample": "every ordered pair" if nc is None else
+                                f"the first {nc} of {len(wx)} points as centres, every point "
+                                f"as neighbour"}
     return {"value": n_in / dt / 1e9, "unit": "G pair tests/s", "cores": threads,
             "kind": "oracle", "cpu": cpu,
             "sample": f"observed set of the workload plus {sets - 1} of its {cfg['sims']} CSR "
                       f"simulations ({sets} sets of {n} points, every ordered pair); "
-                      f"{n_in} in-range ordered pairs in {dt:.2f} s"}
+                      f"{n_in} in-range ordered pairs in {dt:.2f} s",
+            "one_thread": one}
 
 
 def serving(ripk, workloads, n_req, slots, load):
@@ -201,6 +228,8 @@ def main():
     from paper_1912_04753_amd import ripk, workloads
 
     torch.cuda.set_device(0)
+    dev = ripk.ripk_device_query(0)
+    PEAK["lane_ops"] = dev["compute_units"] * 64 * dev["clock_khz"] * 1e3
     if args.copy_calibration:
         copy_calibration(torch)
     cfg = workloads.workload("uniform-100k-99csr")
@@ -273,7 +302,8 @@ def main():
                                              (two_ms * 1e-3) / 1e9, 3),
                  "sims_per_s": round(m / (sum(r[3] for r in recs2) / len(recs2)), 3),
                  "pair_kernel_us": {"observed": round(sum(r[0]["us_pair"] for r in recs2) / len(recs2), 2),
-                                    "simulations": round(sum(r[1]["us_pair"] for r in recs2) / len(recs2), 2)}}
+                                    "simulations": round(sum(r[1]["us_pair"] for r in recs2) / len(recs2), 2)},
+                 "roofline_simulations": leg_roof(recs2[0][1], sum(r[1]["us_pair"] for r in recs2) / len(recs2))}
     # end to end with the observed points in host memory (H2D copy inside the call)
     t_h = time.perf_counter()
     for _ in range(3):
@@ -306,7 +336,8 @@ def main():
     resampled = {}
     for name, method in (("permutation", ripk.RIPK_SIM_PERMUTE), ("bootstrap", ripk.RIPK_SIM_BOOTSTRAP)):
         rdesc = ripk.make_desc(cfg["window"], cfg["s_max"], cfg["t_max"], cfg["n_s"], cfg["n_t"],
-                               n_max=n, m_max=m, cell_div=cd, tcell_div=td, sim_method=method)
+                               n_max=n, m_max=m, cell_div=cd, tcell_div=td, sim_method=method,
+                               flags=ripk.RIPK_PLAN_TIMING)
         rplan = ripk.ripk_plan(rdesc)
         ripk.ripk_compute_K(rplan, dx, dy, dt, stream=stream)
         ripk.ripk_simulate_envelope(rplan, n, m, cfg["seed"], stream=stream)
@@ -316,20 +347,24 @@ def main():
             ripk.ripk_simulate_envelope(rplan, n, m, cfg["seed"], stream=stream)
         torch.cuda.synchronize()
         dt_r = (time.perf_counter() - t_r) / 3
+        rst = ripk.ripk_plan_stats(rplan)
         resampled[name] = {"sims_per_s": round(m / dt_r, 3),
-                           "pair_tests_per_s_G": round(ripk.ripk_plan_stats(rplan)["n_in"] / dt_r / 1e9, 3)}
+                           "pair_tests_per_s_G": round(rst["n_in"] / dt_r / 1e9, 3),
+                           "roofline": leg_roof(rst, rst["us_pair"])}
         rplan.destroy()
     # cross (two-type) K: the same set read as two types of n/2 points each,
     # observed cross K + m CSR simulations keeping the split, autotuned cells
     n1 = n // 2
     xplan = ripk.ripk_plan(ripk.make_desc(cfg["window"], cfg["s_max"], cfg["t_max"], cfg["n_s"],
                                           cfg["n_t"], n_max=n, m_max=m,
-                                          flags=ripk.RIPK_PLAN_CROSS | ripk.RIPK_PLAN_AUTOTUNE))
+                                          flags=ripk.RIPK_PLAN_CROSS | ripk.RIPK_PLAN_AUTOTUNE |
+                                          ripk.RIPK_PLAN_TIMING))
 
     def xstep():
         t1 = time.perf_counter()
         ripk.ripk_compute_K_envelope(xplan, dx, dy, dt, m, cfg["seed"], n_centres=n1, stream=stream)
-        return ripk.ripk_plan_stats(xplan)["n_in"], time.perf_counter() - t1
+        b = ripk.ripk_plan_stats(xplan)
+        return b["n_in"], time.perf_counter() - t1, b
 
     xstep()  # tuning
     xstep()
@@ -343,6 +378,7 @@ def main():
              "pair_tests_per_s_G": round(xs[0][0] / (x_ms * 1e-3) / 1e9, 3),
              "sims_per_s": round(m / (sum(v[1] for v in xs) / 3), 3),
              "cells_m_s": [xi["cell_s"], xi["cell_t"]],
+             "roofline": leg_roof(xs[0][2], sum(v[2]["us_pair"] for v in xs) / 3),
              "note": "types = first and second half of the set; ordered cross pairs"}
     xplan.destroy()
     # polygon study area: 100k points uniform inside an 85-vertex boundary of the
@@ -359,7 +395,7 @@ def main():
         t1 = time.perf_counter()
         ripk.ripk_compute_K_envelope(pplan, px, py, pt, pm, pc["seed"], stream=stream)
         b = ripk.ripk_plan_stats(pplan)
-        return b["n_in"], time.perf_counter() - t1, b["us_pair"]
+        return b["n_in"], time.perf_counter() - t1, b["us_pair"], b
 
     pstep()  # tuning
     pstep()
@@ -374,6 +410,7 @@ def main():
                "sims_per_s": round(pm / (sum(v[1] for v in ps) / 3), 3),
                "pair_kernel_us": round(sum(v[2] for v in ps) / 3, 2),
                "cells_m_s": [pi_["cell_s"], pi_["cell_t"]],
+               "roofline": leg_roof(ps[0][3], sum(v[2] for v in ps) / 3),
                "note": "100k uniform points inside an 85-vertex star-shaped boundary "
                        "(46% of the 20 km x 20 km window), 180 d, 25x15 grid to 2 km/30 d, "
                        "observed K + 99 CSR simulations"}
@@ -386,17 +423,22 @@ def main():
     dlam = torch.from_numpy((n / AD) * fx / fx.mean()).cuda()
     iplan = ripk.ripk_plan(ripk.make_desc(cfg["window"], cfg["s_max"], cfg["t_max"], cfg["n_s"],
                                           cfg["n_t"], n_max=n,
-                                          flags=ripk.RIPK_PLAN_INHOM | ripk.RIPK_PLAN_AUTOTUNE))
+                                          flags=ripk.RIPK_PLAN_INHOM | ripk.RIPK_PLAN_AUTOTUNE |
+                                          ripk.RIPK_PLAN_TIMING))
     for _ in range(2):
         ripk.ripk_compute_K(iplan, dx, dy, dt, stream=stream, lam=dlam)
     torch.cuda.synchronize()
     t_i = time.perf_counter()
+    ius = []
     for _ in range(5):
         ripk.ripk_compute_K(iplan, dx, dy, dt, stream=stream, lam=dlam)
+        ius.append(ripk.ripk_plan_stats(iplan)["us_pair"])
     torch.cuda.synchronize()
     i_ms = 1e3 * (time.perf_counter() - t_i) / 5
+    ist = ripk.ripk_plan_stats(iplan)
     inhom = {"ms_per_call": round(i_ms, 3),
-             "pair_tests_per_s_G": round(ripk.ripk_plan_stats(iplan)["n_in"] / (i_ms * 1e-3) / 1e9, 3),
+             "pair_tests_per_s_G": round(ist["n_in"] / (i_ms * 1e-3) / 1e9, 3),
+             "roofline": leg_roof(ist, sum(ius) / len(ius)),
              "note": "observed K_I of the 100k set, intensity per point (device), autotuned cells"}
     iplan.destroy()
     # the two larger workloads, autotuned: 200k clustered points (observed K), and
@@ -408,7 +450,7 @@ def main():
         wn, wm = len(wx), wc["sims"]
         wplan = ripk.ripk_plan(ripk.make_desc(wc["window"], wc["s_max"], wc["t_max"], wc["n_s"],
                                               wc["n_t"], n_max=wn, m_max=wm,
-                                              flags=ripk.RIPK_PLAN_AUTOTUNE))
+                                              flags=ripk.RIPK_PLAN_AUTOTUNE | ripk.RIPK_PLAN_TIMING))
 
         def wstep():
             t1 = time.perf_counter()
@@ -416,7 +458,8 @@ def main():
                 ripk.ripk_compute_K(wplan, wx, wy, wt, stream=stream)
             else:
                 ripk.ripk_compute_K_envelope(wplan, wx, wy, wt, wm, wc["seed"], stream=stream)
-            return ripk.ripk_plan_stats(wplan)["n_in"], time.perf_counter() - t1
+            b = ripk.ripk_plan_stats(wplan)
+            return b["n_in"], time.perf_counter() - t1, b
 
         wstep()  # tuning
         torch.cuda.synchronize()
@@ -430,7 +473,8 @@ def main():
                          "n_in_per_step": ws[0][0],
                          "sims_per_s": round(wm / (sum(v[1] for v in ws) / reps), 3) if wm else None,
                          "cells_m_s": [wi["cell_s"], wi["cell_t"]],
-                         "split": ripk.ripk_plan_stats(wplan)["split"]}
+                         "split": ripk.ripk_plan_stats(wplan)["split"],
+                         "roofline": leg_roof(ws[0][2], sum(v[2]["us_pair"] for v in ws) / reps)}
         wplan.destroy()
         del wx, wy, wt
     plan.destroy()
@@ -447,7 +491,7 @@ def main():
     achieved = OPS_PER_EVAL * evals / (avg_us * 1e-6) / 1e12
     # the same with the binning work of the in-range pairs counted as well
     achieved_all = (OPS_PER_EVAL * evals + OPS_PER_IN * n_in) / (avg_us * 1e-6) / 1e12
-    peak = PEAK_LANE_OPS / 1e12
+    peak = PEAK["lane_ops"] / 1e12
     from paper_1912_04753_amd.profiling import load_traffic
     tr = load_traffic(os.path.join(ROOT, "profiles", "k_pair_uniform100k_99csr_traffic.json"))
     out = {
@@ -480,6 +524,10 @@ def main():
         "observed_host_input": {"ms": round(host_obs_ms, 3),
                                 "pair_tests_per_s_G": round(n_in_obs / (host_obs_ms * 1e-3) / 1e9, 3),
                                 "note": "ripk_compute_K on host arrays: PCIe copy of 1.2 MB inside the call"},
+        "device": {"compute_units": dev["compute_units"], "clock_mhz": dev["clock_khz"] / 1e3,
+                   "lds_per_cu_kib": dev["lds_per_cu_bytes"] / 1024, "arch": dev["arch"],
+                   "note": "read with hipGetDeviceProperties; the roofline peak is "
+                           "compute_units x 64 lanes x clock"},
         "n_in_per_step": n_in,
         "n_eval_per_step": evals,
         "pair_kernel_us": round(avg_us, 2),

@@ -346,6 +346,21 @@ ripk_status ripk_plan_stats(ripk_plan_t plan, ripk_stats *out);
  * tuned cells). */
 ripk_status ripk_plan_get_info(ripk_plan_t plan, ripk_plan_info *out);
 
+/* The device figures the pair kernel's integer-ALU roofline is priced on
+ * (compute units x 64 lanes x peak engine clock), read with
+ * hipGetDeviceProperties: multiProcessorCount, clockRate (kHz),
+ * maxSharedMemoryPerMultiProcessor, totalGlobalMem, warpSize, gcnArchName.
+ * RIPK_EINVAL for a null output, RIPK_EDEVICE when the query fails. */
+typedef struct {
+  int32_t compute_units;
+  int32_t clock_khz;
+  int64_t lds_per_cu_bytes;
+  int64_t hbm_bytes;
+  int32_t wavefront;
+  char arch[68];
+} ripk_device_props;
+ripk_status ripk_device_query(int32_t device, ripk_device_props *out);
+
 /* Test hook for the pair kernel's histogram flush (the merge of each
  * workgroup's LDS bins into a set's global bins).  A workgroup flushes when
  * it moves on to another point set and, within a set, once it has examined

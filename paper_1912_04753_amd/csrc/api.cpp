@@ -1373,6 +1373,21 @@ ripk_status ripk_plan_stats(ripk_plan_t p, ripk_stats *out) {
   return RIPK_OK;
 }
 
+ripk_status ripk_device_query(int32_t device, ripk_device_props *out) {
+  if (!out) return fail(RIPK_EINVAL, "null output");
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess)
+    return fail(RIPK_EDEVICE, "hipGetDeviceProperties failed for device %d", device);
+  std::memset(out, 0, sizeof *out);
+  out->compute_units = prop.multiProcessorCount;
+  out->clock_khz = prop.clockRate;
+  out->lds_per_cu_bytes = (int64_t)prop.maxSharedMemoryPerMultiProcessor;
+  out->hbm_bytes = (int64_t)prop.totalGlobalMem;
+  out->wavefront = prop.warpSize;
+  std::strncpy(out->arch, prop.gcnArchName, sizeof out->arch - 1);
+  return RIPK_OK;
+}
+
 ripk_status ripk_plan_set_flush_bound(ripk_plan_t p, int64_t candidates) {
   if (!p) return fail(RIPK_EINVAL, "null plan");
   if (candidates < 0) return fail(RIPK_EINVAL, "flush bound must be >= 0");

@@ -81,6 +81,11 @@ class EnvOut(ctypes.Structure):
                 ("W_sims", _P(_f64)), ("K_sims", _P(_f64))]
 
 
+class DeviceProps(ctypes.Structure):
+    _fields_ = [("compute_units", _i32), ("clock_khz", _i32), ("lds_per_cu_bytes", _i64),
+                ("hbm_bytes", _i64), ("wavefront", _i32), ("arch", ctypes.c_char * 68)]
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("n_sets", _i64), ("n_points", _i64), ("n_in", _i64), ("n_eval", _i64),
                 ("n_items", _i64), ("pair_grid", _i32), ("symmetric", _i32), ("split", _i32),
@@ -135,6 +140,7 @@ _SIGS = {
     "ripk_plan_stats": (_i32, [ctypes.c_void_p, _P(Stats)]),
     "ripk_plan_get_info": (_i32, [ctypes.c_void_p, _P(PlanInfo)]),
     "ripk_plan_set_flush_bound": (_i32, [ctypes.c_void_p, ctypes.c_int64]),
+    "ripk_device_query": (_i32, [_i32, _P(DeviceProps)]),
     "ripk_server_create": (_i32, [_P(ServerDesc), _P(ctypes.c_void_p)]),
     "ripk_server_destroy": (None, [ctypes.c_void_p]),
     "ripk_submit": (_i32, [ctypes.c_void_p, _P(Request), _P(_u64)]),
@@ -415,6 +421,14 @@ def ripk_compute_K_noalloc(desc, x, y, t, out, n_centres=0, stream=None):
     _check(lib().ripk_compute_K_noalloc(ctypes.byref(desc), ctypes.byref(pts), st,
                                         ctypes.byref(kout)), "ripk_compute_K_noalloc")
     del kx, ky, kt
+
+
+def ripk_device_query(device=0):
+    p = DeviceProps()
+    _check(lib().ripk_device_query(int(device), ctypes.byref(p)), "ripk_device_query")
+    d = {k: getattr(p, k) for k, _ in DeviceProps._fields_}
+    d["arch"] = p.arch.decode(errors="replace")
+    return d
 
 
 def ripk_plan_set_flush_bound(plan, candidates):

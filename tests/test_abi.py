@@ -41,7 +41,8 @@ def test_struct_layouts_match_the_c_compiler(tmp_path):
                "ripk_plan_info": ripk.PlanInfo, "ripk_stats": ripk.Stats,
                "ripk_server_desc": ripk.ServerDesc, "ripk_request": ripk.Request,
                "ripk_result": ripk.Result, "ripk_server_state": ripk.ServerState,
-               "ripk_K_out": ripk.KOut, "ripk_env_out": ripk.EnvOut}
+               "ripk_K_out": ripk.KOut, "ripk_env_out": ripk.EnvOut,
+               "ripk_device_props": ripk.DeviceProps}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ripk.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
