@@ -368,13 +368,7 @@ ripk_status derive(const ripk_plan_desc *d, Layout *L) {
   // scaled down by 2^-20 so that the pair kernel's FP32 step estimates never
   // exceed the exact step (it then corrects upward by at most one)
   g.inv_ds = (float)((double)d->n_s / (double)d->s_max * (1.0 - 0x1p-20));
-  {
-    uint32_t sh = 0;
-    while ((int64_t)d->n_t > ((int64_t)d->t_max << sh)) ++sh;
-    const uint64_t num = (uint64_t)d->n_t << (32 - sh);
-    g.tmul = (uint32_t)((num + (uint64_t)d->t_max - 1) / (uint64_t)d->t_max - 1);
-    g.tsh = sh;
-  }
+  g.inv_dt = (float)((double)d->n_t / (double)d->t_max * (1.0 - 0x1p-20));
   L->clamp_e = (int32_t)d->s_max;
   g.poly = nullptr;
   g.near = nullptr;
@@ -413,6 +407,12 @@ struct ripk_plan_s {
   int32_t bound_cd = 1, bound_td = 1;  // cell subdivisions of the bound geometry
   bool split_runs = false;             // run fractions for this call's launch
   uint64_t flush_evals = 0;            // ripk_plan_set_flush_bound (0: default)
+  // served plans (plan_set_sharing): host-visible count of busy slots, the
+  // share of the pair kernel's grid kept while others are busy, and the
+  // slice length of long pair launches
+  const int32_t *share_word = nullptr;
+  double share_frac = 1.0;
+  double slice_us = 0.0;
   uint64_t bind_gen = 0;               // bumped whenever a geometry is bound
   // RIPK_PLAN_GRAPH: the captured launch sequence of the last call shape
   hipGraphExec_t gexec = nullptr;
@@ -628,9 +628,29 @@ ripk_status enqueue_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_cent
   a.wbudget = inhom ? wide_budget(n) : 0;
   a.bins = bins;
   a.flush_evals = p->flush_evals;
+  a.share_word = p->share_word;
+  a.share_grid = (int32_t)std::max<int64_t>(1, (int64_t)(p->share_frac * (double)slots));
+  a.slice_ticks = 0;
   const int64_t groups_cap = items_bound * split / kItemsPerGroup + 1;
   const int grid = (int)std::min<int64_t>(slots, groups_cap);
-  HIPCHK(launch_pair(a, grid, st));
+  // A served plan cuts a long pair launch into slices: workgroups leave after
+  // slice_us, the next launch on the stream carries on with the same work
+  // queue, and the last launch runs to the end.  Between slices the other
+  // requests' kernels get the device.  The launch time is estimated from the
+  // candidates a uniform set would have (full stencil rows, symmetric half).
+  int slices = 1;
+  if (p->slice_us > 0.0) {
+    const double W = (double)(g.x1 - g.x0), H = (double)(g.y1 - g.y0), D = (double)(g.t1 - g.t0);
+    const double reach = std::min(1.0, (2.0 * g.rs + 1) * g.cell_s / W) *
+                         std::min(1.0, (2.0 * g.rs + 1) * g.cell_s / H) *
+                         std::min(1.0, (2.0 * g.rt + 1) * g.cell_t / D);
+    const double est_us = 0.5 * (double)S * (double)n * (double)n * reach / 1.0e6;
+    slices = (int)std::min(64.0, std::floor(est_us / p->slice_us)) + 1;
+  }
+  for (int sl = 0; sl < slices; ++sl) {
+    a.slice_ticks = sl + 1 < slices ? (uint32_t)(p->slice_us * 100.0) : 0u;  // 100 MHz ticks
+    HIPCHK(launch_pair(a, grid, st));
+  }
   if (timing) HIPCHK(hipEventRecord(p->ev[3], st));
 
   // K = AD * W / Nn; inhomogeneous K is W / (A D)
@@ -829,6 +849,14 @@ ripk_status bind_geometry(ripk_plan_s *p, const ripk_plan_desc *desc, hipStream_
 // Binds a descriptor to a plan whose buffers hold its capacities; the
 // threshold tables are copied on `stream`.  With RIPK_PLAN_AUTOTUNE the cells
 // are tuned afresh on the next calls.
+void plan_set_sharing(ripk_plan_s *p, const int32_t *share_word, double share_frac,
+                      double slice_us) {
+  p->share_word = share_word;
+  p->share_frac = share_frac;
+  p->slice_us = slice_us;
+  ++p->bind_gen;  // a captured graph holds the old launch sequence
+}
+
 ripk_status plan_bind(ripk_plan_s *p, const ripk_plan_desc *desc, hipStream_t stream) {
   ripk_status s = bind_geometry(p, desc, stream);
   if (s != RIPK_OK) return s;

@@ -289,16 +289,20 @@ __device__ __forceinline__ void drain_b(WaveLds &W, QState &q, uint32_t c, int l
     q.nb -= c;
     return;
   }
+  // rectangle: queue A already added the interior value (1 + half) 2^23 of
+  // every side, so a boundary side adds its excess over it (w >= 1)
   uint32_t qv;
   if (MODE == kModePacked) {
     // d2 < 2^31 and side distances < 2^15: 32-bit arithmetic throughout
     const float oi = omega_f32(r.z & 0xFFFFu, r.z >> 16, r.y);
     const float oj = omega_f32(r.w & 0xFFFFu, r.w >> 16, r.y);
-    qv = (((r.x >> 14) & 1u) ? qweight(oi, (r.x >> 12) & 1u) : 0u) +
-         (((r.x >> 15) & 1u) ? qweight(oj, (r.x >> 13) & 1u) : 0u);
+    const uint32_t hi = (r.x >> 12) & 1u, hj = (r.x >> 13) & 1u;
+    qv = (((r.x >> 14) & 1u) ? qweight(oi, hi) - ((1u + hi) << kFracBits) : 0u) +
+         (((r.x >> 15) & 1u) ? qweight(oj, hj) - ((1u + hj) << kFracBits) : 0u);
   } else {
-    qv = qweight(omega_f32(r.z, r.w, (uint64_t)r.y | ((uint64_t)(r.x >> 13) << 32)),
-                 (r.x >> 12) & 1u);
+    const uint32_t h = (r.x >> 12) & 1u;
+    qv = qweight(omega_f32(r.z, r.w, (uint64_t)r.y | ((uint64_t)(r.x >> 13) << 32)), h) -
+         ((1u + h) << kFracBits);
   }
   if ((uint32_t)lane < c) atomicAdd(&hw[bin], (unsigned long long)qv);
   q.hb = (q.hb + c) & (kQB - 1);
@@ -386,13 +390,12 @@ __device__ __forceinline__ void drain_a(WaveLds &W, QState &q,
   // tables (S2[k] = floor(s_k^2) and d2 is an integer).  inv_ds carries a
   // factor 1 - 2^-20, larger than the FP32 error of the quotient, so x' < x
   // whenever x > 0 and trunc(x') + 1 is k* or k* - 1: one comparison with the
-  // table restores the exact step.  The time estimate is an integer product
-  // high word with the same two properties (below u n_t / t_max by less than
-  // 1/4, strictly below it for u > 0), corrected with the T table.  kk, ll are
-  // the 0-based steps.
+  // table restores the exact step.  The time estimate u n_t / t_max is formed
+  // the same way (inv_dt; u < 2^30 is rounded to FP32 within 2^-24) and
+  // corrected with the T table.  kk, ll are the 0-based steps.
   const float d2f = MODE == kModeWide ? (float)d2 : (float)d2lo;
   const uint32_t k0 = (uint32_t)(__builtin_amdgcn_sqrtf(d2f) * g.inv_ds);
-  const uint32_t l0 = __umulhi(u << g.tsh, g.tmul);
+  const uint32_t l0 = (uint32_t)((float)u * g.inv_dt);
   const uint32_t sk = S2lo[k0], tl = T[l0];
   bool up_k;
   if (MODE == kModeWide)
@@ -406,15 +409,22 @@ __device__ __forceinline__ void drain_a(WaveLds &W, QState &q,
   // v = 1/2 when an end of [t-u, t+u] leaves the period: the weight doubles
   const Side si = side_of<MODE>(pi, d2lo, d2, g);
   const uint32_t hfi = (tp && u > min(si.T, D - si.T)) ? 1u : 0u;
-  uint32_t qsum = si.slow ? 0u : (hfi ? (2u << kFracBits) : (1u << kFracBits));
   Side sj = si;
   sj.slow = false;
   uint32_t hfj = 0;
   if (SYM) {
     sj = side_of<MODE>(pj, d2lo, d2, g);
     hfj = (tp && u > min(sj.T, D - sj.T)) ? 1u : 0u;
-    qsum += sj.slow ? 0u : (hfj ? (2u << kFracBits) : (1u << kFracBits));
   }
+  // interior values in units of 2^23: the rectangle adds 1 + half for every
+  // side (queue B adds a boundary side's excess); polygon launches only the
+  // sides that take the interior path (queue B adds the others whole)
+  uint32_t units;
+  if (POLY || INHOM)
+    units = (si.slow ? 0u : 1u + hfi) + ((SYM && !sj.slow) ? 1u + hfj : 0u);
+  else
+    units = 1u + hfi + (SYM ? 1u + hfj : 0u);
+  const uint32_t qsum = units << kFracBits;
   // boundary-queue mask, taken next to the compares (separate ballots fold
   // into their masks; taken after the branch below they would be rebuilt)
   const unsigned long long mslow =
@@ -442,7 +452,7 @@ __device__ __forceinline__ void drain_a(WaveLds &W, QState &q,
     }
   } else if (v) {
     if (bins == kBinsPacked) {
-      atomicAdd(&hist[bin], (1ull << kCountShift) | (unsigned long long)(qsum >> kFracBits));
+      atomicAdd(&hist[bin], (1ull << kCountShift) | (unsigned long long)units);
     } else {
       atomicAdd(&hist[bin], (unsigned long long)qsum);
       if (bins == kBinsSplit64)
@@ -630,48 +640,52 @@ __device__ __forceinline__ void scan_run(Ctx<SYM, MODE, POLY, INHOM> &x, uint32_
     const uint32_t lane_tag =
         (uint32_t)((const unsigned char *)&W.cen[0][lane] - (const unsigned char *)&W) |
         ((uint32_t)((const unsigned char *)&W.tile[0][0] - (const unsigned char *)&W) << 16);
-    typedef uint32_t gvec __attribute__((ext_vector_type(kGroup)));
-    for (uint32_t jj = 0; jj < nt; jj += kGroup) {
-      int4 pj[kGroup];
+    // four neighbours per LDS access, a drain check after every kGroup; a
+    // partial last group reads padding entries, which fail every time test
+    typedef uint32_t gvec __attribute__((ext_vector_type(4)));
+    static_assert(kGroup == 2, "the scan takes two pushes per drain check");
+    for (uint32_t jj = 0; jj < nt; jj += 4) {
+      int4 pj[4];
       {
-        // components the candidate test needs, kGroup neighbours per access
+        // components the candidate test needs
         const gvec c0 = *(const gvec *)&W.tile[0][jj];
         const gvec c1 = *(const gvec *)&W.tile[1][jj];
         gvec c2 = c1;
         if (MODE != kModePacked) c2 = *(const gvec *)&W.tile[2][jj];
 #pragma unroll
-        for (int u = 0; u < kGroup; ++u) pj[u] = make_int4((int)c0[u], (int)c1[u], (int)c2[u], 0);
+        for (int u = 0; u < 4; ++u) pj[u] = make_int4((int)c0[u], (int)c1[u], (int)c2[u], 0);
       }
 #pragma unroll
-      for (int u = 0; u < kGroup; ++u) {
+      for (int u = 0; u < 4; ++u) {
         bool cs, ct;
         cand<MODE>(me, tplus, thr, pj[u], x.g, cs, ct);
         const uint32_t j = tb + jj + u;
         const bool hc = HOME ? (SYM ? (j > mi) : (j != mi)) : true;
         // separate ballots fold into the compare masks; the per-lane predicate
-        // only steers the store (PACKED: empty lanes already fail cs)
+        // only steers the store (PACKED: empty lanes already fail cs).  Almost
+        // every neighbour has some centre in range, so there is no test for
+        // an empty mask.
         unsigned long long mask = __builtin_amdgcn_ballot_w64(cs) & __builtin_amdgcn_ballot_w64(ct);
         if (MODE != kModePacked) mask &= valid;
         if (HOME) mask &= __builtin_amdgcn_ballot_w64(hc);
-        if (mask) {
-          const uint32_t base = q.ta;
-          q.ta = base + (uint32_t)__popcll(mask);
-          const bool pass = MODE == kModePacked ? (cs & ct & hc) : (cs & ct & lv & hc);
-          if (pass) W.qa[base + lane_rank(mask, 0)] = lane_tag + ((jj + u) << 18);
-          if (q.ta >= kQA) {
-            // the push reached the ring's end: move what ran past it to the
-            // start (those slots were drained: fewer than kQA are pending)
-            const uint32_t over = q.ta - kQA;
-            if (over) {
-              wave_sync();
-              if ((uint32_t)lane < over) W.qa[lane] = W.qa[kQA + lane];
-              wave_sync();
-            }
-            q.ta = over;
+        const uint32_t base = q.ta;
+        q.ta = base + (uint32_t)__popcll(mask);
+        const bool pass = MODE == kModePacked ? (cs & ct & hc) : (cs & ct & lv & hc);
+        if (pass) W.qa[base + lane_rank(mask, 0)] = lane_tag + ((jj + u) << 18);
+        if (q.ta >= kQA) {
+          // the push reached the ring's end: move what ran past it to the
+          // start (those slots were drained: fewer than kQA are pending)
+          const uint32_t over = q.ta - kQA;
+          if (over) {
+            wave_sync();
+            if ((uint32_t)lane < over) W.qa[lane] = W.qa[kQA + lane];
+            wave_sync();
           }
+          q.ta = over;
         }
+        if (u & 1)
+          for (uint32_t na = na_of(q); na >= 64; na -= 64) drain_oldest(x, 64);
       }
-      for (uint32_t na = na_of(q); na >= 64; na -= 64) drain_oldest(x, 64);
     }
   }
 }
@@ -714,6 +728,18 @@ k_pair(PairArgs a) {
   }
   if (tid < g.n_t) T[tid] = a.T[tid];
   if (tid == 0) *evals_lds = 0;
+  // device sharing: the slots above share_grid stay free while other streams
+  // have work (the word lives in host memory; one read per workgroup)
+  if (a.share_word) {
+    if (tid == 0)
+      *grp_lds = (uint32_t)__hip_atomic_load(a.share_word, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_SYSTEM);
+    __syncthreads();
+    const bool leave = uni(*grp_lds) > 1u && (int)blockIdx.x >= a.share_grid;
+    __syncthreads();
+    if (leave) return;
+  }
+  const unsigned long long t_start = a.slice_ticks ? __builtin_amdgcn_s_memrealtime() : 0ull;
   const uint32_t n_items = *a.n_items;
   const unsigned long long flush_bound =
       a.flush_evals ? a.flush_evals : ((packed || WIDE) ? kFlushEvalsPacked : kFlushEvals);
@@ -781,6 +807,8 @@ k_pair(PairArgs a) {
     __syncthreads();  // previous group finished by every wave
     if (tid == 0) {
       uint32_t got = 0xFFFFFFFFu;
+      // a sliced launch stops taking groups at the end of its slice
+      if (a.slice_ticks && __builtin_amdgcn_s_memrealtime() - t_start > a.slice_ticks) q_left = 0;
       while (q_left > 0) {
         const uint32_t lo = (uint32_t)((uint64_t)qp * n_groups / kQueues);
         const uint32_t hi = (uint32_t)((uint64_t)(qp + 1) * n_groups / kQueues);

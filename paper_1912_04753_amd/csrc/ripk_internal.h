@@ -35,10 +35,7 @@ struct Geom {
   uint64_t s2max;                  // S2[n_s-1]
   uint32_t tmax;                   // T[n_t-1]
   float inv_ds;                    // n_s / s_max * (1 - 2^-20)
-  // time step estimate l0 = mulhi(u << tsh, tmul): tmul = ceil(2^(32-tsh) n_t / t_max) - 1
-  // (tsh = 0 unless n_t > t_max), so that u n_t / t_max - 1/4 < l0 <= u n_t / t_max, with
-  // the second inequality strict for u > 0
-  uint32_t tmul, tsh;
+  float inv_dt;                    // n_t / t_max * (1 - 2^-20)
   // polygon study area (poly_n = 0: the rectangle): window-relative vertices,
   // per xy-cell lists of the edges within s_max (see poly.h), orientation sign
   const int2 *poly;
@@ -105,6 +102,16 @@ struct PairArgs {
   // candidates a workgroup examines before it flushes its LDS bins within a
   // set (0: the layout's own bound)
   unsigned long long flush_evals;
+  // Sharing the device with other streams (a server's concurrent requests):
+  // with share_word set, a workgroup whose index is share_grid or more exits
+  // at once while the host-visible count *share_word exceeds 1, leaving those
+  // slots to the other streams' kernels; with slice_ticks > 0 a workgroup
+  // stops taking groups after that many ticks of the 100 MHz real-time
+  // counter, so that a long launch can be cut into several (the work queue
+  // persists between them; the last launch of a call runs without a slice).
+  const int32_t *share_word;
+  int32_t share_grid;
+  uint32_t slice_ticks;
 };
 
 // Words per bin of the global weight sums (see PairArgs::binW).
@@ -150,6 +157,10 @@ ripk_status plan_bind(ripk_plan_s *p, const ripk_plan_desc *desc, hipStream_t st
 const Caps &plan_caps(const ripk_plan_s *p);
 void plan_free(ripk_plan_s *p);
 ripk_status set_error(ripk_status s, const char *msg);  // sets ripk_last_error()
+// Served plans: device sharing and launch slicing of the pair kernel (see
+// PairArgs); slice_us = 0 turns slicing off, a null word sharing.
+void plan_set_sharing(ripk_plan_s *p, const int32_t *share_word, double share_frac,
+                      double slice_us);
 // ripk_compute_K of one rectangle set with every device buffer cut from the
 // region [scratch, scratch + scratch_bytes) of the descriptor's device;
 // outputs are device buffers (api.cpp)

@@ -4,12 +4,25 @@
 // A server owns `slots` worker threads.  Each slot has its own HIP stream
 // (non-blocking, default priority) and keeps one device workspace (a plan
 // sized by capacities) that it rebinds to every request it can hold.
-// Requests wait in a FIFO queue.  The head of the queue is admitted by the
-// first idle slot as soon as its device footprint fits the server's HBM
-// budget: the slot's own workspace if large enough, else a grown one, after
-// freeing idle slots' workspaces when the budget is short.  Admitted requests
-// run concurrently on their slots' streams, so their kernels overlap on the
-// device.  Each request is an observed K (Eq. 2-4) plus, when m > 0, its m CSR
+//
+// Admission is by size.  Each request's work is estimated at submit as
+// (m + 1) (n^2 f + 64 n), f the share of a uniform set's ordered pairs within
+// the thresholds (about the in-range pairs of the observed set and each CSR
+// simulation).  Requests above kLargeWork are large: at most one of them
+// runs at a time, oldest first, so that large requests are not stretched by
+// one another; the other slots take the smallest waiting requests first, so
+// that small ones do not queue behind large ones.  A request is admitted by
+// an idle slot when its device footprint fits the server's HBM budget: the
+// slot's own workspace if large enough, else a grown one, after releasing
+// idle slots' workspaces when the budget is short (freed outside the lock).
+//
+// Admitted requests run concurrently on their slots' streams.  A persistent
+// pair kernel would hold every compute unit until it ends, so the slots'
+// plans share the device: while more than one slot is busy (a count in host
+// memory that the kernel reads), a pair launch keeps 7/8 of its workgroups
+// and leaves the rest to the other streams, and long pair launches are cut
+// into 20 ms slices so that the other requests' kernels start between them.
+// Each request is an observed K (Eq. 2-4) plus, when m > 0, its m CSR
 // simulations and envelopes (Sec. 3); results are exact integer sums, so they
 // are the same whatever else shares the device.
 #include <hip/hip_runtime.h>
@@ -34,6 +47,9 @@ using namespace ripk;
 namespace {
 
 constexpr int kMaxSlots = 16;
+constexpr double kLargeWork = 2e10;   // pair evaluations of a large request (about 30 ms)
+constexpr double kShareFrac = 0.875;  // share of the pair kernel's grid kept while others run
+constexpr double kSliceUs = 20000.0;  // slice length of long pair launches
 
 double mono_now() {
   timespec ts;
@@ -46,6 +62,7 @@ struct Request {
   ripk_plan_desc desc{};
   Caps caps{};
   int64_t n = 0, n_centres = 0;
+  double work = 0;  // estimated pair evaluations (admission order)
   int32_t m = 0;
   uint32_t flags = 0;
   uint64_t seed = 0;
@@ -86,21 +103,44 @@ struct ripk_server_s {
   uint64_t epoch = 1;  // bumped on every submit and completion
   int64_t used = 0;    // device bytes held by slot workspaces
   bool stop = false;
+  int32_t *busy_word = nullptr;  // busy slots, in host memory the pair kernels read
+  int busy = 0;
+  int large_running = 0;
   Slot slots[kMaxSlots];
 };
 
 namespace {
 
-// Picks the queue head for slot k if its footprint fits; sets *target to the
+bool is_large(const Request *r) { return r->work > kLargeWork; }
+
+// The next request for a free slot: the oldest large request when none is
+// running, else the smallest waiting request that is not large.
+std::deque<Request *>::iterator pick(ripk_server_s *sv) {
+  auto best = sv->queue.end();
+  for (auto it = sv->queue.begin(); it != sv->queue.end(); ++it) {
+    if (is_large(*it)) {
+      if (sv->large_running == 0) return it;  // queue order: the oldest large one
+      continue;
+    }
+    if (best == sv->queue.end() || (*it)->work < (*best)->work) best = it;
+  }
+  return best;
+}
+
+// Picks a request for slot k if its footprint fits; sets *target to the
 // capacities the slot must (re)allocate, or leaves it empty for reuse.  Called
-// with the server lock held; may free idle slots' workspaces.
-Request *try_admit(ripk_server_s *sv, int k, Caps *target, bool *realloc) {
+// with the server lock held; idle slots' workspaces that must go to make room
+// are detached into *release (freed by the caller without the lock).
+Request *try_admit(ripk_server_s *sv, int k, Caps *target, bool *realloc,
+                   std::vector<ripk_plan_s *> *release) {
   if (sv->queue.empty()) return nullptr;
   Slot &me = sv->slots[k];
-  Request *r = sv->queue.front();
+  const auto it = pick(sv);
+  if (it == sv->queue.end()) return nullptr;
+  Request *r = *it;
   *realloc = false;
   if (me.plan && caps_fit(plan_caps(me.plan), r->caps)) {
-    sv->queue.pop_front();
+    sv->queue.erase(it);
     return r;
   }
   const int64_t budget = sv->desc.hbm_budget_bytes;
@@ -110,7 +150,7 @@ Request *try_admit(ripk_server_s *sv, int k, Caps *target, bool *realloc) {
     if (others + caps_bytes(grow) <= budget) {
       *target = grow;
       *realloc = true;
-      sv->queue.pop_front();
+      sv->queue.erase(it);
       return r;
     }
   }
@@ -119,7 +159,7 @@ Request *try_admit(ripk_server_s *sv, int k, Caps *target, bool *realloc) {
     for (int j = 0; j < sv->desc.slots; ++j) {
       Slot &o = sv->slots[j];
       if (j == k || o.busy || !o.plan) continue;
-      plan_free(o.plan);
+      release->push_back(o.plan);
       o.plan = nullptr;
       sv->used -= o.bytes;
       o.bytes = 0;
@@ -129,7 +169,7 @@ Request *try_admit(ripk_server_s *sv, int k, Caps *target, bool *realloc) {
   }
   *target = r->caps;
   *realloc = true;
-  sv->queue.pop_front();
+  sv->queue.erase(it);
   return r;
 }
 
@@ -216,9 +256,18 @@ void slot_main(ripk_server_s *sv, int k) {
     me.seen_epoch = sv->epoch;
     Caps target;
     bool realloc = false;
-    Request *r = try_admit(sv, k, &target, &realloc);
+    std::vector<ripk_plan_s *> release;
+    Request *r = try_admit(sv, k, &target, &realloc, &release);
+    if (!release.empty()) {
+      lk.unlock();
+      for (ripk_plan_s *pl : release) plan_free(pl);
+      lk.lock();
+    }
     if (!r) continue;
     me.busy = true;
+    const bool large = is_large(r);
+    sv->large_running += large ? 1 : 0;
+    __atomic_store_n(sv->busy_word, ++sv->busy, __ATOMIC_RELEASE);
     r->slot = k;
     r->t_admit = mono_now();
     ripk_plan_s *old = nullptr;
@@ -234,6 +283,7 @@ void slot_main(ripk_server_s *sv, int k) {
     if (realloc) {
       if (old) plan_free(old);
       st = plan_create(sv->desc.device, target, &me.plan);
+      if (st == RIPK_OK) plan_set_sharing(me.plan, sv->busy_word, kShareFrac, kSliceUs);
     }
     if (st == RIPK_OK) st = run_request(me, r);
     std::string msg = st == RIPK_OK ? std::string() : std::string(ripk_last_error());
@@ -248,6 +298,8 @@ void slot_main(ripk_server_s *sv, int k) {
     r->t_done = mono_now();
     r->done = true;
     me.busy = false;
+    sv->large_running -= large ? 1 : 0;
+    __atomic_store_n(sv->busy_word, --sv->busy, __ATOMIC_RELEASE);
     ++sv->epoch;
     sv->cv_done.notify_all();
     sv->cv_work.notify_all();
@@ -301,7 +353,13 @@ ripk_status ripk_server_create(const ripk_server_desc *desc, ripk_server_t *out)
   ripk_server_s *sv = new ripk_server_s();
   sv->desc = *desc;
   ripk_status st = RIPK_OK;
-  for (int k = 0; k < desc->slots; ++k)
+  if (hipHostMalloc((void **)&sv->busy_word, sizeof(int32_t), hipHostMallocCoherent) != hipSuccess) {
+    sv->busy_word = nullptr;
+    st = set_error(RIPK_ENOMEM, "pinned allocation failed");
+  } else {
+    *sv->busy_word = 0;
+  }
+  for (int k = 0; k < desc->slots && st == RIPK_OK; ++k)
     if (hipStreamCreateWithFlags(&sv->slots[k].stream, hipStreamNonBlocking) != hipSuccess) {
       st = set_error(RIPK_EDEVICE, "stream creation failed");
       break;
@@ -310,6 +368,7 @@ ripk_status ripk_server_create(const ripk_server_desc *desc, ripk_server_t *out)
   if (st != RIPK_OK) {
     for (int k = 0; k < desc->slots; ++k)
       if (sv->slots[k].stream) (void)hipStreamDestroy(sv->slots[k].stream);
+    if (sv->busy_word) (void)hipHostFree(sv->busy_word);
     delete sv;
     return st;
   }
@@ -343,6 +402,7 @@ void ripk_server_destroy(ripk_server_t sv) {
     if (s.stage) (void)hipHostFree(s.stage);
     if (s.stream) (void)hipStreamDestroy(s.stream);
   }
+  if (sv->busy_word) (void)hipHostFree(sv->busy_word);
   (void)hipSetDevice(prev);
   for (auto &kv : sv->all) delete kv.second;
   delete sv;
@@ -377,6 +437,14 @@ ripk_status ripk_submit(ripk_server_t sv, const ripk_request *req, uint64_t *tic
   }
   r->n = p.n;
   r->n_centres = p.n_centres;
+  {
+    // in-range share of a uniform set's ordered pairs (Sec. 3 thresholds)
+    const double A = (double)(r->desc.x1 - r->desc.x0) * (double)(r->desc.y1 - r->desc.y0);
+    const double D = (double)(r->desc.t1 - r->desc.t0);
+    const double f = std::min(1.0, 3.141592653589793 * (double)r->desc.s_max * r->desc.s_max / A) *
+                     std::min(1.0, 2.0 * (double)r->desc.t_max / D);
+    r->work = (double)(req->m + 1) * ((double)p.n * (double)p.n * f + 64.0 * (double)p.n);
+  }
   r->m = req->m;
   r->flags = req->flags;
   r->seed = req->seed;
