@@ -92,14 +92,22 @@ def cpu_baseline(cfg, x, y, t, target_s):
             "one_thread": one}
 
 
-def serving(ripk, workloads, n_req, slots, load):
+# the server configuration the serving leg reports (ripk_server_desc fields)
+SERVER = {"admission": 1, "large_work": 2e10, "age_ms": 1000.0, "max_large": 2,
+          "device_share": 0.9375, "slice_ms": 20.0}
+
+
+def serving(ripk, workloads, n_req, slots, load, cap_n=200, variants=()):
     """The request stream served two ways on the same arrival schedule: the plain
     path (one request at a time, in arrival order: a plan, ripk_compute_K and
     ripk_simulate_envelope each) and the server (continuous batching over
-    `slots` streams).  Arrivals are Poisson at `load` x the plain path's measured
-    capacity; latency = completion - scheduled arrival."""
+    `slots` streams).  Arrivals are Poisson at `load` x the plain path's
+    capacity, measured on the first `cap_n` requests; latency = completion -
+    scheduled arrival.  The server's own capacity is the first `cap_n`
+    requests submitted at once."""
     import numpy as np
     reqs = workloads.serving_requests(num=n_req)
+    cap_n = min(cap_n, n_req)
     pts = [workloads.request_points(r) for r in reqs]
     descs = [ripk.make_desc(r["window"], r["s_max"], r["t_max"], r["n_s"], r["n_t"],
                             n_max=len(p[0]), m_max=r["sims"]) for r, p in zip(reqs, pts)]
@@ -119,8 +127,11 @@ def serving(ripk, workloads, n_req, slots, load):
 
     plain_one(0)  # warm-up
     t0 = time.monotonic()
-    n_in_total = sum(plain_one(i) for i in range(n_req))
-    capacity = n_req / (time.monotonic() - t0)
+    for i in range(cap_n):
+        plain_one(i)
+    capacity = cap_n / (time.monotonic() - t0)
+    print(f"serving: plain capacity {capacity:.2f} requests/s on {cap_n}", file=sys.stderr,
+          flush=True)
     rate = load * capacity
     gaps = np.random.Generator(np.random.PCG64(55)).exponential(1.0 / rate, n_req)
     offs = np.cumsum(gaps) - gaps[0]
@@ -132,47 +143,57 @@ def serving(ripk, workloads, n_req, slots, load):
 
     # plain path on the arrival schedule
     start = time.monotonic() + 0.05
-    lat_plain, end_plain = [], start
+    lat_plain, end_plain, n_in_total = [], start, 0
     for i in range(n_req):
         a = start + offs[i]
         wait_until(a)
-        plain_one(i)
+        n_in_total += plain_one(i)
         end_plain = time.monotonic()
         lat_plain.append(end_plain - a)
+        if (i + 1) % 250 == 0:
+            print(f"serving: plain {i + 1}/{n_req}", file=sys.stderr, flush=True)
     span_plain = end_plain - start
 
-    # server on the same schedule
-    sv = ripk.ripk_server_create(slots=slots, queue_cap=n_req, hbm_budget_bytes=64 << 30)
-    tickets = [None] * n_req
-    ready = [threading.Event() for _ in range(n_req)]
-    start = time.monotonic() + 0.05
+    def replay(cfg, burst):
+        """The server with configuration cfg on the same schedule; with burst,
+        its capacity on the first cap_n requests submitted at once."""
+        sv = ripk.ripk_server_create(slots=slots, queue_cap=n_req, hbm_budget_bytes=64 << 30,
+                                     **cfg)
+        tickets = [None] * n_req
+        ready = [threading.Event() for _ in range(n_req)]
+        start = time.monotonic() + 0.05
 
-    def submitter():
+        def submitter():
+            for i in range(n_req):
+                wait_until(start + offs[i])
+                r, (x, y, t) = reqs[i], pts[i]
+                tickets[i] = ripk.ripk_submit(sv, descs[i], x, y, t, m=r["sims"], seed=r["seed"])
+                ready[i].set()
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        lat_srv, end_srv, n_in_srv = [], start, 0
         for i in range(n_req):
-            wait_until(start + offs[i])
-            r, (x, y, t) = reqs[i], pts[i]
-            tickets[i] = ripk.ripk_submit(sv, descs[i], x, y, t, m=r["sims"], seed=r["seed"])
-            ready[i].set()
+            ready[i].wait()
+            res = ripk.ripk_poll(sv, tickets[i], timeout_ms=-1)
+            lat_srv.append(res["t_done"] - (start + offs[i]))
+            end_srv = max(end_srv, res["t_done"])
+            n_in_srv += res["n_in"]
+            if (i + 1) % 250 == 0:
+                print(f"serving: served {i + 1}/{n_req}", file=sys.stderr, flush=True)
+        th.join()
+        assert n_in_srv == n_in_total
+        cap = None
+        if burst:
+            t_burst = time.monotonic()
+            tks = [ripk.ripk_submit(sv, descs[i], *pts[i], m=reqs[i]["sims"],
+                                    seed=reqs[i]["seed"]) for i in range(cap_n)]
+            end_burst = max(ripk.ripk_poll(sv, tk, timeout_ms=-1)["t_done"] for tk in tks)
+            cap = cap_n / (end_burst - t_burst)
+        sv.destroy()
+        return lat_srv, end_srv - start, cap
 
-    th = threading.Thread(target=submitter)
-    th.start()
-    lat_srv, end_srv, n_in_srv = [], start, 0
-    for i in range(n_req):
-        ready[i].wait()
-        res = ripk.ripk_poll(sv, tickets[i], timeout_ms=-1)
-        lat_srv.append(res["t_done"] - (start + offs[i]))
-        end_srv = max(end_srv, res["t_done"])
-        n_in_srv += res["n_in"]
-    th.join()
-    span_srv = end_srv - start
-    assert n_in_srv == n_in_total
-    # capacity of the server: the whole stream submitted at once
-    t_burst = time.monotonic()
-    burst = [ripk.ripk_submit(sv, descs[i], *pts[i], m=reqs[i]["sims"], seed=reqs[i]["seed"])
-             for i in range(n_req)]
-    end_burst = max(ripk.ripk_poll(sv, tk, timeout_ms=-1)["t_done"] for tk in burst)
-    served_capacity = n_req / (end_burst - t_burst)
-    sv.destroy()
+    lat_srv, span_srv, served_capacity = replay(SERVER, True)
 
     def summary(lat, span):
         lat = np.sort(np.asarray(lat)) * 1e3
@@ -180,14 +201,24 @@ def serving(ripk, workloads, n_req, slots, load):
                 "p99_ms": round(float(np.percentile(lat, 99)), 2),
                 "pair_tests_per_s_G": round(n_in_total / span / 1e9, 3)}
 
-    return {"requests": n_req, "load": load, "rate_per_s": round(rate, 3),
+    plain, served = summary(lat_plain, span_plain), summary(lat_srv, span_srv)
+    others = []
+    for cfg in variants:
+        lat_v, span_v, _ = replay(cfg, False)
+        sm = summary(lat_v, span_v)
+        others.append({"server": cfg, **sm,
+                       "over_plain": {"p50": round(sm["p50_ms"] / plain["p50_ms"], 3),
+                                      "p99": round(sm["p99_ms"] / plain["p99_ms"], 3)}})
+    return {"requests": n_req, "of_stream": 5000, "load": load, "rate_per_s": round(rate, 3),
             "plain_capacity_per_s": round(capacity, 3),
-            "served_capacity_per_s": round(served_capacity, 3), "slots": slots,
-            "n_in": int(n_in_total),
-            "plain": summary(lat_plain, span_plain), "served": summary(lat_srv, span_srv),
+            "served_capacity_per_s": round(served_capacity, 3), "capacity_requests": cap_n,
+            "slots": slots, "n_in": int(n_in_total), "server": SERVER,
+            "plain": plain, "served": served, "variants": others,
+            "served_over_plain": {"p50": round(served["p50_ms"] / plain["p50_ms"], 3),
+                                  "p99": round(served["p99_ms"] / plain["p99_ms"], 3)},
             "note": "request stream: n log-uniform [1e3, 5e5], uniform or Thomas, own window "
                     "and grid, 0-99 CSR sims; host points in, H2D included; plain path "
-                    "creates a plan per request"}
+                    "creates a plan per request; capacities on the first capacity_requests"}
 
 
 def copy_calibration(torch):
@@ -206,8 +237,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--serve-requests", type=int, default=300,
-                    help="requests of the serving stream (0 = skip the serving leg)")
+    ap.add_argument("--serve-requests", type=int, default=1000,
+                    help="requests of the 5,000-request serving stream (0 = skip the serving "
+                         "leg)")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="run the serving leg alone and print its JSON object")
+    ap.add_argument("--serve-variants", default="",
+                    help="--serve-only: JSON list of further server configurations "
+                         "(ripk_server_desc fields) replayed on the same schedule")
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-load", type=float, default=0.7)
     ap.add_argument("--no-autotune", action="store_true",
@@ -228,6 +265,12 @@ def main():
     from paper_1912_04753_amd import ripk, workloads
 
     torch.cuda.set_device(0)
+    if args.serve_only:
+        variants = json.loads(args.serve_variants) if args.serve_variants else ()
+        print(json.dumps({"serving": serving(ripk, workloads, args.serve_requests,
+                                             args.serve_slots, args.serve_load,
+                                             variants=variants)}), flush=True)
+        return
     dev = ripk.ripk_device_query(0)
     PEAK["lane_ops"] = dev["compute_units"] * 64 * dev["clock_khz"] * 1e3
     if args.copy_calibration:

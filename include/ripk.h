@@ -390,12 +390,31 @@ ripk_status ripk_plan_set_flush_bound(ripk_plan_t plan, int64_t candidates);
  */
 typedef struct ripk_server_s *ripk_server_t;
 
+/* Admission orders.  FIFO: the oldest waiting request first.  SIZE: each
+ * request's work is estimated at submit as (m + 1)(n^2 f + 64 n), f the share
+ * of a uniform set's ordered pairs within the thresholds; a request above
+ * large_work is large.  A free slot takes the oldest request that has waited
+ * longer than age_ms, else the oldest large request while fewer than
+ * max_large are running, else the smallest waiting request that is not
+ * large.  Either way a request is admitted once its device footprint fits
+ * the HBM budget. */
+enum { RIPK_ADMIT_FIFO = 0, RIPK_ADMIT_SIZE = 1 };
+
 typedef struct {
   int32_t device;            /* HIP device ordinal                                     */
   int32_t slots;             /* requests evaluated concurrently, 1..16                 */
   int32_t queue_cap;         /* requests that may wait for admission, >= 1             */
-  int32_t reserved;          /* set to 0                                               */
+  uint32_t admission;        /* RIPK_ADMIT_*                                           */
   int64_t hbm_budget_bytes;  /* device bytes all slot workspaces may hold together     */
+  double large_work;         /* SIZE: work above which a request is large (0: 2e10)    */
+  double age_ms;             /* SIZE: wait after which a request goes first (0: none)  */
+  int32_t max_large;         /* SIZE: large requests running at once (0: no limit)     */
+  float device_share;        /* share of a pair launch's workgroups kept while other   */
+                             /* slots are busy, in (0, 1] (0: 1, no sharing)           */
+  float slice_ms;            /* pair launches of a request are cut into slices of this */
+                             /* length (0: none); the other slots' kernels start       */
+                             /* between slices                                         */
+  int32_t reserved;          /* set to 0                                               */
 } ripk_server_desc;
 
 #define RIPK_REQ_KEEP_SIMS (1u << 0) /* keep per-simulation C, W, K for ripk_poll */

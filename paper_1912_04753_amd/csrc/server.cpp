@@ -5,23 +5,26 @@
 // (non-blocking, default priority) and keeps one device workspace (a plan
 // sized by capacities) that it rebinds to every request it can hold.
 //
-// Admission is by size.  Each request's work is estimated at submit as
-// (m + 1) (n^2 f + 64 n), f the share of a uniform set's ordered pairs within
-// the thresholds (about the in-range pairs of the observed set and each CSR
-// simulation).  Requests above kLargeWork are large: at most one of them
-// runs at a time, oldest first, so that large requests are not stretched by
-// one another; the other slots take the smallest waiting requests first, so
-// that small ones do not queue behind large ones.  A request is admitted by
-// an idle slot when its device footprint fits the server's HBM budget: the
-// slot's own workspace if large enough, else a grown one, after releasing
-// idle slots' workspaces when the budget is short (freed outside the lock).
+// Admission (ripk_server_desc.admission) is first come first served, or by
+// size: each request's work is estimated at submit as (m + 1) (n^2 f + 64 n),
+// f the share of a uniform set's ordered pairs within the thresholds (about
+// the in-range pairs of the observed set and each CSR simulation).  Requests
+// above large_work are large; a free slot takes a request that has waited
+// longer than age_ms first (oldest first), then the oldest large request while
+// fewer than max_large run, then the smallest waiting request that is not
+// large, so that small requests do not queue behind large ones.  A request is
+// admitted by an idle slot when its device footprint fits the server's HBM
+// budget: the slot's own workspace if large enough, else a grown one, after
+// releasing idle slots' workspaces when the budget is short (freed outside
+// the lock).
 //
 // Admitted requests run concurrently on their slots' streams.  A persistent
-// pair kernel would hold every compute unit until it ends, so the slots'
-// plans share the device: while more than one slot is busy (a count in host
-// memory that the kernel reads), a pair launch keeps 7/8 of its workgroups
-// and leaves the rest to the other streams, and long pair launches are cut
-// into 20 ms slices so that the other requests' kernels start between them.
+// pair kernel holds every compute unit it gets until it ends; with
+// device_share < 1 a pair launch keeps that share of its workgroups while
+// more than one slot is busy (a count in host memory that the kernel reads),
+// leaving the rest to the other streams, and with slice_ms long pair launches
+// are cut into slices, so that the other requests' kernels start between
+// them and the share is taken afresh.
 // Each request is an observed K (Eq. 2-4) plus, when m > 0, its m CSR
 // simulations and envelopes (Sec. 3); results are exact integer sums, so they
 // are the same whatever else shares the device.
@@ -47,9 +50,7 @@ using namespace ripk;
 namespace {
 
 constexpr int kMaxSlots = 16;
-constexpr double kLargeWork = 2e10;   // pair evaluations of a large request (about 30 ms)
-constexpr double kShareFrac = 0.875;  // share of the pair kernel's grid kept while others run
-constexpr double kSliceUs = 20000.0;  // slice length of long pair launches
+constexpr double kLargeWorkDefault = 2e10;  // pair evaluations of a large request (~30 ms)
 
 double mono_now() {
   timespec ts;
@@ -111,19 +112,28 @@ struct ripk_server_s {
 
 namespace {
 
-bool is_large(const Request *r) { return r->work > kLargeWork; }
+bool is_large(const ripk_server_s *sv, const Request *r) {
+  const double lw = sv->desc.large_work > 0 ? sv->desc.large_work : kLargeWorkDefault;
+  return sv->desc.admission == RIPK_ADMIT_SIZE && r->work > lw;
+}
 
-// The next request for a free slot: the oldest large request when none is
-// running, else the smallest waiting request that is not large.
+// The next request for a free slot (see the admission orders above).
 std::deque<Request *>::iterator pick(ripk_server_s *sv) {
-  auto best = sv->queue.end();
+  if (sv->desc.admission != RIPK_ADMIT_SIZE) return sv->queue.begin();
+  const double now = mono_now();
+  const double age = sv->desc.age_ms * 1e-3;
+  auto best = sv->queue.end(), large = sv->queue.end();
   for (auto it = sv->queue.begin(); it != sv->queue.end(); ++it) {
-    if (is_large(*it)) {
-      if (sv->large_running == 0) return it;  // queue order: the oldest large one
+    if (age > 0 && now - (*it)->t_submit > age) return it;  // queue order: the oldest
+    if (is_large(sv, *it)) {
+      if (large == sv->queue.end()) large = it;
       continue;
     }
     if (best == sv->queue.end() || (*it)->work < (*best)->work) best = it;
   }
+  if (large != sv->queue.end() &&
+      (sv->desc.max_large <= 0 || sv->large_running < sv->desc.max_large))
+    return large;
   return best;
 }
 
@@ -265,7 +275,7 @@ void slot_main(ripk_server_s *sv, int k) {
     }
     if (!r) continue;
     me.busy = true;
-    const bool large = is_large(r);
+    const bool large = is_large(sv, r);
     sv->large_running += large ? 1 : 0;
     __atomic_store_n(sv->busy_word, ++sv->busy, __ATOMIC_RELEASE);
     r->slot = k;
@@ -283,7 +293,10 @@ void slot_main(ripk_server_s *sv, int k) {
     if (realloc) {
       if (old) plan_free(old);
       st = plan_create(sv->desc.device, target, &me.plan);
-      if (st == RIPK_OK) plan_set_sharing(me.plan, sv->busy_word, kShareFrac, kSliceUs);
+      if (st == RIPK_OK && (sv->desc.device_share > 0.f || sv->desc.slice_ms > 0.f))
+        plan_set_sharing(me.plan, sv->desc.device_share > 0.f ? sv->busy_word : nullptr,
+                         sv->desc.device_share > 0.f ? sv->desc.device_share : 1.0,
+                         1e3 * (double)sv->desc.slice_ms);
     }
     if (st == RIPK_OK) st = run_request(me, r);
     std::string msg = st == RIPK_OK ? std::string() : std::string(ripk_last_error());
@@ -344,6 +357,13 @@ ripk_status ripk_server_create(const ripk_server_desc *desc, ripk_server_t *out)
   if (desc->slots < 1 || desc->slots > kMaxSlots) return set_error(RIPK_EINVAL, "slots must be in [1, 16]");
   if (desc->queue_cap < 1) return set_error(RIPK_EINVAL, "queue_cap must be >= 1");
   if (desc->hbm_budget_bytes < 1) return set_error(RIPK_EINVAL, "hbm_budget_bytes must be >= 1");
+  if (desc->admission > RIPK_ADMIT_SIZE) return set_error(RIPK_EINVAL, "unknown admission order");
+  if (!(desc->large_work >= 0) || !(desc->age_ms >= 0) || desc->max_large < 0 ||
+      !(desc->device_share >= 0.f && desc->device_share <= 1.f) || !(desc->slice_ms >= 0.f) ||
+      desc->reserved != 0)
+    return set_error(RIPK_EINVAL,
+                     "bad admission or sharing parameters (large_work, age_ms, max_large >= 0; "
+                     "device_share in [0, 1]; slice_ms >= 0; reserved 0)");
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return set_error(RIPK_EDEVICE, "no HIP device available");
   if (desc->device < 0 || desc->device >= ndev) return set_error(RIPK_EINVAL, "device out of range");

@@ -95,8 +95,10 @@ class Stats(ctypes.Structure):
 
 
 class ServerDesc(ctypes.Structure):
-    _fields_ = [("device", _i32), ("slots", _i32), ("queue_cap", _i32), ("reserved", _i32),
-                ("hbm_budget_bytes", _i64)]
+    _fields_ = [("device", _i32), ("slots", _i32), ("queue_cap", _i32), ("admission", _u32),
+                ("hbm_budget_bytes", _i64), ("large_work", _f64), ("age_ms", _f64),
+                ("max_large", _i32), ("device_share", ctypes.c_float),
+                ("slice_ms", ctypes.c_float), ("reserved", _i32)]
 
 
 class Request(ctypes.Structure):
@@ -461,8 +463,15 @@ class Server:
             pass
 
 
-def ripk_server_create(device=0, slots=4, queue_cap=4096, hbm_budget_bytes=64 << 30):
-    d = ServerDesc(int(device), int(slots), int(queue_cap), 0, int(hbm_budget_bytes))
+RIPK_ADMIT_FIFO, RIPK_ADMIT_SIZE = 0, 1
+
+
+def ripk_server_create(device=0, slots=4, queue_cap=4096, hbm_budget_bytes=64 << 30,
+                       admission=RIPK_ADMIT_FIFO, large_work=0.0, age_ms=0.0, max_large=0,
+                       device_share=0.0, slice_ms=0.0):
+    d = ServerDesc(int(device), int(slots), int(queue_cap), int(admission),
+                   int(hbm_budget_bytes), float(large_work), float(age_ms), int(max_large),
+                   float(device_share), float(slice_ms), 0)
     h = ctypes.c_void_p()
     _check(lib().ripk_server_create(ctypes.byref(d), ctypes.byref(h)), "ripk_server_create")
     return Server(h)

@@ -117,7 +117,7 @@ def test_status_strings():
 
 
 def test_server_structs_and_argument_checks():
-    assert ctypes.sizeof(ripk.ServerDesc) == 4 * 4 + 8
+    assert ctypes.sizeof(ripk.ServerDesc) == 4 * 4 + 8 + 2 * 8 + 4 * 4
     assert ctypes.sizeof(ripk.Request) == ctypes.sizeof(ripk.PlanDesc) + ctypes.sizeof(ripk.Points) + 16
     assert ctypes.sizeof(ripk.Result) == 4 * 8 + 8 * 8 + 4 + 4 + 3 * 8 + 8
     for slots in (0, 17):
@@ -127,6 +127,12 @@ def test_server_structs_and_argument_checks():
     with pytest.raises(ripk.RipkError) as e:
         ripk.ripk_server_create(hbm_budget_bytes=0)
     assert e.value.status == ripk.RIPK_EINVAL
+    for bad in (dict(admission=2), dict(device_share=1.5), dict(device_share=-0.5),
+                dict(slice_ms=-1.0), dict(max_large=-1), dict(age_ms=-1.0),
+                dict(large_work=float("nan"))):
+        with pytest.raises(ripk.RipkError) as e:
+            ripk.ripk_server_create(**bad)
+        assert e.value.status == ripk.RIPK_EINVAL, bad
 
 
 def _simple_brute(P):

@@ -86,6 +86,21 @@ def run_server(reqs, keep_sims=False, **kw):
     return out, state
 
 
+def test_size_admission_sharing_and_slices_equal_alone():
+    """Size-ordered admission (most requests large, one large at a time, aging)
+    with device sharing at half the grid and pair launches cut into 50 us
+    slices (several slices per request): every result bit-identical to the
+    plain path, since slices and shares only change which workgroup takes
+    which group of work items."""
+    reqs = make_requests(16, seed=13)
+    say("16 requests, sharing and slices")
+    served, state = run_server(reqs, slots=4, admission=ripk.RIPK_ADMIT_SIZE, large_work=1e7,
+                               age_ms=200.0, max_large=1, device_share=0.5, slice_ms=0.05)
+    assert state["queued"] == 0 and state["unpolled"] == 0
+    for i, (q, r) in enumerate(zip(reqs, served)):
+        same(r, plain(q), f"request {i}")
+
+
 def test_mix_equals_alone_and_oracle():
     reqs = make_requests(24, seed=11)
     say("24 requests, n", [len(q["x"]) for q in reqs])
