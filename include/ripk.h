@@ -210,6 +210,10 @@ typedef struct {
   int32_t dist_mode;       /* distance test: 0 packed 16-bit, 1 32-bit, 2 64-bit squares */
   int32_t n_bins;          /* n_s*n_t                                                    */
   int64_t device_bytes;    /* device memory a plan of this descriptor allocates          */
+  int32_t near_edges_max;  /* polygon study areas: most boundary edges listed for one
+                              xy-cell (edges within s_max of it; 33 = more than 32, and
+                              such a cell scans every edge); 0 for the rectangle          */
+  int32_t near_cells;      /* polygon study areas: xy-cells with a nonempty edge list    */
 } ripk_plan_info;
 
 /* A point set in structure-of-arrays form.  Points [0, n_centres) act as

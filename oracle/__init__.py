@@ -25,7 +25,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liboracle.so")
+# RIPK_ORACLE_LIB names another build of oracle.c (the sanitizer build of the
+# CPU tests)
+LIB_PATH = os.environ.get("RIPK_ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
 
 EDGE_SPATIAL = 1
 EDGE_TEMPORAL = 2

@@ -187,6 +187,18 @@ void build_near(const Layout &L, int64_t s_max, std::vector<uint16_t> *out) {
   }
 }
 
+// The longest list (kNearMax + 1 for "every edge") and the cells with a list.
+void near_summary(const std::vector<uint16_t> &near, ripk_plan_info *info) {
+  int mx = 0, cells = 0;
+  for (size_t c = 0; c < near.size(); c += kNearMax + 1) {
+    const int k = near[c] == kNearAll ? kNearMax + 1 : (int)near[c];
+    mx = std::max(mx, k);
+    cells += k > 0 ? 1 : 0;
+  }
+  info->near_edges_max = mx;
+  info->near_cells = cells;
+}
+
 }  // namespace
 
 namespace ripk {
@@ -923,6 +935,7 @@ ripk_status bind_geometry(ripk_plan_s *p, const ripk_plan_desc *desc, hipStream_
   HIPCHK(hipMemcpyAsync(p->T, p->Th, sizeof p->Th, hipMemcpyHostToDevice, stream));
   if (!p->lay.V.empty()) {
     build_near(p->lay, desc->s_max, &p->nearh);
+    near_summary(p->nearh, &p->lay.info);
     HIPCHK(hipMemcpyAsync(p->poly, p->lay.V.data(), sizeof(int2) * p->lay.V.size(),
                           hipMemcpyHostToDevice, stream));
     HIPCHK(hipMemcpyAsync(p->near, p->nearh.data(), sizeof(uint16_t) * p->nearh.size(),
@@ -1156,6 +1169,12 @@ ripk_status ripk_plan_check(const ripk_plan_desc *desc, ripk_plan_info *info) {
   Layout L;
   ripk_status s = derive(desc, &L);
   if (s != RIPK_OK) return s;
+  if (!L.V.empty()) {
+    // the per-cell edge lists a plan of this geometry builds (host only)
+    std::vector<uint16_t> near;
+    build_near(L, desc->s_max, &near);
+    near_summary(near, &L.info);
+  }
   if (info) *info = L.info;
   return RIPK_OK;
 }

@@ -13,7 +13,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libripk.so")
+# RIPK_LIB names another build of the same library (the host-sanitizer build
+# of the CPU tests)
+LIB_PATH = os.environ.get("RIPK_LIB") or os.path.join(HERE, "libripk.so")
 
 RIPK_OK = 0
 RIPK_PENDING = 1
@@ -63,7 +65,7 @@ class PlanInfo(ctypes.Structure):
     _fields_ = [("S2", _i64 * 64), ("T", _i64 * 64), ("cell_s", _i64), ("cell_t", _i64),
                 ("nx", _i32), ("ny", _i32), ("nt", _i32), ("reach_s", _i32),
                 ("reach_t", _i32), ("n_cells", _i64), ("dist_mode", _i32), ("n_bins", _i32),
-                ("device_bytes", _i64)]
+                ("device_bytes", _i64), ("near_edges_max", _i32), ("near_cells", _i32)]
 
 
 class Points(ctypes.Structure):
@@ -212,7 +214,8 @@ def _info_dict(info, desc):
             "cell_s": info.cell_s, "cell_t": info.cell_t, "nx": info.nx, "ny": info.ny,
             "nt": info.nt, "reach_s": info.reach_s, "reach_t": info.reach_t,
             "n_cells": info.n_cells, "dist_mode": info.dist_mode, "n_bins": info.n_bins,
-            "device_bytes": info.device_bytes}
+            "device_bytes": info.device_bytes, "near_edges_max": info.near_edges_max,
+            "near_cells": info.near_cells}
 
 
 def ripk_plan_check(desc):

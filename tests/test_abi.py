@@ -193,3 +193,26 @@ def test_polygon_validation_matches_brute_force():
         assert got == want, (trial, P)
         seen[want] += 1
     assert seen[True] > 30 and seen[False] > 30
+
+
+def test_polygon_edge_lists_reported():
+    """ripk_plan_check builds a polygon plan's per-cell edge lists on the host:
+    the 85-vertex boundary lists a few edges per cell near it; a comb whose
+    teeth crowd one cell lists more than 32 there (every edge is scanned)."""
+    from paper_1912_04753_amd import workloads
+    c = workloads.workload("polygon-100k-99csr")
+    P = workloads.polygon_of(c)
+    info = ripk.ripk_plan_check(ripk.make_desc(c["window"], c["s_max"], c["t_max"], c["n_s"],
+                                               c["n_t"], n_max=10, poly=P))
+    assert 1 <= info["near_edges_max"] <= 32
+    assert 0 < info["near_cells"] < info["nx"] * info["ny"]
+    comb = [(0, 0), (4000, 0)] + [p for k in range(40)
+                                  for p in ((4000 - 50 * k, 3000), (3975 - 50 * k, 3000),
+                                            (3975 - 50 * k, 100), (3950 - 50 * k, 100))][:-1] + \
+           [(0, 3000)]
+    info = ripk.ripk_plan_check(ripk.make_desc((0, 0, 4000, 4000, 0, 1000), 400, 100, 4, 2,
+                                               n_max=10, poly=comb))
+    assert info["near_edges_max"] == 33
+    rect = ripk.ripk_plan_check(ripk.make_desc(c["window"], c["s_max"], c["t_max"], c["n_s"],
+                                               c["n_t"], n_max=10))
+    assert rect["near_edges_max"] == 0 and rect["near_cells"] == 0
