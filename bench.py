@@ -502,7 +502,7 @@ def main():
             else:
                 ripk.ripk_compute_K_envelope(wplan, wx, wy, wt, wm, wc["seed"], stream=stream)
             b = ripk.ripk_plan_stats(wplan)
-            return b["n_in"], time.perf_counter() - t1, b
+            return b["n_in"], time.perf_counter() - t1, dict(b)
 
         wstep()  # tuning
         torch.cuda.synchronize()
@@ -517,7 +517,10 @@ def main():
                          "sims_per_s": round(wm / (sum(v[1] for v in ws) / reps), 3) if wm else None,
                          "cells_m_s": [wi["cell_s"], wi["cell_t"]],
                          "split": ripk.ripk_plan_stats(wplan)["split"],
-                         "roofline": leg_roof(ws[0][2], sum(v[2]["us_pair"] for v in ws) / reps)}
+                         "roofline": leg_roof(ws[0][2], sum(v[2]["us_pair"] for v in ws) / reps),
+                         "cost_ordered": ws[0][2]["cost_ordered"],
+                         "workgroup_end_us": {k: round(ws[-1][2]["us_wg_end_" + k], 1)
+                                              for k in ("median", "p90", "max")}}
         wplan.destroy()
         del wx, wy, wt
     plan.destroy()

@@ -98,6 +98,18 @@ enum {
                                         /* extension named in Sec. 7: see below         */
 #define RIPK_PLAN_INHOM (1u << 6)       /* inhomogeneous K, the second extension named  */
                                         /* in Sec. 7: see below                         */
+#define RIPK_PLAN_COST_ORDER (1u << 8)  /* a launch whose work items are split (few    */
+                                        /* sets) hands out its groups of items in      */
+                                        /* descending order of estimated candidates,   */
+                                        /* dealt over the work-queue partitions, so    */
+                                        /* that dense clusters do not end the launch   */
+                                        /* (costs a sort of the groups; taken when     */
+                                        /* they are fewer than the launch's points).   */
+                                        /* Without this                                */
+                                        /* flag an autotuned plan times its chosen     */
+                                        /* single-set geometry with and without the    */
+                                        /* order and keeps the faster; results do not  */
+                                        /* depend on it                                */
 #define RIPK_PLAN_SPLIT_RUNS (1u << 7)  /* a single-set launch that wants more work     */
                                         /* items than stencil rows also cuts each row's */
                                         /* neighbour run into equal fractions (uneven,  */
@@ -265,6 +277,13 @@ typedef struct {
                               (polygon weights, inhomogeneous K)                         */
   double us_total;         /* wall time of the call, microseconds                        */
   double us_gen, us_grid, us_pair, us_finalize; /* device phases (RIPK_PLAN_TIMING)      */
+  /* RIPK_PLAN_TIMING: when the pair kernel's workgroups ended, microseconds after
+   * the first one started (the device's 100 MHz real-time counter): median, 90th
+   * percentile and last; and the groups of the work list, 1 if they were handed
+   * out in descending order of estimated cost                                    */
+  double us_wg_end_median, us_wg_end_p90, us_wg_end_max;
+  int32_t cost_ordered;
+  int32_t reserved;
 } ripk_stats;
 
 /* Validate a descriptor and derive its geometry; host only, no device use.
@@ -322,8 +341,8 @@ ripk_status ripk_compute_K_envelope(ripk_plan_t plan, const ripk_points *pts, in
  * call clears what it needs cleared.
  *
  *  - desc: a rectangle study area (poly_n = 0), one point type, no
- *    intensities: flags may hold RIPK_PLAN_ORDERED, RIPK_PLAN_WIDE_COUNTS and
- *    RIPK_PLAN_SPLIT_RUNS only; cell_div/tcell_div as in ripk_plan (no
+ *    intensities: flags may hold RIPK_PLAN_ORDERED, RIPK_PLAN_WIDE_COUNTS,
+ *    RIPK_PLAN_SPLIT_RUNS and RIPK_PLAN_COST_ORDER only; cell_div/tcell_div as in ripk_plan (no
  *    autotuning); n_max and m_max are ignored (the call is sized by pts->n).
  *  - pts: as for ripk_compute_K (host or device coordinates; n_centres as
  *    there; lambda ignored).

@@ -302,7 +302,7 @@ ripk_status derive(const ripk_plan_desc *d, Layout *L) {
   if (d->norm > RIPK_NORM_N2) return fail(RIPK_EINVAL, "unknown normalisation");
   if (d->flags & ~(RIPK_PLAN_ORDERED | RIPK_PLAN_TIMING | RIPK_PLAN_WIDE_COUNTS |
                    RIPK_PLAN_AUTOTUNE | RIPK_PLAN_GRAPH | RIPK_PLAN_CROSS | RIPK_PLAN_INHOM |
-                   RIPK_PLAN_SPLIT_RUNS))
+                   RIPK_PLAN_SPLIT_RUNS | RIPK_PLAN_COST_ORDER))
     return fail(RIPK_EINVAL, "unknown plan flags");
   if ((d->flags & RIPK_PLAN_INHOM) && ((d->flags & RIPK_PLAN_CROSS) || d->poly_n != 0))
     return fail(RIPK_EINVAL, "inhomogeneous K plans take one point type and the rectangle");
@@ -407,6 +407,7 @@ struct TuneState {
   bool done = false;
   int32_t cd = 1, td = 1;
   bool split_runs = false;
+  bool cost_order = false;
   double us[2 * kTuneN] = {};
 };
 
@@ -418,6 +419,7 @@ struct ripk_plan_s {
   Layout lay;
   int32_t bound_cd = 1, bound_td = 1;  // cell subdivisions of the bound geometry
   bool split_runs = false;             // run fractions for this call's launch
+  bool cost_order = false;             // cost-ordered work list for this call's launch
   uint64_t flush_evals = 0;            // ripk_plan_set_flush_bound (0: default)
   // served plans (plan_set_sharing): host-visible count of busy slots, the
   // share of the pair kernel's grid kept while others are busy, and the
@@ -465,6 +467,9 @@ struct ripk_plan_s {
   // a call's scalars and result rows, packed on the device and brought to
   // pinned host memory in one copy (kScalWords + kPackRows * n_bins words)
   unsigned long long *dstage = nullptr;
+  // RIPK_PLAN_TIMING: start and end of every pair-kernel workgroup (2 words
+  // each, up to kMaxWgPerCu per compute unit)
+  unsigned long long *wg_times = nullptr;
   unsigned long long *hstage = nullptr;
   hipEvent_t ev[6] = {};
   ripk_stats stats{};
@@ -486,7 +491,8 @@ void release(ripk_plan_s *p) {
                   p->vals[1],
                   p->sort_temp, p->cs, p->P, p->chunks, p->offs, p->set_base, p->scan_temp,
                   p->items, p->binC, p->binW, p->outC, p->outW, p->outK, p->outL, p->env,
-                  p->Lobs, p->S2, p->T, p->poly, p->near, p->lam, p->rho, p->scal, p->dstage};
+                  p->Lobs, p->S2, p->T, p->poly, p->near, p->lam, p->rho, p->scal, p->dstage,
+                  p->wg_times};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   if (p->hstage) (void)hipHostFree(p->hstage);
@@ -643,7 +649,22 @@ ripk_status enqueue_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_cent
   a.share_word = p->share_word;
   a.share_grid = (int32_t)std::max<int64_t>(1, (int64_t)(p->share_frac * (double)slots));
   a.slice_ticks = 0;
+  a.perm = nullptr;
+  a.wg_times = timing ? p->wg_times : nullptr;
   const int64_t groups_cap = items_bound * split / kItemsPerGroup + 1;
+  // A launch whose items are split (few sets) hands its groups out costliest
+  // first, dealt over the queue partitions, so that the long groups of dense
+  // clusters do not start last.  The sort reuses the point-sort buffers, free
+  // once the records are gathered.
+  p->stats.cost_ordered = 0;
+  if (p->cost_order && split > 1) {
+    const uint64_t mg = ordered_slots((uint32_t)std::min<int64_t>(groups_cap, 1LL << 30));
+    if (mg <= (uint64_t)N && radix_sort_temp_bytes((uint32_t)mg) <= radix_sort_temp_bytes(N, S)) {
+      HIPCHK(launch_order_groups(a, (uint32_t)mg, p->keys[0], p->vals[0], p->keys[1], p->vals[1],
+                                 p->sort_temp, &a.perm, st));
+      p->stats.cost_ordered = 1;
+    }
+  }
   const int grid = (int)std::min<int64_t>(slots, groups_cap);
   // A served plan cuts a long pair launch into slices: workgroups leave after
   // slice_us, the next launch on the stream carries on with the same work
@@ -708,7 +729,7 @@ ripk_status run_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_centres,
                             (uint64_t)(uintptr_t)x, (uint64_t)(uintptr_t)y, (uint64_t)(uintptr_t)t,
                             seed, (uint64_t)has_Lobs, p->bind_gen, S_split,
                             (uint64_t)(uintptr_t)p->cur_lam, (uint64_t)with_obs,
-                            (uint64_t)p->split_runs};
+                            (uint64_t)p->split_runs | ((uint64_t)p->cost_order << 1)};
   if (!p->gexec || std::memcmp(key, p->gkey, sizeof key) != 0) {
     if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
     p->gexec = nullptr;
@@ -765,6 +786,27 @@ ripk_status collect_stats(ripk_plan_s *p, hipStream_t st, uint32_t S, uint32_t n
     p->stats.us_grid = 1e3 * ms[1];
     p->stats.us_pair = 1e3 * ms[2];
     p->stats.us_finalize = 1e3 * ms[3];
+    // workgroup end times of the last pair launch, after the earliest start
+    // (100 MHz ticks); workgroups that took no work left zeros
+    p->stats.us_wg_end_median = p->stats.us_wg_end_p90 = p->stats.us_wg_end_max = 0.0;
+    const int grid = p->stats.pair_grid;
+    if (p->wg_times && grid > 0 && grid <= std::max(p->cus, 1) * kMaxWgPerCu) {
+      std::vector<unsigned long long> tw(2 * (size_t)grid);
+      HIPCHK(hipMemcpy(tw.data(), p->wg_times, sizeof(unsigned long long) * tw.size(),
+                       hipMemcpyDeviceToHost));
+      unsigned long long t0 = ~0ull;
+      for (int w = 0; w < grid; ++w)
+        if (tw[2 * w]) t0 = std::min(t0, tw[2 * w]);
+      std::vector<double> ends;
+      for (int w = 0; w < grid; ++w)
+        if (tw[2 * w] && tw[2 * w + 1] >= t0) ends.push_back(0.01 * (double)(tw[2 * w + 1] - t0));
+      if (!ends.empty()) {
+        std::sort(ends.begin(), ends.end());
+        p->stats.us_wg_end_median = ends[ends.size() / 2];
+        p->stats.us_wg_end_p90 = ends[std::min(ends.size() - 1, ends.size() * 9 / 10)];
+        p->stats.us_wg_end_max = ends.back();
+      }
+    }
   }
   return RIPK_OK;
 }
@@ -835,6 +877,7 @@ ripk_status plan_create(int device, const Caps &c, ripk_plan_s **out) {
   ALLOC(p->lam, c.R); ALLOC(p->rho, c.R);
   ALLOC(p->scal, (kQueues + 1) * kQueueStride);
   ALLOC(p->dstage, kScalWords + kPackRows * c.NB);
+  ALLOC(p->wg_times, 2 * (size_t)std::max(p->cus, 1) * kMaxWgPerCu);
 #undef ALLOC
   if (e == hipSuccess)
     e = hipHostMalloc((void **)&p->hstage, sizeof(unsigned long long) * (kScalWords + kPackRows * c.NB),
@@ -997,8 +1040,34 @@ ripk_status run_tuned(ripk_plan_s *p, int which, uint32_t S, uint32_t S_tune, ui
       ts.cd = kTuneCand[bi % kTuneN][0];
       ts.td = kTuneCand[bi % kTuneN][1];
       ts.split_runs = forced || bi >= kTuneN;
+      ts.cost_order = (p->user_desc.flags & RIPK_PLAN_COST_ORDER) != 0;
+      if (which == 0 && S == 1 && !ts.cost_order) {
+        // the chosen geometry once more with the cost-ordered work list
+        d.cell_div = ts.cd;
+        d.tcell_div = ts.td;
+        p->split_runs = ts.split_runs;
+        p->cost_order = true;
+        ripk_status s = bind_geometry(p, &d, st);
+        if (s != RIPK_OK) return s;
+        double us = 1e300;
+        for (int rep = 0; rep < 2; ++rep) {
+          HIPCHK(hipEventRecord(p->tev[0], st));
+          s = run_sets(p, S_tune, n, nc, x, y, t, simulate, seed, nullptr, st, sym, S, with_obs);
+          if (s != RIPK_OK) return s;
+          HIPCHK(hipEventRecord(p->tev[1], st));
+          uint32_t err = 0;
+          s = collect_stats(p, st, S_tune, n, &err);
+          if (s != RIPK_OK) return s;
+          if (err) return err_status(err);
+          float ms = 0;
+          HIPCHK(hipEventElapsedTime(&ms, p->tev[0], p->tev[1]));
+          us = std::min(us, 1e3 * (double)ms);
+        }
+        ts.cost_order = us < best;
+      }
     }
     p->split_runs = ts.split_runs;
+    p->cost_order = ts.cost_order;
     if (p->bound_cd != ts.cd || p->bound_td != ts.td) {
       d.cell_div = ts.cd;
       d.tcell_div = ts.td;
@@ -1007,6 +1076,7 @@ ripk_status run_tuned(ripk_plan_s *p, int which, uint32_t S, uint32_t S_tune, ui
     }
   } else {
     p->split_runs = (p->user_desc.flags & RIPK_PLAN_SPLIT_RUNS) != 0;
+    p->cost_order = (p->user_desc.flags & RIPK_PLAN_COST_ORDER) != 0;
   }
   return run_sets(p, S, n, nc, x, y, t, simulate, seed, L_obs, st, sym, 0, with_obs);
 }
@@ -1075,10 +1145,11 @@ ripk_status compute_K_in_scratch(const ripk_plan_desc *desc, const ripk_points *
   if (!desc || !pts) return fail(RIPK_EINVAL, "null descriptor or points");
   if (desc->poly_n != 0 || desc->poly)
     return fail(RIPK_EINVAL, "the allocation-free call takes the rectangle (no polygon)");
-  if (desc->flags & ~(RIPK_PLAN_ORDERED | RIPK_PLAN_WIDE_COUNTS | RIPK_PLAN_SPLIT_RUNS))
+  if (desc->flags & ~(RIPK_PLAN_ORDERED | RIPK_PLAN_WIDE_COUNTS | RIPK_PLAN_SPLIT_RUNS |
+                      RIPK_PLAN_COST_ORDER))
     return fail(RIPK_EINVAL,
-                "the allocation-free call takes RIPK_PLAN_ORDERED, RIPK_PLAN_WIDE_COUNTS and "
-                "RIPK_PLAN_SPLIT_RUNS only");
+                "the allocation-free call takes RIPK_PLAN_ORDERED, RIPK_PLAN_WIDE_COUNTS, "
+                "RIPK_PLAN_SPLIT_RUNS and RIPK_PLAN_COST_ORDER only");
   const int64_t n = pts->n;
   const int64_t nc = pts->n_centres ? pts->n_centres : n;
   if (n < 2) return fail(RIPK_EINVAL, "need n >= 2 points (n(n-1) = 0 otherwise)");
@@ -1116,6 +1187,7 @@ ripk_status compute_K_in_scratch(const ripk_plan_desc *desc, const ripk_points *
   if (s != RIPK_OK) return s;
   p.user_desc = d;
   p.split_runs = (d.flags & RIPK_PLAN_SPLIT_RUNS) != 0;
+  p.cost_order = (d.flags & RIPK_PLAN_COST_ORDER) != 0;
   const int32_t *x = pts->x, *y = pts->y, *t = pts->t;
   if (host_points) {
     HIPCHK(hipMemcpyAsync(p.x, x, sizeof(int32_t) * n, hipMemcpyHostToDevice, st));

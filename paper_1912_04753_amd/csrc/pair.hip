@@ -246,11 +246,13 @@ __device__ __forceinline__ double qweight_poly(double om, uint32_t half) {
   return rint(poly_div(1.0, om) * (double)(1u << (kFracBits + half)));
 }
 
-// Polygon records (every distance mode): {bin | half_i<<12 | half_j<<13 |
-// slow_i<<14 | slow_j<<15 | d2 hi<<16, d2 lo, i, j} with i, j the sorted-record
-// indices of the two points; each side's weight goes to the bin's three wide
-// words hw[3 bin ..] (see Pieces).
-// INHOM: the same records as POLY; per side the rectangle's weight w times
+// Polygon records (every distance mode), one per boundary side: {bin |
+// half<<12 | d2 hi<<16, d2 lo, c, 0} with c the sorted-record index of the
+// side's centre; the weight goes to the bin's three wide words hw[3 bin ..]
+// (see Pieces).
+// INHOM records name both points, one per pair with a boundary side: {bin |
+// half_i<<12 | half_j<<13 | slow_i<<14 | slow_j<<15 | d2 hi<<16, d2 lo, i, j};
+// per side the rectangle's weight w times
 // 1/(lambda_i lambda_j) = rho_i rho_j, scaled by 2^F (wscale) and 2^half and
 // rounded: round(((w rho_i rho_j) 2^F) 2^half), which is the interior path's
 // value when w = 1.
@@ -263,24 +265,33 @@ __device__ __forceinline__ void drain_b(WaveLds &W, QState &q, uint32_t c, int l
   const uint4 r = W.qb[(q.hb + lane) & (kQB - 1)];
   wave_sync();
   const uint32_t bin = r.x & 0xFFFu;
-  if (POLY || INHOM) {
+  if (POLY) {
+    // one side per record: {bin | half<<12 | d2 hi<<16, d2 lo, centre record, 0}
     const uint64_t d2 = (uint64_t)r.y | ((uint64_t)(r.x >> 16) << 32);
     if ((uint32_t)lane < c) {
       Pieces pc;
-      const double rr = INHOM ? rho[r.z] * rho[r.w] : 0.0;
+      const int4 p = P[r.z];
+      pc.add(qweight_poly(poly_omega(g, p.x, p.y, d2), (r.x >> 12) & 1u));
+      pc.commit(hw + 3 * bin);
+    }
+    q.hb = (q.hb + c) & (kQB - 1);
+    q.nb -= c;
+    return;
+  }
+  if (INHOM) {
+    const uint64_t d2 = (uint64_t)r.y | ((uint64_t)(r.x >> 16) << 32);
+    if ((uint32_t)lane < c) {
+      Pieces pc;
+      const double rr = rho[r.z] * rho[r.w];
 #pragma unroll 1
       for (uint32_t side = 0; side < 2; ++side) {
         if ((r.x >> (14 + side)) & 1u) {
           const int4 p = P[side ? r.w : r.z];
           const uint32_t half = (r.x >> (12 + side)) & 1u;
-          if (POLY) {
-            pc.add(qweight_poly(poly_omega(g, p.x, p.y, d2), half));
-          } else {
-            const uint32_t ex = (uint32_t)min(p.x, g.x1 - g.x0 - p.x);
-            const uint32_t ey = (uint32_t)min(p.y, g.y1 - g.y0 - p.y);
-            const float w = fmaxf(__builtin_amdgcn_rcpf(omega_f32(ex, ey, d2)), 1.0f);
-            pc.add(rint((((double)w * rr) * wscale) * (double)(1u << half)));
-          }
+          const uint32_t ex = (uint32_t)min(p.x, g.x1 - g.x0 - p.x);
+          const uint32_t ey = (uint32_t)min(p.y, g.y1 - g.y0 - p.y);
+          const float w = fmaxf(__builtin_amdgcn_rcpf(omega_f32(ex, ey, d2)), 1.0f);
+          pc.add(rint((((double)w * rr) * wscale) * (double)(1u << half)));
         }
       }
       pc.commit(hw + 3 * bin);
@@ -468,7 +479,25 @@ __device__ __forceinline__ void drain_a(WaveLds &W, QState &q,
     q.ha = 0;
     q.ta = 0;
   }
-  if (POLY || INHOM) {
+  if (POLY) {
+    // one record per boundary side, naming its centre's sorted record: the
+    // costly weight then runs once per record with every lane busy
+#pragma unroll 1
+    for (int side = 0; side < (SYM ? 2 : 1); ++side) {
+      const bool need = side ? sj.slow : si.slow;
+      const unsigned long long m = __builtin_amdgcn_ballot_w64(need) & vmask;
+      if (m) {
+        const uint32_t pos = lane_rank(m, q.hb + q.nb) & (kQB - 1);
+        q.nb += (uint32_t)__popcll(m);
+        if (need && v)
+          W.qb[pos] = make_uint4(bin | ((side ? hfj : hfi) << 12) | (d2hi << 16), d2lo,
+                                 side ? tb + (((tag >> 16) - kTileOff) >> 2)
+                                      : begin + (((tag & 0xFFFFu) - kCenOff) >> 2),
+                                 0u);
+        if (q.nb >= 64) drain_b<MODE, POLY, INHOM>(W, q, 64, lane, hw, g, P, rho, wscale);
+      }
+    }
+  } else if (INHOM) {
     // one record per pair with a boundary side, naming both points
     const bool need = si.slow || sj.slow;
     const unsigned long long m = mslow;
@@ -737,9 +766,16 @@ k_pair(PairArgs a) {
     __syncthreads();
     const bool leave = uni(*grp_lds) > 1u && (int)blockIdx.x >= a.share_grid;
     __syncthreads();
-    if (leave) return;
+    if (leave) {
+      if (a.wg_times && tid == 0) {
+        a.wg_times[2 * blockIdx.x] = 0ull;
+        a.wg_times[2 * blockIdx.x + 1] = 0ull;
+      }
+      return;
+    }
   }
-  const unsigned long long t_start = a.slice_ticks ? __builtin_amdgcn_s_memrealtime() : 0ull;
+  const unsigned long long t_start =
+      (a.slice_ticks || a.wg_times) ? __builtin_amdgcn_s_memrealtime() : 0ull;
   const uint32_t n_items = *a.n_items;
   const unsigned long long flush_bound =
       a.flush_evals ? a.flush_evals : ((packed || WIDE) ? kFlushEvalsPacked : kFlushEvals);
@@ -800,7 +836,9 @@ k_pair(PairArgs a) {
   // (its XCD under round-robin dispatch, so neighbouring groups share an L2)
   // and moves to the next partition when one runs dry; a plain read of the
   // counter first spares the atomic on a partition already handed out.
-  const uint32_t n_groups = n_items / kItemsPerGroup;
+  // (a cost-ordered list deals its groups over the partitions: whole rounds)
+  const uint32_t n_groups =
+      a.perm ? ordered_slots(n_items / kItemsPerGroup) : n_items / kItemsPerGroup;
   const int home = (int)(blockIdx.x % kQueues);
   int qp = home, q_left = kQueues;
   for (;;) {
@@ -816,7 +854,7 @@ k_pair(PairArgs a) {
         if (lo + __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < hi) {
           const uint32_t gq = lo + atomicAdd(ctr, 1u);
           if (gq < hi) {
-            got = gq;
+            got = a.perm ? a.perm[gq] : gq;
             break;
           }
         }
@@ -828,6 +866,7 @@ k_pair(PairArgs a) {
     __syncthreads();
     const uint32_t grp = uni(*grp_lds);
     if (grp == 0xFFFFFFFFu) break;
+    if (grp == kEmptySlot) continue;
     const uint32_t base = grp * kItemsPerGroup;
     const int set = (int)uni(a.items[base].set);
     const unsigned long long pend = *evals_lds;
@@ -959,6 +998,83 @@ k_pair(PairArgs a) {
   }
   if (cur_set >= 0) flush(cur_set);
   if (lane == 0 && evals_total) atomicAdd(a.queues + (size_t)home * kQueueStride + 1, evals_total);
+  if (a.wg_times && tid == 0) {
+    a.wg_times[2 * blockIdx.x] = t_start;
+    a.wg_times[2 * blockIdx.x + 1] = __builtin_amdgcn_s_memrealtime();
+  }
+}
+
+// Estimated candidates of each group of the work list (slots past the
+// groups get the largest key and an empty value): per item, its centres times
+// the length of every neighbour run its part of the stencil rows covers (a
+// fraction of a run when rows are cut into fractions), as the pair kernel
+// walks them; key = 255 - round(6 log2(1 + cost)) (a sixth of an octave per
+// step, costs up to 2^42), so that an ascending sort, one radix pass, puts the
+// costliest groups first.
+__global__ void k_group_cost(PairArgs a, uint32_t max_groups, uint32_t *__restrict__ keys,
+                             uint32_t *__restrict__ vals) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= max_groups) return;
+  const Geom &g = a.g;
+  const uint32_t G = *a.n_items / kItemsPerGroup;
+  if (s >= G) {
+    keys[s] = 0xFFu;
+    vals[s] = kEmptySlot;
+    return;
+  }
+  const bool sym = a.symmetric != 0, blocked = a.blocked != 0;
+  double cost = 0.0;
+  for (int w = 0; w < kItemsPerGroup; ++w) {
+    const Item it = a.items[s * kItemsPerGroup + w];
+    const uint32_t cnt = it.count & 0x7Fu;
+    if (cnt == 0) continue;
+    const bool frm = (it.count >> 31) != 0;
+    const int r0 = (int)((it.count >> 7) & 0xFFFu);
+    const int r1 = frm ? r0 + 1 : ((it.count >> 19) ? (int)(it.count >> 19) : 0x7FFFFFFF);
+    const uint32_t kf = frm ? ((it.count >> 25) & 63u) : 1u;
+    uint32_t rest;
+    int cxa, cxb;
+    if (a.row_items) {
+      cxa = min(a.P[it.begin].x / g.cell_s, g.nx - 1);
+      cxb = min(a.P[it.begin + cnt - 1].x / g.cell_s, g.nx - 1);
+      rest = it.cell;
+    } else {
+      cxa = cxb = (int)(it.cell % (uint32_t)g.nx);
+      rest = it.cell / (uint32_t)g.nx;
+    }
+    const int cy = (int)(rest % (uint32_t)g.ny), ct = (int)(rest / (uint32_t)g.ny);
+    const uint32_t cst = blocked ? 1u : 2u;
+    const uint32_t nb_off =
+        blocked ? (2u * it.set + 1u) * g.n_cells : it.set * g.n_cells;
+    int ridx = 0;
+    for (int dt = sym ? 0 : -g.rt; dt <= g.rt; ++dt)
+      for (int dy = -g.rs; dy <= g.rs; ++dy) {
+        if (sym && dt == 0 && dy < 0) continue;
+        const int rid = ridx++;
+        if (rid < r0 || rid >= r1) continue;
+        const int tt = ct + dt, yy = cy + dy;
+        if (tt < 0 || tt >= g.nt || yy < 0 || yy >= g.ny) continue;
+        const bool home = dt == 0 && dy == 0 && !blocked;
+        const int xlo = (sym && home) ? cxa : max(cxa - g.rs, 0);
+        const int xhi = min(cxb + g.rs, g.nx - 1);
+        const uint32_t row = nb_off + (uint32_t)(tt * g.ny + yy) * (uint32_t)g.nx;
+        const uint32_t j0 = a.cs[cst * (row + (uint32_t)xlo)];
+        const uint32_t j1 = a.cs[cst * (row + (uint32_t)xhi + 1u)];
+        cost += (double)cnt * (double)(j1 - j0) / (double)kf;
+      }
+  }
+  keys[s] = 0xFFu - min(0xFFu, (uint32_t)rint(6.0 * log2(1.0 + cost)));
+  vals[s] = s;
+}
+
+// Sorted rank r goes to partition r % kQueues, at offset r / kQueues.
+__global__ void k_deal_groups(const uint32_t *__restrict__ n_items, uint32_t max_groups,
+                              const uint32_t *__restrict__ sorted, uint32_t *__restrict__ perm) {
+  const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t slots = ordered_slots(*n_items / kItemsPerGroup);
+  if (r >= slots || r >= max_groups) return;
+  const uint32_t per = slots / kQueues;
+  perm[(r % kQueues) * per + r / kQueues] = sorted[r];
 }
 
 template <bool SYM, int MODE, bool POLY, bool INHOM>
@@ -1021,6 +1137,23 @@ hipError_t pair_occupancy(int n_s, int n_t, int bins, int symmetric, int mode, i
                           int *per_cu) {
   const int lds = pair_lds_bytes(n_s, n_t, bins, var == 2);
   return symmetric ? occ_var<true>(var, mode, lds, per_cu) : occ_var<false>(var, mode, lds, per_cu);
+}
+
+hipError_t launch_order_groups(const PairArgs &a, uint32_t max_groups, uint32_t *kA,
+                               uint32_t *vA, uint32_t *kB, uint32_t *vB, void *temp,
+                               const uint32_t **perm, hipStream_t s) {
+  const uint32_t blocks = (max_groups + 255) / 256;
+  hipLaunchKernelGGL(k_group_cost, dim3(blocks), dim3(256), 0, s, a, max_groups, kA, vA);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  int alt = 0;
+  e = radix_sort(kA, vA, kB, vB, max_groups, 8, temp, s, &alt);
+  if (e != hipSuccess) return e;
+  uint32_t *out = alt ? vA : vB;
+  hipLaunchKernelGGL(k_deal_groups, dim3(blocks), dim3(256), 0, s, a.n_items, max_groups,
+                     alt ? vB : vA, out);
+  *perm = out;
+  return hipGetLastError();
 }
 
 hipError_t launch_pair(const PairArgs &a, int grid, hipStream_t s) {

@@ -112,7 +112,22 @@ struct PairArgs {
   const int32_t *share_word;
   int32_t share_grid;
   uint32_t slice_ticks;
+  // Cost-ordered work list: slot s of the work queue holds group perm[s]
+  // (kEmptySlot: none); the queue then has (groups + 7) & ~7 slots.  Null:
+  // slot s is group s.
+  const uint32_t *perm;
+  // RIPK_PLAN_TIMING: per workgroup its start and end on the 100 MHz
+  // real-time counter (2 words per workgroup of the launch), else null
+  unsigned long long *wg_times;
 };
+constexpr uint32_t kEmptySlot = 0xFFFFFFFEu;
+constexpr int kMaxWgPerCu = 32;  // pair-kernel workgroups a compute unit can hold, at most
+// Slots of the cost-ordered work list: the sorted groups dealt round-robin
+// over the kQueues partitions, so that each partition hands out its groups
+// in descending cost.
+__host__ __device__ inline uint32_t ordered_slots(uint32_t groups) {
+  return (groups + kQueues - 1) / kQueues * kQueues;
+}
 
 // Words per bin of the global weight sums (see PairArgs::binW).
 constexpr int kBinWords = 4;
@@ -231,6 +246,15 @@ struct Zero3 {
 };
 hipError_t launch_zero3(const Zero3 &z, hipStream_t s);
 hipError_t launch_pair(const PairArgs &a, int grid, hipStream_t s);
+// The cost-ordered work list of a launch of at most max_groups groups: an
+// estimate of each group's candidates (centres x neighbour-run lengths of its
+// stencil rows), an 8-bit key of its logarithm, a stable radix sort (keys
+// and values in kA/vA with kB/vB and temp as scratch, each of max_groups
+// words, max_groups a multiple of kQueues) and the round-robin deal into
+// whichever value buffer the sort left free (*perm).
+hipError_t launch_order_groups(const PairArgs &a, uint32_t max_groups, uint32_t *kA,
+                               uint32_t *vA, uint32_t *kB, uint32_t *vB, void *temp,
+                               const uint32_t **perm, hipStream_t s);
 // LDS bin layouts of the pair kernel.  Packed: one 64-bit word per bin holds
 // the pair count (bits 34-63) and the interior-path weights in units of 2^23
 // (bits 0-33), so a pair costs one LDS atomic; boundary weights go to a second

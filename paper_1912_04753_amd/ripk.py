@@ -45,6 +45,7 @@ RIPK_PLAN_GRAPH = 16
 RIPK_PLAN_CROSS = 32
 RIPK_PLAN_INHOM = 64
 RIPK_PLAN_SPLIT_RUNS = 128
+RIPK_PLAN_COST_ORDER = 256
 RIPK_REQ_KEEP_SIMS = 1
 
 _i64, _i32, _u32, _u64, _f64 = (ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32,
@@ -93,7 +94,8 @@ class Stats(ctypes.Structure):
                 ("n_items", _i64), ("pair_grid", _i32), ("symmetric", _i32), ("split", _i32),
                 ("bin_layout", _i32),
                 ("us_total", _f64), ("us_gen", _f64), ("us_grid", _f64), ("us_pair", _f64),
-                ("us_finalize", _f64)]
+                ("us_finalize", _f64), ("us_wg_end_median", _f64), ("us_wg_end_p90", _f64),
+                ("us_wg_end_max", _f64), ("cost_ordered", _i32), ("reserved", _i32)]
 
 
 class ServerDesc(ctypes.Structure):

@@ -249,3 +249,44 @@ def test_stream_sampled_large_requests_against_golden():
         assert m == min(r["sims"], 3) and len(x) > 20_000
         say("stream large: request %d n=%d sims=%d" % (i, len(x), m))
         _stream_check(r, x, y, t, m, list(zip(C, K)))
+
+
+@pytest.mark.parametrize("name", ["uniform2k", "thomas200k", "sparse", "polygon", "inhom"])
+def test_cost_ordered_work_list_matches_default(name):
+    """RIPK_PLAN_COST_ORDER hands the groups of a split launch out costliest
+    first: the same sums bit for bit, in symmetric and ordered plans, and the
+    workgroups of the 200k clustered set end close together."""
+    args, x, y, t, kw = _flush_case(name)
+    flags = kw.pop("flags", 0)
+    for extra in (0, ripk.RIPK_PLAN_ORDERED):
+        a = _run(args, x, y, t, flags=flags | extra | ripk.RIPK_PLAN_TIMING, **kw)
+        b = _run(args, x, y, t, flags=flags | extra | ripk.RIPK_PLAN_TIMING |
+                 ripk.RIPK_PLAN_COST_ORDER, **kw)
+        say("cost order", name, extra, a["stats"]["split"], b["stats"]["cost_ordered"],
+            "ends (median, p90, max) us", b["stats"]["us_wg_end_median"],
+            b["stats"]["us_wg_end_p90"], b["stats"]["us_wg_end_max"])
+        assert a["stats"]["cost_ordered"] == 0
+        # (the order needs a split launch whose groups fit the point buffers)
+        if name in ("thomas200k", "polygon"):
+            assert b["stats"]["cost_ordered"] == 1
+        for k in ("C", "W", "K", "L"):
+            assert np.array_equal(a[k], b[k]), k
+        assert a["stats"]["n_eval"] == b["stats"]["n_eval"]
+
+
+def test_cost_ordered_clustered_set_ends_together():
+    """The 200k clustered set on half-s_max, half-t_max cells with run
+    fractions: handed out costliest first, its workgroups end within 15% of
+    the median one (unordered, the dense clusters' groups end the launch)."""
+    c = workloads.workload("thomas-200k")
+    x, y, t = workloads.make_points(c)
+    kw = dict(cell_div=2, tcell_div=2)
+    fl = ripk.RIPK_PLAN_TIMING | ripk.RIPK_PLAN_SPLIT_RUNS
+    for _ in range(2):   # (first launches warm the device up)
+        a = _run(_args(c), x, y, t, flags=fl, **kw)
+        b = _run(_args(c), x, y, t, flags=fl | ripk.RIPK_PLAN_COST_ORDER, **kw)
+    sa, sb = a["stats"], b["stats"]
+    say("clustered ends: default", sa["us_wg_end_median"], sa["us_wg_end_max"],
+        "cost ordered", sb["us_wg_end_median"], sb["us_wg_end_max"])
+    assert sb["cost_ordered"] == 1 and np.array_equal(a["W"], b["W"])
+    assert sb["us_wg_end_max"] <= 1.15 * sb["us_wg_end_median"]
