@@ -22,8 +22,9 @@ __device__ __forceinline__ void add128(unsigned long long &lo, unsigned long lon
   lo = r;
 }
 
-// One workgroup per set.  binC/binW are cumulated in place (each bin's first
-// two weight words then hold the 128-bit value, low word first).
+// One workgroup per set.  binC/binW are cumulated in place (a set's weight
+// words are [kBinWords][nb]; words 0 and 1 of a bin then hold its 128-bit
+// value, low word first).
 __global__ void k_finalize(unsigned long long *__restrict__ binC,
                            unsigned long long *__restrict__ binW, int n_s, int n_t,
                            double s_max, double t_max, double AD, double N,
@@ -50,14 +51,14 @@ __global__ void k_finalize(unsigned long long *__restrict__ binC,
       int b = k * n_t + l;
       rc += c[b];
       c[b] = rc;
-      unsigned long long *wb = w + (size_t)kBinWords * b;
-      const unsigned long long s0 = wb[0], s1 = wb[1], s2 = wb[2], s3 = wb[3];
+      unsigned long long *wb = w + b;
+      const unsigned long long s0 = wb[0], s1 = wb[nb], s2 = wb[2 * nb], s3 = wb[3 * nb];
       add128(rlo, rhi, s0, 0ull);
       add128(rlo, rhi, s1 << 32, s1 >> 32);
       add128(rlo, rhi, 0ull, s2);
       add128(rlo, rhi, 0ull, s3 << 32);
       wb[0] = rlo;
-      wb[1] = rhi;
+      wb[nb] = rhi;
     }
   }
   __threadfence_block();
@@ -69,10 +70,10 @@ __global__ void k_finalize(unsigned long long *__restrict__ binC,
       int b = k * n_t + l;
       rc += c[b];
       c[b] = rc;
-      unsigned long long *wb = w + (size_t)kBinWords * b;
-      add128(rlo, rhi, wb[0], wb[1]);
+      unsigned long long *wb = w + b;
+      add128(rlo, rhi, wb[0], wb[nb]);
       wb[0] = rlo;
-      wb[1] = rhi;
+      wb[nb] = rhi;
     }
   }
   __threadfence_block();
@@ -81,8 +82,8 @@ __global__ void k_finalize(unsigned long long *__restrict__ binC,
   for (int b = threadIdx.x; b < nb; b += blockDim.x) {
     int k = b / n_t, l = b - k * n_t;
     // fixed point: W = (hi * 2^64 + lo) * 2^-F
-    const unsigned long long *wb = w + (size_t)kBinWords * b;
-    double wv = ldexp((double)wb[1], 64 - fbits) + ldexp((double)wb[0], -fbits);
+    const unsigned long long *wb = w + b;
+    double wv = ldexp((double)wb[nb], 64 - fbits) + ldexp((double)wb[0], -fbits);
     double Kv = AD * wv / N;
     double sk = (double)(k + 1) * s_max / (double)n_s;
     double tl = (double)(l + 1) * t_max / (double)n_t;

@@ -805,7 +805,9 @@ k_pair(PairArgs a) {
       c *= SYM ? 2ull : 1ull;
       if (c) {
         const size_t o = (size_t)set * NB + b;
-        unsigned long long *gw = a.binW + (size_t)kBinWords * o;
+        // word k of bin b at gw[k * NB]: a wave's flush atomics on one word
+        // touch consecutive addresses
+        unsigned long long *gw = a.binW + (size_t)set * NB * kBinWords + b;
         atomicAdd(&a.binC[o], c);
         hist[b] = 0;
         if (WIDE) {
@@ -813,15 +815,15 @@ k_pair(PairArgs a) {
           unsigned long long *w3 = (unsigned long long *)aux + 3 * b;
           const unsigned long long A = w3[0], B = w3[1], C = w3[2];
           if (A & M) atomicAdd(&gw[0], A & M);
-          if ((A >> 32) + (B & M)) atomicAdd(&gw[1], (A >> 32) + (B & M));
-          if ((B >> 32) + (C & M)) atomicAdd(&gw[2], (B >> 32) + (C & M));
-          if (C >> 32) atomicAdd(&gw[3], C >> 32);
+          if ((A >> 32) + (B & M)) atomicAdd(&gw[NB], (A >> 32) + (B & M));
+          if ((B >> 32) + (C & M)) atomicAdd(&gw[2 * NB], (B >> 32) + (C & M));
+          if (C >> 32) atomicAdd(&gw[3 * NB], C >> 32);
           w3[0] = 0;
           w3[1] = 0;
           w3[2] = 0;
         } else {
           atomicAdd(&gw[0], w & M);
-          if (w >> 32) atomicAdd(&gw[1], w >> 32);
+          if (w >> 32) atomicAdd(&gw[NB], w >> 32);
           if (bins == kBinsSplit32)
             ((uint32_t *)aux)[b] = 0;
           else

@@ -82,7 +82,7 @@ struct PairArgs {
   const uint64_t *S2;       // n_s thresholds (device)
   const uint32_t *T;        // n_t thresholds (device)
   unsigned long long *binC;  // [sets][n_bins] counts
-  // [sets][n_bins][kBinWords] fixed-point weight sums, split so that no flush
+  // [sets][kBinWords][n_bins] fixed-point weight sums, split so that no flush
   // needs the old value: word k sums the k-th 32-bit pieces of the
   // workgroups' partial sums (each addend below 2^34), and the weight is
   // sum_k word_k * 2^(32 k) mod 2^128 times 2^-F (F = kFracBits, or the
