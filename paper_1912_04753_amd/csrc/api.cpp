@@ -622,8 +622,16 @@ ripk_status enqueue_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_cent
     if (k >= 2) split = (int64_t)n_rows * k;
   }
   split = std::max<int64_t>(split, 1);
+  // (with split items, each item is written once into the free point-sort key
+  // buffer and expanded in parallel, when it has room for every item)
+  Item *tmp_items = nullptr;
+  uint32_t max_slots = 0;
+  if (split > 1 && items_bound <= (int64_t)N / 4) {
+    tmp_items = (Item *)p->keys[0];
+    max_slots = (uint32_t)std::min<int64_t>(p->caps.items, items_bound * split);
+  }
   HIPCHK(launch_items(p->cs, S, g, row_items, cross, (uint32_t)split, n_rows, p->chunks, p->offs,
-                      p->set_base, p->items, n_items, p->scan_temp, st));
+                      p->set_base, p->items, n_items, p->scan_temp, st, tmp_items, max_slots));
 
   if (timing) HIPCHK(hipEventRecord(p->ev[2], st));
 

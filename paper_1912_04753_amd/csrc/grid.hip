@@ -592,6 +592,29 @@ __global__ void k_emit(const uint32_t *__restrict__ cs, const uint32_t *__restri
   }
 }
 
+// Part p of every item, one thread per slot (the serial walk of k_emit then
+// writes each item once, not `split` times): the slot's set from set_base
+// (binary search), its item o and part p by inverting item_slot.
+__global__ void k_expand(const Item *__restrict__ base, const uint32_t *__restrict__ set_base,
+                         uint32_t n_sets, uint32_t split, uint32_t n_rows,
+                         const uint32_t *__restrict__ n_items, uint32_t max_slots,
+                         Item *__restrict__ items) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= max_slots || s >= *n_items) return;
+  uint32_t lo = 0, hi = n_sets;  // largest k with set_base[k] * split <= s
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) / 2;
+    if (set_base[mid] * split <= s) lo = mid; else hi = mid;
+  }
+  const uint32_t sb = set_base[lo];
+  const uint32_t r = s - sb * split, gp = r / kItemsPerGroup;
+  const uint32_t q = (gp / split) * kItemsPerGroup + r % kItemsPerGroup, p = gp % split;
+  Item it = base[sb + q];
+  const uint32_t cnt = it.count & 0x7Fu;
+  it.count = cnt ? item_count(cnt, p, split, n_rows) : 0u;
+  items[s] = it;
+}
+
 // zeroes up to three ranges in one launch
 __global__ void k_zero3(Zero3 z) {
   const size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -741,7 +764,7 @@ hipError_t launch_gather_rho(const uint32_t *vals, uint32_t n, const double *lam
 hipError_t launch_items(const uint32_t *cs, uint32_t n_sets, const Geom &g, bool row_items,
                         bool blocked, uint32_t split, uint32_t n_rows, uint32_t *chunks,
                         uint32_t *offs, uint32_t *set_base, Item *items, uint32_t *n_items,
-                        void *scan_temp, hipStream_t s) {
+                        void *scan_temp, hipStream_t s, Item *tmp, uint32_t max_slots) {
   const uint32_t unit = row_items ? (uint32_t)g.nx : 1u;
   const uint32_t n_units = g.n_cells / unit;
   const uint32_t tot = n_sets * n_units;
@@ -752,8 +775,16 @@ hipError_t launch_items(const uint32_t *cs, uint32_t n_sets, const Geom &g, bool
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_set_base, dim3(1), dim3(kThreads), 0, s, offs, n_sets, n_units, split,
                      set_base, n_items);
-  hipLaunchKernelGGL(k_emit, dim3(blocks_for(tot, kThreads)), dim3(kThreads), 0, s, cs, offs,
-                     set_base, n_sets, n_units, unit, split, n_rows, ci, items);
+  if (split > 1 && tmp) {
+    // each item once into tmp, then its parts in parallel
+    hipLaunchKernelGGL(k_emit, dim3(blocks_for(tot, kThreads)), dim3(kThreads), 0, s, cs, offs,
+                       set_base, n_sets, n_units, unit, 1u, n_rows, ci, tmp);
+    hipLaunchKernelGGL(k_expand, dim3(blocks_for(max_slots, kThreads)), dim3(kThreads), 0, s, tmp,
+                       set_base, n_sets, split, n_rows, n_items, max_slots, items);
+  } else {
+    hipLaunchKernelGGL(k_emit, dim3(blocks_for(tot, kThreads)), dim3(kThreads), 0, s, cs, offs,
+                       set_base, n_sets, n_units, unit, split, n_rows, ci, items);
+  }
   return hipGetLastError();
 }
 

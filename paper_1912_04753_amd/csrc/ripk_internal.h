@@ -235,10 +235,14 @@ hipError_t launch_bounds_gather(const uint32_t *keys, const uint32_t *vals, uint
 // *err
 hipError_t launch_gather_rho(const uint32_t *vals, uint32_t n, const double *lambda, double *rho,
                              uint32_t *err, unsigned long long *rho_max, hipStream_t s);
+// With split > 1 and tmp (room for every item before splitting) the items are
+// written once into tmp and expanded into their `split` parts in parallel
+// (at most max_slots slots); otherwise each item's walk writes all its parts.
 hipError_t launch_items(const uint32_t *cs, uint32_t n_sets, const Geom &g, bool row_items,
                         bool blocked, uint32_t split, uint32_t n_rows, uint32_t *chunks,
                         uint32_t *offs, uint32_t *set_base, Item *items, uint32_t *n_items,
-                        void *scan_temp, hipStream_t s);
+                        void *scan_temp, hipStream_t s, Item *tmp = nullptr,
+                        uint32_t max_slots = 0);
 // zeroes the ranges (p[r], n[r]) in one launch (a kernel, not memset nodes)
 struct Zero3 {
   unsigned long long *p[3];
