@@ -230,6 +230,45 @@ def copy_calibration(torch):
     torch.cuda.synchronize()
 
 
+def polygon_leg(ripk, workloads, torch, stream, steps=3):
+    """Polygon study area: 100k points uniform inside an 85-vertex boundary of
+    the 20 km window, observed K + 99 CSR simulations (rejection inside the
+    polygon) in one call, autotuned cells."""
+    pc = workloads.workload("polygon-100k-99csr")
+    poly = workloads.polygon_of(pc)
+    px, py, pt = (torch.from_numpy(a).cuda() for a in workloads.make_points(pc))
+    pn, pm = len(px), pc["sims"]
+    pplan = ripk.ripk_plan(ripk.make_desc(pc["window"], pc["s_max"], pc["t_max"], pc["n_s"],
+                                          pc["n_t"], n_max=pn, m_max=pm, poly=poly,
+                                          flags=ripk.RIPK_PLAN_AUTOTUNE | ripk.RIPK_PLAN_TIMING))
+
+    def pstep():
+        t1 = time.perf_counter()
+        ripk.ripk_compute_K_envelope(pplan, px, py, pt, pm, pc["seed"], stream=stream)
+        b = ripk.ripk_plan_stats(pplan)
+        return b["n_in"], time.perf_counter() - t1, b["us_pair"], b
+
+    pstep()  # tuning
+    pstep()
+    torch.cuda.synchronize()
+    t_p = time.perf_counter()
+    ps = [pstep() for _ in range(steps)]
+    torch.cuda.synchronize()
+    p_ms = 1e3 * (time.perf_counter() - t_p) / steps
+    pi_ = ripk.ripk_plan_get_info(pplan)
+    polygon = {"ms_per_step": round(p_ms, 3),
+               "pair_tests_per_s_G": round(ps[0][0] / (p_ms * 1e-3) / 1e9, 3),
+               "sims_per_s": round(pm / (sum(v[1] for v in ps) / steps), 3),
+               "pair_kernel_us": round(sum(v[2] for v in ps) / steps, 2),
+               "cells_m_s": [pi_["cell_s"], pi_["cell_t"]],
+               "roofline": leg_roof(ps[0][3], sum(v[2] for v in ps) / steps),
+               "note": "100k uniform points inside an 85-vertex star-shaped boundary "
+                       "(46% of the 20 km x 20 km window), 180 d, 25x15 grid to 2 km/30 d, "
+                       "observed K + 99 CSR simulations"}
+    pplan.destroy()
+    return polygon
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -251,6 +290,8 @@ def main():
                     help="fixed cells (one per s_max and t_max) instead of the tuned grid")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain device copy of known size first (counter runs)")
+    ap.add_argument("--polygon-only", action="store_true",
+                    help="run the polygon leg alone (--steps timed calls) and print its JSON object")
     ap.add_argument("--main-only", action="store_true",
                     help="stop after the timed steps: no host-input, graph or resampled legs, so "
                          "the last pair-kernel launches of a trace are the timed steps")
@@ -273,6 +314,11 @@ def main():
         return
     dev = ripk.ripk_device_query(0)
     PEAK["lane_ops"] = dev["compute_units"] * 64 * dev["clock_khz"] * 1e3
+    if args.polygon_only:
+        st = torch.cuda.current_stream().cuda_stream
+        print(json.dumps({"polygon": polygon_leg(ripk, workloads, torch, st, steps=args.steps)}),
+              flush=True)
+        return
     if args.copy_calibration:
         copy_calibration(torch)
     cfg = workloads.workload("uniform-100k-99csr")
@@ -424,40 +470,7 @@ def main():
              "roofline": leg_roof(xs[0][2], sum(v[2]["us_pair"] for v in xs) / 3),
              "note": "types = first and second half of the set; ordered cross pairs"}
     xplan.destroy()
-    # polygon study area: 100k points uniform inside an 85-vertex boundary of the
-    # same window, observed K + m CSR simulations (rejection inside the polygon)
-    pc = workloads.workload("polygon-100k-99csr")
-    poly = workloads.polygon_of(pc)
-    px, py, pt = (torch.from_numpy(a).cuda() for a in workloads.make_points(pc))
-    pn, pm = len(px), pc["sims"]
-    pplan = ripk.ripk_plan(ripk.make_desc(pc["window"], pc["s_max"], pc["t_max"], pc["n_s"],
-                                          pc["n_t"], n_max=pn, m_max=pm, poly=poly,
-                                          flags=ripk.RIPK_PLAN_AUTOTUNE | ripk.RIPK_PLAN_TIMING))
-
-    def pstep():
-        t1 = time.perf_counter()
-        ripk.ripk_compute_K_envelope(pplan, px, py, pt, pm, pc["seed"], stream=stream)
-        b = ripk.ripk_plan_stats(pplan)
-        return b["n_in"], time.perf_counter() - t1, b["us_pair"], b
-
-    pstep()  # tuning
-    pstep()
-    torch.cuda.synchronize()
-    t_p = time.perf_counter()
-    ps = [pstep() for _ in range(3)]
-    torch.cuda.synchronize()
-    p_ms = 1e3 * (time.perf_counter() - t_p) / 3
-    pi_ = ripk.ripk_plan_get_info(pplan)
-    polygon = {"ms_per_step": round(p_ms, 3),
-               "pair_tests_per_s_G": round(ps[0][0] / (p_ms * 1e-3) / 1e9, 3),
-               "sims_per_s": round(pm / (sum(v[1] for v in ps) / 3), 3),
-               "pair_kernel_us": round(sum(v[2] for v in ps) / 3, 2),
-               "cells_m_s": [pi_["cell_s"], pi_["cell_t"]],
-               "roofline": leg_roof(ps[0][3], sum(v[2] for v in ps) / 3),
-               "note": "100k uniform points inside an 85-vertex star-shaped boundary "
-                       "(46% of the 20 km x 20 km window), 180 d, 25x15 grid to 2 km/30 d, "
-                       "observed K + 99 CSR simulations"}
-    pplan.destroy()
+    polygon = polygon_leg(ripk, workloads, torch, stream)
     # inhomogeneous K: the same 100k points with an intensity per point (a smooth
     # bump about the window centre, mean n/(A*D)); observed K_I only
     AD = (cfg["window"][2] - cfg["window"][0]) * (cfg["window"][3] - cfg["window"][1]) * \

@@ -235,7 +235,8 @@ int64_t caps_bytes(const Caps &c) {
   bytes += 8 * (kQueues + 1) * kQueueStride;   // scalars and work-queue blocks
   bytes += 8 * (kScalWords + kPackRows * c.NB);  // result staging
   bytes += 3 * 4 * c.P;                       // copy of the observed set (resampling)
-  bytes += 8 * c.V + 2 * (kNearMax + 1) * c.NXY;  // polygon and its per-cell edge lists
+  bytes += 16 * c.V + 2 * (kNearMax + 1) * c.NXY;  // polygon edges and per-cell edge lists
+  if (c.V > 0) bytes += 4 * kRowWords * c.N;       // per-record edge distance ranges
   bytes += 16 * c.R;                          // intensities and their sorted reciprocals
   return bytes;
 }
@@ -384,6 +385,7 @@ ripk_status derive(const ripk_plan_desc *d, Layout *L) {
   L->clamp_e = (int32_t)d->s_max;
   g.poly = nullptr;
   g.near = nullptr;
+  g.prow = nullptr;
   g.poly_n = (int32_t)L->V.size();
   g.poly_sign = area2 < 0 ? -1 : 1;
   L->area = L->V.empty() ? (double)W * (double)H : 0.5 * (double)std::llabs(area2);
@@ -458,9 +460,11 @@ struct ripk_plan_s {
   double *lam = nullptr;       // intensities of the observed set (host input staged here)
   double *rho = nullptr;       // 1/lambda per sorted record
   const double *cur_lam = nullptr;  // intensities of the current call (device)
-  int2 *poly = nullptr;        // polygon vertices (window-relative)
+  int4 *poly = nullptr;        // polygon edges {V[k], V[k+1 mod n]} (window-relative)
+  uint32_t *prow = nullptr;    // per-record polygon rows (kRowWords words each)
   uint16_t *near = nullptr;    // per xy-cell edge lists of the bound geometry
   std::vector<uint16_t> nearh; // host copy of the lists (source of the upload)
+  std::vector<int4> edgeh;     // host copy of the edges (source of the upload)
   // [0] n_eval, [1] n_in, [2] err|n_items (u32s); from word kQueueStride on,
   // the pair kernel's kQueues work-queue blocks
   unsigned long long *scal = nullptr;
@@ -491,7 +495,7 @@ void release(ripk_plan_s *p) {
                   p->vals[1],
                   p->sort_temp, p->cs, p->P, p->chunks, p->offs, p->set_base, p->scan_temp,
                   p->items, p->binC, p->binW, p->outC, p->outW, p->outK, p->outL, p->env,
-                  p->Lobs, p->S2, p->T, p->poly, p->near, p->lam, p->rho, p->scal, p->dstage,
+                  p->Lobs, p->S2, p->T, p->poly, p->near, p->prow, p->lam, p->rho, p->scal, p->dstage,
                   p->wg_times};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
@@ -576,7 +580,7 @@ ripk_status enqueue_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_cent
   // (cross K sets are sorted in blocked order, each type one cell-sorted block:
   // centres come from the type-1 block and neighbour runs from the type-2 block)
   HIPCHK(launch_bounds_gather(p->keys[alt], p->vals[alt], N, (uint32_t)n_keys, p->cs, x, y, t, g,
-                              p->lay.clamp_e, p->P, st));
+                              p->lay.clamp_e, p->P, p->prow, st));
   const bool inhom = (p->desc.flags & RIPK_PLAN_INHOM) != 0 && !simulate;
   // (scal[3]: the largest 1/lambda of an inhomogeneous launch, as its bits)
   unsigned long long *rho_max = p->scal + 3;
@@ -882,6 +886,7 @@ ripk_status plan_create(int device, const Caps &c, ripk_plan_s **out) {
   ALLOC(p->env, 5 * c.NB); ALLOC(p->Lobs, c.NB);
   ALLOC(p->S2, kMaxSteps); ALLOC(p->T, kMaxSteps);
   ALLOC(p->poly, c.V); ALLOC(p->near, (kNearMax + 1) * c.NXY);
+  if (c.V > 0) ALLOC(p->prow, (int64_t)kRowWords * c.N);
   ALLOC(p->lam, c.R); ALLOC(p->rho, c.R);
   ALLOC(p->scal, (kQueues + 1) * kQueueStride);
   ALLOC(p->dstage, kScalWords + kPackRows * c.NB);
@@ -987,14 +992,21 @@ ripk_status bind_geometry(ripk_plan_s *p, const ripk_plan_desc *desc, hipStream_
   if (!p->lay.V.empty()) {
     build_near(p->lay, desc->s_max, &p->nearh);
     near_summary(p->nearh, &p->lay.info);
-    HIPCHK(hipMemcpyAsync(p->poly, p->lay.V.data(), sizeof(int2) * p->lay.V.size(),
-                          hipMemcpyHostToDevice, stream));
+    const size_t nv = p->lay.V.size();
+    p->edgeh.resize(nv);
+    for (size_t k = 0; k < nv; ++k) {
+      const int2 a = p->lay.V[k], b = p->lay.V[k + 1 == nv ? 0 : k + 1];
+      p->edgeh[k] = make_int4(a.x, a.y, b.x, b.y);
+    }
+    HIPCHK(hipMemcpyAsync(p->poly, p->edgeh.data(), sizeof(int4) * nv, hipMemcpyHostToDevice,
+                          stream));
     HIPCHK(hipMemcpyAsync(p->near, p->nearh.data(), sizeof(uint16_t) * p->nearh.size(),
                           hipMemcpyHostToDevice, stream));
     // the host sources are replaced by the next bind: let the copies finish
     HIPCHK(hipStreamSynchronize(stream));
     p->lay.g.poly = p->poly;
     p->lay.g.near = p->near;
+    p->lay.g.prow = pair_poly(p->lay.g) ? p->prow : nullptr;
   }
   return RIPK_OK;
 }

@@ -413,12 +413,14 @@ __global__ void k_sort_scatter(const uint32_t *__restrict__ keys,
 // One pass over the sorted keys: the cell bounds cs[k] = first index whose
 // key >= k, for k in [0, n_keys], and the sorted point records: window-relative
 // coordinates (all >= 0) and the distance to the nearest side clamped to s_max
-// (a circle no larger than that is whole).
+// (a circle no larger than that is whole); with a polygon and spatial
+// correction, each record's row of edge distance ranges (poly_row).
 __global__ void k_bounds_gather(const uint32_t *__restrict__ keys,
                                 const uint32_t *__restrict__ vals, uint32_t n, uint32_t n_keys,
                                 uint32_t *__restrict__ cs, const int32_t *__restrict__ x,
                                 const int32_t *__restrict__ y, const int32_t *__restrict__ t,
-                                Geom g, int32_t clamp_e, int4 *__restrict__ P) {
+                                Geom g, int32_t clamp_e, int4 *__restrict__ P,
+                                uint32_t *__restrict__ prow) {
   const uint32_t r = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (r > n) return;
   const int64_t prev = (r == 0) ? -1 : (int64_t)keys[r - 1];
@@ -430,6 +432,7 @@ __global__ void k_bounds_gather(const uint32_t *__restrict__ keys,
   int32_t e;
   if (g.poly_n) {
     e = poly_edist(g, X, Y, clamp_e);
+    if (g.prow) poly_row(g, X, Y, prow + (size_t)r * kRowWords);
   } else {
     e = min(min(X, g.x1 - g.x0 - X), min(Y, g.y1 - g.y0 - Y));
     e = min(max(e, 0), clamp_e);
@@ -747,9 +750,10 @@ hipError_t radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32
 hipError_t launch_bounds_gather(const uint32_t *keys, const uint32_t *vals, uint32_t n,
                                 uint32_t n_keys, uint32_t *cs, const int32_t *x, const int32_t *y,
                                 const int32_t *t, const Geom &g, int32_t clamp_e, int4 *P,
-                                hipStream_t s) {
+                                uint32_t *prow, hipStream_t s) {
   hipLaunchKernelGGL(k_bounds_gather, dim3(xcd_grid(blocks_for((uint64_t)n + 1, kThreads))),
-                     dim3(kThreads), 0, s, keys, vals, n, n_keys, cs, x, y, t, g, clamp_e, P);
+                     dim3(kThreads), 0, s, keys, vals, n, n_keys, cs, x, y, t, g, clamp_e, P,
+                     prow);
   return hipGetLastError();
 }
 

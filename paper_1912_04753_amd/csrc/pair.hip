@@ -271,7 +271,7 @@ __device__ __forceinline__ void drain_b(WaveLds &W, QState &q, uint32_t c, int l
     if ((uint32_t)lane < c) {
       Pieces pc;
       const int4 p = P[r.z];
-      pc.add(qweight_poly(poly_omega(g, p.x, p.y, d2), (r.x >> 12) & 1u));
+      pc.add(qweight_poly(poly_omega(g, p.x, p.y, d2, r.z), (r.x >> 12) & 1u));
       pc.commit(hw + 3 * bin);
     }
     q.hb = (q.hb + c) & (kQB - 1);

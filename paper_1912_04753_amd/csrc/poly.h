@@ -6,7 +6,7 @@
 // Vertices are window-relative int32 (coordinates below 2^24), so every vector
 // product below is an integer below 2^52, exact in FP64, and the circle-edge
 // discriminant is exact in 128-bit integers where its sign is in doubt.
-// Edges are (V[k], V[k+1 mod n]).  Each xy-cell of the grid lists the edges
+// Edges are (V[k], V[k+1 mod n]), one int4 {a, b} each.  Each xy-cell of the grid lists the edges
 // within s_max of the cell ({count, index...}, kNearMax + 1 u16 words; count
 // kNearAll = every edge): a circle of radius <= s_max centred in the cell meets
 // no other edge.
@@ -17,31 +17,33 @@ namespace ripk {
 
 // Strictly inside: crossing number along +x with the half-open rule, exact
 // integers; a point on an edge is not inside.
-__device__ __forceinline__ bool poly_inside(const int2 *__restrict__ V, int nv, int px, int py) {
+__device__ __forceinline__ bool poly_inside(const int4 *__restrict__ E, int nv, int px, int py) {
   bool in = false;
-  int2 a = V[nv - 1];
   for (int k = 0; k < nv; ++k) {
-    const int2 b = V[k];
-    const long long ex = (long long)b.x - a.x, ey = (long long)b.y - a.y;
-    const long long qx = (long long)px - a.x, qy = (long long)py - a.y;
-    if (ex * qy == ey * qx && px >= min(a.x, b.x) && px <= max(a.x, b.x) &&
-        py >= min(a.y, b.y) && py <= max(a.y, b.y))
+    const int4 e = E[k];  // a = (e.x, e.y), b = (e.z, e.w)
+    const long long ex = (long long)e.z - e.x, ey = (long long)e.w - e.y;
+    const long long qx = (long long)px - e.x, qy = (long long)py - e.y;
+    if (ex * qy == ey * qx && px >= min(e.x, e.z) && px <= max(e.x, e.z) &&
+        py >= min(e.y, e.w) && py <= max(e.y, e.w))
       return false;
-    if ((a.y > py) != (b.y > py)) {
+    if ((e.y > py) != (e.w > py)) {
       // px left of the edge's crossing with the line y = py
       const long long num = qy * ex, lhs = qx * ey;
       if (ey > 0 ? lhs < num : lhs > num) in = !in;
     }
-    a = b;
   }
   return in;
 }
 
-// the list of edges near the xy-cell of a window-relative point
-__device__ __forceinline__ const uint16_t *poly_list(const Geom &g, int px, int py) {
+// the xy-cell of a window-relative point, and the list of edges near it
+__device__ __forceinline__ uint32_t poly_cell(const Geom &g, int px, int py) {
   const uint32_t cx = min((uint32_t)px / (uint32_t)g.cell_s, (uint32_t)g.nx - 1u);
   const uint32_t cy = min((uint32_t)py / (uint32_t)g.cell_s, (uint32_t)g.ny - 1u);
-  return g.near + (size_t)(cy * (uint32_t)g.nx + cx) * (kNearMax + 1);
+  return cy * (uint32_t)g.nx + cx;
+}
+
+__device__ __forceinline__ const uint16_t *poly_list(const Geom &g, int px, int py) {
+  return g.near + (size_t)poly_cell(g, px, py) * (kNearMax + 1);
 }
 
 template <typename F>
@@ -61,12 +63,11 @@ __device__ __forceinline__ void poly_for_near(const Geom &g, int px, int py, F f
 // its error, so a pair with d2 <= e^2 has its whole circle inside.
 __device__ __forceinline__ int32_t poly_edist(const Geom &g, int px, int py, int32_t cap) {
   double best = (double)cap * (double)cap;
-  const int2 *__restrict__ V = g.poly;
-  const int nv = g.poly_n;
+  const int4 *__restrict__ E = g.poly;
   poly_for_near(g, px, py, [&](int k) {
-    const int2 a = V[k], b = V[k + 1 == nv ? 0 : k + 1];
-    const double ex = (double)b.x - a.x, ey = (double)b.y - a.y;
-    const double qx = (double)px - a.x, qy = (double)py - a.y;
+    const int4 e = E[k];
+    const double ex = (double)e.z - e.x, ey = (double)e.w - e.y;
+    const double qx = (double)px - e.x, qy = (double)py - e.y;
     const double ee = ex * ex + ey * ey;
     const double s = fmin(fmax(ee > 0.0 ? (qx * ex + qy * ey) / ee : 0.0, 0.0), 1.0);
     const double dx = qx - s * ex, dy = qy - s * ey;
@@ -74,6 +75,34 @@ __device__ __forceinline__ int32_t poly_edist(const Geom &g, int px, int py, int
   });
   if (best >= (double)cap * (double)cap) return cap;
   return (int32_t)fmax(floor(sqrt(best * (1.0 - 1e-12))) - 1.0, 0.0);
+}
+
+// The row of a point for the weight: its xy-cell (word 0 of a 4-word head),
+// then from word 4, for each edge of the cell's list, the range [lo, hi] of
+// distances from the point to the edge's points, in metres as 16-bit integers
+// (lo | hi << 16), lo rounded down and hi up with a margin well above the FP64
+// error: a circle about the point meets the edge only if lo <= radius <= hi.
+// Entries up to the next multiple of 4 hold an empty range (lo > hi).  Cells
+// that scan every edge keep only the cell.
+__device__ __forceinline__ void poly_row(const Geom &g, int px, int py, uint32_t *__restrict__ row) {
+  const uint32_t cell = poly_cell(g, px, py);
+  row[0] = cell;
+  const uint16_t *lst = g.near + (size_t)cell * (kNearMax + 1);
+  const uint32_t cnt = lst[0];
+  if (cnt == kNearAll) return;
+  for (uint32_t i = cnt; i < ((cnt + 3u) & ~3u); ++i) row[4 + i] = 0xFFFFu;
+  for (uint32_t i = 0; i < cnt; ++i) {
+    const int4 e = g.poly[lst[1 + i]];
+    const double ax = (double)(e.x - px), ay = (double)(e.y - py);
+    const double bx = (double)(e.z - px), by = (double)(e.w - py);
+    const double ex = bx - ax, ey = by - ay;
+    const double ee = ex * ex + ey * ey;
+    const double s = fmin(fmax(ee > 0.0 ? -(ax * ex + ay * ey) / ee : 0.0, 0.0), 1.0);
+    const double dx = ax + s * ex, dy = ay + s * ey;
+    const double lo = fmax(floor(sqrt(dx * dx + dy * dy) * (1.0 - 1e-12)) - 1.0, 0.0);
+    const double hi = ceil(sqrt(fmax(ax * ax + ay * ay, bx * bx + by * by)) * (1.0 + 1e-12)) + 1.0;
+    row[4 + i] = (uint32_t)fmin(lo, 65535.0) | ((uint32_t)fmin(hi, 65535.0) << 16);
+  }
 }
 
 // a / b from the hardware reciprocal, one Newton step on it and one on the
@@ -131,7 +160,10 @@ __device__ __forceinline__ double poly_sqrt(double x) {
 }
 
 // Share of the circle centred on the window-relative point (px, py), strictly
-// inside the polygon, with radius sqrt(d2) inside the polygon.
+// inside the polygon, with radius sqrt(d2) inside the polygon; rec is the
+// point's sorted record (its row, see poly_row).  The circle passes through
+// the pair's other point, also strictly inside, so a circle that crosses the
+// boundary nowhere lies inside.
 //
 // Walking the circle counter-clockwise, the inside length is the sum of the
 // exit angles minus the sum of the entry angles, plus 2 pi when the walk
@@ -152,22 +184,26 @@ __device__ __forceinline__ double poly_sqrt(double x) {
 // only touching it cancels (an edge tangent at the vertex counts as leaving the
 // disk); the two halves are added at the edge the vertex starts, so a vertex
 // is one crossing or none.  An edge tangent inside its span (zero
-// discriminant) counts nothing.
-// With no net crossing the circle is wholly inside unless the polygon lies
-// within it (some vertex strictly inside the disk).  Only the angles are
-// floating point (FP64); the integer quantities are carried in FP64 registers,
-// where they are exact.
-__device__ __forceinline__ double poly_omega(const Geom &g, int px, int py, uint64_t d2u) {
+// discriminant) counts nothing.  Only the angles are floating point (FP64);
+// the integer quantities are carried in FP64 registers, where they are exact.
+//
+// The edges go in chunks of 32 list entries.  A first pass keeps, in a bit
+// mask, the entries whose distance range from the point holds the radius
+// (two integer compares per entry on the point's row); the exact work above
+// then runs only for those.  The lanes of a wave hold different circles, so a
+// single pass paid for the crossing work at almost every entry, while a
+// circle meets few of them (two, near a smooth boundary).  Cells that scan
+// every edge (more than 32 near it) take the first pass on exact integers.
+__device__ __forceinline__ double poly_omega(const Geom &g, int px, int py, uint64_t d2u,
+                                             uint32_t rec) {
   if (d2u == 0) return 1.0;
-  const int2 *__restrict__ V = g.poly;
+  const int4 *__restrict__ E = g.poly;
   const int nv = g.poly_n;
   // every quantity below is an integer of at most 52 bits, exact in FP64
   const double d2 = (double)d2u;
-  const int R = (int)sqrt(d2) + 1;  // R^2 > d2: edges whose box misses [-R, R]^2 miss the circle
   const double sg = (double)g.poly_sign;
   double Px = 1.0, Py = 0.0;   // product of the crossings' directions
   bool crossed = false;
-  bool vin = false;
   // P <- P (x + i y), rescaled so that its larger component lies in [1, 2)
   auto turn = [&](double x, double y) {
     const double nx = fma(Px, x, -Py * y), ny = fma(Px, y, Py * x);
@@ -176,57 +212,101 @@ __device__ __forceinline__ double poly_omega(const Geom &g, int px, int py, uint
     Py = ldexp(ny, -e);
     crossed = true;
   };
-  poly_for_near(g, px, py, [&](int k) {
-    const int2 a = V[k], b = V[k + 1 == nv ? 0 : k + 1];
-    const int Ax = a.x - px, Ay = a.y - py, Bx = b.x - px, By = b.y - py;
-    if (min(Ax, Bx) > R || max(Ax, Bx) < -R || min(Ay, By) > R || max(Ay, By) < -R) return;
-    const double ax = (double)Ax, ay = (double)Ay, bx = (double)Bx, by = (double)By;
-    const double ex = bx - ax, ey = by - ay;
-    const double ee = fma(ex, ex, ey * ey), ae = fma(ax, ex, ay * ey);
-    const double aa = fma(ax, ax, ay * ay), bb = fma(bx, bx, by * by);
-    vin = vin || aa < d2 || bb < d2;
-    if (ee == 0.0) return;
-    // vertex a on the circle: its halves from this edge (a-end) and from the
-    // previous one (b-end), each signed by the side of the circle the edge
-    // lies on next to the vertex (this edge: E.A > 0 lies outside beyond a;
-    // the previous edge, F = a - prev: F.A > 0 lies inside before a), an edge
-    // tangent there (zero product) lying outside the disk; +-1/2 each, exact
-    // integer products
-    if (aa == d2) {
-      const int2 pv = V[k == 0 ? nv - 1 : k - 1];
-      const double fx = (double)(a.x - pv.x), fy = (double)(a.y - pv.y);
-      const int h = (ae >= 0.0 ? -1 : 1) + (fma(fx, ax, fy * ay) > 0.0 ? -1 : 1);
-      if (h != 0) turn(ax, (h > 0 ? sg : -sg) * ay);
-    }
-    // discriminant ae^2 - ee (aa - d2): its sign from FP64 when clear of the
-    // rounding bound, else from exact 128-bit integers
-    const double t1 = ae * ae, t2 = ee * (aa - d2);
-    double disc = t1 - t2;
-    if (fabs(disc) <= 0x1p-50 * (fabs(t1) + fabs(t2))) {
-      const long long iae = (long long)ae, iee = (long long)ee, iad = (long long)(aa - d2);
-      const __int128 e = (__int128)iae * iae - (__int128)iee * iad;
-      disc = e > 0 ? (double)e : 0.0;
-    }
-    if (disc > 0.0) {
-      const double sq = poly_sqrt(disc);
-      // the crossing A + s E with s = (-ae -+ sq)/ee, scaled by ee > 0 (the
-      // angle depends on the direction only)
-      // smaller root strictly inside the edge: an exit (counter-clockwise)
-      // (its angle is added with the orientation's sign: direction (x, sg y))
-      if (ae < 0.0 && aa > d2 && (ae + ee > 0.0 || bb < d2)) {
-        const double sm = -ae - sq;
-        turn(fma(sm, ex, ee * ax), sg * fma(sm, ey, ee * ay));
+  const uint32_t *__restrict__ row = g.prow + (size_t)rec * kRowWords;
+  const uint16_t *__restrict__ lst = g.near + (size_t)row[0] * (kNearMax + 1);
+  const bool all = lst[0] == kNearAll;
+  const uint32_t len = all ? (uint32_t)nv : (uint32_t)lst[0];
+  // d2 is at most s_max^2 < 2^27 here
+  const uint32_t d2s = (uint32_t)d2u;
+  for (uint32_t base = 0; base < len; base += 32) {
+    const uint32_t m = min(len - base, 32u);
+    uint32_t keep = 0;
+    if (!all) {
+      for (uint32_t i = 0; i < m; i += 4) {
+        const uint4 w = *(const uint4 *)(row + 4 + i);
+        const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const uint32_t lo = ws[u] & 0xFFFFu, hi = ws[u] >> 16;
+          const bool k = __umul24(lo, lo) <= d2s && d2s <= __umul24(hi, hi);
+          keep |= (uint32_t)k << (i + u);
+        }
       }
-      // larger root strictly inside the edge: an entry (angle subtracted)
-      if ((ae < 0.0 || aa < d2) && ae + ee > 0.0 && bb > d2) {
-        const double sp = -ae + sq;
-        turn(fma(sp, ex, ee * ax), -sg * fma(sp, ey, ee * ay));
+    } else {
+      for (uint32_t i = 0; i < m; ++i) {
+        const int4 e = E[base + i];
+        const double ax = (double)(e.x - px), ay = (double)(e.y - py);
+        const double bx = (double)(e.z - px), by = (double)(e.w - py);
+        const double ex = bx - ax, ey = by - ay;
+        const double ee = fma(ex, ex, ey * ey), ae = fma(ax, ex, ay * ey);
+        const double aa = fma(ax, ax, ay * ay), bb = fma(bx, bx, by * by);
+        // a root strictly inside the edge, or vertex a on the circle: from
+        // inside only if b is outside; from outside to inside always; with
+        // both ends on or outside, only if the line's closest point lies
+        // strictly inside the edge and the discriminant is not negative
+        // beyond its rounding bound (the test below)
+        const double t1 = ae * ae, t2 = ee * (aa - d2);
+        const bool k = aa == d2 || (aa < d2 && bb > d2) || (aa > d2 && bb < d2) ||
+                       (aa > d2 && ae < 0.0 && ae + ee > 0.0 &&
+                        (bb == d2 || t1 - t2 >= -0x1p-50 * (t1 + t2)));
+        keep |= (uint32_t)k << i;
       }
     }
-  });
+    while (keep) {
+      const uint32_t i = (uint32_t)__builtin_ctz(keep);
+      keep &= keep - 1u;
+      const int kk = all ? (int)(base + i) : (int)lst[1 + i];
+      const int4 e = E[kk];
+      const double ax = (double)(e.x - px), ay = (double)(e.y - py);
+      const double bx = (double)(e.z - px), by = (double)(e.w - py);
+      const double ex = bx - ax, ey = by - ay;
+      const double ee = fma(ex, ex, ey * ey), ae = fma(ax, ex, ay * ey);
+      const double aa = fma(ax, ax, ay * ay), bb = fma(bx, bx, by * by);
+      if (ee == 0.0) continue;
+      // vertex a on the circle: its halves from this edge (a-end) and from the
+      // previous one (b-end), each signed by the side of the circle the edge
+      // lies on next to the vertex (this edge: E.A > 0 lies outside beyond a;
+      // the previous edge, F = a - prev: F.A > 0 lies inside before a), an
+      // edge tangent there (zero product) lying outside the disk; +-1/2 each,
+      // exact integer products
+      if (aa == d2) {
+        const int4 pe = E[kk == 0 ? nv - 1 : kk - 1];
+        const double fx = (double)(e.x - pe.x), fy = (double)(e.y - pe.y);
+        const int h = (ae >= 0.0 ? -1 : 1) + (fma(fx, ax, fy * ay) > 0.0 ? -1 : 1);
+        if (h != 0) turn(ax, (h > 0 ? sg : -sg) * ay);
+      }
+      // discriminant ae^2 - ee (aa - d2): its sign from FP64 when clear of the
+      // rounding bound, else from exact 128-bit integers
+      const double t1 = ae * ae, t2 = ee * (aa - d2);
+      double disc = t1 - t2;
+      if (fabs(disc) <= 0x1p-50 * (fabs(t1) + fabs(t2))) {
+        const long long iae = (long long)ae, iee = (long long)ee, iad = (long long)(aa - d2);
+        const __int128 q = (__int128)iae * iae - (__int128)iee * iad;
+        disc = q > 0 ? (double)q : 0.0;
+      }
+      if (disc > 0.0) {
+        // the crossing A + s E with s = (-ae -+ sq)/ee, scaled by ee > 0 (the
+        // angle depends on the direction only).  Smaller root strictly inside
+        // the edge: an exit (counter-clockwise), its angle added with the
+        // orientation's sign (direction (x, sg y)); larger root strictly
+        // inside: an entry, its angle subtracted.
+        const bool out = ae < 0.0 && aa > d2 && (ae + ee > 0.0 || bb < d2);
+        const bool in = (ae < 0.0 || aa < d2) && ae + ee > 0.0 && bb > d2;
+        if (out || in) {
+          const double sq = poly_sqrt(disc);
+          const double s1 = out ? -ae - sq : -ae + sq;
+          turn(fma(s1, ex, ee * ax), (out ? sg : -sg) * fma(s1, ey, ee * ay));
+          if (out && in) {
+            const double s2 = -ae + sq;
+            turn(fma(s2, ex, ee * ax), -sg * fma(s2, ey, ee * ay));
+          }
+        }
+      }
+    }
+  }
+  if (!crossed) return 1.0;
   const double two_pi = 6.283185307179586476925;
-  const double L = crossed ? poly_angle(Px, Py) : (vin ? 0.0 : two_pi);
-  return L / two_pi;
+  return poly_angle(Px, Py) / two_pi;
 }
 
 }  // namespace ripk

@@ -36,16 +36,21 @@ struct Geom {
   uint32_t tmax;                   // T[n_t-1]
   float inv_ds;                    // n_s / s_max * (1 - 2^-20)
   float inv_dt;                    // n_t / t_max * (1 - 2^-20)
-  // polygon study area (poly_n = 0: the rectangle): window-relative vertices,
-  // per xy-cell lists of the edges within s_max (see poly.h), orientation sign
-  const int2 *poly;
+  // polygon study area (poly_n = 0: the rectangle): window-relative edges
+  // {V[k], V[k+1 mod n]}, per xy-cell lists of the edges within s_max (see
+  // poly.h), orientation sign
+  const int4 *poly;
   const uint16_t *near;
+  // per sorted record (spatial correction): its xy-cell, then the distance
+  // range of each listed edge from the point (see poly_row); kRowWords words
+  const uint32_t *prow;
   int32_t poly_n;
   int32_t poly_sign;  // +1 counter-clockwise, -1 clockwise
 };
 constexpr int kMaxPoly = 4096;       // vertices of a polygon study area
 constexpr int kNearMax = 32;         // edges listed per cell (more: every edge is scanned)
 constexpr uint16_t kNearAll = 0xFFFF;
+constexpr int kRowWords = 4 + kNearMax;  // per-record polygon row: 4-word head, a word per listed edge
 
 // Work item of the pair kernel: up to kChunk consecutive centres of one unit
 // of one set: a cell, or an x-row of cells (row items).
@@ -228,7 +233,7 @@ hipError_t exclusive_scan(const uint32_t *in, uint32_t *out, uint32_t n, void *t
 hipError_t launch_bounds_gather(const uint32_t *keys, const uint32_t *vals, uint32_t n,
                                 uint32_t n_keys, uint32_t *cs, const int32_t *x, const int32_t *y,
                                 const int32_t *t, const Geom &g, int32_t clamp_e, int4 *P,
-                                hipStream_t s);
+                                uint32_t *prow, hipStream_t s);
 // rho[r] = 1 / lambda[vals[r]] for the sorted records, and the largest rho
 // as its bit pattern in *rho_max (zeroed before; positive doubles order as
 // their bit patterns); a value that is not positive and finite sets bit 2 of
