@@ -260,6 +260,8 @@ def polygon_leg(ripk, workloads, torch, stream, steps=3):
                "pair_tests_per_s_G": round(ps[0][0] / (p_ms * 1e-3) / 1e9, 3),
                "sims_per_s": round(pm / (sum(v[1] for v in ps) / steps), 3),
                "pair_kernel_us": round(sum(v[2] for v in ps) / steps, 2),
+               "phases_us": {k: round(sum(v[3][k] for v in ps) / steps, 1)
+                             for k in ("us_gen", "us_grid", "us_pair", "us_finalize")},
                "cells_m_s": [pi_["cell_s"], pi_["cell_t"]],
                "roofline": leg_roof(ps[0][3], sum(v[2] for v in ps) / steps),
                "note": "100k uniform points inside an 85-vertex star-shaped boundary "

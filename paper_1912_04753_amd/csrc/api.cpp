@@ -134,6 +134,33 @@ double seg_point_d2(double ax, double ay, double bx, double by, double px, doubl
 
 // Per xy-cell lists of the edges within s_max (plus a margin) of the cell's
 // rectangle (the last cell of an axis reaches the window's side).
+// Edges by horizontal band of height 2^band_shift (the containment test's
+// lists): band b holds every edge whose closed y-range meets the band.
+void build_bands(const Layout &L, std::vector<uint32_t> *off, std::vector<uint16_t> *idx) {
+  const Geom &g = L.g;
+  const int nv = (int)L.V.size();
+  const uint32_t nb = ((uint32_t)(g.y1 - g.y0) >> g.band_shift) + 1u;
+  off->assign((size_t)nb + 1, 0);
+  auto span = [&](int k, uint32_t *b0, uint32_t *b1) {
+    const int2 a = L.V[(size_t)k], b = L.V[(size_t)((k + 1) % nv)];
+    *b0 = (uint32_t)std::min(a.y, b.y) >> g.band_shift;
+    *b1 = (uint32_t)std::max(a.y, b.y) >> g.band_shift;
+  };
+  for (int k = 0; k < nv; ++k) {
+    uint32_t b0, b1;
+    span(k, &b0, &b1);
+    for (uint32_t b = b0; b <= b1; ++b) ++(*off)[b + 1];
+  }
+  for (uint32_t b = 0; b < nb; ++b) (*off)[b + 1] += (*off)[b];
+  idx->assign((*off)[nb], 0);
+  std::vector<uint32_t> fill(off->begin(), off->end() - 1);
+  for (int k = 0; k < nv; ++k) {
+    uint32_t b0, b1;
+    span(k, &b0, &b1);
+    for (uint32_t b = b0; b <= b1; ++b) (*idx)[fill[b]++] = (uint16_t)k;
+  }
+}
+
 void build_near(const Layout &L, int64_t s_max, std::vector<uint16_t> *out) {
   const Geom &g = L.g;
   const int nv = (int)L.V.size();
@@ -237,6 +264,7 @@ int64_t caps_bytes(const Caps &c) {
   bytes += 3 * 4 * c.P;                       // copy of the observed set (resampling)
   bytes += 16 * c.V + 2 * (kNearMax + 1) * c.NXY;  // polygon edges and per-cell edge lists
   if (c.V > 0) bytes += 4 * kRowWords * c.N;       // per-record edge distance ranges
+  if (c.V > 0) bytes += 4 * (kBandsMax + 1) + 2 * c.V * kBandsMax;  // edges by band
   bytes += 16 * c.R;                          // intensities and their sorted reciprocals
   return bytes;
 }
@@ -386,6 +414,10 @@ ripk_status derive(const ripk_plan_desc *d, Layout *L) {
   g.poly = nullptr;
   g.near = nullptr;
   g.prow = nullptr;
+  g.band_off = nullptr;
+  g.band_idx = nullptr;
+  g.band_shift = 0;
+  while ((H >> g.band_shift) >= kBandsMax) ++g.band_shift;
   g.poly_n = (int32_t)L->V.size();
   g.poly_sign = area2 < 0 ? -1 : 1;
   L->area = L->V.empty() ? (double)W * (double)H : 0.5 * (double)std::llabs(area2);
@@ -462,6 +494,10 @@ struct ripk_plan_s {
   const double *cur_lam = nullptr;  // intensities of the current call (device)
   int4 *poly = nullptr;        // polygon edges {V[k], V[k+1 mod n]} (window-relative)
   uint32_t *prow = nullptr;    // per-record polygon rows (kRowWords words each)
+  uint32_t *band_off = nullptr;  // polygon edges by horizontal band (see Geom)
+  uint16_t *band_idx = nullptr;
+  std::vector<uint32_t> band_offh;  // host copies (sources of the upload)
+  std::vector<uint16_t> band_idxh;
   uint16_t *near = nullptr;    // per xy-cell edge lists of the bound geometry
   std::vector<uint16_t> nearh; // host copy of the lists (source of the upload)
   std::vector<int4> edgeh;     // host copy of the edges (source of the upload)
@@ -495,7 +531,7 @@ void release(ripk_plan_s *p) {
                   p->vals[1],
                   p->sort_temp, p->cs, p->P, p->chunks, p->offs, p->set_base, p->scan_temp,
                   p->items, p->binC, p->binW, p->outC, p->outW, p->outK, p->outL, p->env,
-                  p->Lobs, p->S2, p->T, p->poly, p->near, p->prow, p->lam, p->rho, p->scal, p->dstage,
+                  p->Lobs, p->S2, p->T, p->poly, p->near, p->prow, p->band_off, p->band_idx, p->lam, p->rho, p->scal, p->dstage,
                   p->wg_times};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
@@ -887,6 +923,8 @@ ripk_status plan_create(int device, const Caps &c, ripk_plan_s **out) {
   ALLOC(p->S2, kMaxSteps); ALLOC(p->T, kMaxSteps);
   ALLOC(p->poly, c.V); ALLOC(p->near, (kNearMax + 1) * c.NXY);
   if (c.V > 0) ALLOC(p->prow, (int64_t)kRowWords * c.N);
+  if (c.V > 0) ALLOC(p->band_off, kBandsMax + 1);
+  if (c.V > 0) ALLOC(p->band_idx, (int64_t)kBandsMax * c.V);
   ALLOC(p->lam, c.R); ALLOC(p->rho, c.R);
   ALLOC(p->scal, (kQueues + 1) * kQueueStride);
   ALLOC(p->dstage, kScalWords + kPackRows * c.NB);
@@ -1002,11 +1040,18 @@ ripk_status bind_geometry(ripk_plan_s *p, const ripk_plan_desc *desc, hipStream_
                           stream));
     HIPCHK(hipMemcpyAsync(p->near, p->nearh.data(), sizeof(uint16_t) * p->nearh.size(),
                           hipMemcpyHostToDevice, stream));
+    build_bands(p->lay, &p->band_offh, &p->band_idxh);
+    HIPCHK(hipMemcpyAsync(p->band_off, p->band_offh.data(), sizeof(uint32_t) * p->band_offh.size(),
+                          hipMemcpyHostToDevice, stream));
+    HIPCHK(hipMemcpyAsync(p->band_idx, p->band_idxh.data(), sizeof(uint16_t) * p->band_idxh.size(),
+                          hipMemcpyHostToDevice, stream));
     // the host sources are replaced by the next bind: let the copies finish
     HIPCHK(hipStreamSynchronize(stream));
     p->lay.g.poly = p->poly;
     p->lay.g.near = p->near;
     p->lay.g.prow = pair_poly(p->lay.g) ? p->prow : nullptr;
+    p->lay.g.band_off = p->band_off;
+    p->lay.g.band_idx = p->band_idx;
   }
   return RIPK_OK;
 }

@@ -50,7 +50,7 @@ __global__ void k_keys(const int32_t *__restrict__ x, const int32_t *__restrict_
   bool bad;
   uint32_t c = cell_of(x[i], y[i], t[i], g, &bad);
   // a polygon study area holds its points strictly inside
-  if (!bad && g.poly_n && !poly_inside(g.poly, g.poly_n, x[i] - g.x0, y[i] - g.y0)) bad = true;
+  if (!bad && g.poly_n && !poly_inside(g, x[i] - g.x0, y[i] - g.y0)) bad = true;
   if (bad) atomicOr(err, 1u);
   keys[i] = sort_key(set_base, c, i >= n_centres ? 1u : 0u, g, blocked != 0);
   vals[i] = i;
@@ -110,7 +110,7 @@ __global__ void k_csr(uint32_t n, uint32_t n_centres, uint32_t m, uint64_t seed,
     px = g.x0 + (int32_t)__umul64hi(r.v[0], W);
     py = g.y0 + (int32_t)__umul64hi(r.v[1], H);
     pt = g.t0 + (int32_t)__umul64hi(r.v[2], D);
-    if (!g.poly_n || poly_inside(g.poly, g.poly_n, px - g.x0, py - g.y0)) break;
+    if (!g.poly_n || poly_inside(g, px - g.x0, py - g.y0)) break;
     if (a + 1 == kMaxAttempts) {
       atomicOr(err, 2u);
       break;

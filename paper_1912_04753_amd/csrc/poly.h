@@ -15,22 +15,24 @@
 
 namespace ripk {
 
-// Strictly inside: crossing number along +x with the half-open rule, exact
-// integers; a point on an edge is not inside.
-__device__ __forceinline__ bool poly_inside(const int4 *__restrict__ E, int nv, int px, int py) {
+// Strictly inside: crossing number along +x with the half-open rule; a point
+// on an edge is not inside.  Only the edges of the point's horizontal band can
+// straddle its y or hold it.  The products are integers below 2^49, exact in
+// FP64.
+__device__ __forceinline__ bool poly_inside(const Geom &g, int px, int py) {
+  const uint32_t b = (uint32_t)py >> g.band_shift;
+  const uint32_t i1 = g.band_off[b + 1];
   bool in = false;
-  for (int k = 0; k < nv; ++k) {
-    const int4 e = E[k];  // a = (e.x, e.y), b = (e.z, e.w)
-    const long long ex = (long long)e.z - e.x, ey = (long long)e.w - e.y;
-    const long long qx = (long long)px - e.x, qy = (long long)py - e.y;
-    if (ex * qy == ey * qx && px >= min(e.x, e.z) && px <= max(e.x, e.z) &&
-        py >= min(e.y, e.w) && py <= max(e.y, e.w))
+  for (uint32_t i = g.band_off[b]; i < i1; ++i) {
+    const int4 e = g.poly[g.band_idx[i]];  // a = (e.x, e.y), b = (e.z, e.w)
+    const double ex = (double)(e.z - e.x), ey = (double)(e.w - e.y);
+    const double qx = (double)(px - e.x), qy = (double)(py - e.y);
+    const double lhs = qx * ey, num = qy * ex;
+    if (lhs == num && px >= min(e.x, e.z) && px <= max(e.x, e.z) && py >= min(e.y, e.w) &&
+        py <= max(e.y, e.w))
       return false;
-    if ((e.y > py) != (e.w > py)) {
-      // px left of the edge's crossing with the line y = py
-      const long long num = qy * ex, lhs = qx * ey;
-      if (ey > 0 ? lhs < num : lhs > num) in = !in;
-    }
+    // px left of the edge's crossing with the line y = py
+    if (((e.y > py) != (e.w > py)) && (ey > 0.0 ? lhs < num : lhs > num)) in = !in;
   }
   return in;
 }
@@ -222,14 +224,19 @@ __device__ __forceinline__ double poly_omega(const Geom &g, int px, int py, uint
     const uint32_t m = min(len - base, 32u);
     uint32_t keep = 0;
     if (!all) {
-      for (uint32_t i = 0; i < m; i += 4) {
-        const uint4 w = *(const uint4 *)(row + 4 + i);
+      // four entries per load, the next load issued before the current
+      // entries are tested
+      const uint4 *__restrict__ rw = (const uint4 *)(row + 4);
+      const uint32_t nq = (m + 3u) >> 2;
+      uint4 w = rw[0];
+      for (uint32_t q = 0; q < nq; ++q) {
         const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+        if (q + 1u < nq) w = rw[q + 1u];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const uint32_t lo = ws[u] & 0xFFFFu, hi = ws[u] >> 16;
           const bool k = __umul24(lo, lo) <= d2s && d2s <= __umul24(hi, hi);
-          keep |= (uint32_t)k << (i + u);
+          keep |= (uint32_t)k << (4u * q + (uint32_t)u);
         }
       }
     } else {
@@ -252,11 +259,18 @@ __device__ __forceinline__ double poly_omega(const Geom &g, int px, int py, uint
         keep |= (uint32_t)k << i;
       }
     }
+    // the next kept edge is loaded while the current one is worked
+    auto edge_at = [&](uint32_t i) { return all ? (int)(base + i) : (int)lst[1 + i]; };
+    int kn = keep ? edge_at((uint32_t)__builtin_ctz(keep)) : 0;
+    int4 en = keep ? E[kn] : make_int4(0, 0, 0, 0);
     while (keep) {
-      const uint32_t i = (uint32_t)__builtin_ctz(keep);
       keep &= keep - 1u;
-      const int kk = all ? (int)(base + i) : (int)lst[1 + i];
-      const int4 e = E[kk];
+      const int kk = kn;
+      const int4 e = en;
+      if (keep) {
+        kn = edge_at((uint32_t)__builtin_ctz(keep));
+        en = E[kn];
+      }
       const double ax = (double)(e.x - px), ay = (double)(e.y - py);
       const double bx = (double)(e.z - px), by = (double)(e.w - py);
       const double ex = bx - ax, ey = by - ay;

@@ -44,12 +44,19 @@ struct Geom {
   // per sorted record (spatial correction): its xy-cell, then the distance
   // range of each listed edge from the point (see poly_row); kRowWords words
   const uint32_t *prow;
+  // edges by horizontal band of height 2^band_shift: band b lists the edges
+  // whose y-range meets [b 2^shift, (b + 1) 2^shift), band_idx[band_off[b] ..
+  // band_off[b + 1])
+  const uint32_t *band_off;
+  const uint16_t *band_idx;
+  int32_t band_shift;
   int32_t poly_n;
   int32_t poly_sign;  // +1 counter-clockwise, -1 clockwise
 };
 constexpr int kMaxPoly = 4096;       // vertices of a polygon study area
 constexpr int kNearMax = 32;         // edges listed per cell (more: every edge is scanned)
 constexpr uint16_t kNearAll = 0xFFFF;
+constexpr int kBandsMax = 1024;       // horizontal bands of the containment test
 constexpr int kRowWords = 4 + kNearMax;  // per-record polygon row: 4-word head, a word per listed edge
 
 // Work item of the pair kernel: up to kChunk consecutive centres of one unit
