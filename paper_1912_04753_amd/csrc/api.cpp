@@ -414,6 +414,8 @@ ripk_status derive(const ripk_plan_desc *d, Layout *L) {
   g.poly = nullptr;
   g.near = nullptr;
   g.prow = nullptr;
+  g.row_shift = 0;
+  while ((((int64_t)d->s_max + 2) << (g.row_shift + 1)) <= 65535 && g.row_shift < 8) ++g.row_shift;
   g.band_off = nullptr;
   g.band_idx = nullptr;
   g.band_shift = 0;

@@ -242,8 +242,8 @@ struct Pieces {
 // and on the circle, at least 1/|E| from every edge line on the integer
 // lattice (|E| < 2^24.5), so omega >= 1/(pi |E| s_max) and the value stays
 // below 2^75.
-__device__ __forceinline__ double qweight_poly(double om, uint32_t half) {
-  return rint(poly_div(1.0, om) * (double)(1u << (kFracBits + half)));
+__device__ __forceinline__ double qweight_poly(double inv_om, uint32_t half) {
+  return rint(inv_om * (double)(1u << (kFracBits + half)));
 }
 
 // Polygon records (every distance mode), one per boundary side: {bin |
@@ -271,7 +271,7 @@ __device__ __forceinline__ void drain_b(WaveLds &W, QState &q, uint32_t c, int l
     if ((uint32_t)lane < c) {
       Pieces pc;
       const int4 p = P[r.z];
-      pc.add(qweight_poly(poly_omega(g, p.x, p.y, d2, r.z), (r.x >> 12) & 1u));
+      pc.add(qweight_poly(poly_inv_omega(g, p.x, p.y, d2, r.z), (r.x >> 12) & 1u));
       pc.commit(hw + 3 * bin);
     }
     q.hb = (q.hb + c) & (kQB - 1);

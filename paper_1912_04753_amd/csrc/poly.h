@@ -81,9 +81,10 @@ __device__ __forceinline__ int32_t poly_edist(const Geom &g, int px, int py, int
 
 // The row of a point for the weight: its xy-cell (word 0 of a 4-word head),
 // then from word 4, for each edge of the cell's list, the range [lo, hi] of
-// distances from the point to the edge's points, in metres as 16-bit integers
-// (lo | hi << 16), lo rounded down and hi up with a margin well above the FP64
-// error: a circle about the point meets the edge only if lo <= radius <= hi.
+// distances from the point to the edge's points, in units of 2^-row_shift
+// metres as 16-bit integers (lo | hi << 16; (s_max + 2) 2^row_shift < 2^16),
+// lo rounded down and hi up by a unit beyond the FP64 error: a circle about
+// the point meets the edge only if lo <= radius <= hi.
 // Entries up to the next multiple of 4 hold an empty range (lo > hi).  Cells
 // that scan every edge keep only the cell.
 __device__ __forceinline__ void poly_row(const Geom &g, int px, int py, uint32_t *__restrict__ row) {
@@ -101,8 +102,9 @@ __device__ __forceinline__ void poly_row(const Geom &g, int px, int py, uint32_t
     const double ee = ex * ex + ey * ey;
     const double s = fmin(fmax(ee > 0.0 ? -(ax * ex + ay * ey) / ee : 0.0, 0.0), 1.0);
     const double dx = ax + s * ex, dy = ay + s * ey;
-    const double lo = fmax(floor(sqrt(dx * dx + dy * dy) * (1.0 - 1e-12)) - 1.0, 0.0);
-    const double hi = ceil(sqrt(fmax(ax * ax + ay * ay, bx * bx + by * by)) * (1.0 + 1e-12)) + 1.0;
+    const double u = ldexp(1.0, g.row_shift);
+    const double lo = fmax(floor(sqrt(dx * dx + dy * dy) * u * (1.0 - 1e-12)) - 1.0, 0.0);
+    const double hi = ceil(sqrt(fmax(ax * ax + ay * ay, bx * bx + by * by)) * u * (1.0 + 1e-12)) + 1.0;
     row[4 + i] = (uint32_t)fmin(lo, 65535.0) | ((uint32_t)fmin(hi, 65535.0) << 16);
   }
 }
@@ -161,11 +163,11 @@ __device__ __forceinline__ double poly_sqrt(double x) {
   return fma(fma(-s, s, x), 0.5 * r, s);
 }
 
-// Share of the circle centred on the window-relative point (px, py), strictly
-// inside the polygon, with radius sqrt(d2) inside the polygon; rec is the
-// point's sorted record (its row, see poly_row).  The circle passes through
-// the pair's other point, also strictly inside, so a circle that crosses the
-// boundary nowhere lies inside.
+// 1/omega, omega the share of the circle centred on the window-relative point
+// (px, py), strictly inside the polygon, with radius sqrt(d2) inside the
+// polygon; rec is the point's sorted record (its row, see poly_row).  The
+// circle passes through the pair's other point, also strictly inside, so a
+// circle that crosses the boundary nowhere lies inside (1/omega = 1).
 //
 // Walking the circle counter-clockwise, the inside length is the sum of the
 // exit angles minus the sum of the entry angles, plus 2 pi when the walk
@@ -196,8 +198,8 @@ __device__ __forceinline__ double poly_sqrt(double x) {
 // single pass paid for the crossing work at almost every entry, while a
 // circle meets few of them (two, near a smooth boundary).  Cells that scan
 // every edge (more than 32 near it) take the first pass on exact integers.
-__device__ __forceinline__ double poly_omega(const Geom &g, int px, int py, uint64_t d2u,
-                                             uint32_t rec) {
+__device__ __forceinline__ double poly_inv_omega(const Geom &g, int px, int py, uint64_t d2u,
+                                                 uint32_t rec) {
   if (d2u == 0) return 1.0;
   const int4 *__restrict__ E = g.poly;
   const int nv = g.poly_n;
@@ -218,8 +220,8 @@ __device__ __forceinline__ double poly_omega(const Geom &g, int px, int py, uint
   const uint16_t *__restrict__ lst = g.near + (size_t)row[0] * (kNearMax + 1);
   const bool all = lst[0] == kNearAll;
   const uint32_t len = all ? (uint32_t)nv : (uint32_t)lst[0];
-  // d2 is at most s_max^2 < 2^27 here
-  const uint32_t d2s = (uint32_t)d2u;
+  // the squared radius in the row's units: d2 <= s_max^2, so below 2^32
+  const uint32_t d2s = (uint32_t)d2u << (2 * g.row_shift);
   for (uint32_t base = 0; base < len; base += 32) {
     const uint32_t m = min(len - base, 32u);
     uint32_t keep = 0;
@@ -319,8 +321,7 @@ __device__ __forceinline__ double poly_omega(const Geom &g, int px, int py, uint
     }
   }
   if (!crossed) return 1.0;
-  const double two_pi = 6.283185307179586476925;
-  return poly_angle(Px, Py) / two_pi;
+  return poly_div(6.283185307179586476925, poly_angle(Px, Py));
 }
 
 }  // namespace ripk

@@ -44,6 +44,7 @@ struct Geom {
   // per sorted record (spatial correction): its xy-cell, then the distance
   // range of each listed edge from the point (see poly_row); kRowWords words
   const uint32_t *prow;
+  int32_t row_shift;  // rows hold distances in units of 2^-row_shift metres
   // edges by horizontal band of height 2^band_shift: band b lists the edges
   // whose y-range meets [b 2^shift, (b + 1) 2^shift), band_idx[band_off[b] ..
   // band_off[b + 1])
