@@ -316,13 +316,13 @@ def main():
         return
     dev = ripk.ripk_device_query(0)
     PEAK["lane_ops"] = dev["compute_units"] * 64 * dev["clock_khz"] * 1e3
+    if args.copy_calibration:
+        copy_calibration(torch)
     if args.polygon_only:
         st = torch.cuda.current_stream().cuda_stream
         print(json.dumps({"polygon": polygon_leg(ripk, workloads, torch, st, steps=args.steps)}),
               flush=True)
         return
-    if args.copy_calibration:
-        copy_calibration(torch)
     cfg = workloads.workload("uniform-100k-99csr")
     x, y, t = workloads.make_points(cfg)
     n, m = len(x), cfg["sims"]
