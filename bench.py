@@ -502,7 +502,7 @@ def main():
     # the two larger workloads, autotuned: 200k clustered points (observed K), and
     # 1M uniform + 1M clustered points with 19 CSR simulations
     larger = {}
-    for wname, reps in (("thomas-200k", 3), ("mixed-2M-19csr", 2)):
+    for wname, reps in (("thomas-200k", 10), ("mixed-2M-19csr", 2)):
         wc = workloads.workload(wname)
         wx, wy, wt = (torch.from_numpy(a).cuda() for a in workloads.make_points(wc))
         wn, wm = len(wx), wc["sims"]
@@ -524,13 +524,40 @@ def main():
         t_w = time.perf_counter()
         ws = [wstep() for _ in range(reps)]
         torch.cuda.synchronize()
-        w_ms = 1e3 * (time.perf_counter() - t_w) / reps
+        w_ms_timed = 1e3 * (time.perf_counter() - t_w) / reps
         wi = ripk.ripk_plan_get_info(wplan)
+        # the same calls through an autotuned plan without per-phase timing (its
+        # events and the workgroup-time read-back are diagnostics): the step time
+        uplan = ripk.ripk_plan(ripk.make_desc(wc["window"], wc["s_max"], wc["t_max"], wc["n_s"],
+                                              wc["n_t"], n_max=wn, m_max=wm,
+                                              flags=ripk.RIPK_PLAN_AUTOTUNE))
+
+        def ustep():
+            if wm == 0:
+                ripk.ripk_compute_K(uplan, wx, wy, wt, stream=stream)
+            else:
+                ripk.ripk_compute_K_envelope(uplan, wx, wy, wt, wm, wc["seed"], stream=stream)
+
+        ustep()  # tuning
+        ustep()
+        torch.cuda.synchronize()
+        t_u = time.perf_counter()
+        for _ in range(reps):
+            ustep()
+        torch.cuda.synchronize()
+        w_ms = 1e3 * (time.perf_counter() - t_u) / reps
+        ui = ripk.ripk_plan_get_info(uplan)
+        uplan.destroy()
         larger[wname] = {"ms_per_step": round(w_ms, 3),
                          "pair_tests_per_s_G": round(ws[0][0] / (w_ms * 1e-3) / 1e9, 3),
                          "n_in_per_step": ws[0][0],
-                         "sims_per_s": round(wm / (sum(v[1] for v in ws) / reps), 3) if wm else None,
-                         "cells_m_s": [wi["cell_s"], wi["cell_t"]],
+                         "sims_per_s": round(wm / (w_ms * 1e-3), 3) if wm else None,
+                         "cells_m_s": [ui["cell_s"], ui["cell_t"]],
+                         "timed_plan": {"ms_per_step": round(w_ms_timed, 3),
+                                        "cells_m_s": [wi["cell_s"], wi["cell_t"]],
+                                        "phases_us": {k: round(sum(v[2][k] for v in ws) / reps, 1)
+                                                      for k in ("us_gen", "us_grid", "us_pair",
+                                                                "us_finalize")}},
                          "split": ripk.ripk_plan_stats(wplan)["split"],
                          "roofline": leg_roof(ws[0][2], sum(v[2]["us_pair"] for v in ws) / reps),
                          "cost_ordered": ws[0][2]["cost_ordered"],

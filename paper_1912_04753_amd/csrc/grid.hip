@@ -492,6 +492,16 @@ __device__ __forceinline__ uint32_t chunk_walk(const uint32_t *__restrict__ cs, 
   uint32_t c = 0, items = 0;
   while (pos < end) {
     while (cs[ci.at(c0 + c) + 1] <= pos) ++c;  // cell holding pos (row units: no halo entries)
+    // while kChunk centres remain in this cell the greedy item is exactly
+    // those kChunk: emit the whole run of them without reloading the bounds
+    const uint32_t ce = cs[ci.at(c0 + c) + 1];
+    if (ce - pos >= (uint32_t)kChunk) {
+      const uint32_t k = (ce - pos) / (uint32_t)kChunk;
+      for (uint32_t j = 0; j < k; ++j) emit(pos + j * (uint32_t)kChunk, (uint32_t)kChunk);
+      items += k;
+      pos += k * (uint32_t)kChunk;
+      continue;
+    }
     const uint32_t last = min(c + (uint32_t)kItemExtent, unit - 1);
     const uint32_t lim = min(min(pos + (uint32_t)kChunk, end), cs[ci.at(c0 + last) + 1]);
     emit(pos, lim - pos);
