@@ -299,3 +299,41 @@ def test_polygon_plan_size_limit():
     assert e.value.status == ripk.RIPK_EINVAL
     ripk.ripk_plan_check(ripk.make_desc(*args, n_max=(1 << 22) - 1, poly=L_SHAPE))
     ripk.ripk_plan_check(ripk.make_desc(*args, n_max=1 << 22, poly=L_SHAPE, edge=2))
+
+
+HOUSE = [(0, 0), (64, 0), (64, 16), (40, 16), (40, 40), (32, 47), (24, 40), (24, 16), (0, 16)]
+
+
+def test_polygon_small_lattice_window_against_oracle():
+    """A 64 m x 48 m window on the integer lattice: band lists one metre high
+    (every vertex y starts a band), many CSR attempts land exactly on edges or
+    vertices and must be rejected, repeated points give d = 0, and many circles
+    pass through vertices.  Observed set and three CSR simulations against the
+    oracle, counts bit for bit."""
+    win = (0, 0, 64, 48, 0, 1000)
+    args = (win, 8, 200, 4, 2)
+    rng = np.random.default_rng(72)
+    P = np.asarray(HOUSE)
+    xs, ys = [], []
+    while sum(len(a) for a in xs) < 1500:
+        x = rng.integers(0, 65, 4096)
+        y = rng.integers(0, 49, 4096)
+        ok = workloads._strictly_inside(P, x, y)
+        xs.append(x[ok]); ys.append(y[ok])
+    x = np.concatenate(xs)[:1500].astype(np.int32)
+    y = np.concatenate(ys)[:1500].astype(np.int32)
+    t = rng.integers(0, 1000, 1500).astype(np.int32)
+    n, m, seed = len(x), 3, 123
+    say("polygon small lattice window n=%d m=%d" % (n, m))
+    d = oracle.desc(*args, poly=HOUSE)
+    r = oracle.estimate(d, x, y, t)
+    ref = oracle.envelope(d, n, m, seed)
+    plan = ripk.ripk_plan(ripk.make_desc(*args, n_max=n, m_max=m, poly=HOUSE))
+    try:
+        g = ripk.ripk_compute_K(plan, x, y, t)
+        gs = ripk.ripk_simulate_envelope(plan, n, m, seed, L_obs=g["L"], per_sim=True)
+    finally:
+        plan.destroy()
+    compare(g, r, *args[1:], where="polygon small lattice window")
+    assert np.array_equal(gs["C_sims"], ref["C_sims"].astype(np.uint64))
+    np.testing.assert_allclose(gs["K_sims"], ref["K_sims"], rtol=1e-6, atol=0)
