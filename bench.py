@@ -22,6 +22,7 @@ sample of centres of the 200k clustered set.
 import argparse
 import json
 import os
+import subprocess
 import sys
 import threading
 import time
@@ -541,11 +542,16 @@ def main():
         ustep()  # tuning
         ustep()
         torch.cuda.synchronize()
-        t_u = time.perf_counter()
+        # each call returns its results to the host (it ends synchronised), so
+        # calls are timed one by one; the step time is their median (a single
+        # host-side stall would otherwise dominate a mean of ~1 ms calls)
+        u_ms = []
         for _ in range(reps):
+            t_u = time.perf_counter()
             ustep()
+            u_ms.append(1e3 * (time.perf_counter() - t_u))
         torch.cuda.synchronize()
-        w_ms = 1e3 * (time.perf_counter() - t_u) / reps
+        w_ms = sorted(u_ms)[len(u_ms) // 2]
         ui = ripk.ripk_plan_get_info(uplan)
         uplan.destroy()
         larger[wname] = {"ms_per_step": round(w_ms, 3),
@@ -553,6 +559,7 @@ def main():
                          "n_in_per_step": ws[0][0],
                          "sims_per_s": round(wm / (w_ms * 1e-3), 3) if wm else None,
                          "cells_m_s": [ui["cell_s"], ui["cell_t"]],
+                         "ms_per_call_mean": round(sum(u_ms) / len(u_ms), 3),
                          "timed_plan": {"ms_per_step": round(w_ms_timed, 3),
                                         "cells_m_s": [wi["cell_s"], wi["cell_t"]],
                                         "phases_us": {k: round(sum(v[2][k] for v in ws) / reps, 1)
@@ -629,8 +636,16 @@ def main():
                              f"ordered pair (bin + weight)"},
     }
     if args.serve_requests > 0:
-        out["serving"] = serving(ripk, workloads, args.serve_requests, args.serve_slots,
-                                 args.serve_load)
+        # in a process of its own: the plans and cached device memory of the
+        # legs above would otherwise stay with the serving measurement
+        torch.cuda.synchronize()
+        cmd = [sys.executable, os.path.abspath(__file__), "--serve-only",
+               "--serve-requests", str(args.serve_requests), "--serve-slots", str(args.serve_slots),
+               "--serve-load", str(args.serve_load)]
+        res = subprocess.run(cmd, stdout=subprocess.PIPE, text=True, check=True)
+        out["serving"] = json.loads([ln for ln in res.stdout.splitlines()
+                                     if ln.startswith("{")][-1])["serving"]
+        out["serving"]["process"] = "own process (bench.py --serve-only)"
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, x, y, t, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -1078,14 +1078,19 @@ ripk_status run_tuned(ripk_plan_s *p, int which, uint32_t S, uint32_t S_tune, ui
     if (!ts.done) {
       double best = 1e300;
       int bi = 0;
-      for (int i = 0; i < n_cand; ++i) {
-        d.cell_div = kTuneCand[i % kTuneN][0];
-        d.tcell_div = kTuneCand[i % kTuneN][1];
-        p->split_runs = forced || i >= kTuneN;
-        ripk_status s = bind_geometry(p, &d, st);
-        if (s != RIPK_OK) return s;
-        ts.us[i] = 1e300;
-        for (int rep = 0; rep < 2; ++rep) {  // best of two: candidates can be a few % apart
+      for (int i = 0; i < n_cand; ++i) ts.us[i] = 1e300;
+      // one untimed run first, then the candidates in two rounds, each kept at
+      // its faster run: candidates can be a few % apart, and a device still
+      // raising its clock at the start of the call would otherwise favour the
+      // ones timed last
+      for (int rep = -1; rep < 2; ++rep) {
+        for (int i = 0; i < n_cand; ++i) {
+          if (rep < 0 && i > 0) break;
+          d.cell_div = kTuneCand[i % kTuneN][0];
+          d.tcell_div = kTuneCand[i % kTuneN][1];
+          p->split_runs = forced || i >= kTuneN;
+          ripk_status s = bind_geometry(p, &d, st);
+          if (s != RIPK_OK) return s;
           HIPCHK(hipEventRecord(p->tev[0], st));
           s = run_sets(p, S_tune, n, nc, x, y, t, simulate, seed, nullptr, st, sym, S, with_obs);
           if (s != RIPK_OK) return s;
@@ -1096,13 +1101,14 @@ ripk_status run_tuned(ripk_plan_s *p, int which, uint32_t S, uint32_t S_tune, ui
           if (err) return err_status(err);
           float ms = 0;
           HIPCHK(hipEventElapsedTime(&ms, p->tev[0], p->tev[1]));
-          ts.us[i] = std::min(ts.us[i], 1e3 * (double)ms);
+          if (rep >= 0) ts.us[i] = std::min(ts.us[i], 1e3 * (double)ms);
         }
+      }
+      for (int i = 0; i < n_cand; ++i)
         if (ts.us[i] < best) {
           best = ts.us[i];
           bi = i;
         }
-      }
       ts.done = true;
       ts.cd = kTuneCand[bi % kTuneN][0];
       ts.td = kTuneCand[bi % kTuneN][1];
