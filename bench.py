@@ -539,8 +539,8 @@ def main():
             else:
                 ripk.ripk_compute_K_envelope(uplan, wx, wy, wt, wm, wc["seed"], stream=stream)
 
-        ustep()  # tuning
-        ustep()
+        for _ in range(3):  # tuning, warm-up
+            ustep()
         torch.cuda.synchronize()
         # each call returns its results to the host (it ends synchronised), so
         # calls are timed one by one; the step time is their median (a single
@@ -560,6 +560,7 @@ def main():
                          "sims_per_s": round(wm / (w_ms * 1e-3), 3) if wm else None,
                          "cells_m_s": [ui["cell_s"], ui["cell_t"]],
                          "ms_per_call_mean": round(sum(u_ms) / len(u_ms), 3),
+                         "ms_per_call": [round(v, 3) for v in u_ms],
                          "timed_plan": {"ms_per_step": round(w_ms_timed, 3),
                                         "cells_m_s": [wi["cell_s"], wi["cell_t"]],
                                         "phases_us": {k: round(sum(v[2][k] for v in ws) / reps, 1)
