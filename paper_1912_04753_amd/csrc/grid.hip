@@ -315,8 +315,15 @@ __global__ void k_scan_down(const uint32_t *__restrict__ in, uint32_t n,
 // straddle a segment.  Digit counts are laid out (segment, digit, tile), so
 // their exclusive scan gives each tile's start for each digit.  One segment
 // with stride 0 is a plain sort.
-constexpr int kSortItems = 16;
-constexpr int kSortTile = kThreads * kSortItems;
+// Keys per thread of a tile: 16 (4,096 keys per workgroup), or 4 for sorts of
+// at most kSmallSort keys, which would otherwise run on too few workgroups
+// (a 200k-key pass on 49 of them was latency-bound in its 16 serial rounds).
+constexpr uint32_t kSortItems = 16;
+constexpr uint32_t kSortItemsSmall = 4;
+constexpr uint32_t kSmallSort = 1u << 20;
+__host__ __device__ inline uint32_t sort_items(uint32_t n) {
+  return n <= kSmallSort ? kSortItemsSmall : kSortItems;
+}
 
 struct SortTile {
   uint32_t seg, t, base, end, key0;
@@ -337,8 +344,9 @@ __device__ __forceinline__ SortTile sort_tile(const SortSeg &sg, uint32_t b) {
   SortTile r;
   r.seg = b / sg.tiles;
   r.t = b - r.seg * sg.tiles;
-  r.base = r.seg * sg.len + r.t * kSortTile;
-  r.end = min(r.base + (uint32_t)kSortTile, (r.seg + 1) * sg.len);
+  const uint32_t tile = (uint32_t)kThreads * sg.items;
+  r.base = r.seg * sg.len + r.t * tile;
+  r.end = min(r.base + tile, (r.seg + 1) * sg.len);
   r.key0 = r.seg * sg.stride;
   return r;
 }
@@ -353,7 +361,7 @@ __global__ void k_sort_hist(const uint32_t *__restrict__ keys, SortSeg sg, int s
   const SortTile tl = sort_tile(sg, blockIdx.x);
   h[threadIdx.x] = 0;
   __syncthreads();
-  for (int k = 0; k < kSortItems; ++k) {
+  for (uint32_t k = 0; k < sg.items; ++k) {
     uint32_t i = tl.base + k * kThreads + threadIdx.x;
     if (i < tl.end) atomicAdd(&h[((keys[i] - tl.key0) >> shift) & mask], 1u);
   }
@@ -377,7 +385,7 @@ __global__ void k_sort_scatter(const uint32_t *__restrict__ keys,
   for (int q = 0; q < kThreads / 64; ++q) wc[q][threadIdx.x] = 0;
   __syncthreads();
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  for (int k = 0; k < kSortItems; ++k) {
+  for (uint32_t k = 0; k < sg.items; ++k) {
     uint32_t i = tl.base + k * kThreads + threadIdx.x;
     bool valid = i < tl.end;
     uint32_t key = valid ? keys[i] : 0u;
@@ -715,7 +723,11 @@ hipError_t exclusive_scan(const uint32_t *in, uint32_t *out, uint32_t n, void *t
 
 size_t radix_sort_temp_bytes(uint32_t n, uint32_t n_segs) {
   // tiles: at most one partial tile per segment beyond the whole ones
-  size_t nb = blocks_for(n > 0 ? n : 1, kSortTile) + n_segs;
+  // (the tile is smaller for small sorts: the larger of the two block counts)
+  const uint32_t m = n > 0 ? n : 1;
+  size_t nb = std::max<size_t>(blocks_for(m, kThreads * kSortItems),
+                               blocks_for(std::min(m, kSmallSort), kThreads * kSortItemsSmall)) +
+              n_segs;
   size_t cnt = 256 * nb;
   return sizeof(uint32_t) * (2 * cnt + 1) + scan_temp_bytes((uint32_t)cnt) + 256;
 }
@@ -728,7 +740,8 @@ hipError_t radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32
   if (n_segs == 0 || n % n_segs != 0) return hipErrorInvalidValue;
   SortSeg sg;
   sg.len = n / n_segs;
-  sg.tiles = blocks_for(sg.len, kSortTile);
+  sg.items = sort_items(n);
+  sg.tiles = blocks_for(sg.len, kThreads * sg.items);
   sg.stride = n_segs > 1 ? seg_stride : 0u;
   const uint32_t nb = n_segs * sg.tiles;
   size_t cnt = 256 * (size_t)nb;

@@ -227,6 +227,7 @@ hipError_t launch_resample(int method, uint32_t n, uint32_t n_centres, uint32_t 
 // each segment is sorted by key - g*seg_stride, key_bits covering seg_stride.
 struct SortSeg {
   uint32_t len, tiles, stride;
+  uint32_t items;  // keys per thread of a tile (tile = 256 threads x items)
 };
 size_t radix_sort_temp_bytes(uint32_t n, uint32_t n_segs = 1);
 hipError_t radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt,
