@@ -79,19 +79,21 @@ __device__ __forceinline__ int32_t poly_edist(const Geom &g, int px, int py, int
   return (int32_t)fmax(floor(sqrt(best * (1.0 - 1e-12))) - 1.0, 0.0);
 }
 
-// The row of a point for the weight: its xy-cell (word 0 of a 4-word head),
+// The row of a point for the weight: its xy-cell and the length of the cell's
+// list (words 0 and 1 of a 4-word head),
 // then from word 4, for each edge of the cell's list, the range [lo, hi] of
 // distances from the point to the edge's points, in units of 2^-row_shift
 // metres as 16-bit integers (lo | hi << 16; (s_max + 2) 2^row_shift < 2^16),
 // lo rounded down and hi up by a unit beyond the FP64 error: a circle about
 // the point meets the edge only if lo <= radius <= hi.
 // Entries up to the next multiple of 4 hold an empty range (lo > hi).  Cells
-// that scan every edge keep only the cell.
+// that scan every edge keep only the head.
 __device__ __forceinline__ void poly_row(const Geom &g, int px, int py, uint32_t *__restrict__ row) {
   const uint32_t cell = poly_cell(g, px, py);
-  row[0] = cell;
   const uint16_t *lst = g.near + (size_t)cell * (kNearMax + 1);
   const uint32_t cnt = lst[0];
+  row[0] = cell;
+  row[1] = cnt;
   if (cnt == kNearAll) return;
   for (uint32_t i = cnt; i < ((cnt + 3u) & ~3u); ++i) row[4 + i] = 0xFFFFu;
   for (uint32_t i = 0; i < cnt; ++i) {
@@ -217,9 +219,10 @@ __device__ __forceinline__ double poly_inv_omega(const Geom &g, int px, int py, 
     crossed = true;
   };
   const uint32_t *__restrict__ row = g.prow + (size_t)rec * kRowWords;
-  const uint16_t *__restrict__ lst = g.near + (size_t)row[0] * (kNearMax + 1);
-  const bool all = lst[0] == kNearAll;
-  const uint32_t len = all ? (uint32_t)nv : (uint32_t)lst[0];
+  const uint2 head = *(const uint2 *)row;  // the cell and its list length, one load
+  const uint16_t *__restrict__ lst = g.near + (size_t)head.x * (kNearMax + 1);
+  const bool all = head.y == kNearAll;
+  const uint32_t len = all ? (uint32_t)nv : head.y;
   // the squared radius in the row's units: d2 <= s_max^2, so below 2^32
   const uint32_t d2s = (uint32_t)d2u << (2 * g.row_shift);
   for (uint32_t base = 0; base < len; base += 32) {
