@@ -203,7 +203,11 @@ typedef struct {
  *     2*s_max <= min(x1-x0, y1-y0) does not apply;
  *   - with RIPK_EDGE_SPATIAL_ISO, n_max must be below 2^22 (RIPK_EINVAL);
  *   - CSR simulations draw by rejection: attempt a of point k of set s uses the
- *     Philox counter (k, s, a, 0) and the first attempt strictly inside is kept.
+ *     Philox counter (k, s, a, 0) and the first attempt strictly inside is kept;
+ *   - device memory (in ripk_plan_info.device_bytes): besides the edges and
+ *     their per-cell and per-band lists, a polygon plan keeps 144 bytes per
+ *     point of its largest call (S * n_max points: each point's distance range
+ *     to every nearby edge, which the weight reads).
  * The vertex array is read during ripk_plan_check, ripk_plan and ripk_submit
  * and copied; the caller keeps ownership.
  */
