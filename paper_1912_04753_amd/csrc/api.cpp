@@ -132,8 +132,6 @@ double seg_point_d2(double ax, double ay, double bx, double by, double px, doubl
   return dx * dx + dy * dy;
 }
 
-// Per xy-cell lists of the edges within s_max (plus a margin) of the cell's
-// rectangle (the last cell of an axis reaches the window's side).
 // Edges by horizontal band of height 2^band_shift (the containment test's
 // lists): band b holds every edge whose closed y-range meets the band.
 void build_bands(const Layout &L, std::vector<uint32_t> *off, std::vector<uint16_t> *idx) {
@@ -161,6 +159,8 @@ void build_bands(const Layout &L, std::vector<uint32_t> *off, std::vector<uint16
   }
 }
 
+// Per xy-cell lists of the edges within s_max (plus a margin) of the cell's
+// rectangle (the last cell of an axis reaches the window's side).
 void build_near(const Layout &L, int64_t s_max, std::vector<uint16_t> *out) {
   const Geom &g = L.g;
   const int nv = (int)L.V.size();
@@ -533,8 +533,8 @@ void release(ripk_plan_s *p) {
                   p->vals[1],
                   p->sort_temp, p->cs, p->P, p->chunks, p->offs, p->set_base, p->scan_temp,
                   p->items, p->binC, p->binW, p->outC, p->outW, p->outK, p->outL, p->env,
-                  p->Lobs, p->S2, p->T, p->poly, p->near, p->prow, p->band_off, p->band_idx, p->lam, p->rho, p->scal, p->dstage,
-                  p->wg_times};
+                  p->Lobs, p->S2, p->T, p->poly, p->near, p->prow, p->band_off, p->band_idx,
+                  p->lam, p->rho, p->scal, p->dstage, p->wg_times};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   if (p->hstage) (void)hipHostFree(p->hstage);

@@ -6,10 +6,12 @@
 // Vertices are window-relative int32 (coordinates below 2^24), so every vector
 // product below is an integer below 2^52, exact in FP64, and the circle-edge
 // discriminant is exact in 128-bit integers where its sign is in doubt.
-// Edges are (V[k], V[k+1 mod n]), one int4 {a, b} each.  Each xy-cell of the grid lists the edges
-// within s_max of the cell ({count, index...}, kNearMax + 1 u16 words; count
-// kNearAll = every edge): a circle of radius <= s_max centred in the cell meets
-// no other edge.
+// Edges are (V[k], V[k+1 mod n]), one int4 {a, b} each.  Each xy-cell of the
+// grid lists the edges within s_max of the cell ({count, index...}, kNearMax +
+// 1 u16 words; count kNearAll = every edge): a circle of radius <= s_max
+// centred in the cell meets no other edge.  Each horizontal band of the window
+// lists the edges whose y-range meets it (containment), and each sorted point
+// record has a row of distance ranges to its cell's edges (poly_row).
 #pragma once
 #include "ripk_internal.h"
 
@@ -79,13 +81,12 @@ __device__ __forceinline__ int32_t poly_edist(const Geom &g, int px, int py, int
   return (int32_t)fmax(floor(sqrt(best * (1.0 - 1e-12))) - 1.0, 0.0);
 }
 
-// The row of a point for the weight: its xy-cell and the length of the cell's
-// list (words 0 and 1 of a 4-word head),
-// then from word 4, for each edge of the cell's list, the range [lo, hi] of
-// distances from the point to the edge's points, in units of 2^-row_shift
-// metres as 16-bit integers (lo | hi << 16; (s_max + 2) 2^row_shift < 2^16),
-// lo rounded down and hi up by a unit beyond the FP64 error: a circle about
-// the point meets the edge only if lo <= radius <= hi.
+// The row of a point for the weight: a 4-word head holding its xy-cell and the
+// length of that cell's list, then from word 4, for each edge of the list, the
+// range [lo, hi] of distances from the point to the edge's points, in units of
+// 2^-row_shift metres as 16-bit integers (lo | hi << 16; (s_max + 2)
+// 2^row_shift < 2^16), lo rounded down and hi up by a unit beyond the FP64
+// error: a circle about the point meets the edge only if lo <= radius <= hi.
 // Entries up to the next multiple of 4 hold an empty range (lo > hi).  Cells
 // that scan every edge keep only the head.
 __device__ __forceinline__ void poly_row(const Geom &g, int px, int py, uint32_t *__restrict__ row) {
@@ -96,6 +97,7 @@ __device__ __forceinline__ void poly_row(const Geom &g, int px, int py, uint32_t
   row[1] = cnt;
   if (cnt == kNearAll) return;
   for (uint32_t i = cnt; i < ((cnt + 3u) & ~3u); ++i) row[4 + i] = 0xFFFFu;
+  const double u = ldexp(1.0, g.row_shift);
   for (uint32_t i = 0; i < cnt; ++i) {
     const int4 e = g.poly[lst[1 + i]];
     const double ax = (double)(e.x - px), ay = (double)(e.y - py);
@@ -104,7 +106,6 @@ __device__ __forceinline__ void poly_row(const Geom &g, int px, int py, uint32_t
     const double ee = ex * ex + ey * ey;
     const double s = fmin(fmax(ee > 0.0 ? -(ax * ex + ay * ey) / ee : 0.0, 0.0), 1.0);
     const double dx = ax + s * ex, dy = ay + s * ey;
-    const double u = ldexp(1.0, g.row_shift);
     const double lo = fmax(floor(sqrt(dx * dx + dy * dy) * u * (1.0 - 1e-12)) - 1.0, 0.0);
     const double hi = ceil(sqrt(fmax(ax * ax + ay * ay, bx * bx + by * by)) * u * (1.0 + 1e-12)) + 1.0;
     row[4 + i] = (uint32_t)fmin(lo, 65535.0) | ((uint32_t)fmin(hi, 65535.0) << 16);
