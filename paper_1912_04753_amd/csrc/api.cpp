@@ -452,6 +452,7 @@ struct ripk_plan_s {
   ripk_plan_desc user_desc;  // descriptor as given (autotuning varies the cells)
   TuneState tune[2];         // [0] observed sets, [1] simulations
   hipEvent_t tev[2] = {};    // autotuner timing
+  bool tuning = false;       // autotuner trials in progress (eager launches)
   Layout lay;
   int32_t bound_cd = 1, bound_td = 1;  // cell subdivisions of the bound geometry
   bool split_runs = false;             // run fractions for this call's launch
@@ -771,7 +772,8 @@ ripk_status run_sets(ripk_plan_s *p, uint32_t S, uint32_t n, uint32_t n_centres,
   const bool has_Lobs = simulate && L_obs != nullptr;
   if (has_Lobs) HIPCHK(hipMemcpyAsync(p->Lobs, L_obs, sizeof(double) * NB, hipMemcpyHostToDevice, st));
   const bool timing = (p->desc.flags & RIPK_PLAN_TIMING) != 0;
-  const bool graph = (p->desc.flags & RIPK_PLAN_GRAPH) && !timing && st != nullptr;
+  // (autotuner trials run eager: a capture inside a timed trial would count)
+  const bool graph = (p->desc.flags & RIPK_PLAN_GRAPH) && !timing && st != nullptr && !p->tuning;
   if (!graph)
     return enqueue_sets(p, S, n, n_centres, x, y, t, simulate, seed, has_Lobs, st, symmetric, timing,
                         S_split, with_obs);
@@ -1078,6 +1080,11 @@ ripk_status run_tuned(ripk_plan_s *p, int which, uint32_t S, uint32_t S_tune, ui
     if (!ts.done) {
       double best = 1e300;
       int bi = 0;
+      struct Tuning {  // trials run eager, whatever way the tuning ends
+        ripk_plan_s *p;
+        ~Tuning() { p->tuning = false; }
+      } tuning_scope{p};
+      p->tuning = true;
       for (int i = 0; i < n_cand; ++i) ts.us[i] = 1e300;
       // one untimed run first, then the candidates in two rounds, each kept at
       // its faster run: candidates can be a few % apart, and a device still
