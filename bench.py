@@ -649,10 +649,13 @@ def main():
         cmd = [sys.executable, os.path.abspath(__file__), "--serve-only",
                "--serve-requests", str(args.serve_requests), "--serve-slots", str(args.serve_slots),
                "--serve-load", str(args.serve_load)]
-        res = subprocess.run(cmd, stdout=subprocess.PIPE, text=True, check=True)
-        out["serving"] = json.loads([ln for ln in res.stdout.splitlines()
-                                     if ln.startswith("{")][-1])["serving"]
-        out["serving"]["process"] = "own process (bench.py --serve-only)"
+        res = subprocess.run(cmd, stdout=subprocess.PIPE, text=True)
+        lines = [ln for ln in res.stdout.splitlines() if ln.startswith("{")]
+        if res.returncode == 0 and lines:
+            out["serving"] = json.loads(lines[-1])["serving"]
+            out["serving"]["process"] = "own process (bench.py --serve-only)"
+        else:
+            out["serving"] = {"error": f"serving process exited with status {res.returncode}"}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, x, y, t, args.cpu_seconds)
     print(json.dumps(out), flush=True)
