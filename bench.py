@@ -386,6 +386,7 @@ def main():
                           "unit": "G pair tests/s", "n_gpus": 1, "steps": args.steps,
                           "warmup": args.warmup, "ms_per_step": round(ms, 4),
                           "pair_kernel_us": [r[0]["us_pair"] for r in recs],
+                          "n_eval": recs[0][0]["n_eval"], "cells_m_s": cells["step"],
                           "note": "main steps only"}), flush=True)
         return
     # the same step as two calls

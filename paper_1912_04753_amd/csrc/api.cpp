@@ -1086,13 +1086,14 @@ ripk_status run_tuned(ripk_plan_s *p, int which, uint32_t S, uint32_t S_tune, ui
       } tuning_scope{p};
       p->tuning = true;
       for (int i = 0; i < n_cand; ++i) ts.us[i] = 1e300;
-      // one untimed run first, then the candidates in two rounds, each kept at
-      // its faster run: candidates can be a few % apart, and a device still
-      // raising its clock at the start of the call would otherwise favour the
-      // ones timed last
-      for (int rep = -1; rep < 2; ++rep) {
-        for (int i = 0; i < n_cand; ++i) {
-          if (rep < 0 && i > 0) break;
+      // three untimed runs first, then the candidates in two rounds, the
+      // second in reverse order, each kept at its faster run: candidates can be
+      // a few % apart, and a device still raising its clock at the start of the
+      // call would otherwise favour the ones timed last
+      for (int rep = -3; rep < 2; ++rep) {
+        for (int j = 0; j < n_cand; ++j) {
+          if (rep < 0 && j > 0) break;
+          const int i = rep == 1 ? n_cand - 1 - j : j;
           d.cell_div = kTuneCand[i % kTuneN][0];
           d.tcell_div = kTuneCand[i % kTuneN][1];
           p->split_runs = forced || i >= kTuneN;
