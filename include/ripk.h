@@ -205,7 +205,7 @@ typedef struct {
  *   - CSR simulations draw by rejection: attempt a of point k of set s uses the
  *     Philox counter (k, s, a, 0) and the first attempt strictly inside is kept;
  *   - device memory (in ripk_plan_info.device_bytes): besides the edges and
- *     their per-cell and per-band lists, a polygon plan keeps 144 bytes per
+ *     their per-cell and per-band lists, a polygon plan keeps 80 bytes per
  *     point of its largest call (S * n_max points: each point's distance range
  *     to every nearby edge, which the weight reads).
  * The vertex array is read during ripk_plan_check, ripk_plan and ripk_submit

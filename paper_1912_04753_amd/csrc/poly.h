@@ -88,14 +88,15 @@ __device__ __forceinline__ int32_t poly_edist(const Geom &g, int px, int py, int
 // 2^row_shift < 2^16), lo rounded down and hi up by a unit beyond the FP64
 // error: a circle about the point meets the edge only if lo <= radius <= hi.
 // Entries up to the next multiple of 4 hold an empty range (lo > hi).  Cells
-// that scan every edge keep only the head.
+// with more than kRowEdges edges listed, or that scan every edge, keep only the
+// head.
 __device__ __forceinline__ void poly_row(const Geom &g, int px, int py, uint32_t *__restrict__ row) {
   const uint32_t cell = poly_cell(g, px, py);
   const uint16_t *lst = g.near + (size_t)cell * (kNearMax + 1);
   const uint32_t cnt = lst[0];
   row[0] = cell;
   row[1] = cnt;
-  if (cnt == kNearAll) return;
+  if (cnt > (uint32_t)kRowEdges) return;  // (kNearAll included)
   for (uint32_t i = cnt; i < ((cnt + 3u) & ~3u); ++i) row[4 + i] = 0xFFFFu;
   const double u = ldexp(1.0, g.row_shift);
   for (uint32_t i = 0; i < cnt; ++i) {
@@ -200,7 +201,8 @@ __device__ __forceinline__ double poly_sqrt(double x) {
 // then runs only for those.  The lanes of a wave hold different circles, so a
 // single pass paid for the crossing work at almost every entry, while a
 // circle meets few of them (two, near a smooth boundary).  Cells that scan
-// every edge (more than 32 near it) take the first pass on exact integers.
+// every edge (more than 32 near it), or that list more than kRowEdges, take the
+// first pass on exact integers.
 __device__ __forceinline__ double poly_inv_omega(const Geom &g, int px, int py, uint64_t d2u,
                                                  uint32_t rec) {
   if (d2u == 0) return 1.0;
@@ -224,12 +226,13 @@ __device__ __forceinline__ double poly_inv_omega(const Geom &g, int px, int py, 
   const uint16_t *__restrict__ lst = g.near + (size_t)head.x * (kNearMax + 1);
   const bool all = head.y == kNearAll;
   const uint32_t len = all ? (uint32_t)nv : head.y;
+  const bool rows = len <= (uint32_t)kRowEdges && !all;
   // the squared radius in the row's units: d2 <= s_max^2, so below 2^32
   const uint32_t d2s = (uint32_t)d2u << (2 * g.row_shift);
   for (uint32_t base = 0; base < len; base += 32) {
     const uint32_t m = min(len - base, 32u);
     uint32_t keep = 0;
-    if (!all) {
+    if (rows) {
       // four entries per load, the next load issued before the current
       // entries are tested
       const uint4 *__restrict__ rw = (const uint4 *)(row + 4);
@@ -247,7 +250,7 @@ __device__ __forceinline__ double poly_inv_omega(const Geom &g, int px, int py, 
       }
     } else {
       for (uint32_t i = 0; i < m; ++i) {
-        const int4 e = E[base + i];
+        const int4 e = E[all ? base + i : (uint32_t)lst[1 + i]];
         const double ax = (double)(e.x - px), ay = (double)(e.y - py);
         const double bx = (double)(e.z - px), by = (double)(e.w - py);
         const double ex = bx - ax, ey = by - ay;

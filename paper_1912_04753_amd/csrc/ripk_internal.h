@@ -58,7 +58,10 @@ constexpr int kMaxPoly = 4096;       // vertices of a polygon study area
 constexpr int kNearMax = 32;         // edges listed per cell (more: every edge is scanned)
 constexpr uint16_t kNearAll = 0xFFFF;
 constexpr int kBandsMax = 1024;       // horizontal bands of the containment test
-constexpr int kRowWords = 4 + kNearMax;  // per-record polygon row: 4-word head, a word per listed edge
+// per-record polygon row: a 4-word head and a word per listed edge, for lists
+// of up to kRowEdges edges (longer lists take the exact first pass)
+constexpr int kRowEdges = 16;
+constexpr int kRowWords = 4 + kRowEdges;
 
 // Work item of the pair kernel: up to kChunk consecutive centres of one unit
 // of one set: a cell, or an x-row of cells (row items).
