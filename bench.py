@@ -272,6 +272,80 @@ def polygon_leg(ripk, workloads, torch, stream, steps=3):
     return polygon
 
 
+def larger_leg(ripk, workloads, torch, stream, wname, reps):
+    """One of the larger workloads, autotuned: its step time from an untimed plan
+    (median call), its phases and roofline from a timed plan."""
+    wc = workloads.workload(wname)
+    wx, wy, wt = (torch.from_numpy(a).cuda() for a in workloads.make_points(wc))
+    wn, wm = len(wx), wc["sims"]
+    wplan = ripk.ripk_plan(ripk.make_desc(wc["window"], wc["s_max"], wc["t_max"], wc["n_s"],
+                                          wc["n_t"], n_max=wn, m_max=wm,
+                                          flags=ripk.RIPK_PLAN_AUTOTUNE | ripk.RIPK_PLAN_TIMING))
+
+    def wstep():
+        t1 = time.perf_counter()
+        if wm == 0:
+            ripk.ripk_compute_K(wplan, wx, wy, wt, stream=stream)
+        else:
+            ripk.ripk_compute_K_envelope(wplan, wx, wy, wt, wm, wc["seed"], stream=stream)
+        b = ripk.ripk_plan_stats(wplan)
+        return b["n_in"], time.perf_counter() - t1, dict(b)
+
+    wstep()  # tuning
+    torch.cuda.synchronize()
+    t_w = time.perf_counter()
+    ws = [wstep() for _ in range(reps)]
+    torch.cuda.synchronize()
+    w_ms_timed = 1e3 * (time.perf_counter() - t_w) / reps
+    wi = ripk.ripk_plan_get_info(wplan)
+    # the same calls through an autotuned plan without per-phase timing (its
+    # events and the workgroup-time read-back are diagnostics): the step time
+    uplan = ripk.ripk_plan(ripk.make_desc(wc["window"], wc["s_max"], wc["t_max"], wc["n_s"],
+                                          wc["n_t"], n_max=wn, m_max=wm,
+                                          flags=ripk.RIPK_PLAN_AUTOTUNE))
+
+    def ustep():
+        if wm == 0:
+            ripk.ripk_compute_K(uplan, wx, wy, wt, stream=stream)
+        else:
+            ripk.ripk_compute_K_envelope(uplan, wx, wy, wt, wm, wc["seed"], stream=stream)
+
+    for _ in range(3):  # tuning, warm-up
+        ustep()
+    torch.cuda.synchronize()
+    # each call returns its results to the host (it ends synchronised), so
+    # calls are timed one by one; the step time is their median (a single
+    # host-side stall would otherwise dominate a mean of ~1 ms calls)
+    u_ms = []
+    for _ in range(reps):
+        t_u = time.perf_counter()
+        ustep()
+        u_ms.append(1e3 * (time.perf_counter() - t_u))
+    torch.cuda.synchronize()
+    w_ms = sorted(u_ms)[len(u_ms) // 2]
+    ui = ripk.ripk_plan_get_info(uplan)
+    uplan.destroy()
+    res = {"ms_per_step": round(w_ms, 3),
+           "pair_tests_per_s_G": round(ws[0][0] / (w_ms * 1e-3) / 1e9, 3),
+           "n_in_per_step": ws[0][0],
+           "sims_per_s": round(wm / (w_ms * 1e-3), 3) if wm else None,
+           "cells_m_s": [ui["cell_s"], ui["cell_t"]],
+           "ms_per_call_mean": round(sum(u_ms) / len(u_ms), 3),
+           "ms_per_call": [round(v, 3) for v in u_ms],
+           "timed_plan": {"ms_per_step": round(w_ms_timed, 3),
+                          "cells_m_s": [wi["cell_s"], wi["cell_t"]],
+                          "phases_us": {k: round(sum(v[2][k] for v in ws) / reps, 1)
+                                        for k in ("us_gen", "us_grid", "us_pair",
+                                                  "us_finalize")}},
+           "split": ripk.ripk_plan_stats(wplan)["split"],
+           "roofline": leg_roof(ws[0][2], sum(v[2]["us_pair"] for v in ws) / reps),
+           "cost_ordered": ws[0][2]["cost_ordered"],
+           "workgroup_end_us": {k: round(ws[-1][2]["us_wg_end_" + k], 1)
+                                for k in ("median", "p90", "max")}}
+    wplan.destroy()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -293,6 +367,8 @@ def main():
                     help="fixed cells (one per s_max and t_max) instead of the tuned grid")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain device copy of known size first (counter runs)")
+    ap.add_argument("--clustered-only", action="store_true",
+                    help="run the 200k clustered-set leg alone and print its JSON object")
     ap.add_argument("--polygon-only", action="store_true",
                     help="run the polygon leg alone (--steps timed calls) and print its JSON object")
     ap.add_argument("--main-only", action="store_true",
@@ -325,6 +401,11 @@ def main():
     PEAK["lane_ops"] = dev["compute_units"] * 64 * dev["clock_khz"] * 1e3
     if args.copy_calibration:
         copy_calibration(torch)
+    if args.clustered_only:
+        st = torch.cuda.current_stream().cuda_stream
+        print(json.dumps({"thomas-200k": larger_leg(ripk, workloads, torch, st, "thomas-200k",
+                                                    args.steps)}), flush=True)
+        return
     if args.polygon_only:
         st = torch.cuda.current_stream().cuda_stream
         print(json.dumps({"polygon": polygon_leg(ripk, workloads, torch, st, steps=args.steps)}),
@@ -509,77 +590,8 @@ def main():
     iplan.destroy()
     # the two larger workloads, autotuned: 200k clustered points (observed K), and
     # 1M uniform + 1M clustered points with 19 CSR simulations
-    larger = {}
-    for wname, reps in (("thomas-200k", 10), ("mixed-2M-19csr", 2)):
-        wc = workloads.workload(wname)
-        wx, wy, wt = (torch.from_numpy(a).cuda() for a in workloads.make_points(wc))
-        wn, wm = len(wx), wc["sims"]
-        wplan = ripk.ripk_plan(ripk.make_desc(wc["window"], wc["s_max"], wc["t_max"], wc["n_s"],
-                                              wc["n_t"], n_max=wn, m_max=wm,
-                                              flags=ripk.RIPK_PLAN_AUTOTUNE | ripk.RIPK_PLAN_TIMING))
-
-        def wstep():
-            t1 = time.perf_counter()
-            if wm == 0:
-                ripk.ripk_compute_K(wplan, wx, wy, wt, stream=stream)
-            else:
-                ripk.ripk_compute_K_envelope(wplan, wx, wy, wt, wm, wc["seed"], stream=stream)
-            b = ripk.ripk_plan_stats(wplan)
-            return b["n_in"], time.perf_counter() - t1, dict(b)
-
-        wstep()  # tuning
-        torch.cuda.synchronize()
-        t_w = time.perf_counter()
-        ws = [wstep() for _ in range(reps)]
-        torch.cuda.synchronize()
-        w_ms_timed = 1e3 * (time.perf_counter() - t_w) / reps
-        wi = ripk.ripk_plan_get_info(wplan)
-        # the same calls through an autotuned plan without per-phase timing (its
-        # events and the workgroup-time read-back are diagnostics): the step time
-        uplan = ripk.ripk_plan(ripk.make_desc(wc["window"], wc["s_max"], wc["t_max"], wc["n_s"],
-                                              wc["n_t"], n_max=wn, m_max=wm,
-                                              flags=ripk.RIPK_PLAN_AUTOTUNE))
-
-        def ustep():
-            if wm == 0:
-                ripk.ripk_compute_K(uplan, wx, wy, wt, stream=stream)
-            else:
-                ripk.ripk_compute_K_envelope(uplan, wx, wy, wt, wm, wc["seed"], stream=stream)
-
-        for _ in range(3):  # tuning, warm-up
-            ustep()
-        torch.cuda.synchronize()
-        # each call returns its results to the host (it ends synchronised), so
-        # calls are timed one by one; the step time is their median (a single
-        # host-side stall would otherwise dominate a mean of ~1 ms calls)
-        u_ms = []
-        for _ in range(reps):
-            t_u = time.perf_counter()
-            ustep()
-            u_ms.append(1e3 * (time.perf_counter() - t_u))
-        torch.cuda.synchronize()
-        w_ms = sorted(u_ms)[len(u_ms) // 2]
-        ui = ripk.ripk_plan_get_info(uplan)
-        uplan.destroy()
-        larger[wname] = {"ms_per_step": round(w_ms, 3),
-                         "pair_tests_per_s_G": round(ws[0][0] / (w_ms * 1e-3) / 1e9, 3),
-                         "n_in_per_step": ws[0][0],
-                         "sims_per_s": round(wm / (w_ms * 1e-3), 3) if wm else None,
-                         "cells_m_s": [ui["cell_s"], ui["cell_t"]],
-                         "ms_per_call_mean": round(sum(u_ms) / len(u_ms), 3),
-                         "ms_per_call": [round(v, 3) for v in u_ms],
-                         "timed_plan": {"ms_per_step": round(w_ms_timed, 3),
-                                        "cells_m_s": [wi["cell_s"], wi["cell_t"]],
-                                        "phases_us": {k: round(sum(v[2][k] for v in ws) / reps, 1)
-                                                      for k in ("us_gen", "us_grid", "us_pair",
-                                                                "us_finalize")}},
-                         "split": ripk.ripk_plan_stats(wplan)["split"],
-                         "roofline": leg_roof(ws[0][2], sum(v[2]["us_pair"] for v in ws) / reps),
-                         "cost_ordered": ws[0][2]["cost_ordered"],
-                         "workgroup_end_us": {k: round(ws[-1][2]["us_wg_end_" + k], 1)
-                                              for k in ("median", "p90", "max")}}
-        wplan.destroy()
-        del wx, wy, wt
+    larger = {wname: larger_leg(ripk, workloads, torch, stream, wname, reps)
+              for wname, reps in (("thomas-200k", 10), ("mixed-2M-19csr", 2))}
     plan.destroy()
 
     ms = 1e3 * t_total / args.steps
