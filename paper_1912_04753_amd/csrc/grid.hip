@@ -201,7 +201,7 @@ __global__ void k_resample(uint32_t n, uint32_t n_centres, uint32_t m, uint64_t 
   vals[gid] = (uint32_t)gid;
 }
 
-// ---- exclusive scan of uint32 (3 phases) ------------------------------------
+// ---- exclusive scan of uint32 ------------------------------------------------
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kThreads * kScanItems;
 
@@ -729,7 +729,8 @@ hipError_t exclusive_scan(const uint32_t *in, uint32_t *out, uint32_t n, void *t
     hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kThreads), 0, s, out, 0u);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kThreads), 0, s, in, n, part);
+  // (one tile: the down-sweep alone, which reads no tile sums for block 0)
+  if (nb > 1) hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kThreads), 0, s, in, n, part);
   hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kThreads), 0, s, in, n, part, out);
   return hipGetLastError();
 }
