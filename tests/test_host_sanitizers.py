@@ -46,7 +46,9 @@ def test_cpu_suite_under_host_sanitizers(tmp_path):
                     "-fno-omit-frame-pointer", "-fopenmp", "-fPIC", "-shared",
                     os.path.join(ROOT, "oracle", "oracle.c"), "-lm", "-o", olib],
                    check=True, capture_output=True)
-    env = dict(os.environ, LD_PRELOAD=rt, RIPK_LIB=lib, RIPK_ORACLE_LIB=olib,
+    # the sanitizer runtime first; anything already preloaded stays, after it
+    pre = ":".join([rt] + ([os.environ["LD_PRELOAD"]] if os.environ.get("LD_PRELOAD") else []))
+    env = dict(os.environ, LD_PRELOAD=pre, RIPK_LIB=lib, RIPK_ORACLE_LIB=olib,
                ASAN_OPTIONS="detect_leaks=0:halt_on_error=1:abort_on_error=0",
                UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
     cmd = [sys.executable, "-m", "pytest", os.path.join(ROOT, "tests"), "-m", "not gpu", "-x",
