@@ -298,6 +298,8 @@ def larger_leg(ripk, workloads, torch, stream, wname, reps):
     torch.cuda.synchronize()
     w_ms_timed = 1e3 * (time.perf_counter() - t_w) / reps
     wi = ripk.ripk_plan_get_info(wplan)
+    w_split = ripk.ripk_plan_stats(wplan)["split"]
+    wplan.destroy()  # one plan at a time on the device
     # the same calls through an autotuned plan without per-phase timing (its
     # events and the workgroup-time read-back are diagnostics): the step time
     uplan = ripk.ripk_plan(ripk.make_desc(wc["window"], wc["s_max"], wc["t_max"], wc["n_s"],
@@ -324,6 +326,7 @@ def larger_leg(ripk, workloads, torch, stream, wname, reps):
     torch.cuda.synchronize()
     w_ms = sorted(u_ms)[len(u_ms) // 2]
     ui = ripk.ripk_plan_get_info(uplan)
+    us_ = ripk.ripk_plan_stats(uplan)
     uplan.destroy()
     res = {"ms_per_step": round(w_ms, 3),
            "pair_tests_per_s_G": round(ws[0][0] / (w_ms * 1e-3) / 1e9, 3),
@@ -332,17 +335,17 @@ def larger_leg(ripk, workloads, torch, stream, wname, reps):
            "cells_m_s": [ui["cell_s"], ui["cell_t"]],
            "ms_per_call_mean": round(sum(u_ms) / len(u_ms), 3),
            "ms_per_call": [round(v, 3) for v in u_ms],
+           "split_untimed": us_["split"], "cost_ordered_untimed": us_["cost_ordered"],
            "timed_plan": {"ms_per_step": round(w_ms_timed, 3),
                           "cells_m_s": [wi["cell_s"], wi["cell_t"]],
                           "phases_us": {k: round(sum(v[2][k] for v in ws) / reps, 1)
                                         for k in ("us_gen", "us_grid", "us_pair",
                                                   "us_finalize")}},
-           "split": ripk.ripk_plan_stats(wplan)["split"],
+           "split": w_split,
            "roofline": leg_roof(ws[0][2], sum(v[2]["us_pair"] for v in ws) / reps),
            "cost_ordered": ws[0][2]["cost_ordered"],
            "workgroup_end_us": {k: round(ws[-1][2]["us_wg_end_" + k], 1)
                                 for k in ("median", "p90", "max")}}
-    wplan.destroy()
     return res
 
 

@@ -1123,15 +1123,18 @@ ripk_status run_tuned(ripk_plan_s *p, int which, uint32_t S, uint32_t S_tune, ui
       ts.split_runs = forced || bi >= kTuneN;
       ts.cost_order = (p->user_desc.flags & RIPK_PLAN_COST_ORDER) != 0;
       if (which == 0 && S == 1 && !ts.cost_order) {
-        // the chosen geometry once more with the cost-ordered work list
+        // the chosen geometry with and without the cost-ordered work list,
+        // in turn (three runs each, the faster of each kept), so that both
+        // see the same device state
         d.cell_div = ts.cd;
         d.tcell_div = ts.td;
         p->split_runs = ts.split_runs;
-        p->cost_order = true;
         ripk_status s = bind_geometry(p, &d, st);
         if (s != RIPK_OK) return s;
-        double us = 1e300;
-        for (int rep = 0; rep < 2; ++rep) {
+        double us[2] = {1e300, 1e300};
+        for (int rep = 0; rep < 6; ++rep) {
+          const int on = (rep & 1) ^ 1;
+          p->cost_order = on != 0;
           HIPCHK(hipEventRecord(p->tev[0], st));
           s = run_sets(p, S_tune, n, nc, x, y, t, simulate, seed, nullptr, st, sym, S, with_obs);
           if (s != RIPK_OK) return s;
@@ -1142,9 +1145,9 @@ ripk_status run_tuned(ripk_plan_s *p, int which, uint32_t S, uint32_t S_tune, ui
           if (err) return err_status(err);
           float ms = 0;
           HIPCHK(hipEventElapsedTime(&ms, p->tev[0], p->tev[1]));
-          us = std::min(us, 1e3 * (double)ms);
+          us[on] = std::min(us[on], 1e3 * (double)ms);
         }
-        ts.cost_order = us < best;
+        ts.cost_order = us[1] < us[0];
       }
     }
     p->split_runs = ts.split_runs;

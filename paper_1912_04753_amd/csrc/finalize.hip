@@ -22,78 +22,84 @@ __device__ __forceinline__ void add128(unsigned long long &lo, unsigned long lon
   lo = r;
 }
 
-// One workgroup per set.  binC/binW are cumulated in place (a set's weight
-// words are [kBinWords][nb]; words 0 and 1 of a bin then hold its 128-bit
-// value, low word first).
-__global__ void k_finalize(unsigned long long *__restrict__ binC,
-                           unsigned long long *__restrict__ binW, int n_s, int n_t,
+// One workgroup per set.  The set's bins are read once into LDS (the counts,
+// and each weight assembled as a 128-bit value from its four sums of 32-bit
+// pieces, sum_k w_k 2^(32 k) mod 2^128), cumulated there along t and then
+// along s, and the results written once: the prefix loops then wait on LDS,
+// not on a chain of global loads.  LDS: 24 bytes per bin.
+__global__ void k_finalize(const unsigned long long *__restrict__ binC,
+                           const unsigned long long *__restrict__ binW, int n_s, int n_t,
                            double s_max, double t_max, double AD, double N,
                            unsigned long long *__restrict__ C, double *__restrict__ W,
                            double *__restrict__ K, double *__restrict__ L,
                            const unsigned long long *__restrict__ queues,
                            unsigned long long *__restrict__ scal,
                            const unsigned long long *__restrict__ rho_max, int wbudget) {
+  extern __shared__ unsigned long long fin_lds[];
   const int set = blockIdx.x;
   const int nb = n_s * n_t;
-  unsigned long long *c = binC + (size_t)set * nb;
-  unsigned long long *w = binW + (size_t)set * nb * kBinWords;
+  const unsigned long long *c = binC + (size_t)set * nb;
+  const unsigned long long *w = binW + (size_t)set * nb * kBinWords;
+  unsigned long long *lc = fin_lds, *llo = fin_lds + nb, *lhi = fin_lds + 2 * nb;
   const int fbits = rho_max ? wide_fbits(*rho_max, wbudget) : kFracBits;
   if (set == 0 && threadIdx.x == 0) {
     unsigned long long ev = 0;
     for (int q = 0; q < kQueues; ++q) ev += queues[q * kQueueStride + 1];
     scal[0] = ev;
   }
-  // prefix along t within each s row (fixed point: the sums of 32-bit pieces
-  // first assembled as a 128-bit value, sum_k w_k 2^(32 k) mod 2^128)
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+    const unsigned long long s0 = w[b], s1 = w[nb + b], s2 = w[2 * nb + b], s3 = w[3 * nb + b];
+    unsigned long long lo = 0, hi = 0;
+    add128(lo, hi, s0, 0ull);
+    add128(lo, hi, s1 << 32, s1 >> 32);
+    add128(lo, hi, 0ull, s2);
+    add128(lo, hi, 0ull, s3 << 32);
+    lc[b] = c[b];
+    llo[b] = lo;
+    lhi[b] = hi;
+  }
+  __syncthreads();
+  // prefix along t within each s row
   for (int k = threadIdx.x; k < n_s; k += blockDim.x) {
     unsigned long long rc = 0, rlo = 0, rhi = 0;
     for (int l = 0; l < n_t; ++l) {
-      int b = k * n_t + l;
-      rc += c[b];
-      c[b] = rc;
-      unsigned long long *wb = w + b;
-      const unsigned long long s0 = wb[0], s1 = wb[nb], s2 = wb[2 * nb], s3 = wb[3 * nb];
-      add128(rlo, rhi, s0, 0ull);
-      add128(rlo, rhi, s1 << 32, s1 >> 32);
-      add128(rlo, rhi, 0ull, s2);
-      add128(rlo, rhi, 0ull, s3 << 32);
-      wb[0] = rlo;
-      wb[nb] = rhi;
+      const int b = k * n_t + l;
+      rc += lc[b];
+      lc[b] = rc;
+      add128(rlo, rhi, llo[b], lhi[b]);
+      llo[b] = rlo;
+      lhi[b] = rhi;
     }
   }
-  __threadfence_block();
   __syncthreads();
   // prefix along s within each t column
   for (int l = threadIdx.x; l < n_t; l += blockDim.x) {
     unsigned long long rc = 0, rlo = 0, rhi = 0;
     for (int k = 0; k < n_s; ++k) {
-      int b = k * n_t + l;
-      rc += c[b];
-      c[b] = rc;
-      unsigned long long *wb = w + b;
-      add128(rlo, rhi, wb[0], wb[nb]);
-      wb[0] = rlo;
-      wb[nb] = rhi;
+      const int b = k * n_t + l;
+      rc += lc[b];
+      lc[b] = rc;
+      add128(rlo, rhi, llo[b], lhi[b]);
+      llo[b] = rlo;
+      lhi[b] = rhi;
     }
   }
-  __threadfence_block();
   __syncthreads();
   const double two_pi = 6.283185307179586476925286766559;
   for (int b = threadIdx.x; b < nb; b += blockDim.x) {
     int k = b / n_t, l = b - k * n_t;
     // fixed point: W = (hi * 2^64 + lo) * 2^-F
-    const unsigned long long *wb = w + b;
-    double wv = ldexp((double)wb[nb], 64 - fbits) + ldexp((double)wb[0], -fbits);
+    double wv = ldexp((double)lhi[b], 64 - fbits) + ldexp((double)llo[b], -fbits);
     double Kv = AD * wv / N;
     double sk = (double)(k + 1) * s_max / (double)n_s;
     double tl = (double)(l + 1) * t_max / (double)n_t;
     size_t o = (size_t)set * nb + b;
-    C[o] = c[b];
+    C[o] = lc[b];
     W[o] = wv;
     K[o] = Kv;
     L[o] = sqrt(Kv / (two_pi * tl)) - sk;
   }
-  if (threadIdx.x == 0) atomicAdd(scal + 1, c[nb - 1]);
+  if (threadIdx.x == 0) atomicAdd(scal + 1, lc[nb - 1]);
 }
 
 // env rows: K_lo, K_hi, L_lo, L_hi, dL_hi
@@ -141,7 +147,8 @@ hipError_t launch_finalize(unsigned long long *binC, unsigned long long *binW, u
                            unsigned long long *C, double *W, double *K, double *L,
                            const unsigned long long *queues, unsigned long long *scal,
                            hipStream_t s, const unsigned long long *rho_max, int wbudget) {
-  hipLaunchKernelGGL(k_finalize, dim3(n_sets), dim3(256), 0, s, binC, binW, n_s, n_t, s_max,
+  hipLaunchKernelGGL(k_finalize, dim3(n_sets), dim3(256), 24 * n_s * n_t, s, binC, binW, n_s,
+                     n_t, s_max,
                      t_max, AD, N, C, W, K, L, queues, scal, rho_max, wbudget);
   return hipGetLastError();
 }
