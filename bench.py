@@ -326,7 +326,7 @@ def larger_leg(ripk, workloads, torch, stream, wname, reps):
     torch.cuda.synchronize()
     w_ms = sorted(u_ms)[len(u_ms) // 2]
     ui = ripk.ripk_plan_get_info(uplan)
-    us_ = ripk.ripk_plan_stats(uplan)
+    u_stats = ripk.ripk_plan_stats(uplan)
     uplan.destroy()
     res = {"ms_per_step": round(w_ms, 3),
            "pair_tests_per_s_G": round(ws[0][0] / (w_ms * 1e-3) / 1e9, 3),
@@ -335,7 +335,7 @@ def larger_leg(ripk, workloads, torch, stream, wname, reps):
            "cells_m_s": [ui["cell_s"], ui["cell_t"]],
            "ms_per_call_mean": round(sum(u_ms) / len(u_ms), 3),
            "ms_per_call": [round(v, 3) for v in u_ms],
-           "split_untimed": us_["split"], "cost_ordered_untimed": us_["cost_ordered"],
+           "split_untimed": u_stats["split"], "cost_ordered_untimed": u_stats["cost_ordered"],
            "timed_plan": {"ms_per_step": round(w_ms_timed, 3),
                           "cells_m_s": [wi["cell_s"], wi["cell_t"]],
                           "phases_us": {k: round(sum(v[2][k] for v in ws) / reps, 1)
