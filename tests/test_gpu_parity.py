@@ -238,6 +238,22 @@ def test_edge_case_sets(case):
     assert g["stats"]["bin_layout"] == 0 and gw["stats"]["bin_layout"] == 2
 
 
+@pytest.mark.parametrize("n", [1024, 1025, 16384, 16385])
+def test_sort_and_scan_tile_boundaries(n):
+    """Set sizes at the radix sort's tile boundaries (1,024 keys per tile for
+    sorts of up to 2^20 keys) and at its digit-count scan's: 16 tiles give
+    4,096 counts, one scan tile (the down-sweep alone), 17 tiles two."""
+    rng = np.random.default_rng(n)
+    win = (0, 0, 8000, 8000, 0, 200 * workloads.DAY)
+    x, y, t = workloads.uniform_points(rng, n, win)
+    args = (win, 800, 20 * workloads.DAY, 12, 9)
+    say("tile boundary n=%d" % n)
+    g = gpu_K(x, y, t, *args)
+    r = ref_K(x, y, t, *args)
+    compare(g, r, 800, 20 * workloads.DAY, 12, 9, where="tile boundary n=%d" % n)
+    assert g["stats"]["n_in"] == int(r["C"][-1, -1])
+
+
 def test_wide_distances():
     """Cells so large that squared candidate distances need 64 bits."""
     rng = np.random.default_rng(8)
