@@ -315,14 +315,17 @@ __global__ void k_scan_down(const uint32_t *__restrict__ in, uint32_t n,
 // straddle a segment.  Digit counts are laid out (segment, digit, tile), so
 // their exclusive scan gives each tile's start for each digit.  One segment
 // with stride 0 is a plain sort.
-// Keys per thread of a tile: 16 (4,096 keys per workgroup), or 4 for sorts of
-// at most kSmallSort keys, which would otherwise run on too few workgroups
-// (a 200k-key pass on 49 of them was latency-bound in its 16 serial rounds).
+// Keys per thread of a tile: 16 (4,096 keys per workgroup); 2 for sorts of at
+// most kSmallSort keys, which would otherwise run on too few workgroups (a
+// 200k-key pass on 49 of them was latency-bound in its 16 serial rounds); 1
+// for at most kTinySort keys (the work list's cost order).
 constexpr uint32_t kSortItems = 16;
-constexpr uint32_t kSortItemsSmall = 4;
+constexpr uint32_t kSortItemsSmall = 2;
 constexpr uint32_t kSmallSort = 1u << 20;
+constexpr uint32_t kSortItemsTiny = 1;
+constexpr uint32_t kTinySort = 1u << 16;
 __host__ __device__ inline uint32_t sort_items(uint32_t n) {
-  return n <= kSmallSort ? kSortItemsSmall : kSortItems;
+  return n <= kTinySort ? kSortItemsTiny : n <= kSmallSort ? kSortItemsSmall : kSortItems;
 }
 
 struct SortTile {
@@ -739,8 +742,9 @@ size_t radix_sort_temp_bytes(uint32_t n, uint32_t n_segs) {
   // tiles: at most one partial tile per segment beyond the whole ones
   // (the tile is smaller for small sorts: the larger of the two block counts)
   const uint32_t m = n > 0 ? n : 1;
-  size_t nb = std::max<size_t>(blocks_for(m, kThreads * kSortItems),
-                               blocks_for(std::min(m, kSmallSort), kThreads * kSortItemsSmall)) +
+  size_t nb = std::max<size_t>({blocks_for(m, kThreads * kSortItems),
+                                blocks_for(std::min(m, kSmallSort), kThreads * kSortItemsSmall),
+                                blocks_for(std::min(m, kTinySort), kThreads * kSortItemsTiny)}) +
               n_segs;
   size_t cnt = 256 * nb;
   return sizeof(uint32_t) * (2 * cnt + 1) + scan_temp_bytes((uint32_t)cnt) + 256;

@@ -238,11 +238,12 @@ def test_edge_case_sets(case):
     assert g["stats"]["bin_layout"] == 0 and gw["stats"]["bin_layout"] == 2
 
 
-@pytest.mark.parametrize("n", [1024, 1025, 16384, 16385])
+@pytest.mark.parametrize("n", [256, 257, 4096, 4097, 65536, 65537])
 def test_sort_and_scan_tile_boundaries(n):
-    """Set sizes at the radix sort's tile boundaries (1,024 keys per tile for
-    sorts of up to 2^20 keys) and at its digit-count scan's: 16 tiles give
-    4,096 counts, one scan tile (the down-sweep alone), 17 tiles two."""
+    """Set sizes at the radix sort's tile boundaries (256 keys per tile for
+    sorts of up to 2^16 keys, 512 up to 2^20) and at its digit-count scan's:
+    16 tiles give 4,096 counts, one scan tile (the down-sweep alone), 17 tiles
+    two."""
     rng = np.random.default_rng(n)
     win = (0, 0, 8000, 8000, 0, 200 * workloads.DAY)
     x, y, t = workloads.uniform_points(rng, n, win)
